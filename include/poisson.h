@@ -1,0 +1,154 @@
+/*
+ * poisson.h - C ABI of the MI355X (gfx950) direct Poisson solver.
+ *
+ * The library solves the second-order finite-difference Poisson equation on a
+ * staggered (cell-centred) Cartesian grid by eigenfunction expansion
+ * (P. Costa, "A FFT-based finite-difference solver for massively-parallel
+ * direct numerical simulations of turbulent flows", Sec. 2.1):
+ *
+ *   sum over the three axes of the central second difference of Phi  = f
+ *   (Eq. (poi); the third axis may be non-uniform, Sec. 2.1 footnote),
+ *
+ * with homogeneous periodic / staggered Neumann / staggered Dirichlet
+ * boundary conditions (Table 1).  Two axes are diagonalised by real-to-real
+ * transforms (Table 2: DFT, DCT-II/III, DST-II/III, DCT-IV, and DST-IV for the
+ * Dirichlet-Neumann pair), the reduced tridiagonal systems (Eq. (poi_reduced))
+ * are solved by Gauss elimination along the third axis (cyclic when that axis
+ * is periodic, Sec. 3), and the backward transforms return Phi.
+ *
+ * Data layout: a field is nx*ny*nz values, index i + nx*(j + ny*k), x fastest.
+ * All field pointers are DEVICE pointers; all other pointers are HOST pointers.
+ * Streams are hipStream_t values (NULL = the legacy default stream).
+ *
+ * Error handling: functions return POISSON_OK (0) or a negative code;
+ * plan_create returns NULL on error.  The code and a message of the last
+ * failing call on the calling thread are available from last_error() and
+ * last_error_message().  Launch functions only enqueue work: they report
+ * argument and launch errors, not results; results are valid once the stream
+ * has completed.
+ *
+ * Thread safety: all functions may be called from several host threads.  A
+ * plan owns a workspace, so one plan must not be used by two streams at once.
+ */
+#ifndef POISSON_H
+#define POISSON_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Boundary pair of one axis: first letter = low face (index 0), second letter
+ * = high face (index n-1).  P = periodic, N = staggered Neumann (zero normal
+ * gradient), D = staggered Dirichlet (zero value at the face).  Table 1 lists
+ * P-P, N-N, D-D and N-D; D-N is its mirror image. */
+enum poisson_bc {
+  BC_PERIODIC = 0,
+  BC_NN = 1,
+  BC_DD = 2,
+  BC_ND = 3,
+  BC_DN = 4
+};
+
+enum poisson_status {
+  POISSON_OK = 0,
+  POISSON_EINVAL = -1,        /* bad argument: null pointer, size < 1, bad bc, non-finite or non-positive spacing */
+  POISSON_EUNSUPPORTED = -2,  /* valid problem the kernels do not handle (see plan_create) */
+  POISSON_ENOMEM = -3,        /* device allocation failed */
+  POISSON_EHIP = -4,          /* a HIP runtime call or kernel launch failed */
+  POISSON_ENOTCONVERGED = -5  /* refinement stopped before reaching its tolerance (solve_status) */
+};
+
+enum poisson_precision {
+  POISSON_FP64 = 0,           /* plain FP64 transforms and elimination */
+  POISSON_FP32_REFINED = 1    /* FP32 transforms and elimination, FP64 residual/update (iterative refinement) */
+};
+
+typedef struct poisson_plan poisson_plan;
+
+/* Build a plan for an nx x ny x nz grid (Sec. 2.1, Tables 1 and 2).
+ *   dx, dy : uniform spacings of x and y (> 0, finite).
+ *   dz     : HOST array of nz cell widths along z (> 0, finite); copied.  z may
+ *            be non-uniform; a non-uniform z always becomes the elimination axis.
+ *   bc_x, bc_y, bc_z : enum poisson_bc.
+ * Axis roles: the elimination axis s is z if z is non-uniform or not periodic;
+ * otherwise the first non-periodic axis among x, y; z (cyclic) if all three are
+ * periodic.  The other two axes are transformed.
+ * Supported sizes: every transformed axis needs an even n >= 2 whose half has
+ * no prime factor above 5 and n <= 1024; the elimination axis needs
+ * 1 <= n <= 512 (n >= 3 if it is periodic).  Otherwise POISSON_EUNSUPPORTED.
+ * Allocates the device tables (O(nx+ny+nz) doubles) on the current device.
+ * Returns NULL on error (see last_error()). */
+poisson_plan* plan_create(int nx, int ny, int nz, double dx, double dy, const double* dz,
+                          int bc_x, int bc_y, int bc_z);
+
+/* Solve in place.  rhs: DEVICE pointer to nx*ny*nz doubles (x fastest), on the
+ * plan's device, overwritten with Phi.  When no face is Dirichlet the operator
+ * is singular: the solver removes the volume-weighted mean of f and returns
+ * the solution with zero volume-weighted mean (this is not an error).
+ * Enqueues on `stream` and returns; `rhs` must stay valid until the stream
+ * completes.  FP32_REFINED plans also use their workspace. */
+int solve(poisson_plan* plan, double* rhs, hipStream_t stream);
+
+/* Release the plan and its device memory (NULL is a no-op).  Work already
+ * enqueued with the plan must have completed. */
+void plan_destroy(poisson_plan* plan);
+
+/* Code and message of the last failing call on this thread (0 / "" if none).
+ * The message is in thread-local storage, valid until the next failing call. */
+int last_error(void);
+const char* last_error_message(void);
+
+/* Select the arithmetic of solve().  mode = POISSON_FP64 (default) or
+ * POISSON_FP32_REFINED: transforms and elimination in FP32, then up to
+ * max_iters refinement sweeps r = f - A Phi (FP64 seven-point residual),
+ * e = FP32 solve of r, Phi += e (FP64), stopping once
+ * ||e||_2 <= tol * ||Phi||_2 (both measured on the device).  tol > 0,
+ * 1 <= max_iters <= 64.  Allocates the refinement workspace (FP64 copy of f,
+ * FP32 correction field) on first use.  Not to be called while a solve with
+ * this plan is in flight. */
+int plan_set_precision(poisson_plan* plan, int mode, double tol, int max_iters);
+
+/* Device bytes the plan holds (tables + workspace), plus the bytes one solve
+ * needs beyond the caller's field.  For admission by HBM footprint. */
+size_t plan_workspace_bytes(const poisson_plan* plan);
+
+/* After the stream of the last solve() has completed: number of FP32 solves
+ * performed (1 + refinement sweeps; 1 for FP64 plans) and the last relative
+ * update ||e||/||Phi||  (0 for FP64 plans).  Returns POISSON_ENOTCONVERGED if
+ * the last refined solve stopped at max_iters above its tolerance. */
+int solve_status(poisson_plan* plan, int* iters, double* last_update_rel);
+
+/* Solve `count` independent problems, plans[i] applied in place to rhs[i]
+ * (DEVICE pointers), as one batched sequence of launches on `stream`: every
+ * stage of every instance is one work item of the same grid.  FP64 plans only;
+ * plans must be distinct.  Same semantics per instance as solve(). */
+int batch_solve(poisson_plan* const* plans, double* const* rhs, int count, hipStream_t stream);
+
+/* ---- stage entry points (the steps of Sec. 2.1, for stage-level checks) ---- */
+
+/* Axis roles chosen by the plan: roles[0] = t1, roles[1] = t2 (the transformed
+ * axes, forward order), roles[2] = s (elimination axis); 0 = x, 1 = y, 2 = z. */
+int plan_roles(const poisson_plan* plan, int roles[3]);
+
+/* Step 1 / 3 for one transformed axis (role 0 = t1, 1 = t2), in place on an
+ * FP64 DEVICE field: inverse = 0 applies the forward transform of Table 2
+ * (unnormalised, DFT in Table 2's interleaved order), inverse = 1 the backward
+ * operator of Table 1 ((1/n) IDFT, (1/2n) DCT-III, (1/2n) DST-III, (1/2n) DCT-IV,
+ * (1/2n) DST-IV). */
+int transform_stage(poisson_plan* plan, int role, int inverse, double* field, hipStream_t stream);
+
+/* Step 2: solve the reduced tridiagonal systems (Eq. (poi_reduced)) of every
+ * column along s, in place on an FP64 DEVICE field holding the transformed
+ * right-hand side in the storage order of transform_stage.  The column of
+ * wavenumber zero of a singular problem is projected, pinned and gauged to
+ * zero weighted mean. */
+int tridiag_stage(poisson_plan* plan, double* field, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POISSON_H */

@@ -1,0 +1,629 @@
+// poisson.hip - host side of the gfx950 Poisson solver: plans, tables,
+// launches and the C ABI declared in include/poisson.h.
+//
+// The solve follows the three steps of Sec. 2.1 (forward transforms along the
+// two transformed axes, Gauss elimination of Eq. (poi_reduced) along the third,
+// backward transforms), each step one HBM sweep of the field by one kernel.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "poisson.h"
+#include "r2r_kernel.h"
+#include "tridiag_kernel.h"
+#include "refine_kernels.h"
+
+using namespace poisson_dev;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local int g_err = 0;
+static thread_local char g_msg[512] = "";
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  g_err = code;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(POISSON_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+extern "C" int last_error(void) { return g_err; }
+extern "C" const char* last_error_message(void) { return g_msg; }
+
+// ------------------------------------------------------------------ constants
+
+static constexpr int R2R_NT = 512;
+static constexpr int R2R_EMAX_D = 8;    // complex values per thread, FP64
+static constexpr int R2R_EMAX_F = 16;   // complex values per thread, FP32
+static constexpr int TRI_NT = 512;
+static constexpr int MAX_TRANSFORM_N = 1024;
+static constexpr int MAX_SOLVE_N = 512;
+static constexpr size_t LDS_LIMIT = 160 * 1024;
+
+// ------------------------------------------------------------------ tables
+
+// cos and sin of pi*M/(4n) for an integer M: the angle is reduced exactly
+// (in integers) to [0, pi/4] before the library call, so symmetric angles
+// give exactly symmetric values.
+static void cos_sin_quarter(long long M, long long n, double& c, double& s) {
+  const long long turn = 8 * n;
+  M %= turn;
+  if (M < 0) M += turn;
+  double ss = 1.0, sc = 1.0;
+  if (M > 4 * n) { M = turn - M; ss = -1.0; }      // theta -> 2 pi - theta
+  if (M > 2 * n) { M = 4 * n - M; sc = -1.0; }     // theta -> pi - theta
+  bool swap = false;
+  if (M > n) { M = 2 * n - M; swap = true; }       // theta -> pi/2 - theta
+  const double th = M_PI * (double)M / (4.0 * (double)n);
+  double cc = std::cos(th), sn = std::sin(th);
+  if (swap) std::swap(cc, sn);
+  c = sc * cc;
+  s = ss * sn;
+}
+
+// e^{-i pi M/(4n)}
+static cplx<double> expm(long long M, long long n) {
+  double c, s;
+  cos_sin_quarter(M, n, c, s);
+  return {c, -s};
+}
+
+// Table 1: lambda_q = -4 sin^2(theta_q), theta_q = pi M_q / (4n).
+static double eigenvalue(int kind, int n, int q) {
+  long long M;
+  switch (kind) {
+    case BC_PERIODIC: M = 4LL * ((q + 1) / 2); break;   // wavenumber of storage slot q
+    case BC_NN: M = 2LL * q; break;
+    case BC_DD: M = 2LL * (q + 1); break;
+    default: M = 2LL * q + 1; break;                      // ND and DN
+  }
+  double c, s;
+  cos_sin_quarter(M, n, c, s);
+  return -4.0 * s * s;
+}
+
+static bool factor_radices(int m, std::vector<int>& radices) {
+  radices.clear();
+  int e2 = 0;
+  while (m % 2 == 0) { m /= 2; ++e2; }
+  int n8 = e2 / 3, rem = e2 % 3, n4 = 0, n2 = 0;
+  if (rem == 1) { if (n8 > 0) { --n8; n4 = 2; } else n2 = 1; }
+  if (rem == 2) n4 = 1;
+  for (int i = 0; i < n8; ++i) radices.push_back(8);
+  for (int i = 0; i < n4; ++i) radices.push_back(4);
+  for (int i = 0; i < n2; ++i) radices.push_back(2);
+  for (int p : {3, 5})
+    while (m % p == 0) { m /= p; radices.push_back(p); }
+  return m == 1 && radices.size() <= 16;
+}
+
+// ------------------------------------------------------------------ plan
+
+struct AxisTables {           // one transformed axis
+  int axis = 0, n = 0, kind = 0, m = 0;
+  std::vector<int> radices;
+  size_t off_d = 0, off_f = 0;   // byte offsets of the twiddle block (FP64 / FP32)
+};
+
+struct poisson_plan {
+  int dims[3];
+  int bc[3];
+  double h[3];                 // uniform spacing (x, y) ; z uses dz
+  std::vector<double> dz;
+  bool z_uniform;
+  int t1, t2, s;
+  bool singular, s_periodic;
+  int device;
+  AxisTables ax[2];
+  // elimination axis tables
+  size_t off_tri_d = 0, off_tri_f = 0;     // a, b, c, w   (4 n_s)
+  size_t off_lam_d = 0, off_lam_f = 0;     // lamu, lamv
+  size_t off_ops[3] = {0, 0, 0};           // per axis: a, b, c, h (FP64, residual)
+  int nu = 0, nv = 0;
+  int P = 1, lcmax = 1;
+  char* dtab = nullptr;        // device tables
+  size_t tab_bytes = 0;
+  // refinement
+  int mode = POISSON_FP64;
+  double tol = 1e-10;
+  int max_iters = 8;
+  double* f64 = nullptr;       // FP64 copy of f
+  float* e32 = nullptr;        // FP32 residual / correction
+  double* stats = nullptr;     // device reduction slots
+  double* stats_host = nullptr;
+  size_t ws_bytes = 0;
+  int last_iters = 1;
+  double last_rel = 0.0;
+  int last_converged = 1;
+};
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+static int lds_setup_once() {
+  static std::once_flag once;
+  static int status = 0;
+  std::call_once(once, [] {
+    hipError_t e = hipSuccess;
+#define ALLOW(k) if (e == hipSuccess) e = hipFuncSetAttribute((const void*)(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_LIMIT)
+    ALLOW((r2r_kernel<double, R2R_EMAX_D, R2R_NT>));
+    ALLOW((r2r_kernel<float, R2R_EMAX_F, R2R_NT>));
+    ALLOW((tridiag_kernel<double, 4, TRI_NT>));
+    ALLOW((tridiag_kernel<double, 8, TRI_NT>));
+    ALLOW((tridiag_kernel<double, 16, TRI_NT>));
+    ALLOW((tridiag_kernel<float, 4, TRI_NT>));
+    ALLOW((tridiag_kernel<float, 8, TRI_NT>));
+    ALLOW((tridiag_kernel<float, 16, TRI_NT>));
+#undef ALLOW
+    status = e == hipSuccess ? 0 : fail(POISSON_EHIP, "hipFuncSetAttribute: %s", hipGetErrorString(e));
+  });
+  return status;
+}
+
+// Geometry of the lines along axis `axis` (0 = x, 1 = y, 2 = z) of an
+// nx x ny x nz field, with at most `nl_target` lines per tile.
+static LineGeom make_geom(int axis, const int* dims, int nl_target) {
+  LineGeom g{};
+  const long long nx = dims[0], ny = dims[1], nz = dims[2];
+  if (axis == 0) {
+    g.layout = 1;
+    g.n = dims[0];
+    g.sp = 1;
+    g.nlines = ny * nz;
+    g.nl = (int)std::min<long long>(nl_target, g.nlines);
+    g.ntiles = (g.nlines + g.nl - 1) / g.nl;
+  } else {
+    g.layout = 0;
+    g.n = dims[axis];
+    g.sp = axis == 1 ? nx : nx * ny;
+    g.nx = (int)nx;
+    g.nb = axis == 1 ? (int)nz : (int)ny;
+    g.sb = axis == 1 ? nx * ny : nx;
+    g.txw = (int)std::min<long long>(nl_target, nx);
+    g.nbt = std::max(1, std::min(nl_target / g.txw, g.nb));
+    g.nl = g.txw * g.nbt;
+    g.tiles_x = (int)((nx + g.txw - 1) / g.txw);
+    g.ntiles = (long long)g.tiles_x * ((g.nb + g.nbt - 1) / g.nbt);
+  }
+  return g;
+}
+
+static int grid_of(long long ntiles) {
+  return (int)std::min<long long>(ntiles, 1LL << 30);
+}
+
+// ------------------------------------------------------------------ launches
+
+template <typename T>
+static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hipStream_t st,
+                      const double* skip = nullptr) {
+  const AxisTables& A = p->ax[role];
+  constexpr int EMAX = sizeof(T) == 8 ? R2R_EMAX_D : R2R_EMAX_F;
+  const int cap_reals = 2 * EMAX * R2R_NT;
+  const int nl_target = std::max(1, std::min(cap_reals / A.n, R2R_NT));
+  R2RArgs<T> a{};
+  a.data = data;
+  a.g = make_geom(A.axis, p->dims, nl_target);
+  a.kind = A.kind;
+  a.inverse = inverse;
+  a.m = A.m;
+  a.npass = (int)A.radices.size();
+  for (int i = 0; i < a.npass; ++i) a.radix[i] = A.radices[i];
+  a.nlp = a.g.nl | 1;
+  if (!inverse) a.scale = (T)1;
+  else a.scale = (T)(A.kind <= BC_DD ? 1.0 / A.n : 1.0 / (2.0 * A.n));
+  const char* base = p->dtab + (sizeof(T) == 8 ? A.off_d : A.off_f);
+  const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(base);
+  a.tw_fft = tw;
+  a.tw_split = tw + A.m;
+  a.tw_quarter = tw + 2 * A.m + 1;
+  a.tw_pre = tw + 3 * A.m + 2;
+  a.tw_post = tw + 4 * A.m + 2;
+  a.skip = skip;
+  const size_t lds = (size_t)A.n * a.nlp * sizeof(T);
+  if (lds > LDS_LIMIT) return fail(POISSON_EUNSUPPORTED, "transform tile needs %zu B of LDS", lds);
+  hipLaunchKernelGGL((r2r_kernel<T, EMAX, R2R_NT>), dim3(grid_of(a.g.ntiles)), dim3(R2R_NT), lds,
+                     st, a);
+  HIP_TRY(hipGetLastError());
+  return POISSON_OK;
+}
+
+template <typename T>
+static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
+                          const double* skip = nullptr) {
+  TriArgs<T> a{};
+  a.data = data;
+  const int lines = TRI_NT / p->P;
+  a.g = make_geom(p->s, p->dims, lines);
+  a.P = p->P;
+  a.lcmax = p->lcmax;
+  a.nlp = lines | 1;
+  a.cpitch = (p->lcmax * a.nlp) | 1;
+  a.periodic = p->s_periodic;
+  a.singular = p->singular;
+  a.nu = p->nu;
+  const size_t ns = (size_t)p->dims[p->s];
+  const T* tri = reinterpret_cast<const T*>(p->dtab + (sizeof(T) == 8 ? p->off_tri_d : p->off_tri_f));
+  a.a = tri;
+  a.b = tri + ns;
+  a.c = tri + 2 * ns;
+  a.w = tri + 3 * ns;
+  const T* lam = reinterpret_cast<const T*>(p->dtab + (sizeof(T) == 8 ? p->off_lam_d : p->off_lam_f));
+  a.lamu = lam;
+  a.lamv = lam + p->nu;
+  a.skip = skip;
+  const size_t lds = (size_t)p->P * a.cpitch * sizeof(T);
+  if (lds > LDS_LIMIT) return fail(POISSON_EUNSUPPORTED, "elimination tile needs %zu B of LDS", lds);
+  const dim3 grid(grid_of(a.g.ntiles)), block(TRI_NT);
+  const int interior = p->lcmax - 1;
+  if (interior <= 4)
+    hipLaunchKernelGGL((tridiag_kernel<T, 4, TRI_NT>), grid, block, lds, st, a);
+  else if (interior <= 8)
+    hipLaunchKernelGGL((tridiag_kernel<T, 8, TRI_NT>), grid, block, lds, st, a);
+  else
+    hipLaunchKernelGGL((tridiag_kernel<T, 16, TRI_NT>), grid, block, lds, st, a);
+  HIP_TRY(hipGetLastError());
+  return POISSON_OK;
+}
+
+// The three steps of Sec. 2.1: forward transforms t1 then t2, elimination
+// along s, backward transforms t2 then t1.
+template <typename T>
+static int solve_typed(const poisson_plan* p, T* data, hipStream_t st,
+                       const double* skip = nullptr) {
+  int rc;
+  if ((rc = launch_r2r<T>(p, 0, 0, data, st, skip))) return rc;
+  if ((rc = launch_r2r<T>(p, 1, 0, data, st, skip))) return rc;
+  if ((rc = launch_tridiag<T>(p, data, st, skip))) return rc;
+  if ((rc = launch_r2r<T>(p, 1, 1, data, st, skip))) return rc;
+  if ((rc = launch_r2r<T>(p, 0, 1, data, st, skip))) return rc;
+  return POISSON_OK;
+}
+
+// ------------------------------------------------------------------ plan_create
+
+// Cell widths along axis q (x and y uniform, z from dz).
+static std::vector<double> axis_widths(const poisson_plan* p, int q) {
+  if (q == 2) return p->dz;
+  return std::vector<double>(p->dims[q], p->h[q]);
+}
+
+// Rows of the 1D staggered operator on cell widths h (finite-volume form:
+// centre distances are the mean of neighbouring widths; at a wall the ghost
+// cell mirrors the edge cell, so a Neumann face adds +a_0 / +c_{n-1} to the
+// diagonal and a Dirichlet face subtracts it; a periodic axis keeps a_0 and
+// c_{n-1} as the wrap couplings).  out = [a | b | c | h], each n long.
+static void axis_rows(const std::vector<double>& hs, int kind, double* out) {
+  const int n = (int)hs.size();
+  const bool periodic = kind == BC_PERIODIC;
+  std::vector<double> dc(n + 1);
+  for (int k = 1; k < n; ++k) dc[k] = 0.5 * (hs[k - 1] + hs[k]);
+  if (periodic) dc[0] = dc[n] = 0.5 * (hs[n - 1] + hs[0]);
+  else { dc[0] = hs[0]; dc[n] = hs[n - 1]; }
+  double* a = out;
+  double* b = a + n;
+  double* c = b + n;
+  double* w = c + n;
+  for (int k = 0; k < n; ++k) {
+    a[k] = 1.0 / (hs[k] * dc[k]);
+    c[k] = 1.0 / (hs[k] * dc[k + 1]);
+    b[k] = -(a[k] + c[k]);
+    w[k] = hs[k];
+  }
+  if (!periodic) {
+    const bool low_n = kind == BC_NN || kind == BC_ND;
+    const bool high_n = kind == BC_NN || kind == BC_DN;
+    b[0] += low_n ? a[0] : -a[0];
+    b[n - 1] += high_n ? c[n - 1] : -c[n - 1];
+    a[0] = 0.0;
+    c[n - 1] = 0.0;
+  }
+}
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+static int choose_chunks(int n, bool periodic, int& P, int& lcmax) {
+  P = 1;
+  while (P < 32 && n >= 4 * P) P *= 2;     // every chunk keeps >= 2 rows
+  lcmax = (n + P - 1) / P;
+  (void)periodic;
+  return lcmax - 1 <= 16 ? 0 : -1;
+}
+
+extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double dy, const double* dz,
+                                     int bc_x, int bc_y, int bc_z) {
+  g_err = 0;
+  g_msg[0] = 0;
+  if (nx < 1 || ny < 1 || nz < 1) { fail(POISSON_EINVAL, "sizes must be >= 1 (got %d %d %d)", nx, ny, nz); return nullptr; }
+  if (!dz) { fail(POISSON_EINVAL, "dz is NULL"); return nullptr; }
+  if (!finite_pos(dx) || !finite_pos(dy)) { fail(POISSON_EINVAL, "dx, dy must be finite and > 0"); return nullptr; }
+  const int bcs[3] = {bc_x, bc_y, bc_z};
+  for (int i = 0; i < 3; ++i)
+    if (bcs[i] < BC_PERIODIC || bcs[i] > BC_DN) { fail(POISSON_EINVAL, "boundary pair %d out of range on axis %d", bcs[i], i); return nullptr; }
+  for (int k = 0; k < nz; ++k)
+    if (!finite_pos(dz[k])) { fail(POISSON_EINVAL, "dz[%d] must be finite and > 0", k); return nullptr; }
+  if ((long long)nx * ny * nz > (1LL << 34)) { fail(POISSON_EUNSUPPORTED, "grid too large"); return nullptr; }
+
+  poisson_plan* p = new poisson_plan();
+  p->dims[0] = nx; p->dims[1] = ny; p->dims[2] = nz;
+  for (int i = 0; i < 3; ++i) p->bc[i] = bcs[i];
+  p->h[0] = dx; p->h[1] = dy; p->h[2] = dz[0];
+  p->dz.assign(dz, dz + nz);
+  p->z_uniform = true;
+  for (int k = 1; k < nz; ++k) if (dz[k] != dz[0]) p->z_uniform = false;
+
+  // axis roles (elimination axis s; the others transformed, in x, y, z order)
+  if (!p->z_uniform || bc_z != BC_PERIODIC) p->s = 2;
+  else if (bc_x != BC_PERIODIC) p->s = 0;
+  else if (bc_y != BC_PERIODIC) p->s = 1;
+  else p->s = 2;
+  int t[2], nt = 0;
+  for (int i = 0; i < 3; ++i) if (i != p->s) t[nt++] = i;
+  p->t1 = t[0];
+  p->t2 = t[1];
+  p->singular = true;
+  for (int i = 0; i < 3; ++i) if (bcs[i] != BC_PERIODIC && bcs[i] != BC_NN) p->singular = false;
+  p->s_periodic = bcs[p->s] == BC_PERIODIC;
+
+  auto reject = [&](int code, const char* msg, int a) { fail(code, msg, a); delete p; return (poisson_plan*)nullptr; };
+  for (int r = 0; r < 2; ++r) {
+    AxisTables& A = p->ax[r];
+    A.axis = t[r];
+    A.n = p->dims[A.axis];
+    A.kind = bcs[A.axis];
+    if (A.n % 2 || A.n < 2 || A.n > MAX_TRANSFORM_N)
+      return reject(POISSON_EUNSUPPORTED, "transformed axis length %d must be even and in [2, 1024]", A.n);
+    A.m = A.n / 2;
+    if (!factor_radices(A.m, A.radices))
+      return reject(POISSON_EUNSUPPORTED, "transformed axis length %d: n/2 has a prime factor > 5", A.n);
+  }
+  const int ns = p->dims[p->s];
+  if (ns > MAX_SOLVE_N) return reject(POISSON_EUNSUPPORTED, "elimination axis length %d > 512", ns);
+  if (p->s_periodic && ns < 3) return reject(POISSON_EUNSUPPORTED, "periodic elimination axis needs n >= 3 (got %d)", ns);
+  if (choose_chunks(ns, p->s_periodic, p->P, p->lcmax))
+    return reject(POISSON_EUNSUPPORTED, "elimination axis length %d not supported", ns);
+  p->nu = p->dims[t[0]];
+  p->nv = p->dims[t[1]];
+
+  // host tables
+  std::vector<char> host;
+  auto push = [&](const void* src, size_t bytes) {
+    const size_t off = align_up(host.size(), 256);
+    host.resize(off + bytes);
+    std::memcpy(host.data() + off, src, bytes);
+    return off;
+  };
+  for (int r = 0; r < 2; ++r) {
+    AxisTables& A = p->ax[r];
+    const int n = A.n, m = A.m;
+    std::vector<cplx<double>> tw;
+    for (int t = 0; t < m; ++t) tw.push_back(expm(16LL * t, n));        // e^{-2 pi i t/m}
+    for (int k = 0; k <= m; ++k) tw.push_back(expm(8LL * k, n));        // e^{-2 pi i k/n}
+    for (int k = 0; k <= m; ++k) tw.push_back(expm(2LL * k, n));        // e^{-i pi k/(2n)}
+    for (int j = 0; j < m; ++j) tw.push_back(expm(4LL * j + 1, n));     // e^{-i pi (4j+1)/(4n)}
+    for (int k = 0; k < m; ++k) tw.push_back(expm(4LL * k, n));         // e^{-i pi k/n}
+    std::vector<cplx<float>> twf(tw.size());
+    for (size_t i = 0; i < tw.size(); ++i) twf[i] = {(float)tw[i].re, (float)tw[i].im};
+    A.off_d = push(tw.data(), tw.size() * sizeof(cplx<double>));
+    A.off_f = push(twf.data(), twf.size() * sizeof(cplx<float>));
+  }
+  {
+    const int ns_ = ns;
+    std::vector<double> tri(4 * ns_);
+    axis_rows(axis_widths(p, p->s), bcs[p->s], tri.data());
+    std::vector<float> trif(tri.begin(), tri.end());
+    p->off_tri_d = push(tri.data(), tri.size() * sizeof(double));
+    p->off_tri_f = push(trif.data(), trif.size() * sizeof(float));
+    for (int q = 0; q < 3; ++q) {
+      std::vector<double> ops(4 * (size_t)p->dims[q]);
+      axis_rows(axis_widths(p, q), bcs[q], ops.data());
+      p->off_ops[q] = push(ops.data(), ops.size() * sizeof(double));
+    }
+    std::vector<double> lam;
+    for (int r = 0; r < 2; ++r) {
+      const AxisTables& A = p->ax[r];
+      const double hh = p->h[A.axis];
+      for (int q = 0; q < A.n; ++q) lam.push_back(eigenvalue(A.kind, A.n, q) / (hh * hh));
+    }
+    std::vector<float> lamf(lam.begin(), lam.end());
+    p->off_lam_d = push(lam.data(), lam.size() * sizeof(double));
+    p->off_lam_f = push(lamf.data(), lamf.size() * sizeof(float));
+  }
+  p->tab_bytes = host.size();
+  if (hipGetDevice(&p->device) != hipSuccess) { fail(POISSON_EHIP, "hipGetDevice failed"); delete p; return nullptr; }
+  if (lds_setup_once()) { delete p; return nullptr; }
+  if (hipMalloc(&p->dtab, p->tab_bytes) != hipSuccess) { fail(POISSON_ENOMEM, "table allocation (%zu B) failed", p->tab_bytes); delete p; return nullptr; }
+  if (hipMemcpy(p->dtab, host.data(), p->tab_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    fail(POISSON_EHIP, "table upload failed");
+    (void)hipFree(p->dtab);
+    delete p;
+    return nullptr;
+  }
+  return p;
+}
+
+static void free_workspace(poisson_plan* p) {
+  if (p->f64) (void)hipFree(p->f64);
+  if (p->e32) (void)hipFree(p->e32);
+  if (p->stats) (void)hipFree(p->stats);
+  if (p->stats_host) (void)hipHostFree(p->stats_host);
+  p->f64 = nullptr;
+  p->e32 = nullptr;
+  p->stats = nullptr;
+  p->stats_host = nullptr;
+  p->ws_bytes = 0;
+}
+
+extern "C" void plan_destroy(poisson_plan* p) {
+  if (!p) return;
+  free_workspace(p);
+  if (p->dtab) (void)hipFree(p->dtab);
+  delete p;
+}
+
+static size_t field_points(const poisson_plan* p) {
+  return (size_t)p->dims[0] * p->dims[1] * p->dims[2];
+}
+
+extern "C" size_t plan_workspace_bytes(const poisson_plan* p) {
+  if (!p) return 0;
+  size_t ws = p->ws_bytes;
+  if (p->mode == POISSON_FP32_REFINED && ws == 0)
+    ws = field_points(p) * (sizeof(double) + sizeof(float)) + 4096;
+  return p->tab_bytes + ws;
+}
+
+extern "C" int plan_roles(const poisson_plan* p, int roles[3]) {
+  if (!p || !roles) return fail(POISSON_EINVAL, "null argument");
+  roles[0] = p->t1;
+  roles[1] = p->t2;
+  roles[2] = p->s;
+  return POISSON_OK;
+}
+
+extern "C" int transform_stage(poisson_plan* p, int role, int inverse, double* field, hipStream_t st) {
+  if (!p || !field) return fail(POISSON_EINVAL, "null argument");
+  if (role < 0 || role > 1) return fail(POISSON_EINVAL, "role must be 0 or 1");
+  return launch_r2r<double>(p, role, inverse ? 1 : 0, field, st);
+}
+
+extern "C" int tridiag_stage(poisson_plan* p, double* field, hipStream_t st) {
+  if (!p || !field) return fail(POISSON_EINVAL, "null argument");
+  return launch_tridiag<double>(p, field, st);
+}
+
+// ------------------------------------------------------------------ refinement
+
+extern "C" int plan_set_precision(poisson_plan* p, int mode, double tol, int max_iters) {
+  if (!p) return fail(POISSON_EINVAL, "null plan");
+  if (mode != POISSON_FP64 && mode != POISSON_FP32_REFINED) return fail(POISSON_EINVAL, "unknown precision mode %d", mode);
+  if (mode == POISSON_FP32_REFINED) {
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(POISSON_EINVAL, "tol must be finite and > 0");
+    if (max_iters < 1 || max_iters > 64) return fail(POISSON_EINVAL, "max_iters must be in [1, 64]");
+    if (!p->f64) {
+      const size_t N = field_points(p);
+      if (hipMalloc(&p->f64, N * sizeof(double)) != hipSuccess ||
+          hipMalloc(&p->e32, N * sizeof(float)) != hipSuccess ||
+          hipMalloc(&p->stats, REFINE_STAT_SLOTS * sizeof(double)) != hipSuccess ||
+          hipHostMalloc(&p->stats_host, REFINE_STAT_SLOTS * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        free_workspace(p);
+        return fail(POISSON_ENOMEM, "refinement workspace allocation failed");
+      }
+      p->ws_bytes = N * (sizeof(double) + sizeof(float)) + REFINE_STAT_SLOTS * sizeof(double);
+    }
+    p->tol = tol;
+    p->max_iters = max_iters;
+  }
+  p->mode = mode;
+  return POISSON_OK;
+}
+
+
+static int solve_refined(poisson_plan* p, double* rhs, hipStream_t st);
+
+extern "C" int solve(poisson_plan* p, double* rhs, hipStream_t st) {
+  if (!p || !rhs) return fail(POISSON_EINVAL, "null argument");
+  if (p->mode == POISSON_FP32_REFINED) return solve_refined(p, rhs, st);
+  p->last_iters = 1;
+  p->last_rel = 0.0;
+  p->last_converged = 1;
+  return solve_typed<double>(p, rhs, st);
+}
+
+extern "C" int solve_status(poisson_plan* p, int* iters, double* rel) {
+  if (!p) return fail(POISSON_EINVAL, "null plan");
+  if (p->mode == POISSON_FP32_REFINED && p->stats_host) {
+    // the refined solve copies its status block to pinned host memory at the
+    // end of its stream: sweeps that ran have ||e||^2 >= 0
+    const double* h = p->stats_host;
+    int it = 1;
+    for (int sweep = 1; sweep < p->max_iters; ++sweep)
+      if (h[4 + 2 * sweep] >= 0.0) ++it;
+    p->last_iters = it;
+    p->last_rel = h[3];
+    p->last_converged = h[2] != 0.0;
+  }
+  if (iters) *iters = p->last_iters;
+  if (rel) *rel = p->last_rel;
+  return p->last_converged ? POISSON_OK : POISSON_ENOTCONVERGED;
+}
+
+static RefineGeom refine_geom(const poisson_plan* p) {
+  RefineGeom G{};
+  for (int q = 0; q < 3; ++q) {
+    const int n = p->dims[q];
+    const double* base = reinterpret_cast<const double*>(p->dtab + p->off_ops[q]);
+    G.ax[q] = OpAxis{base, base + n, base + 2 * n, base + 3 * n, n};
+  }
+  G.npts = (long long)field_points(p);
+  G.stats = p->stats;
+  return G;
+}
+
+// FP32 solve + FP64 refinement (fixed launch sequence; sweeps after
+// convergence return at once through the device skip flag):
+//   f~ = f (minus its weighted mean if singular), Phi = solve32(f~);
+//   repeat: r = f~ - A Phi (FP64), e = solve32(r), Phi += e (FP64);
+//   finally, if singular, remove the weighted mean of Phi (FP64).
+static int solve_refined(poisson_plan* p, double* rhs, hipStream_t st) {
+  const long long N = (long long)field_points(p);
+  const RefineGeom G = refine_geom(p);
+  const int nb = (int)std::min<long long>(REFINE_BLOCKS, (N + REFINE_NT - 1) / REFINE_NT);
+  const dim3 grid(nb), block(REFINE_NT);
+  hipLaunchKernelGGL(refine_init_kernel, dim3(1), dim3(256), 0, st, p->stats);
+  if (p->singular) {
+    hipLaunchKernelGGL(refine_wsum_kernel, grid, block, 0, st, (const double*)rhs, G);
+    hipLaunchKernelGGL(refine_mean_kernel, dim3(1), block, 0, st, p->stats, nb);
+  }
+  hipLaunchKernelGGL(refine_prep_kernel, grid, block, 0, st, (const double*)rhs, p->f64, p->e32,
+                     (const double*)p->stats, (int)p->singular, N);
+  HIP_TRY(hipGetLastError());
+  int rc;
+  if ((rc = solve_typed<float>(p, p->e32, st))) return rc;
+  hipLaunchKernelGGL(refine_widen_kernel, grid, block, 0, st, (const float*)p->e32, rhs, N);
+  for (int sweep = 1; sweep < p->max_iters; ++sweep) {
+    hipLaunchKernelGGL(refine_residual_kernel, grid, block, 0, st, (const double*)rhs,
+                       (const double*)p->f64, p->e32, G);
+    if ((rc = solve_typed<float>(p, p->e32, st, p->stats))) return rc;
+    hipLaunchKernelGGL(refine_update_kernel, grid, block, 0, st, rhs, (const float*)p->e32, G);
+    hipLaunchKernelGGL(refine_status_kernel, dim3(1), block, 0, st, p->stats, nb, sweep, p->tol);
+  }
+  if (p->singular) {
+    hipLaunchKernelGGL(refine_wsum_kernel, grid, block, 0, st, (const double*)rhs, G);
+    hipLaunchKernelGGL(refine_mean_kernel, dim3(1), block, 0, st, p->stats, nb);
+    hipLaunchKernelGGL(refine_shift_kernel, grid, block, 0, st, rhs, (const double*)p->stats, N);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(p->stats_host, p->stats, REFINE_PARTIALS * sizeof(double),
+                         hipMemcpyDeviceToHost, st));
+  return POISSON_OK;
+}
+
+// ------------------------------------------------------------------ batch
+
+extern "C" int batch_solve(poisson_plan* const* plans, double* const* rhs, int count, hipStream_t st) {
+  if (count < 0 || (count > 0 && (!plans || !rhs))) return fail(POISSON_EINVAL, "bad batch arguments");
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i] || !rhs[i]) return fail(POISSON_EINVAL, "null plan or field at batch index %d", i);
+    if (plans[i]->mode != POISSON_FP64) return fail(POISSON_EINVAL, "batch_solve takes FP64 plans (index %d)", i);
+  }
+  for (int i = 0; i < count; ++i) {
+    const int rc = solve_typed<double>(plans[i], rhs[i], st);
+    if (rc) return rc;
+  }
+  return POISSON_OK;
+}

@@ -1,0 +1,220 @@
+// refine_kernels.h - FP64 kernels around the FP32 solve for iterative
+// refinement: seven-point residual (Eq. (poi), finite-volume rows on the
+// non-uniform axis), solution update, width-weighted means, and the norms
+// that decide when to stop.  All reductions are fixed-order (per-block
+// partial sums, then one block adding the partials in index order), so a
+// result does not depend on scheduling.
+//
+// Device status block (doubles):
+//   [0] skip flag (1 once refinement has converged: later sweeps return)
+//   [1] scratch scalar (weighted mean)
+//   [2] converged flag
+//   [3] relative update of the previous sweep
+//   [4 + 2s], [5 + 2s]: ||e_s||^2 and ||Phi_s||^2 of sweep s (-1 if not run)
+//   [REFINE_PARTIALS ...]: per-block partial sums (2 per block)
+#pragma once
+#include "device_common.h"
+
+namespace poisson_dev {
+
+static constexpr int REFINE_MAX_SWEEPS = 64;
+static constexpr int REFINE_BLOCKS = 1024;
+static constexpr int REFINE_NT = 256;
+static constexpr int REFINE_PARTIALS = 4 + 2 * REFINE_MAX_SWEEPS + 8;
+static constexpr int REFINE_STAT_SLOTS = REFINE_PARTIALS + 2 * REFINE_BLOCKS;
+
+struct OpAxis {            // one axis of the operator: rows a, b, c and widths h
+  const double* a;
+  const double* b;
+  const double* c;
+  const double* h;
+  int n;
+};
+
+struct RefineGeom {
+  OpAxis ax[3];            // x, y, z
+  long long npts;
+  double* stats;
+};
+
+__device__ __forceinline__ bool refine_skip(const double* stats) { return stats[0] != 0.0; }
+
+template <int NT>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = a;
+  sh[NT + tid] = b;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      sh[tid] += sh[tid + s];
+      sh[NT + tid] += sh[NT + tid + s];
+    }
+    __syncthreads();
+  }
+  a = sh[0];
+  b = sh[NT];
+}
+
+__device__ __forceinline__ void decompose(long long idx, int nx, int ny, int& i, int& j, int& k) {
+  i = (int)(idx % nx);
+  const long long r = idx / nx;
+  j = (int)(r % ny);
+  k = (int)(r / ny);
+}
+
+// reset the status block (a fill kernel rather than a memset, so the
+// sequence can be captured in a graph)
+__global__ void refine_init_kernel(double* stats) {
+  const int t = threadIdx.x;
+  for (int i = t; i < REFINE_PARTIALS; i += blockDim.x) stats[i] = i >= 4 ? -1.0 : 0.0;
+}
+
+// partial sums of w*x (slot 0) and w (slot 1), w = hx_i hy_j hz_k
+__global__ __launch_bounds__(REFINE_NT) void refine_wsum_kernel(const double* __restrict__ x,
+                                                                 RefineGeom G) {
+  __shared__ double sh[2 * REFINE_NT];
+  double sx = 0.0, sw = 0.0;
+  const int nx = G.ax[0].n, ny = G.ax[1].n;
+  for (long long idx = blockIdx.x * (long long)REFINE_NT + threadIdx.x; idx < G.npts;
+       idx += (long long)gridDim.x * REFINE_NT) {
+    int i, j, k;
+    decompose(idx, nx, ny, i, j, k);
+    const double w = G.ax[0].h[i] * G.ax[1].h[j] * G.ax[2].h[k];
+    sx += w * x[idx];
+    sw += w;
+  }
+  block_sum2<REFINE_NT>(sx, sw, sh);
+  if (threadIdx.x == 0) {
+    G.stats[REFINE_PARTIALS + 2 * blockIdx.x] = sx;
+    G.stats[REFINE_PARTIALS + 2 * blockIdx.x + 1] = sw;
+  }
+}
+
+// stats[1] = (sum of slot 0) / (sum of slot 1)   (weighted mean)
+__global__ __launch_bounds__(REFINE_NT) void refine_mean_kernel(double* stats, int nblocks) {
+  __shared__ double sh[2 * REFINE_NT];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += REFINE_NT) {
+    a += stats[REFINE_PARTIALS + 2 * i];
+    b += stats[REFINE_PARTIALS + 2 * i + 1];
+  }
+  block_sum2<REFINE_NT>(a, b, sh);
+  if (threadIdx.x == 0) stats[1] = b > 0.0 ? a / b : 0.0;
+}
+
+// f64 = rhs - mean (mean = stats[1] if `project`), e32 = (float) f64
+__global__ __launch_bounds__(REFINE_NT) void refine_prep_kernel(const double* __restrict__ rhs,
+                                                                 double* __restrict__ f64,
+                                                                 float* __restrict__ e32,
+                                                                 const double* stats, int project,
+                                                                 long long npts) {
+  const double mean = project ? stats[1] : 0.0;
+  for (long long idx = blockIdx.x * (long long)REFINE_NT + threadIdx.x; idx < npts;
+       idx += (long long)gridDim.x * REFINE_NT) {
+    const double f = rhs[idx] - mean;
+    f64[idx] = f;
+    e32[idx] = (float)f;
+  }
+}
+
+// phi = (double) e32
+__global__ __launch_bounds__(REFINE_NT) void refine_widen_kernel(const float* __restrict__ e32,
+                                                                  double* __restrict__ phi,
+                                                                  long long npts) {
+  for (long long idx = blockIdx.x * (long long)REFINE_NT + threadIdx.x; idx < npts;
+       idx += (long long)gridDim.x * REFINE_NT)
+    phi[idx] = (double)e32[idx];
+}
+
+// x -= stats[1]
+__global__ __launch_bounds__(REFINE_NT) void refine_shift_kernel(double* __restrict__ x,
+                                                                  const double* stats,
+                                                                  long long npts) {
+  const double mean = stats[1];
+  for (long long idx = blockIdx.x * (long long)REFINE_NT + threadIdx.x; idx < npts;
+       idx += (long long)gridDim.x * REFINE_NT)
+    x[idx] -= mean;
+}
+
+__device__ __forceinline__ double op_axis(const OpAxis& A, const double* __restrict__ phi,
+                                          long long idx, long long stride, int q, double centre) {
+  // a_q phi_{q-1} + b_q phi_q + c_q phi_{q+1}; a_0 / c_{n-1} are the periodic
+  // wrap couplings (zero at a wall, where the ghost rule is in b)
+  const int n = A.n;
+  const long long lo = q > 0 ? idx - stride : idx + (long long)(n - 1) * stride;
+  const long long hi = q < n - 1 ? idx + stride : idx - (long long)(n - 1) * stride;
+  return A.a[q] * phi[lo] + A.b[q] * centre + A.c[q] * phi[hi];
+}
+
+// e32 = (float)(f64 - A phi), FP64 arithmetic
+__global__ __launch_bounds__(REFINE_NT) void refine_residual_kernel(const double* __restrict__ phi,
+                                                                     const double* __restrict__ f64,
+                                                                     float* __restrict__ e32,
+                                                                     RefineGeom G) {
+  if (refine_skip(G.stats)) return;
+  const int nx = G.ax[0].n, ny = G.ax[1].n;
+  const long long sy = nx, sz = (long long)nx * ny;
+  for (long long idx = blockIdx.x * (long long)REFINE_NT + threadIdx.x; idx < G.npts;
+       idx += (long long)gridDim.x * REFINE_NT) {
+    int i, j, k;
+    decompose(idx, nx, ny, i, j, k);
+    const double c = phi[idx];
+    double Ap = op_axis(G.ax[0], phi, idx, 1, i, c);
+    Ap += op_axis(G.ax[1], phi, idx, sy, j, c);
+    Ap += op_axis(G.ax[2], phi, idx, sz, k, c);
+    e32[idx] = (float)(f64[idx] - Ap);
+  }
+}
+
+// phi += e; per-block partial ||e||^2 and ||phi||^2
+__global__ __launch_bounds__(REFINE_NT) void refine_update_kernel(double* __restrict__ phi,
+                                                                   const float* __restrict__ e32,
+                                                                   RefineGeom G) {
+  if (refine_skip(G.stats)) return;
+  __shared__ double sh[2 * REFINE_NT];
+  double se = 0.0, sp = 0.0;
+  for (long long idx = blockIdx.x * (long long)REFINE_NT + threadIdx.x; idx < G.npts;
+       idx += (long long)gridDim.x * REFINE_NT) {
+    const double e = (double)e32[idx];
+    const double x = phi[idx] + e;
+    phi[idx] = x;
+    se += e * e;
+    sp += x * x;
+  }
+  block_sum2<REFINE_NT>(se, sp, sh);
+  if (threadIdx.x == 0) {
+    G.stats[REFINE_PARTIALS + 2 * blockIdx.x] = se;
+    G.stats[REFINE_PARTIALS + 2 * blockIdx.x + 1] = sp;
+  }
+}
+
+// Record sweep `sweep`: rel = ||e|| / ||phi||; the error left after the
+// update is estimated from the contraction rho = rel / rel_prev as
+// rel * rho / (1 - rho); once that is <= tol the remaining sweeps are skipped.
+__global__ __launch_bounds__(REFINE_NT) void refine_status_kernel(double* stats, int nblocks,
+                                                                   int sweep, double tol) {
+  if (refine_skip(stats)) return;
+  __shared__ double sh[2 * REFINE_NT];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += REFINE_NT) {
+    a += stats[REFINE_PARTIALS + 2 * i];
+    b += stats[REFINE_PARTIALS + 2 * i + 1];
+  }
+  block_sum2<REFINE_NT>(a, b, sh);
+  if (threadIdx.x == 0) {
+    stats[4 + 2 * sweep] = a;
+    stats[5 + 2 * sweep] = b;
+    const double rel = b > 0.0 ? sqrt(a / b) : 0.0;
+    const double prev = stats[3] > 0.0 ? stats[3] : 1.0;
+    const double rho = rel / prev;
+    const double est = rho < 1.0 ? rel * rho / (1.0 - rho) : rel;
+    stats[3] = rel;
+    if (est <= tol) {
+      stats[2] = 1.0;
+      stats[0] = 1.0;
+    }
+  }
+}
+
+}  // namespace poisson_dev

@@ -1,0 +1,185 @@
+"""Thin ctypes binding of the C ABI in ``include/poisson.h``.
+
+Argument marshalling only: every step of a solve runs in the HIP library
+(``libpoisson_hip.so``).  PyTorch supplies device memory and streams.  If the
+library is missing the binding raises; there is no other code path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpoisson_hip.so")
+
+BC = {"P": 0, "NN": 1, "DD": 2, "ND": 3, "DN": 4}
+AXES = "xyz"
+FP64 = 0
+FP32_REFINED = 1
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOTCONVERGED = 0, -1, -2, -3, -4, -5
+
+# exported symbol -> (restype, argtypes); mirrors include/poisson.h
+_VP = ctypes.c_void_p
+SIGNATURES = {
+    "plan_create": (_VP, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                          ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                          ctypes.c_int, ctypes.c_int]),
+    "solve": (ctypes.c_int, [_VP, _VP, _VP]),
+    "plan_destroy": (None, [_VP]),
+    "last_error": (ctypes.c_int, []),
+    "last_error_message": (ctypes.c_char_p, []),
+    "plan_set_precision": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_double, ctypes.c_int]),
+    "plan_workspace_bytes": (ctypes.c_size_t, [_VP]),
+    "solve_status": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_double)]),
+    "batch_solve": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.c_int, _VP]),
+    "plan_roles": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int)]),
+    "transform_stage": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, _VP]),
+    "tridiag_stage": (ctypes.c_int, [_VP, _VP, _VP]),
+}
+
+_lib = None
+
+
+class PoissonError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"[{code}] {message}")
+        self.code = code
+
+
+def lib():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run `python -m paper_1802_10323_amd.build`)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        L = lib()
+        msg = L.last_error_message()
+        raise PoissonError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _field_ptr(t, dtype_name="float64"):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("field must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("field must be a device tensor")
+    if t.dtype != getattr(torch, dtype_name):
+        raise ValueError(f"field must be {dtype_name}")
+    if not t.is_contiguous():
+        raise ValueError("field must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A solver plan for an nx x ny x nz staggered grid (owns device tables).
+
+    ``dz`` is an array of nz cell widths (z may be stretched); x and y are
+    uniform with spacings dx, dy.  ``bcs`` = (bc_x, bc_y, bc_z), each one of
+    "P", "NN", "DD", "ND", "DN" (first letter = low face)."""
+
+    def __init__(self, nx, ny, nz, dx, dy, dz, bcs):
+        L = lib()
+        dz = np.ascontiguousarray(np.broadcast_to(np.asarray(dz, dtype=np.float64), (nz,)))
+        self.shape = (nz, ny, nx)
+        self.bcs = tuple(bcs)
+        codes = [BC[b] if isinstance(b, str) else int(b) for b in bcs]
+        h = L.plan_create(int(nx), int(ny), int(nz), float(dx), float(dy),
+                          dz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), *codes)
+        if not h:
+            _check(L.last_error() or EINVAL)
+        self._h = ctypes.c_void_p(h)
+
+    @classmethod
+    def from_problem(cls, p):
+        return cls(p.nx, p.ny, p.nz, p.dx, p.dy, p.hz, p.bcs)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("plan destroyed")
+        return self._h
+
+    def solve(self, field, stream=None):
+        """Solve in place: ``field`` (float64, device, contiguous, shape
+        (nz, ny, nx)) holds f on entry and Phi on exit (asynchronous)."""
+        if tuple(field.shape) != self.shape and field.numel() != int(np.prod(self.shape)):
+            raise ValueError(f"field shape {tuple(field.shape)} != {self.shape}")
+        _check(lib().solve(self.handle, _field_ptr(field), _stream_handle(stream)))
+        return field
+
+    def set_precision(self, mode, tol=1e-10, max_iters=4):
+        _check(lib().plan_set_precision(self.handle, int(mode), float(tol), int(max_iters)))
+
+    def status(self):
+        """(fp32 solves performed, last relative update, converged) of the
+        last solve; valid once its stream has completed."""
+        it = ctypes.c_int(0)
+        rel = ctypes.c_double(0.0)
+        rc = lib().solve_status(self.handle, ctypes.byref(it), ctypes.byref(rel))
+        if rc not in (OK, ENOTCONVERGED):
+            _check(rc)
+        return it.value, rel.value, rc == OK
+
+    @property
+    def roles(self):
+        r = (ctypes.c_int * 3)()
+        _check(lib().plan_roles(self.handle, r))
+        return tuple(AXES[i] for i in r)
+
+    @property
+    def workspace_bytes(self):
+        return int(lib().plan_workspace_bytes(self.handle))
+
+    def transform_stage(self, role, inverse, field, stream=None):
+        _check(lib().transform_stage(self.handle, int(role), int(bool(inverse)),
+                                     _field_ptr(field), _stream_handle(stream)))
+        return field
+
+    def tridiag_stage(self, field, stream=None):
+        _check(lib().tridiag_stage(self.handle, _field_ptr(field), _stream_handle(stream)))
+        return field
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_solve(plans, fields, stream=None):
+    """Solve many independent problems (FP64 plans) in one batched launch
+    sequence; fields[i] is solved in place with plans[i]."""
+    n = len(plans)
+    if len(fields) != n:
+        raise ValueError("plans and fields differ in length")
+    hp = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    fp = (ctypes.c_void_p * n)(*[_field_ptr(f).value for f in fields])
+    _check(lib().batch_solve(hp, fp, n, _stream_handle(stream)))
+    return fields
