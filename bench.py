@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X Poisson solver: grid points solved per second.
+
+One step = one complete FP64 solve (forward transforms t1, t2, elimination
+along s, backward transforms t2, t1) of the channel workload: 512 x 256 x 192
+cells, Lx = 4 pi, Ly = 2 pi, Lz = 2, periodic x/y, Neumann z clustered by tanh
+(beta 1.8), seeded synthetic right-hand side.  Inputs are resident in HBM
+before the timed region (one fresh copy per step).  The timed region is K
+steps between two device synchronisations; HIP events on the solver's stream
+separate the five kernels of every step, giving each kernel's average
+duration for the roofline.
+
+Prints one JSON line.  Extra objects: `roofline` (dominant kernel: algorithmic
+16 B/point per launch over its measured duration, against the 8 TB/s HBM
+peak), `cpu_baseline` (the FP64 oracle on the host cores), `kernels` (every
+kernel's duration and bandwidth), and `forms` (the FP32 + refinement, batched
+and served forms, each measured separately; not part of `value`).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+BYTES_PER_POINT_FP64 = 16.0     # one sweep: read + write 8 B per point
+STAGES = ("fwd_t1", "fwd_t2", "tridiag", "inv_t2", "inv_t1")
+KERNEL_SOURCES = ("r2r_kernel.h", "tridiag_kernel.h", "device_common.h")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1802_10323_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload, stage):
+    """HBM bytes per launch measured by rocprofv3 counters (profiles/), or
+    None when absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch", {}).get(stage)
+
+
+def make_problem(workload, seed=0):
+    from paper_1802_10323_amd import inputs
+    if workload == "channel":
+        return inputs.channel(seed), "channel 512x256x192 (P,P,NN; tanh z beta 1.8; Lx=4pi Ly=2pi Lz=2)"
+    if workload == "cube":
+        return inputs.cube(seed), "cube 512^3 (DD,ND,P; uniform, unit box)"
+    if workload == "small":
+        return inputs.small(seed), "small 32^3 (P,P,NN; uniform, unit box)"
+    raise SystemExit(f"unknown workload {workload!r}")
+
+
+def time_fp64(plan, src, steps, warmup, torch):
+    """K timed steps of the five stage kernels, with events between them."""
+    N = src.numel()
+    nbuf = max(1, min(steps, int(12e9 // (8 * N))))
+    bufs = [torch.empty_like(src) for _ in range(nbuf)]
+    stream = torch.cuda.current_stream()
+
+    def step(buf, evs=None):
+        if evs:
+            evs[0].record(stream)
+        plan.transform_stage(0, False, buf)
+        if evs:
+            evs[1].record(stream)
+        plan.transform_stage(1, False, buf)
+        if evs:
+            evs[2].record(stream)
+        plan.tridiag_stage(buf)
+        if evs:
+            evs[3].record(stream)
+        plan.transform_stage(1, True, buf)
+        if evs:
+            evs[4].record(stream)
+        plan.transform_stage(0, True, buf)
+        if evs:
+            evs[5].record(stream)
+
+    for i in range(warmup):
+        bufs[i % nbuf].copy_(src)
+        step(bufs[i % nbuf])
+    for b in bufs:
+        b.copy_(src)
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        step(bufs[s % nbuf], events[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per_stage = [0.0] * 5
+    for evs in events:
+        for i in range(5):
+            per_stage[i] += evs[i].elapsed_time(evs[i + 1])
+    per_stage = [v / steps for v in per_stage]        # ms
+    return t1 - t0, per_stage
+
+
+def cpu_baseline(prob, budget_s=12.0, max_reps=6):
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    times = []
+    phi = None
+    t_start = time.perf_counter()
+    while len(times) < max_reps and (time.perf_counter() - t_start) < budget_s:
+        t = time.perf_counter()
+        phi = oracle.solve(prob.rhs, prob.hx, prob.hy, prob.hz, *prob.bcs)
+        times.append(time.perf_counter() - t)
+    med = float(np.median(times))
+    return {"value": prob.points / med, "unit": "points/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"full workload ({prob.points} points), {len(times)} FP64 oracle solves "
+                      f"(dense Table-2 sums via BLAS + Thomas), median {med:.3f} s"}, phi
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="channel", choices=["channel", "cube", "small"])
+    ap.add_argument("--forms", default="all",
+                    help="extra forms to measure: none, or a comma list of mixed,batch,serve (all)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("this build drives one GPU: multi-GPU runs are not part of it "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("RANK", "0")) != 0:
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_1802_10323_amd import Plan, lib
+
+    lib()
+    torch.cuda.set_device(0)
+    prob, workload_desc = make_problem(args.workload)
+    log(f"[bench] workload {workload_desc}: {prob.points} points")
+    plan = Plan.from_problem(prob)
+    src = torch.from_numpy(prob.rhs).cuda()
+
+    elapsed, per_stage = time_fp64(plan, src, args.steps, args.warmup, torch)
+    N = prob.points
+    value = N * args.steps / elapsed
+    ms_per_step = elapsed / args.steps * 1e3
+    log(f"[bench] {args.steps} steps in {elapsed:.4f} s: {value:.4e} points/s, {ms_per_step:.3f} ms/step")
+
+    roles = plan.roles
+    names = {"fwd_t1": f"r2r forward {roles[0]}", "fwd_t2": f"r2r forward {roles[1]}",
+             "tridiag": f"tridiagonal along {roles[2]}", "inv_t2": f"r2r backward {roles[1]}",
+             "inv_t1": f"r2r backward {roles[0]}"}
+    alg_bytes = BYTES_PER_POINT_FP64 * N
+    kernels = []
+    for st, ms in zip(STAGES, per_stage):
+        kernels.append({"stage": st, "kernel": names[st], "avg_ms": round(ms, 5),
+                        "achieved_GBs": round(alg_bytes / (ms * 1e-3) / 1e9, 1),
+                        "frac": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+    dom = max(range(5), key=lambda i: per_stage[i])
+    achieved = alg_bytes / (per_stage[dom] * 1e-3) / 1e9
+    traffic = stored_traffic(args.workload, STAGES[dom])
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": names[STAGES[dom]], "algorithmic_bytes_per_launch": alg_bytes}
+
+    # correctness of the product entry point on this workload
+    check = src.clone()
+    plan.solve(check)
+    torch.cuda.synchronize()
+    gpu_phi = check.cpu().numpy()
+    del check
+
+    cpu = None
+    rel = None
+    if not args.no_cpu_baseline:
+        cpu, phi = cpu_baseline(prob)
+        rel = float(np.linalg.norm(gpu_phi - phi) / np.linalg.norm(phi))
+        log(f"[bench] oracle {cpu['value']:.3e} points/s on {cpu['cores']} threads; GPU rel-L2 vs oracle {rel:.3e}")
+
+    forms = {}
+    wanted = set() if args.forms == "none" else (
+        {"mixed", "batch", "serve"} if args.forms == "all" else set(args.forms.split(",")))
+    if wanted:
+        from paper_1802_10323_amd import benchforms
+        forms = benchforms.run(wanted, log)
+
+    out = {
+        "metric": "Poisson grid points solved/s (FP64 direct solve) + %HBM roofline",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload_desc, "points": N, "roles": "".join(roles),
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "hbm_effective": {"bytes_per_point": 5 * BYTES_PER_POINT_FP64,
+                          "GBs": round(5 * alg_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+                          "frac": round(5 * alg_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "kernels": kernels,
+        "rel_l2_vs_oracle": rel,
+        "cpu_baseline": cpu,
+        "forms": forms,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

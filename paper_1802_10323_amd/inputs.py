@@ -144,8 +144,9 @@ def channel(seed=0, nx=512, ny=256, nz=192, modes=64, noise=1e-3):
     hy = uniform_widths(ny, Ly)
     hz = tanh_widths(nz, Lz, 1.8)
     xc, yc, zc = centres(hx), centres(hy), centres(hz)
-    f = np.zeros((nz, ny, nx))
-    for _ in range(modes):
+    FZ = np.empty((modes, nz))
+    FYX = np.empty((modes, ny * nx))
+    for m in range(modes):
         kx = int(rng.integers(0, nx // 2 + 1))
         ky = int(rng.integers(0, ny // 2 + 1))
         kz = int(rng.integers(0, nz))
@@ -154,8 +155,9 @@ def channel(seed=0, nx=512, ny=256, nz=192, modes=64, noise=1e-3):
         amp = rng.uniform(-1.0, 1.0)
         fx = np.cos(2.0 * math.pi * kx * xc / Lx - px)
         fy = np.cos(2.0 * math.pi * ky * yc / Ly - py)
-        fz = np.cos(math.pi * kz * zc / Lz)
-        f += amp * fz[:, None, None] * fy[None, :, None] * fx[None, None, :]
+        FZ[m] = amp * np.cos(math.pi * kz * zc / Lz)
+        FYX[m] = np.outer(fy, fx).reshape(-1)
+    f = (FZ.T @ FYX).reshape(nz, ny, nx)              # sum of the separable modes
     f += noise * rng.uniform(-1.0, 1.0, size=f.shape)
     f = remove_weighted_mean(f, hx, hy, hz)
     return Problem(hx, hy, hz, "P", "P", "NN", f, name="channel")
