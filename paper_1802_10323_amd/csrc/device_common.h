@@ -2,17 +2,22 @@
 //
 // Every kernel works on "lines": the n values of the field along the axis the
 // kernel processes (a transformed axis or the elimination axis).  A workgroup
-// stages a tile of `nl` lines in LDS, laid out point-major / line-minor:
+// stages a tile of nl = 2^lognl lines in LDS, laid out point-major /
+// line-minor:
 //   element (line l, point p) at lds[p * nlp + l]      (nlp >= nl: row pitch)
 // so that lanes with consecutive l touch consecutive LDS words.
 //
 // Two tile shapes exist, chosen by the axis stride:
 //  * strided  - the processed axis is y or z; lines run along the contiguous
-//               x axis, so a tile holds `txw` consecutive x positions times
-//               `nbt` consecutive positions of the third ("batch") axis, and
-//               every global access of a row of the tile is contiguous in x.
-//  * contiguous - the processed axis is x itself; a tile holds `nl`
-//               consecutive lines, each n contiguous values.
+//               x axis, so a tile holds txw = 2^logtxw consecutive x positions
+//               times nbt = 2^lognbt consecutive positions of the third
+//               ("batch") axis, and every global access of a row of the tile
+//               is contiguous in x;
+//  * contiguous - the processed axis is x itself; a tile holds nl consecutive
+//               lines, each n contiguous values, read by 2^logtpl lanes per
+//               line.
+// All index arithmetic is 32-bit shifts and masks except the final element
+// offset (64-bit).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -49,46 +54,84 @@ struct LineGeom {
   int nx;           // extent of the lane (x) axis
   int nb;           // extent of the batch axis
   long long sb;     // element stride of the batch axis
-  int txw;          // x positions per tile
-  int nbt;          // batch positions per tile
+  int logtxw;       // x positions per tile = 2^logtxw
+  int lognbt;       // batch positions per tile = 2^lognbt
   int tiles_x;      // ceil(nx / txw)
   // contiguous layout
-  long long nlines; // number of lines (each n contiguous values, stride n)
+  int nlines;       // number of lines (each n contiguous values, stride n)
+  int logtpl;       // lanes per line in the contiguous loaders = 2^logtpl
   // both
-  int nl;           // lines per tile
-  long long ntiles; // tiles in the launch
+  int lognl;        // lines per tile = 2^lognl
+  int ntiles;       // tiles in the launch
 };
 
-// Global element offset of the first point of line l of tile `tile`, or -1
-// if that line lies outside the field (ragged last tile).
-__device__ __forceinline__ long long line_base(const LineGeom& g, long long tile, int l) {
+// First line of a tile: x0/b0 (strided) or line index L0 (contiguous).
+struct TileOrigin {
+  int x0, b0, L0;
+};
+
+__device__ __forceinline__ TileOrigin tile_origin(const LineGeom& g, int tile) {
+  TileOrigin o{0, 0, 0};
   if (g.layout == 0) {
-    const long long tx = tile % g.tiles_x;
-    const long long tb = tile / g.tiles_x;
-    const long long x = tx * g.txw + (l % g.txw);
-    const long long b = tb * g.nbt + (l / g.txw);
-    if (l >= g.nl || x >= g.nx || b >= g.nb) return -1;
-    return x + b * g.sb;
+    const int tb = tile / g.tiles_x;
+    o.x0 = (tile - tb * g.tiles_x) << g.logtxw;
+    o.b0 = tb << g.lognbt;
+  } else {
+    o.L0 = tile << g.lognl;
   }
-  const long long L = tile * g.nl + l;
-  if (l >= g.nl || L >= g.nlines) return -1;
-  return L * g.n;
+  return o;
 }
 
-// Spectral coordinates (u, v) of line l of a tile: the indices along the two
-// other axes, u along the lane / first line axis, v along the second.
-__device__ __forceinline__ void line_coords(const LineGeom& g, long long tile, int l, int nu,
+// Element offset of point 0 of line l of the tile, or -1 if the line lies
+// outside the field (ragged last tile).
+__device__ __forceinline__ long long line_base(const LineGeom& g, const TileOrigin& o, int l) {
+  if (g.layout == 0) {
+    const int x = o.x0 + (l & ((1 << g.logtxw) - 1));
+    const int b = o.b0 + (l >> g.logtxw);
+    if (x >= g.nx || b >= g.nb) return -1;
+    return x + (long long)b * g.sb;
+  }
+  const int L = o.L0 + l;
+  if (L >= g.nlines) return -1;
+  return (long long)L * g.n;
+}
+
+// Coordinates (u, v) of line l along the two axes other than the processed
+// one: u along the lower-numbered axis, v along the higher.
+__device__ __forceinline__ void line_coords(const LineGeom& g, const TileOrigin& o, int l, int nu,
                                             int& u, int& v) {
   if (g.layout == 0) {
-    const long long tx = tile % g.tiles_x;
-    const long long tb = tile / g.tiles_x;
-    u = (int)(tx * g.txw + (l % g.txw));
-    v = (int)(tb * g.nbt + (l / g.txw));
+    u = o.x0 + (l & ((1 << g.logtxw) - 1));
+    v = o.b0 + (l >> g.logtxw);
   } else {
-    const long long L = tile * g.nl + l;
-    u = (int)(L % nu);
-    v = (int)(L / nu);
+    const int L = o.L0 + l;
+    v = L / nu;
+    u = L - v * nu;
   }
+}
+
+// Visit every (line, point) of a tile once, with coalesced global order:
+// f(l, p, base) with base = line_base(l) (negative for a line outside the field).
+template <int NT, typename F>
+__device__ __forceinline__ void for_tile(const LineGeom& g, const TileOrigin& o, int tid, F&& f) {
+  if (g.layout == 0) {
+    const int l = tid & ((1 << g.lognl) - 1);
+    const long long base = line_base(g, o, l);
+    const int step = NT >> g.lognl;
+    for (int p = tid >> g.lognl; p < g.n; p += step) f(l, p, base);
+  } else {
+    const int tpl = 1 << g.logtpl;
+    const int nl = 1 << g.lognl;
+    for (int l = tid >> g.logtpl; l < nl; l += NT >> g.logtpl) {
+      const long long base = line_base(g, o, l);
+      for (int p = tid & (tpl - 1); p < g.n; p += tpl) f(l, p, base);
+    }
+  }
+}
+
+// floor(j / d) for j, d < 2^16 with magic = ceil(2^32 / d), d > 1.
+__device__ __forceinline__ int fast_div(int j, unsigned magic) {
+  return (int)__umulhi((unsigned)j, magic);
 }
 
 }  // namespace poisson_dev

@@ -164,28 +164,38 @@ static int lds_setup_once() {
     ALLOW((r2r_kernel<float, R2R_EMAX_F, R2R_NT>));
     ALLOW((tridiag_kernel<double, 4, TRI_NT>));
     ALLOW((tridiag_kernel<double, 8, TRI_NT>));
-    ALLOW((tridiag_kernel<double, 16, TRI_NT>));
     ALLOW((tridiag_kernel<float, 4, TRI_NT>));
     ALLOW((tridiag_kernel<float, 8, TRI_NT>));
-    ALLOW((tridiag_kernel<float, 16, TRI_NT>));
 #undef ALLOW
     status = e == hipSuccess ? 0 : fail(POISSON_EHIP, "hipFuncSetAttribute: %s", hipGetErrorString(e));
   });
   return status;
 }
 
+static int ilog2(int v) {
+  int l = 0;
+  while ((1 << (l + 1)) <= v) ++l;
+  return l;
+}
+static int pow2_ceil_log(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
 // Geometry of the lines along axis `axis` (0 = x, 1 = y, 2 = z) of an
-// nx x ny x nz field, with at most `nl_target` lines per tile.
-static LineGeom make_geom(int axis, const int* dims, int nl_target) {
+// nx x ny x nz field, with at most 2^lognl_max lines per tile.
+static LineGeom make_geom(int axis, const int* dims, int lognl_max) {
   LineGeom g{};
   const long long nx = dims[0], ny = dims[1], nz = dims[2];
   if (axis == 0) {
     g.layout = 1;
     g.n = dims[0];
     g.sp = 1;
-    g.nlines = ny * nz;
-    g.nl = (int)std::min<long long>(nl_target, g.nlines);
-    g.ntiles = (g.nlines + g.nl - 1) / g.nl;
+    g.nlines = (int)(ny * nz);
+    g.lognl = std::min(lognl_max, pow2_ceil_log(g.nlines));
+    g.logtpl = std::min(6, pow2_ceil_log(g.n));
+    g.ntiles = (g.nlines + (1 << g.lognl) - 1) >> g.lognl;
   } else {
     g.layout = 0;
     g.n = dims[axis];
@@ -193,13 +203,18 @@ static LineGeom make_geom(int axis, const int* dims, int nl_target) {
     g.nx = (int)nx;
     g.nb = axis == 1 ? (int)nz : (int)ny;
     g.sb = axis == 1 ? nx * ny : nx;
-    g.txw = (int)std::min<long long>(nl_target, nx);
-    g.nbt = std::max(1, std::min(nl_target / g.txw, g.nb));
-    g.nl = g.txw * g.nbt;
-    g.tiles_x = (int)((nx + g.txw - 1) / g.txw);
-    g.ntiles = (long long)g.tiles_x * ((g.nb + g.nbt - 1) / g.nbt);
+    g.logtxw = std::min(lognl_max, pow2_ceil_log(g.nx));
+    g.lognbt = std::min(lognl_max - g.logtxw, pow2_ceil_log(g.nb));
+    g.lognl = g.logtxw + g.lognbt;
+    g.tiles_x = (g.nx + (1 << g.logtxw) - 1) >> g.logtxw;
+    g.ntiles = g.tiles_x * ((g.nb + (1 << g.lognbt) - 1) >> g.lognbt);
   }
   return g;
+}
+
+// ceil(2^32 / d) for 1 < d < 2^16 (0 for d = 1: never used)
+static unsigned div_magic(int d) {
+  return d > 1 ? (unsigned)((((unsigned long long)1 << 32) + d - 1) / d) : 0u;
 }
 
 static int grid_of(long long ntiles) {
@@ -214,16 +229,21 @@ static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hip
   const AxisTables& A = p->ax[role];
   constexpr int EMAX = sizeof(T) == 8 ? R2R_EMAX_D : R2R_EMAX_F;
   const int cap_reals = 2 * EMAX * R2R_NT;
-  const int nl_target = std::max(1, std::min(cap_reals / A.n, R2R_NT));
+  const int lognl_max = ilog2(std::max(1, std::min(cap_reals / A.n, R2R_NT)));
   R2RArgs<T> a{};
   a.data = data;
-  a.g = make_geom(A.axis, p->dims, nl_target);
+  a.g = make_geom(A.axis, p->dims, lognl_max);
   a.kind = A.kind;
   a.inverse = inverse;
   a.m = A.m;
   a.npass = (int)A.radices.size();
-  for (int i = 0; i < a.npass; ++i) a.radix[i] = A.radices[i];
-  a.nlp = a.g.nl | 1;
+  int Ns = 1;
+  for (int i = 0; i < a.npass; ++i) {
+    a.radix[i] = A.radices[i];
+    a.ns_magic[i] = div_magic(Ns);
+    Ns *= A.radices[i];
+  }
+  a.nlp = (1 << a.g.lognl) | 1;
   if (!inverse) a.scale = (T)1;
   else a.scale = (T)(A.kind <= BC_DD ? 1.0 / A.n : 1.0 / (2.0 * A.n));
   const char* base = p->dtab + (sizeof(T) == 8 ? A.off_d : A.off_f);
@@ -247,8 +267,8 @@ static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
                           const double* skip = nullptr) {
   TriArgs<T> a{};
   a.data = data;
-  const int lines = TRI_NT / p->P;
-  a.g = make_geom(p->s, p->dims, lines);
+  const int lines = TRI_NT / p->P;            // lines covered by the block's threads
+  a.g = make_geom(p->s, p->dims, ilog2(lines));
   a.P = p->P;
   a.lcmax = p->lcmax;
   a.nlp = lines | 1;
@@ -266,16 +286,15 @@ static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
   a.lamu = lam;
   a.lamv = lam + p->nu;
   a.skip = skip;
-  const size_t lds = (size_t)p->P * a.cpitch * sizeof(T);
+  // tile + row-offset table (one int per row)
+  const size_t lds = align_up((size_t)p->P * a.cpitch * sizeof(T), 16) + (size_t)ns * sizeof(int);
   if (lds > LDS_LIMIT) return fail(POISSON_EUNSUPPORTED, "elimination tile needs %zu B of LDS", lds);
   const dim3 grid(grid_of(a.g.ntiles)), block(TRI_NT);
   const int interior = p->lcmax - 1;
   if (interior <= 4)
     hipLaunchKernelGGL((tridiag_kernel<T, 4, TRI_NT>), grid, block, lds, st, a);
-  else if (interior <= 8)
-    hipLaunchKernelGGL((tridiag_kernel<T, 8, TRI_NT>), grid, block, lds, st, a);
   else
-    hipLaunchKernelGGL((tridiag_kernel<T, 16, TRI_NT>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((tridiag_kernel<T, 8, TRI_NT>), grid, block, lds, st, a);
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
 }
@@ -336,12 +355,15 @@ static void axis_rows(const std::vector<double>& hs, int kind, double* out) {
 
 static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-static int choose_chunks(int n, bool periodic, int& P, int& lcmax) {
+// Chunks per line of the elimination kernel: a power of two (the interface
+// reduction is cyclic on a periodic axis), every chunk >= 2 rows, at most 8
+// rows per chunk (64 chunks = one line per wavefront for long lines).
+static int choose_chunks(int n, int& P, int& lcmax) {
   P = 1;
-  while (P < 32 && n >= 4 * P) P *= 2;     // every chunk keeps >= 2 rows
+  while (P < 32 && n >= 4 * P) P *= 2;
+  if ((n + P - 1) / P > 8 && n >= 2 * 64) P = 64;
   lcmax = (n + P - 1) / P;
-  (void)periodic;
-  return lcmax - 1 <= 16 ? 0 : -1;
+  return lcmax - 1 <= 8 ? 0 : -1;
 }
 
 extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double dy, const double* dz,
@@ -394,7 +416,7 @@ extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double d
   const int ns = p->dims[p->s];
   if (ns > MAX_SOLVE_N) return reject(POISSON_EUNSUPPORTED, "elimination axis length %d > 512", ns);
   if (p->s_periodic && ns < 3) return reject(POISSON_EUNSUPPORTED, "periodic elimination axis needs n >= 3 (got %d)", ns);
-  if (choose_chunks(ns, p->s_periodic, p->P, p->lcmax))
+  if (choose_chunks(ns, p->P, p->lcmax))
     return reject(POISSON_EUNSUPPORTED, "elimination axis length %d not supported", ns);
   p->nu = p->dims[t[0]];
   p->nv = p->dims[t[1]];

@@ -39,6 +39,7 @@ struct R2RArgs {
   int m;                     // n / 2
   int npass;
   int radix[16];
+  unsigned ns_magic[16];     // ceil(2^32 / Ns) of each pass (Ns = product of earlier radices)
   int nlp;                   // LDS row pitch (elements)
   T scale;                   // applied at the store (1, 1/n or 1/2n)
   const cplx<T>* tw_fft;     // m     : e^{-2 pi i t/m}
@@ -156,11 +157,11 @@ __device__ __forceinline__ void st_c(T* lds, int nlp, int l, int j, cplx<T> v) {
 // then gets its own register allocation instead of the union of all of them.
 
 template <int R, typename T, bool FWD, int EMAX, int NT>
-__device__ __noinline__ void fft_pass(T* lds, int m, int Ns, int nl, int nlp,
-                                         const cplx<T>* __restrict__ tw, int tid) {
+__device__ __noinline__ void fft_pass(T* lds, int m, int Ns, unsigned ns_magic, int lognl, int nlp,
+                                      const cplx<T>* __restrict__ tw, int tid) {
   constexpr int S = (EMAX + R - 1) / R;
   const int nbf = m / R;
-  const int total = nbf * nl;
+  const int total = nbf << lognl;
   const int tstride = m / (Ns * R);
   cplx<T> v[S][R];
   int lsave[S], jout[S];
@@ -170,9 +171,9 @@ __device__ __noinline__ void fft_pass(T* lds, int m, int Ns, int nl, int nlp,
     lsave[s] = -1;
     jout[s] = 0;
     if (b < total) {
-      const int l = b % nl;
-      const int j = b / nl;
-      const int k = j % Ns;
+      const int l = b & ((1 << lognl) - 1);
+      const int j = b >> lognl;
+      const int k = Ns > 1 ? j - Ns * fast_div(j, ns_magic) : 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[s][r] = ld_c(lds, nlp, l, j + r * nbf);
       if (Ns > 1) {
@@ -200,16 +201,17 @@ __device__ __noinline__ void fft_pass(T* lds, int m, int Ns, int nl, int nlp,
 }
 
 template <typename T, bool FWD, int EMAX, int NT>
-__device__ void fft_all(T* lds, const R2RArgs<T>& A, int nl, int nlp, int tid) {
+__device__ void fft_all(T* lds, const R2RArgs<T>& A, int lognl, int nlp, int tid) {
   int Ns = 1;
   for (int ip = 0; ip < A.npass; ++ip) {
     const int R = A.radix[ip];
+    const unsigned mg = A.ns_magic[ip];
     switch (R) {
-      case 8: fft_pass<8, T, FWD, EMAX, NT>(lds, A.m, Ns, nl, nlp, A.tw_fft, tid); break;
-      case 4: fft_pass<4, T, FWD, EMAX, NT>(lds, A.m, Ns, nl, nlp, A.tw_fft, tid); break;
-      case 2: fft_pass<2, T, FWD, EMAX, NT>(lds, A.m, Ns, nl, nlp, A.tw_fft, tid); break;
-      case 3: fft_pass<3, T, FWD, EMAX, NT>(lds, A.m, Ns, nl, nlp, A.tw_fft, tid); break;
-      default: fft_pass<5, T, FWD, EMAX, NT>(lds, A.m, Ns, nl, nlp, A.tw_fft, tid); break;
+      case 8: fft_pass<8, T, FWD, EMAX, NT>(lds, A.m, Ns, mg, lognl, nlp, A.tw_fft, tid); break;
+      case 4: fft_pass<4, T, FWD, EMAX, NT>(lds, A.m, Ns, mg, lognl, nlp, A.tw_fft, tid); break;
+      case 2: fft_pass<2, T, FWD, EMAX, NT>(lds, A.m, Ns, mg, lognl, nlp, A.tw_fft, tid); break;
+      case 3: fft_pass<3, T, FWD, EMAX, NT>(lds, A.m, Ns, mg, lognl, nlp, A.tw_fft, tid); break;
+      default: fft_pass<5, T, FWD, EMAX, NT>(lds, A.m, Ns, mg, lognl, nlp, A.tw_fft, tid); break;
     }
     Ns *= R;
   }
@@ -264,11 +266,11 @@ __device__ __forceinline__ int store_row(int kind, int inverse, int q, int n, bo
 // O = -i (Z_k - conj Z_{m-k})/2, w = e^{-2 pi i k/n}:
 // X_k = E + w O and X_{m-k} = conj(E - w O).
 template <typename T, int EMAX, int NT>
-__device__ __noinline__ void split_forward(T* lds, int kind, int n, int m, int nl, int nlp,
+__device__ __noinline__ void split_forward(T* lds, int kind, int n, int m, int lognl, int nlp,
                                            const cplx<T>* __restrict__ tw_split,
                                            const cplx<T>* __restrict__ tw_quarter, int tid) {
   constexpr int S = EMAX / 2 + 1;
-  const int total = (m / 2 + 1) * nl;
+  const int total = (m / 2 + 1) << lognl;
   cplx<T> X[S], Y[S];
   int ks[S], ls[S];
 #pragma unroll
@@ -277,8 +279,8 @@ __device__ __noinline__ void split_forward(T* lds, int kind, int n, int m, int n
     ls[s] = -1;
     ks[s] = 0;
     if (b < total) {
-      const int l = b % nl;
-      const int k = b / nl;
+      const int l = b & ((1 << lognl) - 1);
+      const int k = b >> lognl;
       const cplx<T> zk = ld_c(lds, nlp, l, k);
       const cplx<T> zc = cconj(ld_c(lds, nlp, l, (m - k) % m));
       const cplx<T> E = {(T)0.5 * (zk.re + zc.re), (T)0.5 * (zk.im + zc.im)};
@@ -346,11 +348,11 @@ __device__ __forceinline__ cplx<T> spectrum_at(const T* lds, int nlp, int l, int
 }
 
 template <typename T, int EMAX, int NT>
-__device__ __noinline__ void combine_inverse(T* lds, int kind, int n, int m, int nl, int nlp,
+__device__ __noinline__ void combine_inverse(T* lds, int kind, int n, int m, int lognl, int nlp,
                                              const cplx<T>* __restrict__ tw_split,
                                              const cplx<T>* __restrict__ tw_quarter, int tid) {
   constexpr int S = EMAX / 2 + 1;
-  const int total = (m / 2 + 1) * nl;
+  const int total = (m / 2 + 1) << lognl;
   cplx<T> Zk[S], Zj[S];
   int ks[S], ls[S];
 #pragma unroll
@@ -359,8 +361,8 @@ __device__ __noinline__ void combine_inverse(T* lds, int kind, int n, int m, int
     ls[s] = -1;
     ks[s] = 0;
     if (b < total) {
-      const int l = b % nl;
-      const int k = b / nl;
+      const int l = b & ((1 << lognl) - 1);
+      const int k = b >> lognl;
       const int j = m - k;
       const cplx<T> Xk = spectrum_at(lds, nlp, l, k, kind, n, m, tw_quarter);
       const cplx<T> Xj = spectrum_at(lds, nlp, l, j, kind, n, m, tw_quarter);
@@ -392,12 +394,12 @@ __device__ __noinline__ void combine_inverse(T* lds, int kind, int n, int m, int
 // DCT-IV pre-twiddle, in place (each element is read and written by the
 // same thread).
 template <typename T, int NT>
-__device__ __noinline__ void iv_pre(T* lds, int m, int nl, int nlp,
+__device__ __noinline__ void iv_pre(T* lds, int m, int lognl, int nlp,
                                     const cplx<T>* __restrict__ tw_pre, int tid) {
-  const int total = m * nl;
+  const int total = m << lognl;
   for (int b = tid; b < total; b += NT) {
-    const int l = b % nl;
-    const int j = b / nl;
+    const int l = b & ((1 << lognl) - 1);
+    const int j = b >> lognl;
     st_c(lds, nlp, l, j, cmul(ld_c(lds, nlp, l, j), tw_pre[j]));
   }
   __syncthreads();
@@ -405,10 +407,10 @@ __device__ __noinline__ void iv_pre(T* lds, int m, int nl, int nlp,
 
 // DCT-IV post-step: V_k = Z_k e^{-i pi k/n}; y_2k = 2 Re V_k, y_{n-1-2k} = -2 Im V_k.
 template <typename T, int EMAX, int NT>
-__device__ __noinline__ void iv_post(T* lds, int n, int m, int nl, int nlp,
+__device__ __noinline__ void iv_post(T* lds, int n, int m, int lognl, int nlp,
                                      const cplx<T>* __restrict__ tw_post, int tid) {
   constexpr int S = EMAX;
-  const int total = m * nl;
+  const int total = m << lognl;
   cplx<T> V[S];
   int ks[S], ls[S];
 #pragma unroll
@@ -417,8 +419,8 @@ __device__ __noinline__ void iv_post(T* lds, int n, int m, int nl, int nlp,
     ls[s] = -1;
     ks[s] = 0;
     if (b < total) {
-      const int l = b % nl;
-      const int k = b / nl;
+      const int l = b & ((1 << lognl) - 1);
+      const int k = b >> lognl;
       V[s] = cmul(ld_c(lds, nlp, l, k), tw_post[k]);
       ls[s] = l;
       ks[s] = k;
@@ -437,48 +439,48 @@ __device__ __noinline__ void iv_post(T* lds, int n, int m, int nl, int nlp,
 // ---------------------------------------------------------------- kernel
 
 template <typename T, int EMAX, int NT>
-__global__ __launch_bounds__(NT) void r2r_kernel(R2RArgs<T> A) {
+// at least 4 waves per SIMD: two 512-thread tiles resident per CU
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+void r2r_kernel(R2RArgs<T> A) {
   if (A.skip && A.skip[0] != 0.0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   const int tid = threadIdx.x;
   const LineGeom& g = A.g;
-  const int n = g.n, nl = g.nl, nlp = A.nlp;
-  const int total = n * nl;
-  const bool fwd_fft = !(A.inverse && A.kind <= K_DD);
+  const int n = g.n, lognl = g.lognl, nlp = A.nlp;
+  const int kind = A.kind, inverse = A.inverse;
+  const long long sp = g.sp;
+  T* __restrict__ data = A.data;
+  const bool fwd_fft = !(inverse && kind <= K_DD);
 
-  for (long long tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
-    for (int e = tid; e < total; e += NT) {
-      int l, p;
-      if (g.layout == 0) { l = e % nl; p = e / nl; } else { p = e % n; l = e / n; }
-      const long long base = line_base(g, tile, l);
-      const T v = base >= 0 ? A.data[base + p * g.sp] : (T)0;
+  for (int tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
+    const TileOrigin o = tile_origin(g, tile);
+    for_tile<NT>(g, o, tid, [&](int l, int p, long long base) {
+      const T v = base >= 0 ? data[base + p * sp] : (T)0;
       bool neg;
-      const int r = load_row(A.kind, A.inverse, p, n, neg);
+      const int r = load_row(kind, inverse, p, n, neg);
       lds[r * nlp + l] = neg ? -v : v;
-    }
+    });
     __syncthreads();
 
-    if (A.kind >= K_ND) iv_pre<T, NT>(lds, A.m, nl, nlp, A.tw_pre, tid);
-    else if (A.inverse)
-      combine_inverse<T, EMAX, NT>(lds, A.kind, n, A.m, nl, nlp, A.tw_split, A.tw_quarter, tid);
+    if (kind >= K_ND) iv_pre<T, NT>(lds, A.m, lognl, nlp, A.tw_pre, tid);
+    else if (inverse)
+      combine_inverse<T, EMAX, NT>(lds, kind, n, A.m, lognl, nlp, A.tw_split, A.tw_quarter, tid);
 
-    if (fwd_fft) fft_all<T, true, EMAX, NT>(lds, A, nl, nlp, tid);
-    else fft_all<T, false, EMAX, NT>(lds, A, nl, nlp, tid);
+    if (fwd_fft) fft_all<T, true, EMAX, NT>(lds, A, lognl, nlp, tid);
+    else fft_all<T, false, EMAX, NT>(lds, A, lognl, nlp, tid);
 
-    if (A.kind >= K_ND) iv_post<T, EMAX, NT>(lds, n, A.m, nl, nlp, A.tw_post, tid);
-    else if (!A.inverse)
-      split_forward<T, EMAX, NT>(lds, A.kind, n, A.m, nl, nlp, A.tw_split, A.tw_quarter, tid);
+    if (kind >= K_ND) iv_post<T, EMAX, NT>(lds, n, A.m, lognl, nlp, A.tw_post, tid);
+    else if (!inverse)
+      split_forward<T, EMAX, NT>(lds, kind, n, A.m, lognl, nlp, A.tw_split, A.tw_quarter, tid);
 
-    for (int e = tid; e < total; e += NT) {
-      int l, q;
-      if (g.layout == 0) { l = e % nl; q = e / nl; } else { q = e % n; l = e / n; }
-      const long long base = line_base(g, tile, l);
+    const T scale = A.scale;
+    for_tile<NT>(g, o, tid, [&](int l, int q, long long base) {
       bool neg;
-      const int r = store_row(A.kind, A.inverse, q, n, neg);
-      const T v = lds[r * nlp + l] * A.scale;
-      if (base >= 0) A.data[base + q * g.sp] = neg ? -v : v;
-    }
+      const int r = store_row(kind, inverse, q, n, neg);
+      const T v = lds[r * nlp + l] * scale;
+      if (base >= 0) data[base + q * sp] = neg ? -v : v;
+    });
     __syncthreads();
   }
 }

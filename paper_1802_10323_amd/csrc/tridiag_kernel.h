@@ -7,7 +7,7 @@
 // with a_0 and c_{n-1} the periodic wrap couplings (zero on a walled axis).
 //
 // A tile of nl lines is staged in LDS.  Each line is cut into P chunks
-// (P a power of two <= 32), one per lane of a group of P consecutive lanes of
+// (P a power of two <= 64), one per lane of a group of P consecutive lanes of
 // a wavefront, so the whole line is eliminated by P threads at once:
 //  phase 1  every chunk eliminates its interior rows (all rows but the last)
 //           top-down with no pivoting (the rows are weakly diagonally
@@ -51,10 +51,7 @@ struct TriArgs {
   const double* skip; // optional: when *skip != 0 the launch does nothing
 };
 
-__device__ __forceinline__ int chunk_start(int c, int n, int P) { return (int)(((long long)c * n) / P); }
-__device__ __forceinline__ int chunk_of(int r, int n, int P) {
-  return (int)(((long long)(r + 1) * P - 1) / n);
-}
+__device__ __forceinline__ int chunk_start(int c, int n, int P) { return (c * n) / P; }
 
 template <typename T>
 __device__ __forceinline__ T shfl(T v, int src) { return __shfl(v, src, 64); }
@@ -66,13 +63,17 @@ __device__ __forceinline__ T group_sum(T v, int P) {
 }
 
 template <typename T, int LC, int NT>
-__global__ __launch_bounds__(NT) void tridiag_kernel(TriArgs<T> A) {
+// at least 4 waves per SIMD: two 512-thread tiles resident per CU
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+void tridiag_kernel(TriArgs<T> A) {
   if (A.skip && A.skip[0] != 0.0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   const int tid = threadIdx.x;
   const LineGeom& g = A.g;
-  const int n = g.n, nl = g.nl, nlp = A.nlp, P = A.P, cpitch = A.cpitch;
+  const int n = g.n, nl = 1 << g.lognl, nlp = A.nlp, P = A.P, cpitch = A.cpitch;
+  const long long sp = g.sp;
+  T* __restrict__ data = A.data;
   const int lane = tid & 63;
   const int c = lane & (P - 1);                   // chunk of this thread
   const int gbase = lane - c;                     // first lane of the group
@@ -80,24 +81,27 @@ __global__ __launch_bounds__(NT) void tridiag_kernel(TriArgs<T> A) {
   const int s0 = chunk_start(c, n, P);
   const int e0 = chunk_start(c + 1, n, P) - 1;    // interface row
   const int ni = e0 - s0;                         // interior rows (< LC)
-  const int total = n * nl;
   T* col = lds + c * cpitch + l;                  // row k of my chunk: col[k * nlp]
 
-  for (long long tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
-    for (int e = tid; e < total; e += NT) {
-      int ll, p;
-      if (g.layout == 0) { ll = e % nl; p = e / nl; } else { p = e % n; ll = e / n; }
-      const long long base = line_base(g, tile, ll);
-      const int cc = chunk_of(p, n, P);
-      lds[cc * cpitch + (p - chunk_start(cc, n, P)) * nlp + ll] =
-          base >= 0 ? A.data[base + p * g.sp] : (T)0;
-    }
+  // LDS offset of every row of a line (chunk block + row within the chunk)
+  int* rowoff = reinterpret_cast<int*>(lds + P * cpitch);
+  if (tid < P) {
+    const int a0 = chunk_start(tid, n, P), a1 = chunk_start(tid + 1, n, P);
+    for (int r = a0; r < a1; ++r) rowoff[r] = tid * cpitch + (r - a0) * nlp;
+  }
+  __syncthreads();
+
+  for (int tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
+    const TileOrigin o = tile_origin(g, tile);
+    for_tile<NT>(g, o, tid, [&](int ll, int p, long long base) {
+      lds[rowoff[p] + ll] = base >= 0 ? data[base + p * sp] : (T)0;
+    });
     __syncthreads();
 
     // this line's shift and status
-    const bool valid = l < nl && line_base(g, tile, l) >= 0;
+    const bool valid = l < nl && line_base(g, o, l) >= 0;
     int u = 0, v = 0;
-    if (valid) line_coords(g, tile, l, A.nu, u, v);
+    if (valid) line_coords(g, o, l, A.nu, u, v);
     const T mu = valid ? A.lamu[u] + A.lamv[v] : (T)-1;
     const bool sing = A.singular && valid && u == 0 && v == 0;
     const bool wave_sing = __any(sing);
@@ -225,14 +229,9 @@ __global__ __launch_bounds__(NT) void tridiag_kernel(TriArgs<T> A) {
     }
     __syncthreads();
 
-    for (int e = tid; e < total; e += NT) {
-      int ll, p;
-      if (g.layout == 0) { ll = e % nl; p = e / nl; } else { p = e % n; ll = e / n; }
-      const long long base = line_base(g, tile, ll);
-      const int cc = chunk_of(p, n, P);
-      if (base >= 0)
-        A.data[base + p * g.sp] = lds[cc * cpitch + (p - chunk_start(cc, n, P)) * nlp + ll];
-    }
+    for_tile<NT>(g, o, tid, [&](int ll, int p, long long base) {
+      if (base >= 0) data[base + p * sp] = lds[rowoff[p] + ll];
+    });
     __syncthreads();
   }
 }
