@@ -65,6 +65,18 @@ struct LineGeom {
   int ntiles;       // tiles in the launch
 };
 
+// LineGeom as separate scalar parameters of a non-inlined device function
+// (a struct passed by value would go through scratch memory).
+#define GEOM_PARAMS                                                                      \
+  int g_n, int g_layout, long long g_sp, int g_nx, int g_nb, long long g_sb, int g_logtxw, \
+      int g_lognbt, int g_tiles_x, int g_nlines, int g_logtpl, int g_lognl, int g_ntiles
+#define GEOM_ARGS(g)                                                                      \
+  (g).n, (g).layout, (g).sp, (g).nx, (g).nb, (g).sb, (g).logtxw, (g).lognbt, (g).tiles_x, \
+      (g).nlines, (g).logtpl, (g).lognl, (g).ntiles
+#define GEOM_REBUILD                                                                     \
+  LineGeom { g_n, g_layout, g_sp, g_nx, g_nb, g_sb, g_logtxw, g_lognbt, g_tiles_x,       \
+             g_nlines, g_logtpl, g_lognl, g_ntiles }
+
 // First line of a tile: x0/b0 (strided) or line index L0 (contiguous).
 struct TileOrigin {
   int x0, b0, L0;
@@ -129,9 +141,69 @@ __device__ __forceinline__ void for_tile(const LineGeom& g, const TileOrigin& o,
   }
 }
 
+// Tiles of this block in a persistent launch.  The 8 XCDs of the chip
+// receive consecutive blocks round-robin (block b runs on XCD b mod 8), and
+// each XCD has its own L2: every XCD gets one contiguous eighth of the tiles,
+// so the blocks running together on an XCD work on neighbouring tiles.
+struct TileRange {
+  int first, end, step;
+};
+__device__ __forceinline__ TileRange xcd_tiles(int ntiles) {
+  const int G = gridDim.x, b = blockIdx.x;
+  if (G < 8 || (G & 7)) return {b, ntiles, G};
+  const int chunk = (ntiles + 7) >> 3;
+  const int x = b & 7;
+  const int end = min(ntiles, (x + 1) * chunk);
+  return {x * chunk + (b >> 3), end, G >> 3};
+}
+
+// Field pointers seen as global-address-space pointers, so that loads and
+// stores compile to global_* (not flat_*) instructions inside non-inlined
+// device functions.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+  return (gptr<T>)p;
+}
+// element i of a read-only complex table in global memory
+template <typename T>
+__device__ __forceinline__ cplx<T> ldg(const cplx<T>* p, int i) {
+  const gptr<const T> q = (gptr<const T>)p;
+  return {q[2 * i], q[2 * i + 1]};
+}
+// ... and LDS pointers as local-address-space pointers (ds_* instructions).
+template <typename T>
+using lptr = __attribute__((address_space(3))) T*;
+template <typename T>
+__device__ __forceinline__ lptr<T> as_lds(T* p) {
+  return (lptr<T>)p;
+}
+
 // floor(j / d) for j, d < 2^16 with magic = ceil(2^32 / d), d > 1.
 __device__ __forceinline__ int fast_div(int j, unsigned magic) {
   return (int)__umulhi((unsigned)j, magic);
+}
+
+// Element i (0 <= i < EPT) of thread tid in a tile of NT threads: line l,
+// point p, and its global offset (-1 if outside the tile or the field).
+//  strided: thread tid keeps line tid mod nl, points step by NT/nl;
+//  contiguous: the tile's lines are one contiguous run of nl*n values, so
+//  element e = tid + i*NT sits at offset L0*n + e (l, p = divmod(e, n)).
+// `sbase` is line_base() of the thread's line (strided layout only).
+template <int NT>
+__device__ __forceinline__ long long tile_elem(const LineGeom& g, const TileOrigin& o,
+                                               long long sbase, unsigned n_magic, int tid, int i,
+                                               int& l, int& p) {
+  if (g.layout == 0) {
+    l = tid & ((1 << g.lognl) - 1);
+    p = (tid >> g.lognl) + i * (NT >> g.lognl);
+    return (p < g.n && sbase >= 0) ? sbase + p * g.sp : -1;
+  }
+  const int e = tid + i * NT;
+  l = g.n > 1 ? fast_div(e, n_magic) : e;
+  p = e - l * g.n;
+  return (l < (1 << g.lognl) && o.L0 + l < g.nlines) ? (long long)o.L0 * g.n + e : -1;
 }
 
 }  // namespace poisson_dev

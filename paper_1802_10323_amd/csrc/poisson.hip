@@ -217,8 +217,31 @@ static unsigned div_magic(int d) {
   return d > 1 ? (unsigned)((((unsigned long long)1 << 32) + d - 1) / d) : 0u;
 }
 
-static int grid_of(long long ntiles) {
-  return (int)std::min<long long>(ntiles, 1LL << 30);
+// Persistent grid: as many blocks as can be resident at once (CUs x blocks
+// per CU for this kernel, block size and LDS), each looping over tiles, so
+// that no block pays launch and set-up more than once per launch.
+static int resident_grid(const void* fn, int block, size_t lds, long long ntiles) {
+  static std::mutex mu;
+  static std::vector<std::pair<std::pair<const void*, size_t>, std::pair<int, int>>> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int per_cu = 0, cus = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& e : cache)
+      if (e.first.first == fn && e.first.second == lds + (size_t)dev * 0x100000000ull) {
+        per_cu = e.second.first;
+        cus = e.second.second;
+      }
+  }
+  if (!cus) {
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess) per_cu = 1;
+    per_cu = std::max(per_cu, 1);
+    std::lock_guard<std::mutex> lk(mu);
+    cache.push_back({{fn, lds + (size_t)dev * 0x100000000ull}, {per_cu, cus}});
+  }
+  return (int)std::min<long long>(ntiles, (long long)cus * per_cu);
 }
 
 // ------------------------------------------------------------------ launches
@@ -244,6 +267,7 @@ static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hip
     Ns *= A.radices[i];
   }
   a.nlp = (1 << a.g.lognl) | 1;
+  a.n_magic = div_magic(A.n);
   if (!inverse) a.scale = (T)1;
   else a.scale = (T)(A.kind <= BC_DD ? 1.0 / A.n : 1.0 / (2.0 * A.n));
   const char* base = p->dtab + (sizeof(T) == 8 ? A.off_d : A.off_f);
@@ -256,8 +280,9 @@ static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hip
   a.skip = skip;
   const size_t lds = (size_t)A.n * a.nlp * sizeof(T);
   if (lds > LDS_LIMIT) return fail(POISSON_EUNSUPPORTED, "transform tile needs %zu B of LDS", lds);
-  hipLaunchKernelGGL((r2r_kernel<T, EMAX, R2R_NT>), dim3(grid_of(a.g.ntiles)), dim3(R2R_NT), lds,
-                     st, a);
+  const void* fn = reinterpret_cast<const void*>(&r2r_kernel<T, EMAX, R2R_NT>);
+  hipLaunchKernelGGL((r2r_kernel<T, EMAX, R2R_NT>),
+                     dim3(resident_grid(fn, R2R_NT, lds, a.g.ntiles)), dim3(R2R_NT), lds, st, a);
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
 }
@@ -273,6 +298,7 @@ static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
   a.lcmax = p->lcmax;
   a.nlp = lines | 1;
   a.cpitch = (p->lcmax * a.nlp) | 1;
+  a.n_magic = div_magic(p->dims[p->s]);
   a.periodic = p->s_periodic;
   a.singular = p->singular;
   a.nu = p->nu;
@@ -289,12 +315,16 @@ static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
   // tile + row-offset table (one int per row)
   const size_t lds = align_up((size_t)p->P * a.cpitch * sizeof(T), 16) + (size_t)ns * sizeof(int);
   if (lds > LDS_LIMIT) return fail(POISSON_EUNSUPPORTED, "elimination tile needs %zu B of LDS", lds);
-  const dim3 grid(grid_of(a.g.ntiles)), block(TRI_NT);
-  const int interior = p->lcmax - 1;
-  if (interior <= 4)
-    hipLaunchKernelGGL((tridiag_kernel<T, 4, TRI_NT>), grid, block, lds, st, a);
-  else
-    hipLaunchKernelGGL((tridiag_kernel<T, 8, TRI_NT>), grid, block, lds, st, a);
+  const dim3 block(TRI_NT);
+  if (p->lcmax - 1 <= 4) {
+    const void* fn = reinterpret_cast<const void*>(&tridiag_kernel<T, 4, TRI_NT>);
+    hipLaunchKernelGGL((tridiag_kernel<T, 4, TRI_NT>),
+                       dim3(resident_grid(fn, TRI_NT, lds, a.g.ntiles)), block, lds, st, a);
+  } else {
+    const void* fn = reinterpret_cast<const void*>(&tridiag_kernel<T, 8, TRI_NT>);
+    hipLaunchKernelGGL((tridiag_kernel<T, 8, TRI_NT>),
+                       dim3(resident_grid(fn, TRI_NT, lds, a.g.ntiles)), block, lds, st, a);
+  }
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
 }

@@ -40,6 +40,7 @@ struct R2RArgs {
   int npass;
   int radix[16];
   unsigned ns_magic[16];     // ceil(2^32 / Ns) of each pass (Ns = product of earlier radices)
+  unsigned n_magic;          // ceil(2^32 / n)
   int nlp;                   // LDS row pitch (elements)
   T scale;                   // applied at the store (1, 1/n or 1/2n)
   const cplx<T>* tw_fft;     // m     : e^{-2 pi i t/m}
@@ -179,7 +180,7 @@ __device__ __noinline__ void fft_pass(T* lds, int m, int Ns, unsigned ns_magic, 
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cplx<T> w = tw[r * k * tstride];
+          cplx<T> w = ldg(tw, r * k * tstride);
           if (!FWD) w.im = -w.im;
           v[s][r] = cmul(v[s][r], w);
         }
@@ -286,7 +287,7 @@ __device__ __noinline__ void split_forward(T* lds, int kind, int n, int m, int l
       const cplx<T> E = {(T)0.5 * (zk.re + zc.re), (T)0.5 * (zk.im + zc.im)};
       const cplx<T> D = csub(zk, zc);
       const cplx<T> O = {(T)0.5 * D.im, (T)-0.5 * D.re};
-      const cplx<T> wO = cmul(tw_split[k], O);
+      const cplx<T> wO = cmul(ldg(tw_split, k), O);
       X[s] = cadd(E, wO);
       Y[s] = cconj(csub(E, wO));
       ls[s] = l;
@@ -314,11 +315,11 @@ __device__ __noinline__ void split_forward(T* lds, int kind, int n, int m, int l
       // DCT-II outputs y_r = 2 Re(q_r X_r), y_{n-r} = -2 Im(q_r X_r);
       // the DST-II stores y_r at n-1-r.
       const bool rev = kind == K_DD;
-      const cplx<T> u = cmul(tw_quarter[k], X[s]);
+      const cplx<T> u = cmul(ldg(tw_quarter, k), X[s]);
       lds[(rev ? n - 1 - k : k) * nlp + l] = (T)2 * u.re;
       if (k > 0) lds[(rev ? k - 1 : n - k) * nlp + l] = (T)-2 * u.im;
       if (j != k) {
-        const cplx<T> u2 = cmul(tw_quarter[j], Y[s]);
+        const cplx<T> u2 = cmul(ldg(tw_quarter, j), Y[s]);
         lds[(rev ? n - 1 - j : j) * nlp + l] = (T)2 * u2.re;
         if (j != m) lds[(rev ? j - 1 : n - j) * nlp + l] = (T)-2 * u2.im;
       }
@@ -343,7 +344,7 @@ __device__ __forceinline__ cplx<T> spectrum_at(const T* lds, int nlp, int l, int
   }
   const T yk = lds[k * nlp + l];
   const T ynk = k == 0 ? (T)0 : lds[(n - k) * nlp + l];
-  const cplx<T> q = cconj(quarter[k]);
+  const cplx<T> q = cconj(ldg(quarter, k));
   return cmul(q, cplx<T>{(T)0.5 * yk, (T)-0.5 * ynk});
 }
 
@@ -368,12 +369,12 @@ __device__ __noinline__ void combine_inverse(T* lds, int kind, int n, int m, int
       const cplx<T> Xj = spectrum_at(lds, nlp, l, j, kind, n, m, tw_quarter);
       {
         const cplx<T> s1 = cadd(Xk, cconj(Xj));
-        const cplx<T> d1 = cmul(csub(Xk, cconj(Xj)), cconj(tw_split[k]));
+        const cplx<T> d1 = cmul(csub(Xk, cconj(Xj)), cconj(ldg(tw_split, k)));
         Zk[s] = {s1.re - d1.im, s1.im + d1.re};     // s1 + i d1
       }
       {
         const cplx<T> s2 = cadd(Xj, cconj(Xk));
-        const cplx<T> d2 = cmul(csub(Xj, cconj(Xk)), cconj(tw_split[j]));
+        const cplx<T> d2 = cmul(csub(Xj, cconj(Xk)), cconj(ldg(tw_split, j)));
         Zj[s] = {s2.re - d2.im, s2.im + d2.re};
       }
       ls[s] = l;
@@ -400,7 +401,7 @@ __device__ __noinline__ void iv_pre(T* lds, int m, int lognl, int nlp,
   for (int b = tid; b < total; b += NT) {
     const int l = b & ((1 << lognl) - 1);
     const int j = b >> lognl;
-    st_c(lds, nlp, l, j, cmul(ld_c(lds, nlp, l, j), tw_pre[j]));
+    st_c(lds, nlp, l, j, cmul(ld_c(lds, nlp, l, j), ldg(tw_pre, j)));
   }
   __syncthreads();
 }
@@ -421,7 +422,7 @@ __device__ __noinline__ void iv_post(T* lds, int n, int m, int lognl, int nlp,
     if (b < total) {
       const int l = b & ((1 << lognl) - 1);
       const int k = b >> lognl;
-      V[s] = cmul(ld_c(lds, nlp, l, k), tw_post[k]);
+      V[s] = cmul(ld_c(lds, nlp, l, k), ldg(tw_post, k));
       ls[s] = l;
       ks[s] = k;
     }
@@ -434,6 +435,66 @@ __device__ __noinline__ void iv_post(T* lds, int n, int m, int lognl, int nlp,
     lds[(n - 1 - 2 * ks[s]) * nlp + ls[s]] = (T)-2 * V[s].im;
   }
   __syncthreads();
+}
+
+// ---------------------------------------------------------------- tile load / store
+// All EPT global loads of a thread are issued before the first LDS write
+// (and all LDS reads before the first global store), so a wavefront keeps
+// EPT memory requests in flight.  Not inlined, so that nothing of this
+// phase stays live across the FFT passes.
+
+template <typename T, int EPT, int NT>
+__device__ __noinline__ void r2r_load_tile(T* lds, const T* __restrict__ data, GEOM_PARAMS,
+                                           int tile, int kind, int inverse, int nlp,
+                                           unsigned n_magic, int tid) {
+  const LineGeom g = GEOM_REBUILD;
+  const TileOrigin o = tile_origin(g, tile);
+  const long long sbase = g.layout == 0 ? line_base(g, o, tid & ((1 << g.lognl) - 1)) : 0;
+  T buf[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    int l, p;
+    const long long off = tile_elem<NT>(g, o, sbase, n_magic, tid, i, l, p);
+    buf[i] = off >= 0 ? as_global(data)[off] : (T)0;
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    int l, p;
+    tile_elem<NT>(g, o, sbase, n_magic, tid, i, l, p);
+    if (p < g.n && l < (1 << g.lognl)) {
+      bool neg;
+      const int r = load_row(kind, inverse, p, g.n, neg);
+      lds[r * nlp + l] = neg ? -buf[i] : buf[i];
+    }
+  }
+}
+
+template <typename T, int EPT, int NT>
+__device__ __noinline__ void r2r_store_tile(const T* lds, T* __restrict__ data, GEOM_PARAMS,
+                                            int tile, int kind, int inverse, int nlp,
+                                            unsigned n_magic, T scale, int tid) {
+  const LineGeom g = GEOM_REBUILD;
+  const TileOrigin o = tile_origin(g, tile);
+  const long long sbase = g.layout == 0 ? line_base(g, o, tid & ((1 << g.lognl) - 1)) : 0;
+  T buf[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    int l, q;
+    tile_elem<NT>(g, o, sbase, n_magic, tid, i, l, q);
+    buf[i] = (T)0;
+    if (q < g.n && l < (1 << g.lognl)) {
+      bool neg;
+      const int r = store_row(kind, inverse, q, g.n, neg);
+      const T v = lds[r * nlp + l] * scale;
+      buf[i] = neg ? -v : v;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    int l, q;
+    const long long off = tile_elem<NT>(g, o, sbase, n_magic, tid, i, l, q);
+    if (off >= 0) as_global(data)[off] = buf[i];
+  }
 }
 
 // ---------------------------------------------------------------- kernel
@@ -449,18 +510,12 @@ void r2r_kernel(R2RArgs<T> A) {
   const LineGeom& g = A.g;
   const int n = g.n, lognl = g.lognl, nlp = A.nlp;
   const int kind = A.kind, inverse = A.inverse;
-  const long long sp = g.sp;
   T* __restrict__ data = A.data;
   const bool fwd_fft = !(inverse && kind <= K_DD);
 
-  for (int tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
-    const TileOrigin o = tile_origin(g, tile);
-    for_tile<NT>(g, o, tid, [&](int l, int p, long long base) {
-      const T v = base >= 0 ? data[base + p * sp] : (T)0;
-      bool neg;
-      const int r = load_row(kind, inverse, p, n, neg);
-      lds[r * nlp + l] = neg ? -v : v;
-    });
+  const TileRange tr = xcd_tiles(g.ntiles);
+  for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+    r2r_load_tile<T, 2 * EMAX, NT>(lds, data, GEOM_ARGS(g), tile, kind, inverse, nlp, A.n_magic, tid);
     __syncthreads();
 
     if (kind >= K_ND) iv_pre<T, NT>(lds, A.m, lognl, nlp, A.tw_pre, tid);
@@ -474,13 +529,7 @@ void r2r_kernel(R2RArgs<T> A) {
     else if (!inverse)
       split_forward<T, EMAX, NT>(lds, kind, n, A.m, lognl, nlp, A.tw_split, A.tw_quarter, tid);
 
-    const T scale = A.scale;
-    for_tile<NT>(g, o, tid, [&](int l, int q, long long base) {
-      bool neg;
-      const int r = store_row(kind, inverse, q, n, neg);
-      const T v = lds[r * nlp + l] * scale;
-      if (base >= 0) data[base + q * sp] = neg ? -v : v;
-    });
+    r2r_store_tile<T, 2 * EMAX, NT>(lds, data, GEOM_ARGS(g), tile, kind, inverse, nlp, A.n_magic, A.scale, tid);
     __syncthreads();
   }
 }

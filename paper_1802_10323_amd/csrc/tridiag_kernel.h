@@ -49,6 +49,7 @@ struct TriArgs {
   const T* lamu;      // [extent of u]
   const T* lamv;      // [extent of v]
   const double* skip; // optional: when *skip != 0 the launch does nothing
+  unsigned n_magic;   // ceil(2^32 / n)
 };
 
 __device__ __forceinline__ int chunk_start(int c, int n, int P) { return (c * n) / P; }
@@ -62,6 +63,55 @@ __device__ __forceinline__ T group_sum(T v, int P) {
   return v;
 }
 
+// Tile load / store: all global loads (LDS reads) of a thread issued before
+// the first LDS write (global store); not inlined, so that nothing of them
+// stays live through the elimination.
+template <typename T, int EPT, int NT>
+__device__ __noinline__ void tri_load_tile(T* lds, const T* __restrict__ data, GEOM_PARAMS,
+                                           int tile, const int* rowoff, unsigned n_magic,
+                                           int tid) {
+  const LineGeom g = GEOM_REBUILD;
+  const TileOrigin o = tile_origin(g, tile);
+  const int nl = 1 << g.lognl;
+  const long long sbase = g.layout == 0 ? line_base(g, o, tid & (nl - 1)) : 0;
+  T buf[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    int ll, p;
+    const long long off = tile_elem<NT>(g, o, sbase, n_magic, tid, i, ll, p);
+    buf[i] = off >= 0 ? as_global(data)[off] : (T)0;
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    int ll, p;
+    tile_elem<NT>(g, o, sbase, n_magic, tid, i, ll, p);
+    if (p < g.n && ll < nl) as_lds(lds)[as_lds(rowoff)[p] + ll] = buf[i];
+  }
+}
+
+template <typename T, int EPT, int NT>
+__device__ __noinline__ void tri_store_tile(const T* lds, T* __restrict__ data, GEOM_PARAMS,
+                                            int tile, const int* rowoff, unsigned n_magic,
+                                            int tid) {
+  const LineGeom g = GEOM_REBUILD;
+  const TileOrigin o = tile_origin(g, tile);
+  const int nl = 1 << g.lognl;
+  const long long sbase = g.layout == 0 ? line_base(g, o, tid & (nl - 1)) : 0;
+  T buf[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    int ll, p;
+    tile_elem<NT>(g, o, sbase, n_magic, tid, i, ll, p);
+    buf[i] = (p < g.n && ll < nl) ? as_lds(lds)[as_lds(rowoff)[p] + ll] : (T)0;
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    int ll, p;
+    const long long off = tile_elem<NT>(g, o, sbase, n_magic, tid, i, ll, p);
+    if (off >= 0) as_global(data)[off] = buf[i];
+  }
+}
+
 template <typename T, int LC, int NT>
 // at least 4 waves per SIMD: two 512-thread tiles resident per CU
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
@@ -72,7 +122,6 @@ void tridiag_kernel(TriArgs<T> A) {
   const int tid = threadIdx.x;
   const LineGeom& g = A.g;
   const int n = g.n, nl = 1 << g.lognl, nlp = A.nlp, P = A.P, cpitch = A.cpitch;
-  const long long sp = g.sp;
   T* __restrict__ data = A.data;
   const int lane = tid & 63;
   const int c = lane & (P - 1);                   // chunk of this thread
@@ -91,11 +140,14 @@ void tridiag_kernel(TriArgs<T> A) {
   }
   __syncthreads();
 
-  for (int tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
+  // tile values per thread: nl * n / NT = n / P <= lcmax <= LC + 1
+  constexpr int EPT = LC + 1;
+  const unsigned n_magic = A.n_magic;
+
+  const TileRange tr = xcd_tiles(g.ntiles);
+  for (int tile = tr.first; tile < tr.end; tile += tr.step) {
     const TileOrigin o = tile_origin(g, tile);
-    for_tile<NT>(g, o, tid, [&](int ll, int p, long long base) {
-      lds[rowoff[p] + ll] = base >= 0 ? data[base + p * sp] : (T)0;
-    });
+    tri_load_tile<T, EPT, NT>(lds, data, GEOM_ARGS(g), tile, rowoff, n_magic, tid);
     __syncthreads();
 
     // this line's shift and status
@@ -229,9 +281,7 @@ void tridiag_kernel(TriArgs<T> A) {
     }
     __syncthreads();
 
-    for_tile<NT>(g, o, tid, [&](int ll, int p, long long base) {
-      if (base >= 0) data[base + p * sp] = lds[rowoff[p] + ll];
-    });
+    tri_store_tile<T, EPT, NT>(lds, data, GEOM_ARGS(g), tile, rowoff, n_magic, tid);
     __syncthreads();
   }
 }

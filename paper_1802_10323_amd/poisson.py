@@ -10,7 +10,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpoisson_hip.so")
+# POISSON_HIP_LIB selects another build of the same library (A/B timing)
+LIB_PATH = os.environ.get("POISSON_HIP_LIB") or os.path.join(HERE, "libpoisson_hip.so")
 
 BC = {"P": 0, "NN": 1, "DD": 2, "ND": 3, "DN": 4}
 AXES = "xyz"
