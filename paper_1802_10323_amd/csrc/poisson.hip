@@ -9,12 +9,14 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
 
 #include "poisson.h"
 #include "r2r_kernel.h"
+#include "r2r_fast.h"
 #include "tridiag_kernel.h"
 #include "refine_kernels.h"
 
@@ -126,6 +128,7 @@ struct poisson_plan {
   double h[3];                 // uniform spacing (x, y) ; z uses dz
   std::vector<double> dz;
   bool z_uniform;
+  bool generic_r2r = false;    // POISSON_GENERIC_R2R=1: size-generic transform kernel only
   int t1, t2, s;
   bool singular, s_periodic;
   int device;
@@ -162,6 +165,10 @@ static int lds_setup_once() {
 #define ALLOW(k) if (e == hipSuccess) e = hipFuncSetAttribute((const void*)(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_LIMIT)
     ALLOW((r2r_kernel<double, R2R_EMAX_D, R2R_NT>));
     ALLOW((r2r_kernel<float, R2R_EMAX_F, R2R_NT>));
+#define ALLOW_FAST(M) ALLOW((r2r_fast_kernel<double, M>)); ALLOW((r2r_fast_kernel<float, M>))
+    ALLOW_FAST(16); ALLOW_FAST(32); ALLOW_FAST(48); ALLOW_FAST(64);
+    ALLOW_FAST(96); ALLOW_FAST(128); ALLOW_FAST(192); ALLOW_FAST(256);
+#undef ALLOW_FAST
     ALLOW((tridiag_kernel<double, 4, TRI_NT>));
     ALLOW((tridiag_kernel<double, 8, TRI_NT>));
     ALLOW((tridiag_kernel<float, 4, TRI_NT>));
@@ -246,10 +253,50 @@ static int resident_grid(const void* fn, int block, size_t lds, long long ntiles
 
 // ------------------------------------------------------------------ launches
 
+// Size-specialised transform kernel (r2r_fast.h) for complex length M.
+template <typename T, int M>
+static int launch_fast(const poisson_plan* p, const AxisTables& A, int inverse, T* data,
+                       hipStream_t st, const double* skip) {
+  using L = FastLayout<T, M>;
+  R2RFastArgs<T> a{};
+  a.data = data;
+  a.g = make_geom(A.axis, p->dims, ilog2(L::NL));
+  a.kind = A.kind;
+  a.inverse = inverse;
+  if (!inverse) a.scale = (T)1;
+  else a.scale = (T)(A.kind <= BC_DD ? 1.0 / A.n : 1.0 / (2.0 * A.n));
+  const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(p->dtab + (sizeof(T) == 8 ? A.off_d : A.off_f));
+  a.tw_fft = tw;
+  a.tw_split = tw + M;
+  a.tw_quarter = tw + 2 * M + 1;
+  a.tw_pre = tw + 3 * M + 2;
+  a.tw_post = tw + 4 * M + 2;
+  a.skip = skip;
+  const size_t lds = fast_lds_bytes<T, M>();
+  const void* fn = reinterpret_cast<const void*>(&r2r_fast_kernel<T, M>);
+  hipLaunchKernelGGL((r2r_fast_kernel<T, M>), dim3(resident_grid(fn, L::NT, lds, a.g.ntiles)),
+                     dim3(L::NT), lds, st, a);
+  HIP_TRY(hipGetLastError());
+  return POISSON_OK;
+}
+
 template <typename T>
 static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hipStream_t st,
                       const double* skip = nullptr) {
   const AxisTables& A = p->ax[role];
+  if (!p->generic_r2r) {
+    switch (A.m) {
+      case 16: return launch_fast<T, 16>(p, A, inverse, data, st, skip);
+      case 32: return launch_fast<T, 32>(p, A, inverse, data, st, skip);
+      case 48: return launch_fast<T, 48>(p, A, inverse, data, st, skip);
+      case 64: return launch_fast<T, 64>(p, A, inverse, data, st, skip);
+      case 96: return launch_fast<T, 96>(p, A, inverse, data, st, skip);
+      case 128: return launch_fast<T, 128>(p, A, inverse, data, st, skip);
+      case 192: return launch_fast<T, 192>(p, A, inverse, data, st, skip);
+      case 256: return launch_fast<T, 256>(p, A, inverse, data, st, skip);
+      default: break;
+    }
+  }
   constexpr int EMAX = sizeof(T) == 8 ? R2R_EMAX_D : R2R_EMAX_F;
   const int cap_reals = 2 * EMAX * R2R_NT;
   const int lognl_max = ilog2(std::max(1, std::min(cap_reals / A.n, R2R_NT)));
@@ -416,6 +463,10 @@ extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double d
   p->h[0] = dx; p->h[1] = dy; p->h[2] = dz[0];
   p->dz.assign(dz, dz + nz);
   p->z_uniform = true;
+  {
+    const char* env = std::getenv("POISSON_GENERIC_R2R");
+    p->generic_r2r = env && env[0] == '1';
+  }
   for (int k = 1; k < nz; ++k) if (dz[k] != dz[0]) p->z_uniform = false;
 
   // axis roles (elimination axis s; the others transformed, in x, y, z order)

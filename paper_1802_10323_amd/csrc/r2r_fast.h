@@ -1,0 +1,473 @@
+// r2r_fast.h - size-specialised version of the batched real-to-real
+// transforms (Table 2 / Table 1) for the common lengths n = 2M,
+// M in {16, 32, 48, 64, 96, 128, 192, 256}.
+//
+// Same mathematics as r2r_kernel.h (one complex FFT of length M per line
+// plus the per-type pre/post steps), but the FFT length, its radix plan,
+// the lines per tile (NL) and the threads per line (QT) are compile-time
+// constants and every step is inlined, so all LDS offsets, twiddle indices
+// and loop counts fold to constants.  A persistent block copies its twiddle
+// tables into LDS once and then loops over tiles.
+//
+// Thread t of NT = QT*NL works on line l = t mod NL (consecutive lanes =
+// consecutive lines, i.e. consecutive x on a strided axis) and handles the
+// butterflies / elements q, q + QT, q + 2 QT, ... of that line, q = t / NL.
+#pragma once
+#include "r2r_kernel.h"
+
+namespace poisson_dev {
+
+// ---------------------------------------------------------------- radix plan
+
+struct RadixPlan {
+  int count;
+  int r[12];
+};
+
+constexpr RadixPlan make_radix_plan(int m) {
+  RadixPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+  int e2 = 0;
+  while (m % 2 == 0) { m /= 2; ++e2; }
+  int n8 = e2 / 3, n4 = 0, n2 = 0;
+  const int rem = e2 % 3;
+  if (rem == 1) {
+    if (n8 > 0) { --n8; n4 = 2; } else { n2 = 1; }
+  }
+  if (rem == 2) n4 = 1;
+  for (int i = 0; i < n8; ++i) p.r[p.count++] = 8;
+  for (int i = 0; i < n4; ++i) p.r[p.count++] = 4;
+  for (int i = 0; i < n2; ++i) p.r[p.count++] = 2;
+  while (m % 3 == 0) { m /= 3; p.r[p.count++] = 3; }
+  while (m % 5 == 0) { m /= 5; p.r[p.count++] = 5; }
+  return p;
+}
+
+constexpr int plan_ns(const RadixPlan& p, int pass) {
+  int ns = 1;
+  for (int i = 0; i < pass; ++i) ns *= p.r[i];
+  return ns;
+}
+
+// Launch shape of the specialised kernel for complex length M.
+template <int M>
+struct FastShape;
+#define POISSON_FAST_SHAPE(M_, QT_, NL_)      \
+  template <>                                 \
+  struct FastShape<M_> {                      \
+    static constexpr int QT = QT_, NL = NL_;  \
+  };
+POISSON_FAST_SHAPE(16, 4, 128)
+POISSON_FAST_SHAPE(32, 4, 128)
+POISSON_FAST_SHAPE(48, 8, 64)
+POISSON_FAST_SHAPE(64, 8, 64)
+POISSON_FAST_SHAPE(96, 8, 32)
+POISSON_FAST_SHAPE(128, 16, 32)
+POISSON_FAST_SHAPE(192, 16, 16)
+POISSON_FAST_SHAPE(256, 32, 16)
+#undef POISSON_FAST_SHAPE
+
+template <int M>
+constexpr int fast_nt() {
+  return FastShape<M>::QT * FastShape<M>::NL;
+}
+
+template <typename T>
+struct R2RFastArgs {
+  T* data;
+  LineGeom g;
+  int kind;
+  int inverse;
+  T scale;
+  const cplx<T>* tw_fft;     // M
+  const cplx<T>* tw_split;   // M + 1
+  const cplx<T>* tw_quarter; // M + 1
+  const cplx<T>* tw_pre;     // M
+  const cplx<T>* tw_post;    // M
+  const double* skip;
+};
+
+template <typename T, int M>
+struct FastLayout {
+  static constexpr int QT = FastShape<M>::QT, NL = FastShape<M>::NL;
+  static constexpr int NT = QT * NL;
+  static constexpr int N = 2 * M;
+  static constexpr int NLP = NL + 1;         // odd LDS row pitch
+  static constexpr int E = M / QT;           // complex values per thread
+  static constexpr int EPT = 2 * E;          // tile reals per thread
+  static constexpr int TILE = N * NLP;       // reals of the tile in LDS
+  static constexpr int AUX = 2 * M + 2;      // second twiddle table (complex)
+  static constexpr RadixPlan plan = make_radix_plan(M);
+};
+
+template <typename T, int M>
+constexpr size_t fast_lds_bytes() {
+  using L = FastLayout<T, M>;
+  return (size_t)L::TILE * sizeof(T) + (size_t)(M + L::AUX) * sizeof(cplx<T>);
+}
+
+// complex element i of an LDS table (address-space structs are read and
+// written field by field)
+template <typename T>
+__device__ __forceinline__ cplx<T> ldc(lptr<const cplx<T>> p, int i) {
+  return {p[i].re, p[i].im};
+}
+template <typename T>
+__device__ __forceinline__ void stc(lptr<cplx<T>> p, int i, cplx<T> v) {
+  p[i].re = v.re;
+  p[i].im = v.im;
+}
+
+// ---------------------------------------------------------------- stages
+// Each stage is a non-inlined function specialised on the sizes, so that it
+// gets a register allocation of its own (a kernel inlining all stages and
+// transform types needs far more registers than any one stage) and the
+// call passes only a few scalars.
+
+// One Stockham pass of radix R (Ns = NS) over the tile, in place in LDS.
+template <typename T, int M, int R, int NS, bool FWD>
+__device__ __noinline__ void fast_pass(lptr<T> lds, lptr<const cplx<T>> tw, int l, int q) {
+  using L = FastLayout<T, M>;
+  constexpr int B = M / R;                       // butterflies per line
+  constexpr int SB = (B + L::QT - 1) / L::QT;    // per thread
+  constexpr int TS = M / (NS * R);               // twiddle stride
+  cplx<T> v[SB][R];
+#pragma unroll
+  for (int s = 0; s < SB; ++s) {
+    const int j = q + s * L::QT;
+    if (B % L::QT == 0 || j < B) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int idx = j + r * B;
+        v[s][r] = {lds[(2 * idx) * L::NLP + l], lds[(2 * idx + 1) * L::NLP + l]};
+      }
+      if (NS > 1) {
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cplx<T> w = ldc(tw, r * k * TS);
+          if (!FWD) w.im = -w.im;
+          v[s][r] = cmul(v[s][r], w);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SB; ++s) {
+    const int j = q + s * L::QT;
+    if (B % L::QT == 0 || j < B) {
+      SmallDFT<R, T, FWD>::run(v[s]);
+      const int k = NS > 1 ? j % NS : 0;
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int idx = base + r * NS;
+        lds[(2 * idx) * L::NLP + l] = v[s][r].re;
+        lds[(2 * idx + 1) * L::NLP + l] = v[s][r].im;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int M, bool FWD, int P>
+__device__ __forceinline__ void fast_passes(lptr<T> lds, lptr<const cplx<T>> tw, int l, int q) {
+  using L = FastLayout<T, M>;
+  if constexpr (P < L::plan.count) {
+    constexpr int R = L::plan.r[P];
+    constexpr int NS = plan_ns(L::plan, P);
+    fast_pass<T, M, R, NS, FWD>(lds, tw, l, q);
+    fast_passes<T, M, FWD, P + 1>(lds, tw, l, q);
+  }
+}
+
+// Tile load: global -> LDS rows with the input permutation of the type.
+// All of a thread's loads are issued before its first LDS write.
+template <typename T, int M>
+__device__ __noinline__ void fast_load(lptr<T> lds, gptr<const T> data, long long base,
+                                       long long sp, int layout, int lines, int kind,
+                                       int inverse, int l, int q, int tid) {
+  using L = FastLayout<T, M>;
+  constexpr int N = L::N;
+  T buf[L::EPT];
+  if (layout == 0) {
+#pragma unroll
+    for (int i = 0; i < L::EPT; ++i)
+      buf[i] = base >= 0 ? data[base + (q + i * L::QT) * sp] : (T)0;
+#pragma unroll
+    for (int i = 0; i < L::EPT; ++i) {
+      const int p = q + i * L::QT;
+      bool neg;
+      const int r = load_row(kind, inverse, p, N, neg);
+      lds[r * L::NLP + l] = neg ? -buf[i] : buf[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < L::EPT; ++i) {
+      const int e = tid + i * L::NT;
+      buf[i] = (e / N) < lines ? data[base + e] : (T)0;
+    }
+#pragma unroll
+    for (int i = 0; i < L::EPT; ++i) {
+      const int e = tid + i * L::NT;
+      const int ll = e / N, p = e % N;
+      bool neg;
+      const int r = load_row(kind, inverse, p, N, neg);
+      lds[r * L::NLP + ll] = neg ? -buf[i] : buf[i];
+    }
+  }
+}
+
+// Tile store: LDS rows -> global with the output permutation, sign, scale.
+template <typename T, int M>
+__device__ __noinline__ void fast_store(lptr<const T> lds, gptr<T> data, long long base,
+                                        long long sp, int layout, int lines, int kind,
+                                        int inverse, T scale, int l, int q, int tid) {
+  using L = FastLayout<T, M>;
+  constexpr int N = L::N;
+  T buf[L::EPT];
+  if (layout == 0) {
+#pragma unroll
+    for (int i = 0; i < L::EPT; ++i) {
+      bool neg;
+      const int r = store_row(kind, inverse, q + i * L::QT, N, neg);
+      const T v = lds[r * L::NLP + l] * scale;
+      buf[i] = neg ? -v : v;
+    }
+    if (base >= 0) {
+#pragma unroll
+      for (int i = 0; i < L::EPT; ++i) data[base + (q + i * L::QT) * sp] = buf[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < L::EPT; ++i) {
+      const int e = tid + i * L::NT;
+      const int ll = e / N, p = e % N;
+      bool neg;
+      const int r = store_row(kind, inverse, p, N, neg);
+      const T v = lds[r * L::NLP + ll] * scale;
+      buf[i] = neg ? -v : v;
+    }
+#pragma unroll
+    for (int i = 0; i < L::EPT; ++i) {
+      const int e = tid + i * L::NT;
+      if ((e / N) < lines) data[base + e] = buf[i];
+    }
+  }
+}
+
+// DCT-IV pre-twiddle (in place: each thread scales its own elements).
+template <typename T, int M>
+__device__ __noinline__ void fast_iv_pre(lptr<T> lds, lptr<const cplx<T>> pre, int l, int q) {
+  using L = FastLayout<T, M>;
+#pragma unroll
+  for (int s = 0; s < L::E; ++s) {
+    const int j = q + s * L::QT;
+    const cplx<T> z = cmul(cplx<T>{lds[(2 * j) * L::NLP + l], lds[(2 * j + 1) * L::NLP + l]},
+                           ldc(pre, j));
+    lds[(2 * j) * L::NLP + l] = z.re;
+    lds[(2 * j + 1) * L::NLP + l] = z.im;
+  }
+  __syncthreads();
+}
+
+// DCT-IV post-step: V_k = Z_k e^{-i pi k/n}; y_2k = 2 Re V_k, y_{n-1-2k} = -2 Im V_k.
+template <typename T, int M>
+__device__ __noinline__ void fast_iv_post(lptr<T> lds, lptr<const cplx<T>> post, int l, int q) {
+  using L = FastLayout<T, M>;
+  constexpr int N = L::N;
+  cplx<T> V[L::E];
+#pragma unroll
+  for (int s = 0; s < L::E; ++s) {
+    const int k = q + s * L::QT;
+    V[s] = cmul(cplx<T>{lds[(2 * k) * L::NLP + l], lds[(2 * k + 1) * L::NLP + l]}, ldc(post, k));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < L::E; ++s) {
+    const int k = q + s * L::QT;
+    lds[(2 * k) * L::NLP + l] = (T)2 * V[s].re;
+    lds[(N - 1 - 2 * k) * L::NLP + l] = (T)-2 * V[s].im;
+  }
+  __syncthreads();
+}
+
+// Inverse P/NN/DD: rebuild the length-M spectrum
+// Z'_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) e^{2 pi i k/n}.
+template <typename T, int M>
+__device__ __noinline__ void fast_combine(lptr<T> lds, lptr<const cplx<T>> split,
+                                          lptr<const cplx<T>> quarter, int kind, int l, int q) {
+  using L = FastLayout<T, M>;
+  constexpr int N = L::N, NLP = L::NLP;
+  constexpr int NP = M / 2 + 1;
+  constexpr int SP = (NP + L::QT - 1) / L::QT;
+  cplx<T> zk[SP], zj[SP];
+#pragma unroll
+  for (int s = 0; s < SP; ++s) {
+    const int k = q + s * L::QT;
+    if (k < NP) {
+      const int j = M - k;
+      cplx<T> xk, xj;
+      if (kind == K_P) {
+        xk = k == 0 ? cplx<T>{lds[l], (T)0}
+                    : cplx<T>{lds[(2 * k - 1) * NLP + l], -lds[(2 * k) * NLP + l]};
+        xj = j == M ? cplx<T>{lds[(N - 1) * NLP + l], (T)0}
+                    : cplx<T>{lds[(2 * j - 1) * NLP + l], -lds[(2 * j) * NLP + l]};
+      } else {
+        const T yk = lds[k * NLP + l], ynk = k == 0 ? (T)0 : lds[(N - k) * NLP + l];
+        const T yj = lds[j * NLP + l], ynj = lds[(N - j) * NLP + l];
+        xk = cmul(cconj(ldc(quarter, k)), cplx<T>{(T)0.5 * yk, (T)-0.5 * ynk});
+        xj = cmul(cconj(ldc(quarter, j)), cplx<T>{(T)0.5 * yj, (T)-0.5 * ynj});
+      }
+      const cplx<T> s1 = cadd(xk, cconj(xj));
+      const cplx<T> d1 = cmul(csub(xk, cconj(xj)), cconj(ldc(split, k)));
+      zk[s] = {s1.re - d1.im, s1.im + d1.re};
+      const cplx<T> s2 = cadd(xj, cconj(xk));
+      const cplx<T> d2 = cmul(csub(xj, cconj(xk)), cconj(ldc(split, j)));
+      zj[s] = {s2.re - d2.im, s2.im + d2.re};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SP; ++s) {
+    const int k = q + s * L::QT;
+    if (k < NP) {
+      const int j = M - k;
+      lds[(2 * k) * NLP + l] = zk[s].re;
+      lds[(2 * k + 1) * NLP + l] = zk[s].im;
+      if (k > 0 && j != k) {
+        lds[(2 * j) * NLP + l] = zj[s].re;
+        lds[(2 * j + 1) * NLP + l] = zj[s].im;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Forward P/NN/DD: even/odd split of the FFT into the real DFT X_k of the
+// (reordered) input and the stored coefficients (see r2r_kernel.h).
+template <typename T, int M>
+__device__ __noinline__ void fast_split(lptr<T> lds, lptr<const cplx<T>> split,
+                                        lptr<const cplx<T>> quarter, int kind, int l, int q) {
+  using L = FastLayout<T, M>;
+  constexpr int N = L::N, NLP = L::NLP;
+  constexpr int NP = M / 2 + 1;
+  constexpr int SP = (NP + L::QT - 1) / L::QT;
+  cplx<T> X[SP], Y[SP];
+#pragma unroll
+  for (int s = 0; s < SP; ++s) {
+    const int k = q + s * L::QT;
+    if (k < NP) {
+      const int kc = (M - k) % M;
+      const cplx<T> z = {lds[(2 * k) * NLP + l], lds[(2 * k + 1) * NLP + l]};
+      const cplx<T> zc = {lds[(2 * kc) * NLP + l], -lds[(2 * kc + 1) * NLP + l]};
+      const cplx<T> E = {(T)0.5 * (z.re + zc.re), (T)0.5 * (z.im + zc.im)};
+      const cplx<T> D = csub(z, zc);
+      const cplx<T> O = {(T)0.5 * D.im, (T)-0.5 * D.re};
+      const cplx<T> wO = cmul(ldc(split, k), O);
+      X[s] = cadd(E, wO);
+      Y[s] = cconj(csub(E, wO));
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SP; ++s) {
+    const int k = q + s * L::QT;
+    if (k < NP) {
+      const int j = M - k;
+      if (kind == K_P) {
+        if (k == 0) {
+          lds[l] = X[s].re;
+          lds[(N - 1) * NLP + l] = Y[s].re;
+        } else {
+          lds[(2 * k - 1) * NLP + l] = X[s].re;
+          lds[(2 * k) * NLP + l] = -X[s].im;
+          if (j != k) {
+            lds[(2 * j - 1) * NLP + l] = Y[s].re;
+            lds[(2 * j) * NLP + l] = -Y[s].im;
+          }
+        }
+      } else {
+        const bool rev = kind == K_DD;
+        const cplx<T> u = cmul(ldc(quarter, k), X[s]);
+        lds[(rev ? N - 1 - k : k) * NLP + l] = (T)2 * u.re;
+        if (k > 0) lds[(rev ? k - 1 : N - k) * NLP + l] = (T)-2 * u.im;
+        if (j != k) {
+          const cplx<T> u2 = cmul(ldc(quarter, j), Y[s]);
+          lds[(rev ? N - 1 - j : j) * NLP + l] = (T)2 * u2.re;
+          if (j != M) lds[(rev ? j - 1 : N - j) * NLP + l] = (T)-2 * u2.im;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- kernel
+
+template <typename T, int M>
+__global__ __launch_bounds__(fast_nt<M>()) __attribute__((amdgpu_waves_per_eu(4)))
+void r2r_fast_kernel(R2RFastArgs<T> A) {
+  using L = FastLayout<T, M>;
+  constexpr int NL = L::NL, NT = L::NT;
+  if (A.skip && A.skip[0] != 0.0) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const lptr<T> lds = as_lds(reinterpret_cast<T*>(smem_raw));
+  const lptr<cplx<T>> twf = as_lds(reinterpret_cast<cplx<T>*>(reinterpret_cast<T*>(smem_raw) + L::TILE));
+  const lptr<cplx<T>> twa = twf + M;
+  const int tid = threadIdx.x;
+  const int l = tid % NL;
+  const int q = tid / NL;
+  const LineGeom& g = A.g;
+  const int kind = A.kind, inverse = A.inverse;
+  const bool ivk = kind >= K_ND;
+
+  // twiddle tables -> LDS (once per block)
+  for (int i = tid; i < M; i += NT) stc(twf, i, ldg(A.tw_fft, i));
+  if (ivk) {
+    for (int i = tid; i < M; i += NT) {
+      stc(twa, i, ldg(A.tw_pre, i));
+      stc(twa, M + 1 + i, ldg(A.tw_post, i));
+    }
+  } else {
+    for (int i = tid; i <= M; i += NT) {
+      stc(twa, i, ldg(A.tw_split, i));
+      stc(twa, M + 1 + i, ldg(A.tw_quarter, i));
+    }
+  }
+  const lptr<const cplx<T>> tw_fft = twf;
+  const lptr<const cplx<T>> tw_a = twa;           // pre   or split
+  const lptr<const cplx<T>> tw_b = twa + (M + 1); // post  or quarter
+  __syncthreads();
+
+  const TileRange tr = xcd_tiles(g.ntiles);
+  for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+    const TileOrigin o = tile_origin(g, tile);
+    long long base;
+    int lines = 0;
+    if (g.layout == 0) {
+      base = l < (1 << g.lognl) ? line_base(g, o, l) : -1;
+    } else {
+      base = (long long)o.L0 * L::N;
+      lines = g.nlines - o.L0;
+    }
+    fast_load<T, M>(lds, as_global((const T*)A.data), base, g.sp, g.layout, lines, kind, inverse,
+                    l, q, tid);
+    __syncthreads();
+
+    if (ivk) fast_iv_pre<T, M>(lds, tw_a, l, q);
+    else if (inverse) fast_combine<T, M>(lds, tw_a, tw_b, kind, l, q);
+
+    if (!(inverse && kind <= K_DD)) fast_passes<T, M, true, 0>(lds, tw_fft, l, q);
+    else fast_passes<T, M, false, 0>(lds, tw_fft, l, q);
+
+    if (ivk) fast_iv_post<T, M>(lds, tw_b, l, q);
+    else if (!inverse) fast_split<T, M>(lds, tw_a, tw_b, kind, l, q);
+
+    fast_store<T, M>(lds, as_global(A.data), base, g.sp, g.layout, lines, kind, inverse,
+                     A.scale, l, q, tid);
+    __syncthreads();
+  }
+}
+
+}  // namespace poisson_dev
