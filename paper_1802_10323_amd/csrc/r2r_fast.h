@@ -5,9 +5,15 @@
 // Same mathematics as r2r_kernel.h (one complex FFT of length M per line
 // plus the per-type pre/post steps), but the FFT length, its radix plan,
 // the lines per tile (NL) and the threads per line (QT) are compile-time
-// constants and every step is inlined, so all LDS offsets, twiddle indices
-// and loop counts fold to constants.  A persistent block copies its twiddle
+// constants of each (non-inlined) stage, so LDS offsets, twiddle indices and
+// loop counts fold to constants.  A persistent block copies its twiddle
 // tables into LDS once and then loops over tiles.
+//
+// LDS per block: the tile (2M rows of NL+1 values) plus 3M complex twiddles:
+// the FFT table (M) and either the DCT-IV pre/post tables (M + M) or half
+// of the even/odd split table (M/2 + 1, the other half follows from
+// w_{M-k} = -conj(w_k)) and the quarter-wave table (M + 1).  For M = 256 in
+// FP64 that is exactly 80 KiB, so two blocks share a CU.
 //
 // Thread t of NT = QT*NL works on line l = t mod NL (consecutive lanes =
 // consecutive lines, i.e. consecutive x on a strided axis) and handles the
@@ -95,8 +101,10 @@ struct FastLayout {
   static constexpr int E = M / QT;           // complex values per thread
   static constexpr int EPT = 2 * E;          // tile reals per thread
   static constexpr int TILE = N * NLP;       // reals of the tile in LDS
-  static constexpr int AUX = 2 * M + 2;      // second twiddle table (complex)
+  static constexpr int AUX = 2 * M;          // pre/post or split/quarter tables (complex)
+  static constexpr int SPLIT = M / 2 + 1;    // split-table entries kept in LDS
   static constexpr RadixPlan plan = make_radix_plan(M);
+  static_assert(SPLIT + M + 1 <= AUX, "split + quarter tables exceed the LDS slot");
 };
 
 template <typename T, int M>
@@ -319,11 +327,13 @@ __device__ __noinline__ void fast_combine(lptr<T> lds, lptr<const cplx<T>> split
         xk = cmul(cconj(ldc(quarter, k)), cplx<T>{(T)0.5 * yk, (T)-0.5 * ynk});
         xj = cmul(cconj(ldc(quarter, j)), cplx<T>{(T)0.5 * yj, (T)-0.5 * ynj});
       }
+      // split_{M-k} = -conj(split_k)
+      const cplx<T> sk = ldc(split, k);
       const cplx<T> s1 = cadd(xk, cconj(xj));
-      const cplx<T> d1 = cmul(csub(xk, cconj(xj)), cconj(ldc(split, k)));
+      const cplx<T> d1 = cmul(csub(xk, cconj(xj)), cconj(sk));
       zk[s] = {s1.re - d1.im, s1.im + d1.re};
       const cplx<T> s2 = cadd(xj, cconj(xk));
-      const cplx<T> d2 = cmul(csub(xj, cconj(xk)), cconj(ldc(split, j)));
+      const cplx<T> d2 = cmul(csub(cconj(xk), xj), sk);
       zj[s] = {s2.re - d2.im, s2.im + d2.re};
     }
   }
@@ -427,17 +437,15 @@ void r2r_fast_kernel(R2RFastArgs<T> A) {
   if (ivk) {
     for (int i = tid; i < M; i += NT) {
       stc(twa, i, ldg(A.tw_pre, i));
-      stc(twa, M + 1 + i, ldg(A.tw_post, i));
+      stc(twa, M + i, ldg(A.tw_post, i));
     }
   } else {
-    for (int i = tid; i <= M; i += NT) {
-      stc(twa, i, ldg(A.tw_split, i));
-      stc(twa, M + 1 + i, ldg(A.tw_quarter, i));
-    }
+    for (int i = tid; i < L::SPLIT; i += NT) stc(twa, i, ldg(A.tw_split, i));
+    for (int i = tid; i <= M; i += NT) stc(twa, L::SPLIT + i, ldg(A.tw_quarter, i));
   }
   const lptr<const cplx<T>> tw_fft = twf;
   const lptr<const cplx<T>> tw_a = twa;           // pre   or split
-  const lptr<const cplx<T>> tw_b = twa + (M + 1); // post  or quarter
+  const lptr<const cplx<T>> tw_b = twa + (ivk ? M : L::SPLIT);  // post or quarter
   __syncthreads();
 
   const TileRange tr = xcd_tiles(g.ntiles);
