@@ -18,6 +18,7 @@
 #include "r2r_kernel.h"
 #include "r2r_fast.h"
 #include "tridiag_kernel.h"
+#include "tri_fast.h"
 #include "refine_kernels.h"
 
 using namespace poisson_dev;
@@ -129,6 +130,7 @@ struct poisson_plan {
   std::vector<double> dz;
   bool z_uniform;
   bool generic_r2r = false;    // POISSON_GENERIC_R2R=1: size-generic transform kernel only
+  bool generic_tri = false;    // POISSON_GENERIC_TRI=1: size-generic elimination kernel only
   int t1, t2, s;
   bool singular, s_periodic;
   int device;
@@ -173,6 +175,10 @@ static int lds_setup_once() {
     ALLOW((tridiag_kernel<double, 8, TRI_NT>));
     ALLOW((tridiag_kernel<float, 4, TRI_NT>));
     ALLOW((tridiag_kernel<float, 8, TRI_NT>));
+#define ALLOW_TRI(R, P) ALLOW((tri_fast_kernel<double, R, P>)); ALLOW((tri_fast_kernel<float, R, P>))
+    ALLOW_TRI(4, 16); ALLOW_TRI(6, 16); ALLOW_TRI(4, 32); ALLOW_TRI(6, 32);
+    ALLOW_TRI(8, 32); ALLOW_TRI(6, 64); ALLOW_TRI(8, 64);
+#undef ALLOW_TRI
 #undef ALLOW
     status = e == hipSuccess ? 0 : fail(POISSON_EHIP, "hipFuncSetAttribute: %s", hipGetErrorString(e));
   });
@@ -334,9 +340,48 @@ static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hip
   return POISSON_OK;
 }
 
+template <typename T, int RPC, int P>
+static int launch_tri_fast(const poisson_plan* p, T* data, hipStream_t st, const double* skip) {
+  using L = TriFastLayout<T, RPC, P>;
+  TriFastArgs<T> a{};
+  a.data = data;
+  a.g = make_geom(p->s, p->dims, ilog2(L::NL));
+  a.periodic = p->s_periodic;
+  a.singular = p->singular;
+  a.nu = p->nu;
+  const T* tri = reinterpret_cast<const T*>(p->dtab + (sizeof(T) == 8 ? p->off_tri_d : p->off_tri_f));
+  a.a = tri;
+  a.b = tri + L::N;
+  a.c = tri + 2 * L::N;
+  a.w = tri + 3 * L::N;
+  const T* lam = reinterpret_cast<const T*>(p->dtab + (sizeof(T) == 8 ? p->off_lam_d : p->off_lam_f));
+  a.lamu = lam;
+  a.lamv = lam + p->nu;
+  a.skip = skip;
+  const size_t lds = tri_fast_lds_bytes<T, RPC, P>();
+  const void* fn = reinterpret_cast<const void*>(&tri_fast_kernel<T, RPC, P>);
+  hipLaunchKernelGGL((tri_fast_kernel<T, RPC, P>), dim3(resident_grid(fn, L::NT, lds, a.g.ntiles)),
+                     dim3(L::NT), lds, st, a);
+  HIP_TRY(hipGetLastError());
+  return POISSON_OK;
+}
+
 template <typename T>
 static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
                           const double* skip = nullptr) {
+  if (!p->generic_tri && p->dims[p->s] == p->P * p->lcmax) {
+    const int key = p->lcmax * 100 + p->P;
+    switch (key) {
+      case 416: return launch_tri_fast<T, 4, 16>(p, data, st, skip);
+      case 616: return launch_tri_fast<T, 6, 16>(p, data, st, skip);
+      case 432: return launch_tri_fast<T, 4, 32>(p, data, st, skip);
+      case 632: return launch_tri_fast<T, 6, 32>(p, data, st, skip);
+      case 832: return launch_tri_fast<T, 8, 32>(p, data, st, skip);
+      case 664: return launch_tri_fast<T, 6, 64>(p, data, st, skip);
+      case 864: return launch_tri_fast<T, 8, 64>(p, data, st, skip);
+      default: break;
+    }
+  }
   TriArgs<T> a{};
   a.data = data;
   const int lines = TRI_NT / p->P;            // lines covered by the block's threads
@@ -466,6 +511,8 @@ extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double d
   {
     const char* env = std::getenv("POISSON_GENERIC_R2R");
     p->generic_r2r = env && env[0] == '1';
+    env = std::getenv("POISSON_GENERIC_TRI");
+    p->generic_tri = env && env[0] == '1';
   }
   for (int k = 1; k < nz; ++k) if (dz[k] != dz[0]) p->z_uniform = false;
 

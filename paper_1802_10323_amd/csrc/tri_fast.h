@@ -1,0 +1,320 @@
+// tri_fast.h - size-specialised elimination of the reduced systems of
+// Eq. (poi_reduced) for lines whose length n is a multiple of the chunk
+// count: n = RPC * P, RPC rows per chunk, P chunks (lanes) per line.
+//
+// Same algorithm as tridiag_kernel.h (chunked Thomas, interface system by
+// parallel cyclic reduction, back substitution), with every loop bound a
+// compile-time constant, so that
+//  * each thread reads its RPC right-hand-side values and the RPC rows of
+//    coefficients it needs in one burst of LDS reads (the coefficients of
+//    the axis are copied to LDS once per block, laid out [row in chunk][chunk]
+//    so that the P lanes of a line read consecutive words);
+//  * the whole chunk (values, pivots, spike vector) lives in registers from
+//    the first read to the final write;
+//  * the reciprocal of every pivot is the hardware estimate refined by
+//    Newton steps (relative error at the rounding level of the type)
+//    instead of a correctly rounded division sequence.
+#pragma once
+#include "tridiag_kernel.h"
+
+namespace poisson_dev {
+
+template <typename T>
+struct TriFastArgs {
+  T* data;
+  LineGeom g;
+  int periodic;
+  int singular;
+  int nu;             // extent of u (contiguous layout: line index = u + nu v)
+  const T* a;         // [n]
+  const T* b;         // [n]
+  const T* c;         // [n]
+  const T* w;         // [n] cell widths along s (gauge weights)
+  const T* lamu;
+  const T* lamv;
+  const double* skip;
+};
+
+template <typename T, int RPC, int P>
+struct TriFastLayout {
+  static constexpr int NT = 512;
+  static constexpr int NL = NT / P;           // lines per tile
+  static constexpr int N = RPC * P;           // line length
+  static constexpr int NLP = NL + 1;          // row pitch
+  static constexpr int CP = (RPC * NLP) | 1;  // chunk pitch (odd)
+  static constexpr int TILE = P * CP;         // reals of the tile
+  static_assert(RPC >= 2 && P >= 2 && P <= 64 && (P & (P - 1)) == 0, "unsupported chunking");
+};
+
+template <typename T, int RPC, int P>
+constexpr size_t tri_fast_lds_bytes() {
+  using L = TriFastLayout<T, RPC, P>;
+  return (size_t)(L::TILE + 4 * L::N) * sizeof(T);
+}
+
+// 1/d: hardware reciprocal estimate refined by Newton steps.
+__device__ __forceinline__ double fast_rcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float fast_rcp(float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  const float e = __builtin_fmaf(-d, r, 1.0f);
+  return __builtin_fmaf(r, e, r);
+}
+
+// LDS position of point p of line ll of the tile.
+template <typename T, int RPC, int P>
+__device__ __forceinline__ int tri_fast_slot(int p, int ll) {
+  using L = TriFastLayout<T, RPC, P>;
+  const int ch = p / RPC;
+  return ch * L::CP + (p - ch * RPC) * L::NLP + ll;
+}
+
+// Tile load: global -> LDS; all global loads of a thread are issued before
+// its first LDS write.  Strided layout: line tid mod NL, points
+// tid / NL + i P; contiguous layout: element tid + i NT of the tile's run.
+template <typename T, int RPC, int P>
+__device__ __noinline__ void tri_fast_load(lptr<T> lds, gptr<const T> data, long long base,
+                                           long long sp, int layout, int lines, int tid) {
+  using L = TriFastLayout<T, RPC, P>;
+  T buf[RPC];
+  if (layout == 0) {
+    const int l = tid % L::NL, q = tid / L::NL;
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) buf[i] = base >= 0 ? data[base + (q + i * P) * sp] : (T)0;
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) lds[tri_fast_slot<T, RPC, P>(q + i * P, l)] = buf[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) {
+      const int e = tid + i * L::NT;
+      buf[i] = e / L::N < lines ? data[base + e] : (T)0;
+    }
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) {
+      const int e = tid + i * L::NT;
+      const int ll = e / L::N;
+      lds[tri_fast_slot<T, RPC, P>(e - ll * L::N, ll)] = buf[i];
+    }
+  }
+}
+
+template <typename T, int RPC, int P>
+__device__ __noinline__ void tri_fast_store(lptr<const T> lds, gptr<T> data, long long base,
+                                            long long sp, int layout, int lines, int tid) {
+  using L = TriFastLayout<T, RPC, P>;
+  T buf[RPC];
+  if (layout == 0) {
+    const int l = tid % L::NL, q = tid / L::NL;
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) buf[i] = lds[tri_fast_slot<T, RPC, P>(q + i * P, l)];
+    if (base >= 0) {
+#pragma unroll
+      for (int i = 0; i < RPC; ++i) data[base + (q + i * P) * sp] = buf[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) {
+      const int e = tid + i * L::NT;
+      const int ll = e / L::N;
+      buf[i] = lds[tri_fast_slot<T, RPC, P>(e - ll * L::N, ll)];
+    }
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) {
+      const int e = tid + i * L::NT;
+      if (e / L::N < lines) data[base + e] = buf[i];
+    }
+  }
+}
+
+// Sum over the P lanes of a line.
+template <typename T, int P>
+__device__ __forceinline__ T line_sum(T v) {
+#pragma unroll
+  for (int off = 1; off < P; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Eliminate the line held by this lane's group: chunk c of the line, LDS
+// column col (row i at col[i * NLP]), coefficient tables ca/cb/cc/cw laid out
+// [row in chunk][chunk], shift mu, and the singular-line flags.
+template <typename T, int RPC, int P>
+__device__ __noinline__ void tri_fast_line(lptr<T> col, lptr<const T> coef, int c, T mu,
+                                           int sing, int wave_sing, int periodic) {
+  using L = TriFastLayout<T, RPC, P>;
+  constexpr int N = L::N;
+  const lptr<const T> ca = coef, cb = coef + N, cc = coef + 2 * N, cw = coef + 3 * N;
+  const int lane = threadIdx.x & 63;
+  const int gbase = lane - c;
+
+  T x[RPC], av[RPC], bv[RPC], cv[RPC];
+#pragma unroll
+  for (int i = 0; i < RPC; ++i) {
+    x[i] = col[i * L::NLP];
+    av[i] = ca[i * P + c];
+    bv[i] = cb[i * P + c];
+    cv[i] = cc[i * P + c];
+  }
+
+  if (wave_sing) {   // project the right-hand side of the null-space line
+    T sw = 0, swf = 0;
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) {
+      const T wi = cw[i * P + c];
+      sw += wi;
+      swf += wi * x[i];
+    }
+    sw = line_sum<T, P>(sw);
+    swf = line_sum<T, P>(swf);
+    if (sing) {
+      const T mean = swf / sw;
+#pragma unroll
+      for (int i = 0; i < RPC; ++i) x[i] -= mean;
+    }
+  }
+
+  // phase 1: interior rows 0 .. RPC-2, top-down; x <- d (eliminated rhs),
+  // qv = spike of the previous interface, cp = c / pivot
+  constexpr int NI = RPC - 1;
+  T cp[NI], qv[NI];
+  T r = fast_rcp(bv[0] + mu);
+  x[0] *= r;
+  qv[0] = av[0] * r;
+  cp[0] = cv[0] * r;
+#pragma unroll
+  for (int i = 1; i < NI; ++i) {
+    r = fast_rcp(bv[i] + mu - av[i] * cp[i - 1]);
+    x[i] = (x[i] - av[i] * x[i - 1]) * r;
+    qv[i] = -av[i] * qv[i - 1] * r;
+    cp[i] = cv[i] * r;
+  }
+  // first-row values of y = T^-1 f, v = T^-1 (a e_first), w = T^-1 (c e_last)
+  const T yl = x[NI - 1], vl = qv[NI - 1], wl = cv[NI - 1] * r;
+  T yf = yl, vf = vl, wf = wl;
+#pragma unroll
+  for (int i = NI - 2; i >= 0; --i) {
+    yf = x[i] - cp[i] * yf;
+    vf = qv[i] - cp[i] * vf;
+    wf = -cp[i] * wf;
+  }
+
+  // phase 2: interface row (last row of the chunk), reduced by PCR
+  T ae = av[NI], be = bv[NI] + mu, ce = cv[NI], fe = x[NI];
+  if (sing && c == P - 1) { ae = 0; be = 1; ce = 0; fe = 0; }   // pin x_{n-1} = 0
+  const int nxt = gbase + ((c + 1) & (P - 1));
+  const T yf_n = __shfl(yf, nxt, 64), vf_n = __shfl(vf, nxt, 64), wf_n = __shfl(wf, nxt, 64);
+  T Lq = -ae * vl;
+  T Dq = be - ae * wl - ce * vf_n;
+  T Uq = -ce * wf_n;
+  T Rq = fe - ae * yl - ce * yf_n;
+#pragma unroll
+  for (int st = 1; st < P; st <<= 1) {
+    const int cm = c - st, cpl = c + st;
+    const int srcm = gbase + (cm & (P - 1));
+    const int srcp = gbase + (cpl & (P - 1));
+    T Lm = __shfl(Lq, srcm, 64), Dm = __shfl(Dq, srcm, 64);
+    T Um = __shfl(Uq, srcm, 64), Rm = __shfl(Rq, srcm, 64);
+    T Lp = __shfl(Lq, srcp, 64), Dp = __shfl(Dq, srcp, 64);
+    T Up = __shfl(Uq, srcp, 64), Rp = __shfl(Rq, srcp, 64);
+    if (!periodic && cm < 0) { Lm = 0; Dm = 1; Um = 0; Rm = 0; }
+    if (!periodic && cpl >= P) { Lp = 0; Dp = 1; Up = 0; Rp = 0; }
+    const T k1 = Lq * fast_rcp(Dm);
+    const T k2 = Uq * fast_rcp(Dp);
+    Dq = Dq - Um * k1 - Lp * k2;
+    Rq = Rq - Rm * k1 - Rp * k2;
+    Lq = -Lm * k1;
+    Uq = -Up * k2;
+  }
+  // after the reduction the remaining couplings point back at this unknown
+  const T Ic = Rq / (periodic ? Lq + Dq + Uq : Dq);
+  T Ip = __shfl(Ic, gbase + ((c - 1) & (P - 1)), 64);
+  if (!periodic && c == 0) Ip = 0;
+
+  // phase 3: back substitution of the interior
+  x[NI] = Ic;
+  x[NI - 1] = yl - Ip * vl - Ic * wl;
+#pragma unroll
+  for (int i = NI - 2; i >= 0; --i) x[i] = x[i] - Ip * qv[i] - cp[i] * x[i + 1];
+
+  if (wave_sing) {   // gauge: zero width-weighted mean of the null-space line
+    T sw = 0, swx = 0;
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) {
+      const T wi = cw[i * P + c];
+      sw += wi;
+      swx += wi * x[i];
+    }
+    sw = line_sum<T, P>(sw);
+    swx = line_sum<T, P>(swx);
+    if (sing) {
+      const T mean = swx / sw;
+#pragma unroll
+      for (int i = 0; i < RPC; ++i) x[i] -= mean;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RPC; ++i) col[i * L::NLP] = x[i];
+}
+
+template <typename T, int RPC, int P>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+void tri_fast_kernel(TriFastArgs<T> A) {
+  using L = TriFastLayout<T, RPC, P>;
+  constexpr int N = L::N, NL = L::NL, NT = L::NT;
+  if (A.skip && A.skip[0] != 0.0) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const lptr<T> lds = as_lds(reinterpret_cast<T*>(smem_raw));
+  const lptr<T> coef = lds + L::TILE;
+  const int tid = threadIdx.x;
+  const LineGeom& g = A.g;
+
+  // coefficients -> LDS, [row in chunk][chunk]
+  for (int k = tid; k < N; k += NT) {
+    const int ch = k / RPC, i = k - ch * RPC;
+    const int s = i * P + ch;
+    coef[s] = as_global(A.a)[k];
+    coef[N + s] = as_global(A.b)[k];
+    coef[2 * N + s] = as_global(A.c)[k];
+    coef[3 * N + s] = as_global(A.w)[k];
+  }
+  __syncthreads();
+
+  const int c = tid % P;        // chunk of this thread
+  const int l = tid / P;        // line of this thread within the tile
+  const int nlt = 1 << g.lognl; // lines in a full tile of this launch (<= NL)
+  const lptr<T> col = lds + c * L::CP + l;
+
+  const TileRange tr = xcd_tiles(g.ntiles);
+  for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+    const TileOrigin o = tile_origin(g, tile);
+    long long base;
+    int lines = 0;
+    if (g.layout == 0) {
+      const int ll = tid % NL;
+      base = ll < nlt ? line_base(g, o, ll) : -1;
+    } else {
+      base = (long long)o.L0 * N;
+      lines = min(g.nlines - o.L0, nlt);
+    }
+    tri_fast_load<T, RPC, P>(lds, as_global((const T*)A.data), base, g.sp, g.layout, lines, tid);
+    __syncthreads();
+
+    const bool valid = l < nlt && line_base(g, o, l) >= 0;
+    int u = 0, v = 0;
+    if (valid) line_coords(g, o, l, A.nu, u, v);
+    const T mu = valid ? A.lamu[u] + A.lamv[v] : (T)-1;
+    const bool sing = A.singular && valid && u == 0 && v == 0;
+    const int wave_sing = __any(sing) ? 1 : 0;
+    tri_fast_line<T, RPC, P>(col, coef, c, mu, sing ? 1 : 0, wave_sing, A.periodic);
+    __syncthreads();
+
+    tri_fast_store<T, RPC, P>(lds, as_global(A.data), base, g.sp, g.layout, lines, tid);
+    __syncthreads();
+  }
+}
+
+}  // namespace poisson_dev
