@@ -56,6 +56,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
                                "(run `python -m paper_1802_10323_amd.build`)")
+        # torch ships its own HIP runtime under the same soname as the system
+        # one; loading torch first makes this library bind to that runtime,
+        # so that both share one runtime (and one device context).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

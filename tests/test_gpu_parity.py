@@ -90,13 +90,19 @@ def test_stages_match_oracle(shape, bcs, stretched):
     plan.close()
 
 
+@pytest.mark.parametrize("path", ["specialised", "generic"])
 @pytest.mark.parametrize("kind", KINDS)
-@pytest.mark.parametrize("n", [2, 4, 6, 10, 18, 30, 50, 64, 96, 160, 250, 256, 384, 512, 1024])
-def test_transform_lengths(kind, n):
+@pytest.mark.parametrize("n", [2, 4, 6, 10, 18, 30, 32, 50, 64, 96, 128, 160, 192, 250, 256,
+                               384, 512, 1024])
+def test_transform_lengths(kind, n, path, monkeypatch):
     """Every supported transform length class on the contiguous (x) and the
-    strided (y) axis, against the Table 2 sums; round trip is the identity."""
+    strided (y) axis, against the Table 2 sums; round trip is the identity.
+    Lengths 2M with M in {16, 32, 48, 64, 96, 128, 192, 256} have
+    size-specialised kernels; the generic kernel is run on them too."""
     from oracle import transforms as tr
     from paper_1802_10323_amd import Plan
+    if path == "generic":
+        monkeypatch.setenv("POISSON_GENERIC_R2R", "1")
     rng = np.random.default_rng(n)
     # walls on z make z the elimination axis, so x is role 0 and y role 1
     for axis_name, shape in (("x", (3, 6, n)), ("y", (3, n, 8))):
@@ -114,6 +120,88 @@ def test_transform_lengths(kind, n):
         plan.transform_stage(role, True, d)
         assert rel_l2(to_host(d), f) <= 1e-13
         plan.close()
+
+
+ELIM_LENGTHS = [64, 96, 128, 192, 256, 384, 512]
+UNIT = 2.0 ** -53
+
+
+def _line_systems(x, f, a, b, c, periodic, shift):
+    """Largest normwise backward error over the lines (columns) of
+    (b + shift) x + a x_{k-1} + c x_{k+1} = f."""
+    ax = (b[:, None] + shift[None, :]) * x
+    ax[1:] += a[1:, None] * x[:-1]
+    ax[:-1] += c[:-1, None] * x[1:]
+    if periodic:
+        ax[0] += a[0] * x[-1]
+        ax[-1] += c[-1] * x[0]
+    norm_a = (np.abs(a)[:, None] + np.abs(b[:, None] + shift[None, :]) + np.abs(c)[:, None]).max(axis=0)
+    scale = norm_a * np.linalg.norm(x, axis=0) + np.linalg.norm(f, axis=0)
+    return float((np.linalg.norm(ax - f, axis=0) / scale).max())
+
+
+@pytest.mark.parametrize("path", ["specialised", "generic"])
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("n", ELIM_LENGTHS)
+def test_elimination_lengths(n, kind, path, monkeypatch):
+    """The elimination stage alone for lengths that have size-specialised
+    kernels (and the size-generic kernel on the same input), on the strided
+    (s = z) and contiguous (s = x) layouts, singular and regular, uniform and
+    stretched, with ragged last tiles.
+
+    Checks: (1) every regular line's normwise backward error is at rounding
+    level (<= 1e-14, condition-independent); (2) the result matches the
+    oracle within max(1e-12, kappa u), kappa the 2-norm condition number of
+    the zero-shift (or, when singular, pinned) line operator, which bounds
+    the forward error of any backward-stable solver of the worst line."""
+    from oracle import transforms as tr
+    from oracle import tridiagonal as td
+    from oracle.poisson import tridiagonal_stage
+    from paper_1802_10323_amd import Plan
+    import oracle
+    if path == "generic":
+        monkeypatch.setenv("POISSON_GENERIC_TRI", "1")
+    if kind == "P":   # a periodic elimination axis only occurs when all axes are
+        cases = [((20, 10, n), ("P", "P", "P"), "z")]
+    else:
+        cases = [((20, 10, n), ("P", "P", kind), "z"), ((20, 10, n), ("P", "DD", kind), "z"),
+                 ((n, 10, 6), (kind, "P", "P"), "x"), ((n, 10, 6), (kind, "DD", "P"), "x")]
+    for shape, bcs, s_expect in cases:
+        for stretched in ((False, True) if bcs[2] != "P" else (False,)):
+            prob = inputs.make_uniform(*shape, bcs, seed=n + len(kind),
+                                       stretch_z=1.8 if stretched else None)
+            plan = Plan.from_problem(prob)
+            t1, t2, s = plan.roles
+            assert s == s_expect
+            h = {"x": prob.hx, "y": prob.hy, "z": prob.hz}
+            bc = dict(zip("xyz", bcs))
+            dims = dict(zip("xyz", shape))
+            singular = oracle.is_singular(*bcs)
+            # lines along s as columns: (n_s, n_t1 * n_t2)
+            order = (AXIS[s], AXIS[t1], AXIS[t2])
+            fin = np.transpose(prob.rhs, order).copy()
+            if singular:   # the zero-wavenumber line of a transformed compatible field
+                w = h[s]
+                fin[:, 0, 0] -= (w * fin[:, 0, 0]).sum() / w.sum()
+            f = np.ascontiguousarray(np.transpose(fin, np.argsort(order)))
+            lam1 = tr.eigenvalues(bc[t1], dims[t1]) / h[t1][0] ** 2
+            lam2 = tr.eigenvalues(bc[t2], dims[t2]) / h[t2][0] ** 2
+            ref = tridiagonal_stage(f, s, h[s], bc[s], lam1, lam2, t1, t2, singular)
+            d = to_dev(f)
+            plan.tridiag_stage(d)
+            got = to_host(d)
+            plan.close()
+            a, b, c, periodic = td.coefficients(h[s], bc[s])
+            shift = (lam1[:, None] + lam2[None, :]).reshape(-1)
+            xg = np.transpose(got, order).reshape(dims[s], -1)
+            fl = fin.reshape(dims[s], -1)
+            first = 1 if singular else 0
+            back = _line_systems(xg[:, first:], fl[:, first:], a, b, c, periodic, shift[first:])
+            assert back <= 1e-14, (shape, bcs, stretched, "backward error", back)
+            ops = np.diag(b) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+            kappa = np.linalg.cond(ops[:-1, :-1] if singular else ops)
+            err = rel_l2(got, ref)
+            assert err <= max(1e-12, kappa * UNIT), (shape, bcs, stretched, err, kappa)
 
 
 # --------------------------------------------------------------- whole solve
@@ -224,6 +312,9 @@ def test_cube_full_size_residual():
     ((48, 40, 36), ("P", "P", "NN"), True),
     ((40, 36, 30), ("NN", "NN", "NN"), False),
     ((32, 30, 28), ("P", "P", "P"), False),
+    ((128, 96, 192), ("P", "P", "NN"), True),
+    ((256, 20, 64), ("DD", "P", "P"), False),
+    ((64, 512, 24), ("P", "DN", "DD"), True),
 ])
 def test_mixed_precision_refinement(shape, bcs, stretched):
     prob = inputs.make_uniform(*shape, bcs, seed=5, stretch_z=1.8 if stretched else None)
