@@ -176,7 +176,7 @@ static int lds_setup_once() {
     ALLOW((tridiag_kernel<float, 4, TRI_NT>));
     ALLOW((tridiag_kernel<float, 8, TRI_NT>));
 #define ALLOW_TRI(R, P) ALLOW((tri_fast_kernel<double, R, P>)); ALLOW((tri_fast_kernel<float, R, P>))
-    ALLOW_TRI(4, 16); ALLOW_TRI(6, 16); ALLOW_TRI(4, 32); ALLOW_TRI(6, 32);
+    ALLOW_TRI(4, 16); ALLOW_TRI(6, 16); ALLOW_TRI(8, 16); ALLOW_TRI(12, 16);
     ALLOW_TRI(8, 32); ALLOW_TRI(6, 64); ALLOW_TRI(8, 64);
 #undef ALLOW_TRI
 #undef ALLOW
@@ -369,16 +369,16 @@ static int launch_tri_fast(const poisson_plan* p, T* data, hipStream_t st, const
 template <typename T>
 static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
                           const double* skip = nullptr) {
-  if (!p->generic_tri && p->dims[p->s] == p->P * p->lcmax) {
-    const int key = p->lcmax * 100 + p->P;
-    switch (key) {
-      case 416: return launch_tri_fast<T, 4, 16>(p, data, st, skip);
-      case 616: return launch_tri_fast<T, 6, 16>(p, data, st, skip);
-      case 432: return launch_tri_fast<T, 4, 32>(p, data, st, skip);
-      case 632: return launch_tri_fast<T, 6, 32>(p, data, st, skip);
-      case 832: return launch_tri_fast<T, 8, 32>(p, data, st, skip);
-      case 664: return launch_tri_fast<T, 6, 64>(p, data, st, skip);
-      case 864: return launch_tri_fast<T, 8, 64>(p, data, st, skip);
+  if (!p->generic_tri) {
+    // size-specialised kernels: rows per chunk x chunks per line
+    switch (p->dims[p->s]) {
+      case 64: return launch_tri_fast<T, 4, 16>(p, data, st, skip);
+      case 96: return launch_tri_fast<T, 6, 16>(p, data, st, skip);
+      case 128: return launch_tri_fast<T, 8, 16>(p, data, st, skip);
+      case 192: return launch_tri_fast<T, 12, 16>(p, data, st, skip);
+      case 256: return launch_tri_fast<T, 8, 32>(p, data, st, skip);
+      case 384: return launch_tri_fast<T, 6, 64>(p, data, st, skip);
+      case 512: return launch_tri_fast<T, 8, 64>(p, data, st, skip);
       default: break;
     }
   }

@@ -5,15 +5,19 @@
 // Same algorithm as tridiag_kernel.h (chunked Thomas, interface system by
 // parallel cyclic reduction, back substitution), with every loop bound a
 // compile-time constant, so that
-//  * each thread reads its RPC right-hand-side values and the RPC rows of
-//    coefficients it needs in one burst of LDS reads (the coefficients of
-//    the axis are copied to LDS once per block, laid out [row in chunk][chunk]
-//    so that the P lanes of a line read consecutive words);
+//  * the coefficients of the axis are copied to LDS once per block, laid out
+//    [row in chunk][chunk] so that the P lanes of a line read consecutive
+//    words, instead of being fetched from global memory row by row;
 //  * the whole chunk (values, pivots, spike vector) lives in registers from
 //    the first read to the final write;
 //  * the reciprocal of every pivot is the hardware estimate refined by
 //    Newton steps (relative error at the rounding level of the type)
-//    instead of a correctly rounded division sequence.
+//    instead of a correctly rounded division sequence;
+//  * the interface system is reduced in normalised form (unit diagonal:
+//    three values move between lanes per step instead of four, one
+//    reciprocal instead of two), and a line of 16 chunks occupies one
+//    16-lane row of the wavefront, so its exchanges are DPP row rotations
+//    (VALU) instead of LDS permutes.
 #pragma once
 #include "tridiag_kernel.h"
 
@@ -139,11 +143,66 @@ __device__ __forceinline__ T line_sum(T v) {
   return v;
 }
 
+// Cyclic rotation inside a row of 16 lanes (DPP row_ror: lane i reads lane
+// (i - R) mod 16 of its row); a VALU operation, no LDS traffic.
+template <int R>
+__device__ __forceinline__ int dpp_ror(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x120 + R, 0xF, 0xF, false);
+}
+template <int R>
+__device__ __forceinline__ float dpp_ror(float v) {
+  return __builtin_bit_cast(float, dpp_ror<R>(__builtin_bit_cast(int, v)));
+}
+template <int R>
+__device__ __forceinline__ double dpp_ror(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)dpp_ror<R>((int)(unsigned)b);
+  const unsigned hi = (unsigned)dpp_ror<R>((int)(unsigned)(b >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// v of the lane ST places before (AFTER = false) or after (AFTER = true)
+// this one, cyclically within its group of P lanes.  A group of 16 lanes is
+// one DPP row; larger groups go through ds_bpermute.
+template <int P, int ST, bool AFTER, typename T>
+__device__ __forceinline__ T group_rot(T v, int gbase, int c) {
+  if constexpr (P == 16) {
+    return dpp_ror<AFTER ? 16 - ST : ST>(v);
+  } else {
+    return __shfl(v, gbase + ((AFTER ? c + ST : c - ST) & (P - 1)), 64);
+  }
+}
+
+// Parallel cyclic reduction of the interface equations, kept normalised:
+// x_c + l x_{c-ST} + u x_{c+ST} = r.  Each step subtracts l times the
+// equation of lane c-ST and u times that of lane c+ST, doubling the coupling
+// distance; outside a non-periodic line the neighbour is the identity
+// equation x = 0.
+template <typename T, int P, int ST>
+__device__ __forceinline__ void pcr(T& l, T& u, T& r, int c, int gbase, int periodic) {
+  if constexpr (ST < P) {
+    T lm = group_rot<P, ST, false>(l, gbase, c);
+    T um = group_rot<P, ST, false>(u, gbase, c);
+    T rm = group_rot<P, ST, false>(r, gbase, c);
+    T lp = group_rot<P, ST, true>(l, gbase, c);
+    T up = group_rot<P, ST, true>(u, gbase, c);
+    T rp = group_rot<P, ST, true>(r, gbase, c);
+    if (!periodic && c < ST) { lm = 0; um = 0; rm = 0; }
+    if (!periodic && c + ST >= P) { lp = 0; up = 0; rp = 0; }
+    const T inv = fast_rcp((T)1 - l * um - u * lp);
+    const T rn = (r - l * rm - u * rp) * inv;
+    l = -l * lm * inv;
+    u = -u * up * inv;
+    r = rn;
+    pcr<T, P, 2 * ST>(l, u, r, c, gbase, periodic);
+  }
+}
+
 // Eliminate the line held by this lane's group: chunk c of the line, LDS
 // column col (row i at col[i * NLP]), coefficient tables ca/cb/cc/cw laid out
 // [row in chunk][chunk], shift mu, and the singular-line flags.
 template <typename T, int RPC, int P>
-__device__ __noinline__ void tri_fast_line(lptr<T> col, lptr<const T> coef, int c, T mu,
+__device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const T> coef, int c, T mu,
                                            int sing, int wave_sing, int periodic) {
   using L = TriFastLayout<T, RPC, P>;
   constexpr int N = L::N;
@@ -151,14 +210,9 @@ __device__ __noinline__ void tri_fast_line(lptr<T> col, lptr<const T> coef, int 
   const int lane = threadIdx.x & 63;
   const int gbase = lane - c;
 
-  T x[RPC], av[RPC], bv[RPC], cv[RPC];
+  T x[RPC];
 #pragma unroll
-  for (int i = 0; i < RPC; ++i) {
-    x[i] = col[i * L::NLP];
-    av[i] = ca[i * P + c];
-    bv[i] = cb[i * P + c];
-    cv[i] = cc[i * P + c];
-  }
+  for (int i = 0; i < RPC; ++i) x[i] = col[i * L::NLP];
 
   if (wave_sing) {   // project the right-hand side of the null-space line
     T sw = 0, swf = 0;
@@ -181,19 +235,20 @@ __device__ __noinline__ void tri_fast_line(lptr<T> col, lptr<const T> coef, int 
   // qv = spike of the previous interface, cp = c / pivot
   constexpr int NI = RPC - 1;
   T cp[NI], qv[NI];
-  T r = fast_rcp(bv[0] + mu);
+  T r = fast_rcp(cb[c] + mu);
   x[0] *= r;
-  qv[0] = av[0] * r;
-  cp[0] = cv[0] * r;
+  qv[0] = ca[c] * r;
+  cp[0] = cc[c] * r;
 #pragma unroll
   for (int i = 1; i < NI; ++i) {
-    r = fast_rcp(bv[i] + mu - av[i] * cp[i - 1]);
-    x[i] = (x[i] - av[i] * x[i - 1]) * r;
-    qv[i] = -av[i] * qv[i - 1] * r;
-    cp[i] = cv[i] * r;
+    const T ai = ca[i * P + c], bi = cb[i * P + c], ci = cc[i * P + c];
+    r = fast_rcp(bi + mu - ai * cp[i - 1]);
+    x[i] = (x[i] - ai * x[i - 1]) * r;
+    qv[i] = -ai * qv[i - 1] * r;
+    cp[i] = ci * r;
   }
   // first-row values of y = T^-1 f, v = T^-1 (a e_first), w = T^-1 (c e_last)
-  const T yl = x[NI - 1], vl = qv[NI - 1], wl = cv[NI - 1] * r;
+  const T yl = x[NI - 1], vl = qv[NI - 1], wl = cc[(NI - 1) * P + c] * r;
   T yf = yl, vf = vl, wf = wl;
 #pragma unroll
   for (int i = NI - 2; i >= 0; --i) {
@@ -203,35 +258,19 @@ __device__ __noinline__ void tri_fast_line(lptr<T> col, lptr<const T> coef, int 
   }
 
   // phase 2: interface row (last row of the chunk), reduced by PCR
-  T ae = av[NI], be = bv[NI] + mu, ce = cv[NI], fe = x[NI];
+  T ae = ca[NI * P + c], be = cb[NI * P + c] + mu, ce = cc[NI * P + c], fe = x[NI];
   if (sing && c == P - 1) { ae = 0; be = 1; ce = 0; fe = 0; }   // pin x_{n-1} = 0
-  const int nxt = gbase + ((c + 1) & (P - 1));
-  const T yf_n = __shfl(yf, nxt, 64), vf_n = __shfl(vf, nxt, 64), wf_n = __shfl(wf, nxt, 64);
-  T Lq = -ae * vl;
-  T Dq = be - ae * wl - ce * vf_n;
-  T Uq = -ce * wf_n;
-  T Rq = fe - ae * yl - ce * yf_n;
-#pragma unroll
-  for (int st = 1; st < P; st <<= 1) {
-    const int cm = c - st, cpl = c + st;
-    const int srcm = gbase + (cm & (P - 1));
-    const int srcp = gbase + (cpl & (P - 1));
-    T Lm = __shfl(Lq, srcm, 64), Dm = __shfl(Dq, srcm, 64);
-    T Um = __shfl(Uq, srcm, 64), Rm = __shfl(Rq, srcm, 64);
-    T Lp = __shfl(Lq, srcp, 64), Dp = __shfl(Dq, srcp, 64);
-    T Up = __shfl(Uq, srcp, 64), Rp = __shfl(Rq, srcp, 64);
-    if (!periodic && cm < 0) { Lm = 0; Dm = 1; Um = 0; Rm = 0; }
-    if (!periodic && cpl >= P) { Lp = 0; Dp = 1; Up = 0; Rp = 0; }
-    const T k1 = Lq * fast_rcp(Dm);
-    const T k2 = Uq * fast_rcp(Dp);
-    Dq = Dq - Um * k1 - Lp * k2;
-    Rq = Rq - Rm * k1 - Rp * k2;
-    Lq = -Lm * k1;
-    Uq = -Up * k2;
-  }
+  const T yf_n = group_rot<P, 1, true>(yf, gbase, c);
+  const T vf_n = group_rot<P, 1, true>(vf, gbase, c);
+  const T wf_n = group_rot<P, 1, true>(wf, gbase, c);
+  const T inv = fast_rcp(be - ae * wl - ce * vf_n);
+  T lq = -ae * vl * inv;
+  T uq = -ce * wf_n * inv;
+  T rq = (fe - ae * yl - ce * yf_n) * inv;
+  pcr<T, P, 1>(lq, uq, rq, c, gbase, periodic);
   // after the reduction the remaining couplings point back at this unknown
-  const T Ic = Rq / (periodic ? Lq + Dq + Uq : Dq);
-  T Ip = __shfl(Ic, gbase + ((c - 1) & (P - 1)), 64);
+  const T Ic = periodic ? rq / ((T)1 + lq + uq) : rq;
+  T Ip = group_rot<P, 1, false>(Ic, gbase, c);
   if (!periodic && c == 0) Ip = 0;
 
   // phase 3: back substitution of the interior
