@@ -17,7 +17,6 @@ kernel's duration and bandwidth), and `forms` (the FP32 + refinement, batched
 and served forms, each measured separately; not part of `value`).
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,35 +29,24 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 BYTES_PER_POINT_FP64 = 16.0     # one sweep: read + write 8 B per point
 STAGES = ("fwd_t1", "fwd_t2", "tridiag", "inv_t2", "inv_t1")
-KERNEL_SOURCES = ("r2r_kernel.h", "tridiag_kernel.h", "device_common.h")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1802_10323_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def stored_traffic(workload, stage):
-    """HBM bytes per launch measured by rocprofv3 counters (profiles/), or
-    None when absent or taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    """HBM bytes per launch of `stage` measured by rocprofv3 counters
+    (profiles/traffic_<workload>.txt), or None when absent or taken on
+    other kernel sources."""
+    from paper_1802_10323_amd import profiling
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
-    try:
-        with open(path) as fh:
-            rec = json.load(fh)
-    except (OSError, ValueError):
+    src, per_stage = profiling.read_traffic(path)
+    if src != profiling.kernel_source_hash():
         return None
-    if rec.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    return rec.get("bytes_per_launch", {}).get(stage)
+    return per_stage.get(stage)
 
 
 def make_problem(workload, seed=0):
