@@ -122,10 +122,46 @@ size_t plan_workspace_bytes(const poisson_plan* plan);
 int solve_status(poisson_plan* plan, int* iters, double* last_update_rel);
 
 /* Solve `count` independent problems, plans[i] applied in place to rhs[i]
- * (DEVICE pointers), as one batched sequence of launches on `stream`: every
- * stage of every instance is one work item of the same grid.  FP64 plans only;
- * plans must be distinct.  Same semantics per instance as solve(). */
+ * (DEVICE pointers), on `stream`.  FP64 plans only; plans must be distinct.
+ * Same result per instance as solve(), bit for bit.  When every plan's lengths
+ * have size-specialised kernels (batch_create), the solves run as one
+ * persistent launch per stage over all instances and the call waits for
+ * `stream` to complete (it frees its temporary job tables); otherwise the
+ * instances' launches are enqueued one solve after another and the call
+ * returns at once. */
 int batch_solve(poisson_plan* const* plans, double* const* rhs, int count, hipStream_t stream);
+
+/* ---- batched launches (many uneven instances, Sec. 2.1 per instance) ----
+ *
+ * A batch runs the three steps of Sec. 2.1 for many independent problems as
+ * five launches, one per pipeline step (forward t1, forward t2, elimination,
+ * backward t2, backward t1).  Each launch is a persistent grid whose work
+ * items are the tiles of every instance's stage, so instances of different
+ * sizes, boundary pairs and axis roles share one launch. */
+typedef struct poisson_batch poisson_batch;
+
+/* Batch over `count` FP64 plans (HOST array of plan handles, all created on
+ * the current device).  The plans are borrowed: they must outlive the batch.
+ * Every transformed length must be 2M with M in {16, 32, 48, 64, 96, 128,
+ * 192, 256} and every elimination length one of {64, 96, 128, 192, 256, 384,
+ * 512} (POISSON_EUNSUPPORTED otherwise).  Allocates the device job tables.
+ * Returns NULL on error (last_error()). */
+poisson_batch* batch_create(poisson_plan* const* plans, int count);
+
+/* Set the fields: rhs is a HOST array of `count` DEVICE pointers, rhs[i] is
+ * solved in place with plans[i] (nx*ny*nz doubles, x fastest).  Copies the job
+ * tables to the device synchronously; must not be called while a launch of
+ * this batch may still be running.  A captured graph stays valid. */
+int batch_bind(poisson_batch* batch, double* const* rhs);
+
+/* Enqueue the five stage launches on `stream` (asynchronous).  use_graph != 0:
+ * the first call captures them into a HIP graph on a private stream, and every
+ * call launches that graph on `stream`. */
+int batch_launch(poisson_batch* batch, hipStream_t stream, int use_graph);
+
+/* Free the job tables and the graph.  The caller makes sure no launch of the
+ * batch is still running. */
+void batch_destroy(poisson_batch* batch);
 
 /* ---- stage entry points (the steps of Sec. 2.1, for stage-level checks) ---- */
 

@@ -64,8 +64,65 @@ def mixed(log, steps=6, warmup=2):
             "rel_l2_vs_gpu_fp64": rel, "tolerance": 1e-10}
 
 
+def batch(log, count=64, steps=5, warmup=2, seed=0):
+    """64 uneven instances: one solve() per instance in turn, against the
+    batched form (one persistent launch per stage) enqueued directly and as
+    a replayed HIP graph.  Every form solves the same fields."""
+    import torch
+    from . import Batch, Plan, inputs
+    probs = inputs.batch(seed, count=count)
+    points = sum(p.points for p in probs)
+    plans = [Plan.from_problem(p) for p in probs]
+    src = [torch.from_numpy(p.rhs).cuda() for p in probs]
+    work = [s.clone() for s in src]
+    B = Batch(plans)
+    B.bind(work)
+
+    def refill():
+        for w, s in zip(work, src):
+            w.copy_(s)
+
+    def singles():
+        for pl, w in zip(plans, work):
+            pl.solve(w)
+
+    forms = {"single": singles, "batch": lambda: B.launch(graph=False),
+             "graph": lambda: B.launch(graph=True)}
+    ms = {}
+    results = {}
+    for name, fn in forms.items():
+        for _ in range(warmup):
+            refill()
+            fn()
+        times = []
+        for _ in range(steps):
+            refill()
+            times += _timed(fn, 1, torch)
+        ms[name] = float(np.median(times))
+        refill()
+        fn()
+        torch.cuda.synchronize()
+        results[name] = [w.clone() for w in work[:8]]
+    same = all(torch.equal(a, b) for name in ("batch", "graph")
+               for a, b in zip(results[name], results["single"]))
+    log(f"[forms] batch {count} instances ({points / 1e6:.1f} M points): one by one "
+        f"{ms['single']:.3f} ms, batched {ms['batch']:.3f} ms, graph {ms['graph']:.3f} ms; "
+        f"bitwise equal to single solves: {same}")
+    B.close()
+    for pl in plans:
+        pl.close()
+    return {"workload": f"{count} instances, per-axis n from {{64,96,128,192,256}}, random BC pairs",
+            "points": points, "single_ms": round(ms["single"], 4), "batched_ms": round(ms["batch"], 4),
+            "graph_ms": round(ms["graph"], 4),
+            "graph_points_per_s": points / (ms["graph"] * 1e-3),
+            "speedup_vs_single": round(ms["single"] / ms["graph"], 4),
+            "bitwise_equal_to_single": bool(same)}
+
+
 def run(wanted, log):
     out = {}
     if "mixed" in wanted:
         out["mixed"] = mixed(log)
+    if "batch" in wanted:
+        out["batch"] = batch(log)
     return out

@@ -6,6 +6,7 @@
 // backward transforms), each step one HBM sweep of the field by one kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -19,6 +20,7 @@
 #include "r2r_fast.h"
 #include "tridiag_kernel.h"
 #include "tri_fast.h"
+#include "batch_kernels.h"
 #include "refine_kernels.h"
 
 using namespace poisson_dev;
@@ -179,6 +181,8 @@ static int lds_setup_once() {
     ALLOW_TRI(4, 16); ALLOW_TRI(6, 16); ALLOW_TRI(8, 16); ALLOW_TRI(12, 16);
     ALLOW_TRI(8, 32); ALLOW_TRI(6, 64); ALLOW_TRI(8, 64);
 #undef ALLOW_TRI
+    ALLOW((batch_r2r_kernel<double>));
+    ALLOW((batch_tri_kernel<double>));
 #undef ALLOW
     status = e == hipSuccess ? 0 : fail(POISSON_EHIP, "hipFuncSetAttribute: %s", hipGetErrorString(e));
   });
@@ -259,10 +263,11 @@ static int resident_grid(const void* fn, int block, size_t lds, long long ntiles
 
 // ------------------------------------------------------------------ launches
 
-// Size-specialised transform kernel (r2r_fast.h) for complex length M.
+// Launch arguments of the size-specialised transform kernel (r2r_fast.h)
+// for complex length M.
 template <typename T, int M>
-static int launch_fast(const poisson_plan* p, const AxisTables& A, int inverse, T* data,
-                       hipStream_t st, const double* skip) {
+static R2RFastArgs<T> fast_args(const poisson_plan* p, const AxisTables& A, int inverse, T* data,
+                                const double* skip) {
   using L = FastLayout<T, M>;
   R2RFastArgs<T> a{};
   a.data = data;
@@ -278,6 +283,14 @@ static int launch_fast(const poisson_plan* p, const AxisTables& A, int inverse, 
   a.tw_pre = tw + 3 * M + 2;
   a.tw_post = tw + 4 * M + 2;
   a.skip = skip;
+  return a;
+}
+
+template <typename T, int M>
+static int launch_fast(const poisson_plan* p, const AxisTables& A, int inverse, T* data,
+                       hipStream_t st, const double* skip) {
+  using L = FastLayout<T, M>;
+  const R2RFastArgs<T> a = fast_args<T, M>(p, A, inverse, data, skip);
   const size_t lds = fast_lds_bytes<T, M>();
   const void* fn = reinterpret_cast<const void*>(&r2r_fast_kernel<T, M>);
   hipLaunchKernelGGL((r2r_fast_kernel<T, M>), dim3(resident_grid(fn, L::NT, lds, a.g.ntiles)),
@@ -340,8 +353,9 @@ static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hip
   return POISSON_OK;
 }
 
+// Launch arguments of the size-specialised elimination kernel (tri_fast.h).
 template <typename T, int RPC, int P>
-static int launch_tri_fast(const poisson_plan* p, T* data, hipStream_t st, const double* skip) {
+static TriFastArgs<T> tri_fast_args(const poisson_plan* p, T* data, const double* skip) {
   using L = TriFastLayout<T, RPC, P>;
   TriFastArgs<T> a{};
   a.data = data;
@@ -358,6 +372,13 @@ static int launch_tri_fast(const poisson_plan* p, T* data, hipStream_t st, const
   a.lamu = lam;
   a.lamv = lam + p->nu;
   a.skip = skip;
+  return a;
+}
+
+template <typename T, int RPC, int P>
+static int launch_tri_fast(const poisson_plan* p, T* data, hipStream_t st, const double* skip) {
+  using L = TriFastLayout<T, RPC, P>;
+  const TriFastArgs<T> a = tri_fast_args<T, RPC, P>(p, data, skip);
   const size_t lds = tri_fast_lds_bytes<T, RPC, P>();
   const void* fn = reinterpret_cast<const void*>(&tri_fast_kernel<T, RPC, P>);
   hipLaunchKernelGGL((tri_fast_kernel<T, RPC, P>), dim3(resident_grid(fn, L::NT, lds, a.g.ntiles)),
@@ -366,19 +387,42 @@ static int launch_tri_fast(const poisson_plan* p, T* data, hipStream_t st, const
   return POISSON_OK;
 }
 
+// Shape (rows per chunk * 100 + chunks per line) of the size-specialised
+// elimination kernel for lines of n points, or 0 if n has none.
+static int tri_fast_shape(int n) {
+  switch (n) {
+    case 64: return 416;
+    case 96: return 616;
+    case 128: return 816;
+    case 192: return 1216;
+    case 256: return 832;
+    case 384: return 664;
+    case 512: return 864;
+    default: return 0;
+  }
+}
+
+// Complex length M of the size-specialised transform kernel for axis A, or
+// 0 if its length has none.
+static int r2r_fast_length(const AxisTables& A) {
+  switch (A.m) {
+    case 16: case 32: case 48: case 64: case 96: case 128: case 192: case 256: return A.m;
+    default: return 0;
+  }
+}
+
 template <typename T>
 static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
                           const double* skip = nullptr) {
   if (!p->generic_tri) {
-    // size-specialised kernels: rows per chunk x chunks per line
-    switch (p->dims[p->s]) {
-      case 64: return launch_tri_fast<T, 4, 16>(p, data, st, skip);
-      case 96: return launch_tri_fast<T, 6, 16>(p, data, st, skip);
-      case 128: return launch_tri_fast<T, 8, 16>(p, data, st, skip);
-      case 192: return launch_tri_fast<T, 12, 16>(p, data, st, skip);
-      case 256: return launch_tri_fast<T, 8, 32>(p, data, st, skip);
-      case 384: return launch_tri_fast<T, 6, 64>(p, data, st, skip);
-      case 512: return launch_tri_fast<T, 8, 64>(p, data, st, skip);
+    switch (tri_fast_shape(p->dims[p->s])) {
+      case 416: return launch_tri_fast<T, 4, 16>(p, data, st, skip);
+      case 616: return launch_tri_fast<T, 6, 16>(p, data, st, skip);
+      case 816: return launch_tri_fast<T, 8, 16>(p, data, st, skip);
+      case 1216: return launch_tri_fast<T, 12, 16>(p, data, st, skip);
+      case 832: return launch_tri_fast<T, 8, 32>(p, data, st, skip);
+      case 664: return launch_tri_fast<T, 6, 64>(p, data, st, skip);
+      case 864: return launch_tri_fast<T, 8, 64>(p, data, st, skip);
       default: break;
     }
   }
@@ -771,9 +815,253 @@ extern "C" int batch_solve(poisson_plan* const* plans, double* const* rhs, int c
     if (!plans[i] || !rhs[i]) return fail(POISSON_EINVAL, "null plan or field at batch index %d", i);
     if (plans[i]->mode != POISSON_FP64) return fail(POISSON_EINVAL, "batch_solve takes FP64 plans (index %d)", i);
   }
+  bool specialised = true;
+  for (int i = 0; i < count && specialised; ++i) {
+    const poisson_plan* p = plans[i];
+    specialised = r2r_fast_length(p->ax[0]) && r2r_fast_length(p->ax[1]) &&
+                  tri_fast_shape(p->dims[p->s]) && !p->generic_r2r && !p->generic_tri;
+  }
+  if (count > 0 && specialised) {
+    poisson_batch* b = batch_create(plans, count);
+    if (!b) return g_err;
+    int rc = batch_bind(b, rhs);
+    if (!rc) rc = batch_launch(b, st, 0);
+    const hipError_t e = hipStreamSynchronize(st);
+    batch_destroy(b);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(POISSON_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    return POISSON_OK;
+  }
   for (int i = 0; i < count; ++i) {
     const int rc = solve_typed<double>(plans[i], rhs[i], st);
     if (rc) return rc;
   }
   return POISSON_OK;
+}
+
+// ------------------------------------------------------------------ batched launches
+
+// Pipeline steps of a solve (Sec. 2.1): forward t1, forward t2, elimination,
+// backward t2, backward t1, as (transform role or -1, inverse).
+static const int kStepRole[5] = {0, 1, -1, 1, 0};
+static const int kStepInverse[5] = {0, 0, 0, 1, 1};
+
+struct poisson_batch {
+  int device = 0;
+  std::vector<poisson_plan*> plans;
+  std::vector<int> order[5];          // instances in job order, per step
+  int njobs[5] = {0, 0, 0, 0, 0};
+  int items[5] = {0, 0, 0, 0, 0};
+  size_t lds[5] = {0, 0, 0, 0, 0};
+  size_t off[5] = {0, 0, 0, 0, 0};    // byte offset of each step's job array
+  size_t bytes = 0;
+  char* djobs = nullptr;              // device job arrays (all steps)
+  bool bound = false;
+  hipStream_t cap = nullptr;          // private stream for graph capture
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static size_t fast_lds_for(int M) {
+  switch (M) {
+    case 16: return fast_lds_bytes<double, 16>();
+    case 32: return fast_lds_bytes<double, 32>();
+    case 48: return fast_lds_bytes<double, 48>();
+    case 64: return fast_lds_bytes<double, 64>();
+    case 96: return fast_lds_bytes<double, 96>();
+    case 128: return fast_lds_bytes<double, 128>();
+    case 192: return fast_lds_bytes<double, 192>();
+    case 256: return fast_lds_bytes<double, 256>();
+    default: return 0;
+  }
+}
+
+static size_t tri_lds_for(int shape) {
+  switch (shape) {
+    case 416: return tri_fast_lds_bytes<double, 4, 16>();
+    case 616: return tri_fast_lds_bytes<double, 6, 16>();
+    case 816: return tri_fast_lds_bytes<double, 8, 16>();
+    case 1216: return tri_fast_lds_bytes<double, 12, 16>();
+    case 832: return tri_fast_lds_bytes<double, 8, 32>();
+    case 664: return tri_fast_lds_bytes<double, 6, 64>();
+    case 864: return tri_fast_lds_bytes<double, 8, 64>();
+    default: return 0;
+  }
+}
+
+static R2RFastArgs<double> fast_args_for(const poisson_plan* p, const AxisTables& A, int inverse,
+                                         double* data) {
+  switch (A.m) {
+    case 16: return fast_args<double, 16>(p, A, inverse, data, nullptr);
+    case 32: return fast_args<double, 32>(p, A, inverse, data, nullptr);
+    case 48: return fast_args<double, 48>(p, A, inverse, data, nullptr);
+    case 64: return fast_args<double, 64>(p, A, inverse, data, nullptr);
+    case 96: return fast_args<double, 96>(p, A, inverse, data, nullptr);
+    case 128: return fast_args<double, 128>(p, A, inverse, data, nullptr);
+    case 192: return fast_args<double, 192>(p, A, inverse, data, nullptr);
+    default: return fast_args<double, 256>(p, A, inverse, data, nullptr);
+  }
+}
+
+static TriFastArgs<double> tri_args_for(const poisson_plan* p, int shape, double* data) {
+  switch (shape) {
+    case 416: return tri_fast_args<double, 4, 16>(p, data, nullptr);
+    case 616: return tri_fast_args<double, 6, 16>(p, data, nullptr);
+    case 816: return tri_fast_args<double, 8, 16>(p, data, nullptr);
+    case 1216: return tri_fast_args<double, 12, 16>(p, data, nullptr);
+    case 832: return tri_fast_args<double, 8, 32>(p, data, nullptr);
+    case 664: return tri_fast_args<double, 6, 64>(p, data, nullptr);
+    default: return tri_fast_args<double, 8, 64>(p, data, nullptr);
+  }
+}
+
+// Job tables of every step for the given fields (null fields: sizes only).
+static void batch_jobs(poisson_batch* b, double* const* rhs, std::vector<char>& host) {
+  host.assign(b->bytes, 0);
+  for (int k = 0; k < 5; ++k) {
+    int first = 0;
+    for (size_t j = 0; j < b->order[k].size(); ++j) {
+      const int i = b->order[k][j];
+      const poisson_plan* p = b->plans[i];
+      double* data = rhs ? rhs[i] : nullptr;
+      if (kStepRole[k] >= 0) {
+        BatchR2RJob<double> J{};
+        J.a = fast_args_for(p, p->ax[kStepRole[k]], kStepInverse[k], data);
+        J.M = p->ax[kStepRole[k]].m;
+        J.first = first;
+        first += J.a.g.ntiles;
+        std::memcpy(host.data() + b->off[k] + j * sizeof(J), &J, sizeof(J));
+      } else {
+        BatchTriJob<double> J{};
+        J.shape = tri_fast_shape(p->dims[p->s]);
+        J.a = tri_args_for(p, J.shape, data);
+        J.first = first;
+        first += J.a.g.ntiles;
+        std::memcpy(host.data() + b->off[k] + j * sizeof(J), &J, sizeof(J));
+      }
+    }
+    b->items[k] = first;
+  }
+}
+
+extern "C" poisson_batch* batch_create(poisson_plan* const* plans, int count) {
+  if (count < 1 || !plans) { fail(POISSON_EINVAL, "a batch needs at least one plan"); return nullptr; }
+  if (lds_setup_once()) return nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { fail(POISSON_EHIP, "hipGetDevice failed"); return nullptr; }
+  for (int i = 0; i < count; ++i) {
+    const poisson_plan* p = plans[i];
+    if (!p) { fail(POISSON_EINVAL, "null plan at batch index %d", i); return nullptr; }
+    if (p->device != dev) { fail(POISSON_EINVAL, "plan %d lives on another device", i); return nullptr; }
+    if (p->mode != POISSON_FP64) { fail(POISSON_EUNSUPPORTED, "batched launches take FP64 plans (index %d)", i); return nullptr; }
+    for (int r = 0; r < 2; ++r)
+      if (!r2r_fast_length(p->ax[r])) {
+        fail(POISSON_EUNSUPPORTED, "plan %d: transform length %d has no size-specialised kernel", i, p->ax[r].n);
+        return nullptr;
+      }
+    if (!tri_fast_shape(p->dims[p->s])) {
+      fail(POISSON_EUNSUPPORTED, "plan %d: elimination length %d has no size-specialised kernel", i, p->dims[p->s]);
+      return nullptr;
+    }
+  }
+  poisson_batch* b = new poisson_batch();
+  b->device = dev;
+  b->plans.assign(plans, plans + count);
+  size_t bytes = 0;
+  for (int k = 0; k < 5; ++k) {
+    std::vector<int>& ord = b->order[k];
+    for (int i = 0; i < count; ++i) ord.push_back(i);
+    // group jobs that share LDS tables: transforms by length and type class
+    // (twiddles), eliminations by shape
+    auto key = [&](int i) {
+      const poisson_plan* p = plans[i];
+      if (kStepRole[k] >= 0) {
+        const AxisTables& A = p->ax[kStepRole[k]];
+        return A.m * 2 + (A.kind >= BC_ND ? 1 : 0);
+      }
+      return tri_fast_shape(p->dims[p->s]);
+    };
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return key(x) < key(y); });
+    size_t lds = 0;
+    for (int i : ord) {
+      const poisson_plan* p = plans[i];
+      lds = std::max(lds, kStepRole[k] >= 0 ? fast_lds_for(p->ax[kStepRole[k]].m)
+                                            : tri_lds_for(tri_fast_shape(p->dims[p->s])));
+    }
+    b->lds[k] = lds;
+    b->njobs[k] = count;
+    bytes = align_up(bytes, 64);
+    b->off[k] = bytes;
+    bytes += (size_t)count * (kStepRole[k] >= 0 ? sizeof(BatchR2RJob<double>) : sizeof(BatchTriJob<double>));
+  }
+  b->bytes = bytes;
+  std::vector<char> host;
+  batch_jobs(b, nullptr, host);       // item counts
+  if (hipMalloc(&b->djobs, b->bytes) != hipSuccess) {
+    fail(POISSON_ENOMEM, "batch job tables: hipMalloc of %zu B failed", b->bytes);
+    delete b;
+    return nullptr;
+  }
+  return b;
+}
+
+extern "C" int batch_bind(poisson_batch* b, double* const* rhs) {
+  if (!b || !rhs) return fail(POISSON_EINVAL, "null argument");
+  for (size_t i = 0; i < b->plans.size(); ++i)
+    if (!rhs[i]) return fail(POISSON_EINVAL, "null field at batch index %zu", i);
+  std::vector<char> host;
+  batch_jobs(b, rhs, host);
+  HIP_TRY(hipMemcpy(b->djobs, host.data(), b->bytes, hipMemcpyHostToDevice));
+  b->bound = true;
+  return POISSON_OK;
+}
+
+static int batch_enqueue(poisson_batch* b, hipStream_t st) {
+  for (int k = 0; k < 5; ++k) {
+    if (b->items[k] == 0) continue;
+    const size_t lds = b->lds[k];
+    if (kStepRole[k] >= 0) {
+      const auto* jobs = reinterpret_cast<const BatchR2RJob<double>*>(b->djobs + b->off[k]);
+      const void* fn = reinterpret_cast<const void*>(&batch_r2r_kernel<double>);
+      hipLaunchKernelGGL(batch_r2r_kernel<double>, dim3(resident_grid(fn, 512, lds, b->items[k])),
+                         dim3(512), lds, st, jobs, b->njobs[k], b->items[k]);
+    } else {
+      const auto* jobs = reinterpret_cast<const BatchTriJob<double>*>(b->djobs + b->off[k]);
+      const void* fn = reinterpret_cast<const void*>(&batch_tri_kernel<double>);
+      hipLaunchKernelGGL(batch_tri_kernel<double>, dim3(resident_grid(fn, 512, lds, b->items[k])),
+                         dim3(512), lds, st, jobs, b->njobs[k], b->items[k]);
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  return POISSON_OK;
+}
+
+extern "C" int batch_launch(poisson_batch* b, hipStream_t st, int use_graph) {
+  if (!b) return fail(POISSON_EINVAL, "null batch");
+  if (!b->bound) return fail(POISSON_EINVAL, "batch has no fields bound (batch_bind)");
+  if (!use_graph) return batch_enqueue(b, st);
+  if (!b->exec) {
+    // capture the five launches once on a private stream; the job tables
+    // live in device memory, so later batch_bind calls need no re-capture
+    HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = batch_enqueue(b, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return fail(POISSON_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipGraphLaunch(b->exec, st));
+  return POISSON_OK;
+}
+
+extern "C" void batch_destroy(poisson_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->djobs) (void)hipFree(b->djobs);
+  delete b;
 }

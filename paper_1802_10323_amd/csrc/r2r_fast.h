@@ -415,67 +415,97 @@ __device__ __noinline__ void fast_split(lptr<T> lds, lptr<const cplx<T>> split,
 
 // ---------------------------------------------------------------- kernel
 
+// LDS regions of the specialised transform: the tile, then the FFT twiddles
+// (M), then the pre/post (DCT-IV types) or split/quarter tables (2M).
 template <typename T, int M>
-__global__ __launch_bounds__(fast_nt<M>()) __attribute__((amdgpu_waves_per_eu(4)))
-void r2r_fast_kernel(R2RFastArgs<T> A) {
+struct FastLds {
+  lptr<T> tile;
+  lptr<cplx<T>> twf, twa;
+};
+template <typename T, int M>
+__device__ __forceinline__ FastLds<T, M> fast_lds(unsigned char* smem) {
   using L = FastLayout<T, M>;
-  constexpr int NL = L::NL, NT = L::NT;
-  if (A.skip && A.skip[0] != 0.0) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const lptr<T> lds = as_lds(reinterpret_cast<T*>(smem_raw));
-  const lptr<cplx<T>> twf = as_lds(reinterpret_cast<cplx<T>*>(reinterpret_cast<T*>(smem_raw) + L::TILE));
-  const lptr<cplx<T>> twa = twf + M;
-  const int tid = threadIdx.x;
+  FastLds<T, M> r;
+  r.tile = as_lds(reinterpret_cast<T*>(smem));
+  r.twf = as_lds(reinterpret_cast<cplx<T>*>(reinterpret_cast<T*>(smem) + L::TILE));
+  r.twa = r.twf + M;
+  return r;
+}
+
+// Twiddle tables of transform `kind` (those of the DCT-IV types, or those
+// of the others) into LDS; ends with a barrier.  The values depend only on
+// n = 2M and the type class.
+template <typename T, int M>
+__device__ __forceinline__ void fast_twiddles(const FastLds<T, M>& S, const R2RFastArgs<T>& A,
+                                              int tid) {
+  using L = FastLayout<T, M>;
+  constexpr int NT = L::NT;
+  for (int i = tid; i < M; i += NT) stc(S.twf, i, ldg(A.tw_fft, i));
+  if (A.kind >= K_ND) {
+    for (int i = tid; i < M; i += NT) {
+      stc(S.twa, i, ldg(A.tw_pre, i));
+      stc(S.twa, M + i, ldg(A.tw_post, i));
+    }
+  } else {
+    for (int i = tid; i < L::SPLIT; i += NT) stc(S.twa, i, ldg(A.tw_split, i));
+    for (int i = tid; i <= M; i += NT) stc(S.twa, L::SPLIT + i, ldg(A.tw_quarter, i));
+  }
+  __syncthreads();
+}
+
+// One tile of lines of the launch described by A, with the twiddles of its
+// type class already in LDS; ends with a barrier.
+template <typename T, int M>
+__device__ __forceinline__ void fast_tile(const FastLds<T, M>& S, const R2RFastArgs<T>& A,
+                                          int tile, int tid) {
+  using L = FastLayout<T, M>;
+  constexpr int NL = L::NL;
   const int l = tid % NL;
   const int q = tid / NL;
   const LineGeom& g = A.g;
   const int kind = A.kind, inverse = A.inverse;
   const bool ivk = kind >= K_ND;
+  const lptr<const cplx<T>> tw_fft = S.twf;
+  const lptr<const cplx<T>> tw_a = S.twa;                           // pre or split
+  const lptr<const cplx<T>> tw_b = S.twa + (ivk ? M : L::SPLIT);    // post or quarter
 
-  // twiddle tables -> LDS (once per block)
-  for (int i = tid; i < M; i += NT) stc(twf, i, ldg(A.tw_fft, i));
-  if (ivk) {
-    for (int i = tid; i < M; i += NT) {
-      stc(twa, i, ldg(A.tw_pre, i));
-      stc(twa, M + i, ldg(A.tw_post, i));
-    }
+  const TileOrigin o = tile_origin(g, tile);
+  long long base;
+  int lines = 0;
+  if (g.layout == 0) {
+    base = l < (1 << g.lognl) ? line_base(g, o, l) : -1;
   } else {
-    for (int i = tid; i < L::SPLIT; i += NT) stc(twa, i, ldg(A.tw_split, i));
-    for (int i = tid; i <= M; i += NT) stc(twa, L::SPLIT + i, ldg(A.tw_quarter, i));
+    base = (long long)o.L0 * L::N;
+    lines = g.nlines - o.L0;
   }
-  const lptr<const cplx<T>> tw_fft = twf;
-  const lptr<const cplx<T>> tw_a = twa;           // pre   or split
-  const lptr<const cplx<T>> tw_b = twa + (ivk ? M : L::SPLIT);  // post or quarter
+  fast_load<T, M>(S.tile, as_global((const T*)A.data), base, g.sp, g.layout, lines, kind, inverse,
+                  l, q, tid);
   __syncthreads();
 
-  const TileRange tr = xcd_tiles(g.ntiles);
-  for (int tile = tr.first; tile < tr.end; tile += tr.step) {
-    const TileOrigin o = tile_origin(g, tile);
-    long long base;
-    int lines = 0;
-    if (g.layout == 0) {
-      base = l < (1 << g.lognl) ? line_base(g, o, l) : -1;
-    } else {
-      base = (long long)o.L0 * L::N;
-      lines = g.nlines - o.L0;
-    }
-    fast_load<T, M>(lds, as_global((const T*)A.data), base, g.sp, g.layout, lines, kind, inverse,
-                    l, q, tid);
-    __syncthreads();
+  if (ivk) fast_iv_pre<T, M>(S.tile, tw_a, l, q);
+  else if (inverse) fast_combine<T, M>(S.tile, tw_a, tw_b, kind, l, q);
 
-    if (ivk) fast_iv_pre<T, M>(lds, tw_a, l, q);
-    else if (inverse) fast_combine<T, M>(lds, tw_a, tw_b, kind, l, q);
+  if (!(inverse && kind <= K_DD)) fast_passes<T, M, true, 0>(S.tile, tw_fft, l, q);
+  else fast_passes<T, M, false, 0>(S.tile, tw_fft, l, q);
 
-    if (!(inverse && kind <= K_DD)) fast_passes<T, M, true, 0>(lds, tw_fft, l, q);
-    else fast_passes<T, M, false, 0>(lds, tw_fft, l, q);
+  if (ivk) fast_iv_post<T, M>(S.tile, tw_b, l, q);
+  else if (!inverse) fast_split<T, M>(S.tile, tw_a, tw_b, kind, l, q);
 
-    if (ivk) fast_iv_post<T, M>(lds, tw_b, l, q);
-    else if (!inverse) fast_split<T, M>(lds, tw_a, tw_b, kind, l, q);
+  fast_store<T, M>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind, inverse,
+                   A.scale, l, q, tid);
+  __syncthreads();
+}
 
-    fast_store<T, M>(lds, as_global(A.data), base, g.sp, g.layout, lines, kind, inverse,
-                     A.scale, l, q, tid);
-    __syncthreads();
-  }
+template <typename T, int M>
+__global__ __launch_bounds__(fast_nt<M>()) __attribute__((amdgpu_waves_per_eu(4)))
+void r2r_fast_kernel(R2RFastArgs<T> A) {
+  if (A.skip && A.skip[0] != 0.0) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const FastLds<T, M> S = fast_lds<T, M>(smem_raw);
+  const int tid = threadIdx.x;
+  fast_twiddles<T, M>(S, A, tid);
+  const TileRange tr = xcd_tiles(A.g.ntiles);
+  for (int tile = tr.first; tile < tr.end; tile += tr.step) fast_tile<T, M>(S, A, tile, tid);
 }
 
 }  // namespace poisson_dev

@@ -299,20 +299,13 @@ __device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const T> coef, i
   for (int i = 0; i < RPC; ++i) col[i * L::NLP] = x[i];
 }
 
+// Coefficients of the elimination axis into LDS, [row in chunk][chunk];
+// ends with a barrier.
 template <typename T, int RPC, int P>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
-void tri_fast_kernel(TriFastArgs<T> A) {
+__device__ __forceinline__ void tri_fast_coefs(lptr<T> coef, const TriFastArgs<T>& A, int tid) {
   using L = TriFastLayout<T, RPC, P>;
-  constexpr int N = L::N, NL = L::NL, NT = L::NT;
-  if (A.skip && A.skip[0] != 0.0) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const lptr<T> lds = as_lds(reinterpret_cast<T*>(smem_raw));
-  const lptr<T> coef = lds + L::TILE;
-  const int tid = threadIdx.x;
-  const LineGeom& g = A.g;
-
-  // coefficients -> LDS, [row in chunk][chunk]
-  for (int k = tid; k < N; k += NT) {
+  constexpr int N = L::N;
+  for (int k = tid; k < N; k += L::NT) {
     const int ch = k / RPC, i = k - ch * RPC;
     const int s = i * P + ch;
     coef[s] = as_global(A.a)[k];
@@ -321,39 +314,60 @@ void tri_fast_kernel(TriFastArgs<T> A) {
     coef[3 * N + s] = as_global(A.w)[k];
   }
   __syncthreads();
+}
 
+// One tile of lines of the launch described by A, with the coefficients in
+// LDS; ends with a barrier.
+template <typename T, int RPC, int P>
+__device__ __forceinline__ void tri_fast_tile(lptr<T> lds, lptr<const T> coef,
+                                              const TriFastArgs<T>& A, int tile, int tid) {
+  using L = TriFastLayout<T, RPC, P>;
+  constexpr int N = L::N, NL = L::NL;
+  const LineGeom& g = A.g;
   const int c = tid % P;        // chunk of this thread
   const int l = tid / P;        // line of this thread within the tile
   const int nlt = 1 << g.lognl; // lines in a full tile of this launch (<= NL)
   const lptr<T> col = lds + c * L::CP + l;
 
-  const TileRange tr = xcd_tiles(g.ntiles);
-  for (int tile = tr.first; tile < tr.end; tile += tr.step) {
-    const TileOrigin o = tile_origin(g, tile);
-    long long base;
-    int lines = 0;
-    if (g.layout == 0) {
-      const int ll = tid % NL;
-      base = ll < nlt ? line_base(g, o, ll) : -1;
-    } else {
-      base = (long long)o.L0 * N;
-      lines = min(g.nlines - o.L0, nlt);
-    }
-    tri_fast_load<T, RPC, P>(lds, as_global((const T*)A.data), base, g.sp, g.layout, lines, tid);
-    __syncthreads();
-
-    const bool valid = l < nlt && line_base(g, o, l) >= 0;
-    int u = 0, v = 0;
-    if (valid) line_coords(g, o, l, A.nu, u, v);
-    const T mu = valid ? A.lamu[u] + A.lamv[v] : (T)-1;
-    const bool sing = A.singular && valid && u == 0 && v == 0;
-    const int wave_sing = __any(sing) ? 1 : 0;
-    tri_fast_line<T, RPC, P>(col, coef, c, mu, sing ? 1 : 0, wave_sing, A.periodic);
-    __syncthreads();
-
-    tri_fast_store<T, RPC, P>(lds, as_global(A.data), base, g.sp, g.layout, lines, tid);
-    __syncthreads();
+  const TileOrigin o = tile_origin(g, tile);
+  long long base;
+  int lines = 0;
+  if (g.layout == 0) {
+    const int ll = tid % NL;
+    base = ll < nlt ? line_base(g, o, ll) : -1;
+  } else {
+    base = (long long)o.L0 * N;
+    lines = min(g.nlines - o.L0, nlt);
   }
+  tri_fast_load<T, RPC, P>(lds, as_global((const T*)A.data), base, g.sp, g.layout, lines, tid);
+  __syncthreads();
+
+  const bool valid = l < nlt && line_base(g, o, l) >= 0;
+  int u = 0, v = 0;
+  if (valid) line_coords(g, o, l, A.nu, u, v);
+  const T mu = valid ? A.lamu[u] + A.lamv[v] : (T)-1;
+  const bool sing = A.singular && valid && u == 0 && v == 0;
+  const int wave_sing = __any(sing) ? 1 : 0;
+  tri_fast_line<T, RPC, P>(col, coef, c, mu, sing ? 1 : 0, wave_sing, A.periodic);
+  __syncthreads();
+
+  tri_fast_store<T, RPC, P>(lds, as_global(A.data), base, g.sp, g.layout, lines, tid);
+  __syncthreads();
+}
+
+template <typename T, int RPC, int P>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+void tri_fast_kernel(TriFastArgs<T> A) {
+  using L = TriFastLayout<T, RPC, P>;
+  if (A.skip && A.skip[0] != 0.0) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const lptr<T> lds = as_lds(reinterpret_cast<T*>(smem_raw));
+  const lptr<T> coef = lds + L::TILE;
+  const int tid = threadIdx.x;
+  tri_fast_coefs<T, RPC, P>(coef, A, tid);
+  const TileRange tr = xcd_tiles(A.g.ntiles);
+  for (int tile = tr.first; tile < tr.end; tile += tr.step)
+    tri_fast_tile<T, RPC, P>(lds, coef, A, tile, tid);
 }
 
 }  // namespace poisson_dev

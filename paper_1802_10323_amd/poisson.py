@@ -38,6 +38,10 @@ SIGNATURES = {
     "plan_roles": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int)]),
     "transform_stage": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, _VP]),
     "tridiag_stage": (ctypes.c_int, [_VP, _VP, _VP]),
+    "batch_create": (_VP, [ctypes.POINTER(_VP), ctypes.c_int]),
+    "batch_bind": (ctypes.c_int, [_VP, ctypes.POINTER(_VP)]),
+    "batch_launch": (ctypes.c_int, [_VP, _VP, ctypes.c_int]),
+    "batch_destroy": (None, [_VP]),
 }
 
 _lib = None
@@ -188,3 +192,44 @@ def batch_solve(plans, fields, stream=None):
     fp = (ctypes.c_void_p * n)(*[_field_ptr(f).value for f in fields])
     _check(lib().batch_solve(hp, fp, n, _stream_handle(stream)))
     return fields
+
+
+class Batch:
+    """Many independent FP64 problems solved by one persistent launch per
+    stage (``batch_create`` / ``batch_bind`` / ``batch_launch``).  The plans
+    must outlive the batch; ``bind`` sets the fields (device, float64,
+    contiguous; solved in place) and must not be called while a launch of
+    this batch is in flight."""
+
+    def __init__(self, plans):
+        L = lib()
+        self.plans = list(plans)
+        hp = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = L.batch_create(hp, len(self.plans))
+        if not h:
+            _check(L.last_error() or EINVAL)
+        self._h = ctypes.c_void_p(h)
+
+    def bind(self, fields):
+        if len(fields) != len(self.plans):
+            raise ValueError("one field per plan")
+        for p, f in zip(self.plans, fields):
+            if f.numel() != int(np.prod(p.shape)):
+                raise ValueError(f"field of {f.numel()} values for a {p.shape} plan")
+        fp = (ctypes.c_void_p * len(fields))(*[_field_ptr(f).value for f in fields])
+        _check(lib().batch_bind(self._h, fp))
+
+    def launch(self, stream=None, graph=False):
+        """Enqueue the five stage launches (or replay them as a HIP graph)."""
+        _check(lib().batch_launch(self._h, _stream_handle(stream), int(bool(graph))))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -347,3 +347,78 @@ def test_batch_equals_single_solves():
         assert rel_l2(got, oracle_solve(p)) <= TOL64
     for pl in plans:
         pl.close()
+
+
+def _batch_case(seed, count):
+    probs = inputs.batch(seed, count=count)
+    return probs
+
+
+def test_persistent_batch_equals_single_solves():
+    """One persistent launch per stage over uneven instances (sizes from
+    {64, ..., 256} per axis, random boundary pairs, stretched and uniform z):
+    bitwise equal to the single solves, and within 1e-12 of the oracle."""
+    from paper_1802_10323_amd import Batch, Plan
+    probs = _batch_case(1, 10)
+    say("batch shapes", [p.shape for p in probs])
+    plans = [Plan.from_problem(p) for p in probs]
+    fields = [to_dev(p.rhs) for p in probs]
+    batch = Batch(plans)
+    batch.bind(fields)
+    batch.launch()
+    got = [to_host(f) for f in fields]
+    for p, g in zip(probs, got):
+        single, _ = gpu_solve(p)
+        assert np.array_equal(g, single), p
+        assert rel_l2(g, oracle_solve(p)) <= TOL64, p
+    batch.close()
+    for pl in plans:
+        pl.close()
+
+
+def test_persistent_batch_graph_replays():
+    """The HIP-graph form: several replays with eager work (refills, host
+    synchronisations) between them, then a re-bind to other fields without
+    re-capture; every replay equals the eager batched launch bit for bit."""
+    import torch
+    from paper_1802_10323_amd import Batch, Plan
+    probs = _batch_case(2, 6)
+    plans = [Plan.from_problem(p) for p in probs]
+    src = [to_dev(p.rhs) for p in probs]
+    eager = [s.clone() for s in src]
+    batch = Batch(plans)
+    batch.bind(eager)
+    batch.launch(graph=False)
+    ref = [to_host(f) for f in eager]
+    work = [torch.empty_like(s) for s in src]
+    batch.bind(work)
+    for rep in range(3):
+        for w, s in zip(work, src):
+            w.copy_(s)
+        torch.cuda.synchronize()
+        batch.launch(graph=True)
+        for w, r in zip(work, ref):
+            assert np.array_equal(to_host(w), r), rep
+        _ = torch.ones(1000, device="cuda").sum().item()     # eager work between replays
+    other = [s.clone() for s in src]
+    batch.bind(other)
+    batch.launch(graph=True)
+    for o, r in zip(other, ref):
+        assert np.array_equal(to_host(o), r)
+    batch.close()
+    for pl in plans:
+        pl.close()
+
+
+def test_batch_rejects_unspecialised_lengths_and_batch_solve_falls_back():
+    from paper_1802_10323_amd import Batch, Plan, PoissonError, batch_solve
+    probs = inputs.batch(3, count=4, sizes=(16, 24, 30, 40))
+    plans = [Plan.from_problem(p) for p in probs]
+    with pytest.raises(PoissonError):
+        Batch(plans)
+    fields = [to_dev(p.rhs) for p in probs]
+    batch_solve(plans, fields)
+    for p, f in zip(probs, fields):
+        assert rel_l2(to_host(f), oracle_solve(p)) <= TOL64
+    for pl in plans:
+        pl.close()
