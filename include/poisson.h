@@ -163,6 +163,56 @@ int batch_launch(poisson_batch* batch, hipStream_t stream, int use_graph);
  * batch is still running. */
 void batch_destroy(poisson_batch* batch);
 
+/* ---- continuous-batching server (many independent solves, Sec. 2.1 each) ----
+ *
+ * A server owns `slots` HIP streams and a worker thread.  Requests are queued
+ * in arrival order; the request at the head is admitted as soon as a slot is
+ * free and the HBM it holds while running (8 B per point for the field, plus
+ * 12 B per point of refinement workspace for POISSON_FP32_REFINED) fits the
+ * budget next to the requests already running, and its solve is enqueued on
+ * that slot's stream at once, so it overlaps on the device with the solves in
+ * flight.  Plans are cached by problem and reused (FP64 plans are shared by
+ * concurrent requests; a refined plan serves one request at a time).  Each
+ * result equals solve() of the same request on its own. */
+typedef struct poisson_server poisson_server;
+
+typedef struct poisson_request_info {
+  int status;               /* POISSON_OK, POISSON_ENOTCONVERGED or an error code */
+  int iters;                /* FP32 solves performed (1 for FP64) */
+  int plan_cached;          /* 1 if the request reused a cached plan */
+  double last_update_rel;   /* last relative refinement update (0 for FP64) */
+  double submit_s;          /* host steady-clock times (seconds): submission, */
+  double start_s;           /*   admission (launch enqueued), */
+  double done_s;            /*   completion observed */
+  long long points;         /* nx * ny * nz */
+} poisson_request_info;
+
+/* slots: streams (1..64); hbm_budget: bytes (0 = 80 % of the device's free
+ * memory now); max_plans: plans kept when idle (least recently used evicted).
+ * Uses the current device.  NULL on error. */
+poisson_server* server_create(int slots, size_t hbm_budget, int max_plans);
+
+/* Queue one solve (arguments as plan_create, plus precision mode, tolerance and
+ * sweep limit as plan_set_precision; field: DEVICE pointer, nx*ny*nz doubles,
+ * solved in place, owned by the caller and kept alive until server_wait
+ * returns for this request).  dz is copied.  Returns a request id >= 0, or a
+ * negative error code (POISSON_EUNSUPPORTED if the request alone exceeds the
+ * budget). */
+long long server_submit(poisson_server* server, int nx, int ny, int nz, double dx, double dy,
+                        const double* dz, int bc_x, int bc_y, int bc_z, int precision,
+                        double tol, int max_iters, double* field);
+
+/* Block until request `id` has completed; fills *info (may be NULL) and
+ * forgets the request.  Returns its status. */
+int server_wait(poisson_server* server, long long id, poisson_request_info* info);
+
+/* Plan-cache counters and the admission budget in bytes (any pointer may be NULL). */
+int server_stats(poisson_server* server, long long* plan_hits, long long* plan_misses,
+                 int* plans_resident, size_t* budget);
+
+/* Finish every queued request, stop the worker, free the cached plans. */
+void server_destroy(poisson_server* server);
+
 /* ---- stage entry points (the steps of Sec. 2.1, for stage-level checks) ---- */
 
 /* Axis roles chosen by the plan: roles[0] = t1, roles[1] = t2 (the transformed

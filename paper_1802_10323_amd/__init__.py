@@ -1,5 +1,5 @@
 """MI355X (gfx950) direct solver for the staggered second-order Poisson
 equation by eigenfunction expansion: hand-written HIP kernels behind a C ABI
 (``include/poisson.h``), with a thin Python binding (``poisson``)."""
-from .poisson import (BC, FP32_REFINED, FP64, Batch, Plan, PoissonError,  # noqa: F401
+from .poisson import (BC, FP32_REFINED, FP64, Batch, Plan, PoissonError, Server,  # noqa: F401
                       batch_solve, lib)

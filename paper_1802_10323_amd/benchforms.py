@@ -119,10 +119,102 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
             "bitwise_equal_to_single": bool(same)}
 
 
+def serve(log, count=400, warmup=50, seed=0, slots=8, load=0.8, sample=12):
+    """Served stream: per request, per-axis n log-uniform in [32, 512]
+    (snapped to even 2^a 3^b 5^c), random boundary pairs, z stretched with
+    probability 1/2 when walled, FP64 or FP32 + refinement (tol 1e-10) with
+    probability 1/2.  Fields are filled on the device from a seeded
+    generator.  Capacity = requests/s of a closed-loop run (all requests
+    queued at once); then Poisson arrivals at `load` x capacity, latency =
+    completion - submission per request."""
+    import torch
+    from . import FP32_REFINED, FP64, Plan, Server, inputs
+    specs = [inputs.served_request(seed, i, with_rhs=False) for i in range(warmup + count)]
+    gen = torch.Generator(device="cuda")
+    fields = [torch.empty(sp.points, dtype=torch.float64, device="cuda") for sp in specs]
+
+    def refill():
+        gen.manual_seed(seed)
+        for f in fields:
+            f.uniform_(-1.0, 1.0, generator=gen)
+        torch.cuda.synchronize()
+
+    srv = Server(slots=slots)
+
+    def submit(i):
+        sp = specs[i]
+        return srv.submit(sp, fields[i], FP32_REFINED if sp.mixed else FP64, 1e-10, 6)
+
+    refill()
+    for rid in [submit(i) for i in range(warmup)]:
+        srv.wait(rid)
+    timed = list(range(warmup, warmup + count))
+    points = sum(specs[i].points for i in timed)
+
+    # closed loop: everything queued at once
+    refill()
+    t0 = time.perf_counter()
+    infos = [srv.wait(r) for r in [submit(i) for i in timed]]
+    closed_s = time.perf_counter() - t0
+    capacity = count / closed_s
+    bad = sum(1 for x in infos if x["status"] != 0)
+
+    # open loop: Poisson arrivals at load x capacity
+    refill()
+    rng = np.random.default_rng(seed + 1)
+    arrivals = np.cumsum(rng.exponential(1.0 / (load * capacity), count))
+    keep = set(timed[:: max(1, count // sample)])
+    saved = {i: fields[i].clone() for i in keep}
+    torch.cuda.synchronize()
+    ids = []
+    t0 = time.perf_counter()
+    for k, i in enumerate(timed):
+        while time.perf_counter() - t0 < arrivals[k]:
+            pass
+        ids.append(submit(i))
+    infos = [srv.wait(r) for r in ids]
+    lat = np.array([x["done_s"] - x["submit_s"] for x in infos]) * 1e3
+    queue = np.array([x["start_s"] - x["submit_s"] for x in infos]) * 1e3
+    span = max(x["done_s"] for x in infos) - min(x["submit_s"] for x in infos)
+    bad += sum(1 for x in infos if x["status"] != 0)
+    stats = srv.stats()
+    srv.close()
+
+    # the same requests alone (fresh plan, default stream)
+    same = True
+    for i in sorted(keep):
+        sp = specs[i]
+        plan = Plan.from_problem(sp)
+        if sp.mixed:
+            plan.set_precision(FP32_REFINED, 1e-10, 6)
+        plan.solve(saved[i])
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(saved[i], fields[i]))
+        plan.close()
+    out = {"workload": "served stream, per-axis n log-uniform [32, 512], random BC pairs, "
+                       "FP64 or FP32+IR (1e-10) with p = 1/2",
+           "requests": count, "warmup": warmup, "slots": slots, "points": points,
+           "closed_loop_req_per_s": capacity,
+           "closed_loop_points_per_s": points / closed_s,
+           "arrival_rate_req_per_s": load * capacity,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "mean_queue_ms": float(queue.mean()),
+           "open_loop_points_per_s": points / span,
+           "failed": bad, "plan_cache": stats,
+           "sampled_equal_to_solo": same, "sampled": len(keep)}
+    log(f"[forms] serve: capacity {capacity:.1f} req/s ({points / closed_s:.3e} points/s closed "
+        f"loop); at {load:.0%}: p50 {out['p50_ms']:.3f} ms, p99 {out['p99_ms']:.3f} ms, "
+        f"{out['open_loop_points_per_s']:.3e} points/s; {len(keep)} sampled results equal "
+        f"to solo solves: {same}")
+    return out
+
+
 def run(wanted, log):
     out = {}
     if "mixed" in wanted:
         out["mixed"] = mixed(log)
     if "batch" in wanted:
         out["batch"] = batch(log)
+    if "serve" in wanted:
+        out["serve"] = serve(log)
     return out

@@ -1065,3 +1065,7 @@ extern "C" void batch_destroy(poisson_batch* b) {
   if (b->djobs) (void)hipFree(b->djobs);
   delete b;
 }
+
+// ------------------------------------------------------------------ server
+
+#include "server.h"

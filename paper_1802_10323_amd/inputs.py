@@ -67,12 +67,12 @@ class Problem:
         self.hy = np.asarray(hy, dtype=np.float64)
         self.hz = np.asarray(hz, dtype=np.float64)
         self.bcx, self.bcy, self.bcz = bcx, bcy, bcz
-        self.rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        self.rhs = None if rhs is None else np.ascontiguousarray(rhs, dtype=np.float64)
         self.name = name
 
     @property
     def shape(self):
-        return self.rhs.shape          # (nz, ny, nx)
+        return (self.nz, self.ny, self.nx)
 
     @property
     def nx(self):
@@ -88,7 +88,7 @@ class Problem:
 
     @property
     def points(self):
-        return self.rhs.size
+        return self.nx * self.ny * self.nz
 
     @property
     def bcs(self):
@@ -112,14 +112,18 @@ def random_field(rng, nx, ny, nz):
 
 
 def make_uniform(nx, ny, nz, bcs, seed, lengths=(1.0, 1.0, 1.0), stretch_z=None,
-                 name=""):
+                 name="", with_rhs=True):
     """f ~ U[-1, 1] on a box; z optionally tanh-stretched with factor
-    ``stretch_z``; weighted mean removed when the problem has a null space."""
+    ``stretch_z``; weighted mean removed when the problem has a null space.
+    ``with_rhs=False`` builds the grid only (rhs None), for callers that
+    fill the field on the device themselves."""
     rng = np.random.default_rng(seed)
     hx = uniform_widths(nx, lengths[0])
     hy = uniform_widths(ny, lengths[1])
     hz = (tanh_widths(nz, lengths[2], stretch_z) if stretch_z
           else uniform_widths(nz, lengths[2]))
+    if not with_rhs:
+        return Problem(hx, hy, hz, *bcs, None, name=name)
     f = random_field(rng, nx, ny, nz)
     if has_null_space(*bcs):
         f = remove_weighted_mean(f, hx, hy, hz)
@@ -205,7 +209,7 @@ def snap_size(x, sizes):
     return min(sizes, key=lambda s: (abs(s - x), s))
 
 
-def served_request(seed, i, lo=32, hi=512, beta=1.8, max_points=None):
+def served_request(seed, i, lo=32, hi=512, beta=1.8, max_points=None, with_rhs=True):
     """One request of the served stream: per-axis size log-uniform in
     [lo, hi] snapped to an even 2^a 3^b 5^c, random boundary pairs, z
     stretched with probability 1/2 when not periodic, precision FP64 or
@@ -221,6 +225,6 @@ def served_request(seed, i, lo=32, hi=512, beta=1.8, max_points=None):
     stretch = beta if (bcs[2] != "P" and rng.uniform() < 0.5) else None
     mixed = bool(rng.uniform() < 0.5)
     p = make_uniform(dims[0], dims[1], dims[2], bcs, seed * 1000 + i + 500000,
-                     stretch_z=stretch, name=f"req{i}")
+                     stretch_z=stretch, name=f"req{i}", with_rhs=with_rhs)
     p.mixed = mixed
     return p

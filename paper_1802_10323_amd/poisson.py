@@ -42,6 +42,17 @@ SIGNATURES = {
     "batch_bind": (ctypes.c_int, [_VP, ctypes.POINTER(_VP)]),
     "batch_launch": (ctypes.c_int, [_VP, _VP, ctypes.c_int]),
     "batch_destroy": (None, [_VP]),
+    "server_create": (_VP, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int]),
+    "server_submit": (ctypes.c_longlong, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_double,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_int, _VP]),
+    "server_wait": (ctypes.c_int, [_VP, ctypes.c_longlong, _VP]),
+    "server_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_longlong),
+                                    ctypes.POINTER(ctypes.c_longlong),
+                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t)]),
+    "server_destroy": (None, [_VP]),
 }
 
 _lib = None
@@ -227,6 +238,77 @@ class Batch:
         if getattr(self, "_h", None) is not None:
             lib().batch_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class RequestInfo(ctypes.Structure):
+    """poisson_request_info of include/poisson.h."""
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("plan_cached", ctypes.c_int),
+                ("last_update_rel", ctypes.c_double), ("submit_s", ctypes.c_double),
+                ("start_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("points", ctypes.c_longlong)]
+
+
+class Server:
+    """Continuous-batching solve server (``server_create`` ...): requests are
+    admitted in arrival order as stream slots and HBM budget free up, and run
+    concurrently on the device.  Fields are solved in place and must stay
+    alive until ``wait`` returns for them (this object keeps a reference)."""
+
+    def __init__(self, slots=8, hbm_budget=0, max_plans=64):
+        L = lib()
+        h = L.server_create(int(slots), int(hbm_budget), int(max_plans))
+        if not h:
+            _check(L.last_error() or EINVAL)
+        self._h = ctypes.c_void_p(h)
+        self._fields = {}
+
+    def submit(self, problem, field, precision=FP64, tol=1e-10, max_iters=4):
+        """Queue the solve of ``problem`` (an inputs.Problem or anything with
+        nx, ny, nz, dx, dy, hz, bcs) on ``field`` (device float64, contiguous);
+        returns the request id."""
+        dz = np.ascontiguousarray(np.asarray(problem.hz, dtype=np.float64))
+        if field.numel() != problem.nx * problem.ny * problem.nz:
+            raise ValueError("field size does not match the problem")
+        codes = [BC[b] if isinstance(b, str) else int(b) for b in problem.bcs]
+        rid = lib().server_submit(self._h, int(problem.nx), int(problem.ny), int(problem.nz),
+                                  float(problem.dx), float(problem.dy),
+                                  dz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), *codes,
+                                  int(precision), float(tol), int(max_iters),
+                                  _field_ptr(field))
+        if rid < 0:
+            _check(int(rid))
+        self._fields[rid] = field
+        return rid
+
+    def wait(self, rid):
+        """Block until request ``rid`` is done; returns its RequestInfo as a
+        dict (times in host steady-clock seconds)."""
+        info = RequestInfo()
+        rc = lib().server_wait(self._h, int(rid), ctypes.byref(info))
+        self._fields.pop(rid, None)
+        if rc not in (OK, ENOTCONVERGED):
+            _check(rc)
+        return {k: getattr(info, k) for k, _ in RequestInfo._fields_}
+
+    def stats(self):
+        hits, misses = ctypes.c_longlong(0), ctypes.c_longlong(0)
+        resident, budget = ctypes.c_int(0), ctypes.c_size_t(0)
+        _check(lib().server_stats(self._h, ctypes.byref(hits), ctypes.byref(misses),
+                                  ctypes.byref(resident), ctypes.byref(budget)))
+        return {"plan_hits": hits.value, "plan_misses": misses.value,
+                "plans_resident": resident.value, "hbm_budget": budget.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().server_destroy(self._h)
+            self._h = None
+            self._fields.clear()
 
     def __del__(self):
         try:

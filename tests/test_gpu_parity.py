@@ -422,3 +422,78 @@ def test_batch_rejects_unspecialised_lengths_and_batch_solve_falls_back():
         assert rel_l2(to_host(f), oracle_solve(p)) <= TOL64
     for pl in plans:
         pl.close()
+
+
+# --------------------------------------------------------------- served
+
+def _solo(prob, field):
+    """The request solved on its own, with a fresh plan, on the default stream."""
+    from paper_1802_10323_amd import FP32_REFINED, Plan
+    plan = Plan.from_problem(prob)
+    if getattr(prob, "mixed", False):
+        plan.set_precision(FP32_REFINED, 1e-10, 6)
+    plan.solve(field)
+    out = to_host(field)
+    st = plan.status()
+    plan.close()
+    return out, st
+
+
+def test_server_results_equal_solo_solves():
+    """Requests of mixed sizes, boundary pairs and precisions submitted at
+    once run concurrently on the server's streams; each result equals the
+    same request solved alone, bit for bit (FP64 and FP32 + refinement), and
+    the small ones match the oracle within their tolerance."""
+    from paper_1802_10323_amd import FP32_REFINED, FP64, Server
+    probs = [inputs.served_request(5, i, lo=32, hi=160) for i in range(14)]
+    say("served", [(p.shape, p.bcs, p.mixed) for p in probs])
+    inputs_dev = [to_dev(p.rhs) for p in probs]
+    fields = [f.clone() for f in inputs_dev]
+    srv = Server(slots=4)
+    ids = [srv.submit(p, f, FP32_REFINED if p.mixed else FP64, 1e-10, 6)
+           for p, f in zip(probs, fields)]
+    infos = [srv.wait(i) for i in ids]
+    for p, f, info, src in zip(probs, fields, infos, inputs_dev):
+        assert info["status"] == 0, (p, info)
+        got = to_host(f)
+        solo, (iters, _, conv) = _solo(p, src.clone())
+        assert np.array_equal(got, solo), p
+        assert info["iters"] == (iters if p.mixed else 1)
+        if p.points <= 200_000:
+            assert rel_l2(got, oracle_solve(p)) <= (1e-10 if p.mixed else TOL64), p
+    # the same problem again: its plan is reused from the cache
+    again = inputs_dev[0].clone()
+    rid = srv.submit(probs[0], again, FP32_REFINED if probs[0].mixed else FP64, 1e-10, 6)
+    info = srv.wait(rid)
+    assert info["plan_cached"] == 1
+    assert np.array_equal(to_host(again), to_host(fields[0]))
+    st = srv.stats()
+    assert st["plan_hits"] >= 1
+    srv.close()
+
+
+def test_server_admission_by_hbm_budget():
+    """With a budget that holds only the largest request, requests run one
+    at a time (never two in flight) and still give the solo results; a
+    request larger than the budget is refused."""
+    from paper_1802_10323_amd import FP64, PoissonError, Server
+    probs = [inputs.served_request(6, i, lo=32, hi=96) for i in range(6)]
+    need = max(8 * p.points + (12 * p.points if p.mixed else 0) for p in probs)
+    from paper_1802_10323_amd import FP32_REFINED
+    srv = Server(slots=4, hbm_budget=need)
+    src = [to_dev(p.rhs) for p in probs]
+    fields = [f.clone() for f in src]
+    ids = [srv.submit(p, f, FP32_REFINED if p.mixed else FP64, 1e-10, 6)
+           for p, f in zip(probs, fields)]
+    infos = [srv.wait(i) for i in ids]
+    spans = sorted((i["start_s"], i["done_s"]) for i in infos)
+    for (s0, d0), (s1, d1) in zip(spans, spans[1:]):
+        assert s1 >= d0 - 1e-4, "two requests in flight under a one-request budget"
+    for p, f, s in zip(probs, fields, src):
+        solo, _ = _solo(p, s.clone())
+        assert np.array_equal(to_host(f), solo)
+    big = inputs.make_uniform(64, 64, 64, ("P", "P", "DD"), seed=1)
+    if 8 * big.points > need:
+        with pytest.raises(PoissonError):
+            srv.submit(big, to_dev(big.rhs))
+    srv.close()
