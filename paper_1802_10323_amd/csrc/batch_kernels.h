@@ -49,6 +49,7 @@ __device__ __forceinline__ int batch_job_of(const J* __restrict__ jobs, int njob
 template <typename T, int M>
 __device__ __forceinline__ void batch_r2r_item(unsigned char* smem, const R2RFastArgs<T>& A,
                                                int tile, int& loaded, int tid) {
+  static_assert(fast_nt<M>() == 512, "the batched transform kernel runs 512-thread blocks");
   const FastLds<T, M> S = fast_lds<T, M>(smem);
   const int key = 2 * M + (A.kind >= K_ND ? 1 : 0);
   if (loaded != key) {
@@ -86,6 +87,7 @@ template <typename T, int RPC, int P>
 __device__ __noinline__ void batch_tri_item(unsigned char* smem, const TriFastArgs<T>& A,
                                                int job, int tile, int& loaded, int tid) {
   using L = TriFastLayout<T, RPC, P>;
+  static_assert(L::NT == 512, "the batched elimination kernel runs 512-thread blocks");
   const lptr<T> lds = as_lds(reinterpret_cast<T*>(smem));
   const lptr<T> coef = lds + L::TILE;
   if (loaded != job) {

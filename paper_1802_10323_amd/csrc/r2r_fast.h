@@ -66,14 +66,17 @@ POISSON_FAST_SHAPE(16, 4, 128)
 POISSON_FAST_SHAPE(32, 4, 128)
 POISSON_FAST_SHAPE(48, 8, 64)
 POISSON_FAST_SHAPE(64, 8, 64)
-POISSON_FAST_SHAPE(96, 8, 32)
+POISSON_FAST_SHAPE(96, 16, 32)
 POISSON_FAST_SHAPE(128, 16, 32)
-POISSON_FAST_SHAPE(192, 16, 16)
+POISSON_FAST_SHAPE(192, 32, 16)
 POISSON_FAST_SHAPE(256, 32, 16)
 #undef POISSON_FAST_SHAPE
 
+// Every shape has 512 threads: the batched kernel runs all lengths in
+// blocks of that size.
 template <int M>
 constexpr int fast_nt() {
+  static_assert(FastShape<M>::QT * FastShape<M>::NL == 512, "transform blocks have 512 threads");
   return FastShape<M>::QT * FastShape<M>::NL;
 }
 
