@@ -163,6 +163,34 @@ int batch_launch(poisson_batch* batch, hipStream_t stream, int use_graph);
  * batch is still running. */
 void batch_destroy(poisson_batch* batch);
 
+/* ---- autotuner: kernel variants per length ----
+ *
+ * Each specialised length has several compiled variants: four for the
+ * transforms (two tile shapes, lines per tile x threads per line, times two
+ * FFT radix orders, radix 8 first or radix 4 first) and two for the
+ * elimination (two chunkings, rows per chunk x chunks per line).  All give
+ * the same result up to rounding.  The variant used for a length is chosen
+ * per device, precision and layout (strided: the axis is y or z;
+ * contiguous: x) from a process-wide table; variant 0 where nothing was
+ * tuned.  Plans and batches read the table when they launch (batches when
+ * they are bound). */
+
+/* Time every variant of this plan's kernels (both transformed axes and the
+ * elimination, FP64 and FP32) on `scratch` (DEVICE, at least nx*ny*nz
+ * doubles; overwritten), `reps` launches each after one warm-up, and record
+ * the fastest in the table.  Synchronous (waits for `stream`).  report (HOST,
+ * may be NULL): 2 x (4 + 4 + 2) doubles, per precision (FP64 first) the
+ * average ms of variants 0-3 of t1, 0-3 of t2 (forward + backward pair) and
+ * 0-1 of the elimination, -1 where the length has no variants. */
+int plan_autotune(poisson_plan* plan, double* scratch, int reps, hipStream_t stream, double* report);
+
+/* Variant in the table for kernel family 0 (transform) or 1 (elimination),
+ * line length n, layout 0 (strided) or 1 (contiguous), fp64 1 or 0. */
+int tuned_variant(int family, int n, int layout, int fp64);
+
+/* Set that entry by hand (POISSON_EUNSUPPORTED if n has no variants). */
+int set_tuned_variant(int family, int n, int layout, int fp64, int variant);
+
 /* ---- continuous-batching server (many independent solves, Sec. 2.1 each) ----
  *
  * A server owns `slots` HIP streams and a worker thread.  Requests are queued

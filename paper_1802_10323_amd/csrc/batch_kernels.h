@@ -24,13 +24,14 @@ template <typename T>
 struct BatchR2RJob {
   R2RFastArgs<T> a;
   int M;        // complex FFT length (n = 2M)
+  int V;        // variant (tile shape, radix order)
   int first;    // items of the jobs before this one
 };
 
 template <typename T>
 struct BatchTriJob {
   TriFastArgs<T> a;
-  int shape;    // rows per chunk * 100 + chunks per line
+  int key;      // 2 * line length + variant (chunking)
   int first;
 };
 
@@ -46,17 +47,20 @@ __device__ __forceinline__ int batch_job_of(const J* __restrict__ jobs, int njob
   return lo;
 }
 
-template <typename T, int M>
-__device__ __forceinline__ void batch_r2r_item(unsigned char* smem, const R2RFastArgs<T>& A,
-                                               int tile, int& loaded, int tid) {
-  static_assert(fast_nt<M>() == 512, "the batched transform kernel runs 512-thread blocks");
-  const FastLds<T, M> S = fast_lds<T, M>(smem);
-  const int key = 2 * M + (A.kind >= K_ND ? 1 : 0);
+// One item of a transform job; not inlined, so that each of the many
+// configurations keeps its own register allocation.
+template <typename T, typename C>
+__device__ __noinline__ void batch_r2r_item(unsigned char* smem, const R2RFastArgs<T>& A,
+                                            int tile, int& loaded, int tid) {
+  const FastLds<T, C> S = fast_lds<T, C>(smem);
+  // twiddle values depend on the length and the type class, their LDS place
+  // on the tile size
+  const int key = (C::M * 1024 + C::NL) * 2 + (A.kind >= K_ND ? 1 : 0);
   if (loaded != key) {
-    fast_twiddles<T, M>(S, A, tid);
+    fast_twiddles<T, C>(S, A, tid);
     loaded = key;
   }
-  fast_tile<T, M>(S, A, tile, tid);
+  fast_tile<T, C>(S, A, tile, tid);
 }
 
 template <typename T>
@@ -69,16 +73,15 @@ void batch_r2r_kernel(const BatchR2RJob<T>* __restrict__ jobs, int njobs, int it
   for (int it = tr.first; it < tr.end; it += tr.step) {
     const BatchR2RJob<T>& J = jobs[batch_job_of(jobs, njobs, it)];
     const int tile = it - J.first;
-    switch (J.M) {
-      case 16: batch_r2r_item<T, 16>(smem_raw, J.a, tile, loaded, tid); break;
-      case 32: batch_r2r_item<T, 32>(smem_raw, J.a, tile, loaded, tid); break;
-      case 48: batch_r2r_item<T, 48>(smem_raw, J.a, tile, loaded, tid); break;
-      case 64: batch_r2r_item<T, 64>(smem_raw, J.a, tile, loaded, tid); break;
-      case 96: batch_r2r_item<T, 96>(smem_raw, J.a, tile, loaded, tid); break;
-      case 128: batch_r2r_item<T, 128>(smem_raw, J.a, tile, loaded, tid); break;
-      case 192: batch_r2r_item<T, 192>(smem_raw, J.a, tile, loaded, tid); break;
-      case 256: batch_r2r_item<T, 256>(smem_raw, J.a, tile, loaded, tid); break;
-      default: break;   // the host only builds jobs of the lengths above
+    switch (J.M * 4 + J.V) {
+#define POISSON_BV(M_, V_) \
+  case M_ * 4 + V_: batch_r2r_item<T, FastVar<M_, V_>>(smem_raw, J.a, tile, loaded, tid); break;
+#define POISSON_BM(M_) POISSON_BV(M_, 0) POISSON_BV(M_, 1) POISSON_BV(M_, 2) POISSON_BV(M_, 3)
+      POISSON_BM(16) POISSON_BM(32) POISSON_BM(48) POISSON_BM(64)
+      POISSON_BM(96) POISSON_BM(128) POISSON_BM(192) POISSON_BM(256)
+#undef POISSON_BM
+#undef POISSON_BV
+      default: break;   // the host only builds jobs of the configurations above
     }
   }
 }
@@ -108,15 +111,18 @@ void batch_tri_kernel(const BatchTriJob<T>* __restrict__ jobs, int njobs, int it
     const int j = batch_job_of(jobs, njobs, it);
     const BatchTriJob<T>& J = jobs[j];
     const int tile = it - J.first;
-    switch (J.shape) {
-      case 416: batch_tri_item<T, 4, 16>(smem_raw, J.a, j, tile, loaded, tid); break;
-      case 616: batch_tri_item<T, 6, 16>(smem_raw, J.a, j, tile, loaded, tid); break;
-      case 816: batch_tri_item<T, 8, 16>(smem_raw, J.a, j, tile, loaded, tid); break;
-      case 1216: batch_tri_item<T, 12, 16>(smem_raw, J.a, j, tile, loaded, tid); break;
-      case 832: batch_tri_item<T, 8, 32>(smem_raw, J.a, j, tile, loaded, tid); break;
-      case 664: batch_tri_item<T, 6, 64>(smem_raw, J.a, j, tile, loaded, tid); break;
-      case 864: batch_tri_item<T, 8, 64>(smem_raw, J.a, j, tile, loaded, tid); break;
-      default: break;   // the host only builds jobs of the shapes above
+    switch (J.key) {
+#define POISSON_BT(N_, V_, R_, P_) \
+  case N_ * 2 + V_: batch_tri_item<T, R_, P_>(smem_raw, J.a, j, tile, loaded, tid); break;
+      POISSON_BT(64, 0, 4, 16) POISSON_BT(64, 1, 2, 32)
+      POISSON_BT(96, 0, 6, 16) POISSON_BT(96, 1, 3, 32)
+      POISSON_BT(128, 0, 8, 16) POISSON_BT(128, 1, 4, 32)
+      POISSON_BT(192, 0, 12, 16) POISSON_BT(192, 1, 6, 32)
+      POISSON_BT(256, 0, 8, 32) POISSON_BT(256, 1, 16, 16)
+      POISSON_BT(384, 0, 6, 64) POISSON_BT(384, 1, 12, 32)
+      POISSON_BT(512, 0, 8, 64) POISSON_BT(512, 1, 16, 32)
+#undef POISSON_BT
+      default: break;   // the host only builds jobs of the configurations above
     }
   }
 }

@@ -12,7 +12,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "poisson.h"
@@ -161,6 +163,69 @@ struct poisson_plan {
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// ------------------------------------------------------------------ variants
+
+// Elimination chunking: rows per chunk x chunks per line.
+template <int RPC_, int P_>
+struct TriCfg {
+  static constexpr int RPC = RPC_, P = P_;
+};
+
+static constexpr int kFastVariants = 4;   // transform: tile shape x radix order
+static constexpr int kTriVariants = 2;    // elimination: two chunkings per length
+
+// Call f(FastVar<M, V>{}) for a specialised transform length; -1 otherwise.
+template <typename F>
+static long long with_fast_cfg(int M, int V, F&& f) {
+  switch (M * 4 + (V & 3)) {
+#define POISSON_FV(M_, V_) case M_ * 4 + V_: return f(FastVar<M_, V_>{});
+#define POISSON_FM(M_) POISSON_FV(M_, 0) POISSON_FV(M_, 1) POISSON_FV(M_, 2) POISSON_FV(M_, 3)
+    POISSON_FM(16) POISSON_FM(32) POISSON_FM(48) POISSON_FM(64)
+    POISSON_FM(96) POISSON_FM(128) POISSON_FM(192) POISSON_FM(256)
+#undef POISSON_FM
+#undef POISSON_FV
+    default: return -1;
+  }
+}
+
+// Call f(TriCfg<RPC, P>{}) for a specialised elimination length; -1 otherwise.
+template <typename F>
+static long long with_tri_cfg(int n, int V, F&& f) {
+  switch (n * 2 + (V & 1)) {
+#define POISSON_TV(N_, V_, R_, P_) case N_ * 2 + V_: return f(TriCfg<R_, P_>{});
+    POISSON_TV(64, 0, 4, 16) POISSON_TV(64, 1, 2, 32)
+    POISSON_TV(96, 0, 6, 16) POISSON_TV(96, 1, 3, 32)
+    POISSON_TV(128, 0, 8, 16) POISSON_TV(128, 1, 4, 32)
+    POISSON_TV(192, 0, 12, 16) POISSON_TV(192, 1, 6, 32)
+    POISSON_TV(256, 0, 8, 32) POISSON_TV(256, 1, 16, 16)
+    POISSON_TV(384, 0, 6, 64) POISSON_TV(384, 1, 12, 32)
+    POISSON_TV(512, 0, 8, 64) POISSON_TV(512, 1, 16, 32)
+#undef POISSON_TV
+    default: return -1;
+  }
+}
+
+// Variants chosen by the autotuner, per device, kernel family (0 transform,
+// 1 elimination), element size, length and layout (0 strided, 1
+// contiguous); variant 0 where nothing was tuned.
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int, int>, int> g_tune;
+
+static int tuned_choice(int family, int bytes, int n, int layout) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const auto it = g_tune.find(std::make_tuple(dev, family, bytes, n, layout));
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+static void set_tuned_choice(int family, int bytes, int n, int layout, int v) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[std::make_tuple(dev, family, bytes, n, layout)] = v;
+}
+
 static int lds_setup_once() {
   static std::once_flag once;
   static int status = 0;
@@ -169,18 +234,26 @@ static int lds_setup_once() {
 #define ALLOW(k) if (e == hipSuccess) e = hipFuncSetAttribute((const void*)(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_LIMIT)
     ALLOW((r2r_kernel<double, R2R_EMAX_D, R2R_NT>));
     ALLOW((r2r_kernel<float, R2R_EMAX_F, R2R_NT>));
-#define ALLOW_FAST(M) ALLOW((r2r_fast_kernel<double, M>)); ALLOW((r2r_fast_kernel<float, M>))
-    ALLOW_FAST(16); ALLOW_FAST(32); ALLOW_FAST(48); ALLOW_FAST(64);
-    ALLOW_FAST(96); ALLOW_FAST(128); ALLOW_FAST(192); ALLOW_FAST(256);
-#undef ALLOW_FAST
+    for (int M : {16, 32, 48, 64, 96, 128, 192, 256})
+      for (int V = 0; V < kFastVariants; ++V)
+        with_fast_cfg(M, V, [&](auto cfg) {
+          using C = decltype(cfg);
+          ALLOW((r2r_fast_kernel<double, C>));
+          ALLOW((r2r_fast_kernel<float, C>));
+          return 0LL;
+        });
     ALLOW((tridiag_kernel<double, 4, TRI_NT>));
     ALLOW((tridiag_kernel<double, 8, TRI_NT>));
     ALLOW((tridiag_kernel<float, 4, TRI_NT>));
     ALLOW((tridiag_kernel<float, 8, TRI_NT>));
-#define ALLOW_TRI(R, P) ALLOW((tri_fast_kernel<double, R, P>)); ALLOW((tri_fast_kernel<float, R, P>))
-    ALLOW_TRI(4, 16); ALLOW_TRI(6, 16); ALLOW_TRI(8, 16); ALLOW_TRI(12, 16);
-    ALLOW_TRI(8, 32); ALLOW_TRI(6, 64); ALLOW_TRI(8, 64);
-#undef ALLOW_TRI
+    for (int n : {64, 96, 128, 192, 256, 384, 512})
+      for (int V = 0; V < kTriVariants; ++V)
+        with_tri_cfg(n, V, [&](auto cfg) {
+          using C = decltype(cfg);
+          ALLOW((tri_fast_kernel<double, C::RPC, C::P>));
+          ALLOW((tri_fast_kernel<float, C::RPC, C::P>));
+          return 0LL;
+        });
     ALLOW((batch_r2r_kernel<double>));
     ALLOW((batch_tri_kernel<double>));
 #undef ALLOW
@@ -264,14 +337,14 @@ static int resident_grid(const void* fn, int block, size_t lds, long long ntiles
 // ------------------------------------------------------------------ launches
 
 // Launch arguments of the size-specialised transform kernel (r2r_fast.h)
-// for complex length M.
-template <typename T, int M>
+// of configuration C.
+template <typename T, typename C>
 static R2RFastArgs<T> fast_args(const poisson_plan* p, const AxisTables& A, int inverse, T* data,
                                 const double* skip) {
-  using L = FastLayout<T, M>;
+  constexpr int M = C::M;
   R2RFastArgs<T> a{};
   a.data = data;
-  a.g = make_geom(A.axis, p->dims, ilog2(L::NL));
+  a.g = make_geom(A.axis, p->dims, ilog2(C::NL));
   a.kind = A.kind;
   a.inverse = inverse;
   if (!inverse) a.scale = (T)1;
@@ -286,17 +359,25 @@ static R2RFastArgs<T> fast_args(const poisson_plan* p, const AxisTables& A, int 
   return a;
 }
 
-template <typename T, int M>
+template <typename T, typename C>
 static int launch_fast(const poisson_plan* p, const AxisTables& A, int inverse, T* data,
                        hipStream_t st, const double* skip) {
-  using L = FastLayout<T, M>;
-  const R2RFastArgs<T> a = fast_args<T, M>(p, A, inverse, data, skip);
-  const size_t lds = fast_lds_bytes<T, M>();
-  const void* fn = reinterpret_cast<const void*>(&r2r_fast_kernel<T, M>);
-  hipLaunchKernelGGL((r2r_fast_kernel<T, M>), dim3(resident_grid(fn, L::NT, lds, a.g.ntiles)),
-                     dim3(L::NT), lds, st, a);
+  const R2RFastArgs<T> a = fast_args<T, C>(p, A, inverse, data, skip);
+  const size_t lds = fast_lds_bytes<T, C>();
+  const void* fn = reinterpret_cast<const void*>(&r2r_fast_kernel<T, C>);
+  hipLaunchKernelGGL((r2r_fast_kernel<T, C>), dim3(resident_grid(fn, 512, lds, a.g.ntiles)),
+                     dim3(512), lds, st, a);
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
+}
+
+// Specialised transform of axis A in variant V (-1: the length has none).
+template <typename T>
+static int launch_fast_variant(const poisson_plan* p, const AxisTables& A, int V, int inverse,
+                               T* data, hipStream_t st, const double* skip) {
+  return (int)with_fast_cfg(A.m, V, [&](auto cfg) {
+    return (long long)launch_fast<T, decltype(cfg)>(p, A, inverse, data, st, skip);
+  });
 }
 
 template <typename T>
@@ -304,17 +385,9 @@ static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hip
                       const double* skip = nullptr) {
   const AxisTables& A = p->ax[role];
   if (!p->generic_r2r) {
-    switch (A.m) {
-      case 16: return launch_fast<T, 16>(p, A, inverse, data, st, skip);
-      case 32: return launch_fast<T, 32>(p, A, inverse, data, st, skip);
-      case 48: return launch_fast<T, 48>(p, A, inverse, data, st, skip);
-      case 64: return launch_fast<T, 64>(p, A, inverse, data, st, skip);
-      case 96: return launch_fast<T, 96>(p, A, inverse, data, st, skip);
-      case 128: return launch_fast<T, 128>(p, A, inverse, data, st, skip);
-      case 192: return launch_fast<T, 192>(p, A, inverse, data, st, skip);
-      case 256: return launch_fast<T, 256>(p, A, inverse, data, st, skip);
-      default: break;
-    }
+    const int rc = launch_fast_variant<T>(p, A, tuned_choice(0, sizeof(T), A.m, A.axis == 0),
+                                          inverse, data, st, skip);
+    if (rc != -1) return rc;
   }
   constexpr int EMAX = sizeof(T) == 8 ? R2R_EMAX_D : R2R_EMAX_F;
   const int cap_reals = 2 * EMAX * R2R_NT;
@@ -387,19 +460,19 @@ static int launch_tri_fast(const poisson_plan* p, T* data, hipStream_t st, const
   return POISSON_OK;
 }
 
-// Shape (rows per chunk * 100 + chunks per line) of the size-specialised
-// elimination kernel for lines of n points, or 0 if n has none.
-static int tri_fast_shape(int n) {
-  switch (n) {
-    case 64: return 416;
-    case 96: return 616;
-    case 128: return 816;
-    case 192: return 1216;
-    case 256: return 832;
-    case 384: return 664;
-    case 512: return 864;
-    default: return 0;
-  }
+// Specialised elimination in variant V (-1: the length has none).
+template <typename T>
+static int launch_tri_variant(const poisson_plan* p, int V, T* data, hipStream_t st,
+                              const double* skip) {
+  return (int)with_tri_cfg(p->dims[p->s], V, [&](auto cfg) {
+    using C = decltype(cfg);
+    return (long long)launch_tri_fast<T, C::RPC, C::P>(p, data, st, skip);
+  });
+}
+
+// True if lines of n points have size-specialised elimination kernels.
+static bool tri_fast_length(int n) {
+  return with_tri_cfg(n, 0, [](auto) { return 0LL; }) == 0;
 }
 
 // Complex length M of the size-specialised transform kernel for axis A, or
@@ -415,16 +488,9 @@ template <typename T>
 static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
                           const double* skip = nullptr) {
   if (!p->generic_tri) {
-    switch (tri_fast_shape(p->dims[p->s])) {
-      case 416: return launch_tri_fast<T, 4, 16>(p, data, st, skip);
-      case 616: return launch_tri_fast<T, 6, 16>(p, data, st, skip);
-      case 816: return launch_tri_fast<T, 8, 16>(p, data, st, skip);
-      case 1216: return launch_tri_fast<T, 12, 16>(p, data, st, skip);
-      case 832: return launch_tri_fast<T, 8, 32>(p, data, st, skip);
-      case 664: return launch_tri_fast<T, 6, 64>(p, data, st, skip);
-      case 864: return launch_tri_fast<T, 8, 64>(p, data, st, skip);
-      default: break;
-    }
+    const int n = p->dims[p->s];
+    const int rc = launch_tri_variant<T>(p, tuned_choice(1, sizeof(T), n, p->s == 0), data, st, skip);
+    if (rc != -1) return rc;
   }
   TriArgs<T> a{};
   a.data = data;
@@ -819,7 +885,7 @@ extern "C" int batch_solve(poisson_plan* const* plans, double* const* rhs, int c
   for (int i = 0; i < count && specialised; ++i) {
     const poisson_plan* p = plans[i];
     specialised = r2r_fast_length(p->ax[0]) && r2r_fast_length(p->ax[1]) &&
-                  tri_fast_shape(p->dims[p->s]) && !p->generic_r2r && !p->generic_tri;
+                  tri_fast_length(p->dims[p->s]) && !p->generic_r2r && !p->generic_tri;
   }
   if (count > 0 && specialised) {
     poisson_batch* b = batch_create(plans, count);
@@ -862,85 +928,48 @@ struct poisson_batch {
   hipGraphExec_t exec = nullptr;
 };
 
-static size_t fast_lds_for(int M) {
-  switch (M) {
-    case 16: return fast_lds_bytes<double, 16>();
-    case 32: return fast_lds_bytes<double, 32>();
-    case 48: return fast_lds_bytes<double, 48>();
-    case 64: return fast_lds_bytes<double, 64>();
-    case 96: return fast_lds_bytes<double, 96>();
-    case 128: return fast_lds_bytes<double, 128>();
-    case 192: return fast_lds_bytes<double, 192>();
-    case 256: return fast_lds_bytes<double, 256>();
-    default: return 0;
-  }
-}
-
-static size_t tri_lds_for(int shape) {
-  switch (shape) {
-    case 416: return tri_fast_lds_bytes<double, 4, 16>();
-    case 616: return tri_fast_lds_bytes<double, 6, 16>();
-    case 816: return tri_fast_lds_bytes<double, 8, 16>();
-    case 1216: return tri_fast_lds_bytes<double, 12, 16>();
-    case 832: return tri_fast_lds_bytes<double, 8, 32>();
-    case 664: return tri_fast_lds_bytes<double, 6, 64>();
-    case 864: return tri_fast_lds_bytes<double, 8, 64>();
-    default: return 0;
-  }
-}
-
-static R2RFastArgs<double> fast_args_for(const poisson_plan* p, const AxisTables& A, int inverse,
-                                         double* data) {
-  switch (A.m) {
-    case 16: return fast_args<double, 16>(p, A, inverse, data, nullptr);
-    case 32: return fast_args<double, 32>(p, A, inverse, data, nullptr);
-    case 48: return fast_args<double, 48>(p, A, inverse, data, nullptr);
-    case 64: return fast_args<double, 64>(p, A, inverse, data, nullptr);
-    case 96: return fast_args<double, 96>(p, A, inverse, data, nullptr);
-    case 128: return fast_args<double, 128>(p, A, inverse, data, nullptr);
-    case 192: return fast_args<double, 192>(p, A, inverse, data, nullptr);
-    default: return fast_args<double, 256>(p, A, inverse, data, nullptr);
-  }
-}
-
-static TriFastArgs<double> tri_args_for(const poisson_plan* p, int shape, double* data) {
-  switch (shape) {
-    case 416: return tri_fast_args<double, 4, 16>(p, data, nullptr);
-    case 616: return tri_fast_args<double, 6, 16>(p, data, nullptr);
-    case 816: return tri_fast_args<double, 8, 16>(p, data, nullptr);
-    case 1216: return tri_fast_args<double, 12, 16>(p, data, nullptr);
-    case 832: return tri_fast_args<double, 8, 32>(p, data, nullptr);
-    case 664: return tri_fast_args<double, 6, 64>(p, data, nullptr);
-    default: return tri_fast_args<double, 8, 64>(p, data, nullptr);
-  }
-}
-
-// Job tables of every step for the given fields (null fields: sizes only).
+// Job tables of every step for the given fields (null fields: sizes only),
+// with the variants chosen now; sets item counts and LDS sizes.
 static void batch_jobs(poisson_batch* b, double* const* rhs, std::vector<char>& host) {
   host.assign(b->bytes, 0);
   for (int k = 0; k < 5; ++k) {
     int first = 0;
+    size_t lds = 0;
     for (size_t j = 0; j < b->order[k].size(); ++j) {
       const int i = b->order[k][j];
       const poisson_plan* p = b->plans[i];
       double* data = rhs ? rhs[i] : nullptr;
       if (kStepRole[k] >= 0) {
+        const AxisTables& A = p->ax[kStepRole[k]];
         BatchR2RJob<double> J{};
-        J.a = fast_args_for(p, p->ax[kStepRole[k]], kStepInverse[k], data);
-        J.M = p->ax[kStepRole[k]].m;
+        J.M = A.m;
+        J.V = tuned_choice(0, sizeof(double), A.m, A.axis == 0);
+        with_fast_cfg(J.M, J.V, [&](auto cfg) {
+          using C = decltype(cfg);
+          J.a = fast_args<double, C>(p, A, kStepInverse[k], data, nullptr);
+          lds = std::max(lds, fast_lds_bytes<double, C>());
+          return 0LL;
+        });
         J.first = first;
         first += J.a.g.ntiles;
         std::memcpy(host.data() + b->off[k] + j * sizeof(J), &J, sizeof(J));
       } else {
+        const int n = p->dims[p->s];
         BatchTriJob<double> J{};
-        J.shape = tri_fast_shape(p->dims[p->s]);
-        J.a = tri_args_for(p, J.shape, data);
+        J.key = 2 * n + tuned_choice(1, sizeof(double), n, p->s == 0);
+        with_tri_cfg(n, J.key & 1, [&](auto cfg) {
+          using C = decltype(cfg);
+          J.a = tri_fast_args<double, C::RPC, C::P>(p, data, nullptr);
+          lds = std::max(lds, tri_fast_lds_bytes<double, C::RPC, C::P>());
+          return 0LL;
+        });
         J.first = first;
         first += J.a.g.ntiles;
         std::memcpy(host.data() + b->off[k] + j * sizeof(J), &J, sizeof(J));
       }
     }
     b->items[k] = first;
+    b->lds[k] = lds;
   }
 }
 
@@ -959,7 +988,7 @@ extern "C" poisson_batch* batch_create(poisson_plan* const* plans, int count) {
         fail(POISSON_EUNSUPPORTED, "plan %d: transform length %d has no size-specialised kernel", i, p->ax[r].n);
         return nullptr;
       }
-    if (!tri_fast_shape(p->dims[p->s])) {
+    if (!tri_fast_length(p->dims[p->s])) {
       fail(POISSON_EUNSUPPORTED, "plan %d: elimination length %d has no size-specialised kernel", i, p->dims[p->s]);
       return nullptr;
     }
@@ -972,23 +1001,16 @@ extern "C" poisson_batch* batch_create(poisson_plan* const* plans, int count) {
     std::vector<int>& ord = b->order[k];
     for (int i = 0; i < count; ++i) ord.push_back(i);
     // group jobs that share LDS tables: transforms by length and type class
-    // (twiddles), eliminations by shape
+    // (twiddles), eliminations by length
     auto key = [&](int i) {
       const poisson_plan* p = plans[i];
       if (kStepRole[k] >= 0) {
         const AxisTables& A = p->ax[kStepRole[k]];
         return A.m * 2 + (A.kind >= BC_ND ? 1 : 0);
       }
-      return tri_fast_shape(p->dims[p->s]);
+      return p->dims[p->s];
     };
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return key(x) < key(y); });
-    size_t lds = 0;
-    for (int i : ord) {
-      const poisson_plan* p = plans[i];
-      lds = std::max(lds, kStepRole[k] >= 0 ? fast_lds_for(p->ax[kStepRole[k]].m)
-                                            : tri_lds_for(tri_fast_shape(p->dims[p->s])));
-    }
-    b->lds[k] = lds;
     b->njobs[k] = count;
     bytes = align_up(bytes, 64);
     b->off[k] = bytes;
@@ -1009,8 +1031,18 @@ extern "C" int batch_bind(poisson_batch* b, double* const* rhs) {
   if (!b || !rhs) return fail(POISSON_EINVAL, "null argument");
   for (size_t i = 0; i < b->plans.size(); ++i)
     if (!rhs[i]) return fail(POISSON_EINVAL, "null field at batch index %zu", i);
+  size_t lds_before[5];
+  std::memcpy(lds_before, b->lds, sizeof(lds_before));
   std::vector<char> host;
   batch_jobs(b, rhs, host);
+  if (b->exec && std::memcmp(lds_before, b->lds, sizeof(lds_before)) != 0) {
+    // the variants changed (autotuner) and with them the LDS sizes: the
+    // captured launches no longer fit; capture again at the next launch
+    (void)hipGraphExecDestroy(b->exec);
+    (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+  }
   HIP_TRY(hipMemcpy(b->djobs, host.data(), b->bytes, hipMemcpyHostToDevice));
   b->bound = true;
   return POISSON_OK;
@@ -1043,7 +1075,7 @@ extern "C" int batch_launch(poisson_batch* b, hipStream_t st, int use_graph) {
   if (!b->exec) {
     // capture the five launches once on a private stream; the job tables
     // live in device memory, so later batch_bind calls need no re-capture
-    HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    if (!b->cap) HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     const int rc = batch_enqueue(b, b->cap);
     hipGraph_t g = nullptr;
@@ -1064,6 +1096,114 @@ extern "C" void batch_destroy(poisson_batch* b) {
   if (b->cap) (void)hipStreamDestroy(b->cap);
   if (b->djobs) (void)hipFree(b->djobs);
   delete b;
+}
+
+// ------------------------------------------------------------------ autotuner
+
+__global__ void fill_kernel(double* x, long long n, double v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+// Average time (ms) of `reps` calls of launch() on st, after one untimed call.
+template <typename F>
+static double time_launches(hipStream_t st, int reps, F&& launch, int& rc) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rc = POISSON_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = fail(POISSON_EHIP, "hipEventCreate failed");
+    if (e0) (void)hipEventDestroy(e0);
+    return 0.0;
+  }
+  rc = launch();
+  if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = fail(POISSON_EHIP, "hipEventRecord failed");
+  for (int r = 0; r < reps && !rc; ++r) rc = launch();
+  float ms = 0.0f;
+  if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = fail(POISSON_EHIP, "event timing failed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc ? 0.0 : (double)ms / reps;
+}
+
+template <typename T>
+static int autotune_typed(poisson_plan* p, double* scratch, int reps, hipStream_t st,
+                          double* report) {
+  T* data = reinterpret_cast<T*>(scratch);
+  const long long N = (long long)field_points(p);
+  int rc = POISSON_OK;
+  auto reset = [&]() -> int {
+    hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, st, scratch, N * (long long)sizeof(T) / 8, 0.5);
+    HIP_TRY(hipGetLastError());
+    return POISSON_OK;
+  };
+  for (int role = 0; role < 2; ++role) {
+    const AxisTables& A = p->ax[role];
+    if (!r2r_fast_length(A)) continue;
+    int best = 0;
+    double best_ms = 1e300;
+    for (int V = 0; V < kFastVariants; ++V) {
+      if ((rc = reset())) return rc;
+      // forward then backward: the field keeps its size over the repetitions
+      const double ms = time_launches(st, reps, [&]() -> int {
+        int r = launch_fast_variant<T>(p, A, V, 0, data, st, nullptr);
+        if (!r) r = launch_fast_variant<T>(p, A, V, 1, data, st, nullptr);
+        return r;
+      }, rc);
+      if (rc) return rc;
+      if (report) report[role * kFastVariants + V] = ms;
+      if (ms < best_ms) { best_ms = ms; best = V; }
+    }
+    set_tuned_choice(0, sizeof(T), A.m, A.axis == 0, best);
+  }
+  const int n = p->dims[p->s];
+  if (tri_fast_length(n)) {
+    int best = 0;
+    double best_ms = 1e300;
+    for (int V = 0; V < kTriVariants; ++V) {
+      if ((rc = reset())) return rc;
+      const double ms = time_launches(st, reps, [&]() -> int {
+        return launch_tri_variant<T>(p, V, data, st, nullptr);
+      }, rc);
+      if (rc) return rc;
+      if (report) report[2 * kFastVariants + V] = ms;
+      if (ms < best_ms) { best_ms = ms; best = V; }
+    }
+    set_tuned_choice(1, sizeof(T), n, p->s == 0, best);
+  }
+  return POISSON_OK;
+}
+
+extern "C" int plan_autotune(poisson_plan* p, double* scratch, int reps, hipStream_t st,
+                             double* report) {
+  if (!p || !scratch) return fail(POISSON_EINVAL, "null argument");
+  if (reps < 1 || reps > 1000) return fail(POISSON_EINVAL, "reps must be in [1, 1000]");
+  if (lds_setup_once()) return g_err;
+  if (report)
+    for (int i = 0; i < 2 * (2 * kFastVariants + kTriVariants); ++i) report[i] = -1.0;
+  int rc = autotune_typed<double>(p, scratch, reps, st, report);
+  if (!rc) rc = autotune_typed<float>(p, scratch, reps, st,
+                                      report ? report + 2 * kFastVariants + kTriVariants : nullptr);
+  return rc;
+}
+
+extern "C" int set_tuned_variant(int family, int n, int layout, int fp64, int variant) {
+  if (family != 0 && family != 1) return fail(POISSON_EINVAL, "family must be 0 or 1");
+  const int count = family == 0 ? kFastVariants : kTriVariants;
+  if (variant < 0 || variant >= count) return fail(POISSON_EINVAL, "variant must be in [0, %d)", count);
+  const bool ok = family == 0 ? (n % 2 == 0 && with_fast_cfg(n / 2, 0, [](auto) { return 0LL; }) == 0)
+                              : tri_fast_length(n);
+  if (!ok) return fail(POISSON_EUNSUPPORTED, "length %d has no size-specialised kernels", n);
+  set_tuned_choice(family, fp64 ? 8 : 4, family == 0 ? n / 2 : n, layout ? 1 : 0, variant);
+  return POISSON_OK;
+}
+
+extern "C" int tuned_variant(int family, int n, int layout, int fp64) {
+  if (family != 0 && family != 1) return fail(POISSON_EINVAL, "family must be 0 or 1");
+  const int len = family == 0 ? n / 2 : n;   // transforms are keyed by M = n/2
+  return tuned_choice(family, fp64 ? 8 : 4, len, layout ? 1 : 0);
 }
 
 // ------------------------------------------------------------------ server

@@ -30,7 +30,9 @@ struct RadixPlan {
   int r[12];
 };
 
-constexpr RadixPlan make_radix_plan(int m) {
+// mode 0: as many radix-8 passes as possible (then 4, 2); mode 1: radix 4
+// (then one radix 2); radix 3 and 5 passes last.
+constexpr RadixPlan make_radix_plan(int m, int mode) {
   RadixPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
   int e2 = 0;
   while (m % 2 == 0) { m /= 2; ++e2; }
@@ -40,6 +42,11 @@ constexpr RadixPlan make_radix_plan(int m) {
     if (n8 > 0) { --n8; n4 = 2; } else { n2 = 1; }
   }
   if (rem == 2) n4 = 1;
+  if (mode == 1) {
+    n8 = 0;
+    n4 = e2 / 2;
+    n2 = e2 % 2;
+  }
   for (int i = 0; i < n8; ++i) p.r[p.count++] = 8;
   for (int i = 0; i < n4; ++i) p.r[p.count++] = 4;
   for (int i = 0; i < n2; ++i) p.r[p.count++] = 2;
@@ -54,31 +61,38 @@ constexpr int plan_ns(const RadixPlan& p, int pass) {
   return ns;
 }
 
-// Launch shape of the specialised kernel for complex length M.
-template <int M>
-struct FastShape;
-#define POISSON_FAST_SHAPE(M_, QT_, NL_)      \
-  template <>                                 \
-  struct FastShape<M_> {                      \
-    static constexpr int QT = QT_, NL = NL_;  \
-  };
-POISSON_FAST_SHAPE(16, 4, 128)
-POISSON_FAST_SHAPE(32, 4, 128)
-POISSON_FAST_SHAPE(48, 8, 64)
-POISSON_FAST_SHAPE(64, 8, 64)
-POISSON_FAST_SHAPE(96, 16, 32)
-POISSON_FAST_SHAPE(128, 16, 32)
-POISSON_FAST_SHAPE(192, 32, 16)
-POISSON_FAST_SHAPE(256, 32, 16)
-#undef POISSON_FAST_SHAPE
+// Compile-time configuration of the specialised kernel: complex length M,
+// threads per line QT, lines per tile NL (QT * NL = 512 threads) and the
+// radix order of the FFT (MODE 0: radix 8 first, MODE 1: radix 4 first).
+template <int M_, int QT_, int NL_, int MODE_>
+struct FastCfg {
+  static constexpr int M = M_, QT = QT_, NL = NL_, MODE = MODE_;
+  static_assert(QT * NL == 512, "transform blocks have 512 threads (the batched kernel relies on it)");
+  static_assert(M % QT == 0, "whole complex values per thread");
+};
 
-// Every shape has 512 threads: the batched kernel runs all lengths in
-// blocks of that size.
+// The four variants of each length that the autotuner chooses from:
+// bit 0 selects the tile shape (base or alternative), bit 1 the radix order.
 template <int M>
-constexpr int fast_nt() {
-  static_assert(FastShape<M>::QT * FastShape<M>::NL == 512, "transform blocks have 512 threads");
-  return FastShape<M>::QT * FastShape<M>::NL;
-}
+struct FastShapes;
+#define POISSON_FAST_SHAPES(M_, QT0, NL0, QT1, NL1) \
+  template <>                                       \
+  struct FastShapes<M_> {                           \
+    static constexpr int QT[2] = {QT0, QT1};        \
+    static constexpr int NL[2] = {NL0, NL1};        \
+  };
+POISSON_FAST_SHAPES(16, 4, 128, 8, 64)
+POISSON_FAST_SHAPES(32, 4, 128, 8, 64)
+POISSON_FAST_SHAPES(48, 8, 64, 16, 32)
+POISSON_FAST_SHAPES(64, 8, 64, 16, 32)
+POISSON_FAST_SHAPES(96, 16, 32, 32, 16)
+POISSON_FAST_SHAPES(128, 16, 32, 32, 16)
+POISSON_FAST_SHAPES(192, 32, 16, 64, 8)
+POISSON_FAST_SHAPES(256, 32, 16, 64, 8)
+#undef POISSON_FAST_SHAPES
+
+template <int M, int V>
+using FastVar = FastCfg<M, FastShapes<M>::QT[V & 1], FastShapes<M>::NL[V & 1], (V >> 1) & 1>;
 
 template <typename T>
 struct R2RFastArgs {
@@ -95,9 +109,10 @@ struct R2RFastArgs {
   const double* skip;
 };
 
-template <typename T, int M>
+template <typename T, typename C>
 struct FastLayout {
-  static constexpr int QT = FastShape<M>::QT, NL = FastShape<M>::NL;
+  static constexpr int M = C::M;
+  static constexpr int QT = C::QT, NL = C::NL;
   static constexpr int NT = QT * NL;
   static constexpr int N = 2 * M;
   static constexpr int NLP = NL + 1;         // odd LDS row pitch
@@ -106,13 +121,14 @@ struct FastLayout {
   static constexpr int TILE = N * NLP;       // reals of the tile in LDS
   static constexpr int AUX = 2 * M;          // pre/post or split/quarter tables (complex)
   static constexpr int SPLIT = M / 2 + 1;    // split-table entries kept in LDS
-  static constexpr RadixPlan plan = make_radix_plan(M);
+  static constexpr RadixPlan plan = make_radix_plan(M, C::MODE);
   static_assert(SPLIT + M + 1 <= AUX, "split + quarter tables exceed the LDS slot");
 };
 
-template <typename T, int M>
+template <typename T, typename C>
 constexpr size_t fast_lds_bytes() {
-  using L = FastLayout<T, M>;
+  using L = FastLayout<T, C>;
+  [[maybe_unused]] constexpr int M = L::M;
   return (size_t)L::TILE * sizeof(T) + (size_t)(M + L::AUX) * sizeof(cplx<T>);
 }
 
@@ -135,9 +151,10 @@ __device__ __forceinline__ void stc(lptr<cplx<T>> p, int i, cplx<T> v) {
 // call passes only a few scalars.
 
 // One Stockham pass of radix R (Ns = NS) over the tile, in place in LDS.
-template <typename T, int M, int R, int NS, bool FWD>
+template <typename T, typename C, int R, int NS, bool FWD>
 __device__ __noinline__ void fast_pass(lptr<T> lds, lptr<const cplx<T>> tw, int l, int q) {
-  using L = FastLayout<T, M>;
+  using L = FastLayout<T, C>;
+  [[maybe_unused]] constexpr int M = L::M;
   constexpr int B = M / R;                       // butterflies per line
   constexpr int SB = (B + L::QT - 1) / L::QT;    // per thread
   constexpr int TS = M / (NS * R);               // twiddle stride
@@ -181,24 +198,26 @@ __device__ __noinline__ void fast_pass(lptr<T> lds, lptr<const cplx<T>> tw, int 
   __syncthreads();
 }
 
-template <typename T, int M, bool FWD, int P>
+template <typename T, typename C, bool FWD, int P>
 __device__ __forceinline__ void fast_passes(lptr<T> lds, lptr<const cplx<T>> tw, int l, int q) {
-  using L = FastLayout<T, M>;
+  using L = FastLayout<T, C>;
+  [[maybe_unused]] constexpr int M = L::M;
   if constexpr (P < L::plan.count) {
     constexpr int R = L::plan.r[P];
     constexpr int NS = plan_ns(L::plan, P);
-    fast_pass<T, M, R, NS, FWD>(lds, tw, l, q);
-    fast_passes<T, M, FWD, P + 1>(lds, tw, l, q);
+    fast_pass<T, C, R, NS, FWD>(lds, tw, l, q);
+    fast_passes<T, C, FWD, P + 1>(lds, tw, l, q);
   }
 }
 
 // Tile load: global -> LDS rows with the input permutation of the type.
 // All of a thread's loads are issued before its first LDS write.
-template <typename T, int M>
+template <typename T, typename C>
 __device__ __noinline__ void fast_load(lptr<T> lds, gptr<const T> data, long long base,
                                        long long sp, int layout, int lines, int kind,
                                        int inverse, int l, int q, int tid) {
-  using L = FastLayout<T, M>;
+  using L = FastLayout<T, C>;
+  [[maybe_unused]] constexpr int M = L::M;
   constexpr int N = L::N;
   T buf[L::EPT];
   if (layout == 0) {
@@ -230,11 +249,12 @@ __device__ __noinline__ void fast_load(lptr<T> lds, gptr<const T> data, long lon
 }
 
 // Tile store: LDS rows -> global with the output permutation, sign, scale.
-template <typename T, int M>
+template <typename T, typename C>
 __device__ __noinline__ void fast_store(lptr<const T> lds, gptr<T> data, long long base,
                                         long long sp, int layout, int lines, int kind,
                                         int inverse, T scale, int l, int q, int tid) {
-  using L = FastLayout<T, M>;
+  using L = FastLayout<T, C>;
+  [[maybe_unused]] constexpr int M = L::M;
   constexpr int N = L::N;
   T buf[L::EPT];
   if (layout == 0) {
@@ -268,9 +288,10 @@ __device__ __noinline__ void fast_store(lptr<const T> lds, gptr<T> data, long lo
 }
 
 // DCT-IV pre-twiddle (in place: each thread scales its own elements).
-template <typename T, int M>
+template <typename T, typename C>
 __device__ __noinline__ void fast_iv_pre(lptr<T> lds, lptr<const cplx<T>> pre, int l, int q) {
-  using L = FastLayout<T, M>;
+  using L = FastLayout<T, C>;
+  [[maybe_unused]] constexpr int M = L::M;
 #pragma unroll
   for (int s = 0; s < L::E; ++s) {
     const int j = q + s * L::QT;
@@ -283,9 +304,10 @@ __device__ __noinline__ void fast_iv_pre(lptr<T> lds, lptr<const cplx<T>> pre, i
 }
 
 // DCT-IV post-step: V_k = Z_k e^{-i pi k/n}; y_2k = 2 Re V_k, y_{n-1-2k} = -2 Im V_k.
-template <typename T, int M>
+template <typename T, typename C>
 __device__ __noinline__ void fast_iv_post(lptr<T> lds, lptr<const cplx<T>> post, int l, int q) {
-  using L = FastLayout<T, M>;
+  using L = FastLayout<T, C>;
+  [[maybe_unused]] constexpr int M = L::M;
   constexpr int N = L::N;
   cplx<T> V[L::E];
 #pragma unroll
@@ -305,10 +327,11 @@ __device__ __noinline__ void fast_iv_post(lptr<T> lds, lptr<const cplx<T>> post,
 
 // Inverse P/NN/DD: rebuild the length-M spectrum
 // Z'_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) e^{2 pi i k/n}.
-template <typename T, int M>
+template <typename T, typename C>
 __device__ __noinline__ void fast_combine(lptr<T> lds, lptr<const cplx<T>> split,
                                           lptr<const cplx<T>> quarter, int kind, int l, int q) {
-  using L = FastLayout<T, M>;
+  using L = FastLayout<T, C>;
+  [[maybe_unused]] constexpr int M = L::M;
   constexpr int N = L::N, NLP = L::NLP;
   constexpr int NP = M / 2 + 1;
   constexpr int SP = (NP + L::QT - 1) / L::QT;
@@ -359,10 +382,11 @@ __device__ __noinline__ void fast_combine(lptr<T> lds, lptr<const cplx<T>> split
 
 // Forward P/NN/DD: even/odd split of the FFT into the real DFT X_k of the
 // (reordered) input and the stored coefficients (see r2r_kernel.h).
-template <typename T, int M>
+template <typename T, typename C>
 __device__ __noinline__ void fast_split(lptr<T> lds, lptr<const cplx<T>> split,
                                         lptr<const cplx<T>> quarter, int kind, int l, int q) {
-  using L = FastLayout<T, M>;
+  using L = FastLayout<T, C>;
+  [[maybe_unused]] constexpr int M = L::M;
   constexpr int N = L::N, NLP = L::NLP;
   constexpr int NP = M / 2 + 1;
   constexpr int SP = (NP + L::QT - 1) / L::QT;
@@ -420,15 +444,16 @@ __device__ __noinline__ void fast_split(lptr<T> lds, lptr<const cplx<T>> split,
 
 // LDS regions of the specialised transform: the tile, then the FFT twiddles
 // (M), then the pre/post (DCT-IV types) or split/quarter tables (2M).
-template <typename T, int M>
+template <typename T, typename C>
 struct FastLds {
   lptr<T> tile;
   lptr<cplx<T>> twf, twa;
 };
-template <typename T, int M>
-__device__ __forceinline__ FastLds<T, M> fast_lds(unsigned char* smem) {
-  using L = FastLayout<T, M>;
-  FastLds<T, M> r;
+template <typename T, typename C>
+__device__ __forceinline__ FastLds<T, C> fast_lds(unsigned char* smem) {
+  using L = FastLayout<T, C>;
+  [[maybe_unused]] constexpr int M = L::M;
+  FastLds<T, C> r;
   r.tile = as_lds(reinterpret_cast<T*>(smem));
   r.twf = as_lds(reinterpret_cast<cplx<T>*>(reinterpret_cast<T*>(smem) + L::TILE));
   r.twa = r.twf + M;
@@ -438,10 +463,11 @@ __device__ __forceinline__ FastLds<T, M> fast_lds(unsigned char* smem) {
 // Twiddle tables of transform `kind` (those of the DCT-IV types, or those
 // of the others) into LDS; ends with a barrier.  The values depend only on
 // n = 2M and the type class.
-template <typename T, int M>
-__device__ __forceinline__ void fast_twiddles(const FastLds<T, M>& S, const R2RFastArgs<T>& A,
+template <typename T, typename C>
+__device__ __forceinline__ void fast_twiddles(const FastLds<T, C>& S, const R2RFastArgs<T>& A,
                                               int tid) {
-  using L = FastLayout<T, M>;
+  using L = FastLayout<T, C>;
+  [[maybe_unused]] constexpr int M = L::M;
   constexpr int NT = L::NT;
   for (int i = tid; i < M; i += NT) stc(S.twf, i, ldg(A.tw_fft, i));
   if (A.kind >= K_ND) {
@@ -458,10 +484,11 @@ __device__ __forceinline__ void fast_twiddles(const FastLds<T, M>& S, const R2RF
 
 // One tile of lines of the launch described by A, with the twiddles of its
 // type class already in LDS; ends with a barrier.
-template <typename T, int M>
-__device__ __forceinline__ void fast_tile(const FastLds<T, M>& S, const R2RFastArgs<T>& A,
+template <typename T, typename C>
+__device__ __forceinline__ void fast_tile(const FastLds<T, C>& S, const R2RFastArgs<T>& A,
                                           int tile, int tid) {
-  using L = FastLayout<T, M>;
+  using L = FastLayout<T, C>;
+  [[maybe_unused]] constexpr int M = L::M;
   constexpr int NL = L::NL;
   const int l = tid % NL;
   const int q = tid / NL;
@@ -481,34 +508,34 @@ __device__ __forceinline__ void fast_tile(const FastLds<T, M>& S, const R2RFastA
     base = (long long)o.L0 * L::N;
     lines = g.nlines - o.L0;
   }
-  fast_load<T, M>(S.tile, as_global((const T*)A.data), base, g.sp, g.layout, lines, kind, inverse,
+  fast_load<T, C>(S.tile, as_global((const T*)A.data), base, g.sp, g.layout, lines, kind, inverse,
                   l, q, tid);
   __syncthreads();
 
-  if (ivk) fast_iv_pre<T, M>(S.tile, tw_a, l, q);
-  else if (inverse) fast_combine<T, M>(S.tile, tw_a, tw_b, kind, l, q);
+  if (ivk) fast_iv_pre<T, C>(S.tile, tw_a, l, q);
+  else if (inverse) fast_combine<T, C>(S.tile, tw_a, tw_b, kind, l, q);
 
-  if (!(inverse && kind <= K_DD)) fast_passes<T, M, true, 0>(S.tile, tw_fft, l, q);
-  else fast_passes<T, M, false, 0>(S.tile, tw_fft, l, q);
+  if (!(inverse && kind <= K_DD)) fast_passes<T, C, true, 0>(S.tile, tw_fft, l, q);
+  else fast_passes<T, C, false, 0>(S.tile, tw_fft, l, q);
 
-  if (ivk) fast_iv_post<T, M>(S.tile, tw_b, l, q);
-  else if (!inverse) fast_split<T, M>(S.tile, tw_a, tw_b, kind, l, q);
+  if (ivk) fast_iv_post<T, C>(S.tile, tw_b, l, q);
+  else if (!inverse) fast_split<T, C>(S.tile, tw_a, tw_b, kind, l, q);
 
-  fast_store<T, M>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind, inverse,
+  fast_store<T, C>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind, inverse,
                    A.scale, l, q, tid);
   __syncthreads();
 }
 
-template <typename T, int M>
-__global__ __launch_bounds__(fast_nt<M>()) __attribute__((amdgpu_waves_per_eu(4)))
+template <typename T, typename C>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 void r2r_fast_kernel(R2RFastArgs<T> A) {
   if (A.skip && A.skip[0] != 0.0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const FastLds<T, M> S = fast_lds<T, M>(smem_raw);
+  const FastLds<T, C> S = fast_lds<T, C>(smem_raw);
   const int tid = threadIdx.x;
-  fast_twiddles<T, M>(S, A, tid);
+  fast_twiddles<T, C>(S, A, tid);
   const TileRange tr = xcd_tiles(A.g.ntiles);
-  for (int tile = tr.first; tile < tr.end; tile += tr.step) fast_tile<T, M>(S, A, tile, tid);
+  for (int tile = tr.first; tile < tr.end; tile += tr.step) fast_tile<T, C>(S, A, tile, tid);
 }
 
 }  // namespace poisson_dev

@@ -42,6 +42,10 @@ SIGNATURES = {
     "batch_bind": (ctypes.c_int, [_VP, ctypes.POINTER(_VP)]),
     "batch_launch": (ctypes.c_int, [_VP, _VP, ctypes.c_int]),
     "batch_destroy": (None, [_VP]),
+    "plan_autotune": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP, ctypes.POINTER(ctypes.c_double)]),
+    "tuned_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "set_tuned_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int]),
     "server_create": (_VP, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int]),
     "server_submit": (ctypes.c_longlong, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_double,
@@ -181,6 +185,22 @@ class Plan:
         _check(lib().tridiag_stage(self.handle, _field_ptr(field), _stream_handle(stream)))
         return field
 
+    def autotune(self, scratch, reps=5, stream=None):
+        """Time every kernel variant of this plan on ``scratch`` (a device
+        float64 tensor of the field's size, overwritten) and record the
+        fastest per length; returns the timing report (ms) as
+        {"fp64"|"fp32": {"t1": [4], "t2": [4], "elimination": [2]}}."""
+        if scratch.numel() < int(np.prod(self.shape)):
+            raise ValueError("scratch is smaller than the field")
+        rep = (ctypes.c_double * 20)()
+        _check(lib().plan_autotune(self.handle, _field_ptr(scratch), int(reps),
+                                   _stream_handle(stream), rep))
+        out = {}
+        for k, name in enumerate(("fp64", "fp32")):
+            r = list(rep)[10 * k:10 * (k + 1)]
+            out[name] = {"t1": r[0:4], "t2": r[4:8], "elimination": r[8:10]}
+        return out
+
     def close(self):
         if getattr(self, "_h", None) is not None:
             lib().plan_destroy(self._h)
@@ -315,3 +335,16 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def tuned_variant(family, n, layout, fp64=True):
+    """Variant in the autotuner's table (family 0 transform, 1 elimination;
+    layout 0 strided, 1 contiguous)."""
+    v = lib().tuned_variant(int(family), int(n), int(layout), int(bool(fp64)))
+    if v < 0:
+        _check(v)
+    return v
+
+
+def set_tuned_variant(family, n, layout, variant, fp64=True):
+    _check(lib().set_tuned_variant(int(family), int(n), int(layout), int(bool(fp64)), int(variant)))

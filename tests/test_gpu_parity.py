@@ -144,6 +144,12 @@ def _line_systems(x, f, a, b, c, periodic, shift):
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("n", ELIM_LENGTHS)
 def test_elimination_lengths(n, kind, path, monkeypatch):
+    if path == "generic":
+        monkeypatch.setenv("POISSON_GENERIC_TRI", "1")
+    _check_elimination(n, kind)
+
+
+def _check_elimination(n, kind):
     """The elimination stage alone for lengths that have size-specialised
     kernels (and the size-generic kernel on the same input), on the strided
     (s = z) and contiguous (s = x) layouts, singular and regular, uniform and
@@ -159,8 +165,6 @@ def test_elimination_lengths(n, kind, path, monkeypatch):
     from oracle.poisson import tridiagonal_stage
     from paper_1802_10323_amd import Plan
     import oracle
-    if path == "generic":
-        monkeypatch.setenv("POISSON_GENERIC_TRI", "1")
     if kind == "P":   # a periodic elimination axis only occurs when all axes are
         cases = [((20, 10, n), ("P", "P", "P"), "z")]
     else:
@@ -499,3 +503,108 @@ def test_server_admission_by_hbm_budget():
         with pytest.raises(PoissonError):
             srv.submit(big, to_dev(big.rhs))
     srv.close()
+
+
+# --------------------------------------------------------------- kernel variants
+
+FAST_M = [16, 32, 48, 64, 96, 128, 192, 256]
+
+
+@pytest.fixture
+def default_variants():
+    """Put every entry of the variant table back to 0 afterwards."""
+    from paper_1802_10323_amd import set_tuned_variant
+    yield
+    for fp64 in (True, False):
+        for layout in (0, 1):
+            for M in FAST_M:
+                set_tuned_variant(0, 2 * M, layout, 0, fp64)
+            for n in ELIM_LENGTHS:
+                set_tuned_variant(1, n, layout, 0, fp64)
+
+
+@pytest.mark.parametrize("V", [1, 2, 3])
+@pytest.mark.parametrize("M", FAST_M)
+def test_transform_variants(M, V, default_variants):
+    """Every compiled transform variant (tile shape x radix order) against
+    the Table 2 sums, all five types, contiguous and strided (one partial
+    and one multi-tile strided case); round trip is the identity."""
+    from oracle import transforms as tr
+    from paper_1802_10323_amd import Plan, set_tuned_variant
+    n = 2 * M
+    rng = np.random.default_rng(n + V)
+    for layout in (0, 1):
+        set_tuned_variant(0, n, layout, V)
+    for kind in KINDS:
+        for axis_name, shape in (("x", (3, 6, n)), ("y", (3, n, 8)), ("y", (2, n, 40))):
+            f = rng.uniform(-1, 1, shape)
+            nz, ny, nx = shape
+            bcx, bcy = (kind, "P") if axis_name == "x" else ("P", kind)
+            plan = Plan(nx, ny, nz, 1.0, 1.0, np.ones(nz), (bcx, bcy, "DD"))
+            role = 0 if axis_name == "x" else 1
+            d = to_dev(f)
+            plan.transform_stage(role, False, d)
+            assert rel_l2(to_host(d), tr.forward(f, AXIS[axis_name], kind)) <= 1e-13, (kind, shape)
+            plan.transform_stage(role, True, d)
+            assert rel_l2(to_host(d), f) <= 1e-13, (kind, shape)
+            plan.close()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("n", ELIM_LENGTHS)
+def test_elimination_variants(n, kind, default_variants):
+    """The second chunking of every specialised elimination length, with the
+    checks of test_elimination_lengths."""
+    from paper_1802_10323_amd import set_tuned_variant
+    for layout in (0, 1):
+        set_tuned_variant(1, n, layout, 1)
+    _check_elimination(n, kind)
+
+
+@pytest.mark.parametrize("vt,ve", [(1, 0), (2, 1), (3, 1)])
+def test_fp32_variants_refine(vt, ve, default_variants):
+    """FP32 kernels of the other variants inside the refined solve: it
+    converges to the oracle within 1e-10 in at most 4 FP32 solves."""
+    from paper_1802_10323_amd import set_tuned_variant
+    prob = inputs.make_uniform(128, 96, 192, ("P", "P", "NN"), seed=9, stretch_z=1.8)
+    for layout in (0, 1):
+        set_tuned_variant(0, 128, layout, vt, fp64=False)
+        set_tuned_variant(0, 96, layout, vt, fp64=False)
+        set_tuned_variant(1, 192, layout, ve, fp64=False)
+    got, (iters, rel, conv) = gpu_solve(prob, mixed=True, tol=1e-10, max_iters=6)
+    assert conv and iters <= 4, (iters, rel)
+    assert rel_l2(got, oracle_solve(prob)) <= 1e-10
+
+
+def test_autotune_records_fastest(default_variants):
+    """plan_autotune times every variant and keeps the fastest; solves with
+    the tuned table still match the oracle, and a batch built afterwards is
+    still bitwise equal to single solves."""
+    import torch
+    from paper_1802_10323_amd import Batch, Plan, tuned_variant
+    prob = inputs.make_uniform(128, 96, 192, ("P", "P", "NN"), seed=4, stretch_z=1.8)
+    plan = Plan.from_problem(prob)
+    scratch = torch.empty(prob.points, dtype=torch.float64, device="cuda")
+    rep = plan.autotune(scratch, reps=3)
+    say("autotune report", rep)
+    for prec, fp64 in (("fp64", True), ("fp32", False)):
+        r = rep[prec]
+        assert all(v > 0 for v in r["t1"] + r["t2"] + r["elimination"])
+        assert tuned_variant(0, 128, 1, fp64) == int(np.argmin(r["t1"]))
+        assert tuned_variant(0, 96, 0, fp64) == int(np.argmin(r["t2"]))
+        assert tuned_variant(1, 192, 0, fp64) == int(np.argmin(r["elimination"]))
+    got, _ = gpu_solve(prob)
+    assert rel_l2(got, oracle_solve(prob)) <= TOL64
+    probs = inputs.batch(7, count=4)
+    plans = [Plan.from_problem(p) for p in probs]
+    fields = [to_dev(p.rhs) for p in probs]
+    b = Batch(plans)
+    b.bind(fields)
+    b.launch(graph=True)
+    for p, f in zip(probs, fields):
+        single, _ = gpu_solve(p)
+        assert np.array_equal(to_host(f), single)
+    b.close()
+    for pl in plans:
+        pl.close()
+    plan.close()
