@@ -217,7 +217,11 @@ typedef struct poisson_request_info {
 
 /* slots: streams (1..64); hbm_budget: bytes (0 = 80 % of the device's free
  * memory now); max_plans: plans kept when idle (least recently used evicted).
- * Uses the current device.  NULL on error. */
+ * A cached plan holds only its tables (a few values per grid line): refined
+ * solves run on refinement workspace owned by their slot, grown to the
+ * largest refined request the slot has run and freed by server_destroy, so
+ * serving itself frees no device memory.  Uses the current device.  NULL on
+ * error. */
 poisson_server* server_create(int slots, size_t hbm_budget, int max_plans);
 
 /* Queue one solve (arguments as plan_create, plus precision mode, tolerance and

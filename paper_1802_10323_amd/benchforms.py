@@ -90,7 +90,8 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
              "graph": lambda: B.launch(graph=True)}
     ms = {}
     results = {}
-    for name, fn in forms.items():
+
+    def measure(name, fn):
         for _ in range(warmup):
             refill()
             fn()
@@ -103,11 +104,33 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
         fn()
         torch.cuda.synchronize()
         results[name] = [w.clone() for w in work[:8]]
+
+    for name, fn in forms.items():
+        measure(name, fn)
     same = all(torch.equal(a, b) for name in ("batch", "graph")
                for a, b in zip(results[name], results["single"]))
+    # autotuner: time every kernel variant on each instance's shape, keep the
+    # fastest per length and layout, rebuild the job tables, measure again
+    t0 = time.perf_counter()
+    for pl, w in zip(plans, work):
+        pl.autotune(w, reps=3)
+    tune_s = time.perf_counter() - t0
+    B.bind(work)
+    measure("single_tuned", singles)
+    measure("graph_tuned", lambda: B.launch(graph=True))
+    same = same and all(torch.equal(a, b) for a, b in zip(results["graph_tuned"],
+                                                           results["single_tuned"]))
+    from . import tuned_variant
+    chosen = {}
+    for n in (64, 96, 128, 192, 256):
+        chosen[str(n)] = {"transform_strided": tuned_variant(0, n, 0),
+                          "transform_contiguous": tuned_variant(0, n, 1),
+                          "elimination_strided": tuned_variant(1, n, 0),
+                          "elimination_contiguous": tuned_variant(1, n, 1)}
     log(f"[forms] batch {count} instances ({points / 1e6:.1f} M points): one by one "
         f"{ms['single']:.3f} ms, batched {ms['batch']:.3f} ms, graph {ms['graph']:.3f} ms; "
-        f"bitwise equal to single solves: {same}")
+        f"autotuned ({tune_s:.1f} s): one by one {ms['single_tuned']:.3f} ms, graph "
+        f"{ms['graph_tuned']:.3f} ms; bitwise equal to single solves: {same}")
     B.close()
     for pl in plans:
         pl.close()
@@ -116,6 +139,11 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
             "graph_ms": round(ms["graph"], 4),
             "graph_points_per_s": points / (ms["graph"] * 1e-3),
             "speedup_vs_single": round(ms["single"] / ms["graph"], 4),
+            "autotune_s": round(tune_s, 2),
+            "single_tuned_ms": round(ms["single_tuned"], 4),
+            "graph_tuned_ms": round(ms["graph_tuned"], 4),
+            "graph_tuned_points_per_s": points / (ms["graph_tuned"] * 1e-3),
+            "tuned_variants": chosen,
             "bitwise_equal_to_single": bool(same)}
 
 

@@ -153,6 +153,7 @@ struct poisson_plan {
   int max_iters = 8;
   double* f64 = nullptr;       // FP64 copy of f
   float* e32 = nullptr;        // FP32 residual / correction
+  bool ws_external = false;    // f64 / e32 lent by the owner (a server slot), not freed here
   double* stats = nullptr;     // device reduction slots
   double* stats_host = nullptr;
   size_t ws_bytes = 0;
@@ -717,8 +718,9 @@ extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double d
 }
 
 static void free_workspace(poisson_plan* p) {
-  if (p->f64) (void)hipFree(p->f64);
-  if (p->e32) (void)hipFree(p->e32);
+  if (p->f64 && !p->ws_external) (void)hipFree(p->f64);
+  if (p->e32 && !p->ws_external) (void)hipFree(p->e32);
+  p->ws_external = false;
   if (p->stats) (void)hipFree(p->stats);
   if (p->stats_host) (void)hipHostFree(p->stats_host);
   p->f64 = nullptr;
@@ -792,6 +794,33 @@ extern "C" int plan_set_precision(poisson_plan* p, int mode, double tol, int max
   return POISSON_OK;
 }
 
+
+// FP32 + refinement on workspace lent by the caller (f64: N doubles, e32: N
+// floats, valid while the plan's solves run); only the small reduction
+// slots are the plan's own.
+static int plan_refine_on(poisson_plan* p, double tol, int max_iters, double* f64, float* e32) {
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(POISSON_EINVAL, "tol must be finite and > 0");
+  if (max_iters < 1 || max_iters > 64) return fail(POISSON_EINVAL, "max_iters must be in [1, 64]");
+  if (p->f64 && !p->ws_external) {
+    (void)hipFree(p->f64);
+    (void)hipFree(p->e32);
+  }
+  if (!p->stats) {
+    if (hipMalloc(&p->stats, REFINE_STAT_SLOTS * sizeof(double)) != hipSuccess ||
+        hipHostMalloc(&p->stats_host, REFINE_STAT_SLOTS * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      free_workspace(p);
+      return fail(POISSON_ENOMEM, "refinement status allocation failed");
+    }
+  }
+  p->f64 = f64;
+  p->e32 = e32;
+  p->ws_external = true;
+  p->ws_bytes = REFINE_STAT_SLOTS * sizeof(double);
+  p->tol = tol;
+  p->max_iters = max_iters;
+  p->mode = POISSON_FP32_REFINED;
+  return POISSON_OK;
+}
 
 static int solve_refined(poisson_plan* p, double* rhs, hipStream_t st);
 

@@ -10,8 +10,9 @@
 // is observed through one event per slot.  Plans (device tables and
 // twiddles) are kept in a cache keyed by the problem and reused: an FP64
 // plan only reads its tables and is shared by concurrent requests; a
-// refined plan owns a workspace and serves one request at a time (the cache
-// holds as many copies as are in use at once).
+// refined plan serves one request at a time (the cache holds as many copies
+// as are in use at once) and runs on the refinement workspace of the slot
+// it was admitted to, so a cached plan holds only its small tables.
 //
 // Included by poisson.hip (uses its error reporting and plan internals).
 #pragma once
@@ -83,6 +84,14 @@ struct poisson_server {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
   std::vector<long long> slot_req;
+  // refinement workspace of each slot (FP64 f and FP32 residual), grown to
+  // the largest refined request it has run; replaced buffers are released
+  // only at destruction, so serving never frees device memory (a free waits
+  // for the whole device)
+  std::vector<double*> ws_f64;
+  std::vector<float*> ws_e32;
+  std::vector<size_t> ws_points;
+  std::vector<void*> retired;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<long long> queue;
@@ -129,11 +138,6 @@ static poisson_plan* server_acquire(poisson_server* S, ServerRequest& r) {
   poisson_plan* p = plan_create(r.dims[0], r.dims[1], r.dims[2], r.dx, r.dy, r.dz.data(), r.bc[0],
                                 r.bc[1], r.bc[2]);
   if (!p) return nullptr;
-  if (r.precision == POISSON_FP32_REFINED &&
-      plan_set_precision(p, POISSON_FP32_REFINED, r.tol, r.max_iters)) {
-    plan_destroy(p);
-    return nullptr;
-  }
   std::vector<CachedPlan>& w = S->cache[key];   // (eviction may have rehashed nothing: std::map)
   w.push_back(CachedPlan{p, 1, now_s()});
   ++S->nplans;
@@ -200,7 +204,24 @@ static void server_loop(poisson_server* S) {
         continue;
       }
       if (r.precision == POISSON_FP32_REFINED) {
-        const int rc = plan_set_precision(r.plan, POISSON_FP32_REFINED, r.tol, r.max_iters);
+        const size_t N = (size_t)r.dims[0] * r.dims[1] * r.dims[2];
+        int rc = POISSON_OK;
+        if (S->ws_points[slot] < N) {
+          double* f = nullptr;
+          float* e = nullptr;
+          if (hipMalloc(&f, N * sizeof(double)) != hipSuccess ||
+              hipMalloc(&e, N * sizeof(float)) != hipSuccess) {
+            if (f) S->retired.push_back(f);
+            rc = fail(POISSON_ENOMEM, "refinement workspace of %zu points", N);
+          } else {
+            if (S->ws_f64[slot]) S->retired.push_back(S->ws_f64[slot]);
+            if (S->ws_e32[slot]) S->retired.push_back(S->ws_e32[slot]);
+            S->ws_f64[slot] = f;
+            S->ws_e32[slot] = e;
+            S->ws_points[slot] = N;
+          }
+        }
+        if (!rc) rc = plan_refine_on(r.plan, r.tol, r.max_iters, S->ws_f64[slot], S->ws_e32[slot]);
         if (rc) { server_release(S, r); server_finish(S, r, rc, g_msg); continue; }
       }
       r.t_start = now_s();
@@ -251,6 +272,9 @@ extern "C" poisson_server* server_create(int slots, size_t hbm_budget, int max_p
     S->streams.push_back(st);
     S->events.push_back(ev);
     S->slot_req.push_back(-1);
+    S->ws_f64.push_back(nullptr);
+    S->ws_e32.push_back(nullptr);
+    S->ws_points.push_back(0);
   }
   S->worker = std::thread(server_loop, S);
   return S;
@@ -334,6 +358,9 @@ extern "C" void server_destroy(poisson_server* S) {
   if (S->worker.joinable()) S->worker.join();
   for (auto& kv : S->cache)
     for (CachedPlan& c : kv.second) plan_destroy(c.plan);
+  for (double* f : S->ws_f64) if (f) (void)hipFree(f);
+  for (float* e : S->ws_e32) if (e) (void)hipFree(e);
+  for (void* x : S->retired) (void)hipFree(x);
   for (auto x : S->streams) (void)hipStreamDestroy(x);
   for (auto x : S->events) (void)hipEventDestroy(x);
   delete S;

@@ -280,7 +280,7 @@ class Server:
     concurrently on the device.  Fields are solved in place and must stay
     alive until ``wait`` returns for them (this object keeps a reference)."""
 
-    def __init__(self, slots=8, hbm_budget=0, max_plans=64):
+    def __init__(self, slots=8, hbm_budget=0, max_plans=4096):
         L = lib()
         h = L.server_create(int(slots), int(hbm_budget), int(max_plans))
         if not h:
