@@ -92,7 +92,8 @@ __device__ __noinline__ void batch_tri_item(unsigned char* smem, const TriFastAr
   using L = TriFastLayout<T, RPC, P>;
   static_assert(L::NT == 512, "the batched elimination kernel runs 512-thread blocks");
   const lptr<T> lds = as_lds(reinterpret_cast<T*>(smem));
-  const lptr<T> coef = lds + L::TILE;
+  const lptr<double> coef =
+      as_lds(reinterpret_cast<double*>(smem + tri_fast_coef_offset<T, RPC, P>()));
   if (loaded != job) {
     tri_fast_coefs<T, RPC, P>(coef, A, tid);
     loaded = job;

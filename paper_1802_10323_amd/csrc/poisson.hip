@@ -437,12 +437,13 @@ static TriFastArgs<T> tri_fast_args(const poisson_plan* p, T* data, const double
   a.periodic = p->s_periodic;
   a.singular = p->singular;
   a.nu = p->nu;
-  const T* tri = reinterpret_cast<const T*>(p->dtab + (sizeof(T) == 8 ? p->off_tri_d : p->off_tri_f));
+  // FP64 tables for both field precisions (the recurrences run in FP64)
+  const double* tri = reinterpret_cast<const double*>(p->dtab + p->off_tri_d);
   a.a = tri;
   a.b = tri + L::N;
   a.c = tri + 2 * L::N;
   a.w = tri + 3 * L::N;
-  const T* lam = reinterpret_cast<const T*>(p->dtab + (sizeof(T) == 8 ? p->off_lam_d : p->off_lam_f));
+  const double* lam = reinterpret_cast<const double*>(p->dtab + p->off_lam_d);
   a.lamu = lam;
   a.lamv = lam + p->nu;
   a.skip = skip;

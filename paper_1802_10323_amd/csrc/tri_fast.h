@@ -30,12 +30,14 @@ struct TriFastArgs {
   int periodic;
   int singular;
   int nu;             // extent of u (contiguous layout: line index = u + nu v)
-  const T* a;         // [n]
-  const T* b;         // [n]
-  const T* c;         // [n]
-  const T* w;         // [n] cell widths along s (gauge weights)
-  const T* lamu;
-  const T* lamv;
+  // coefficient tables in FP64 for both field precisions: the recurrences
+  // run in FP64 registers (see tri_fast_line)
+  const double* a;    // [n]
+  const double* b;    // [n]
+  const double* c;    // [n]
+  const double* w;    // [n] cell widths along s (gauge weights)
+  const double* lamu;
+  const double* lamv;
   const double* skip;
 };
 
@@ -50,10 +52,16 @@ struct TriFastLayout {
   static_assert(RPC >= 2 && P >= 2 && P <= 64 && (P & (P - 1)) == 0, "unsupported chunking");
 };
 
+// LDS: the tile (field type), then the FP64 coefficient tables (4N).
+template <typename T, int RPC, int P>
+constexpr size_t tri_fast_coef_offset() {
+  using L = TriFastLayout<T, RPC, P>;
+  return ((size_t)L::TILE * sizeof(T) + 15) / 16 * 16;
+}
 template <typename T, int RPC, int P>
 constexpr size_t tri_fast_lds_bytes() {
   using L = TriFastLayout<T, RPC, P>;
-  return (size_t)(L::TILE + 4 * L::N) * sizeof(T);
+  return tri_fast_coef_offset<T, RPC, P>() + (size_t)4 * L::N * sizeof(double);
 }
 
 // 1/d: hardware reciprocal estimate refined by Newton steps.
@@ -201,31 +209,40 @@ __device__ __forceinline__ void pcr(T& l, T& u, T& r, int c, int gbase, int peri
 // Eliminate the line held by this lane's group: chunk c of the line, LDS
 // column col (row i at col[i * NLP]), coefficient tables ca/cb/cc/cw laid out
 // [row in chunk][chunk], shift mu, and the singular-line flags.
+//
+// The arithmetic is FP64 whatever the field type T: an FP32 field is widened
+// on reading and rounded once on writing.  Gauss elimination amplifies
+// rounding by up to the condition number of the line (about 1e5 for a
+// 512-point Dirichlet line with a small shift), so FP32 recurrences would
+// leave errors near 1e-2 and make iterative refinement slow; in FP64 the
+// FP32 solve is limited by its transforms instead.  The kernel is bound by
+// HBM traffic, which only the field type sets.
 template <typename T, int RPC, int P>
-__device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const T> coef, int c, T mu,
-                                           int sing, int wave_sing, int periodic) {
+__device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const double> coef, int c,
+                                              double mu, int sing, int wave_sing, int periodic) {
   using L = TriFastLayout<T, RPC, P>;
+  using R = double;
   constexpr int N = L::N;
-  const lptr<const T> ca = coef, cb = coef + N, cc = coef + 2 * N, cw = coef + 3 * N;
+  const lptr<const R> ca = coef, cb = coef + N, cc = coef + 2 * N, cw = coef + 3 * N;
   const int lane = threadIdx.x & 63;
   const int gbase = lane - c;
 
-  T x[RPC];
+  R x[RPC];
 #pragma unroll
-  for (int i = 0; i < RPC; ++i) x[i] = col[i * L::NLP];
+  for (int i = 0; i < RPC; ++i) x[i] = (R)col[i * L::NLP];
 
   if (wave_sing) {   // project the right-hand side of the null-space line
-    T sw = 0, swf = 0;
+    R sw = 0, swf = 0;
 #pragma unroll
     for (int i = 0; i < RPC; ++i) {
-      const T wi = cw[i * P + c];
+      const R wi = cw[i * P + c];
       sw += wi;
       swf += wi * x[i];
     }
-    sw = line_sum<T, P>(sw);
-    swf = line_sum<T, P>(swf);
+    sw = line_sum<R, P>(sw);
+    swf = line_sum<R, P>(swf);
     if (sing) {
-      const T mean = swf / sw;
+      const R mean = swf / sw;
 #pragma unroll
       for (int i = 0; i < RPC; ++i) x[i] -= mean;
     }
@@ -234,22 +251,22 @@ __device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const T> coef, i
   // phase 1: interior rows 0 .. RPC-2, top-down; x <- d (eliminated rhs),
   // qv = spike of the previous interface, cp = c / pivot
   constexpr int NI = RPC - 1;
-  T cp[NI], qv[NI];
-  T r = fast_rcp(cb[c] + mu);
+  R cp[NI], qv[NI];
+  R r = fast_rcp(cb[c] + mu);
   x[0] *= r;
   qv[0] = ca[c] * r;
   cp[0] = cc[c] * r;
 #pragma unroll
   for (int i = 1; i < NI; ++i) {
-    const T ai = ca[i * P + c], bi = cb[i * P + c], ci = cc[i * P + c];
+    const R ai = ca[i * P + c], bi = cb[i * P + c], ci = cc[i * P + c];
     r = fast_rcp(bi + mu - ai * cp[i - 1]);
     x[i] = (x[i] - ai * x[i - 1]) * r;
     qv[i] = -ai * qv[i - 1] * r;
     cp[i] = ci * r;
   }
-  // first-row values of y = T^-1 f, v = T^-1 (a e_first), w = T^-1 (c e_last)
-  const T yl = x[NI - 1], vl = qv[NI - 1], wl = cc[(NI - 1) * P + c] * r;
-  T yf = yl, vf = vl, wf = wl;
+  // first-row values of y = R^-1 f, v = R^-1 (a e_first), w = R^-1 (c e_last)
+  const R yl = x[NI - 1], vl = qv[NI - 1], wl = cc[(NI - 1) * P + c] * r;
+  R yf = yl, vf = vl, wf = wl;
 #pragma unroll
   for (int i = NI - 2; i >= 0; --i) {
     yf = x[i] - cp[i] * yf;
@@ -258,19 +275,19 @@ __device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const T> coef, i
   }
 
   // phase 2: interface row (last row of the chunk), reduced by PCR
-  T ae = ca[NI * P + c], be = cb[NI * P + c] + mu, ce = cc[NI * P + c], fe = x[NI];
+  R ae = ca[NI * P + c], be = cb[NI * P + c] + mu, ce = cc[NI * P + c], fe = x[NI];
   if (sing && c == P - 1) { ae = 0; be = 1; ce = 0; fe = 0; }   // pin x_{n-1} = 0
-  const T yf_n = group_rot<P, 1, true>(yf, gbase, c);
-  const T vf_n = group_rot<P, 1, true>(vf, gbase, c);
-  const T wf_n = group_rot<P, 1, true>(wf, gbase, c);
-  const T inv = fast_rcp(be - ae * wl - ce * vf_n);
-  T lq = -ae * vl * inv;
-  T uq = -ce * wf_n * inv;
-  T rq = (fe - ae * yl - ce * yf_n) * inv;
-  pcr<T, P, 1>(lq, uq, rq, c, gbase, periodic);
+  const R yf_n = group_rot<P, 1, true>(yf, gbase, c);
+  const R vf_n = group_rot<P, 1, true>(vf, gbase, c);
+  const R wf_n = group_rot<P, 1, true>(wf, gbase, c);
+  const R inv = fast_rcp(be - ae * wl - ce * vf_n);
+  R lq = -ae * vl * inv;
+  R uq = -ce * wf_n * inv;
+  R rq = (fe - ae * yl - ce * yf_n) * inv;
+  pcr<R, P, 1>(lq, uq, rq, c, gbase, periodic);
   // after the reduction the remaining couplings point back at this unknown
-  const T Ic = periodic ? rq / ((T)1 + lq + uq) : rq;
-  T Ip = group_rot<P, 1, false>(Ic, gbase, c);
+  const R Ic = periodic ? rq / ((R)1 + lq + uq) : rq;
+  R Ip = group_rot<P, 1, false>(Ic, gbase, c);
   if (!periodic && c == 0) Ip = 0;
 
   // phase 3: back substitution of the interior
@@ -280,29 +297,30 @@ __device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const T> coef, i
   for (int i = NI - 2; i >= 0; --i) x[i] = x[i] - Ip * qv[i] - cp[i] * x[i + 1];
 
   if (wave_sing) {   // gauge: zero width-weighted mean of the null-space line
-    T sw = 0, swx = 0;
+    R sw = 0, swx = 0;
 #pragma unroll
     for (int i = 0; i < RPC; ++i) {
-      const T wi = cw[i * P + c];
+      const R wi = cw[i * P + c];
       sw += wi;
       swx += wi * x[i];
     }
-    sw = line_sum<T, P>(sw);
-    swx = line_sum<T, P>(swx);
+    sw = line_sum<R, P>(sw);
+    swx = line_sum<R, P>(swx);
     if (sing) {
-      const T mean = swx / sw;
+      const R mean = swx / sw;
 #pragma unroll
       for (int i = 0; i < RPC; ++i) x[i] -= mean;
     }
   }
 #pragma unroll
-  for (int i = 0; i < RPC; ++i) col[i * L::NLP] = x[i];
+  for (int i = 0; i < RPC; ++i) col[i * L::NLP] = (T)x[i];
 }
 
 // Coefficients of the elimination axis into LDS, [row in chunk][chunk];
 // ends with a barrier.
 template <typename T, int RPC, int P>
-__device__ __forceinline__ void tri_fast_coefs(lptr<T> coef, const TriFastArgs<T>& A, int tid) {
+__device__ __forceinline__ void tri_fast_coefs(lptr<double> coef, const TriFastArgs<T>& A,
+                                               int tid) {
   using L = TriFastLayout<T, RPC, P>;
   constexpr int N = L::N;
   for (int k = tid; k < N; k += L::NT) {
@@ -319,7 +337,7 @@ __device__ __forceinline__ void tri_fast_coefs(lptr<T> coef, const TriFastArgs<T
 // One tile of lines of the launch described by A, with the coefficients in
 // LDS; ends with a barrier.
 template <typename T, int RPC, int P>
-__device__ __forceinline__ void tri_fast_tile(lptr<T> lds, lptr<const T> coef,
+__device__ __forceinline__ void tri_fast_tile(lptr<T> lds, lptr<const double> coef,
                                               const TriFastArgs<T>& A, int tile, int tid) {
   using L = TriFastLayout<T, RPC, P>;
   constexpr int N = L::N, NL = L::NL;
@@ -345,7 +363,7 @@ __device__ __forceinline__ void tri_fast_tile(lptr<T> lds, lptr<const T> coef,
   const bool valid = l < nlt && line_base(g, o, l) >= 0;
   int u = 0, v = 0;
   if (valid) line_coords(g, o, l, A.nu, u, v);
-  const T mu = valid ? A.lamu[u] + A.lamv[v] : (T)-1;
+  const double mu = valid ? A.lamu[u] + A.lamv[v] : -1.0;
   const bool sing = A.singular && valid && u == 0 && v == 0;
   const int wave_sing = __any(sing) ? 1 : 0;
   tri_fast_line<T, RPC, P>(col, coef, c, mu, sing ? 1 : 0, wave_sing, A.periodic);
@@ -362,7 +380,8 @@ void tri_fast_kernel(TriFastArgs<T> A) {
   if (A.skip && A.skip[0] != 0.0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const lptr<T> lds = as_lds(reinterpret_cast<T*>(smem_raw));
-  const lptr<T> coef = lds + L::TILE;
+  const lptr<double> coef =
+      as_lds(reinterpret_cast<double*>(smem_raw + tri_fast_coef_offset<T, RPC, P>()));
   const int tid = threadIdx.x;
   tri_fast_coefs<T, RPC, P>(coef, A, tid);
   const TileRange tr = xcd_tiles(A.g.ntiles);
