@@ -123,7 +123,9 @@ int solve_status(poisson_plan* plan, int* iters, double* last_update_rel);
 
 /* Solve `count` independent problems, plans[i] applied in place to rhs[i]
  * (DEVICE pointers), on `stream`.  FP64 plans only; plans must be distinct.
- * Same result per instance as solve(), bit for bit.  When every plan's lengths
+ * Same result per instance as solve() with the same kernel variants, bit for
+ * bit (batched launches use transform variants 0-3; against solve() with the
+ * staging transform, variant 4, results agree to rounding).  When every plan's lengths
  * have size-specialised kernels (batch_create), the solves run as one
  * persistent launch per stage over all instances and the call waits for
  * `stream` to complete (it frees its temporary job tables); otherwise the
@@ -165,23 +167,26 @@ void batch_destroy(poisson_batch* batch);
 
 /* ---- autotuner: kernel variants per length ----
  *
- * Each specialised length has several compiled variants: four for the
- * transforms (two tile shapes, lines per tile x threads per line, times two
- * FFT radix orders, radix 8 first or radix 4 first) and two for the
- * elimination (two chunkings, rows per chunk x chunks per line).  All give
- * the same result up to rounding.  The variant used for a length is chosen
- * per device, precision and layout (strided: the axis is y or z;
- * contiguous: x) from a process-wide table; variant 0 where nothing was
- * tuned.  Plans and batches read the table when they launch (batches when
- * they are bound). */
+ * Each specialised length has several compiled variants: for the
+ * transforms, variants 0-3 are two tile shapes (lines per tile x threads per
+ * line) times two FFT radix orders (radix 8 first or radix 4 first), and
+ * variant 4 (lengths 256 and 512 only) reads the next tile straight into LDS
+ * while the current one is transformed; for the elimination, two chunkings
+ * (rows per chunk x chunks per line).  All give the same result up to
+ * rounding.  The variant used for a length is chosen per device, precision
+ * and layout (strided: the axis is y or z; contiguous: x) from a
+ * process-wide table; where nothing was tuned, variant 4 for transform
+ * lengths 256 and 512 and variant 0 otherwise.  Plans and batches read the
+ * table when they launch (batches when they are bound; batches use
+ * variants 0-3 only). */
 
 /* Time every variant of this plan's kernels (both transformed axes and the
  * elimination, FP64 and FP32) on `scratch` (DEVICE, at least nx*ny*nz
  * doubles; overwritten), `reps` launches each after one warm-up, and record
  * the fastest in the table.  Synchronous (waits for `stream`).  report (HOST,
- * may be NULL): 2 x (4 + 4 + 2) doubles, per precision (FP64 first) the
- * average ms of variants 0-3 of t1, 0-3 of t2 (forward + backward pair) and
- * 0-1 of the elimination, -1 where the length has no variants. */
+ * may be NULL): 2 x (5 + 5 + 2) doubles, per precision (FP64 first) the
+ * average ms of variants 0-4 of t1, 0-4 of t2 (forward + backward pair) and
+ * 0-1 of the elimination, -1 where a variant does not apply. */
 int plan_autotune(poisson_plan* plan, double* scratch, int reps, hipStream_t stream, double* report);
 
 /* Variant in the table for kernel family 0 (transform) or 1 (elimination),

@@ -107,8 +107,14 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
 
     for name, fn in forms.items():
         measure(name, fn)
-    same = all(torch.equal(a, b) for name in ("batch", "graph")
-               for a, b in zip(results[name], results["single"]))
+
+    def max_rel(name, ref):
+        return max(float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+                   for a, b in zip(results[name], results[ref]))
+
+    # single solves use the staging transform where it is the default; the
+    # batched kernels have the synchronous variants: equal to rounding
+    diff = max(max_rel("batch", "single"), max_rel("graph", "single"))
     # autotuner: time every kernel variant on each instance's shape, keep the
     # fastest per length and layout, rebuild the job tables, measure again
     t0 = time.perf_counter()
@@ -118,8 +124,7 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
     B.bind(work)
     measure("single_tuned", singles)
     measure("graph_tuned", lambda: B.launch(graph=True))
-    same = same and all(torch.equal(a, b) for a, b in zip(results["graph_tuned"],
-                                                           results["single_tuned"]))
+    diff = max(diff, max_rel("graph_tuned", "single_tuned"))
     from . import tuned_variant
     chosen = {}
     for n in (64, 96, 128, 192, 256):
@@ -130,7 +135,7 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
     log(f"[forms] batch {count} instances ({points / 1e6:.1f} M points): one by one "
         f"{ms['single']:.3f} ms, batched {ms['batch']:.3f} ms, graph {ms['graph']:.3f} ms; "
         f"autotuned ({tune_s:.1f} s): one by one {ms['single_tuned']:.3f} ms, graph "
-        f"{ms['graph_tuned']:.3f} ms; bitwise equal to single solves: {same}")
+        f"{ms['graph_tuned']:.3f} ms; max relative difference to single solves {diff:.1e}")
     B.close()
     for pl in plans:
         pl.close()
@@ -144,7 +149,7 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
             "graph_tuned_ms": round(ms["graph_tuned"], 4),
             "graph_tuned_points_per_s": points / (ms["graph_tuned"] * 1e-3),
             "tuned_variants": chosen,
-            "bitwise_equal_to_single": bool(same)}
+            "max_rel_diff_vs_single": diff}
 
 
 def serve(log, count=400, warmup=50, seed=0, slots=8, load=0.8, sample=12):

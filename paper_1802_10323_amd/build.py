@@ -2,7 +2,8 @@
 
     python -m paper_1802_10323_amd.build
 
-produces ``paper_1802_10323_amd/libpoisson_hip.so`` from ``csrc/*.hip``.
+produces ``paper_1802_10323_amd/libpoisson_hip.so`` from the translation units
+in ``csrc/`` (objects in ``paper_1802_10323_amd/_build/``).
 """
 import os
 import subprocess
@@ -11,7 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpoisson_hip.so")
-SOURCES = [os.path.join(HERE, "csrc", "poisson.hip")]
+SOURCES = [os.path.join(HERE, "csrc", name)
+           for name in ("poisson.hip", "r2r_async.hip", "r2r_async_wide.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -25,15 +27,27 @@ FLAGS = [
 ]
 
 
-def build(verbose=False):
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *SOURCES, "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed with status {res.returncode}")
+        raise RuntimeError(f"hipcc failed with status {res.returncode}: {' '.join(cmd)}")
+
+
+def build(verbose=False):
+    """Compile every translation unit (in parallel) and link the library."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = [os.path.join(objdir, os.path.basename(src) + ".o") for src in SOURCES]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
+        list(pool.map(lambda so: _run([HIPCC, *compile_flags, "-c", so[0], "-o", so[1]], verbose),
+                      zip(SOURCES, objs)))
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,0 +1,56 @@
+// async_launch.h - entry into the asynchronous-staging transform kernels
+// (r2r_fast.h).  They are compiled in translation units of their own: the
+// register allocator treats a kernel differently depending on what else is
+// in its unit, and the FP64 length-512 DFT / DCT-IV kernels (which may use
+// up to 256 VGPRs) only avoid spills in a unit without the others
+// (r2r_async_wide.hip); the rest are in r2r_async.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "r2r_fast.h"
+
+namespace poisson_dev {
+
+// Launch the staging transform for complex length M (128 or 256), transform
+// type `kind` and direction `inverse`, arguments as for r2r_fast_kernel with
+// the tile shape of variant 0.  hipErrorInvalidValue if (M, kind) has no
+// instantiation.
+hipError_t async_transform_launch(const R2RFastArgs<double>& a, int M, int kind, int inverse,
+                                  hipStream_t stream);
+hipError_t async_transform_launch(const R2RFastArgs<float>& a, int M, int kind, int inverse,
+                                  hipStream_t stream);
+
+// The kernels of AsyncBudget<double, FastVar<256, 0>, kind>::WIDE
+// (r2r_async_wide.hip).
+hipError_t async_wide_launch(const R2RFastArgs<double>& a, int kind, int inverse,
+                             hipStream_t stream);
+
+// Blocks of a persistent launch of `fn` (512 threads, static LDS only): as
+// many as are resident at once, at most one per tile.
+inline int async_resident_blocks(const void* fn, long long ntiles) {
+  static std::mutex mu;
+  static std::vector<std::pair<std::pair<const void*, int>, int>> cache;   // (fn, device) -> blocks
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int blocks = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& e : cache)
+      if (e.first.first == fn && e.first.second == dev) blocks = e.second;
+  }
+  if (!blocks) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 512, 0) != hipSuccess) per_cu = 1;
+    blocks = cus * std::max(per_cu, 1);
+    std::lock_guard<std::mutex> lk(mu);
+    cache.push_back({{fn, dev}, blocks});
+  }
+  return (int)std::min<long long>(ntiles, blocks);
+}
+
+}  // namespace poisson_dev

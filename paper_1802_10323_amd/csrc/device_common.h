@@ -180,6 +180,16 @@ __device__ __forceinline__ lptr<T> as_lds(T* p) {
   return (lptr<T>)p;
 }
 
+// Barrier for hand-offs through LDS between the waves of a block.  Unlike
+// __syncthreads() it orders LDS accesses only: the wave waits for its own LDS
+// operations, not for its global loads and stores, so a tile's stores (and
+// reads of a next tile already issued) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // floor(j / d) for j, d < 2^16 with magic = ceil(2^32 / d), d > 1.
 __device__ __forceinline__ int fast_div(int j, unsigned magic) {
   return (int)__umulhi((unsigned)j, magic);

@@ -23,6 +23,7 @@
 #include "tridiag_kernel.h"
 #include "tri_fast.h"
 #include "batch_kernels.h"
+#include "async_launch.h"
 #include "refine_kernels.h"
 
 using namespace poisson_dev;
@@ -172,7 +173,8 @@ struct TriCfg {
   static constexpr int RPC = RPC_, P = P_;
 };
 
-static constexpr int kFastVariants = 4;   // transform: tile shape x radix order
+static constexpr int kFastVariants = 5;   // transform: tile shape x radix order, + asynchronous staging
+static constexpr int kAsyncVariant = 4;
 static constexpr int kTriVariants = 2;    // elimination: two chunkings per length
 
 // Call f(FastVar<M, V>{}) for a specialised transform length; -1 otherwise.
@@ -212,12 +214,18 @@ static long long with_tri_cfg(int n, int V, F&& f) {
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int, int, int>, int> g_tune;
 
+// Variant used where nothing was tuned: the asynchronous-staging transform
+// for the lengths it is compiled for, else variant 0.
+static int default_choice(int family, int n) {
+  return family == 0 && (n == 128 || n == 256) ? kAsyncVariant : 0;
+}
+
 static int tuned_choice(int family, int bytes, int n, int layout) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   const auto it = g_tune.find(std::make_tuple(dev, family, bytes, n, layout));
-  return it == g_tune.end() ? 0 : it->second;
+  return it == g_tune.end() ? default_choice(family, n) : it->second;
 }
 
 static void set_tuned_choice(int family, int bytes, int n, int layout, int v) {
@@ -236,7 +244,7 @@ static int lds_setup_once() {
     ALLOW((r2r_kernel<double, R2R_EMAX_D, R2R_NT>));
     ALLOW((r2r_kernel<float, R2R_EMAX_F, R2R_NT>));
     for (int M : {16, 32, 48, 64, 96, 128, 192, 256})
-      for (int V = 0; V < kFastVariants; ++V)
+      for (int V = 0; V < 4; ++V)
         with_fast_cfg(M, V, [&](auto cfg) {
           using C = decltype(cfg);
           ALLOW((r2r_fast_kernel<double, C>));
@@ -372,10 +380,38 @@ static int launch_fast(const poisson_plan* p, const AxisTables& A, int inverse, 
   return POISSON_OK;
 }
 
+// Asynchronous-staging form (r2r_fast.h) for lengths 2M, M in {128, 256};
+// -1 if it does not apply (length, or strided rows that do not split into
+// 16-byte pieces).
+template <typename T>
+static int launch_async(const poisson_plan* p, const AxisTables& A, int inverse, T* data,
+                        hipStream_t st, const double* skip) {
+  if (A.m != 128 && A.m != 256) return -1;
+  if (A.axis != 0 && p->dims[0] % (int)(16 / sizeof(T)) != 0) return -1;
+  const R2RFastArgs<T> a = A.m == 128 ? fast_args<T, FastVar<128, 0>>(p, A, inverse, data, skip)
+                                       : fast_args<T, FastVar<256, 0>>(p, A, inverse, data, skip);
+  const hipError_t e = async_transform_launch(a, A.m, A.kind, inverse, st);
+  if (e != hipSuccess)
+    return fail(POISSON_EHIP, "staging transform launch: %s", hipGetErrorString(e));
+  return POISSON_OK;
+}
+
+// True if the asynchronous-staging form applies to axis A in type T.
+template <typename T>
+static bool async_applies(const poisson_plan* p, const AxisTables& A) {
+  return (A.m == 128 || A.m == 256) &&
+         (A.axis == 0 || p->dims[0] % (int)(16 / sizeof(T)) == 0);
+}
+
 // Specialised transform of axis A in variant V (-1: the length has none).
 template <typename T>
 static int launch_fast_variant(const poisson_plan* p, const AxisTables& A, int V, int inverse,
                                T* data, hipStream_t st, const double* skip) {
+  if (V == kAsyncVariant) {
+    const int rc = launch_async<T>(p, A, inverse, data, st, skip);
+    if (rc != -1) return rc;
+    V = 0;
+  }
   return (int)with_fast_cfg(A.m, V, [&](auto cfg) {
     return (long long)launch_fast<T, decltype(cfg)>(p, A, inverse, data, st, skip);
   });
@@ -974,6 +1010,7 @@ static void batch_jobs(poisson_batch* b, double* const* rhs, std::vector<char>& 
         BatchR2RJob<double> J{};
         J.M = A.m;
         J.V = tuned_choice(0, sizeof(double), A.m, A.axis == 0);
+        if (J.V >= 4) J.V = 0;   // the batched kernel has the synchronous variants
         with_fast_cfg(J.M, J.V, [&](auto cfg) {
           using C = decltype(cfg);
           J.a = fast_args<double, C>(p, A, kStepInverse[k], data, nullptr);
@@ -1175,6 +1212,7 @@ static int autotune_typed(poisson_plan* p, double* scratch, int reps, hipStream_
     int best = 0;
     double best_ms = 1e300;
     for (int V = 0; V < kFastVariants; ++V) {
+      if (V == kAsyncVariant && !async_applies<T>(p, A)) continue;
       if ((rc = reset())) return rc;
       // forward then backward: the field keeps its size over the repetitions
       const double ms = time_launches(st, reps, [&]() -> int {

@@ -152,7 +152,7 @@ __device__ __forceinline__ void stc(lptr<cplx<T>> p, int i, cplx<T> v) {
 
 // One Stockham pass of radix R (Ns = NS) over the tile, in place in LDS.
 template <typename T, typename C, int R, int NS, bool FWD>
-__device__ __noinline__ void fast_pass(lptr<T> lds, lptr<const cplx<T>> tw, int l, int q) {
+__device__ __forceinline__ void fast_pass_body(lptr<T> lds, lptr<const cplx<T>> tw, int l, int q) {
   using L = FastLayout<T, C>;
   [[maybe_unused]] constexpr int M = L::M;
   constexpr int B = M / R;                       // butterflies per line
@@ -179,7 +179,7 @@ __device__ __noinline__ void fast_pass(lptr<T> lds, lptr<const cplx<T>> tw, int 
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int s = 0; s < SB; ++s) {
     const int j = q + s * L::QT;
@@ -195,25 +195,37 @@ __device__ __noinline__ void fast_pass(lptr<T> lds, lptr<const cplx<T>> tw, int 
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
-template <typename T, typename C, bool FWD, int P>
+template <typename T, typename C, int R, int NS, bool FWD>
+__device__ __noinline__ void fast_pass_call(lptr<T> lds, lptr<const cplx<T>> tw, int l, int q) {
+  fast_pass_body<T, C, R, NS, FWD>(lds, tw, l, q);
+}
+
+// INL: inline the stage (async kernel) or call its non-inlined copy
+template <typename T, typename C, int R, int NS, bool FWD, bool INL = false>
+__device__ __forceinline__ void fast_pass(lptr<T> lds, lptr<const cplx<T>> tw, int l, int q) {
+  if constexpr (INL) fast_pass_body<T, C, R, NS, FWD>(lds, tw, l, q);
+  else fast_pass_call<T, C, R, NS, FWD>(lds, tw, l, q);
+}
+
+template <typename T, typename C, bool FWD, int P, bool INL = false>
 __device__ __forceinline__ void fast_passes(lptr<T> lds, lptr<const cplx<T>> tw, int l, int q) {
   using L = FastLayout<T, C>;
   [[maybe_unused]] constexpr int M = L::M;
   if constexpr (P < L::plan.count) {
     constexpr int R = L::plan.r[P];
     constexpr int NS = plan_ns(L::plan, P);
-    fast_pass<T, C, R, NS, FWD>(lds, tw, l, q);
-    fast_passes<T, C, FWD, P + 1>(lds, tw, l, q);
+    fast_pass<T, C, R, NS, FWD, INL>(lds, tw, l, q);
+    fast_passes<T, C, FWD, P + 1, INL>(lds, tw, l, q);
   }
 }
 
 // Tile load: global -> LDS rows with the input permutation of the type.
 // All of a thread's loads are issued before its first LDS write.
 template <typename T, typename C>
-__device__ __noinline__ void fast_load(lptr<T> lds, gptr<const T> data, long long base,
+__device__ __forceinline__ void fast_load_body(lptr<T> lds, gptr<const T> data, long long base,
                                        long long sp, int layout, int lines, int kind,
                                        int inverse, int l, int q, int tid) {
   using L = FastLayout<T, C>;
@@ -248,9 +260,25 @@ __device__ __noinline__ void fast_load(lptr<T> lds, gptr<const T> data, long lon
   }
 }
 
+template <typename T, typename C>
+__device__ __noinline__ void fast_load_call(lptr<T> lds, gptr<const T> data, long long base,
+                                       long long sp, int layout, int lines, int kind,
+                                       int inverse, int l, int q, int tid) {
+  fast_load_body<T, C>(lds, data, base, sp, layout, lines, kind, inverse, l, q, tid);
+}
+
+// INL: inline the stage (async kernel) or call its non-inlined copy
+template <typename T, typename C, bool INL = false>
+__device__ __forceinline__ void fast_load(lptr<T> lds, gptr<const T> data, long long base,
+                                       long long sp, int layout, int lines, int kind,
+                                       int inverse, int l, int q, int tid) {
+  if constexpr (INL) fast_load_body<T, C>(lds, data, base, sp, layout, lines, kind, inverse, l, q, tid);
+  else fast_load_call<T, C>(lds, data, base, sp, layout, lines, kind, inverse, l, q, tid);
+}
+
 // Tile store: LDS rows -> global with the output permutation, sign, scale.
 template <typename T, typename C>
-__device__ __noinline__ void fast_store(lptr<const T> lds, gptr<T> data, long long base,
+__device__ __forceinline__ void fast_store_body(lptr<const T> lds, gptr<T> data, long long base,
                                         long long sp, int layout, int lines, int kind,
                                         int inverse, T scale, int l, int q, int tid) {
   using L = FastLayout<T, C>;
@@ -287,9 +315,25 @@ __device__ __noinline__ void fast_store(lptr<const T> lds, gptr<T> data, long lo
   }
 }
 
+template <typename T, typename C>
+__device__ __noinline__ void fast_store_call(lptr<const T> lds, gptr<T> data, long long base,
+                                        long long sp, int layout, int lines, int kind,
+                                        int inverse, T scale, int l, int q, int tid) {
+  fast_store_body<T, C>(lds, data, base, sp, layout, lines, kind, inverse, scale, l, q, tid);
+}
+
+// INL: inline the stage (async kernel) or call its non-inlined copy
+template <typename T, typename C, bool INL = false>
+__device__ __forceinline__ void fast_store(lptr<const T> lds, gptr<T> data, long long base,
+                                        long long sp, int layout, int lines, int kind,
+                                        int inverse, T scale, int l, int q, int tid) {
+  if constexpr (INL) fast_store_body<T, C>(lds, data, base, sp, layout, lines, kind, inverse, scale, l, q, tid);
+  else fast_store_call<T, C>(lds, data, base, sp, layout, lines, kind, inverse, scale, l, q, tid);
+}
+
 // DCT-IV pre-twiddle (in place: each thread scales its own elements).
 template <typename T, typename C>
-__device__ __noinline__ void fast_iv_pre(lptr<T> lds, lptr<const cplx<T>> pre, int l, int q) {
+__device__ __forceinline__ void fast_iv_pre_body(lptr<T> lds, lptr<const cplx<T>> pre, int l, int q) {
   using L = FastLayout<T, C>;
   [[maybe_unused]] constexpr int M = L::M;
 #pragma unroll
@@ -300,12 +344,24 @@ __device__ __noinline__ void fast_iv_pre(lptr<T> lds, lptr<const cplx<T>> pre, i
     lds[(2 * j) * L::NLP + l] = z.re;
     lds[(2 * j + 1) * L::NLP + l] = z.im;
   }
-  __syncthreads();
+  lds_barrier();
+}
+
+template <typename T, typename C>
+__device__ __noinline__ void fast_iv_pre_call(lptr<T> lds, lptr<const cplx<T>> pre, int l, int q) {
+  fast_iv_pre_body<T, C>(lds, pre, l, q);
+}
+
+// INL: inline the stage (async kernel) or call its non-inlined copy
+template <typename T, typename C, bool INL = false>
+__device__ __forceinline__ void fast_iv_pre(lptr<T> lds, lptr<const cplx<T>> pre, int l, int q) {
+  if constexpr (INL) fast_iv_pre_body<T, C>(lds, pre, l, q);
+  else fast_iv_pre_call<T, C>(lds, pre, l, q);
 }
 
 // DCT-IV post-step: V_k = Z_k e^{-i pi k/n}; y_2k = 2 Re V_k, y_{n-1-2k} = -2 Im V_k.
 template <typename T, typename C>
-__device__ __noinline__ void fast_iv_post(lptr<T> lds, lptr<const cplx<T>> post, int l, int q) {
+__device__ __forceinline__ void fast_iv_post_body(lptr<T> lds, lptr<const cplx<T>> post, int l, int q) {
   using L = FastLayout<T, C>;
   [[maybe_unused]] constexpr int M = L::M;
   constexpr int N = L::N;
@@ -315,20 +371,32 @@ __device__ __noinline__ void fast_iv_post(lptr<T> lds, lptr<const cplx<T>> post,
     const int k = q + s * L::QT;
     V[s] = cmul(cplx<T>{lds[(2 * k) * L::NLP + l], lds[(2 * k + 1) * L::NLP + l]}, ldc(post, k));
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int s = 0; s < L::E; ++s) {
     const int k = q + s * L::QT;
     lds[(2 * k) * L::NLP + l] = (T)2 * V[s].re;
     lds[(N - 1 - 2 * k) * L::NLP + l] = (T)-2 * V[s].im;
   }
-  __syncthreads();
+  lds_barrier();
+}
+
+template <typename T, typename C>
+__device__ __noinline__ void fast_iv_post_call(lptr<T> lds, lptr<const cplx<T>> post, int l, int q) {
+  fast_iv_post_body<T, C>(lds, post, l, q);
+}
+
+// INL: inline the stage (async kernel) or call its non-inlined copy
+template <typename T, typename C, bool INL = false>
+__device__ __forceinline__ void fast_iv_post(lptr<T> lds, lptr<const cplx<T>> post, int l, int q) {
+  if constexpr (INL) fast_iv_post_body<T, C>(lds, post, l, q);
+  else fast_iv_post_call<T, C>(lds, post, l, q);
 }
 
 // Inverse P/NN/DD: rebuild the length-M spectrum
 // Z'_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) e^{2 pi i k/n}.
 template <typename T, typename C>
-__device__ __noinline__ void fast_combine(lptr<T> lds, lptr<const cplx<T>> split,
+__device__ __forceinline__ void fast_combine_body(lptr<T> lds, lptr<const cplx<T>> split,
                                           lptr<const cplx<T>> quarter, int kind, int l, int q) {
   using L = FastLayout<T, C>;
   [[maybe_unused]] constexpr int M = L::M;
@@ -363,7 +431,7 @@ __device__ __noinline__ void fast_combine(lptr<T> lds, lptr<const cplx<T>> split
       zj[s] = {s2.re - d2.im, s2.im + d2.re};
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int s = 0; s < SP; ++s) {
     const int k = q + s * L::QT;
@@ -377,13 +445,27 @@ __device__ __noinline__ void fast_combine(lptr<T> lds, lptr<const cplx<T>> split
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
+}
+
+template <typename T, typename C>
+__device__ __noinline__ void fast_combine_call(lptr<T> lds, lptr<const cplx<T>> split,
+                                          lptr<const cplx<T>> quarter, int kind, int l, int q) {
+  fast_combine_body<T, C>(lds, split, quarter, kind, l, q);
+}
+
+// INL: inline the stage (async kernel) or call its non-inlined copy
+template <typename T, typename C, bool INL = false>
+__device__ __forceinline__ void fast_combine(lptr<T> lds, lptr<const cplx<T>> split,
+                                          lptr<const cplx<T>> quarter, int kind, int l, int q) {
+  if constexpr (INL) fast_combine_body<T, C>(lds, split, quarter, kind, l, q);
+  else fast_combine_call<T, C>(lds, split, quarter, kind, l, q);
 }
 
 // Forward P/NN/DD: even/odd split of the FFT into the real DFT X_k of the
 // (reordered) input and the stored coefficients (see r2r_kernel.h).
 template <typename T, typename C>
-__device__ __noinline__ void fast_split(lptr<T> lds, lptr<const cplx<T>> split,
+__device__ __forceinline__ void fast_split_body(lptr<T> lds, lptr<const cplx<T>> split,
                                         lptr<const cplx<T>> quarter, int kind, int l, int q) {
   using L = FastLayout<T, C>;
   [[maybe_unused]] constexpr int M = L::M;
@@ -406,7 +488,7 @@ __device__ __noinline__ void fast_split(lptr<T> lds, lptr<const cplx<T>> split,
       Y[s] = cconj(csub(E, wO));
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int s = 0; s < SP; ++s) {
     const int k = q + s * L::QT;
@@ -437,7 +519,21 @@ __device__ __noinline__ void fast_split(lptr<T> lds, lptr<const cplx<T>> split,
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
+}
+
+template <typename T, typename C>
+__device__ __noinline__ void fast_split_call(lptr<T> lds, lptr<const cplx<T>> split,
+                                        lptr<const cplx<T>> quarter, int kind, int l, int q) {
+  fast_split_body<T, C>(lds, split, quarter, kind, l, q);
+}
+
+// INL: inline the stage (async kernel) or call its non-inlined copy
+template <typename T, typename C, bool INL = false>
+__device__ __forceinline__ void fast_split(lptr<T> lds, lptr<const cplx<T>> split,
+                                        lptr<const cplx<T>> quarter, int kind, int l, int q) {
+  if constexpr (INL) fast_split_body<T, C>(lds, split, quarter, kind, l, q);
+  else fast_split_call<T, C>(lds, split, quarter, kind, l, q);
 }
 
 // ---------------------------------------------------------------- kernel
@@ -479,7 +575,7 @@ __device__ __forceinline__ void fast_twiddles(const FastLds<T, C>& S, const R2RF
     for (int i = tid; i < L::SPLIT; i += NT) stc(S.twa, i, ldg(A.tw_split, i));
     for (int i = tid; i <= M; i += NT) stc(S.twa, L::SPLIT + i, ldg(A.tw_quarter, i));
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // One tile of lines of the launch described by A, with the twiddles of its
@@ -510,7 +606,7 @@ __device__ __forceinline__ void fast_tile(const FastLds<T, C>& S, const R2RFastA
   }
   fast_load<T, C>(S.tile, as_global((const T*)A.data), base, g.sp, g.layout, lines, kind, inverse,
                   l, q, tid);
-  __syncthreads();
+  lds_barrier();
 
   if (ivk) fast_iv_pre<T, C>(S.tile, tw_a, l, q);
   else if (inverse) fast_combine<T, C>(S.tile, tw_a, tw_b, kind, l, q);
@@ -523,7 +619,7 @@ __device__ __forceinline__ void fast_tile(const FastLds<T, C>& S, const R2RFastA
 
   fast_store<T, C>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind, inverse,
                    A.scale, l, q, tid);
-  __syncthreads();
+  lds_barrier();
 }
 
 template <typename T, typename C>
@@ -537,5 +633,197 @@ void r2r_fast_kernel(R2RFastArgs<T> A) {
   const TileRange tr = xcd_tiles(A.g.ntiles);
   for (int tile = tr.first; tile < tr.end; tile += tr.step) fast_tile<T, C>(S, A, tile, tid);
 }
+
+// ---------------------------------------------------------------- async form
+// The same transform with the next tile's HBM reads in flight while the
+// current tile is transformed: global_load_lds moves the next tile straight
+// into a staging area of LDS (no registers involved), the tile is copied
+// from there into its permuted place at the start of its turn.  Needs LDS
+// for the stage, the tile and the twiddles (one block per CU), 16-byte
+// pieces that never straddle a line (strided axes: even nx in FP64, nx a
+// multiple of 4 in FP32).
+
+template <typename T, typename C>
+struct AsyncLayout {
+  using L = FastLayout<T, C>;
+  static constexpr int EPL = 16 / (int)sizeof(T);            // elements per 16-byte piece
+  static constexpr int STAGE = L::NL * L::N;                   // staged elements
+  static constexpr int CHUNKS = STAGE * (int)sizeof(T) / 1024; // 1 KiB per wave instruction
+  static constexpr int PER_WAVE = CHUNKS / (L::NT / 64);
+  static constexpr int LANES_PER_ROW = L::NL / EPL;             // strided: pieces per row
+  static constexpr int ROWS_PER_CHUNK = 64 / LANES_PER_ROW;
+  static_assert(CHUNKS % (L::NT / 64) == 0, "stage chunks split evenly over the waves");
+  static_assert(L::NL % EPL == 0 && 64 % LANES_PER_ROW == 0, "rows of whole pieces");
+};
+
+template <typename T, typename C>
+constexpr size_t async_lds_bytes() {
+  return (size_t)AsyncLayout<T, C>::STAGE * sizeof(T) + fast_lds_bytes<T, C>();
+}
+
+// One 16-byte piece per lane from global memory straight into LDS: lane i
+// of the wave writes bytes [16 i, 16 i + 16) after `lds_addr` (uniform).
+// Written as inline assembly so that the compiler does not treat it as an
+// LDS write that every later LDS access must wait for (it cannot tell the
+// stage from the tile); the kernel waits for it explicitly (s_waitcnt)
+// before reading the stage.
+__device__ __forceinline__ void lds_dma16(const void* gaddr, unsigned lds_addr) {
+  asm volatile(
+      "s_mov_b32 m0, %1\n\t"
+      "global_load_lds_dwordx4 %0, off"
+      :
+      : "v"(gaddr), "s"(__builtin_amdgcn_readfirstlane(lds_addr))
+      : "memory", "m0");
+}
+
+// Issue the reads of tile `tile` into the stage (asynchronous: completion
+// is awaited by the vector-memory counter before the stage is read).
+template <typename T, typename C>
+__device__ __forceinline__ void async_fetch(lptr<unsigned char> stage, const R2RFastArgs<T>& A,
+                                            int tile, int tid) {
+  using AL = AsyncLayout<T, C>;
+  using L = FastLayout<T, C>;
+  const LineGeom& g = A.g;
+  const TileOrigin o = tile_origin(g, tile);
+  const int wave = tid >> 6, lane = tid & 63;
+  const T* data = A.data;
+  const int nlt = 1 << g.lognl;
+#pragma unroll
+  for (int j = 0; j < AL::PER_WAVE; ++j) {
+    const int c = wave * AL::PER_WAVE + j;     // chunk of this instruction (wave-uniform)
+    const T* src = data;                        // a valid address for pieces outside the field
+    if (g.layout == 0) {
+      const int row = c * AL::ROWS_PER_CHUNK + lane / AL::LANES_PER_ROW;
+      const int l = (lane % AL::LANES_PER_ROW) * AL::EPL;
+      const long long b = l < nlt ? line_base(g, o, l) : -1;
+      if (b >= 0) src = data + b + (long long)row * g.sp;
+    } else {
+      const int e = (c * 64 + lane) * AL::EPL;
+      if (e / L::N < g.nlines - o.L0 && e / L::N < nlt) src = data + (long long)o.L0 * L::N + e;
+    }
+    lds_dma16(src, (unsigned)(size_t)(stage + c * 1024));
+  }
+}
+
+// Stage -> tile rows with the input permutation of the type.
+template <typename T, typename C>
+__device__ __forceinline__ void async_place(lptr<const T> stage, lptr<T> lds, int kind, int inverse,
+                                            int layout, int l, int q, int tid) {
+  using L = FastLayout<T, C>;
+  constexpr int N = L::N;
+  T buf[L::EPT];
+  if (layout == 0) {
+#pragma unroll
+    for (int i = 0; i < L::EPT; ++i) buf[i] = stage[(q + i * L::QT) * L::NL + l];
+#pragma unroll
+    for (int i = 0; i < L::EPT; ++i) {
+      bool neg;
+      const int r = load_row(kind, inverse, q + i * L::QT, N, neg);
+      lds[r * L::NLP + l] = neg ? -buf[i] : buf[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < L::EPT; ++i) buf[i] = stage[tid + i * L::NT];
+#pragma unroll
+    for (int i = 0; i < L::EPT; ++i) {
+      const int e = tid + i * L::NT;
+      const int ll = e / N, p = e % N;
+      bool neg;
+      const int r = load_row(kind, inverse, p, N, neg);
+      lds[r * L::NLP + ll] = neg ? -buf[i] : buf[i];
+    }
+  }
+}
+
+// Register budget of the staging kernel.  FP64 M = 256 (DFT and DCT-IV
+// types): one block fills a CU's LDS, so the kernel may use up to 256 VGPRs
+// and keep every stage's addresses live across the tile loop (fastest).  Otherwise the per-thread
+// indices are made opaque at the top of each tile, so that the addresses are
+// recomputed per stage and the kernel fits 128 VGPRs (FP64 M = 128 would
+// spill otherwise; two FP32 blocks share a CU).
+template <typename T, typename C, int KIND>
+struct AsyncBudget {
+  // (the DCT-II / DST-II pipelines of that length would spill)
+  static constexpr bool WIDE = sizeof(T) == 8 && C::M == 256 && KIND != K_NN && KIND != K_DD;
+};
+
+// One kernel per transform type and direction: with the type a constant
+// every stage inlines into a short straight-line pipeline (a call would make
+// the callee wait for all outstanding memory operations, the next tile's
+// reads included).  Two kernels per configuration, one per register budget
+// (AsyncBudget): r2r_async_kernel keeps the thread's indices as they are,
+// r2r_async_tight_kernel makes them opaque at the top of each tile.  The
+// shared parts are macros so that both compile to the same straight code.
+#define POISSON_ASYNC_SETUP                                                                    \
+  using L = FastLayout<T, C>;                                                                  \
+  using AL = AsyncLayout<T, C>;                                                                \
+  constexpr int M = L::M, NL = L::NL;                                                          \
+  constexpr int kind = KIND, inverse = INV;                                                    \
+  if (A.skip && A.skip[0] != 0.0) return;                                                      \
+  /* two LDS objects, so that the staged reads (asynchronous writes to */                     \
+  /* stage_raw) are told apart from the accesses to the tile */                               \
+  __shared__ __align__(16) unsigned char stage_raw[AL::STAGE * sizeof(T)];                     \
+  __shared__ __align__(16) unsigned char tile_raw[fast_lds_bytes<T, C>()];                     \
+  const lptr<const T> stage = as_lds(reinterpret_cast<const T*>(stage_raw));                   \
+  const FastLds<T, C> S = fast_lds<T, C>(tile_raw);                                            \
+  const int tid = threadIdx.x;                                                                 \
+  const int l = tid % NL, q = tid / NL;                                                        \
+  const LineGeom& g = A.g;                                                                     \
+  constexpr bool ivk = kind >= K_ND;                                                           \
+  const lptr<const cplx<T>> tw_fft = S.twf;                                                    \
+  const lptr<const cplx<T>> tw_a = S.twa;                                                      \
+  const lptr<const cplx<T>> tw_b = S.twa + (ivk ? M : L::SPLIT);                               \
+  fast_twiddles<T, C>(S, A, tid);                                                              \
+  const TileRange tr = xcd_tiles(g.ntiles);                                                    \
+  const lptr<unsigned char> stage_lds = as_lds(stage_raw);                                     \
+  if (tr.first < tr.end) async_fetch<T, C>(stage_lds, A, tr.first, tid);
+
+#define POISSON_ASYNC_TILE(LT, QT, TIDT)                                                        \
+  __builtin_amdgcn_s_waitcnt(0); /* this wave's staged reads (and earlier stores) are done */   \
+  lds_barrier();                 /* ... and every wave's */                                    \
+  async_place<T, C>(stage, S.tile, kind, inverse, g.layout, LT, QT, TIDT);                     \
+  lds_barrier();                                                                               \
+  if (tile + tr.step < tr.end) async_fetch<T, C>(stage_lds, A, tile + tr.step, TIDT);         \
+  if constexpr (ivk) fast_iv_pre<T, C, true>(S.tile, tw_a, LT, QT);                            \
+  else if constexpr (inverse) fast_combine<T, C, true>(S.tile, tw_a, tw_b, kind, LT, QT);      \
+  if constexpr (!(inverse && kind <= K_DD)) fast_passes<T, C, true, 0, true>(S.tile, tw_fft, LT, QT); \
+  else fast_passes<T, C, false, 0, true>(S.tile, tw_fft, LT, QT);                             \
+  if constexpr (ivk) fast_iv_post<T, C, true>(S.tile, tw_b, LT, QT);                           \
+  else if constexpr (!inverse) fast_split<T, C, true>(S.tile, tw_a, tw_b, kind, LT, QT);       \
+  const TileOrigin o = tile_origin(g, tile);                                                   \
+  long long base;                                                                              \
+  int lines = 0;                                                                               \
+  if (g.layout == 0) {                                                                         \
+    base = LT < (1 << g.lognl) ? line_base(g, o, LT) : -1;                                     \
+  } else {                                                                                     \
+    base = (long long)o.L0 * L::N;                                                             \
+    lines = g.nlines - o.L0;                                                                   \
+  }                                                                                            \
+  fast_store<T, C, true>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind,         \
+                         inverse, A.scale, LT, QT, TIDT);                                      \
+  lds_barrier();
+
+template <typename T, typename C, int KIND, int INV>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void r2r_async_kernel(R2RFastArgs<T> A) {
+  POISSON_ASYNC_SETUP
+  for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+    POISSON_ASYNC_TILE(l, q, tid)
+  }
+}
+
+template <typename T, typename C, int KIND, int INV>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+void r2r_async_tight_kernel(R2RFastArgs<T> A) {
+  POISSON_ASYNC_SETUP
+  for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+    int lt = l, qt = q, tidt = tid;
+    asm volatile("" : "+v"(lt), "+v"(qt), "+v"(tidt));
+    POISSON_ASYNC_TILE(lt, qt, tidt)
+  }
+}
+
+#undef POISSON_ASYNC_TILE
+#undef POISSON_ASYNC_SETUP
 
 }  // namespace poisson_dev

@@ -17,6 +17,22 @@ pytestmark = pytest.mark.gpu
 
 KINDS = ("P", "NN", "DD", "ND", "DN")
 TOL64 = 1e-12
+FAST_M = [16, 32, 48, 64, 96, 128, 192, 256]
+ELIM_LENGTHS = [64, 96, 128, 192, 256, 384, 512]
+
+
+@pytest.fixture
+def default_variants():
+    """Put every entry of the variant table back to its default afterwards
+    (the staging transform for lengths 256 and 512, variant 0 otherwise)."""
+    from paper_1802_10323_amd import set_tuned_variant
+    yield
+    for fp64 in (True, False):
+        for layout in (0, 1):
+            for M in FAST_M:
+                set_tuned_variant(0, 2 * M, layout, 4 if M in (128, 256) else 0, fp64)
+            for n in ELIM_LENGTHS:
+                set_tuned_variant(1, n, layout, 0, fp64)
 
 
 def say(*a):
@@ -122,7 +138,6 @@ def test_transform_lengths(kind, n, path, monkeypatch):
         plan.close()
 
 
-ELIM_LENGTHS = [64, 96, 128, 192, 256, 384, 512]
 UNIT = 2.0 ** -53
 
 
@@ -358,10 +373,23 @@ def _batch_case(seed, count):
     return probs
 
 
-def test_persistent_batch_equals_single_solves():
+def _synchronous_variants():
+    """The batched kernels have the synchronous transform variants only:
+    make single solves use variant 0 for the lengths whose default is the
+    staging form, so that both run the same arithmetic."""
+    from paper_1802_10323_amd import set_tuned_variant
+    for fp64 in (True, False):
+        for layout in (0, 1):
+            for n in (256, 512):
+                set_tuned_variant(0, n, layout, 0, fp64)
+
+
+def test_persistent_batch_equals_single_solves(default_variants):
     """One persistent launch per stage over uneven instances (sizes from
     {64, ..., 256} per axis, random boundary pairs, stretched and uniform z):
-    bitwise equal to the single solves, and within 1e-12 of the oracle."""
+    bitwise equal to single solves with the same kernel variants, within
+    1e-14 of single solves with the default ones (staging transforms for
+    length 256), and within 1e-12 of the oracle."""
     from paper_1802_10323_amd import Batch, Plan
     probs = _batch_case(1, 10)
     say("batch shapes", [p.shape for p in probs])
@@ -371,9 +399,12 @@ def test_persistent_batch_equals_single_solves():
     batch.bind(fields)
     batch.launch()
     got = [to_host(f) for f in fields]
-    for p, g in zip(probs, got):
+    defaults = [gpu_solve(p)[0] for p in probs]
+    _synchronous_variants()
+    for p, g, d in zip(probs, got, defaults):
         single, _ = gpu_solve(p)
         assert np.array_equal(g, single), p
+        assert rel_l2(g, d) <= 1e-14, p
         assert rel_l2(g, oracle_solve(p)) <= TOL64, p
     batch.close()
     for pl in plans:
@@ -507,28 +538,15 @@ def test_server_admission_by_hbm_budget():
 
 # --------------------------------------------------------------- kernel variants
 
-FAST_M = [16, 32, 48, 64, 96, 128, 192, 256]
 
-
-@pytest.fixture
-def default_variants():
-    """Put every entry of the variant table back to 0 afterwards."""
-    from paper_1802_10323_amd import set_tuned_variant
-    yield
-    for fp64 in (True, False):
-        for layout in (0, 1):
-            for M in FAST_M:
-                set_tuned_variant(0, 2 * M, layout, 0, fp64)
-            for n in ELIM_LENGTHS:
-                set_tuned_variant(1, n, layout, 0, fp64)
-
-
-@pytest.mark.parametrize("V", [1, 2, 3])
+@pytest.mark.parametrize("V", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("M", FAST_M)
 def test_transform_variants(M, V, default_variants):
-    """Every compiled transform variant (tile shape x radix order) against
-    the Table 2 sums, all five types, contiguous and strided (one partial
-    and one multi-tile strided case); round trip is the identity."""
+    """Every compiled transform variant (tile shape x radix order, and the
+    asynchronous-staging form) against the Table 2 sums, all five types,
+    contiguous and strided (one partial and one multi-tile strided case, and
+    an odd row length that the staging form must hand to variant 0); round
+    trip is the identity."""
     from oracle import transforms as tr
     from paper_1802_10323_amd import Plan, set_tuned_variant
     n = 2 * M
@@ -536,12 +554,17 @@ def test_transform_variants(M, V, default_variants):
     for layout in (0, 1):
         set_tuned_variant(0, n, layout, V)
     for kind in KINDS:
-        for axis_name, shape in (("x", (3, 6, n)), ("y", (3, n, 8)), ("y", (2, n, 40))):
+        for axis_name, shape in (("x", (3, 6, n)), ("y", (3, n, 8)), ("y", (2, n, 40)),
+                                 ("y", (2, n, 7))):
             f = rng.uniform(-1, 1, shape)
             nz, ny, nx = shape
-            bcx, bcy = (kind, "P") if axis_name == "x" else ("P", kind)
-            plan = Plan(nx, ny, nz, 1.0, 1.0, np.ones(nz), (bcx, bcy, "DD"))
-            role = 0 if axis_name == "x" else 1
+            if nx % 2:      # odd rows: x is the elimination axis, y is t1
+                bcs, role = ("DD", kind, "P"), 0
+            else:
+                bcx, bcy = (kind, "P") if axis_name == "x" else ("P", kind)
+                bcs, role = (bcx, bcy, "DD"), 0 if axis_name == "x" else 1
+            plan = Plan(nx, ny, nz, 1.0, 1.0, np.ones(nz), bcs)
+            assert plan.roles[role] == axis_name
             d = to_dev(f)
             plan.transform_stage(role, False, d)
             assert rel_l2(to_host(d), tr.forward(f, AXIS[axis_name], kind)) <= 1e-13, (kind, shape)
@@ -589,9 +612,11 @@ def test_autotune_records_fastest(default_variants):
     say("autotune report", rep)
     for prec, fp64 in (("fp64", True), ("fp32", False)):
         r = rep[prec]
-        assert all(v > 0 for v in r["t1"] + r["t2"] + r["elimination"])
-        assert tuned_variant(0, 128, 1, fp64) == int(np.argmin(r["t1"]))
-        assert tuned_variant(0, 96, 0, fp64) == int(np.argmin(r["t2"]))
+        assert all(v > 0 for v in r["t1"][:4] + r["t2"][:4] + r["elimination"])
+        assert r["t2"][4] == -1.0        # no staging form for length 96
+        t1 = [v if v > 0 else np.inf for v in r["t1"]]
+        assert tuned_variant(0, 128, 1, fp64) == int(np.argmin(t1))
+        assert tuned_variant(0, 96, 0, fp64) == int(np.argmin(r["t2"][:4]))
         assert tuned_variant(1, 192, 0, fp64) == int(np.argmin(r["elimination"]))
     got, _ = gpu_solve(prob)
     assert rel_l2(got, oracle_solve(prob)) <= TOL64
@@ -601,9 +626,11 @@ def test_autotune_records_fastest(default_variants):
     b = Batch(plans)
     b.bind(fields)
     b.launch(graph=True)
-    for p, f in zip(probs, fields):
+    got = [to_host(f) for f in fields]
+    _synchronous_variants()
+    for p, g in zip(probs, got):
         single, _ = gpu_solve(p)
-        assert np.array_equal(to_host(f), single)
+        assert np.array_equal(g, single)
     b.close()
     for pl in plans:
         pl.close()
