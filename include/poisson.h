@@ -171,22 +171,23 @@ void batch_destroy(poisson_batch* batch);
  * transforms, variants 0-3 are two tile shapes (lines per tile x threads per
  * line) times two FFT radix orders (radix 8 first or radix 4 first), and
  * variant 4 (lengths 256 and 512 only) reads the next tile straight into LDS
- * while the current one is transformed; for the elimination, two chunkings
- * (rows per chunk x chunks per line).  All give the same result up to
+ * while the current one is transformed; for the elimination, variants 0-1
+ * are two chunkings (rows per chunk x chunks per line) and variant 2 reads
+ * the next tile into LDS while the current one is eliminated.  All give the same result up to
  * rounding.  The variant used for a length is chosen per device, precision
  * and layout (strided: the axis is y or z; contiguous: x) from a
  * process-wide table; where nothing was tuned, variant 4 for transform
  * lengths 256 and 512 and variant 0 otherwise.  Plans and batches read the
- * table when they launch (batches when they are bound; batches use
- * variants 0-3 only). */
+ * table when they launch (batches when they are bound; batches use the
+ * synchronous variants only: transforms 0-3, elimination 0-1). */
 
 /* Time every variant of this plan's kernels (both transformed axes and the
  * elimination, FP64 and FP32) on `scratch` (DEVICE, at least nx*ny*nz
  * doubles; overwritten), `reps` launches each after one warm-up, and record
  * the fastest in the table.  Synchronous (waits for `stream`).  report (HOST,
- * may be NULL): 2 x (5 + 5 + 2) doubles, per precision (FP64 first) the
+ * may be NULL): 2 x (5 + 5 + 3) doubles, per precision (FP64 first) the
  * average ms of variants 0-4 of t1, 0-4 of t2 (forward + backward pair) and
- * 0-1 of the elimination, -1 where a variant does not apply. */
+ * 0-2 of the elimination, -1 where a variant does not apply. */
 int plan_autotune(poisson_plan* plan, double* scratch, int reps, hipStream_t stream, double* report);
 
 /* Variant in the table for kernel family 0 (transform) or 1 (elimination),

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpoisson_hip.so")
 SOURCES = [os.path.join(HERE, "csrc", name)
-           for name in ("poisson.hip", "r2r_async.hip", "r2r_async_wide.hip")]
+           for name in ("poisson.hip", "r2r_async.hip", "r2r_async_wide.hip", "tri_async.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "r2r_fast.h"
+#include "tri_fast.h"
 
 namespace poisson_dev {
 
@@ -23,6 +24,11 @@ hipError_t async_transform_launch(const R2RFastArgs<double>& a, int M, int kind,
                                   hipStream_t stream);
 hipError_t async_transform_launch(const R2RFastArgs<float>& a, int M, int kind, int inverse,
                                   hipStream_t stream);
+
+// The staging elimination (tri_async.hip) for lines of n points, with the
+// chunking of variant 0 (tri_fast.h).  hipErrorInvalidValue if n has none.
+hipError_t async_elimination_launch(const TriFastArgs<double>& a, int n, hipStream_t stream);
+hipError_t async_elimination_launch(const TriFastArgs<float>& a, int n, hipStream_t stream);
 
 // The kernels of AsyncBudget<double, FastVar<256, 0>, kind>::WIDE
 // (r2r_async_wide.hip).

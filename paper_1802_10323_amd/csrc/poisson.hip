@@ -175,7 +175,8 @@ struct TriCfg {
 
 static constexpr int kFastVariants = 5;   // transform: tile shape x radix order, + asynchronous staging
 static constexpr int kAsyncVariant = 4;
-static constexpr int kTriVariants = 2;    // elimination: two chunkings per length
+static constexpr int kTriVariants = 3;    // elimination: two chunkings, + asynchronous staging
+static constexpr int kTriAsyncVariant = 2;
 
 // Call f(FastVar<M, V>{}) for a specialised transform length; -1 otherwise.
 template <typename F>
@@ -256,7 +257,7 @@ static int lds_setup_once() {
     ALLOW((tridiag_kernel<float, 4, TRI_NT>));
     ALLOW((tridiag_kernel<float, 8, TRI_NT>));
     for (int n : {64, 96, 128, 192, 256, 384, 512})
-      for (int V = 0; V < kTriVariants; ++V)
+      for (int V = 0; V < 2; ++V)
         with_tri_cfg(n, V, [&](auto cfg) {
           using C = decltype(cfg);
           ALLOW((tri_fast_kernel<double, C::RPC, C::P>));
@@ -473,6 +474,7 @@ static TriFastArgs<T> tri_fast_args(const poisson_plan* p, T* data, const double
   a.periodic = p->s_periodic;
   a.singular = p->singular;
   a.nu = p->nu;
+  a.nv = p->nv;
   // FP64 tables for both field precisions (the recurrences run in FP64)
   const double* tri = reinterpret_cast<const double*>(p->dtab + p->off_tri_d);
   a.a = tri;
@@ -498,10 +500,32 @@ static int launch_tri_fast(const poisson_plan* p, T* data, hipStream_t st, const
   return POISSON_OK;
 }
 
+// True if the staging elimination applies in type T (strided rows must split
+// into 16-byte pieces).
+template <typename T>
+static bool tri_async_applies(const poisson_plan* p) {
+  return p->s == 0 || p->dims[0] % (int)(16 / sizeof(T)) == 0;
+}
+
 // Specialised elimination in variant V (-1: the length has none).
 template <typename T>
 static int launch_tri_variant(const poisson_plan* p, int V, T* data, hipStream_t st,
                               const double* skip) {
+  if (V == kTriAsyncVariant) {
+    if (tri_async_applies<T>(p)) {
+      const int n = p->dims[p->s];
+      const long long rc = with_tri_cfg(n, 0, [&](auto cfg) {
+        using C = decltype(cfg);
+        const TriFastArgs<T> a = tri_fast_args<T, C::RPC, C::P>(p, data, skip);
+        const hipError_t e = async_elimination_launch(a, n, st);
+        return (long long)(e == hipSuccess ? POISSON_OK
+                                           : fail(POISSON_EHIP, "staging elimination launch: %s",
+                                                  hipGetErrorString(e)));
+      });
+      if (rc != -1) return (int)rc;
+    }
+    V = 0;
+  }
   return (int)with_tri_cfg(p->dims[p->s], V, [&](auto cfg) {
     using C = decltype(cfg);
     return (long long)launch_tri_fast<T, C::RPC, C::P>(p, data, st, skip);
@@ -1023,7 +1047,8 @@ static void batch_jobs(poisson_batch* b, double* const* rhs, std::vector<char>& 
       } else {
         const int n = p->dims[p->s];
         BatchTriJob<double> J{};
-        J.key = 2 * n + tuned_choice(1, sizeof(double), n, p->s == 0);
+        const int tv = tuned_choice(1, sizeof(double), n, p->s == 0);
+        J.key = 2 * n + (tv < 2 ? tv : 0);   // the batched kernel has the synchronous chunkings
         with_tri_cfg(n, J.key & 1, [&](auto cfg) {
           using C = decltype(cfg);
           J.a = tri_fast_args<double, C::RPC, C::P>(p, data, nullptr);
@@ -1231,6 +1256,7 @@ static int autotune_typed(poisson_plan* p, double* scratch, int reps, hipStream_
     int best = 0;
     double best_ms = 1e300;
     for (int V = 0; V < kTriVariants; ++V) {
+      if (V == kTriAsyncVariant && !tri_async_applies<T>(p)) continue;
       if ((rc = reset())) return rc;
       const double ms = time_launches(st, reps, [&]() -> int {
         return launch_tri_variant<T>(p, V, data, st, nullptr);

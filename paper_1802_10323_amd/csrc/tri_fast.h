@@ -20,6 +20,7 @@
 //    (VALU) instead of LDS permutes.
 #pragma once
 #include "tridiag_kernel.h"
+#include "stage_dma.h"
 
 namespace poisson_dev {
 
@@ -30,6 +31,7 @@ struct TriFastArgs {
   int periodic;
   int singular;
   int nu;             // extent of u (contiguous layout: line index = u + nu v)
+  int nv;             // extent of v
   // coefficient tables in FP64 for both field precisions: the recurrences
   // run in FP64 registers (see tri_fast_line)
   const double* a;    // [n]
@@ -116,8 +118,8 @@ __device__ __noinline__ void tri_fast_load(lptr<T> lds, gptr<const T> data, long
 }
 
 template <typename T, int RPC, int P>
-__device__ __noinline__ void tri_fast_store(lptr<const T> lds, gptr<T> data, long long base,
-                                            long long sp, int layout, int lines, int tid) {
+__device__ __forceinline__ void tri_fast_store_body(lptr<const T> lds, gptr<T> data, long long base,
+                                                    long long sp, int layout, int lines, int tid) {
   using L = TriFastLayout<T, RPC, P>;
   T buf[RPC];
   if (layout == 0) {
@@ -141,6 +143,12 @@ __device__ __noinline__ void tri_fast_store(lptr<const T> lds, gptr<T> data, lon
       if (e / L::N < lines) data[base + e] = buf[i];
     }
   }
+}
+
+template <typename T, int RPC, int P>
+__device__ __noinline__ void tri_fast_store(lptr<const T> lds, gptr<T> data, long long base,
+                                            long long sp, int layout, int lines, int tid) {
+  tri_fast_store_body<T, RPC, P>(lds, data, base, sp, layout, lines, tid);
 }
 
 // Sum over the P lanes of a line.
@@ -387,6 +395,98 @@ void tri_fast_kernel(TriFastArgs<T> A) {
   const TileRange tr = xcd_tiles(A.g.ntiles);
   for (int tile = tr.first; tile < tr.end; tile += tr.step)
     tri_fast_tile<T, RPC, P>(lds, coef, A, tile, tid);
+}
+
+// ---------------------------------------------------------------- async form
+// The elimination with the next tile's HBM reads in flight while the current
+// tile is eliminated: the tile is read straight into a staging area of LDS
+// (stage_dma.h) and moved into its chunked place at the start of its turn.
+// Everything is inlined (a call would wait for the staged reads), the
+// eigenvalue shifts are kept in LDS for the same reason (a global load in
+// the loop would wait for them too).  One block per CU.
+
+static constexpr int TRI_ASYNC_LAM = 1024;   // longest transformed axis
+
+template <typename T, int RPC, int P>
+struct TriAsyncLayout {
+  using L = TriFastLayout<T, RPC, P>;
+  static constexpr int STAGE_BYTES = L::NL * L::N * (int)sizeof(T);
+};
+
+template <typename T, int RPC, int P>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void tri_async_kernel(TriFastArgs<T> A) {
+  using L = TriFastLayout<T, RPC, P>;
+  using SL = StageLayout<T, L::NL, L::N>;
+  constexpr int N = L::N, NL = L::NL, NT = L::NT;
+  if (A.skip && A.skip[0] != 0.0) return;
+  __shared__ __align__(16) unsigned char stage_raw[SL::BYTES];
+  __shared__ __align__(16) T tile_raw[L::TILE];
+  __shared__ __align__(16) double coef_raw[4 * N];
+  __shared__ double lam_raw[2 * TRI_ASYNC_LAM];
+  const lptr<T> lds = as_lds(tile_raw);
+  const lptr<double> coef = as_lds(coef_raw);
+  const lptr<double> lam = as_lds(lam_raw);
+  const lptr<const T> stage = as_lds(reinterpret_cast<const T*>(stage_raw));
+  const lptr<unsigned char> stage_lds = as_lds(stage_raw);
+  const int tid0 = threadIdx.x;
+  const LineGeom& g = A.g;
+  const int nlt = 1 << g.lognl;
+
+  for (int i = tid0; i < A.nu; i += NT) lam[i] = as_global(A.lamu)[i];
+  for (int i = tid0; i < A.nv; i += NT) lam[TRI_ASYNC_LAM + i] = as_global(A.lamv)[i];
+  tri_fast_coefs<T, RPC, P>(coef, A, tid0);   // (ends with a barrier)
+
+  const TileRange tr = xcd_tiles(g.ntiles);
+  if (tr.first < tr.end) stage_fetch<T, NL, N>(stage_lds, A.data, g, tr.first, tid0);
+  for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+    // thread indices opaque per tile: the compiler recomputes the addresses
+    // instead of holding them all live across the loop (registers)
+    int tid = tid0;
+    asm volatile("" : "+v"(tid));
+    const int c = tid % P;
+    const int l = tid / P;
+    const lptr<T> col = lds + c * L::CP + l;
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's staged reads (and earlier stores) are done
+    lds_barrier();                   // ... and every wave's
+    if (g.layout == 0) {
+      const int ll = tid % NL, q = tid / NL;
+#pragma unroll
+      for (int i = 0; i < RPC; ++i)
+        lds[tri_fast_slot<T, RPC, P>(q + i * P, ll)] = stage[(q + i * P) * NL + ll];
+    } else {
+#pragma unroll
+      for (int i = 0; i < RPC; ++i) {
+        const int e = tid + i * NT;
+        const int ll = e / N;
+        lds[tri_fast_slot<T, RPC, P>(e - ll * N, ll)] = stage[e];
+      }
+    }
+    lds_barrier();
+    if (tile + tr.step < tr.end) stage_fetch<T, NL, N>(stage_lds, A.data, g, tile + tr.step, tid);
+
+    const TileOrigin o = tile_origin(g, tile);
+    const bool valid = l < nlt && line_base(g, o, l) >= 0;
+    int u = 0, v = 0;
+    if (valid) line_coords(g, o, l, A.nu, u, v);
+    const double mu = valid ? lam[u] + lam[TRI_ASYNC_LAM + v] : -1.0;
+    const bool sing = A.singular && valid && u == 0 && v == 0;
+    const int wave_sing = __any(sing) ? 1 : 0;
+    tri_fast_line<T, RPC, P>(col, coef, c, mu, sing ? 1 : 0, wave_sing, A.periodic);
+    lds_barrier();
+
+    long long base;
+    int lines = 0;
+    if (g.layout == 0) {
+      const int ll = tid % NL;
+      base = ll < nlt ? line_base(g, o, ll) : -1;
+    } else {
+      base = (long long)o.L0 * N;
+      lines = min(g.nlines - o.L0, nlt);
+    }
+    tri_fast_store_body<T, RPC, P>(lds, as_global(A.data), base, g.sp, g.layout, lines, tid);
+    lds_barrier();
+  }
 }
 
 }  // namespace poisson_dev

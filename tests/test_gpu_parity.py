@@ -573,14 +573,17 @@ def test_transform_variants(M, V, default_variants):
             plan.close()
 
 
+@pytest.mark.parametrize("V", [1, 2])
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("n", ELIM_LENGTHS)
-def test_elimination_variants(n, kind, default_variants):
-    """The second chunking of every specialised elimination length, with the
-    checks of test_elimination_lengths."""
+def test_elimination_variants(n, kind, V, default_variants):
+    """The second chunking (V = 1) and the staging form (V = 2) of every
+    specialised elimination length, with the checks of
+    test_elimination_lengths (their strided cases have an even x extent,
+    so the staging form applies)."""
     from paper_1802_10323_amd import set_tuned_variant
     for layout in (0, 1):
-        set_tuned_variant(1, n, layout, 1)
+        set_tuned_variant(1, n, layout, V)
     _check_elimination(n, kind)
 
 
@@ -613,7 +616,7 @@ def test_autotune_records_fastest(default_variants):
     for prec, fp64 in (("fp64", True), ("fp32", False)):
         r = rep[prec]
         assert all(v > 0 for v in r["t1"][:4] + r["t2"][:4] + r["elimination"])
-        assert r["t2"][4] == -1.0        # no staging form for length 96
+        assert r["t2"][4] == -1.0        # no staging transform for length 96
         t1 = [v if v > 0 else np.inf for v in r["t1"]]
         assert tuned_variant(0, 128, 1, fp64) == int(np.argmin(t1))
         assert tuned_variant(0, 96, 0, fp64) == int(np.argmin(r["t2"][:4]))
