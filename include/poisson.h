@@ -125,7 +125,7 @@ int solve_status(poisson_plan* plan, int* iters, double* last_update_rel);
  * (DEVICE pointers), on `stream`.  FP64 plans only; plans must be distinct.
  * Same result per instance as solve() with the same kernel variants, bit for
  * bit (batched launches use transform variants 0-3; against solve() with the
- * staging transform, variant 4, results agree to rounding).  When every plan's lengths
+ * staging transforms, variants 4 and 5, results agree to rounding).  When every plan's lengths
  * have size-specialised kernels (batch_create), the solves run as one
  * persistent launch per stage over all instances and the call waits for
  * `stream` to complete (it frees its temporary job tables); otherwise the
@@ -170,14 +170,15 @@ void batch_destroy(poisson_batch* batch);
  * Each specialised length has several compiled variants: for the
  * transforms, variants 0-3 are two tile shapes (lines per tile x threads per
  * line) times two FFT radix orders (radix 8 first or radix 4 first), and
- * variant 4 (lengths 256 and 512 only) reads the next tile straight into LDS
- * while the current one is transformed; for the elimination, variants 0-1
+ * variants 4 and 5 (lengths 256 and 512 only; the two tile shapes) read the
+ * next tile straight into LDS while the current one is transformed; for the elimination, variants 0-1
  * are two chunkings (rows per chunk x chunks per line) and variant 2 reads
  * the next tile into LDS while the current one is eliminated.  All give the same result up to
  * rounding.  The variant used for a length is chosen per device, precision
  * and layout (strided: the axis is y or z; contiguous: x) from a
- * process-wide table; where nothing was tuned, variant 4 for transform
- * lengths 256 and 512 and variant 0 otherwise.  Plans and batches read the
+ * process-wide table; where nothing was tuned, a staging transform for
+ * lengths 256 and 512 (variant 5 for FP64 length 256 and for FP32 length 512
+ * on the contiguous axis, else 4) and variant 0 otherwise.  Plans and batches read the
  * table when they launch (batches when they are bound; batches use the
  * synchronous variants only: transforms 0-3, elimination 0-1). */
 
@@ -185,8 +186,8 @@ void batch_destroy(poisson_batch* batch);
  * elimination, FP64 and FP32) on `scratch` (DEVICE, at least nx*ny*nz
  * doubles; overwritten), `reps` launches each after one warm-up, and record
  * the fastest in the table.  Synchronous (waits for `stream`).  report (HOST,
- * may be NULL): 2 x (5 + 5 + 3) doubles, per precision (FP64 first) the
- * average ms of variants 0-4 of t1, 0-4 of t2 (forward + backward pair) and
+ * may be NULL): 2 x (6 + 6 + 3) doubles, per precision (FP64 first) the
+ * average ms of variants 0-5 of t1, 0-5 of t2 (forward + backward pair) and
  * 0-2 of the elimination, -1 where a variant does not apply. */
 int plan_autotune(poisson_plan* plan, double* scratch, int reps, hipStream_t stream, double* report);
 

@@ -16,14 +16,14 @@
 
 namespace poisson_dev {
 
-// Launch the staging transform for complex length M (128 or 256), transform
-// type `kind` and direction `inverse`, arguments as for r2r_fast_kernel with
-// the tile shape of variant 0.  hipErrorInvalidValue if (M, kind) has no
-// instantiation.
-hipError_t async_transform_launch(const R2RFastArgs<double>& a, int M, int kind, int inverse,
-                                  hipStream_t stream);
-hipError_t async_transform_launch(const R2RFastArgs<float>& a, int M, int kind, int inverse,
-                                  hipStream_t stream);
+// Launch the staging transform for complex length M (128 or 256), tile
+// shape `shape` (0 or 1, the shapes of FastVar<M, shape>), transform type
+// `kind` and direction `inverse`, arguments as for r2r_fast_kernel with that
+// tile shape.  hipErrorInvalidValue if (M, shape, kind) has no instantiation.
+hipError_t async_transform_launch(const R2RFastArgs<double>& a, int M, int shape, int kind,
+                                  int inverse, hipStream_t stream);
+hipError_t async_transform_launch(const R2RFastArgs<float>& a, int M, int shape, int kind,
+                                  int inverse, hipStream_t stream);
 
 // The staging elimination (tri_async.hip) for lines of n points, with the
 // chunking of variant 0 (tri_fast.h).  hipErrorInvalidValue if n has none.

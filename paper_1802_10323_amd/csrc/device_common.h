@@ -190,6 +190,16 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Wait until at most N vector-memory operations of this wave are still
+// outstanding.  The counter retires in issue order, so when at least N
+// operations were issued after a group of reads, this waits for those reads
+// and lets the last N (a tile's stores) stay in flight.
+template <int N>
+__device__ __forceinline__ void vm_wait_keep() {
+  static_assert(N >= 0 && N < 64, "vector-memory counter range");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
 // floor(j / d) for j, d < 2^16 with magic = ceil(2^32 / d), d > 1.
 __device__ __forceinline__ int fast_div(int j, unsigned magic) {
   return (int)__umulhi((unsigned)j, magic);

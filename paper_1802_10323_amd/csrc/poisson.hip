@@ -173,8 +173,8 @@ struct TriCfg {
   static constexpr int RPC = RPC_, P = P_;
 };
 
-static constexpr int kFastVariants = 5;   // transform: tile shape x radix order, + asynchronous staging
-static constexpr int kAsyncVariant = 4;
+static constexpr int kFastVariants = 6;   // transform: tile shape x radix order, + asynchronous staging
+static constexpr int kAsyncVariant = 4;   // 4 and 5: asynchronous staging in tile shape 0 and 1
 static constexpr int kTriVariants = 3;    // elimination: two chunkings, + asynchronous staging
 static constexpr int kTriAsyncVariant = 2;
 
@@ -216,9 +216,15 @@ static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int, int, int>, int> g_tune;
 
 // Variant used where nothing was tuned: the asynchronous-staging transform
-// for the lengths it is compiled for, else variant 0.
-static int default_choice(int family, int n) {
-  return family == 0 && (n == 128 || n == 256) ? kAsyncVariant : 0;
+// for the lengths it is compiled for, else variant 0.  Its tile shape:
+// shape 1 (half the lines per tile, so that twice the blocks fit in a CU's
+// LDS) for FP64 length 256 and for FP32 length 512 on the contiguous axis,
+// where the extra overlap pays most; else shape 0, whose wider tile rows
+// (128-256 bytes on the strided axes) use each DRAM page better.
+static int default_choice(int family, int bytes, int n, int layout) {
+  if (family != 0 || (n != 128 && n != 256)) return 0;
+  const bool shape1 = bytes == 8 ? n == 128 : (n == 256 && layout == 1);
+  return kAsyncVariant + (shape1 ? 1 : 0);
 }
 
 static int tuned_choice(int family, int bytes, int n, int layout) {
@@ -226,7 +232,7 @@ static int tuned_choice(int family, int bytes, int n, int layout) {
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   const auto it = g_tune.find(std::make_tuple(dev, family, bytes, n, layout));
-  return it == g_tune.end() ? default_choice(family, n) : it->second;
+  return it == g_tune.end() ? default_choice(family, bytes, n, layout) : it->second;
 }
 
 static void set_tuned_choice(int family, int bytes, int n, int layout, int v) {
@@ -385,13 +391,18 @@ static int launch_fast(const poisson_plan* p, const AxisTables& A, int inverse, 
 // -1 if it does not apply (length, or strided rows that do not split into
 // 16-byte pieces).
 template <typename T>
-static int launch_async(const poisson_plan* p, const AxisTables& A, int inverse, T* data,
-                        hipStream_t st, const double* skip) {
+static int launch_async(const poisson_plan* p, const AxisTables& A, int shape, int inverse,
+                        T* data, hipStream_t st, const double* skip) {
   if (A.m != 128 && A.m != 256) return -1;
   if (A.axis != 0 && p->dims[0] % (int)(16 / sizeof(T)) != 0) return -1;
-  const R2RFastArgs<T> a = A.m == 128 ? fast_args<T, FastVar<128, 0>>(p, A, inverse, data, skip)
-                                       : fast_args<T, FastVar<256, 0>>(p, A, inverse, data, skip);
-  const hipError_t e = async_transform_launch(a, A.m, A.kind, inverse, st);
+  R2RFastArgs<T> a;
+  switch (A.m * 2 + shape) {
+    case 128 * 2 + 0: a = fast_args<T, FastVar<128, 0>>(p, A, inverse, data, skip); break;
+    case 128 * 2 + 1: a = fast_args<T, FastVar<128, 1>>(p, A, inverse, data, skip); break;
+    case 256 * 2 + 0: a = fast_args<T, FastVar<256, 0>>(p, A, inverse, data, skip); break;
+    default: a = fast_args<T, FastVar<256, 1>>(p, A, inverse, data, skip); break;
+  }
+  const hipError_t e = async_transform_launch(a, A.m, shape, A.kind, inverse, st);
   if (e != hipSuccess)
     return fail(POISSON_EHIP, "staging transform launch: %s", hipGetErrorString(e));
   return POISSON_OK;
@@ -408,8 +419,8 @@ static bool async_applies(const poisson_plan* p, const AxisTables& A) {
 template <typename T>
 static int launch_fast_variant(const poisson_plan* p, const AxisTables& A, int V, int inverse,
                                T* data, hipStream_t st, const double* skip) {
-  if (V == kAsyncVariant) {
-    const int rc = launch_async<T>(p, A, inverse, data, st, skip);
+  if (V >= kAsyncVariant) {
+    const int rc = launch_async<T>(p, A, V - kAsyncVariant, inverse, data, st, skip);
     if (rc != -1) return rc;
     V = 0;
   }
@@ -1237,7 +1248,7 @@ static int autotune_typed(poisson_plan* p, double* scratch, int reps, hipStream_
     int best = 0;
     double best_ms = 1e300;
     for (int V = 0; V < kFastVariants; ++V) {
-      if (V == kAsyncVariant && !async_applies<T>(p, A)) continue;
+      if (V >= kAsyncVariant && !async_applies<T>(p, A)) continue;
       if ((rc = reset())) return rc;
       // forward then backward: the field keeps its size over the repetitions
       const double ms = time_launches(st, reps, [&]() -> int {

@@ -28,22 +28,27 @@ hipError_t launch(const R2RFastArgs<T>& a, int kind, int inverse, hipStream_t st
 }
 
 template <typename T>
-hipError_t launch_m(const R2RFastArgs<T>& a, int M, int kind, int inverse, hipStream_t st) {
-  if (M == 128) return launch<T, FastVar<128, 0>>(a, kind, inverse, st);
-  if (M == 256) return launch<T, FastVar<256, 0>>(a, kind, inverse, st);
-  return hipErrorInvalidValue;
+hipError_t launch_m(const R2RFastArgs<T>& a, int M, int shape, int kind, int inverse,
+                    hipStream_t st) {
+  switch (M * 2 + shape) {
+    case 128 * 2 + 0: return launch<T, FastVar<128, 0>>(a, kind, inverse, st);
+    case 128 * 2 + 1: return launch<T, FastVar<128, 1>>(a, kind, inverse, st);
+    case 256 * 2 + 0: return launch<T, FastVar<256, 0>>(a, kind, inverse, st);
+    case 256 * 2 + 1: return launch<T, FastVar<256, 1>>(a, kind, inverse, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
-hipError_t async_transform_launch(const R2RFastArgs<double>& a, int M, int kind, int inverse,
-                                  hipStream_t stream) {
-  return launch_m<double>(a, M, kind, inverse, stream);
+hipError_t async_transform_launch(const R2RFastArgs<double>& a, int M, int shape, int kind,
+                                  int inverse, hipStream_t stream) {
+  return launch_m<double>(a, M, shape, kind, inverse, stream);
 }
 
-hipError_t async_transform_launch(const R2RFastArgs<float>& a, int M, int kind, int inverse,
-                                  hipStream_t stream) {
-  return launch_m<float>(a, M, kind, inverse, stream);
+hipError_t async_transform_launch(const R2RFastArgs<float>& a, int M, int shape, int kind,
+                                  int inverse, hipStream_t stream) {
+  return launch_m<float>(a, M, shape, kind, inverse, stream);
 }
 
 }  // namespace poisson_dev

@@ -735,8 +735,8 @@ __device__ __forceinline__ void async_place(lptr<const T> stage, lptr<T> lds, in
   }
 }
 
-// Register budget of the staging kernel.  FP64 M = 256 (DFT and DCT-IV
-// types): one block fills a CU's LDS, so the kernel may use up to 256 VGPRs
+// Register budget of the staging kernel.  FP64 M = 256 in the 16-line tile
+// shape (DFT and DCT-IV types): one block fills a CU's LDS, so the kernel may use up to 256 VGPRs
 // and keep every stage's addresses live across the tile loop (fastest).  Otherwise the per-thread
 // indices are made opaque at the top of each tile, so that the addresses are
 // recomputed per stage and the kernel fits 128 VGPRs (FP64 M = 128 would
@@ -744,7 +744,8 @@ __device__ __forceinline__ void async_place(lptr<const T> stage, lptr<T> lds, in
 template <typename T, typename C, int KIND>
 struct AsyncBudget {
   // (the DCT-II / DST-II pipelines of that length would spill)
-  static constexpr bool WIDE = sizeof(T) == 8 && C::M == 256 && KIND != K_NN && KIND != K_DD;
+  static constexpr bool WIDE = sizeof(T) == 8 && C::M == 256 && FastLayout<T, C>::NL == 16 &&
+                               KIND != K_NN && KIND != K_DD;
 };
 
 // One kernel per transform type and direction: with the type a constant
@@ -776,10 +777,15 @@ struct AsyncBudget {
   fast_twiddles<T, C>(S, A, tid);                                                              \
   const TileRange tr = xcd_tiles(g.ntiles);                                                    \
   const lptr<unsigned char> stage_lds = as_lds(stage_raw);                                     \
-  if (tr.first < tr.end) async_fetch<T, C>(stage_lds, A, tr.first, tid);
+  if (tr.first < tr.end) async_fetch<T, C>(stage_lds, A, tr.first, tid);                      \
+  /* stores of the previous tile issued after the staged reads: EPT per */                    \
+  /* thread (every wave stores every element row of a whole tile), else 0 */                  \
+  bool stores_pending = false;
 
 #define POISSON_ASYNC_TILE(LT, QT, TIDT)                                                        \
-  __builtin_amdgcn_s_waitcnt(0); /* this wave's staged reads (and earlier stores) are done */   \
+  /* this wave's staged reads are done (the previous tile's stores may not be) */             \
+  if (stores_pending) vm_wait_keep<L::EPT>();                                                  \
+  else __builtin_amdgcn_s_waitcnt(0);                                                          \
   lds_barrier();                 /* ... and every wave's */                                    \
   async_place<T, C>(stage, S.tile, kind, inverse, g.layout, LT, QT, TIDT);                     \
   lds_barrier();                                                                               \
@@ -801,6 +807,9 @@ struct AsyncBudget {
   }                                                                                            \
   fast_store<T, C, true>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind,         \
                          inverse, A.scale, LT, QT, TIDT);                                      \
+  /* strided tiles: each wave holds line 0, which always exists, so it */                     \
+  /* issues all EPT stores; contiguous tiles only when no line is missing */                  \
+  stores_pending = g.layout == 0 || lines >= NL;                                               \
   lds_barrier();
 
 template <typename T, typename C, int KIND, int INV>

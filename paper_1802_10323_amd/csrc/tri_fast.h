@@ -439,6 +439,9 @@ void tri_async_kernel(TriFastArgs<T> A) {
 
   const TileRange tr = xcd_tiles(g.ntiles);
   if (tr.first < tr.end) stage_fetch<T, NL, N>(stage_lds, A.data, g, tr.first, tid0);
+  // stores of the previous tile, issued after the staged reads: RPC per
+  // thread when the tile was whole, else none counted
+  bool stores_pending = false;
   for (int tile = tr.first; tile < tr.end; tile += tr.step) {
     // thread indices opaque per tile: the compiler recomputes the addresses
     // instead of holding them all live across the loop (registers)
@@ -447,7 +450,9 @@ void tri_async_kernel(TriFastArgs<T> A) {
     const int c = tid % P;
     const int l = tid / P;
     const lptr<T> col = lds + c * L::CP + l;
-    __builtin_amdgcn_s_waitcnt(0);   // this wave's staged reads (and earlier stores) are done
+    // this wave's staged reads are done (the previous tile's stores may not be)
+    if (stores_pending) vm_wait_keep<RPC>();
+    else __builtin_amdgcn_s_waitcnt(0);
     lds_barrier();                   // ... and every wave's
     if (g.layout == 0) {
       const int ll = tid % NL, q = tid / NL;
@@ -485,6 +490,9 @@ void tri_async_kernel(TriFastArgs<T> A) {
       lines = min(g.nlines - o.L0, nlt);
     }
     tri_fast_store_body<T, RPC, P>(lds, as_global(A.data), base, g.sp, g.layout, lines, tid);
+    // strided tiles: every wave holds line 0, which always exists, so it
+    // issues all RPC stores; contiguous tiles only when no line is missing
+    stores_pending = g.layout == 0 || lines >= NL;
     lds_barrier();
   }
 }

@@ -23,16 +23,15 @@ ELIM_LENGTHS = [64, 96, 128, 192, 256, 384, 512]
 
 @pytest.fixture
 def default_variants():
-    """Put every entry of the variant table back to its default afterwards
-    (the staging transform for lengths 256 and 512, variant 0 otherwise)."""
-    from paper_1802_10323_amd import set_tuned_variant
+    """Put every entry of the variant table back to what it was before the
+    test."""
+    from paper_1802_10323_amd import set_tuned_variant, tuned_variant
+    keys = [(0, 2 * M, layout, fp64) for M in FAST_M for layout in (0, 1) for fp64 in (True, False)]
+    keys += [(1, n, layout, fp64) for n in ELIM_LENGTHS for layout in (0, 1) for fp64 in (True, False)]
+    saved = [(k, tuned_variant(*k)) for k in keys]
     yield
-    for fp64 in (True, False):
-        for layout in (0, 1):
-            for M in FAST_M:
-                set_tuned_variant(0, 2 * M, layout, 4 if M in (128, 256) else 0, fp64)
-            for n in ELIM_LENGTHS:
-                set_tuned_variant(1, n, layout, 0, fp64)
+    for (family, n, layout, fp64), v in saved:
+        set_tuned_variant(family, n, layout, v, fp64)
 
 
 def say(*a):
@@ -539,11 +538,11 @@ def test_server_admission_by_hbm_budget():
 # --------------------------------------------------------------- kernel variants
 
 
-@pytest.mark.parametrize("V", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("V", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("M", FAST_M)
 def test_transform_variants(M, V, default_variants):
     """Every compiled transform variant (tile shape x radix order, and the
-    asynchronous-staging form) against the Table 2 sums, all five types,
+    asynchronous-staging form in both tile shapes) against the Table 2 sums, all five types,
     contiguous and strided (one partial and one multi-tile strided case, and
     an odd row length that the staging form must hand to variant 0); round
     trip is the identity."""
@@ -616,7 +615,7 @@ def test_autotune_records_fastest(default_variants):
     for prec, fp64 in (("fp64", True), ("fp32", False)):
         r = rep[prec]
         assert all(v > 0 for v in r["t1"][:4] + r["t2"][:4] + r["elimination"])
-        assert r["t2"][4] == -1.0        # no staging transform for length 96
+        assert r["t2"][4] == r["t2"][5] == -1.0   # no staging transform for length 96
         t1 = [v if v > 0 else np.inf for v in r["t1"]]
         assert tuned_variant(0, 128, 1, fp64) == int(np.argmin(t1))
         assert tuned_variant(0, 96, 0, fp64) == int(np.argmin(r["t2"][:4]))
