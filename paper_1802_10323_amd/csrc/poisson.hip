@@ -945,6 +945,7 @@ static int solve_refined(poisson_plan* p, double* rhs, hipStream_t st) {
   const RefineGeom G = refine_geom(p);
   const int nb = (int)std::min<long long>(REFINE_BLOCKS, (N + REFINE_NT - 1) / REFINE_NT);
   const dim3 grid(nb), block(REFINE_NT);
+  const ResidualGrid rg = residual_grid(p->dims[0], p->dims[1], p->dims[2]);
   hipLaunchKernelGGL(refine_init_kernel, dim3(1), dim3(256), 0, st, p->stats);
   if (p->singular) {
     hipLaunchKernelGGL(refine_wsum_kernel, grid, block, 0, st, (const double*)rhs, G);
@@ -957,8 +958,8 @@ static int solve_refined(poisson_plan* p, double* rhs, hipStream_t st) {
   if ((rc = solve_typed<float>(p, p->e32, st))) return rc;
   hipLaunchKernelGGL(refine_widen_kernel, grid, block, 0, st, (const float*)p->e32, rhs, N);
   for (int sweep = 1; sweep < p->max_iters; ++sweep) {
-    hipLaunchKernelGGL(refine_residual_kernel, grid, block, 0, st, (const double*)rhs,
-                       (const double*)p->f64, p->e32, G);
+    hipLaunchKernelGGL(refine_residual_kernel, dim3(rg.blocks), block, 0, st, (const double*)rhs,
+                       (const double*)p->f64, p->e32, G, rg);
     if ((rc = solve_typed<float>(p, p->e32, st, p->stats))) return rc;
     hipLaunchKernelGGL(refine_update_kernel, grid, block, 0, st, rhs, (const float*)p->e32, G);
     hipLaunchKernelGGL(refine_status_kernel, dim3(1), block, 0, st, p->stats, nb, sweep, p->tol);

@@ -13,6 +13,8 @@
 //   [4 + 2s], [5 + 2s]: ||e_s||^2 and ||Phi_s||^2 of sweep s (-1 if not run)
 //   [REFINE_PARTIALS ...]: per-block partial sums (2 per block)
 #pragma once
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace poisson_dev {
@@ -56,12 +58,31 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
   b = sh[NT];
 }
 
-__device__ __forceinline__ void decompose(long long idx, int nx, int ny, int& i, int& j, int& k) {
-  i = (int)(idx % nx);
-  const long long r = idx / nx;
-  j = (int)(r % ny);
-  k = (int)(r / ny);
-}
+// Grid position (i, j, k) of point idx, advanced by a fixed step without
+// 64-bit divisions in the loop (only the set-up divides).
+struct GridWalk {
+  int i, j, k, di, dj, dk, nx, ny;
+  __device__ GridWalk(long long idx, long long step, int nx_, int ny_) : nx(nx_), ny(ny_) {
+    const long long plane = (long long)nx * ny;
+    k = (int)(idx / plane);
+    const int r = (int)(idx - k * plane);
+    j = r / nx;
+    i = r - j * nx;
+    dk = (int)(step / plane);
+    const int rs = (int)(step - dk * plane);
+    dj = rs / nx;
+    di = rs - dj * nx;
+  }
+  __device__ void advance() {
+    i += di;
+    int cj = 0;
+    if (i >= nx) { i -= nx; cj = 1; }
+    j += dj + cj;
+    int ck = 0;
+    if (j >= ny) { j -= ny; ck = 1; }
+    k += dk + ck;
+  }
+};
 
 // reset the status block (a fill kernel rather than a memset, so the
 // sequence can be captured in a graph)
@@ -75,12 +96,11 @@ __global__ __launch_bounds__(REFINE_NT) void refine_wsum_kernel(const double* __
                                                                  RefineGeom G) {
   __shared__ double sh[2 * REFINE_NT];
   double sx = 0.0, sw = 0.0;
-  const int nx = G.ax[0].n, ny = G.ax[1].n;
-  for (long long idx = blockIdx.x * (long long)REFINE_NT + threadIdx.x; idx < G.npts;
-       idx += (long long)gridDim.x * REFINE_NT) {
-    int i, j, k;
-    decompose(idx, nx, ny, i, j, k);
-    const double w = G.ax[0].h[i] * G.ax[1].h[j] * G.ax[2].h[k];
+  const long long step = (long long)gridDim.x * REFINE_NT;
+  const long long first = blockIdx.x * (long long)REFINE_NT + threadIdx.x;
+  GridWalk at(first, step, G.ax[0].n, G.ax[1].n);
+  for (long long idx = first; idx < G.npts; idx += step, at.advance()) {
+    const double w = G.ax[0].h[at.i] * G.ax[1].h[at.j] * G.ax[2].h[at.k];
     sx += w * x[idx];
     sw += w;
   }
@@ -137,33 +157,65 @@ __global__ __launch_bounds__(REFINE_NT) void refine_shift_kernel(double* __restr
     x[idx] -= mean;
 }
 
-__device__ __forceinline__ double op_axis(const OpAxis& A, const double* __restrict__ phi,
-                                          long long idx, long long stride, int q, double centre) {
-  // a_q phi_{q-1} + b_q phi_q + c_q phi_{q+1}; a_0 / c_{n-1} are the periodic
-  // wrap couplings (zero at a wall, where the ghost rule is in b)
-  const int n = A.n;
-  const long long lo = q > 0 ? idx - stride : idx + (long long)(n - 1) * stride;
-  const long long hi = q < n - 1 ? idx + stride : idx - (long long)(n - 1) * stride;
-  return A.a[q] * phi[lo] + A.b[q] * centre + A.c[q] * phi[hi];
+// Launch shape of refine_residual_kernel: blocks of REFINE_NT points of an
+// xy plane, each marching through `kz` consecutive planes; `blocks` is the
+// block count rounded up to a multiple of 8 (see refine_residual_kernel).
+struct ResidualGrid {
+  int plane_blocks, kz, z_chunks, blocks;
+};
+
+inline ResidualGrid residual_grid(int nx, int ny, int nz) {
+  ResidualGrid r;
+  r.plane_blocks = (int)(((long long)nx * ny + REFINE_NT - 1) / REFINE_NT);
+  // about 2048 blocks in all, at least 4 planes each
+  r.kz = (int)std::max<long long>(4, ((long long)nz * r.plane_blocks + 2047) / 2048);
+  r.kz = std::min(r.kz, nz);
+  r.z_chunks = (nz + r.kz - 1) / r.kz;
+  r.blocks = (r.plane_blocks * r.z_chunks + 7) / 8 * 8;
+  return r;
 }
 
-// e32 = (float)(f64 - A phi), FP64 arithmetic
+// e32 = (float)(f64 - A phi), FP64 arithmetic.  One thread per point of an
+// xy plane, marching through kz planes with phi of the planes below, at and
+// above in registers (each phi value is read from HBM about once; its x and
+// y neighbours come from the caches).  The 8 XCDs receive consecutive
+// blocks round-robin: block b works on chunk (b mod 8) * (blocks / 8) +
+// b / 8, so each XCD sweeps a contiguous run of rows, whose y neighbours its
+// own L2 holds.
 __global__ __launch_bounds__(REFINE_NT) void refine_residual_kernel(const double* __restrict__ phi,
                                                                      const double* __restrict__ f64,
                                                                      float* __restrict__ e32,
-                                                                     RefineGeom G) {
+                                                                     RefineGeom G, ResidualGrid rg) {
   if (refine_skip(G.stats)) return;
-  const int nx = G.ax[0].n, ny = G.ax[1].n;
-  const long long sy = nx, sz = (long long)nx * ny;
-  for (long long idx = blockIdx.x * (long long)REFINE_NT + threadIdx.x; idx < G.npts;
-       idx += (long long)gridDim.x * REFINE_NT) {
-    int i, j, k;
-    decompose(idx, nx, ny, i, j, k);
-    const double c = phi[idx];
-    double Ap = op_axis(G.ax[0], phi, idx, 1, i, c);
-    Ap += op_axis(G.ax[1], phi, idx, sy, j, c);
-    Ap += op_axis(G.ax[2], phi, idx, sz, k, c);
-    e32[idx] = (float)(f64[idx] - Ap);
+  const int chunk = (int)(blockIdx.x % 8) * (rg.blocks / 8) + (int)(blockIdx.x / 8);
+  if (chunk >= rg.plane_blocks * rg.z_chunks) return;
+  const int nx = G.ax[0].n, ny = G.ax[1].n, nz = G.ax[2].n;
+  const int p = (chunk % rg.plane_blocks) * REFINE_NT + (int)threadIdx.x;
+  if (p >= nx * ny) return;
+  const int k0 = (chunk / rg.plane_blocks) * rg.kz;
+  const int k1 = min(k0 + rg.kz, nz);
+  const int i = p % nx, j = p / nx;
+  const OpAxis& X = G.ax[0];
+  const OpAxis& Y = G.ax[1];
+  const OpAxis& Z = G.ax[2];
+  // a_q phi_{q-1} + b_q phi_q + c_q phi_{q+1} per axis; a_0 / c_{n-1} are
+  // the periodic wrap couplings (zero at a wall, where the ghost rule is in b)
+  const double ax = X.a[i], bx = X.b[i], cx = X.c[i];
+  const double ay = Y.a[j], by = Y.b[j], cy = Y.c[j];
+  const int xl = (i > 0 ? i - 1 : nx - 1) - i, xh = (i < nx - 1 ? i + 1 : 0) - i;
+  const int yl = ((j > 0 ? j - 1 : ny - 1) - j) * nx, yh = ((j < ny - 1 ? j + 1 : 0) - j) * nx;
+  const long long plane = (long long)nx * ny;
+  double below = phi[(k0 > 0 ? k0 - 1 : nz - 1) * plane + p];
+  double at = phi[k0 * plane + p];
+  for (int k = k0; k < k1; ++k) {
+    const long long o = k * plane + p;
+    const double above = phi[(k < nz - 1 ? o + plane : (long long)p)];
+    const double opx = ax * phi[o + xl] + bx * at + cx * phi[o + xh];
+    const double opy = ay * phi[o + yl] + by * at + cy * phi[o + yh];
+    const double opz = Z.a[k] * below + Z.b[k] * at + Z.c[k] * above;
+    e32[o] = (float)(f64[o] - ((opx + opy) + opz));
+    below = at;
+    at = above;
   }
 }
 
