@@ -171,14 +171,17 @@ void batch_destroy(poisson_batch* batch);
  * transforms, variants 0-3 are two tile shapes (lines per tile x threads per
  * line) times two FFT radix orders (radix 8 first or radix 4 first), and
  * variants 4 and 5 (lengths 256 and 512 only; the two tile shapes) read the
- * next tile straight into LDS while the current one is transformed; for the elimination, variants 0-1
+ * next tile straight into LDS while the current one is transformed, and
+ * variant 6 does so in FP32 for length 512 with 32 lines per tile (in FP64
+ * it runs variant 0); for the elimination, variants 0-1
  * are two chunkings (rows per chunk x chunks per line) and variant 2 reads
  * the next tile into LDS while the current one is eliminated.  All give the same result up to
  * rounding.  The variant used for a length is chosen per device, precision
  * and layout (strided: the axis is y or z; contiguous: x) from a
  * process-wide table; where nothing was tuned, a staging transform for
  * lengths 256 and 512 (variant 5 for FP64 length 256 and for FP32 length 512
- * on the contiguous axis, else 4) and variant 0 otherwise.  Plans and batches read the
+ * on the contiguous axis, 6 for FP32 length 512 on the strided axes, else 4)
+ * and variant 0 otherwise.  Plans and batches read the
  * table when they launch (batches when they are bound; batches use the
  * synchronous variants only: transforms 0-3, elimination 0-1). */
 
@@ -186,8 +189,8 @@ void batch_destroy(poisson_batch* batch);
  * elimination, FP64 and FP32) on `scratch` (DEVICE, at least nx*ny*nz
  * doubles; overwritten), `reps` launches each after one warm-up, and record
  * the fastest in the table.  Synchronous (waits for `stream`).  report (HOST,
- * may be NULL): 2 x (6 + 6 + 3) doubles, per precision (FP64 first) the
- * average ms of variants 0-5 of t1, 0-5 of t2 (forward + backward pair) and
+ * may be NULL): 2 x (7 + 7 + 3) doubles, per precision (FP64 first) the
+ * average ms of variants 0-6 of t1, 0-6 of t2 (forward + backward pair) and
  * 0-2 of the elimination, -1 where a variant does not apply. */
 int plan_autotune(poisson_plan* plan, double* scratch, int reps, hipStream_t stream, double* report);
 

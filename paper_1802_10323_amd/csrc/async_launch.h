@@ -17,9 +17,10 @@
 namespace poisson_dev {
 
 // Launch the staging transform for complex length M (128 or 256), tile
-// shape `shape` (0 or 1, the shapes of FastVar<M, shape>), transform type
-// `kind` and direction `inverse`, arguments as for r2r_fast_kernel with that
-// tile shape.  hipErrorInvalidValue if (M, shape, kind) has no instantiation.
+// shape `shape` (AsyncVar<M, shape>: 0 or 1, and 2 for FP32 length 512),
+// transform type `kind` and direction `inverse`, arguments as for
+// r2r_fast_kernel with that tile shape.  hipErrorInvalidValue if (M, shape,
+// kind) has no instantiation.
 hipError_t async_transform_launch(const R2RFastArgs<double>& a, int M, int shape, int kind,
                                   int inverse, hipStream_t stream);
 hipError_t async_transform_launch(const R2RFastArgs<float>& a, int M, int shape, int kind,

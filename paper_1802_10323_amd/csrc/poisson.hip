@@ -173,8 +173,8 @@ struct TriCfg {
   static constexpr int RPC = RPC_, P = P_;
 };
 
-static constexpr int kFastVariants = 6;   // transform: tile shape x radix order, + asynchronous staging
-static constexpr int kAsyncVariant = 4;   // 4 and 5: asynchronous staging in tile shape 0 and 1
+static constexpr int kFastVariants = 7;   // transform: tile shape x radix order, + asynchronous staging
+static constexpr int kAsyncVariant = 4;   // 4, 5, 6: asynchronous staging in tile shape 0, 1, 2
 static constexpr int kTriVariants = 3;    // elimination: two chunkings, + asynchronous staging
 static constexpr int kTriAsyncVariant = 2;
 
@@ -219,12 +219,15 @@ static std::map<std::tuple<int, int, int, int, int>, int> g_tune;
 // for the lengths it is compiled for, else variant 0.  Its tile shape:
 // shape 1 (half the lines per tile, so that twice the blocks fit in a CU's
 // LDS) for FP64 length 256 and for FP32 length 512 on the contiguous axis,
-// where the extra overlap pays most; else shape 0, whose wider tile rows
-// (128-256 bytes on the strided axes) use each DRAM page better.
+// where the extra overlap pays most; shape 2 (32 lines) for FP32 length 512
+// on the strided axes, whose tile rows are then 128 bytes long; else shape
+// 0, whose wider tile rows use each DRAM page better.
 static int default_choice(int family, int bytes, int n, int layout) {
   if (family != 0 || (n != 128 && n != 256)) return 0;
-  const bool shape1 = bytes == 8 ? n == 128 : (n == 256 && layout == 1);
-  return kAsyncVariant + (shape1 ? 1 : 0);
+  int shape = 0;
+  if (bytes == 8 && n == 128) shape = 1;
+  if (bytes == 4 && n == 256) shape = layout == 1 ? 1 : 2;
+  return kAsyncVariant + shape;
 }
 
 static int tuned_choice(int family, int bytes, int n, int layout) {
@@ -390,17 +393,26 @@ static int launch_fast(const poisson_plan* p, const AxisTables& A, int inverse, 
 // Asynchronous-staging form (r2r_fast.h) for lengths 2M, M in {128, 256};
 // -1 if it does not apply (length, or strided rows that do not split into
 // 16-byte pieces).
+// Staging-transform tile shapes compiled for length M = n/2 in type T.
+template <typename T>
+static bool async_shape_exists(int m, int shape) {
+  if (m != 128 && m != 256) return false;
+  return shape == 0 || shape == 1 || (shape == 2 && m == 256 && sizeof(T) == 4);
+}
+
 template <typename T>
 static int launch_async(const poisson_plan* p, const AxisTables& A, int shape, int inverse,
                         T* data, hipStream_t st, const double* skip) {
   if (A.m != 128 && A.m != 256) return -1;
   if (A.axis != 0 && p->dims[0] % (int)(16 / sizeof(T)) != 0) return -1;
+  if (!async_shape_exists<T>(A.m, shape)) return -1;
   R2RFastArgs<T> a;
-  switch (A.m * 2 + shape) {
-    case 128 * 2 + 0: a = fast_args<T, FastVar<128, 0>>(p, A, inverse, data, skip); break;
-    case 128 * 2 + 1: a = fast_args<T, FastVar<128, 1>>(p, A, inverse, data, skip); break;
-    case 256 * 2 + 0: a = fast_args<T, FastVar<256, 0>>(p, A, inverse, data, skip); break;
-    default: a = fast_args<T, FastVar<256, 1>>(p, A, inverse, data, skip); break;
+  switch (A.m * 4 + shape) {
+    case 128 * 4 + 0: a = fast_args<T, AsyncVar<128, 0>>(p, A, inverse, data, skip); break;
+    case 128 * 4 + 1: a = fast_args<T, AsyncVar<128, 1>>(p, A, inverse, data, skip); break;
+    case 256 * 4 + 0: a = fast_args<T, AsyncVar<256, 0>>(p, A, inverse, data, skip); break;
+    case 256 * 4 + 1: a = fast_args<T, AsyncVar<256, 1>>(p, A, inverse, data, skip); break;
+    default: a = fast_args<T, AsyncVar<256, 2>>(p, A, inverse, data, skip); break;
   }
   const hipError_t e = async_transform_launch(a, A.m, shape, A.kind, inverse, st);
   if (e != hipSuccess)
@@ -408,10 +420,11 @@ static int launch_async(const poisson_plan* p, const AxisTables& A, int shape, i
   return POISSON_OK;
 }
 
-// True if the asynchronous-staging form applies to axis A in type T.
+// True if the asynchronous-staging form in tile shape `shape` applies to
+// axis A in type T.
 template <typename T>
-static bool async_applies(const poisson_plan* p, const AxisTables& A) {
-  return (A.m == 128 || A.m == 256) &&
+static bool async_applies(const poisson_plan* p, const AxisTables& A, int shape) {
+  return async_shape_exists<T>(A.m, shape) &&
          (A.axis == 0 || p->dims[0] % (int)(16 / sizeof(T)) == 0);
 }
 
@@ -1249,7 +1262,7 @@ static int autotune_typed(poisson_plan* p, double* scratch, int reps, hipStream_
     int best = 0;
     double best_ms = 1e300;
     for (int V = 0; V < kFastVariants; ++V) {
-      if (V >= kAsyncVariant && !async_applies<T>(p, A)) continue;
+      if (V >= kAsyncVariant && !async_applies<T>(p, A, V - kAsyncVariant)) continue;
       if ((rc = reset())) return rc;
       // forward then backward: the field keeps its size over the repetitions
       const double ms = time_launches(st, reps, [&]() -> int {

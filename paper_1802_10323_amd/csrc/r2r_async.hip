@@ -30,11 +30,14 @@ hipError_t launch(const R2RFastArgs<T>& a, int kind, int inverse, hipStream_t st
 template <typename T>
 hipError_t launch_m(const R2RFastArgs<T>& a, int M, int shape, int kind, int inverse,
                     hipStream_t st) {
-  switch (M * 2 + shape) {
-    case 128 * 2 + 0: return launch<T, FastVar<128, 0>>(a, kind, inverse, st);
-    case 128 * 2 + 1: return launch<T, FastVar<128, 1>>(a, kind, inverse, st);
-    case 256 * 2 + 0: return launch<T, FastVar<256, 0>>(a, kind, inverse, st);
-    case 256 * 2 + 1: return launch<T, FastVar<256, 1>>(a, kind, inverse, st);
+  switch (M * 4 + shape) {
+    case 128 * 4 + 0: return launch<T, AsyncVar<128, 0>>(a, kind, inverse, st);
+    case 128 * 4 + 1: return launch<T, AsyncVar<128, 1>>(a, kind, inverse, st);
+    case 256 * 4 + 0: return launch<T, AsyncVar<256, 0>>(a, kind, inverse, st);
+    case 256 * 4 + 1: return launch<T, AsyncVar<256, 1>>(a, kind, inverse, st);
+    case 256 * 4 + 2:   // FP32 only: the FP64 tile and stage would not fit in LDS
+      if constexpr (sizeof(T) == 4) return launch<T, AsyncVar<256, 2>>(a, kind, inverse, st);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }

@@ -19,6 +19,7 @@
 // consecutive lines, i.e. consecutive x on a strided axis) and handles the
 // butterflies / elements q, q + QT, q + 2 QT, ... of that line, q = t / NL.
 #pragma once
+#include <type_traits>
 #include "r2r_kernel.h"
 
 namespace poisson_dev {
@@ -93,6 +94,12 @@ POISSON_FAST_SHAPES(256, 32, 16, 64, 8)
 
 template <int M, int V>
 using FastVar = FastCfg<M, FastShapes<M>::QT[V & 1], FastShapes<M>::NL[V & 1], (V >> 1) & 1>;
+
+// Tile shape of the staging transform (shape 0 and 1: those of FastVar;
+// shape 2: FP32 length 512 with 32 lines per tile, so that the rows of a
+// strided tile are 128 bytes long, as in FP64 with 16 lines).
+template <int M, int SHAPE>
+using AsyncVar = std::conditional_t<SHAPE == 2, FastCfg<M, 16, 32, 0>, FastVar<M, SHAPE>>;
 
 template <typename T>
 struct R2RFastArgs {

@@ -189,17 +189,17 @@ class Plan:
         """Time every kernel variant of this plan on ``scratch`` (a device
         float64 tensor of the field's size, overwritten) and record the
         fastest per length; returns the timing report (ms) as
-        {"fp64"|"fp32": {"t1": [6], "t2": [6], "elimination": [3]}}
+        {"fp64"|"fp32": {"t1": [7], "t2": [7], "elimination": [3]}}
         (-1 where a variant does not apply)."""
         if scratch.numel() < int(np.prod(self.shape)):
             raise ValueError("scratch is smaller than the field")
-        rep = (ctypes.c_double * 30)()
+        rep = (ctypes.c_double * 34)()
         _check(lib().plan_autotune(self.handle, _field_ptr(scratch), int(reps),
                                    _stream_handle(stream), rep))
         out = {}
         for k, name in enumerate(("fp64", "fp32")):
-            r = list(rep)[15 * k:15 * (k + 1)]
-            out[name] = {"t1": r[0:6], "t2": r[6:12], "elimination": r[12:15]}
+            r = list(rep)[17 * k:17 * (k + 1)]
+            out[name] = {"t1": r[0:7], "t2": r[7:14], "elimination": r[14:17]}
         return out
 
     def close(self):

@@ -538,11 +538,12 @@ def test_server_admission_by_hbm_budget():
 # --------------------------------------------------------------- kernel variants
 
 
-@pytest.mark.parametrize("V", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("V", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("M", FAST_M)
 def test_transform_variants(M, V, default_variants):
     """Every compiled transform variant (tile shape x radix order, and the
-    asynchronous-staging form in both tile shapes) against the Table 2 sums, all five types,
+    asynchronous-staging form in both tile shapes; variant 6, FP32 only,
+    falls back to variant 0 here) against the Table 2 sums, all five types,
     contiguous and strided (one partial and one multi-tile strided case, and
     an odd row length that the staging form must hand to variant 0); round
     trip is the identity."""
@@ -601,6 +602,22 @@ def test_fp32_variants_refine(vt, ve, default_variants):
     assert rel_l2(got, oracle_solve(prob)) <= 1e-10
 
 
+@pytest.mark.parametrize("vt", [4, 5, 6])
+def test_fp32_staging_variants_refine(vt, default_variants):
+    """FP32 staging transforms of length 512 (all three tile shapes), on the
+    contiguous axis (DCT-II) and on a strided one (DCT-IV), inside the
+    refined solve: it converges to the oracle within 1e-10."""
+    from paper_1802_10323_amd import set_tuned_variant
+    for layout in (0, 1):
+        set_tuned_variant(0, 512, layout, vt, fp64=False)
+    for shape, bcs in (((512, 24, 20), ("DD", "P", "NN")), ((48, 512, 18), ("P", "ND", "DD"))):
+        prob = inputs.make_uniform(*shape, bcs, seed=vt)
+        got, (iters, rel, conv) = gpu_solve(prob, mixed=True, tol=1e-10, max_iters=6)
+        say("fp32 staging", vt, shape, bcs, iters, rel)
+        assert conv and iters <= 4, (iters, rel)
+        assert rel_l2(got, oracle_solve(prob)) <= 1e-10
+
+
 def test_autotune_records_fastest(default_variants):
     """plan_autotune times every variant and keeps the fastest; solves with
     the tuned table still match the oracle, and a batch built afterwards is
@@ -615,7 +632,7 @@ def test_autotune_records_fastest(default_variants):
     for prec, fp64 in (("fp64", True), ("fp32", False)):
         r = rep[prec]
         assert all(v > 0 for v in r["t1"][:4] + r["t2"][:4] + r["elimination"])
-        assert r["t2"][4] == r["t2"][5] == -1.0   # no staging transform for length 96
+        assert r["t2"][4] == r["t2"][5] == r["t2"][6] == -1.0   # no staging transform for length 96
         t1 = [v if v > 0 else np.inf for v in r["t1"]]
         assert tuned_variant(0, 128, 1, fp64) == int(np.argmin(t1))
         assert tuned_variant(0, 96, 0, fp64) == int(np.argmin(r["t2"][:4]))
