@@ -165,6 +165,20 @@ int batch_launch(poisson_batch* batch, hipStream_t stream, int use_graph);
  * batch is still running. */
 void batch_destroy(poisson_batch* batch);
 
+/* Tune the bound batch as a whole: for each of the five steps, time its
+ * launch (`reps` times after one warm-up) with every job in the variant of
+ * the per-length table (see plan_autotune) and with every job in one
+ * synchronous variant (transforms 0-3, elimination 0-1), and keep the
+ * fastest for this batch.  A batched launch runs at the occupancy of its
+ * largest job configuration, so the fastest variant of each instance alone
+ * is not always the fastest together.  Synchronous; OVERWRITES the bound
+ * fields (bind the real ones afterwards: the choice is kept across binds).
+ * The results stay equal, bit for bit, to single solves with the chosen
+ * variants.  report (HOST, may be NULL): 5 x 5 doubles, per step (forward
+ * t1, forward t2, elimination, backward t2, backward t1) the average ms of
+ * the table choice and of variants 0-3, -1 where a variant does not apply. */
+int batch_autotune(poisson_batch* batch, int reps, hipStream_t stream, double* report);
+
 /* ---- autotuner: kernel variants per length ----
  *
  * Each specialised length has several compiled variants: for the

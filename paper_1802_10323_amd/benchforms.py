@@ -123,8 +123,17 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
     tune_s = time.perf_counter() - t0
     B.bind(work)
     measure("single_tuned", singles)
+    measure("graph_table", lambda: B.launch(graph=True))
+    # then the batch as a whole: per step, the per-length choices against one
+    # variant for every job (the launch runs at its largest job's occupancy)
+    t0 = time.perf_counter()
+    steps_report = B.autotune(reps=5)
+    tune_s += time.perf_counter() - t0
+    B.bind(work)
     measure("graph_tuned", lambda: B.launch(graph=True))
-    diff = max(diff, max_rel("graph_tuned", "single_tuned"))
+    diff = max(diff, max_rel("graph_table", "single_tuned"), max_rel("graph_tuned", "single_tuned"))
+    batch_choice = {s: ("table" if int(np.argmin(r)) == 0 else int(np.argmin(r)) - 1)
+                    for s, r in ((s, [v if v > 0 else np.inf for v in r]) for s, r in steps_report.items())}
     from . import tuned_variant
     chosen = {}
     for n in (64, 96, 128, 192, 256):
@@ -134,8 +143,9 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
                           "elimination_contiguous": tuned_variant(1, n, 1)}
     log(f"[forms] batch {count} instances ({points / 1e6:.1f} M points): one by one "
         f"{ms['single']:.3f} ms, batched {ms['batch']:.3f} ms, graph {ms['graph']:.3f} ms; "
-        f"autotuned ({tune_s:.1f} s): one by one {ms['single_tuned']:.3f} ms, graph "
-        f"{ms['graph_tuned']:.3f} ms; max relative difference to single solves {diff:.1e}")
+        f"autotuned ({tune_s:.1f} s): one by one {ms['single_tuned']:.3f} ms, graph with per-length "
+        f"variants {ms['graph_table']:.3f} ms, graph tuned as a batch {ms['graph_tuned']:.3f} ms; "
+        f"max relative difference to single solves {diff:.1e}")
     B.close()
     for pl in plans:
         pl.close()
@@ -146,9 +156,12 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
             "speedup_vs_single": round(ms["single"] / ms["graph"], 4),
             "autotune_s": round(tune_s, 2),
             "single_tuned_ms": round(ms["single_tuned"], 4),
+            "graph_per_length_tuned_ms": round(ms["graph_table"], 4),
             "graph_tuned_ms": round(ms["graph_tuned"], 4),
             "graph_tuned_points_per_s": points / (ms["graph_tuned"] * 1e-3),
+            "speedup_tuned_vs_single_tuned": round(ms["single_tuned"] / ms["graph_tuned"], 4),
             "tuned_variants": chosen,
+            "batch_step_choice": batch_choice,
             "max_rel_diff_vs_single": diff}
 
 

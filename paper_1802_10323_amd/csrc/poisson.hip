@@ -1037,6 +1037,8 @@ struct poisson_batch {
   size_t off[5] = {0, 0, 0, 0, 0};    // byte offset of each step's job array
   size_t bytes = 0;
   char* djobs = nullptr;              // device job arrays (all steps)
+  int force[5] = {-1, -1, -1, -1, -1};  // variant of every job of a step (-1: per-length table)
+  std::vector<double*> rhs;           // bound fields
   bool bound = false;
   hipStream_t cap = nullptr;          // private stream for graph capture
   hipGraph_t graph = nullptr;
@@ -1044,7 +1046,8 @@ struct poisson_batch {
 };
 
 // Job tables of every step for the given fields (null fields: sizes only),
-// with the variants chosen now; sets item counts and LDS sizes.
+// with the variants chosen now (the batch's own choice for a step if it has
+// one, else the per-length table); sets item counts and LDS sizes.
 static void batch_jobs(poisson_batch* b, double* const* rhs, std::vector<char>& host) {
   host.assign(b->bytes, 0);
   for (int k = 0; k < 5; ++k) {
@@ -1058,7 +1061,7 @@ static void batch_jobs(poisson_batch* b, double* const* rhs, std::vector<char>& 
         const AxisTables& A = p->ax[kStepRole[k]];
         BatchR2RJob<double> J{};
         J.M = A.m;
-        J.V = tuned_choice(0, sizeof(double), A.m, A.axis == 0);
+        J.V = b->force[k] >= 0 ? b->force[k] : tuned_choice(0, sizeof(double), A.m, A.axis == 0);
         if (J.V >= 4) J.V = 0;   // the batched kernel has the synchronous variants
         with_fast_cfg(J.M, J.V, [&](auto cfg) {
           using C = decltype(cfg);
@@ -1072,7 +1075,7 @@ static void batch_jobs(poisson_batch* b, double* const* rhs, std::vector<char>& 
       } else {
         const int n = p->dims[p->s];
         BatchTriJob<double> J{};
-        const int tv = tuned_choice(1, sizeof(double), n, p->s == 0);
+        const int tv = b->force[k] >= 0 ? b->force[k] : tuned_choice(1, sizeof(double), n, p->s == 0);
         J.key = 2 * n + (tv < 2 ? tv : 0);   // the batched kernel has the synchronous chunkings
         with_tri_cfg(n, J.key & 1, [&](auto cfg) {
           using C = decltype(cfg);
@@ -1144,17 +1147,18 @@ extern "C" poisson_batch* batch_create(poisson_plan* const* plans, int count) {
   return b;
 }
 
-extern "C" int batch_bind(poisson_batch* b, double* const* rhs) {
-  if (!b || !rhs) return fail(POISSON_EINVAL, "null argument");
-  for (size_t i = 0; i < b->plans.size(); ++i)
-    if (!rhs[i]) return fail(POISSON_EINVAL, "null field at batch index %zu", i);
+// Job tables for the bound fields to the device (synchronous).  The
+// captured launches carry the LDS size, grid and item count of each step:
+// when the variants changed them, capture again at the next launch.
+static int batch_upload(poisson_batch* b) {
   size_t lds_before[5];
+  int items_before[5];
   std::memcpy(lds_before, b->lds, sizeof(lds_before));
+  std::memcpy(items_before, b->items, sizeof(items_before));
   std::vector<char> host;
-  batch_jobs(b, rhs, host);
-  if (b->exec && std::memcmp(lds_before, b->lds, sizeof(lds_before)) != 0) {
-    // the variants changed (autotuner) and with them the LDS sizes: the
-    // captured launches no longer fit; capture again at the next launch
+  batch_jobs(b, b->rhs.data(), host);
+  if (b->exec && (std::memcmp(lds_before, b->lds, sizeof(lds_before)) != 0 ||
+                  std::memcmp(items_before, b->items, sizeof(items_before)) != 0)) {
     (void)hipGraphExecDestroy(b->exec);
     (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
@@ -1165,9 +1169,17 @@ extern "C" int batch_bind(poisson_batch* b, double* const* rhs) {
   return POISSON_OK;
 }
 
-static int batch_enqueue(poisson_batch* b, hipStream_t st) {
-  for (int k = 0; k < 5; ++k) {
-    if (b->items[k] == 0) continue;
+extern "C" int batch_bind(poisson_batch* b, double* const* rhs) {
+  if (!b || !rhs) return fail(POISSON_EINVAL, "null argument");
+  for (size_t i = 0; i < b->plans.size(); ++i)
+    if (!rhs[i]) return fail(POISSON_EINVAL, "null field at batch index %zu", i);
+  b->rhs.assign(rhs, rhs + b->plans.size());
+  return batch_upload(b);
+}
+
+static int batch_enqueue_step(poisson_batch* b, int k, hipStream_t st) {
+  {
+    if (b->items[k] == 0) return POISSON_OK;
     const size_t lds = b->lds[k];
     if (kStepRole[k] >= 0) {
       const auto* jobs = reinterpret_cast<const BatchR2RJob<double>*>(b->djobs + b->off[k]);
@@ -1181,6 +1193,14 @@ static int batch_enqueue(poisson_batch* b, hipStream_t st) {
                          dim3(512), lds, st, jobs, b->njobs[k], b->items[k]);
     }
     HIP_TRY(hipGetLastError());
+  }
+  return POISSON_OK;
+}
+
+static int batch_enqueue(poisson_batch* b, hipStream_t st) {
+  for (int k = 0; k < 5; ++k) {
+    const int rc = batch_enqueue_step(b, k, st);
+    if (rc) return rc;
   }
   return POISSON_OK;
 }
@@ -1306,6 +1326,44 @@ extern "C" int plan_autotune(poisson_plan* p, double* scratch, int reps, hipStre
   if (!rc) rc = autotune_typed<float>(p, scratch, reps, st,
                                       report ? report + 2 * kFastVariants + kTriVariants : nullptr);
   return rc;
+}
+
+// Choice per step of a bound batch: every job of the step in the variant of
+// the per-length table, or all in one synchronous variant.  A batch launch
+// runs at the occupancy of its largest job configuration (its LDS), so the
+// fastest variant of each instance alone is not always the fastest mix.
+static constexpr int kBatchCandidates = 5;   // table, then variants 0-3 (elimination: 0-1)
+
+extern "C" int batch_autotune(poisson_batch* b, int reps, hipStream_t st, double* report) {
+  if (!b) return fail(POISSON_EINVAL, "null batch");
+  if (!b->bound) return fail(POISSON_EINVAL, "batch has no fields bound (batch_bind)");
+  if (reps < 1 || reps > 1000) return fail(POISSON_EINVAL, "reps must be in [1, 1000]");
+  if (report)
+    for (int i = 0; i < 5 * kBatchCandidates; ++i) report[i] = -1.0;
+  HIP_TRY(hipStreamSynchronize(st));   // nothing of the batch in flight before its tables change
+  auto reset = [&]() -> int {
+    for (size_t i = 0; i < b->plans.size(); ++i)
+      hipLaunchKernelGGL(fill_kernel, dim3(256), dim3(256), 0, st, b->rhs[i],
+                         (long long)field_points(b->plans[i]), 0.5);
+    HIP_TRY(hipGetLastError());
+    return POISSON_OK;
+  };
+  int rc = POISSON_OK;
+  for (int k = 0; k < 5; ++k) {
+    const int count = kStepRole[k] >= 0 ? 4 : 2;
+    int best = -1;
+    double best_ms = 1e300;
+    for (int c = -1; c < count; ++c) {
+      b->force[k] = c;
+      if ((rc = batch_upload(b)) || (rc = reset())) return rc;
+      const double ms = time_launches(st, reps, [&]() { return batch_enqueue_step(b, k, st); }, rc);
+      if (rc) return rc;
+      if (report) report[k * kBatchCandidates + c + 1] = ms;
+      if (ms < best_ms) { best_ms = ms; best = c; }
+    }
+    b->force[k] = best;
+  }
+  return batch_upload(b);
 }
 
 extern "C" int set_tuned_variant(int family, int n, int layout, int fp64, int variant) {

@@ -42,6 +42,7 @@ SIGNATURES = {
     "batch_bind": (ctypes.c_int, [_VP, ctypes.POINTER(_VP)]),
     "batch_launch": (ctypes.c_int, [_VP, _VP, ctypes.c_int]),
     "batch_destroy": (None, [_VP]),
+    "batch_autotune": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.POINTER(ctypes.c_double)]),
     "plan_autotune": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP, ctypes.POINTER(ctypes.c_double)]),
     "tuned_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "set_tuned_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -254,6 +255,17 @@ class Batch:
     def launch(self, stream=None, graph=False):
         """Enqueue the five stage launches (or replay them as a HIP graph)."""
         _check(lib().batch_launch(self._h, _stream_handle(stream), int(bool(graph))))
+
+    def autotune(self, reps=5, stream=None):
+        """Pick the variant of each step for this batch as a whole
+        (``batch_autotune``); overwrites the bound fields.  Returns the
+        timings (ms) per step: [table, variant 0, 1, 2, 3], -1 where a
+        variant does not apply."""
+        rep = (ctypes.c_double * 25)()
+        _check(lib().batch_autotune(self._h, int(reps), _stream_handle(stream), rep))
+        r = list(rep)
+        steps = ("fwd_t1", "fwd_t2", "tridiag", "inv_t2", "inv_t1")
+        return {s: r[5 * k:5 * (k + 1)] for k, s in enumerate(steps)}
 
     def close(self):
         if getattr(self, "_h", None) is not None:

@@ -654,3 +654,37 @@ def test_autotune_records_fastest(default_variants):
     for pl in plans:
         pl.close()
     plan.close()
+
+
+def test_batch_autotune_whole_batch():
+    """batch_autotune times each step with the per-length choices and with
+    every synchronous variant for all jobs, and keeps the fastest; a graph
+    captured before tuning is captured again where the tuning changed its
+    launches, and the tuned batch still matches the oracle and the single
+    solves (to rounding: its steps may mix variants a single solve cannot)."""
+    from paper_1802_10323_amd import Batch, Plan
+    probs = inputs.batch(11, count=6)
+    plans = [Plan.from_problem(p) for p in probs]
+    fields = [to_dev(p.rhs) for p in probs]
+    b = Batch(plans)
+    b.bind(fields)
+    b.launch(graph=True)                # captured with the default choices
+    rep = b.autotune(reps=2)
+    say("batch autotune", rep)
+    for step, r in rep.items():
+        count = 3 if step == "tridiag" else 5
+        assert all(v > 0 for v in r[:count]), (step, r)
+        assert all(v == -1.0 for v in r[count:]), (step, r)
+    for _ in range(2):                  # replays of the (re)captured graph
+        fresh = [to_dev(p.rhs) for p in probs]
+        b.bind(fresh)
+        b.launch(graph=True)
+        for p, f in zip(probs, fresh):
+            got = to_host(f)
+            single, _ = gpu_solve(p)
+            assert rel_l2(got, single) <= 1e-14, p.shape
+            if p.points <= 300_000:
+                assert rel_l2(got, oracle_solve(p)) <= TOL64, p.shape
+    b.close()
+    for pl in plans:
+        pl.close()
