@@ -742,6 +742,119 @@ __device__ __forceinline__ void async_place(lptr<const T> stage, lptr<T> lds, in
   }
 }
 
+// Inverse P/NN/DD, fused with the placement: the spectrum is read from the
+// stage (input point p of a line sits in tile row p, DD: row n-1-p) and
+// the length-M spectrum Z' of fast_combine_body is written into the tile.
+// The strided layout keeps the lines on consecutive lanes; the contiguous
+// one puts a line's points on consecutive lanes (the stage holds whole
+// lines there), so that both read the stage without bank conflicts.
+template <typename T, typename C>
+__device__ __forceinline__ void async_place_combine(lptr<const T> stage, lptr<T> lds,
+                                                    lptr<const cplx<T>> split,
+                                                    lptr<const cplx<T>> quarter, int kind,
+                                                    int layout, int l, int q, int tid) {
+  using L = FastLayout<T, C>;
+  constexpr int M = L::M, N = L::N, NL = L::NL, NLP = L::NLP, QT = L::QT;
+  constexpr int NP = M / 2 + 1;
+  constexpr int SP = (NP + QT - 1) / QT;
+  const int ln = layout == 0 ? l : tid / QT;
+  const int qq = layout == 0 ? q : tid % QT;
+  auto row = [&](int r) -> T {   // tile row r of line ln, as the placement would leave it
+    const int p = kind == K_DD ? N - 1 - r : r;
+    return layout == 0 ? stage[p * NL + ln] : stage[ln * N + p];
+  };
+#pragma unroll
+  for (int s = 0; s < SP; ++s) {
+    const int k = qq + s * QT;
+    if (k < NP) {
+      const int j = M - k;
+      cplx<T> xk, xj;
+      if (kind == K_P) {
+        xk = k == 0 ? cplx<T>{row(0), (T)0} : cplx<T>{row(2 * k - 1), -row(2 * k)};
+        xj = j == M ? cplx<T>{row(N - 1), (T)0} : cplx<T>{row(2 * j - 1), -row(2 * j)};
+      } else {
+        const T yk = row(k), ynk = k == 0 ? (T)0 : row(N - k);
+        const T yj = row(j), ynj = row(N - j);
+        xk = cmul(cconj(ldc(quarter, k)), cplx<T>{(T)0.5 * yk, (T)-0.5 * ynk});
+        xj = cmul(cconj(ldc(quarter, j)), cplx<T>{(T)0.5 * yj, (T)-0.5 * ynj});
+      }
+      const cplx<T> sk = ldc(split, k);
+      const cplx<T> s1 = cadd(xk, cconj(xj));
+      const cplx<T> d1 = cmul(csub(xk, cconj(xj)), cconj(sk));
+      lds[(2 * k) * NLP + ln] = s1.re - d1.im;
+      lds[(2 * k + 1) * NLP + ln] = s1.im + d1.re;
+      if (k > 0 && j != k) {
+        const cplx<T> s2 = cadd(xj, cconj(xk));
+        const cplx<T> d2 = cmul(csub(cconj(xk), xj), sk);
+        lds[(2 * j) * NLP + ln] = s2.re - d2.im;
+        lds[(2 * j + 1) * NLP + ln] = s2.im + d2.re;
+      }
+    }
+  }
+}
+
+// Forward P/NN/DD, fused with the store: the even/odd split of
+// fast_split_body, written straight to the field (the forward output order
+// of these types is the tile's row order).  Strided layout: lines on
+// consecutive lanes (rows of NL values); contiguous: a line's points on
+// consecutive lanes.
+template <typename T, typename C>
+__device__ __forceinline__ void async_split_store(lptr<const T> lds, lptr<const cplx<T>> split,
+                                                  lptr<const cplx<T>> quarter, int kind,
+                                                  gptr<T> data, long long base, long long sp,
+                                                  int layout, int lines, T scale, int l, int q,
+                                                  int tid) {
+  using L = FastLayout<T, C>;
+  constexpr int M = L::M, N = L::N, NLP = L::NLP, QT = L::QT;
+  constexpr int NP = M / 2 + 1;
+  constexpr int SP = (NP + QT - 1) / QT;
+  const int ln = layout == 0 ? l : tid / QT;
+  const int qq = layout == 0 ? q : tid % QT;
+  const long long lb = layout == 0 ? base : base + (long long)ln * N;
+  const long long ps = layout == 0 ? sp : 1;
+  if (layout == 0 ? base < 0 : ln >= lines) return;   // line outside the field
+  auto put = [&](int r, T v) { data[lb + r * ps] = v * scale; };
+#pragma unroll
+  for (int s = 0; s < SP; ++s) {
+    const int k = qq + s * QT;
+    if (k < NP) {
+      const int kc = (M - k) % M;
+      const int j = M - k;
+      const cplx<T> z = {lds[(2 * k) * NLP + ln], lds[(2 * k + 1) * NLP + ln]};
+      const cplx<T> zc = {lds[(2 * kc) * NLP + ln], -lds[(2 * kc + 1) * NLP + ln]};
+      const cplx<T> E = {(T)0.5 * (z.re + zc.re), (T)0.5 * (z.im + zc.im)};
+      const cplx<T> D = csub(z, zc);
+      const cplx<T> O = {(T)0.5 * D.im, (T)-0.5 * D.re};
+      const cplx<T> wO = cmul(ldc(split, k), O);
+      const cplx<T> X = cadd(E, wO);
+      const cplx<T> Y = cconj(csub(E, wO));
+      if (kind == K_P) {
+        if (k == 0) {
+          put(0, X.re);
+          put(N - 1, Y.re);
+        } else {
+          put(2 * k - 1, X.re);
+          put(2 * k, -X.im);
+          if (j != k) {
+            put(2 * j - 1, Y.re);
+            put(2 * j, -Y.im);
+          }
+        }
+      } else {
+        const bool rev = kind == K_DD;
+        const cplx<T> u = cmul(ldc(quarter, k), X);
+        put(rev ? N - 1 - k : k, (T)2 * u.re);
+        if (k > 0) put(rev ? k - 1 : N - k, (T)-2 * u.im);
+        if (j != k) {
+          const cplx<T> u2 = cmul(ldc(quarter, j), Y);
+          put(rev ? N - 1 - j : j, (T)2 * u2.re);
+          if (j != M) put(rev ? j - 1 : N - j, (T)-2 * u2.im);
+        }
+      }
+    }
+  }
+}
+
 // Register budget of the staging kernel.  FP64 M = 256 in the 16-line tile
 // shape (DFT and DCT-IV types): one block fills a CU's LDS, so the kernel may use up to 256 VGPRs
 // and keep every stage's addresses live across the tile loop (fastest).  Otherwise the per-thread
@@ -794,15 +907,16 @@ struct AsyncBudget {
   if (stores_pending) vm_wait_keep<L::EPT>();                                                  \
   else __builtin_amdgcn_s_waitcnt(0);                                                          \
   lds_barrier();                 /* ... and every wave's */                                    \
-  async_place<T, C>(stage, S.tile, kind, inverse, g.layout, LT, QT, TIDT);                     \
+  if constexpr (!ivk && inverse)                                                               \
+    async_place_combine<T, C>(stage, S.tile, tw_a, tw_b, kind, g.layout, LT, QT, TIDT);        \
+  else                                                                                         \
+    async_place<T, C>(stage, S.tile, kind, inverse, g.layout, LT, QT, TIDT);                   \
   lds_barrier();                                                                               \
   if (tile + tr.step < tr.end) async_fetch<T, C>(stage_lds, A, tile + tr.step, TIDT);         \
   if constexpr (ivk) fast_iv_pre<T, C, true>(S.tile, tw_a, LT, QT);                            \
-  else if constexpr (inverse) fast_combine<T, C, true>(S.tile, tw_a, tw_b, kind, LT, QT);      \
   if constexpr (!(inverse && kind <= K_DD)) fast_passes<T, C, true, 0, true>(S.tile, tw_fft, LT, QT); \
   else fast_passes<T, C, false, 0, true>(S.tile, tw_fft, LT, QT);                             \
   if constexpr (ivk) fast_iv_post<T, C, true>(S.tile, tw_b, LT, QT);                           \
-  else if constexpr (!inverse) fast_split<T, C, true>(S.tile, tw_a, tw_b, kind, LT, QT);       \
   const TileOrigin o = tile_origin(g, tile);                                                   \
   long long base;                                                                              \
   int lines = 0;                                                                               \
@@ -812,11 +926,17 @@ struct AsyncBudget {
     base = (long long)o.L0 * L::N;                                                             \
     lines = g.nlines - o.L0;                                                                   \
   }                                                                                            \
-  fast_store<T, C, true>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind,         \
-                         inverse, A.scale, LT, QT, TIDT);                                      \
-  /* strided tiles: each wave holds line 0, which always exists, so it */                     \
-  /* issues all EPT stores; contiguous tiles only when no line is missing */                  \
-  stores_pending = g.layout == 0 || lines >= NL;                                               \
+  if constexpr (!ivk && !inverse) {                                                            \
+    async_split_store<T, C>(S.tile, tw_a, tw_b, kind, as_global(A.data), base, g.sp, g.layout,  \
+                            lines, A.scale, LT, QT, TIDT);                                     \
+    stores_pending = false; /* store count varies by lane group: wait for all */               \
+  } else {                                                                                     \
+    fast_store<T, C, true>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind,       \
+                           inverse, A.scale, LT, QT, TIDT);                                    \
+    /* strided tiles: each wave holds line 0, which always exists, so it */                   \
+    /* issues all EPT stores; contiguous tiles only when no line is missing */                \
+    stores_pending = g.layout == 0 || lines >= NL;                                             \
+  }                                                                                            \
   lds_barrier();
 
 template <typename T, typename C, int KIND, int INV>

@@ -231,13 +231,33 @@ __device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const double> co
   using L = TriFastLayout<T, RPC, P>;
   using R = double;
   constexpr int N = L::N;
+  // Long chunks of an FP64 field keep the eliminated right-hand side in the
+  // tile (LDS) instead of registers: the pivots and spikes of RPC rows plus
+  // RPC values would not fit 128 VGPRs.  FP32 fields keep it in registers
+  // (the tile cannot hold FP64 intermediates).
+  constexpr bool XL = sizeof(T) == 8 && RPC >= 12 && RPC * P >= 256;
   const lptr<const R> ca = coef, cb = coef + N, cc = coef + 2 * N, cw = coef + 3 * N;
   const int lane = threadIdx.x & 63;
   const int gbase = lane - c;
 
-  R x[RPC];
+  R xr[XL ? 1 : RPC];
+  auto xget = [&](int i) -> R {
+    if constexpr (XL) return (R)col[i * L::NLP];
+    else return xr[i];
+  };
+  auto xset = [&](int i, R v) {
+    if constexpr (XL) col[i * L::NLP] = (T)v;
+    else xr[i] = v;
+  };
+  // long chunks: keep each row's loads in its own step (the scheduler would
+  // otherwise issue every row's coefficient loads at once, RPC x 3 values live)
+  auto row_fence = [] {
+    if constexpr (XL) __builtin_amdgcn_sched_barrier(0);
+  };
+  if constexpr (!XL) {
 #pragma unroll
-  for (int i = 0; i < RPC; ++i) x[i] = (R)col[i * L::NLP];
+    for (int i = 0; i < RPC; ++i) xr[i] = (R)col[i * L::NLP];
+  }
 
   if (wave_sing) {   // project the right-hand side of the null-space line
     R sw = 0, swf = 0;
@@ -245,14 +265,14 @@ __device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const double> co
     for (int i = 0; i < RPC; ++i) {
       const R wi = cw[i * P + c];
       sw += wi;
-      swf += wi * x[i];
+      swf += wi * xget(i);
     }
     sw = line_sum<R, P>(sw);
     swf = line_sum<R, P>(swf);
     if (sing) {
       const R mean = swf / sw;
 #pragma unroll
-      for (int i = 0; i < RPC; ++i) x[i] -= mean;
+      for (int i = 0; i < RPC; ++i) xset(i, xget(i) - mean);
     }
   }
 
@@ -261,29 +281,33 @@ __device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const double> co
   constexpr int NI = RPC - 1;
   R cp[NI], qv[NI];
   R r = fast_rcp(cb[c] + mu);
-  x[0] *= r;
+  R xp = xget(0) * r;
+  xset(0, xp);
   qv[0] = ca[c] * r;
   cp[0] = cc[c] * r;
 #pragma unroll
   for (int i = 1; i < NI; ++i) {
     const R ai = ca[i * P + c], bi = cb[i * P + c], ci = cc[i * P + c];
     r = fast_rcp(bi + mu - ai * cp[i - 1]);
-    x[i] = (x[i] - ai * x[i - 1]) * r;
+    xp = (xget(i) - ai * xp) * r;
+    xset(i, xp);
     qv[i] = -ai * qv[i - 1] * r;
     cp[i] = ci * r;
+    row_fence();
   }
   // first-row values of y = R^-1 f, v = R^-1 (a e_first), w = R^-1 (c e_last)
-  const R yl = x[NI - 1], vl = qv[NI - 1], wl = cc[(NI - 1) * P + c] * r;
+  const R yl = xp, vl = qv[NI - 1], wl = cc[(NI - 1) * P + c] * r;
   R yf = yl, vf = vl, wf = wl;
 #pragma unroll
   for (int i = NI - 2; i >= 0; --i) {
-    yf = x[i] - cp[i] * yf;
+    yf = xget(i) - cp[i] * yf;
     vf = qv[i] - cp[i] * vf;
     wf = -cp[i] * wf;
+    row_fence();
   }
 
   // phase 2: interface row (last row of the chunk), reduced by PCR
-  R ae = ca[NI * P + c], be = cb[NI * P + c] + mu, ce = cc[NI * P + c], fe = x[NI];
+  R ae = ca[NI * P + c], be = cb[NI * P + c] + mu, ce = cc[NI * P + c], fe = xget(NI);
   if (sing && c == P - 1) { ae = 0; be = 1; ce = 0; fe = 0; }   // pin x_{n-1} = 0
   const R yf_n = group_rot<P, 1, true>(yf, gbase, c);
   const R vf_n = group_rot<P, 1, true>(vf, gbase, c);
@@ -299,10 +323,15 @@ __device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const double> co
   if (!periodic && c == 0) Ip = 0;
 
   // phase 3: back substitution of the interior
-  x[NI] = Ic;
-  x[NI - 1] = yl - Ip * vl - Ic * wl;
+  xset(NI, Ic);
+  R xn = yl - Ip * vl - Ic * wl;
+  xset(NI - 1, xn);
 #pragma unroll
-  for (int i = NI - 2; i >= 0; --i) x[i] = x[i] - Ip * qv[i] - cp[i] * x[i + 1];
+  for (int i = NI - 2; i >= 0; --i) {
+    xn = xget(i) - Ip * qv[i] - cp[i] * xn;
+    xset(i, xn);
+    row_fence();
+  }
 
   if (wave_sing) {   // gauge: zero width-weighted mean of the null-space line
     R sw = 0, swx = 0;
@@ -310,18 +339,20 @@ __device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const double> co
     for (int i = 0; i < RPC; ++i) {
       const R wi = cw[i * P + c];
       sw += wi;
-      swx += wi * x[i];
+      swx += wi * xget(i);
     }
     sw = line_sum<R, P>(sw);
     swx = line_sum<R, P>(swx);
     if (sing) {
       const R mean = swx / sw;
 #pragma unroll
-      for (int i = 0; i < RPC; ++i) x[i] -= mean;
+      for (int i = 0; i < RPC; ++i) xset(i, xget(i) - mean);
     }
   }
+  if constexpr (!XL) {
 #pragma unroll
-  for (int i = 0; i < RPC; ++i) col[i * L::NLP] = (T)x[i];
+    for (int i = 0; i < RPC; ++i) col[i * L::NLP] = (T)xr[i];
+  }
 }
 
 // Coefficients of the elimination axis into LDS, [row in chunk][chunk];
@@ -393,8 +424,14 @@ void tri_fast_kernel(TriFastArgs<T> A) {
   const int tid = threadIdx.x;
   tri_fast_coefs<T, RPC, P>(coef, A, tid);
   const TileRange tr = xcd_tiles(A.g.ntiles);
-  for (int tile = tr.first; tile < tr.end; tile += tr.step)
-    tri_fast_tile<T, RPC, P>(lds, coef, A, tile, tid);
+  for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+    // chunks of 16 rows: thread index opaque per tile, so that the per-row
+    // LDS addresses are recomputed in each tile instead of being held (and
+    // spilled) across the loop; shorter chunks are faster with them held
+    int t = tid;
+    if constexpr (RPC >= 16) asm volatile("" : "+v"(t));
+    tri_fast_tile<T, RPC, P>(lds, coef, A, tile, t);
+  }
 }
 
 // ---------------------------------------------------------------- async form
