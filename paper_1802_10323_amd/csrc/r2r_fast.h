@@ -855,6 +855,57 @@ __device__ __forceinline__ void async_split_store(lptr<const T> lds, lptr<const 
   }
 }
 
+// DCT-IV / DST-IV, fused with the placement: complex value j of the packed
+// sequence (tile rows 2j and 2j+1: input points 2j and n-1-2j for N-D, the
+// mirrored points n-1-2j and 2j for D-N) times the pre-twiddle, into the
+// tile.  Lane mapping as in async_place_combine.
+template <typename T, typename C>
+__device__ __forceinline__ void async_place_pre(lptr<const T> stage, lptr<T> lds,
+                                                lptr<const cplx<T>> pre, int kind, int layout,
+                                                int l, int q, int tid) {
+  using L = FastLayout<T, C>;
+  constexpr int N = L::N, NL = L::NL, NLP = L::NLP, QT = L::QT;
+  const int ln = layout == 0 ? l : tid / QT;
+  const int qq = layout == 0 ? q : tid % QT;
+  auto point = [&](int p) -> T { return layout == 0 ? stage[p * NL + ln] : stage[ln * N + p]; };
+#pragma unroll
+  for (int s = 0; s < L::E; ++s) {
+    const int j = qq + s * QT;
+    const int pe = kind == K_ND ? 2 * j : N - 1 - 2 * j;
+    const int po = kind == K_ND ? N - 1 - 2 * j : 2 * j;
+    const cplx<T> z = cmul(cplx<T>{point(pe), point(po)}, ldc(pre, j));
+    lds[(2 * j) * NLP + ln] = z.re;
+    lds[(2 * j + 1) * NLP + ln] = z.im;
+  }
+}
+
+// DCT-IV / DST-IV, fused with the store: V_k = Z_k times the post-twiddle;
+// output point 2k is 2 Re V_k and point n-1-2k is -2 Im V_k (D-N: odd
+// points change sign).  Lane mapping as in async_split_store.
+template <typename T, typename C>
+__device__ __forceinline__ void async_post_store(lptr<const T> lds, lptr<const cplx<T>> post,
+                                                 int kind, gptr<T> data, long long base,
+                                                 long long sp, int layout, int lines, T scale,
+                                                 int l, int q, int tid) {
+  using L = FastLayout<T, C>;
+  constexpr int N = L::N, NLP = L::NLP, QT = L::QT;
+  const int ln = layout == 0 ? l : tid / QT;
+  const int qq = layout == 0 ? q : tid % QT;
+  const long long lb = layout == 0 ? base : base + (long long)ln * N;
+  const long long ps = layout == 0 ? sp : 1;
+  if (layout == 0 ? base < 0 : ln >= lines) return;   // line outside the field
+#pragma unroll
+  for (int s = 0; s < L::E; ++s) {
+    const int k = qq + s * QT;
+    const cplx<T> V = cmul(cplx<T>{lds[(2 * k) * NLP + ln], lds[(2 * k + 1) * NLP + ln]},
+                           ldc(post, k));
+    const T ye = ((T)2 * V.re) * scale;      // point 2k (even)
+    const T yo = ((T)-2 * V.im) * scale;     // point n-1-2k (odd)
+    data[lb + (2 * k) * ps] = ye;
+    data[lb + (N - 1 - 2 * k) * ps] = kind == K_ND ? yo : -yo;
+  }
+}
+
 // Register budget of the staging kernel.  FP64 M = 256 in the 16-line tile
 // shape (DFT and DCT-IV types): one block fills a CU's LDS, so the kernel may use up to 256 VGPRs
 // and keep every stage's addresses live across the tile loop (fastest).  Otherwise the per-thread
@@ -907,16 +958,16 @@ struct AsyncBudget {
   if (stores_pending) vm_wait_keep<L::EPT>();                                                  \
   else __builtin_amdgcn_s_waitcnt(0);                                                          \
   lds_barrier();                 /* ... and every wave's */                                    \
-  if constexpr (!ivk && inverse)                                                               \
+  if constexpr (ivk)                                                                           \
+    async_place_pre<T, C>(stage, S.tile, tw_a, kind, g.layout, LT, QT, TIDT);                  \
+  else if constexpr (inverse)                                                                  \
     async_place_combine<T, C>(stage, S.tile, tw_a, tw_b, kind, g.layout, LT, QT, TIDT);        \
   else                                                                                         \
     async_place<T, C>(stage, S.tile, kind, inverse, g.layout, LT, QT, TIDT);                   \
   lds_barrier();                                                                               \
   if (tile + tr.step < tr.end) async_fetch<T, C>(stage_lds, A, tile + tr.step, TIDT);         \
-  if constexpr (ivk) fast_iv_pre<T, C, true>(S.tile, tw_a, LT, QT);                            \
   if constexpr (!(inverse && kind <= K_DD)) fast_passes<T, C, true, 0, true>(S.tile, tw_fft, LT, QT); \
   else fast_passes<T, C, false, 0, true>(S.tile, tw_fft, LT, QT);                             \
-  if constexpr (ivk) fast_iv_post<T, C, true>(S.tile, tw_b, LT, QT);                           \
   const TileOrigin o = tile_origin(g, tile);                                                   \
   long long base;                                                                              \
   int lines = 0;                                                                               \
@@ -926,7 +977,11 @@ struct AsyncBudget {
     base = (long long)o.L0 * L::N;                                                             \
     lines = g.nlines - o.L0;                                                                   \
   }                                                                                            \
-  if constexpr (!ivk && !inverse) {                                                            \
+  if constexpr (ivk) {                                                                         \
+    async_post_store<T, C>(S.tile, tw_b, kind, as_global(A.data), base, g.sp, g.layout, lines, \
+                           A.scale, LT, QT, TIDT);                                             \
+    stores_pending = false;                                                                    \
+  } else if constexpr (!inverse) {                                                             \
     async_split_store<T, C>(S.tile, tw_a, tw_b, kind, as_global(A.data), base, g.sp, g.layout,  \
                             lines, A.scale, LT, QT, TIDT);                                     \
     stores_pending = false; /* store count varies by lane group: wait for all */               \
