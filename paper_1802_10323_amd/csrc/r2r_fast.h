@@ -543,6 +543,111 @@ __device__ __forceinline__ void fast_split(lptr<T> lds, lptr<const cplx<T>> spli
   else fast_split_call<T, C>(lds, split, quarter, kind, l, q);
 }
 
+// Forward P/NN/DD, fused with the store: the even/odd split of
+// fast_split_body, written straight to the field (the forward output order
+// of these types is the tile's row order).  Strided layout: lines on
+// consecutive lanes (rows of NL values); contiguous: a line's points on
+// consecutive lanes.
+template <typename T, typename C>
+__device__ __forceinline__ void split_store_body(lptr<const T> lds, lptr<const cplx<T>> split,
+                                                  lptr<const cplx<T>> quarter, int kind,
+                                                  gptr<T> data, long long base, long long sp,
+                                                  int layout, int lines, T scale, int l, int q,
+                                                  int tid) {
+  using L = FastLayout<T, C>;
+  constexpr int M = L::M, N = L::N, NLP = L::NLP, QT = L::QT;
+  constexpr int NP = M / 2 + 1;
+  constexpr int SP = (NP + QT - 1) / QT;
+  const int ln = layout == 0 ? l : tid / QT;
+  const int qq = layout == 0 ? q : tid % QT;
+  const long long lb = layout == 0 ? base : base + (long long)ln * N;
+  const long long ps = layout == 0 ? sp : 1;
+  if (layout == 0 ? base < 0 : ln >= lines) return;   // line outside the field
+  auto put = [&](int r, T v) { data[lb + r * ps] = v * scale; };
+#pragma unroll
+  for (int s = 0; s < SP; ++s) {
+    const int k = qq + s * QT;
+    if (k < NP) {
+      const int kc = (M - k) % M;
+      const int j = M - k;
+      const cplx<T> z = {lds[(2 * k) * NLP + ln], lds[(2 * k + 1) * NLP + ln]};
+      const cplx<T> zc = {lds[(2 * kc) * NLP + ln], -lds[(2 * kc + 1) * NLP + ln]};
+      const cplx<T> E = {(T)0.5 * (z.re + zc.re), (T)0.5 * (z.im + zc.im)};
+      const cplx<T> D = csub(z, zc);
+      const cplx<T> O = {(T)0.5 * D.im, (T)-0.5 * D.re};
+      const cplx<T> wO = cmul(ldc(split, k), O);
+      const cplx<T> X = cadd(E, wO);
+      const cplx<T> Y = cconj(csub(E, wO));
+      if (kind == K_P) {
+        if (k == 0) {
+          put(0, X.re);
+          put(N - 1, Y.re);
+        } else {
+          put(2 * k - 1, X.re);
+          put(2 * k, -X.im);
+          if (j != k) {
+            put(2 * j - 1, Y.re);
+            put(2 * j, -Y.im);
+          }
+        }
+      } else {
+        const bool rev = kind == K_DD;
+        const cplx<T> u = cmul(ldc(quarter, k), X);
+        put(rev ? N - 1 - k : k, (T)2 * u.re);
+        if (k > 0) put(rev ? k - 1 : N - k, (T)-2 * u.im);
+        if (j != k) {
+          const cplx<T> u2 = cmul(ldc(quarter, j), Y);
+          put(rev ? N - 1 - j : j, (T)2 * u2.re);
+          if (j != M) put(rev ? j - 1 : N - j, (T)-2 * u2.im);
+        }
+      }
+    }
+  }
+}
+
+// DCT-IV / DST-IV, fused with the store: V_k = Z_k times the post-twiddle;
+// output point 2k is 2 Re V_k and point n-1-2k is -2 Im V_k (D-N: odd
+// points change sign).  Lane mapping as in split_store_body.
+template <typename T, typename C>
+__device__ __forceinline__ void post_store_body(lptr<const T> lds, lptr<const cplx<T>> post,
+                                                 int kind, gptr<T> data, long long base,
+                                                 long long sp, int layout, int lines, T scale,
+                                                 int l, int q, int tid) {
+  using L = FastLayout<T, C>;
+  constexpr int N = L::N, NLP = L::NLP, QT = L::QT;
+  const int ln = layout == 0 ? l : tid / QT;
+  const int qq = layout == 0 ? q : tid % QT;
+  const long long lb = layout == 0 ? base : base + (long long)ln * N;
+  const long long ps = layout == 0 ? sp : 1;
+  if (layout == 0 ? base < 0 : ln >= lines) return;   // line outside the field
+#pragma unroll
+  for (int s = 0; s < L::E; ++s) {
+    const int k = qq + s * QT;
+    const cplx<T> V = cmul(cplx<T>{lds[(2 * k) * NLP + ln], lds[(2 * k + 1) * NLP + ln]},
+                           ldc(post, k));
+    const T ye = ((T)2 * V.re) * scale;      // point 2k (even)
+    const T yo = ((T)-2 * V.im) * scale;     // point n-1-2k (odd)
+    data[lb + (2 * k) * ps] = ye;
+    data[lb + (N - 1 - 2 * k) * ps] = kind == K_ND ? yo : -yo;
+  }
+}
+
+// Non-inlined copies for the synchronous kernels (own register allocation).
+template <typename T, typename C>
+__device__ __noinline__ void split_store_call(lptr<const T> lds, lptr<const cplx<T>> split,
+                                              lptr<const cplx<T>> quarter, int kind, gptr<T> data,
+                                              long long base, long long sp, int layout, int lines,
+                                              T scale, int l, int q, int tid) {
+  split_store_body<T, C>(lds, split, quarter, kind, data, base, sp, layout, lines, scale, l, q, tid);
+}
+
+template <typename T, typename C>
+__device__ __noinline__ void post_store_call(lptr<const T> lds, lptr<const cplx<T>> post, int kind,
+                                             gptr<T> data, long long base, long long sp, int layout,
+                                             int lines, T scale, int l, int q, int tid) {
+  post_store_body<T, C>(lds, post, kind, data, base, sp, layout, lines, scale, l, q, tid);
+}
+
 // ---------------------------------------------------------------- kernel
 
 // LDS regions of the specialised transform: the tile, then the FFT twiddles
@@ -621,11 +726,16 @@ __device__ __forceinline__ void fast_tile(const FastLds<T, C>& S, const R2RFastA
   if (!(inverse && kind <= K_DD)) fast_passes<T, C, true, 0>(S.tile, tw_fft, l, q);
   else fast_passes<T, C, false, 0>(S.tile, tw_fft, l, q);
 
-  if (ivk) fast_iv_post<T, C>(S.tile, tw_b, l, q);
-  else if (!inverse) fast_split<T, C>(S.tile, tw_a, tw_b, kind, l, q);
-
-  fast_store<T, C>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind, inverse,
-                   A.scale, l, q, tid);
+  // the DCT-IV post-twiddle and the forward split write the field directly
+  if (ivk)
+    post_store_call<T, C>(S.tile, tw_b, kind, as_global(A.data), base, g.sp, g.layout, lines,
+                          A.scale, l, q, tid);
+  else if (!inverse)
+    split_store_call<T, C>(S.tile, tw_a, tw_b, kind, as_global(A.data), base, g.sp, g.layout,
+                           lines, A.scale, l, q, tid);
+  else
+    fast_store<T, C>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind, inverse,
+                     A.scale, l, q, tid);
   lds_barrier();
 }
 
@@ -793,68 +903,6 @@ __device__ __forceinline__ void async_place_combine(lptr<const T> stage, lptr<T>
   }
 }
 
-// Forward P/NN/DD, fused with the store: the even/odd split of
-// fast_split_body, written straight to the field (the forward output order
-// of these types is the tile's row order).  Strided layout: lines on
-// consecutive lanes (rows of NL values); contiguous: a line's points on
-// consecutive lanes.
-template <typename T, typename C>
-__device__ __forceinline__ void async_split_store(lptr<const T> lds, lptr<const cplx<T>> split,
-                                                  lptr<const cplx<T>> quarter, int kind,
-                                                  gptr<T> data, long long base, long long sp,
-                                                  int layout, int lines, T scale, int l, int q,
-                                                  int tid) {
-  using L = FastLayout<T, C>;
-  constexpr int M = L::M, N = L::N, NLP = L::NLP, QT = L::QT;
-  constexpr int NP = M / 2 + 1;
-  constexpr int SP = (NP + QT - 1) / QT;
-  const int ln = layout == 0 ? l : tid / QT;
-  const int qq = layout == 0 ? q : tid % QT;
-  const long long lb = layout == 0 ? base : base + (long long)ln * N;
-  const long long ps = layout == 0 ? sp : 1;
-  if (layout == 0 ? base < 0 : ln >= lines) return;   // line outside the field
-  auto put = [&](int r, T v) { data[lb + r * ps] = v * scale; };
-#pragma unroll
-  for (int s = 0; s < SP; ++s) {
-    const int k = qq + s * QT;
-    if (k < NP) {
-      const int kc = (M - k) % M;
-      const int j = M - k;
-      const cplx<T> z = {lds[(2 * k) * NLP + ln], lds[(2 * k + 1) * NLP + ln]};
-      const cplx<T> zc = {lds[(2 * kc) * NLP + ln], -lds[(2 * kc + 1) * NLP + ln]};
-      const cplx<T> E = {(T)0.5 * (z.re + zc.re), (T)0.5 * (z.im + zc.im)};
-      const cplx<T> D = csub(z, zc);
-      const cplx<T> O = {(T)0.5 * D.im, (T)-0.5 * D.re};
-      const cplx<T> wO = cmul(ldc(split, k), O);
-      const cplx<T> X = cadd(E, wO);
-      const cplx<T> Y = cconj(csub(E, wO));
-      if (kind == K_P) {
-        if (k == 0) {
-          put(0, X.re);
-          put(N - 1, Y.re);
-        } else {
-          put(2 * k - 1, X.re);
-          put(2 * k, -X.im);
-          if (j != k) {
-            put(2 * j - 1, Y.re);
-            put(2 * j, -Y.im);
-          }
-        }
-      } else {
-        const bool rev = kind == K_DD;
-        const cplx<T> u = cmul(ldc(quarter, k), X);
-        put(rev ? N - 1 - k : k, (T)2 * u.re);
-        if (k > 0) put(rev ? k - 1 : N - k, (T)-2 * u.im);
-        if (j != k) {
-          const cplx<T> u2 = cmul(ldc(quarter, j), Y);
-          put(rev ? N - 1 - j : j, (T)2 * u2.re);
-          if (j != M) put(rev ? j - 1 : N - j, (T)-2 * u2.im);
-        }
-      }
-    }
-  }
-}
-
 // DCT-IV / DST-IV, fused with the placement: complex value j of the packed
 // sequence (tile rows 2j and 2j+1: input points 2j and n-1-2j for N-D, the
 // mirrored points n-1-2j and 2j for D-N) times the pre-twiddle, into the
@@ -876,33 +924,6 @@ __device__ __forceinline__ void async_place_pre(lptr<const T> stage, lptr<T> lds
     const cplx<T> z = cmul(cplx<T>{point(pe), point(po)}, ldc(pre, j));
     lds[(2 * j) * NLP + ln] = z.re;
     lds[(2 * j + 1) * NLP + ln] = z.im;
-  }
-}
-
-// DCT-IV / DST-IV, fused with the store: V_k = Z_k times the post-twiddle;
-// output point 2k is 2 Re V_k and point n-1-2k is -2 Im V_k (D-N: odd
-// points change sign).  Lane mapping as in async_split_store.
-template <typename T, typename C>
-__device__ __forceinline__ void async_post_store(lptr<const T> lds, lptr<const cplx<T>> post,
-                                                 int kind, gptr<T> data, long long base,
-                                                 long long sp, int layout, int lines, T scale,
-                                                 int l, int q, int tid) {
-  using L = FastLayout<T, C>;
-  constexpr int N = L::N, NLP = L::NLP, QT = L::QT;
-  const int ln = layout == 0 ? l : tid / QT;
-  const int qq = layout == 0 ? q : tid % QT;
-  const long long lb = layout == 0 ? base : base + (long long)ln * N;
-  const long long ps = layout == 0 ? sp : 1;
-  if (layout == 0 ? base < 0 : ln >= lines) return;   // line outside the field
-#pragma unroll
-  for (int s = 0; s < L::E; ++s) {
-    const int k = qq + s * QT;
-    const cplx<T> V = cmul(cplx<T>{lds[(2 * k) * NLP + ln], lds[(2 * k + 1) * NLP + ln]},
-                           ldc(post, k));
-    const T ye = ((T)2 * V.re) * scale;      // point 2k (even)
-    const T yo = ((T)-2 * V.im) * scale;     // point n-1-2k (odd)
-    data[lb + (2 * k) * ps] = ye;
-    data[lb + (N - 1 - 2 * k) * ps] = kind == K_ND ? yo : -yo;
   }
 }
 
@@ -978,11 +999,11 @@ struct AsyncBudget {
     lines = g.nlines - o.L0;                                                                   \
   }                                                                                            \
   if constexpr (ivk) {                                                                         \
-    async_post_store<T, C>(S.tile, tw_b, kind, as_global(A.data), base, g.sp, g.layout, lines, \
+    post_store_body<T, C>(S.tile, tw_b, kind, as_global(A.data), base, g.sp, g.layout, lines, \
                            A.scale, LT, QT, TIDT);                                             \
     stores_pending = false;                                                                    \
   } else if constexpr (!inverse) {                                                             \
-    async_split_store<T, C>(S.tile, tw_a, tw_b, kind, as_global(A.data), base, g.sp, g.layout,  \
+    split_store_body<T, C>(S.tile, tw_a, tw_b, kind, as_global(A.data), base, g.sp, g.layout,  \
                             lines, A.scale, LT, QT, TIDT);                                     \
     stores_pending = false; /* store count varies by lane group: wait for all */               \
   } else {                                                                                     \
