@@ -648,6 +648,129 @@ __device__ __noinline__ void post_store_call(lptr<const T> lds, lptr<const cplx<
   post_store_body<T, C>(lds, post, kind, data, base, sp, layout, lines, scale, l, q, tid);
 }
 
+// Inverse P/NN/DD, fused with the placement: the length-M spectrum Z' of
+// fast_combine_body written into the tile (column ln, pairs k = qq + s QT)
+// from the input points of the line, point(p) (tile row r holds point r,
+// D-D: point n-1-r).
+template <typename T, typename C, typename Point>
+__device__ __forceinline__ void combine_to_tile(Point point, lptr<T> lds,
+                                                lptr<const cplx<T>> split,
+                                                lptr<const cplx<T>> quarter, int kind, int ln,
+                                                int qq) {
+  using L = FastLayout<T, C>;
+  constexpr int M = L::M, N = L::N, NLP = L::NLP, QT = L::QT;
+  constexpr int NP = M / 2 + 1;
+  constexpr int SP = (NP + QT - 1) / QT;
+  auto row = [&](int r) -> T { return point(kind == K_DD ? N - 1 - r : r); };
+  // all reads first (global reads stay in flight together), then the math
+  T v[SP][4];
+#pragma unroll
+  for (int s = 0; s < SP; ++s) {
+    const int k = qq + s * QT;
+    const int j = M - k;
+    if (k < NP) {
+      if (kind == K_P) {
+        v[s][0] = row(k == 0 ? 0 : 2 * k - 1);
+        v[s][1] = k == 0 ? (T)0 : row(2 * k);
+        v[s][2] = row(j == M ? N - 1 : 2 * j - 1);
+        v[s][3] = j == M ? (T)0 : row(2 * j);
+      } else {
+        v[s][0] = row(k);
+        v[s][1] = k == 0 ? (T)0 : row(N - k);
+        v[s][2] = row(j);
+        v[s][3] = row(N - j);
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < SP; ++s) {
+    const int k = qq + s * QT;
+    if (k < NP) {
+      const int j = M - k;
+      cplx<T> xk, xj;
+      if (kind == K_P) {
+        xk = {v[s][0], k == 0 ? (T)0 : -v[s][1]};
+        xj = {v[s][2], j == M ? (T)0 : -v[s][3]};
+      } else {
+        xk = cmul(cconj(ldc(quarter, k)), cplx<T>{(T)0.5 * v[s][0], (T)-0.5 * v[s][1]});
+        xj = cmul(cconj(ldc(quarter, j)), cplx<T>{(T)0.5 * v[s][2], (T)-0.5 * v[s][3]});
+      }
+      const cplx<T> sk = ldc(split, k);
+      const cplx<T> s1 = cadd(xk, cconj(xj));
+      const cplx<T> d1 = cmul(csub(xk, cconj(xj)), cconj(sk));
+      lds[(2 * k) * NLP + ln] = s1.re - d1.im;
+      lds[(2 * k + 1) * NLP + ln] = s1.im + d1.re;
+      if (k > 0 && j != k) {
+        const cplx<T> s2 = cadd(xj, cconj(xk));
+        const cplx<T> d2 = cmul(csub(cconj(xk), xj), sk);
+        lds[(2 * j) * NLP + ln] = s2.re - d2.im;
+        lds[(2 * j + 1) * NLP + ln] = s2.im + d2.re;
+      }
+    }
+  }
+}
+
+// DCT-IV / DST-IV, fused with the placement: complex value j of the packed
+// sequence (tile rows 2j and 2j+1: input points 2j and n-1-2j for N-D, the
+// mirrored points n-1-2j and 2j for D-N) times the pre-twiddle, into the
+// tile (column ln, j = qq + s QT).
+template <typename T, typename C, typename Point>
+__device__ __forceinline__ void pre_to_tile(Point point, lptr<T> lds, lptr<const cplx<T>> pre,
+                                            int kind, int ln, int qq) {
+  using L = FastLayout<T, C>;
+  constexpr int N = L::N, NLP = L::NLP, QT = L::QT;
+  T v[L::E][2];   // all reads first, then the math
+#pragma unroll
+  for (int s = 0; s < L::E; ++s) {
+    const int j = qq + s * QT;
+    v[s][0] = point(kind == K_ND ? 2 * j : N - 1 - 2 * j);
+    v[s][1] = point(kind == K_ND ? N - 1 - 2 * j : 2 * j);
+  }
+#pragma unroll
+  for (int s = 0; s < L::E; ++s) {
+    const int j = qq + s * QT;
+    const cplx<T> z = cmul(cplx<T>{v[s][0], v[s][1]}, ldc(pre, j));
+    lds[(2 * j) * NLP + ln] = z.re;
+    lds[(2 * j + 1) * NLP + ln] = z.im;
+  }
+}
+
+// The two above from global memory, for the synchronous kernels: the lanes
+// run over lines on a strided axis (each load reads a row of NL values) and
+// over a line's points on the contiguous one; lines outside the field read 0.
+template <typename T, typename C>
+__device__ __noinline__ void load_combine_call(lptr<T> lds, gptr<const T> data, long long base,
+                                               long long sp, int layout, int lines,
+                                               lptr<const cplx<T>> split,
+                                               lptr<const cplx<T>> quarter, int kind, int l,
+                                               int q, int tid) {
+  using L = FastLayout<T, C>;
+  constexpr int N = L::N, QT = L::QT;
+  const int ln = layout == 0 ? l : tid / QT;
+  const int qq = layout == 0 ? q : tid % QT;
+  const long long lb = layout == 0 ? base : base + (long long)ln * N;
+  const long long ps = layout == 0 ? sp : 1;
+  const bool in = layout == 0 ? base >= 0 : ln < lines;
+  auto point = [&](int p) -> T { return in ? data[lb + p * ps] : (T)0; };
+  combine_to_tile<T, C>(point, lds, split, quarter, kind, ln, qq);
+}
+
+template <typename T, typename C>
+__device__ __noinline__ void load_pre_call(lptr<T> lds, gptr<const T> data, long long base,
+                                           long long sp, int layout, int lines,
+                                           lptr<const cplx<T>> pre, int kind, int l, int q,
+                                           int tid) {
+  using L = FastLayout<T, C>;
+  constexpr int N = L::N, QT = L::QT;
+  const int ln = layout == 0 ? l : tid / QT;
+  const int qq = layout == 0 ? q : tid % QT;
+  const long long lb = layout == 0 ? base : base + (long long)ln * N;
+  const long long ps = layout == 0 ? sp : 1;
+  const bool in = layout == 0 ? base >= 0 : ln < lines;
+  auto point = [&](int p) -> T { return in ? data[lb + p * ps] : (T)0; };
+  pre_to_tile<T, C>(point, lds, pre, kind, ln, qq);
+}
+
 // ---------------------------------------------------------------- kernel
 
 // LDS regions of the specialised transform: the tile, then the FFT twiddles
@@ -716,12 +839,17 @@ __device__ __forceinline__ void fast_tile(const FastLds<T, C>& S, const R2RFastA
     base = (long long)o.L0 * L::N;
     lines = g.nlines - o.L0;
   }
-  fast_load<T, C>(S.tile, as_global((const T*)A.data), base, g.sp, g.layout, lines, kind, inverse,
-                  l, q, tid);
+  // the DCT-IV pre-twiddle and the inverse combine read the field directly
+  if (ivk)
+    load_pre_call<T, C>(S.tile, as_global((const T*)A.data), base, g.sp, g.layout, lines, tw_a,
+                        kind, l, q, tid);
+  else if (inverse)
+    load_combine_call<T, C>(S.tile, as_global((const T*)A.data), base, g.sp, g.layout, lines,
+                            tw_a, tw_b, kind, l, q, tid);
+  else
+    fast_load<T, C>(S.tile, as_global((const T*)A.data), base, g.sp, g.layout, lines, kind,
+                    inverse, l, q, tid);
   lds_barrier();
-
-  if (ivk) fast_iv_pre<T, C>(S.tile, tw_a, l, q);
-  else if (inverse) fast_combine<T, C>(S.tile, tw_a, tw_b, kind, l, q);
 
   if (!(inverse && kind <= K_DD)) fast_passes<T, C, true, 0>(S.tile, tw_fft, l, q);
   else fast_passes<T, C, false, 0>(S.tile, tw_fft, l, q);
@@ -852,79 +980,33 @@ __device__ __forceinline__ void async_place(lptr<const T> stage, lptr<T> lds, in
   }
 }
 
-// Inverse P/NN/DD, fused with the placement: the spectrum is read from the
-// stage (input point p of a line sits in tile row p, DD: row n-1-p) and
-// the length-M spectrum Z' of fast_combine_body is written into the tile.
-// The strided layout keeps the lines on consecutive lanes; the contiguous
-// one puts a line's points on consecutive lanes (the stage holds whole
-// lines there), so that both read the stage without bank conflicts.
+// The two above from the stage of the staging kernels.  The strided layout
+// keeps the lines on consecutive lanes; the contiguous one puts a line's
+// points on consecutive lanes (the stage holds whole lines there), so that
+// both read the stage without bank conflicts.
 template <typename T, typename C>
 __device__ __forceinline__ void async_place_combine(lptr<const T> stage, lptr<T> lds,
                                                     lptr<const cplx<T>> split,
                                                     lptr<const cplx<T>> quarter, int kind,
                                                     int layout, int l, int q, int tid) {
   using L = FastLayout<T, C>;
-  constexpr int M = L::M, N = L::N, NL = L::NL, NLP = L::NLP, QT = L::QT;
-  constexpr int NP = M / 2 + 1;
-  constexpr int SP = (NP + QT - 1) / QT;
+  constexpr int N = L::N, NL = L::NL, QT = L::QT;
   const int ln = layout == 0 ? l : tid / QT;
   const int qq = layout == 0 ? q : tid % QT;
-  auto row = [&](int r) -> T {   // tile row r of line ln, as the placement would leave it
-    const int p = kind == K_DD ? N - 1 - r : r;
-    return layout == 0 ? stage[p * NL + ln] : stage[ln * N + p];
-  };
-#pragma unroll
-  for (int s = 0; s < SP; ++s) {
-    const int k = qq + s * QT;
-    if (k < NP) {
-      const int j = M - k;
-      cplx<T> xk, xj;
-      if (kind == K_P) {
-        xk = k == 0 ? cplx<T>{row(0), (T)0} : cplx<T>{row(2 * k - 1), -row(2 * k)};
-        xj = j == M ? cplx<T>{row(N - 1), (T)0} : cplx<T>{row(2 * j - 1), -row(2 * j)};
-      } else {
-        const T yk = row(k), ynk = k == 0 ? (T)0 : row(N - k);
-        const T yj = row(j), ynj = row(N - j);
-        xk = cmul(cconj(ldc(quarter, k)), cplx<T>{(T)0.5 * yk, (T)-0.5 * ynk});
-        xj = cmul(cconj(ldc(quarter, j)), cplx<T>{(T)0.5 * yj, (T)-0.5 * ynj});
-      }
-      const cplx<T> sk = ldc(split, k);
-      const cplx<T> s1 = cadd(xk, cconj(xj));
-      const cplx<T> d1 = cmul(csub(xk, cconj(xj)), cconj(sk));
-      lds[(2 * k) * NLP + ln] = s1.re - d1.im;
-      lds[(2 * k + 1) * NLP + ln] = s1.im + d1.re;
-      if (k > 0 && j != k) {
-        const cplx<T> s2 = cadd(xj, cconj(xk));
-        const cplx<T> d2 = cmul(csub(cconj(xk), xj), sk);
-        lds[(2 * j) * NLP + ln] = s2.re - d2.im;
-        lds[(2 * j + 1) * NLP + ln] = s2.im + d2.re;
-      }
-    }
-  }
+  auto point = [&](int p) -> T { return layout == 0 ? stage[p * NL + ln] : stage[ln * N + p]; };
+  combine_to_tile<T, C>(point, lds, split, quarter, kind, ln, qq);
 }
 
-// DCT-IV / DST-IV, fused with the placement: complex value j of the packed
-// sequence (tile rows 2j and 2j+1: input points 2j and n-1-2j for N-D, the
-// mirrored points n-1-2j and 2j for D-N) times the pre-twiddle, into the
-// tile.  Lane mapping as in async_place_combine.
 template <typename T, typename C>
 __device__ __forceinline__ void async_place_pre(lptr<const T> stage, lptr<T> lds,
                                                 lptr<const cplx<T>> pre, int kind, int layout,
                                                 int l, int q, int tid) {
   using L = FastLayout<T, C>;
-  constexpr int N = L::N, NL = L::NL, NLP = L::NLP, QT = L::QT;
+  constexpr int N = L::N, NL = L::NL, QT = L::QT;
   const int ln = layout == 0 ? l : tid / QT;
   const int qq = layout == 0 ? q : tid % QT;
   auto point = [&](int p) -> T { return layout == 0 ? stage[p * NL + ln] : stage[ln * N + p]; };
-#pragma unroll
-  for (int s = 0; s < L::E; ++s) {
-    const int j = qq + s * QT;
-    const int pe = kind == K_ND ? 2 * j : N - 1 - 2 * j;
-    const int po = kind == K_ND ? N - 1 - 2 * j : 2 * j;
-    const cplx<T> z = cmul(cplx<T>{point(pe), point(po)}, ldc(pre, j));
-    lds[(2 * j) * NLP + ln] = z.re;
-    lds[(2 * j + 1) * NLP + ln] = z.im;
-  }
+  pre_to_tile<T, C>(point, lds, pre, kind, ln, qq);
 }
 
 // Register budget of the staging kernel.  FP64 M = 256 in the 16-line tile
