@@ -338,213 +338,12 @@ __device__ __forceinline__ void fast_store(lptr<const T> lds, gptr<T> data, long
   else fast_store_call<T, C>(lds, data, base, sp, layout, lines, kind, inverse, scale, l, q, tid);
 }
 
-// DCT-IV pre-twiddle (in place: each thread scales its own elements).
-template <typename T, typename C>
-__device__ __forceinline__ void fast_iv_pre_body(lptr<T> lds, lptr<const cplx<T>> pre, int l, int q) {
-  using L = FastLayout<T, C>;
-  [[maybe_unused]] constexpr int M = L::M;
-#pragma unroll
-  for (int s = 0; s < L::E; ++s) {
-    const int j = q + s * L::QT;
-    const cplx<T> z = cmul(cplx<T>{lds[(2 * j) * L::NLP + l], lds[(2 * j + 1) * L::NLP + l]},
-                           ldc(pre, j));
-    lds[(2 * j) * L::NLP + l] = z.re;
-    lds[(2 * j + 1) * L::NLP + l] = z.im;
-  }
-  lds_barrier();
-}
-
-template <typename T, typename C>
-__device__ __noinline__ void fast_iv_pre_call(lptr<T> lds, lptr<const cplx<T>> pre, int l, int q) {
-  fast_iv_pre_body<T, C>(lds, pre, l, q);
-}
-
-// INL: inline the stage (async kernel) or call its non-inlined copy
-template <typename T, typename C, bool INL = false>
-__device__ __forceinline__ void fast_iv_pre(lptr<T> lds, lptr<const cplx<T>> pre, int l, int q) {
-  if constexpr (INL) fast_iv_pre_body<T, C>(lds, pre, l, q);
-  else fast_iv_pre_call<T, C>(lds, pre, l, q);
-}
-
-// DCT-IV post-step: V_k = Z_k e^{-i pi k/n}; y_2k = 2 Re V_k, y_{n-1-2k} = -2 Im V_k.
-template <typename T, typename C>
-__device__ __forceinline__ void fast_iv_post_body(lptr<T> lds, lptr<const cplx<T>> post, int l, int q) {
-  using L = FastLayout<T, C>;
-  [[maybe_unused]] constexpr int M = L::M;
-  constexpr int N = L::N;
-  cplx<T> V[L::E];
-#pragma unroll
-  for (int s = 0; s < L::E; ++s) {
-    const int k = q + s * L::QT;
-    V[s] = cmul(cplx<T>{lds[(2 * k) * L::NLP + l], lds[(2 * k + 1) * L::NLP + l]}, ldc(post, k));
-  }
-  lds_barrier();
-#pragma unroll
-  for (int s = 0; s < L::E; ++s) {
-    const int k = q + s * L::QT;
-    lds[(2 * k) * L::NLP + l] = (T)2 * V[s].re;
-    lds[(N - 1 - 2 * k) * L::NLP + l] = (T)-2 * V[s].im;
-  }
-  lds_barrier();
-}
-
-template <typename T, typename C>
-__device__ __noinline__ void fast_iv_post_call(lptr<T> lds, lptr<const cplx<T>> post, int l, int q) {
-  fast_iv_post_body<T, C>(lds, post, l, q);
-}
-
-// INL: inline the stage (async kernel) or call its non-inlined copy
-template <typename T, typename C, bool INL = false>
-__device__ __forceinline__ void fast_iv_post(lptr<T> lds, lptr<const cplx<T>> post, int l, int q) {
-  if constexpr (INL) fast_iv_post_body<T, C>(lds, post, l, q);
-  else fast_iv_post_call<T, C>(lds, post, l, q);
-}
-
-// Inverse P/NN/DD: rebuild the length-M spectrum
-// Z'_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) e^{2 pi i k/n}.
-template <typename T, typename C>
-__device__ __forceinline__ void fast_combine_body(lptr<T> lds, lptr<const cplx<T>> split,
-                                          lptr<const cplx<T>> quarter, int kind, int l, int q) {
-  using L = FastLayout<T, C>;
-  [[maybe_unused]] constexpr int M = L::M;
-  constexpr int N = L::N, NLP = L::NLP;
-  constexpr int NP = M / 2 + 1;
-  constexpr int SP = (NP + L::QT - 1) / L::QT;
-  cplx<T> zk[SP], zj[SP];
-#pragma unroll
-  for (int s = 0; s < SP; ++s) {
-    const int k = q + s * L::QT;
-    if (k < NP) {
-      const int j = M - k;
-      cplx<T> xk, xj;
-      if (kind == K_P) {
-        xk = k == 0 ? cplx<T>{lds[l], (T)0}
-                    : cplx<T>{lds[(2 * k - 1) * NLP + l], -lds[(2 * k) * NLP + l]};
-        xj = j == M ? cplx<T>{lds[(N - 1) * NLP + l], (T)0}
-                    : cplx<T>{lds[(2 * j - 1) * NLP + l], -lds[(2 * j) * NLP + l]};
-      } else {
-        const T yk = lds[k * NLP + l], ynk = k == 0 ? (T)0 : lds[(N - k) * NLP + l];
-        const T yj = lds[j * NLP + l], ynj = lds[(N - j) * NLP + l];
-        xk = cmul(cconj(ldc(quarter, k)), cplx<T>{(T)0.5 * yk, (T)-0.5 * ynk});
-        xj = cmul(cconj(ldc(quarter, j)), cplx<T>{(T)0.5 * yj, (T)-0.5 * ynj});
-      }
-      // split_{M-k} = -conj(split_k)
-      const cplx<T> sk = ldc(split, k);
-      const cplx<T> s1 = cadd(xk, cconj(xj));
-      const cplx<T> d1 = cmul(csub(xk, cconj(xj)), cconj(sk));
-      zk[s] = {s1.re - d1.im, s1.im + d1.re};
-      const cplx<T> s2 = cadd(xj, cconj(xk));
-      const cplx<T> d2 = cmul(csub(cconj(xk), xj), sk);
-      zj[s] = {s2.re - d2.im, s2.im + d2.re};
-    }
-  }
-  lds_barrier();
-#pragma unroll
-  for (int s = 0; s < SP; ++s) {
-    const int k = q + s * L::QT;
-    if (k < NP) {
-      const int j = M - k;
-      lds[(2 * k) * NLP + l] = zk[s].re;
-      lds[(2 * k + 1) * NLP + l] = zk[s].im;
-      if (k > 0 && j != k) {
-        lds[(2 * j) * NLP + l] = zj[s].re;
-        lds[(2 * j + 1) * NLP + l] = zj[s].im;
-      }
-    }
-  }
-  lds_barrier();
-}
-
-template <typename T, typename C>
-__device__ __noinline__ void fast_combine_call(lptr<T> lds, lptr<const cplx<T>> split,
-                                          lptr<const cplx<T>> quarter, int kind, int l, int q) {
-  fast_combine_body<T, C>(lds, split, quarter, kind, l, q);
-}
-
-// INL: inline the stage (async kernel) or call its non-inlined copy
-template <typename T, typename C, bool INL = false>
-__device__ __forceinline__ void fast_combine(lptr<T> lds, lptr<const cplx<T>> split,
-                                          lptr<const cplx<T>> quarter, int kind, int l, int q) {
-  if constexpr (INL) fast_combine_body<T, C>(lds, split, quarter, kind, l, q);
-  else fast_combine_call<T, C>(lds, split, quarter, kind, l, q);
-}
-
-// Forward P/NN/DD: even/odd split of the FFT into the real DFT X_k of the
-// (reordered) input and the stored coefficients (see r2r_kernel.h).
-template <typename T, typename C>
-__device__ __forceinline__ void fast_split_body(lptr<T> lds, lptr<const cplx<T>> split,
-                                        lptr<const cplx<T>> quarter, int kind, int l, int q) {
-  using L = FastLayout<T, C>;
-  [[maybe_unused]] constexpr int M = L::M;
-  constexpr int N = L::N, NLP = L::NLP;
-  constexpr int NP = M / 2 + 1;
-  constexpr int SP = (NP + L::QT - 1) / L::QT;
-  cplx<T> X[SP], Y[SP];
-#pragma unroll
-  for (int s = 0; s < SP; ++s) {
-    const int k = q + s * L::QT;
-    if (k < NP) {
-      const int kc = (M - k) % M;
-      const cplx<T> z = {lds[(2 * k) * NLP + l], lds[(2 * k + 1) * NLP + l]};
-      const cplx<T> zc = {lds[(2 * kc) * NLP + l], -lds[(2 * kc + 1) * NLP + l]};
-      const cplx<T> E = {(T)0.5 * (z.re + zc.re), (T)0.5 * (z.im + zc.im)};
-      const cplx<T> D = csub(z, zc);
-      const cplx<T> O = {(T)0.5 * D.im, (T)-0.5 * D.re};
-      const cplx<T> wO = cmul(ldc(split, k), O);
-      X[s] = cadd(E, wO);
-      Y[s] = cconj(csub(E, wO));
-    }
-  }
-  lds_barrier();
-#pragma unroll
-  for (int s = 0; s < SP; ++s) {
-    const int k = q + s * L::QT;
-    if (k < NP) {
-      const int j = M - k;
-      if (kind == K_P) {
-        if (k == 0) {
-          lds[l] = X[s].re;
-          lds[(N - 1) * NLP + l] = Y[s].re;
-        } else {
-          lds[(2 * k - 1) * NLP + l] = X[s].re;
-          lds[(2 * k) * NLP + l] = -X[s].im;
-          if (j != k) {
-            lds[(2 * j - 1) * NLP + l] = Y[s].re;
-            lds[(2 * j) * NLP + l] = -Y[s].im;
-          }
-        }
-      } else {
-        const bool rev = kind == K_DD;
-        const cplx<T> u = cmul(ldc(quarter, k), X[s]);
-        lds[(rev ? N - 1 - k : k) * NLP + l] = (T)2 * u.re;
-        if (k > 0) lds[(rev ? k - 1 : N - k) * NLP + l] = (T)-2 * u.im;
-        if (j != k) {
-          const cplx<T> u2 = cmul(ldc(quarter, j), Y[s]);
-          lds[(rev ? N - 1 - j : j) * NLP + l] = (T)2 * u2.re;
-          if (j != M) lds[(rev ? j - 1 : N - j) * NLP + l] = (T)-2 * u2.im;
-        }
-      }
-    }
-  }
-  lds_barrier();
-}
-
-template <typename T, typename C>
-__device__ __noinline__ void fast_split_call(lptr<T> lds, lptr<const cplx<T>> split,
-                                        lptr<const cplx<T>> quarter, int kind, int l, int q) {
-  fast_split_body<T, C>(lds, split, quarter, kind, l, q);
-}
-
-// INL: inline the stage (async kernel) or call its non-inlined copy
-template <typename T, typename C, bool INL = false>
-__device__ __forceinline__ void fast_split(lptr<T> lds, lptr<const cplx<T>> split,
-                                        lptr<const cplx<T>> quarter, int kind, int l, int q) {
-  if constexpr (INL) fast_split_body<T, C>(lds, split, quarter, kind, l, q);
-  else fast_split_call<T, C>(lds, split, quarter, kind, l, q);
-}
-
-// Forward P/NN/DD, fused with the store: the even/odd split of
-// fast_split_body, written straight to the field (the forward output order
+// Forward P/NN/DD, fused with the store: from Z (FFT of z_j = v_2j + i
+// v_2j+1, the reordered line) the real DFT X_k of v, pairs (k, M-k) at
+// once: with E = (Z_k + conj Z_{M-k})/2, O = -i (Z_k - conj Z_{M-k})/2 and
+// w = e^{-2 pi i k/n}, X_k = E + w O and X_{M-k} = conj(E - w O); then the
+// stored coefficients (Table 2's interleaving, or the quarter twiddle of
+// DCT-II/DST-II), written straight to the field (the forward output order
 // of these types is the tile's row order).  Strided layout: lines on
 // consecutive lanes (rows of NL values); contiguous: a line's points on
 // consecutive lanes.
@@ -648,10 +447,13 @@ __device__ __noinline__ void post_store_call(lptr<const T> lds, lptr<const cplx<
   post_store_body<T, C>(lds, post, kind, data, base, sp, layout, lines, scale, l, q, tid);
 }
 
-// Inverse P/NN/DD, fused with the placement: the length-M spectrum Z' of
-// fast_combine_body written into the tile (column ln, pairs k = qq + s QT)
-// from the input points of the line, point(p) (tile row r holds point r,
-// D-D: point n-1-r).
+// Inverse P/NN/DD, fused with the placement: from the stored coefficients
+// X of a line (the real DFT of Table 2's storage, or the quarter-twiddled
+// DCT-II/DST-II spectrum), the length-M complex spectrum
+// Z'_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) e^{2 pi i k/n}
+// whose inverse FFT interleaves the even and odd output points; written
+// into the tile (column ln, pairs k = qq + s QT) from the input points of
+// the line, point(p) (tile row r holds point r, D-D: point n-1-r).
 template <typename T, typename C, typename Point>
 __device__ __forceinline__ void combine_to_tile(Point point, lptr<T> lds,
                                                 lptr<const cplx<T>> split,
