@@ -359,7 +359,7 @@ static int resident_grid(const void* fn, int block, size_t lds, long long ntiles
 // of configuration C.
 template <typename T, typename C>
 static R2RFastArgs<T> fast_args(const poisson_plan* p, const AxisTables& A, int inverse, T* data,
-                                const double* skip) {
+                                const double* skip, double* out64 = nullptr) {
   constexpr int M = C::M;
   R2RFastArgs<T> a{};
   a.data = data;
@@ -375,13 +375,14 @@ static R2RFastArgs<T> fast_args(const poisson_plan* p, const AxisTables& A, int 
   a.tw_pre = tw + 3 * M + 2;
   a.tw_post = tw + 4 * M + 2;
   a.skip = skip;
+  a.out64 = out64;
   return a;
 }
 
 template <typename T, typename C>
 static int launch_fast(const poisson_plan* p, const AxisTables& A, int inverse, T* data,
-                       hipStream_t st, const double* skip) {
-  const R2RFastArgs<T> a = fast_args<T, C>(p, A, inverse, data, skip);
+                       hipStream_t st, const double* skip, double* out64 = nullptr) {
+  const R2RFastArgs<T> a = fast_args<T, C>(p, A, inverse, data, skip, out64);
   const size_t lds = fast_lds_bytes<T, C>();
   const void* fn = reinterpret_cast<const void*>(&r2r_fast_kernel<T, C>);
   hipLaunchKernelGGL((r2r_fast_kernel<T, C>), dim3(resident_grid(fn, 512, lds, a.g.ntiles)),
@@ -402,17 +403,17 @@ static bool async_shape_exists(int m, int shape) {
 
 template <typename T>
 static int launch_async(const poisson_plan* p, const AxisTables& A, int shape, int inverse,
-                        T* data, hipStream_t st, const double* skip) {
+                        T* data, hipStream_t st, const double* skip, double* out64 = nullptr) {
   if (A.m != 128 && A.m != 256) return -1;
   if (A.axis != 0 && p->dims[0] % (int)(16 / sizeof(T)) != 0) return -1;
   if (!async_shape_exists<T>(A.m, shape)) return -1;
   R2RFastArgs<T> a;
   switch (A.m * 4 + shape) {
-    case 128 * 4 + 0: a = fast_args<T, AsyncVar<128, 0>>(p, A, inverse, data, skip); break;
-    case 128 * 4 + 1: a = fast_args<T, AsyncVar<128, 1>>(p, A, inverse, data, skip); break;
-    case 256 * 4 + 0: a = fast_args<T, AsyncVar<256, 0>>(p, A, inverse, data, skip); break;
-    case 256 * 4 + 1: a = fast_args<T, AsyncVar<256, 1>>(p, A, inverse, data, skip); break;
-    default: a = fast_args<T, AsyncVar<256, 2>>(p, A, inverse, data, skip); break;
+    case 128 * 4 + 0: a = fast_args<T, AsyncVar<128, 0>>(p, A, inverse, data, skip, out64); break;
+    case 128 * 4 + 1: a = fast_args<T, AsyncVar<128, 1>>(p, A, inverse, data, skip, out64); break;
+    case 256 * 4 + 0: a = fast_args<T, AsyncVar<256, 0>>(p, A, inverse, data, skip, out64); break;
+    case 256 * 4 + 1: a = fast_args<T, AsyncVar<256, 1>>(p, A, inverse, data, skip, out64); break;
+    default: a = fast_args<T, AsyncVar<256, 2>>(p, A, inverse, data, skip, out64); break;
   }
   const hipError_t e = async_transform_launch(a, A.m, shape, A.kind, inverse, st);
   if (e != hipSuccess)
@@ -431,24 +432,27 @@ static bool async_applies(const poisson_plan* p, const AxisTables& A, int shape)
 // Specialised transform of axis A in variant V (-1: the length has none).
 template <typename T>
 static int launch_fast_variant(const poisson_plan* p, const AxisTables& A, int V, int inverse,
-                               T* data, hipStream_t st, const double* skip) {
+                               T* data, hipStream_t st, const double* skip,
+                               double* out64 = nullptr) {
   if (V >= kAsyncVariant) {
-    const int rc = launch_async<T>(p, A, V - kAsyncVariant, inverse, data, st, skip);
+    const int rc = launch_async<T>(p, A, V - kAsyncVariant, inverse, data, st, skip, out64);
     if (rc != -1) return rc;
     V = 0;
   }
   return (int)with_fast_cfg(A.m, V, [&](auto cfg) {
-    return (long long)launch_fast<T, decltype(cfg)>(p, A, inverse, data, st, skip);
+    return (long long)launch_fast<T, decltype(cfg)>(p, A, inverse, data, st, skip, out64);
   });
 }
 
+// out64 (FP32 only): write the widened result there instead of in place.
 template <typename T>
 static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hipStream_t st,
-                      const double* skip = nullptr) {
+                      const double* skip = nullptr, double* out64 = nullptr) {
   const AxisTables& A = p->ax[role];
+  if constexpr (sizeof(T) == 8) out64 = nullptr;
   if (!p->generic_r2r) {
     const int rc = launch_fast_variant<T>(p, A, tuned_choice(0, sizeof(T), A.m, A.axis == 0),
-                                          inverse, data, st, skip);
+                                          inverse, data, st, skip, out64);
     if (rc != -1) return rc;
   }
   constexpr int EMAX = sizeof(T) == 8 ? R2R_EMAX_D : R2R_EMAX_F;
@@ -479,6 +483,7 @@ static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hip
   a.tw_pre = tw + 3 * A.m + 2;
   a.tw_post = tw + 4 * A.m + 2;
   a.skip = skip;
+  a.out64 = out64;
   const size_t lds = (size_t)A.n * a.nlp * sizeof(T);
   if (lds > LDS_LIMIT) return fail(POISSON_EUNSUPPORTED, "transform tile needs %zu B of LDS", lds);
   const void* fn = reinterpret_cast<const void*>(&r2r_kernel<T, EMAX, R2R_NT>);
@@ -618,16 +623,17 @@ static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
 }
 
 // The three steps of Sec. 2.1: forward transforms t1 then t2, elimination
-// along s, backward transforms t2 then t1.
+// along s, backward transforms t2 then t1.  out64 (FP32 only): the last
+// launch writes the widened solution there instead of in place.
 template <typename T>
 static int solve_typed(const poisson_plan* p, T* data, hipStream_t st,
-                       const double* skip = nullptr) {
+                       const double* skip = nullptr, double* out64 = nullptr) {
   int rc;
   if ((rc = launch_r2r<T>(p, 0, 0, data, st, skip))) return rc;
   if ((rc = launch_r2r<T>(p, 1, 0, data, st, skip))) return rc;
   if ((rc = launch_tridiag<T>(p, data, st, skip))) return rc;
   if ((rc = launch_r2r<T>(p, 1, 1, data, st, skip))) return rc;
-  if ((rc = launch_r2r<T>(p, 0, 1, data, st, skip))) return rc;
+  if ((rc = launch_r2r<T>(p, 0, 1, data, st, skip, out64))) return rc;
   return POISSON_OK;
 }
 
@@ -968,8 +974,8 @@ static int solve_refined(poisson_plan* p, double* rhs, hipStream_t st) {
                      (const double*)p->stats, (int)p->singular, N);
   HIP_TRY(hipGetLastError());
   int rc;
-  if ((rc = solve_typed<float>(p, p->e32, st))) return rc;
-  hipLaunchKernelGGL(refine_widen_kernel, grid, block, 0, st, (const float*)p->e32, rhs, N);
+  // the first FP32 solve's last pass writes Phi (widened) into rhs
+  if ((rc = solve_typed<float>(p, p->e32, st, nullptr, rhs))) return rc;
   for (int sweep = 1; sweep < p->max_iters; ++sweep) {
     hipLaunchKernelGGL(refine_residual_kernel, dim3(rg.blocks), block, 0, st, (const double*)rhs,
                        (const double*)p->f64, p->e32, G, rg);

@@ -114,6 +114,7 @@ struct R2RFastArgs {
   const cplx<T>* tw_pre;     // M
   const cplx<T>* tw_post;    // M
   const double* skip;
+  double* out64;             // optional (FP32): write the widened result there, not in data
 };
 
 template <typename T, typename C>
@@ -284,8 +285,10 @@ __device__ __forceinline__ void fast_load(lptr<T> lds, gptr<const T> data, long 
 }
 
 // Tile store: LDS rows -> global with the output permutation, sign, scale.
-template <typename T, typename C>
-__device__ __forceinline__ void fast_store_body(lptr<const T> lds, gptr<T> data, long long base,
+// O: the element type written (T, or double for the widened last pass of
+// an FP32 solve).
+template <typename T, typename C, typename O = T>
+__device__ __forceinline__ void fast_store_body(lptr<const T> lds, gptr<O> data, long long base,
                                         long long sp, int layout, int lines, int kind,
                                         int inverse, T scale, int l, int q, int tid) {
   using L = FastLayout<T, C>;
@@ -302,7 +305,7 @@ __device__ __forceinline__ void fast_store_body(lptr<const T> lds, gptr<T> data,
     }
     if (base >= 0) {
 #pragma unroll
-      for (int i = 0; i < L::EPT; ++i) data[base + (q + i * L::QT) * sp] = buf[i];
+      for (int i = 0; i < L::EPT; ++i) data[base + (q + i * L::QT) * sp] = (O)buf[i];
     }
   } else {
 #pragma unroll
@@ -317,25 +320,27 @@ __device__ __forceinline__ void fast_store_body(lptr<const T> lds, gptr<T> data,
 #pragma unroll
     for (int i = 0; i < L::EPT; ++i) {
       const int e = tid + i * L::NT;
-      if ((e / N) < lines) data[base + e] = buf[i];
+      if ((e / N) < lines) data[base + e] = (O)buf[i];
     }
   }
 }
 
-template <typename T, typename C>
-__device__ __noinline__ void fast_store_call(lptr<const T> lds, gptr<T> data, long long base,
+template <typename T, typename C, typename O = T>
+__device__ __noinline__ void fast_store_call(lptr<const T> lds, gptr<O> data, long long base,
                                         long long sp, int layout, int lines, int kind,
                                         int inverse, T scale, int l, int q, int tid) {
-  fast_store_body<T, C>(lds, data, base, sp, layout, lines, kind, inverse, scale, l, q, tid);
+  fast_store_body<T, C, O>(lds, data, base, sp, layout, lines, kind, inverse, scale, l, q, tid);
 }
 
 // INL: inline the stage (async kernel) or call its non-inlined copy
-template <typename T, typename C, bool INL = false>
-__device__ __forceinline__ void fast_store(lptr<const T> lds, gptr<T> data, long long base,
+template <typename T, typename C, bool INL = false, typename O = T>
+__device__ __forceinline__ void fast_store(lptr<const T> lds, gptr<O> data, long long base,
                                         long long sp, int layout, int lines, int kind,
                                         int inverse, T scale, int l, int q, int tid) {
-  if constexpr (INL) fast_store_body<T, C>(lds, data, base, sp, layout, lines, kind, inverse, scale, l, q, tid);
-  else fast_store_call<T, C>(lds, data, base, sp, layout, lines, kind, inverse, scale, l, q, tid);
+  if constexpr (INL)
+    fast_store_body<T, C, O>(lds, data, base, sp, layout, lines, kind, inverse, scale, l, q, tid);
+  else
+    fast_store_call<T, C, O>(lds, data, base, sp, layout, lines, kind, inverse, scale, l, q, tid);
 }
 
 // Forward P/NN/DD, fused with the store: from Z (FFT of z_j = v_2j + i
@@ -407,9 +412,9 @@ __device__ __forceinline__ void split_store_body(lptr<const T> lds, lptr<const c
 // DCT-IV / DST-IV, fused with the store: V_k = Z_k times the post-twiddle;
 // output point 2k is 2 Re V_k and point n-1-2k is -2 Im V_k (D-N: odd
 // points change sign).  Lane mapping as in split_store_body.
-template <typename T, typename C>
+template <typename T, typename C, typename O = T>
 __device__ __forceinline__ void post_store_body(lptr<const T> lds, lptr<const cplx<T>> post,
-                                                 int kind, gptr<T> data, long long base,
+                                                 int kind, gptr<O> data, long long base,
                                                  long long sp, int layout, int lines, T scale,
                                                  int l, int q, int tid) {
   using L = FastLayout<T, C>;
@@ -426,8 +431,8 @@ __device__ __forceinline__ void post_store_body(lptr<const T> lds, lptr<const cp
                            ldc(post, k));
     const T ye = ((T)2 * V.re) * scale;      // point 2k (even)
     const T yo = ((T)-2 * V.im) * scale;     // point n-1-2k (odd)
-    data[lb + (2 * k) * ps] = ye;
-    data[lb + (N - 1 - 2 * k) * ps] = kind == K_ND ? yo : -yo;
+    data[lb + (2 * k) * ps] = (O)ye;
+    data[lb + (N - 1 - 2 * k) * ps] = (O)(kind == K_ND ? yo : -yo);
   }
 }
 
@@ -440,11 +445,11 @@ __device__ __noinline__ void split_store_call(lptr<const T> lds, lptr<const cplx
   split_store_body<T, C>(lds, split, quarter, kind, data, base, sp, layout, lines, scale, l, q, tid);
 }
 
-template <typename T, typename C>
+template <typename T, typename C, typename O = T>
 __device__ __noinline__ void post_store_call(lptr<const T> lds, lptr<const cplx<T>> post, int kind,
-                                             gptr<T> data, long long base, long long sp, int layout,
+                                             gptr<O> data, long long base, long long sp, int layout,
                                              int lines, T scale, int l, int q, int tid) {
-  post_store_body<T, C>(lds, post, kind, data, base, sp, layout, lines, scale, l, q, tid);
+  post_store_body<T, C, O>(lds, post, kind, data, base, sp, layout, lines, scale, l, q, tid);
 }
 
 // Inverse P/NN/DD, fused with the placement: from the stored coefficients
@@ -656,16 +661,31 @@ __device__ __forceinline__ void fast_tile(const FastLds<T, C>& S, const R2RFastA
   if (!(inverse && kind <= K_DD)) fast_passes<T, C, true, 0>(S.tile, tw_fft, l, q);
   else fast_passes<T, C, false, 0>(S.tile, tw_fft, l, q);
 
-  // the DCT-IV post-twiddle and the forward split write the field directly
-  if (ivk)
-    post_store_call<T, C>(S.tile, tw_b, kind, as_global(A.data), base, g.sp, g.layout, lines,
-                          A.scale, l, q, tid);
-  else if (!inverse)
-    split_store_call<T, C>(S.tile, tw_a, tw_b, kind, as_global(A.data), base, g.sp, g.layout,
-                           lines, A.scale, l, q, tid);
-  else
-    fast_store<T, C>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind, inverse,
-                     A.scale, l, q, tid);
+  // the DCT-IV post-twiddle and the forward split write the field directly;
+  // an FP32 pass with out64 writes the widened values there instead
+  bool widened = false;
+  if constexpr (sizeof(T) == 4) {
+    if (A.out64) {
+      widened = true;
+      if (ivk)
+        post_store_call<T, C, double>(S.tile, tw_b, kind, as_global(A.out64), base, g.sp, g.layout,
+                                      lines, A.scale, l, q, tid);
+      else
+        fast_store<T, C, false, double>(S.tile, as_global(A.out64), base, g.sp, g.layout, lines,
+                                        kind, inverse, A.scale, l, q, tid);
+    }
+  }
+  if (!widened) {
+    if (ivk)
+      post_store_call<T, C>(S.tile, tw_b, kind, as_global(A.data), base, g.sp, g.layout, lines,
+                            A.scale, l, q, tid);
+    else if (!inverse)
+      split_store_call<T, C>(S.tile, tw_a, tw_b, kind, as_global(A.data), base, g.sp, g.layout,
+                             lines, A.scale, l, q, tid);
+    else
+      fast_store<T, C>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind, inverse,
+                       A.scale, l, q, tid);
+  }
   lds_barrier();
 }
 
@@ -811,6 +831,23 @@ __device__ __forceinline__ void async_place_pre(lptr<const T> stage, lptr<T> lds
   pre_to_tile<T, C>(point, lds, pre, kind, ln, qq);
 }
 
+// The widened store of the last pass of an FP32 solve (staging kernels):
+// the inverse output (or the DCT-IV post-twiddled one) as FP64 into
+// A.out64.  FP32 only.
+template <typename T, typename C, bool IVK>
+__device__ __forceinline__ void async_store_wide(lptr<const T> lds, lptr<const cplx<T>> post,
+                                                 int kind, int inverse, const R2RFastArgs<T>& A,
+                                                 long long base, int lines, int l, int q, int tid) {
+  if constexpr (sizeof(T) == 4) {
+    if constexpr (IVK)
+      post_store_body<T, C, double>(lds, post, kind, as_global(A.out64), base, A.g.sp, A.g.layout,
+                                    lines, A.scale, l, q, tid);
+    else
+      fast_store_body<T, C, double>(lds, as_global(A.out64), base, A.g.sp, A.g.layout, lines, kind,
+                                    inverse, A.scale, l, q, tid);
+  }
+}
+
 // Register budget of the staging kernel.  FP64 M = 256 in the 16-line tile
 // shape (DFT and DCT-IV types): one block fills a CU's LDS, so the kernel may use up to 256 VGPRs
 // and keep every stage's addresses live across the tile loop (fastest).  Otherwise the per-thread
@@ -882,7 +919,10 @@ struct AsyncBudget {
     base = (long long)o.L0 * L::N;                                                             \
     lines = g.nlines - o.L0;                                                                   \
   }                                                                                            \
-  if constexpr (ivk) {                                                                         \
+  if (sizeof(T) == 4 && A.out64) { /* widened last pass of an FP32 solve */                   \
+    async_store_wide<T, C, ivk>(S.tile, tw_b, kind, inverse, A, base, lines, LT, QT, TIDT);      \
+    stores_pending = false;                                                                    \
+  } else if constexpr (ivk) {                                                                  \
     post_store_body<T, C>(S.tile, tw_b, kind, as_global(A.data), base, g.sp, g.layout, lines, \
                            A.scale, LT, QT, TIDT);                                             \
     stores_pending = false;                                                                    \

@@ -49,6 +49,7 @@ struct R2RArgs {
   const cplx<T>* tw_pre;     // m     : e^{-i pi (4j+1)/(4n)}
   const cplx<T>* tw_post;    // m     : e^{-i pi k/n}
   const double* skip;        // optional: when *skip != 0 the launch does nothing
+  double* out64;             // optional (FP32): write the widened result there, not in data
 };
 
 // ---------------------------------------------------------------- small DFTs
@@ -469,8 +470,10 @@ __device__ __noinline__ void r2r_load_tile(T* lds, const T* __restrict__ data, G
   }
 }
 
-template <typename T, int EPT, int NT>
-__device__ __noinline__ void r2r_store_tile(const T* lds, T* __restrict__ data, GEOM_PARAMS,
+// O: the element type written (T, or double for the widened last pass of
+// an FP32 solve).
+template <typename T, int EPT, int NT, typename O = T>
+__device__ __noinline__ void r2r_store_tile(const T* lds, O* __restrict__ data, GEOM_PARAMS,
                                             int tile, int kind, int inverse, int nlp,
                                             unsigned n_magic, T scale, int tid) {
   const LineGeom g = GEOM_REBUILD;
@@ -493,7 +496,7 @@ __device__ __noinline__ void r2r_store_tile(const T* lds, T* __restrict__ data, 
   for (int i = 0; i < EPT; ++i) {
     int l, q;
     const long long off = tile_elem<NT>(g, o, sbase, n_magic, tid, i, l, q);
-    if (off >= 0) as_global(data)[off] = buf[i];
+    if (off >= 0) as_global(data)[off] = (O)buf[i];
   }
 }
 
@@ -529,7 +532,17 @@ void r2r_kernel(R2RArgs<T> A) {
     else if (!inverse)
       split_forward<T, EMAX, NT>(lds, kind, n, A.m, lognl, nlp, A.tw_split, A.tw_quarter, tid);
 
-    r2r_store_tile<T, 2 * EMAX, NT>(lds, data, GEOM_ARGS(g), tile, kind, inverse, nlp, A.n_magic, A.scale, tid);
+    bool widened = false;
+    if constexpr (sizeof(T) == 4) {
+      if (A.out64) {   // last pass of an FP32 solve: the widened result into out64
+        widened = true;
+        r2r_store_tile<T, 2 * EMAX, NT, double>(lds, A.out64, GEOM_ARGS(g), tile, kind, inverse,
+                                                nlp, A.n_magic, A.scale, tid);
+      }
+    }
+    if (!widened)
+      r2r_store_tile<T, 2 * EMAX, NT>(lds, data, GEOM_ARGS(g), tile, kind, inverse, nlp,
+                                      A.n_magic, A.scale, tid);
     __syncthreads();
   }
 }

@@ -138,15 +138,6 @@ __global__ __launch_bounds__(REFINE_NT) void refine_prep_kernel(const double* __
   }
 }
 
-// phi = (double) e32
-__global__ __launch_bounds__(REFINE_NT) void refine_widen_kernel(const float* __restrict__ e32,
-                                                                  double* __restrict__ phi,
-                                                                  long long npts) {
-  for (long long idx = blockIdx.x * (long long)REFINE_NT + threadIdx.x; idx < npts;
-       idx += (long long)gridDim.x * REFINE_NT)
-    phi[idx] = (double)e32[idx];
-}
-
 // x -= stats[1]
 __global__ __launch_bounds__(REFINE_NT) void refine_shift_kernel(double* __restrict__ x,
                                                                   const double* stats,
