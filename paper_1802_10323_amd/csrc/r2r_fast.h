@@ -891,13 +891,20 @@ struct AsyncBudget {
   const TileRange tr = xcd_tiles(g.ntiles);                                                    \
   const lptr<unsigned char> stage_lds = as_lds(stage_raw);                                     \
   if (tr.first < tr.end) async_fetch<T, C>(stage_lds, A, tr.first, tid);                      \
-  /* stores of the previous tile issued after the staged reads: EPT per */                    \
-  /* thread (every wave stores every element row of a whole tile), else 0 */                  \
+  /* Stores of the previous tile issued after the staged reads, a lower */                     \
+  /* bound per wave for a whole tile: the plain and DCT-IV stores write */                    \
+  /* every element (EPT); the forward split writes 4 points for every */                     \
+  /* pair k of 1 <= k < M/2, and each wave has such lanes in each of the */                   \
+  /* first M/(2 QT) steps (its line stride is a run-time value, so the */                     \
+  /* compiler cannot merge two of them into one instruction).  Ragged */                      \
+  /* tiles keep nothing in flight. */                                                          \
+  constexpr int KEEP = (ivk || inverse) ? L::EPT : 4 * (M / (2 * L::QT));                      \
+  static_assert(KEEP >= 1 && KEEP < 64, "vector-memory counter range");                       \
   bool stores_pending = false;
 
 #define POISSON_ASYNC_TILE(LT, QT, TIDT)                                                        \
   /* this wave's staged reads are done (the previous tile's stores may not be) */             \
-  if (stores_pending) vm_wait_keep<L::EPT>();                                                  \
+  if (stores_pending) vm_wait_keep<KEEP>();                                                    \
   else __builtin_amdgcn_s_waitcnt(0);                                                          \
   lds_barrier();                 /* ... and every wave's */                                    \
   if constexpr (ivk)                                                                           \
@@ -925,16 +932,16 @@ struct AsyncBudget {
   } else if constexpr (ivk) {                                                                  \
     post_store_body<T, C>(S.tile, tw_b, kind, as_global(A.data), base, g.sp, g.layout, lines, \
                            A.scale, LT, QT, TIDT);                                             \
-    stores_pending = false;                                                                    \
+    stores_pending = g.layout == 0 || lines >= NL;                                             \
   } else if constexpr (!inverse) {                                                             \
     split_store_body<T, C>(S.tile, tw_a, tw_b, kind, as_global(A.data), base, g.sp, g.layout,  \
                             lines, A.scale, LT, QT, TIDT);                                     \
-    stores_pending = false; /* store count varies by lane group: wait for all */               \
+    stores_pending = g.layout == 0 || lines >= NL;                                             \
   } else {                                                                                     \
     fast_store<T, C, true>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind,       \
                            inverse, A.scale, LT, QT, TIDT);                                    \
     /* strided tiles: each wave holds line 0, which always exists, so it */                   \
-    /* issues all EPT stores; contiguous tiles only when no line is missing */                \
+    /* issues all its stores; contiguous tiles only when no line is missing */                \
     stores_pending = g.layout == 0 || lines >= NL;                                             \
   }                                                                                            \
   lds_barrier();
