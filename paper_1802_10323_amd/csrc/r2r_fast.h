@@ -7,7 +7,13 @@
 // the lines per tile (NL) and the threads per line (QT) are compile-time
 // constants of each (non-inlined) stage, so LDS offsets, twiddle indices and
 // loop counts fold to constants.  A persistent block copies its twiddle
-// tables into LDS once and then loops over tiles.
+// tables into LDS once and then loops over tiles.  The pre-steps (inverse
+// combine, DCT-IV pre-twiddle) are done while the tile is brought into LDS
+// and the post-steps (forward split, DCT-IV post-twiddle) while it is
+// written out, so the FFT passes are the only LDS round trips in between.
+// Two kernel forms: r2r_fast_kernel reads each tile from HBM when it starts
+// on it; the staging kernels (r2r_async_kernel, n = 256 and 512) have the
+// next tile's reads in flight during the current tile.
 //
 // LDS per block: the tile (2M rows of NL+1 values) plus 3M complex twiddles:
 // the FFT table (M) and either the DCT-IV pre/post tables (M + M) or half
@@ -18,6 +24,9 @@
 // Thread t of NT = QT*NL works on line l = t mod NL (consecutive lanes =
 // consecutive lines, i.e. consecutive x on a strided axis) and handles the
 // butterflies / elements q, q + QT, q + 2 QT, ... of that line, q = t / NL.
+// The fused pre/post steps on the contiguous axis instead put a line's
+// points on consecutive lanes (line t / QT, element t mod QT), matching the
+// line-major order of the data there.
 #pragma once
 #include <type_traits>
 #include "r2r_kernel.h"
