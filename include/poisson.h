@@ -122,15 +122,16 @@ size_t plan_workspace_bytes(const poisson_plan* plan);
 int solve_status(poisson_plan* plan, int* iters, double* last_update_rel);
 
 /* Solve `count` independent problems, plans[i] applied in place to rhs[i]
- * (DEVICE pointers), on `stream`.  FP64 plans only; plans must be distinct.
- * Same result per instance as solve() with the same kernel variants, bit for
- * bit (batched launches use transform variants 0-3; against solve() with the
- * staging transforms, variants 4 and 5, results agree to rounding).  When every plan's lengths
- * have size-specialised kernels (batch_create), the solves run as one
- * persistent launch per stage over all instances and the call waits for
- * `stream` to complete (it frees its temporary job tables); otherwise the
- * instances' launches are enqueued one solve after another and the call
- * returns at once. */
+ * (DEVICE pointers), on `stream`.  An FP32 + refinement plan may appear only
+ * once (its workspace is per plan; POISSON_EINVAL otherwise).  Same result
+ * per instance as solve() with the same kernel variants, bit for bit
+ * (batched launches use transform variants 0-3; against solve() with the
+ * staging transforms, variants 4-6, results agree to rounding).  When every
+ * plan's lengths have size-specialised kernels (batch_create) and all plans
+ * have one precision mode, the solves run as batched launches (see below)
+ * and the call waits for `stream` to complete (it frees its temporary job
+ * tables); otherwise the instances are solved one after another with
+ * solve() and the call returns at once. */
 int batch_solve(poisson_plan* const* plans, double* const* rhs, int count, hipStream_t stream);
 
 /* ---- batched launches (many uneven instances, Sec. 2.1 per instance) ----
@@ -139,11 +140,17 @@ int batch_solve(poisson_plan* const* plans, double* const* rhs, int count, hipSt
  * five launches, one per pipeline step (forward t1, forward t2, elimination,
  * backward t2, backward t1).  Each launch is a persistent grid whose work
  * items are the tiles of every instance's stage, so instances of different
- * sizes, boundary pairs and axis roles share one launch. */
+ * sizes, boundary pairs and axis roles share one launch.  A batch of FP32 +
+ * refinement plans runs each FP32 solve of the refinement that way, with
+ * the FP64 refinement kernels of every instance (residual, update,
+ * convergence test) between them; an instance whose refinement has
+ * converged, or reached its max_iters, drops out of the later launches. */
 typedef struct poisson_batch poisson_batch;
 
-/* Batch over `count` FP64 plans (HOST array of plan handles, all created on
- * the current device).  The plans are borrowed: they must outlive the batch.
+/* Batch over `count` plans (HOST array of plan handles, all created on the
+ * current device, all FP64 or all FP32 + refinement; a refined plan at most
+ * once).  The plans are borrowed: they must outlive the batch, and their
+ * precision mode must not change while it exists.
  * Every transformed length must be 2M with M in {16, 32, 48, 64, 96, 128,
  * 192, 256} and every elimination length one of {64, 96, 128, 192, 256, 384,
  * 512} (POISSON_EUNSUPPORTED otherwise).  Allocates the device job tables.
@@ -153,12 +160,15 @@ poisson_batch* batch_create(poisson_plan* const* plans, int count);
 /* Set the fields: rhs is a HOST array of `count` DEVICE pointers, rhs[i] is
  * solved in place with plans[i] (nx*ny*nz doubles, x fastest).  Copies the job
  * tables to the device synchronously; must not be called while a launch of
- * this batch may still be running.  A captured graph stays valid. */
+ * this batch may still be running.  A captured graph stays valid for an
+ * FP64 batch (a refined batch captures again at its next graph launch). */
 int batch_bind(poisson_batch* batch, double* const* rhs);
 
-/* Enqueue the five stage launches on `stream` (asynchronous).  use_graph != 0:
- * the first call captures them into a HIP graph on a private stream, and every
- * call launches that graph on `stream`. */
+/* Enqueue the batched solve on `stream` (asynchronous): the five stage
+ * launches, or for a refined batch the whole refinement sequence (after the
+ * stream completes, solve_status() of each plan reports its refinement).
+ * use_graph != 0: the first call captures the launches into a HIP graph on
+ * a private stream, and every call launches that graph on `stream`. */
 int batch_launch(poisson_batch* batch, hipStream_t stream, int use_graph);
 
 /* Free the job tables and the graph.  The caller makes sure no launch of the

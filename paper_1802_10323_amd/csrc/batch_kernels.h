@@ -72,6 +72,7 @@ void batch_r2r_kernel(const BatchR2RJob<T>* __restrict__ jobs, int njobs, int it
   const TileRange tr = xcd_tiles(items);
   for (int it = tr.first; it < tr.end; it += tr.step) {
     const BatchR2RJob<T>& J = jobs[batch_job_of(jobs, njobs, it)];
+    if (J.a.skip && J.a.skip[0] != 0.0) continue;   // instance done (refinement converged)
     const int tile = it - J.first;
     switch (J.M * 4 + J.V) {
 #define POISSON_BV(M_, V_) \
@@ -111,6 +112,7 @@ void batch_tri_kernel(const BatchTriJob<T>* __restrict__ jobs, int njobs, int it
   for (int it = tr.first; it < tr.end; it += tr.step) {
     const int j = batch_job_of(jobs, njobs, it);
     const BatchTriJob<T>& J = jobs[j];
+    if (J.a.skip && J.a.skip[0] != 0.0) continue;   // instance done (refinement converged)
     const int tile = it - J.first;
     switch (J.key) {
 #define POISSON_BT(N_, V_, R_, P_) \

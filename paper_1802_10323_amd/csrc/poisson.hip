@@ -275,6 +275,8 @@ static int lds_setup_once() {
         });
     ALLOW((batch_r2r_kernel<double>));
     ALLOW((batch_tri_kernel<double>));
+    ALLOW((batch_r2r_kernel<float>));
+    ALLOW((batch_tri_kernel<float>));
 #undef ALLOW
     status = e == hipSuccess ? 0 : fail(POISSON_EHIP, "hipFuncSetAttribute: %s", hipGetErrorString(e));
   });
@@ -959,39 +961,88 @@ static RefineGeom refine_geom(const poisson_plan* p) {
 //   f~ = f (minus its weighted mean if singular), Phi = solve32(f~);
 //   repeat: r = f~ - A Phi (FP64), e = solve32(r), Phi += e (FP64);
 //   finally, if singular, remove the weighted mean of Phi (FP64).
-static int solve_refined(poisson_plan* p, double* rhs, hipStream_t st) {
-  const long long N = (long long)field_points(p);
-  const RefineGeom G = refine_geom(p);
-  const int nb = (int)std::min<long long>(REFINE_BLOCKS, (N + REFINE_NT - 1) / REFINE_NT);
-  const dim3 grid(nb), block(REFINE_NT);
-  const ResidualGrid rg = residual_grid(p->dims[0], p->dims[1], p->dims[2]);
+// Pieces of the refined solve, shared with the batched form.
+struct RefineLaunch {
+  long long N;
+  RefineGeom G;
+  int nb;
+  ResidualGrid rg;
+};
+
+static RefineLaunch refine_launch(const poisson_plan* p) {
+  RefineLaunch r;
+  r.N = (long long)field_points(p);
+  r.G = refine_geom(p);
+  r.nb = (int)std::min<long long>(REFINE_BLOCKS, (r.N + REFINE_NT - 1) / REFINE_NT);
+  r.rg = residual_grid(p->dims[0], p->dims[1], p->dims[2]);
+  return r;
+}
+
+// Status reset, projection of f if singular, the FP64 copy of f and its FP32 cast.
+static int refine_begin(poisson_plan* p, double* rhs, hipStream_t st) {
+  const RefineLaunch r = refine_launch(p);
   hipLaunchKernelGGL(refine_init_kernel, dim3(1), dim3(256), 0, st, p->stats);
   if (p->singular) {
-    hipLaunchKernelGGL(refine_wsum_kernel, grid, block, 0, st, (const double*)rhs, G);
-    hipLaunchKernelGGL(refine_mean_kernel, dim3(1), block, 0, st, p->stats, nb);
+    hipLaunchKernelGGL(refine_wsum_kernel, dim3(r.nb), dim3(REFINE_NT), 0, st, (const double*)rhs, r.G);
+    hipLaunchKernelGGL(refine_mean_kernel, dim3(1), dim3(REFINE_NT), 0, st, p->stats, r.nb);
   }
-  hipLaunchKernelGGL(refine_prep_kernel, grid, block, 0, st, (const double*)rhs, p->f64, p->e32,
-                     (const double*)p->stats, (int)p->singular, N);
+  hipLaunchKernelGGL(refine_prep_kernel, dim3(r.nb), dim3(REFINE_NT), 0, st, (const double*)rhs,
+                     p->f64, p->e32, (const double*)p->stats, (int)p->singular, r.N);
   HIP_TRY(hipGetLastError());
-  int rc;
-  // the first FP32 solve's last pass writes Phi (widened) into rhs
-  if ((rc = solve_typed<float>(p, p->e32, st, nullptr, rhs))) return rc;
-  for (int sweep = 1; sweep < p->max_iters; ++sweep) {
-    hipLaunchKernelGGL(refine_residual_kernel, dim3(rg.blocks), block, 0, st, (const double*)rhs,
-                       (const double*)p->f64, p->e32, G, rg);
-    if ((rc = solve_typed<float>(p, p->e32, st, p->stats))) return rc;
-    hipLaunchKernelGGL(refine_update_kernel, grid, block, 0, st, rhs, (const float*)p->e32, G);
-    hipLaunchKernelGGL(refine_status_kernel, dim3(1), block, 0, st, p->stats, nb, sweep, p->tol);
-  }
+  return POISSON_OK;
+}
+
+// Sweep `sweep` before its FP32 solve: the FP64 residual into e32; a plan
+// whose iteration limit is reached is stopped instead (later kernels of the
+// fixed sequence return at once, the converged flag is left as it is).
+static int refine_sweep_begin(poisson_plan* p, double* rhs, int sweep, hipStream_t st) {
+  const RefineLaunch r = refine_launch(p);
+  if (sweep >= p->max_iters)
+    hipLaunchKernelGGL(refine_stop_kernel, dim3(1), dim3(64), 0, st, p->stats);
+  else
+    hipLaunchKernelGGL(refine_residual_kernel, dim3(r.rg.blocks), dim3(REFINE_NT), 0, st,
+                       (const double*)rhs, (const double*)p->f64, p->e32, r.G, r.rg);
+  HIP_TRY(hipGetLastError());
+  return POISSON_OK;
+}
+
+// Sweep `sweep` after its FP32 solve: Phi += e and the convergence test.
+static int refine_sweep_end(poisson_plan* p, double* rhs, int sweep, hipStream_t st) {
+  const RefineLaunch r = refine_launch(p);
+  hipLaunchKernelGGL(refine_update_kernel, dim3(r.nb), dim3(REFINE_NT), 0, st, rhs,
+                     (const float*)p->e32, r.G);
+  hipLaunchKernelGGL(refine_status_kernel, dim3(1), dim3(REFINE_NT), 0, st, p->stats, r.nb, sweep,
+                     p->tol);
+  HIP_TRY(hipGetLastError());
+  return POISSON_OK;
+}
+
+// Gauge of a singular problem and the status copy for solve_status.
+static int refine_end(poisson_plan* p, double* rhs, hipStream_t st) {
+  const RefineLaunch r = refine_launch(p);
   if (p->singular) {
-    hipLaunchKernelGGL(refine_wsum_kernel, grid, block, 0, st, (const double*)rhs, G);
-    hipLaunchKernelGGL(refine_mean_kernel, dim3(1), block, 0, st, p->stats, nb);
-    hipLaunchKernelGGL(refine_shift_kernel, grid, block, 0, st, rhs, (const double*)p->stats, N);
+    hipLaunchKernelGGL(refine_wsum_kernel, dim3(r.nb), dim3(REFINE_NT), 0, st, (const double*)rhs, r.G);
+    hipLaunchKernelGGL(refine_mean_kernel, dim3(1), dim3(REFINE_NT), 0, st, p->stats, r.nb);
+    hipLaunchKernelGGL(refine_shift_kernel, dim3(r.nb), dim3(REFINE_NT), 0, st, rhs,
+                       (const double*)p->stats, r.N);
   }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(p->stats_host, p->stats, REFINE_PARTIALS * sizeof(double),
                          hipMemcpyDeviceToHost, st));
   return POISSON_OK;
+}
+
+static int solve_refined(poisson_plan* p, double* rhs, hipStream_t st) {
+  int rc;
+  if ((rc = refine_begin(p, rhs, st))) return rc;
+  // the first FP32 solve's last pass writes Phi (widened) into rhs
+  if ((rc = solve_typed<float>(p, p->e32, st, nullptr, rhs))) return rc;
+  for (int sweep = 1; sweep < p->max_iters; ++sweep) {
+    if ((rc = refine_sweep_begin(p, rhs, sweep, st))) return rc;
+    if ((rc = solve_typed<float>(p, p->e32, st, p->stats))) return rc;
+    if ((rc = refine_sweep_end(p, rhs, sweep, st))) return rc;
+  }
+  return refine_end(p, rhs, st);
 }
 
 // ------------------------------------------------------------------ batch
@@ -1000,13 +1051,16 @@ extern "C" int batch_solve(poisson_plan* const* plans, double* const* rhs, int c
   if (count < 0 || (count > 0 && (!plans || !rhs))) return fail(POISSON_EINVAL, "bad batch arguments");
   for (int i = 0; i < count; ++i) {
     if (!plans[i] || !rhs[i]) return fail(POISSON_EINVAL, "null plan or field at batch index %d", i);
-    if (plans[i]->mode != POISSON_FP64) return fail(POISSON_EINVAL, "batch_solve takes FP64 plans (index %d)", i);
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i] && plans[i]->mode == POISSON_FP32_REFINED)
+        return fail(POISSON_EINVAL, "refined plan at batch index %d appears twice", i);
   }
   bool specialised = true;
   for (int i = 0; i < count && specialised; ++i) {
     const poisson_plan* p = plans[i];
     specialised = r2r_fast_length(p->ax[0]) && r2r_fast_length(p->ax[1]) &&
-                  tri_fast_length(p->dims[p->s]) && !p->generic_r2r && !p->generic_tri;
+                  tri_fast_length(p->dims[p->s]) && !p->generic_r2r && !p->generic_tri &&
+                  p->mode == plans[0]->mode;
   }
   if (count > 0 && specialised) {
     poisson_batch* b = batch_create(plans, count);
@@ -1020,7 +1074,7 @@ extern "C" int batch_solve(poisson_plan* const* plans, double* const* rhs, int c
     return POISSON_OK;
   }
   for (int i = 0; i < count; ++i) {
-    const int rc = solve_typed<double>(plans[i], rhs[i], st);
+    const int rc = solve(plans[i], rhs[i], st);
     if (rc) return rc;
   }
   return POISSON_OK;
@@ -1032,15 +1086,22 @@ extern "C" int batch_solve(poisson_plan* const* plans, double* const* rhs, int c
 // backward t2, backward t1, as (transform role or -1, inverse).
 static const int kStepRole[5] = {0, 1, -1, 1, 0};
 static const int kStepInverse[5] = {0, 0, 0, 1, 1};
+static constexpr int kMaxSteps = 10;
 
+// A batch of FP64 plans has the five steps of a solve.  A batch of
+// FP32 + refinement plans has ten: the steps of the first FP32 solve (its
+// last one writes the widened solution into the caller's field) and those
+// of the later sweeps' solves (each job skips once its plan has converged).
 struct poisson_batch {
   int device = 0;
+  bool fp32 = false;                  // FP32 + refinement plans
+  int nsteps = 5;
   std::vector<poisson_plan*> plans;
-  std::vector<int> order[5];          // instances in job order, per step
-  int njobs[5] = {0, 0, 0, 0, 0};
-  int items[5] = {0, 0, 0, 0, 0};
-  size_t lds[5] = {0, 0, 0, 0, 0};
-  size_t off[5] = {0, 0, 0, 0, 0};    // byte offset of each step's job array
+  std::vector<int> order[5];          // instances in job order, per pipeline step
+  int njobs[kMaxSteps] = {};
+  int items[kMaxSteps] = {};
+  size_t lds[kMaxSteps] = {};
+  size_t off[kMaxSteps] = {};         // byte offset of each step's job array
   size_t bytes = 0;
   char* djobs = nullptr;              // device job arrays (all steps)
   int force[5] = {-1, -1, -1, -1, -1};  // variant of every job of a step (-1: per-length table)
@@ -1051,51 +1112,62 @@ struct poisson_batch {
   hipGraphExec_t exec = nullptr;
 };
 
+// Job tables of one step in element type T.
+template <typename T>
+static void batch_step_jobs(poisson_batch* b, int k, double* const* rhs, std::vector<char>& host) {
+  const int ps = k % 5;                       // pipeline step
+  const bool sweep = k >= 5;                  // later sweeps of a refined batch
+  int first = 0;
+  size_t lds = 0;
+  for (size_t j = 0; j < b->order[ps].size(); ++j) {
+    const int i = b->order[ps][j];
+    poisson_plan* p = b->plans[i];
+    T* data = b->fp32 ? reinterpret_cast<T*>(p->e32) : reinterpret_cast<T*>(rhs ? rhs[i] : nullptr);
+    const double* skip = sweep ? p->stats : nullptr;
+    double* out64 = b->fp32 && !sweep && ps == 4 && rhs ? rhs[i] : nullptr;
+    if (kStepRole[ps] >= 0) {
+      const AxisTables& A = p->ax[kStepRole[ps]];
+      BatchR2RJob<T> J{};
+      J.M = A.m;
+      J.V = b->force[ps] >= 0 ? b->force[ps] : tuned_choice(0, sizeof(T), A.m, A.axis == 0);
+      if (J.V >= 4) J.V = 0;   // the batched kernel has the synchronous variants
+      with_fast_cfg(J.M, J.V, [&](auto cfg) {
+        using C = decltype(cfg);
+        J.a = fast_args<T, C>(p, A, kStepInverse[ps], data, skip, out64);
+        lds = std::max(lds, fast_lds_bytes<T, C>());
+        return 0LL;
+      });
+      J.first = first;
+      first += J.a.g.ntiles;
+      std::memcpy(host.data() + b->off[k] + j * sizeof(J), &J, sizeof(J));
+    } else {
+      const int n = p->dims[p->s];
+      BatchTriJob<T> J{};
+      const int tv = b->force[ps] >= 0 ? b->force[ps] : tuned_choice(1, sizeof(T), n, p->s == 0);
+      J.key = 2 * n + (tv < 2 ? tv : 0);   // the batched kernel has the synchronous chunkings
+      with_tri_cfg(n, J.key & 1, [&](auto cfg) {
+        using C = decltype(cfg);
+        J.a = tri_fast_args<T, C::RPC, C::P>(p, data, skip);
+        lds = std::max(lds, tri_fast_lds_bytes<T, C::RPC, C::P>());
+        return 0LL;
+      });
+      J.first = first;
+      first += J.a.g.ntiles;
+      std::memcpy(host.data() + b->off[k] + j * sizeof(J), &J, sizeof(J));
+    }
+  }
+  b->items[k] = first;
+  b->lds[k] = lds;
+}
+
 // Job tables of every step for the given fields (null fields: sizes only),
 // with the variants chosen now (the batch's own choice for a step if it has
 // one, else the per-length table); sets item counts and LDS sizes.
 static void batch_jobs(poisson_batch* b, double* const* rhs, std::vector<char>& host) {
   host.assign(b->bytes, 0);
-  for (int k = 0; k < 5; ++k) {
-    int first = 0;
-    size_t lds = 0;
-    for (size_t j = 0; j < b->order[k].size(); ++j) {
-      const int i = b->order[k][j];
-      const poisson_plan* p = b->plans[i];
-      double* data = rhs ? rhs[i] : nullptr;
-      if (kStepRole[k] >= 0) {
-        const AxisTables& A = p->ax[kStepRole[k]];
-        BatchR2RJob<double> J{};
-        J.M = A.m;
-        J.V = b->force[k] >= 0 ? b->force[k] : tuned_choice(0, sizeof(double), A.m, A.axis == 0);
-        if (J.V >= 4) J.V = 0;   // the batched kernel has the synchronous variants
-        with_fast_cfg(J.M, J.V, [&](auto cfg) {
-          using C = decltype(cfg);
-          J.a = fast_args<double, C>(p, A, kStepInverse[k], data, nullptr);
-          lds = std::max(lds, fast_lds_bytes<double, C>());
-          return 0LL;
-        });
-        J.first = first;
-        first += J.a.g.ntiles;
-        std::memcpy(host.data() + b->off[k] + j * sizeof(J), &J, sizeof(J));
-      } else {
-        const int n = p->dims[p->s];
-        BatchTriJob<double> J{};
-        const int tv = b->force[k] >= 0 ? b->force[k] : tuned_choice(1, sizeof(double), n, p->s == 0);
-        J.key = 2 * n + (tv < 2 ? tv : 0);   // the batched kernel has the synchronous chunkings
-        with_tri_cfg(n, J.key & 1, [&](auto cfg) {
-          using C = decltype(cfg);
-          J.a = tri_fast_args<double, C::RPC, C::P>(p, data, nullptr);
-          lds = std::max(lds, tri_fast_lds_bytes<double, C::RPC, C::P>());
-          return 0LL;
-        });
-        J.first = first;
-        first += J.a.g.ntiles;
-        std::memcpy(host.data() + b->off[k] + j * sizeof(J), &J, sizeof(J));
-      }
-    }
-    b->items[k] = first;
-    b->lds[k] = lds;
+  for (int k = 0; k < b->nsteps; ++k) {
+    if (b->fp32) batch_step_jobs<float>(b, k, rhs, host);
+    else batch_step_jobs<double>(b, k, rhs, host);
   }
 }
 
@@ -1108,7 +1180,14 @@ extern "C" poisson_batch* batch_create(poisson_plan* const* plans, int count) {
     const poisson_plan* p = plans[i];
     if (!p) { fail(POISSON_EINVAL, "null plan at batch index %d", i); return nullptr; }
     if (p->device != dev) { fail(POISSON_EINVAL, "plan %d lives on another device", i); return nullptr; }
-    if (p->mode != POISSON_FP64) { fail(POISSON_EUNSUPPORTED, "batched launches take FP64 plans (index %d)", i); return nullptr; }
+    if (p->mode != plans[0]->mode) {
+      fail(POISSON_EUNSUPPORTED, "a batch takes plans of one precision mode (index %d differs)", i);
+      return nullptr;
+    }
+    if (p->mode == POISSON_FP32_REFINED && (!p->f64 || !p->e32)) {
+      fail(POISSON_EINVAL, "refined plan %d has no workspace", i);
+      return nullptr;
+    }
     for (int r = 0; r < 2; ++r)
       if (!r2r_fast_length(p->ax[r])) {
         fail(POISSON_EUNSUPPORTED, "plan %d: transform length %d has no size-specialised kernel", i, p->ax[r].n);
@@ -1119,10 +1198,17 @@ extern "C" poisson_batch* batch_create(poisson_plan* const* plans, int count) {
       return nullptr;
     }
   }
+  for (int i = 0; i < count; ++i)
+    for (int j = 0; j < i; ++j)
+      if (plans[i] == plans[j] && plans[i]->mode == POISSON_FP32_REFINED) {
+        fail(POISSON_EINVAL, "refined plan %d appears twice (one workspace per plan)", i);
+        return nullptr;
+      }
   poisson_batch* b = new poisson_batch();
   b->device = dev;
+  b->fp32 = plans[0]->mode == POISSON_FP32_REFINED;
+  b->nsteps = b->fp32 ? 10 : 5;
   b->plans.assign(plans, plans + count);
-  size_t bytes = 0;
   for (int k = 0; k < 5; ++k) {
     std::vector<int>& ord = b->order[k];
     for (int i = 0; i < count; ++i) ord.push_back(i);
@@ -1137,10 +1223,16 @@ extern "C" poisson_batch* batch_create(poisson_plan* const* plans, int count) {
       return p->dims[p->s];
     };
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return key(x) < key(y); });
+  }
+  size_t bytes = 0;
+  for (int k = 0; k < b->nsteps; ++k) {
+    const bool r2r = kStepRole[k % 5] >= 0;
+    const size_t job = b->fp32 ? (r2r ? sizeof(BatchR2RJob<float>) : sizeof(BatchTriJob<float>))
+                               : (r2r ? sizeof(BatchR2RJob<double>) : sizeof(BatchTriJob<double>));
     b->njobs[k] = count;
     bytes = align_up(bytes, 64);
     b->off[k] = bytes;
-    bytes += (size_t)count * (kStepRole[k] >= 0 ? sizeof(BatchR2RJob<double>) : sizeof(BatchTriJob<double>));
+    bytes += (size_t)count * job;
   }
   b->bytes = bytes;
   std::vector<char> host;
@@ -1157,8 +1249,8 @@ extern "C" poisson_batch* batch_create(poisson_plan* const* plans, int count) {
 // captured launches carry the LDS size, grid and item count of each step:
 // when the variants changed them, capture again at the next launch.
 static int batch_upload(poisson_batch* b) {
-  size_t lds_before[5];
-  int items_before[5];
+  size_t lds_before[kMaxSteps];
+  int items_before[kMaxSteps];
   std::memcpy(lds_before, b->lds, sizeof(lds_before));
   std::memcpy(items_before, b->items, sizeof(items_before));
   std::vector<char> host;
@@ -1180,34 +1272,72 @@ extern "C" int batch_bind(poisson_batch* b, double* const* rhs) {
   for (size_t i = 0; i < b->plans.size(); ++i)
     if (!rhs[i]) return fail(POISSON_EINVAL, "null field at batch index %zu", i);
   b->rhs.assign(rhs, rhs + b->plans.size());
+  if (b->exec) {
+    // the refinement kernels around the batched steps take the fields as
+    // arguments: a captured sequence of a refined batch is for the old ones
+    if (b->fp32) {
+      (void)hipGraphExecDestroy(b->exec);
+      (void)hipGraphDestroy(b->graph);
+      b->exec = nullptr;
+      b->graph = nullptr;
+    }
+  }
   return batch_upload(b);
 }
 
-static int batch_enqueue_step(poisson_batch* b, int k, hipStream_t st) {
-  {
-    if (b->items[k] == 0) return POISSON_OK;
-    const size_t lds = b->lds[k];
-    if (kStepRole[k] >= 0) {
-      const auto* jobs = reinterpret_cast<const BatchR2RJob<double>*>(b->djobs + b->off[k]);
-      const void* fn = reinterpret_cast<const void*>(&batch_r2r_kernel<double>);
-      hipLaunchKernelGGL(batch_r2r_kernel<double>, dim3(resident_grid(fn, 512, lds, b->items[k])),
-                         dim3(512), lds, st, jobs, b->njobs[k], b->items[k]);
-    } else {
-      const auto* jobs = reinterpret_cast<const BatchTriJob<double>*>(b->djobs + b->off[k]);
-      const void* fn = reinterpret_cast<const void*>(&batch_tri_kernel<double>);
-      hipLaunchKernelGGL(batch_tri_kernel<double>, dim3(resident_grid(fn, 512, lds, b->items[k])),
-                         dim3(512), lds, st, jobs, b->njobs[k], b->items[k]);
-    }
-    HIP_TRY(hipGetLastError());
+// One persistent launch of step k (k >= 5: the sweep tables of a refined batch).
+template <typename T>
+static int batch_enqueue_typed(poisson_batch* b, int k, hipStream_t st) {
+  if (b->items[k] == 0) return POISSON_OK;
+  const size_t lds = b->lds[k];
+  if (kStepRole[k % 5] >= 0) {
+    const auto* jobs = reinterpret_cast<const BatchR2RJob<T>*>(b->djobs + b->off[k]);
+    const void* fn = reinterpret_cast<const void*>(&batch_r2r_kernel<T>);
+    hipLaunchKernelGGL(batch_r2r_kernel<T>, dim3(resident_grid(fn, 512, lds, b->items[k])),
+                       dim3(512), lds, st, jobs, b->njobs[k], b->items[k]);
+  } else {
+    const auto* jobs = reinterpret_cast<const BatchTriJob<T>*>(b->djobs + b->off[k]);
+    const void* fn = reinterpret_cast<const void*>(&batch_tri_kernel<T>);
+    hipLaunchKernelGGL(batch_tri_kernel<T>, dim3(resident_grid(fn, 512, lds, b->items[k])),
+                       dim3(512), lds, st, jobs, b->njobs[k], b->items[k]);
   }
+  HIP_TRY(hipGetLastError());
   return POISSON_OK;
 }
 
+static int batch_enqueue_step(poisson_batch* b, int k, hipStream_t st) {
+  return b->fp32 ? batch_enqueue_typed<float>(b, k, st) : batch_enqueue_typed<double>(b, k, st);
+}
+
+// The whole batched solve: the five steps (FP64), or the refined sequence:
+// per instance the refinement kernels (cheap, one field each), between them
+// the FP32 solves as batched steps over all instances.
 static int batch_enqueue(poisson_batch* b, hipStream_t st) {
-  for (int k = 0; k < 5; ++k) {
-    const int rc = batch_enqueue_step(b, k, st);
-    if (rc) return rc;
+  int rc;
+  if (!b->fp32) {
+    for (int k = 0; k < 5; ++k)
+      if ((rc = batch_enqueue_step(b, k, st))) return rc;
+    return POISSON_OK;
   }
+  const size_t n = b->plans.size();
+  int sweeps = 1;
+  for (const poisson_plan* p : b->plans) sweeps = std::max(sweeps, p->max_iters);
+  for (size_t i = 0; i < n; ++i)
+    if ((rc = refine_begin(b->plans[i], b->rhs[i], st))) return rc;
+  for (int k = 0; k < 5; ++k)
+    if ((rc = batch_enqueue_step(b, k, st))) return rc;
+  for (int sweep = 1; sweep < sweeps; ++sweep) {
+    for (size_t i = 0; i < n; ++i)
+      if ((rc = refine_sweep_begin(b->plans[i], b->rhs[i], sweep, st))) return rc;
+    for (int k = 5; k < 10; ++k)
+      if ((rc = batch_enqueue_step(b, k, st))) return rc;
+    for (size_t i = 0; i < n; ++i)
+      if (sweep < b->plans[i]->max_iters &&
+          (rc = refine_sweep_end(b->plans[i], b->rhs[i], sweep, st)))
+        return rc;
+  }
+  for (size_t i = 0; i < n; ++i)
+    if ((rc = refine_end(b->plans[i], b->rhs[i], st))) return rc;
   return POISSON_OK;
 }
 
@@ -1216,8 +1346,9 @@ extern "C" int batch_launch(poisson_batch* b, hipStream_t st, int use_graph) {
   if (!b->bound) return fail(POISSON_EINVAL, "batch has no fields bound (batch_bind)");
   if (!use_graph) return batch_enqueue(b, st);
   if (!b->exec) {
-    // capture the five launches once on a private stream; the job tables
-    // live in device memory, so later batch_bind calls need no re-capture
+    // capture the launches once on a private stream; the job tables live in
+    // device memory, so later batch_bind calls of an FP64 batch need no
+    // re-capture
     if (!b->cap) HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     const int rc = batch_enqueue(b, b->cap);

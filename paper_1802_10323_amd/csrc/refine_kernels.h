@@ -138,6 +138,11 @@ __global__ __launch_bounds__(REFINE_NT) void refine_prep_kernel(const double* __
   }
 }
 
+// stop the remaining sweeps (iteration limit): skip flag only
+__global__ void refine_stop_kernel(double* stats) {
+  if (threadIdx.x == 0) stats[0] = 1.0;
+}
+
 // x -= stats[1]
 __global__ __launch_bounds__(REFINE_NT) void refine_shift_kernel(double* __restrict__ x,
                                                                   const double* stats,

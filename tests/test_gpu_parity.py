@@ -656,6 +656,67 @@ def test_autotune_records_fastest(default_variants):
     plan.close()
 
 
+def test_refined_batch_equals_single_refined_solves(default_variants):
+    """A batch of FP32 + refinement plans (uneven sizes, random boundary
+    pairs, stretched and uniform z): each FP32 solve of the refinement is one
+    batched launch per stage, the FP64 refinement kernels run per instance in
+    between.  Bitwise equal to refined single solves with the same kernel
+    variants, with the same refinement status; within 1e-10 of the oracle;
+    also as graph replays with new fields bound between them; a plan with a
+    lower iteration limit stops there (not converged) while the others go on."""
+    import torch
+    from paper_1802_10323_amd import FP32_REFINED, Batch, Plan
+    probs = inputs.batch(13, count=5, sizes=(64, 96, 128))
+    plans = [Plan.from_problem(p) for p in probs]
+    for k, pl in enumerate(plans):
+        if k == 2:
+            pl.set_precision(FP32_REFINED, 1e-30, 2)    # stops after 2 FP32 solves
+        else:
+            pl.set_precision(FP32_REFINED, 1e-10, 6)
+    _synchronous_variants()
+    singles, stats = [], []
+    for p, pl in zip(probs, plans):
+        f = to_dev(p.rhs)
+        pl.solve(f)
+        torch.cuda.synchronize()
+        singles.append(to_host(f))
+        stats.append(pl.status())
+    say("refined singles", [(p.shape, p.bcs, s) for p, s in zip(probs, stats)])
+    assert stats[2][0] == 2 and not stats[2][2]
+    b = Batch(plans)
+    src = [to_dev(p.rhs) for p in probs]
+    fields = [s.clone() for s in src]
+    b.bind(fields)
+    for graph in (False, True, True, True):   # eager, capture, two replays
+        for f, s in zip(fields, src):
+            f.copy_(s)
+        torch.cuda.synchronize()
+        b.launch(graph=graph)
+        torch.cuda.synchronize()
+        for k, (p, pl, f) in enumerate(zip(probs, plans, fields)):
+            got = to_host(f)
+            assert np.array_equal(got, singles[k]), (graph, k, p.shape, p.bcs)
+            assert pl.status() == stats[k], (graph, k)
+            if k != 2 and p.points <= 300_000:
+                assert rel_l2(got, oracle_solve(p)) <= 1e-10, (k, p.shape)
+    b.close()
+    for pl in plans:
+        pl.close()
+
+
+def test_batch_rejects_mixed_precision_and_repeated_refined_plans():
+    from paper_1802_10323_amd import FP32_REFINED, Batch, Plan, PoissonError
+    probs = inputs.batch(14, count=2, sizes=(64,))
+    a, c = Plan.from_problem(probs[0]), Plan.from_problem(probs[1])
+    c.set_precision(FP32_REFINED, 1e-10, 4)
+    with pytest.raises(PoissonError):
+        Batch([a, c])
+    with pytest.raises(PoissonError):
+        Batch([c, c])
+    a.close()
+    c.close()
+
+
 def test_batch_autotune_whole_batch():
     """batch_autotune times each step with the per-length choices and with
     every synchronous variant for all jobs, and keeps the fastest; a graph
