@@ -146,7 +146,25 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
         f"autotuned ({tune_s:.1f} s): one by one {ms['single_tuned']:.3f} ms, graph with per-length "
         f"variants {ms['graph_table']:.3f} ms, graph tuned as a batch {ms['graph_tuned']:.3f} ms; "
         f"max relative difference to single solves {diff:.1e}")
+    fp64_ref = results["single_tuned"]
     B.close()
+    # the same instances in FP32 + refinement to 1e-10: one refined solve at
+    # a time against the refined batch (each FP32 solve batched) as a graph
+    from . import FP32_REFINED
+    for pl in plans:
+        pl.set_precision(FP32_REFINED, 1e-10, 6)
+    B32 = Batch(plans)
+    B32.bind(work)
+    measure("single_fp32", singles)
+    measure("graph_fp32", lambda: B32.launch(graph=True))
+    diff32 = max_rel("graph_fp32", "single_fp32")
+    err32 = max(float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+                for a, b in zip(results["graph_fp32"], fp64_ref))
+    solves = [pl.status()[0] for pl in plans]
+    log(f"[forms] batch FP32 + refinement: one by one {ms['single_fp32']:.3f} ms, graph "
+        f"{ms['graph_fp32']:.3f} ms ({min(solves)}-{max(solves)} FP32 solves per instance); "
+        f"max relative difference to refined single solves {diff32:.1e}, to FP64 {err32:.1e}")
+    B32.close()
     for pl in plans:
         pl.close()
     return {"workload": f"{count} instances, per-axis n from {{64,96,128,192,256}}, random BC pairs",
@@ -162,7 +180,14 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
             "speedup_tuned_vs_single_tuned": round(ms["single_tuned"] / ms["graph_tuned"], 4),
             "tuned_variants": chosen,
             "batch_step_choice": batch_choice,
-            "max_rel_diff_vs_single": diff}
+            "max_rel_diff_vs_single": diff,
+            "fp32_refined": {"single_ms": round(ms["single_fp32"], 4),
+                             "graph_ms": round(ms["graph_fp32"], 4),
+                             "graph_points_per_s": points / (ms["graph_fp32"] * 1e-3),
+                             "speedup_vs_single": round(ms["single_fp32"] / ms["graph_fp32"], 4),
+                             "fp32_solves": [min(solves), max(solves)],
+                             "max_rel_diff_vs_single": diff32,
+                             "max_rel_l2_vs_fp64": err32, "tolerance": 1e-10}}
 
 
 def serve(log, count=400, warmup=50, seed=0, slots=8, load=0.8, sample=12):
