@@ -215,15 +215,20 @@ static long long with_tri_cfg(int n, int V, F&& f) {
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int, int, int>, int> g_tune;
 
-// Variant used where nothing was tuned: the asynchronous-staging transform
-// for the lengths it is compiled for, else variant 0.  Its tile shape:
+// Variant used where nothing was tuned.  Transforms: the asynchronous-staging
+// form for the lengths it is compiled for, else variant 0.  Its tile shape:
 // shape 1 (half the lines per tile, so that twice the blocks fit in a CU's
 // LDS) for FP64 length 256 and for FP32 length 512 on the contiguous axis,
 // where the extra overlap pays most; shape 2 (32 lines) for FP32 length 512
 // on the strided axes, whose tile rows are then 128 bytes long; else shape
 // 0, whose wider tile rows use each DRAM page better.
 static int default_choice(int family, int bytes, int n, int layout) {
-  if (family != 0 || (n != 128 && n != 256)) return 0;
+  if (family == 1) {
+    // elimination: the second chunking (shorter interface reduction) wins on
+    // strided lines of 384 points, and of 256 points in FP32
+    return layout == 0 && (n == 384 || (bytes == 4 && n == 256)) ? 1 : 0;
+  }
+  if (n != 128 && n != 256) return 0;
   int shape = 0;
   if (bytes == 8 && n == 128) shape = 1;
   if (bytes == 4 && n == 256) shape = layout == 1 ? 1 : 2;
