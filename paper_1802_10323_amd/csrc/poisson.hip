@@ -966,7 +966,8 @@ static RefineGeom refine_geom(const poisson_plan* p) {
 //   f~ = f (minus its weighted mean if singular), Phi = solve32(f~);
 //   repeat: r = f~ - A Phi (FP64), e = solve32(r), Phi += e (FP64);
 //   finally, if singular, remove the weighted mean of Phi (FP64).
-// Pieces of the refined solve, shared with the batched form.
+// Pieces of the refined solve (the batched form runs the same kernel bodies
+// for all its instances at once, refine_kernels.h).
 struct RefineLaunch {
   long long N;
   RefineGeom G;
@@ -997,16 +998,11 @@ static int refine_begin(poisson_plan* p, double* rhs, hipStream_t st) {
   return POISSON_OK;
 }
 
-// Sweep `sweep` before its FP32 solve: the FP64 residual into e32; a plan
-// whose iteration limit is reached is stopped instead (later kernels of the
-// fixed sequence return at once, the converged flag is left as it is).
-static int refine_sweep_begin(poisson_plan* p, double* rhs, int sweep, hipStream_t st) {
+// Sweep `sweep` before its FP32 solve: the FP64 residual into e32.
+static int refine_sweep_begin(poisson_plan* p, double* rhs, hipStream_t st) {
   const RefineLaunch r = refine_launch(p);
-  if (sweep >= p->max_iters)
-    hipLaunchKernelGGL(refine_stop_kernel, dim3(1), dim3(64), 0, st, p->stats);
-  else
-    hipLaunchKernelGGL(refine_residual_kernel, dim3(r.rg.blocks), dim3(REFINE_NT), 0, st,
-                       (const double*)rhs, (const double*)p->f64, p->e32, r.G, r.rg);
+  hipLaunchKernelGGL(refine_residual_kernel, dim3(r.rg.blocks), dim3(REFINE_NT), 0, st,
+                     (const double*)rhs, (const double*)p->f64, p->e32, r.G, r.rg);
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
 }
@@ -1043,7 +1039,7 @@ static int solve_refined(poisson_plan* p, double* rhs, hipStream_t st) {
   // the first FP32 solve's last pass writes Phi (widened) into rhs
   if ((rc = solve_typed<float>(p, p->e32, st, nullptr, rhs))) return rc;
   for (int sweep = 1; sweep < p->max_iters; ++sweep) {
-    if ((rc = refine_sweep_begin(p, rhs, sweep, st))) return rc;
+    if ((rc = refine_sweep_begin(p, rhs, st))) return rc;
     if ((rc = solve_typed<float>(p, p->e32, st, p->stats))) return rc;
     if ((rc = refine_sweep_end(p, rhs, sweep, st))) return rc;
   }
@@ -1111,6 +1107,9 @@ struct poisson_batch {
   char* djobs = nullptr;              // device job arrays (all steps)
   int force[5] = {-1, -1, -1, -1, -1};  // variant of every job of a step (-1: per-length table)
   std::vector<double*> rhs;           // bound fields
+  RefineJob* drefine = nullptr;       // refined batch: per-instance refinement jobs (device)
+  int refine_eblocks = 0;             // blocks of its element-wise launches
+  int refine_rblocks = 0;             // blocks of its residual launch
   bool bound = false;
   hipStream_t cap = nullptr;          // private stream for graph capture
   hipGraph_t graph = nullptr;
@@ -1242,8 +1241,10 @@ extern "C" poisson_batch* batch_create(poisson_plan* const* plans, int count) {
   b->bytes = bytes;
   std::vector<char> host;
   batch_jobs(b, nullptr, host);       // item counts
-  if (hipMalloc(&b->djobs, b->bytes) != hipSuccess) {
-    fail(POISSON_ENOMEM, "batch job tables: hipMalloc of %zu B failed", b->bytes);
+  if (hipMalloc(&b->djobs, b->bytes) != hipSuccess ||
+      (b->fp32 && hipMalloc(&b->drefine, count * sizeof(RefineJob)) != hipSuccess)) {
+    fail(POISSON_ENOMEM, "batch job tables: hipMalloc failed");
+    if (b->djobs) (void)hipFree(b->djobs);
     delete b;
     return nullptr;
   }
@@ -1268,6 +1269,34 @@ static int batch_upload(poisson_batch* b) {
     b->graph = nullptr;
   }
   HIP_TRY(hipMemcpy(b->djobs, host.data(), b->bytes, hipMemcpyHostToDevice));
+  if (b->fp32) {
+    // refinement jobs: each instance's kernels on its own block range, with
+    // the block counts of its single-plan launches (same reductions)
+    std::vector<RefineJob> jobs(b->plans.size());
+    int fe = 0, fr = 0;
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+      const poisson_plan* p = b->plans[i];
+      const RefineLaunch r = refine_launch(p);
+      RefineJob& J = jobs[i];
+      J.G = r.G;
+      J.phi = b->rhs[i];
+      J.f64 = p->f64;
+      J.e32 = p->e32;
+      J.singular = p->singular ? 1 : 0;
+      J.nb = r.nb;
+      J.rg = r.rg;
+      J.first_e = fe;
+      J.first_r = fr;
+      J.max_iters = p->max_iters;
+      J.tol = p->tol;
+      fe += r.nb;
+      fr += r.rg.blocks;    // a multiple of 8: every job starts XCD-aligned
+    }
+    b->refine_eblocks = fe;
+    b->refine_rblocks = fr;
+    HIP_TRY(hipMemcpy(b->drefine, jobs.data(), jobs.size() * sizeof(RefineJob),
+                      hipMemcpyHostToDevice));
+  }
   b->bound = true;
   return POISSON_OK;
 }
@@ -1324,25 +1353,44 @@ static int batch_enqueue(poisson_batch* b, hipStream_t st) {
       if ((rc = batch_enqueue_step(b, k, st))) return rc;
     return POISSON_OK;
   }
-  const size_t n = b->plans.size();
+  const int n = (int)b->plans.size();
   int sweeps = 1;
-  for (const poisson_plan* p : b->plans) sweeps = std::max(sweeps, p->max_iters);
-  for (size_t i = 0; i < n; ++i)
-    if ((rc = refine_begin(b->plans[i], b->rhs[i], st))) return rc;
+  bool singular = false;
+  for (const poisson_plan* p : b->plans) {
+    sweeps = std::max(sweeps, p->max_iters);
+    singular = singular || p->singular;
+  }
+  const RefineJob* jobs = b->drefine;
+  const dim3 blk(REFINE_NT);
+  // the refinement kernels of all instances, one launch per kind (each
+  // instance on its own block range, as in its single-plan launch)
+  hipLaunchKernelGGL(refine_batch_init, dim3(n), dim3(256), 0, st, jobs);
+  if (singular) {
+    hipLaunchKernelGGL(refine_batch_wsum, dim3(b->refine_eblocks), blk, 0, st, jobs, n);
+    hipLaunchKernelGGL(refine_batch_mean, dim3(n), blk, 0, st, jobs);
+  }
+  hipLaunchKernelGGL(refine_batch_prep, dim3(b->refine_eblocks), blk, 0, st, jobs, n);
+  HIP_TRY(hipGetLastError());
   for (int k = 0; k < 5; ++k)
     if ((rc = batch_enqueue_step(b, k, st))) return rc;
   for (int sweep = 1; sweep < sweeps; ++sweep) {
-    for (size_t i = 0; i < n; ++i)
-      if ((rc = refine_sweep_begin(b->plans[i], b->rhs[i], sweep, st))) return rc;
+    hipLaunchKernelGGL(refine_batch_residual, dim3(b->refine_rblocks), blk, 0, st, jobs, n, sweep);
+    HIP_TRY(hipGetLastError());
     for (int k = 5; k < 10; ++k)
       if ((rc = batch_enqueue_step(b, k, st))) return rc;
-    for (size_t i = 0; i < n; ++i)
-      if (sweep < b->plans[i]->max_iters &&
-          (rc = refine_sweep_end(b->plans[i], b->rhs[i], sweep, st)))
-        return rc;
+    hipLaunchKernelGGL(refine_batch_update, dim3(b->refine_eblocks), blk, 0, st, jobs, n);
+    hipLaunchKernelGGL(refine_batch_status, dim3(n), blk, 0, st, jobs, sweep);
+    HIP_TRY(hipGetLastError());
   }
-  for (size_t i = 0; i < n; ++i)
-    if ((rc = refine_end(b->plans[i], b->rhs[i], st))) return rc;
+  if (singular) {
+    hipLaunchKernelGGL(refine_batch_wsum, dim3(b->refine_eblocks), blk, 0, st, jobs, n);
+    hipLaunchKernelGGL(refine_batch_mean, dim3(n), blk, 0, st, jobs);
+    hipLaunchKernelGGL(refine_batch_shift, dim3(b->refine_eblocks), blk, 0, st, jobs, n);
+  }
+  HIP_TRY(hipGetLastError());
+  for (const poisson_plan* p : b->plans)
+    HIP_TRY(hipMemcpyAsync(p->stats_host, p->stats, REFINE_PARTIALS * sizeof(double),
+                           hipMemcpyDeviceToHost, st));
   return POISSON_OK;
 }
 
@@ -1374,6 +1422,7 @@ extern "C" void batch_destroy(poisson_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   if (b->djobs) (void)hipFree(b->djobs);
+  if (b->drefine) (void)hipFree(b->drefine);
   delete b;
 }
 

@@ -84,20 +84,23 @@ struct GridWalk {
   }
 };
 
+// Each kernel below is a device body over a block range, called by a
+// kernel for one plan (blockIdx / gridDim) and by a batched kernel that
+// runs the same body for every instance of a batch, each on its own block
+// range (same blocks, same reduction order: bitwise the same result).
+
 // reset the status block (a fill kernel rather than a memset, so the
 // sequence can be captured in a graph)
-__global__ void refine_init_kernel(double* stats) {
-  const int t = threadIdx.x;
-  for (int i = t; i < REFINE_PARTIALS; i += blockDim.x) stats[i] = i >= 4 ? -1.0 : 0.0;
+__device__ __forceinline__ void refine_init_body(double* stats) {
+  for (int i = threadIdx.x; i < REFINE_PARTIALS; i += blockDim.x) stats[i] = i >= 4 ? -1.0 : 0.0;
 }
 
 // partial sums of w*x (slot 0) and w (slot 1), w = hx_i hy_j hz_k
-__global__ __launch_bounds__(REFINE_NT) void refine_wsum_kernel(const double* __restrict__ x,
-                                                                 RefineGeom G) {
-  __shared__ double sh[2 * REFINE_NT];
+__device__ __forceinline__ void refine_wsum_body(const double* __restrict__ x, const RefineGeom& G,
+                                                 int block, int nblocks, double* sh) {
   double sx = 0.0, sw = 0.0;
-  const long long step = (long long)gridDim.x * REFINE_NT;
-  const long long first = blockIdx.x * (long long)REFINE_NT + threadIdx.x;
+  const long long step = (long long)nblocks * REFINE_NT;
+  const long long first = block * (long long)REFINE_NT + threadIdx.x;
   GridWalk at(first, step, G.ax[0].n, G.ax[1].n);
   for (long long idx = first; idx < G.npts; idx += step, at.advance()) {
     const double w = G.ax[0].h[at.i] * G.ax[1].h[at.j] * G.ax[2].h[at.k];
@@ -106,14 +109,13 @@ __global__ __launch_bounds__(REFINE_NT) void refine_wsum_kernel(const double* __
   }
   block_sum2<REFINE_NT>(sx, sw, sh);
   if (threadIdx.x == 0) {
-    G.stats[REFINE_PARTIALS + 2 * blockIdx.x] = sx;
-    G.stats[REFINE_PARTIALS + 2 * blockIdx.x + 1] = sw;
+    G.stats[REFINE_PARTIALS + 2 * block] = sx;
+    G.stats[REFINE_PARTIALS + 2 * block + 1] = sw;
   }
 }
 
 // stats[1] = (sum of slot 0) / (sum of slot 1)   (weighted mean)
-__global__ __launch_bounds__(REFINE_NT) void refine_mean_kernel(double* stats, int nblocks) {
-  __shared__ double sh[2 * REFINE_NT];
+__device__ __forceinline__ void refine_mean_body(double* stats, int nblocks, double* sh) {
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < nblocks; i += REFINE_NT) {
     a += stats[REFINE_PARTIALS + 2 * i];
@@ -124,33 +126,75 @@ __global__ __launch_bounds__(REFINE_NT) void refine_mean_kernel(double* stats, i
 }
 
 // f64 = rhs - mean (mean = stats[1] if `project`), e32 = (float) f64
-__global__ __launch_bounds__(REFINE_NT) void refine_prep_kernel(const double* __restrict__ rhs,
-                                                                 double* __restrict__ f64,
-                                                                 float* __restrict__ e32,
-                                                                 const double* stats, int project,
-                                                                 long long npts) {
+__device__ __forceinline__ void refine_prep_body(const double* __restrict__ rhs,
+                                                 double* __restrict__ f64, float* __restrict__ e32,
+                                                 const double* stats, int project, long long npts,
+                                                 int block, int nblocks) {
   const double mean = project ? stats[1] : 0.0;
-  for (long long idx = blockIdx.x * (long long)REFINE_NT + threadIdx.x; idx < npts;
-       idx += (long long)gridDim.x * REFINE_NT) {
+  for (long long idx = block * (long long)REFINE_NT + threadIdx.x; idx < npts;
+       idx += (long long)nblocks * REFINE_NT) {
     const double f = rhs[idx] - mean;
     f64[idx] = f;
     e32[idx] = (float)f;
   }
 }
 
-// stop the remaining sweeps (iteration limit): skip flag only
-__global__ void refine_stop_kernel(double* stats) {
-  if (threadIdx.x == 0) stats[0] = 1.0;
+// x -= stats[1]
+__device__ __forceinline__ void refine_shift_body(double* __restrict__ x, const double* stats,
+                                                  long long npts, int block, int nblocks) {
+  const double mean = stats[1];
+  for (long long idx = block * (long long)REFINE_NT + threadIdx.x; idx < npts;
+       idx += (long long)nblocks * REFINE_NT)
+    x[idx] -= mean;
 }
 
-// x -= stats[1]
-__global__ __launch_bounds__(REFINE_NT) void refine_shift_kernel(double* __restrict__ x,
-                                                                  const double* stats,
-                                                                  long long npts) {
-  const double mean = stats[1];
-  for (long long idx = blockIdx.x * (long long)REFINE_NT + threadIdx.x; idx < npts;
-       idx += (long long)gridDim.x * REFINE_NT)
-    x[idx] -= mean;
+// phi += e; per-block partial ||e||^2 and ||phi||^2
+__device__ __forceinline__ void refine_update_body(double* __restrict__ phi,
+                                                   const float* __restrict__ e32,
+                                                   const RefineGeom& G, int block, int nblocks,
+                                                   double* sh) {
+  if (refine_skip(G.stats)) return;
+  double se = 0.0, sp = 0.0;
+  for (long long idx = block * (long long)REFINE_NT + threadIdx.x; idx < G.npts;
+       idx += (long long)nblocks * REFINE_NT) {
+    const double e = (double)e32[idx];
+    const double x = phi[idx] + e;
+    phi[idx] = x;
+    se += e * e;
+    sp += x * x;
+  }
+  block_sum2<REFINE_NT>(se, sp, sh);
+  if (threadIdx.x == 0) {
+    G.stats[REFINE_PARTIALS + 2 * block] = se;
+    G.stats[REFINE_PARTIALS + 2 * block + 1] = sp;
+  }
+}
+
+// Record sweep `sweep`: rel = ||e|| / ||phi||; the error left after the
+// update is estimated from the contraction rho = rel / rel_prev as
+// rel * rho / (1 - rho); once that is <= tol the remaining sweeps are skipped.
+__device__ __forceinline__ void refine_status_body(double* stats, int nblocks, int sweep,
+                                                   double tol, double* sh) {
+  if (refine_skip(stats)) return;
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += REFINE_NT) {
+    a += stats[REFINE_PARTIALS + 2 * i];
+    b += stats[REFINE_PARTIALS + 2 * i + 1];
+  }
+  block_sum2<REFINE_NT>(a, b, sh);
+  if (threadIdx.x == 0) {
+    stats[4 + 2 * sweep] = a;
+    stats[5 + 2 * sweep] = b;
+    const double rel = b > 0.0 ? sqrt(a / b) : 0.0;
+    const double prev = stats[3] > 0.0 ? stats[3] : 1.0;
+    const double rho = rel / prev;
+    const double est = rho < 1.0 ? rel * rho / (1.0 - rho) : rel;
+    stats[3] = rel;
+    if (est <= tol) {
+      stats[2] = 1.0;
+      stats[0] = 1.0;
+    }
+  }
 }
 
 // Launch shape of refine_residual_kernel: blocks of REFINE_NT points of an
@@ -178,12 +222,12 @@ inline ResidualGrid residual_grid(int nx, int ny, int nz) {
 // blocks round-robin: block b works on chunk (b mod 8) * (blocks / 8) +
 // b / 8, so each XCD sweeps a contiguous run of rows, whose y neighbours its
 // own L2 holds.
-__global__ __launch_bounds__(REFINE_NT) void refine_residual_kernel(const double* __restrict__ phi,
-                                                                     const double* __restrict__ f64,
-                                                                     float* __restrict__ e32,
-                                                                     RefineGeom G, ResidualGrid rg) {
+__device__ __forceinline__ void refine_residual_body(const double* __restrict__ phi,
+                                                     const double* __restrict__ f64,
+                                                     float* __restrict__ e32, const RefineGeom& G,
+                                                     const ResidualGrid& rg, int block) {
   if (refine_skip(G.stats)) return;
-  const int chunk = (int)(blockIdx.x % 8) * (rg.blocks / 8) + (int)(blockIdx.x / 8);
+  const int chunk = (block % 8) * (rg.blocks / 8) + block / 8;
   if (chunk >= rg.plane_blocks * rg.z_chunks) return;
   const int nx = G.ax[0].n, ny = G.ax[1].n, nz = G.ax[2].n;
   const int p = (chunk % rg.plane_blocks) * REFINE_NT + (int)threadIdx.x;
@@ -215,54 +259,145 @@ __global__ __launch_bounds__(REFINE_NT) void refine_residual_kernel(const double
   }
 }
 
-// phi += e; per-block partial ||e||^2 and ||phi||^2
+// ---- kernels for one plan
+
+__global__ void refine_init_kernel(double* stats) { refine_init_body(stats); }
+
+__global__ __launch_bounds__(REFINE_NT) void refine_wsum_kernel(const double* __restrict__ x,
+                                                                 RefineGeom G) {
+  __shared__ double sh[2 * REFINE_NT];
+  refine_wsum_body(x, G, blockIdx.x, gridDim.x, sh);
+}
+
+__global__ __launch_bounds__(REFINE_NT) void refine_mean_kernel(double* stats, int nblocks) {
+  __shared__ double sh[2 * REFINE_NT];
+  refine_mean_body(stats, nblocks, sh);
+}
+
+__global__ __launch_bounds__(REFINE_NT) void refine_prep_kernel(const double* __restrict__ rhs,
+                                                                 double* __restrict__ f64,
+                                                                 float* __restrict__ e32,
+                                                                 const double* stats, int project,
+                                                                 long long npts) {
+  refine_prep_body(rhs, f64, e32, stats, project, npts, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(REFINE_NT) void refine_shift_kernel(double* __restrict__ x,
+                                                                  const double* stats,
+                                                                  long long npts) {
+  refine_shift_body(x, stats, npts, blockIdx.x, gridDim.x);
+}
+
+// e32 = (float)(f64 - A phi), FP64 arithmetic (see refine_residual_body)
+__global__ __launch_bounds__(REFINE_NT) void refine_residual_kernel(const double* __restrict__ phi,
+                                                                     const double* __restrict__ f64,
+                                                                     float* __restrict__ e32,
+                                                                     RefineGeom G, ResidualGrid rg) {
+  refine_residual_body(phi, f64, e32, G, rg, blockIdx.x);
+}
+
 __global__ __launch_bounds__(REFINE_NT) void refine_update_kernel(double* __restrict__ phi,
                                                                    const float* __restrict__ e32,
                                                                    RefineGeom G) {
-  if (refine_skip(G.stats)) return;
   __shared__ double sh[2 * REFINE_NT];
-  double se = 0.0, sp = 0.0;
-  for (long long idx = blockIdx.x * (long long)REFINE_NT + threadIdx.x; idx < G.npts;
-       idx += (long long)gridDim.x * REFINE_NT) {
-    const double e = (double)e32[idx];
-    const double x = phi[idx] + e;
-    phi[idx] = x;
-    se += e * e;
-    sp += x * x;
-  }
-  block_sum2<REFINE_NT>(se, sp, sh);
-  if (threadIdx.x == 0) {
-    G.stats[REFINE_PARTIALS + 2 * blockIdx.x] = se;
-    G.stats[REFINE_PARTIALS + 2 * blockIdx.x + 1] = sp;
-  }
+  refine_update_body(phi, e32, G, blockIdx.x, gridDim.x, sh);
 }
 
-// Record sweep `sweep`: rel = ||e|| / ||phi||; the error left after the
-// update is estimated from the contraction rho = rel / rel_prev as
-// rel * rho / (1 - rho); once that is <= tol the remaining sweeps are skipped.
 __global__ __launch_bounds__(REFINE_NT) void refine_status_kernel(double* stats, int nblocks,
                                                                    int sweep, double tol) {
-  if (refine_skip(stats)) return;
   __shared__ double sh[2 * REFINE_NT];
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nblocks; i += REFINE_NT) {
-    a += stats[REFINE_PARTIALS + 2 * i];
-    b += stats[REFINE_PARTIALS + 2 * i + 1];
+  refine_status_body(stats, nblocks, sweep, tol, sh);
+}
+
+// ---- kernels for a batch: job j owns blocks [first, first + count) of a
+// launch (element-wise kernels: nb blocks; residual: rg.blocks, a multiple
+// of 8 starting at a multiple of 8, so its XCD order is kept); reductions
+// and per-instance steps take one block per job.
+
+struct RefineJob {
+  RefineGeom G;
+  double* phi;          // the caller's field (Phi, and f on entry)
+  double* f64;
+  float* e32;
+  int singular;
+  int nb;               // blocks of the element-wise kernels
+  ResidualGrid rg;
+  int first_e;          // first block in the element-wise launches
+  int first_r;          // first block in the residual launch
+  int max_iters;
+  double tol;
+};
+
+// job of block `b` (jobs sorted by first block, the first one at 0)
+template <bool RESIDUAL>
+__device__ __forceinline__ int refine_job_of(const RefineJob* __restrict__ jobs, int njobs, int b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((RESIDUAL ? jobs[mid].first_r : jobs[mid].first_e) <= b) lo = mid;
+    else hi = mid - 1;
   }
-  block_sum2<REFINE_NT>(a, b, sh);
-  if (threadIdx.x == 0) {
-    stats[4 + 2 * sweep] = a;
-    stats[5 + 2 * sweep] = b;
-    const double rel = b > 0.0 ? sqrt(a / b) : 0.0;
-    const double prev = stats[3] > 0.0 ? stats[3] : 1.0;
-    const double rho = rel / prev;
-    const double est = rho < 1.0 ? rel * rho / (1.0 - rho) : rel;
-    stats[3] = rel;
-    if (est <= tol) {
-      stats[2] = 1.0;
-      stats[0] = 1.0;
-    }
+  return lo;
+}
+
+__global__ void refine_batch_init(const RefineJob* __restrict__ jobs) {
+  refine_init_body(jobs[blockIdx.x].G.stats);
+}
+
+// the projection of f and the gauge of Phi touch singular instances only
+__global__ __launch_bounds__(REFINE_NT) void refine_batch_wsum(const RefineJob* __restrict__ jobs,
+                                                                int njobs) {
+  __shared__ double sh[2 * REFINE_NT];
+  const RefineJob& J = jobs[refine_job_of<false>(jobs, njobs, blockIdx.x)];
+  if (!J.singular) return;
+  refine_wsum_body(J.phi, J.G, blockIdx.x - J.first_e, J.nb, sh);
+}
+
+__global__ __launch_bounds__(REFINE_NT) void refine_batch_mean(const RefineJob* __restrict__ jobs) {
+  __shared__ double sh[2 * REFINE_NT];
+  const RefineJob& J = jobs[blockIdx.x];
+  if (!J.singular) return;
+  refine_mean_body(J.G.stats, J.nb, sh);
+}
+
+__global__ __launch_bounds__(REFINE_NT) void refine_batch_prep(const RefineJob* __restrict__ jobs,
+                                                                int njobs) {
+  const RefineJob& J = jobs[refine_job_of<false>(jobs, njobs, blockIdx.x)];
+  refine_prep_body(J.phi, J.f64, J.e32, J.G.stats, J.singular, J.G.npts, blockIdx.x - J.first_e,
+                   J.nb);
+}
+
+// sweep `sweep`: the residual, or the stop of an instance at its limit
+__global__ __launch_bounds__(REFINE_NT) void refine_batch_residual(const RefineJob* __restrict__ jobs,
+                                                                    int njobs, int sweep) {
+  const RefineJob& J = jobs[refine_job_of<true>(jobs, njobs, blockIdx.x)];
+  const int block = blockIdx.x - J.first_r;
+  if (sweep >= J.max_iters) {
+    if (block == 0 && threadIdx.x == 0) J.G.stats[0] = 1.0;
+    return;
   }
+  refine_residual_body(J.phi, J.f64, J.e32, J.G, J.rg, block);
+}
+
+__global__ __launch_bounds__(REFINE_NT) void refine_batch_update(const RefineJob* __restrict__ jobs,
+                                                                  int njobs) {
+  __shared__ double sh[2 * REFINE_NT];
+  const RefineJob& J = jobs[refine_job_of<false>(jobs, njobs, blockIdx.x)];
+  refine_update_body(J.phi, J.e32, J.G, blockIdx.x - J.first_e, J.nb, sh);
+}
+
+__global__ __launch_bounds__(REFINE_NT) void refine_batch_status(const RefineJob* __restrict__ jobs,
+                                                                  int sweep) {
+  __shared__ double sh[2 * REFINE_NT];
+  const RefineJob& J = jobs[blockIdx.x];
+  refine_status_body(J.G.stats, J.nb, sweep, J.tol, sh);
+}
+
+__global__ __launch_bounds__(REFINE_NT) void refine_batch_shift(const RefineJob* __restrict__ jobs,
+                                                                 int njobs) {
+  const RefineJob& J = jobs[refine_job_of<false>(jobs, njobs, blockIdx.x)];
+  if (!J.singular) return;
+  refine_shift_body(J.phi, J.G.stats, J.G.npts, blockIdx.x - J.first_e, J.nb);
 }
 
 }  // namespace poisson_dev
