@@ -228,11 +228,13 @@ def batch_solve(plans, fields, stream=None):
 
 
 class Batch:
-    """Many independent FP64 problems solved by one persistent launch per
-    stage (``batch_create`` / ``batch_bind`` / ``batch_launch``).  The plans
-    must outlive the batch; ``bind`` sets the fields (device, float64,
-    contiguous; solved in place) and must not be called while a launch of
-    this batch is in flight."""
+    """Many independent problems solved by one persistent launch per stage
+    (``batch_create`` / ``batch_bind`` / ``batch_launch``): all FP64 plans,
+    or all FP32 + refinement plans (each FP32 solve batched, the refinement
+    kernels batched between them; ``Plan.status`` reports each plan's
+    refinement afterwards).  The plans must outlive the batch; ``bind`` sets
+    the fields (device, float64, contiguous; solved in place) and must not be
+    called while a launch of this batch is in flight."""
 
     def __init__(self, plans):
         L = lib()
