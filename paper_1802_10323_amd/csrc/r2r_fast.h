@@ -373,48 +373,54 @@ __device__ __forceinline__ void split_store_body(lptr<const T> lds, lptr<const c
   constexpr int SP = (NP + QT - 1) / QT;
   const int ln = layout == 0 ? l : tid / QT;
   const int qq = layout == 0 ? q : tid % QT;
-  const long long lb = layout == 0 ? base : base + (long long)ln * N;
-  const long long ps = layout == 0 ? sp : 1;
   if (layout == 0 ? base < 0 : ln >= lines) return;   // line outside the field
-  auto put = [&](int r, T v) { data[lb + r * ps] = v * scale; };
+  // the pairs of one thread, written through put(point, value)
+  auto pairs = [&](auto put) {
 #pragma unroll
-  for (int s = 0; s < SP; ++s) {
-    const int k = qq + s * QT;
-    if (k < NP) {
-      const int kc = (M - k) % M;
-      const int j = M - k;
-      const cplx<T> z = {lds[(2 * k) * NLP + ln], lds[(2 * k + 1) * NLP + ln]};
-      const cplx<T> zc = {lds[(2 * kc) * NLP + ln], -lds[(2 * kc + 1) * NLP + ln]};
-      const cplx<T> E = {(T)0.5 * (z.re + zc.re), (T)0.5 * (z.im + zc.im)};
-      const cplx<T> D = csub(z, zc);
-      const cplx<T> O = {(T)0.5 * D.im, (T)-0.5 * D.re};
-      const cplx<T> wO = cmul(ldc(split, k), O);
-      const cplx<T> X = cadd(E, wO);
-      const cplx<T> Y = cconj(csub(E, wO));
-      if (kind == K_P) {
-        if (k == 0) {
-          put(0, X.re);
-          put(N - 1, Y.re);
-        } else {
-          put(2 * k - 1, X.re);
-          put(2 * k, -X.im);
-          if (j != k) {
-            put(2 * j - 1, Y.re);
-            put(2 * j, -Y.im);
+    for (int s = 0; s < SP; ++s) {
+      const int k = qq + s * QT;
+      if (k < NP) {
+        const int kc = (M - k) % M;
+        const int j = M - k;
+        const cplx<T> z = {lds[(2 * k) * NLP + ln], lds[(2 * k + 1) * NLP + ln]};
+        const cplx<T> zc = {lds[(2 * kc) * NLP + ln], -lds[(2 * kc + 1) * NLP + ln]};
+        const cplx<T> E = {(T)0.5 * (z.re + zc.re), (T)0.5 * (z.im + zc.im)};
+        const cplx<T> D = csub(z, zc);
+        const cplx<T> O = {(T)0.5 * D.im, (T)-0.5 * D.re};
+        const cplx<T> wO = cmul(ldc(split, k), O);
+        const cplx<T> X = cadd(E, wO);
+        const cplx<T> Y = cconj(csub(E, wO));
+        if (kind == K_P) {
+          if (k == 0) {
+            put(0, X.re);
+            put(N - 1, Y.re);
+          } else {
+            put(2 * k - 1, X.re);
+            put(2 * k, -X.im);
+            if (j != k) {
+              put(2 * j - 1, Y.re);
+              put(2 * j, -Y.im);
+            }
           }
-        }
-      } else {
-        const bool rev = kind == K_DD;
-        const cplx<T> u = cmul(ldc(quarter, k), X);
-        put(rev ? N - 1 - k : k, (T)2 * u.re);
-        if (k > 0) put(rev ? k - 1 : N - k, (T)-2 * u.im);
-        if (j != k) {
-          const cplx<T> u2 = cmul(ldc(quarter, j), Y);
-          put(rev ? N - 1 - j : j, (T)2 * u2.re);
-          if (j != M) put(rev ? j - 1 : N - j, (T)-2 * u2.im);
+        } else {
+          const bool rev = kind == K_DD;
+          const cplx<T> u = cmul(ldc(quarter, k), X);
+          put(rev ? N - 1 - k : k, (T)2 * u.re);
+          if (k > 0) put(rev ? k - 1 : N - k, (T)-2 * u.im);
+          if (j != k) {
+            const cplx<T> u2 = cmul(ldc(quarter, j), Y);
+            put(rev ? N - 1 - j : j, (T)2 * u2.re);
+            if (j != M) put(rev ? j - 1 : N - j, (T)-2 * u2.im);
+          }
         }
       }
     }
+  };
+  if (layout == 0) {
+    pairs([&](int r, T v) { data[base + r * sp] = v * scale; });
+  } else {   // contiguous: the line's row pointer once, 32-bit offsets in it
+    const gptr<T> row = data + (base + (long long)ln * N);
+    pairs([&](int r, T v) { row[r] = v * scale; });
   }
 }
 
@@ -902,18 +908,23 @@ struct AsyncBudget {
   if (tr.first < tr.end) async_fetch<T, C>(stage_lds, A, tr.first, tid);                      \
   /* Stores of the previous tile issued after the staged reads, a lower */                     \
   /* bound per wave for a whole tile: the plain and DCT-IV stores write */                    \
-  /* every element (EPT); the forward split writes 4 points for every */                     \
-  /* pair k of 1 <= k < M/2, and each wave has such lanes in each of the */                   \
-  /* first M/(2 QT) steps (its line stride is a run-time value, so the */                     \
-  /* compiler cannot merge two of them into one instruction).  Ragged */                      \
-  /* tiles keep nothing in flight. */                                                          \
+  /* every element (EPT) through a run-time stride, one instruction */                        \
+  /* each; the forward split writes 4 points for every pair k of */                          \
+  /* 1 <= k < M/2, and each wave has such lanes in each of the first */                       \
+  /* M/(2 QT) steps.  On the strided axis those are 4 instructions; on */                     \
+  /* the contiguous one two adjacent points may become one store, which */                    \
+  /* leaves at least 2 (KEEP_C).  Ragged tiles keep nothing in flight. */                     \
   constexpr int KEEP = (ivk || inverse) ? L::EPT : 4 * (M / (2 * L::QT));                      \
-  static_assert(KEEP >= 1 && KEEP < 64, "vector-memory counter range");                       \
+  constexpr int KEEP_C = (ivk || inverse) ? L::EPT : 2 * (M / (2 * L::QT));                    \
+  static_assert(KEEP_C >= 1 && KEEP < 64, "vector-memory counter range");                     \
   bool stores_pending = false;
 
 #define POISSON_ASYNC_TILE(LT, QT, TIDT)                                                        \
   /* this wave's staged reads are done (the previous tile's stores may not be) */             \
-  if (stores_pending) vm_wait_keep<KEEP>();                                                    \
+  if (stores_pending) {                                                                        \
+    if (g.layout == 0) vm_wait_keep<KEEP>();                                                   \
+    else vm_wait_keep<KEEP_C>();                                                               \
+  }                                                                                            \
   else __builtin_amdgcn_s_waitcnt(0);                                                          \
   lds_barrier();                 /* ... and every wave's */                                    \
   if constexpr (ivk)                                                                           \
