@@ -15,7 +15,8 @@ hipError_t launch(const R2RFastArgs<T>& a, int kind, int inverse, hipStream_t st
 #define POISSON_AK(K_, I_)                                                                   \
   case K_ * 2 + I_:                                                                          \
     if constexpr (AsyncBudget<T, C, K_>::WIDE) return async_wide_launch(a, K_, I_, st);      \
-    else k = r2r_async_tight_kernel<T, C, K_, I_>;                                          \
+    else k = a.g.layout == 0 ? r2r_async_tight_kernel<T, C, K_, I_, 0>                      \
+                             : r2r_async_tight_kernel<T, C, K_, I_, 1>;                     \
     break;
     POISSON_AK(0, 0) POISSON_AK(0, 1) POISSON_AK(1, 0) POISSON_AK(1, 1) POISSON_AK(2, 0)
     POISSON_AK(2, 1) POISSON_AK(3, 0) POISSON_AK(3, 1) POISSON_AK(4, 0) POISSON_AK(4, 1)

@@ -15,7 +15,8 @@ hipError_t async_wide_launch(const R2RFastArgs<double>& a, int kind, int inverse
 #define POISSON_AW(K_, I_)                                                                   \
   case K_ * 2 + I_:                                                                          \
     static_assert(AsyncBudget<double, C, K_>::WIDE, "wide kernels only");                   \
-    k = r2r_async_kernel<double, C, K_, I_>;                                                \
+    k = a.g.layout == 0 ? r2r_async_kernel<double, C, K_, I_, 0>                            \
+                        : r2r_async_kernel<double, C, K_, I_, 1>;                           \
     break;
     POISSON_AW(0, 0) POISSON_AW(0, 1) POISSON_AW(3, 0) POISSON_AW(3, 1) POISSON_AW(4, 0)
     POISSON_AW(4, 1)

@@ -762,7 +762,7 @@ __device__ __forceinline__ void lds_dma16(const void* gaddr, unsigned lds_addr) 
 // is awaited by the vector-memory counter before the stage is read).
 template <typename T, typename C>
 __device__ __forceinline__ void async_fetch(lptr<unsigned char> stage, const R2RFastArgs<T>& A,
-                                            int tile, int tid) {
+                                            int layout, int tile, int tid) {
   using AL = AsyncLayout<T, C>;
   using L = FastLayout<T, C>;
   const LineGeom& g = A.g;
@@ -774,7 +774,7 @@ __device__ __forceinline__ void async_fetch(lptr<unsigned char> stage, const R2R
   for (int j = 0; j < AL::PER_WAVE; ++j) {
     const int c = wave * AL::PER_WAVE + j;     // chunk of this instruction (wave-uniform)
     const T* src = data;                        // a valid address for pieces outside the field
-    if (g.layout == 0) {
+    if (layout == 0) {
       const int row = c * AL::ROWS_PER_CHUNK + lane / AL::LANES_PER_ROW;
       const int l = (lane % AL::LANES_PER_ROW) * AL::EPL;
       const long long b = l < nlt ? line_base(g, o, l) : -1;
@@ -852,13 +852,14 @@ __device__ __forceinline__ void async_place_pre(lptr<const T> stage, lptr<T> lds
 template <typename T, typename C, bool IVK>
 __device__ __forceinline__ void async_store_wide(lptr<const T> lds, lptr<const cplx<T>> post,
                                                  int kind, int inverse, const R2RFastArgs<T>& A,
-                                                 long long base, int lines, int l, int q, int tid) {
+                                                 int layout, long long base, int lines, int l,
+                                                 int q, int tid) {
   if constexpr (sizeof(T) == 4) {
     if constexpr (IVK)
-      post_store_body<T, C, double>(lds, post, kind, as_global(A.out64), base, A.g.sp, A.g.layout,
+      post_store_body<T, C, double>(lds, post, kind, as_global(A.out64), base, A.g.sp, layout,
                                     lines, A.scale, l, q, tid);
     else
-      fast_store_body<T, C, double>(lds, as_global(A.out64), base, A.g.sp, A.g.layout, lines, kind,
+      fast_store_body<T, C, double>(lds, as_global(A.out64), base, A.g.sp, layout, lines, kind,
                                     inverse, A.scale, l, q, tid);
   }
 }
@@ -888,6 +889,7 @@ struct AsyncBudget {
   using AL = AsyncLayout<T, C>;                                                                \
   constexpr int M = L::M, NL = L::NL;                                                          \
   constexpr int kind = KIND, inverse = INV;                                                    \
+  constexpr int layout = LAYOUT;  /* 0 strided, 1 contiguous: one kernel each */              \
   if (A.skip && A.skip[0] != 0.0) return;                                                      \
   /* two LDS objects, so that the staged reads (asynchronous writes to */                     \
   /* stage_raw) are told apart from the accesses to the tile */                               \
@@ -897,7 +899,8 @@ struct AsyncBudget {
   const FastLds<T, C> S = fast_lds<T, C>(tile_raw);                                            \
   const int tid = threadIdx.x;                                                                 \
   const int l = tid % NL, q = tid / NL;                                                        \
-  const LineGeom& g = A.g;                                                                     \
+  LineGeom g = A.g;                                                                            \
+  g.layout = layout;             /* a constant for the inlined geometry helpers */             \
   constexpr bool ivk = kind >= K_ND;                                                           \
   const lptr<const cplx<T>> tw_fft = S.twf;                                                    \
   const lptr<const cplx<T>> tw_a = S.twa;                                                      \
@@ -905,7 +908,7 @@ struct AsyncBudget {
   fast_twiddles<T, C>(S, A, tid);                                                              \
   const TileRange tr = xcd_tiles(g.ntiles);                                                    \
   const lptr<unsigned char> stage_lds = as_lds(stage_raw);                                     \
-  if (tr.first < tr.end) async_fetch<T, C>(stage_lds, A, tr.first, tid);                      \
+  if (tr.first < tr.end) async_fetch<T, C>(stage_lds, A, layout, tr.first, tid);              \
   /* Stores of the previous tile issued after the staged reads, a lower */                     \
   /* bound per wave for a whole tile: the plain and DCT-IV stores write */                    \
   /* every element (EPT) through a run-time stride, one instruction */                        \
@@ -922,51 +925,53 @@ struct AsyncBudget {
 #define POISSON_ASYNC_TILE(LT, QT, TIDT)                                                        \
   /* this wave's staged reads are done (the previous tile's stores may not be) */             \
   if (stores_pending) {                                                                        \
-    if (g.layout == 0) vm_wait_keep<KEEP>();                                                   \
+    if (layout == 0) vm_wait_keep<KEEP>();                                                   \
     else vm_wait_keep<KEEP_C>();                                                               \
   }                                                                                            \
   else __builtin_amdgcn_s_waitcnt(0);                                                          \
   lds_barrier();                 /* ... and every wave's */                                    \
   if constexpr (ivk)                                                                           \
-    async_place_pre<T, C>(stage, S.tile, tw_a, kind, g.layout, LT, QT, TIDT);                  \
+    async_place_pre<T, C>(stage, S.tile, tw_a, kind, layout, LT, QT, TIDT);                  \
   else if constexpr (inverse)                                                                  \
-    async_place_combine<T, C>(stage, S.tile, tw_a, tw_b, kind, g.layout, LT, QT, TIDT);        \
+    async_place_combine<T, C>(stage, S.tile, tw_a, tw_b, kind, layout, LT, QT, TIDT);        \
   else                                                                                         \
-    async_place<T, C>(stage, S.tile, kind, inverse, g.layout, LT, QT, TIDT);                   \
+    async_place<T, C>(stage, S.tile, kind, inverse, layout, LT, QT, TIDT);                   \
   lds_barrier();                                                                               \
-  if (tile + tr.step < tr.end) async_fetch<T, C>(stage_lds, A, tile + tr.step, TIDT);         \
+  if (tile + tr.step < tr.end)                                                                 \
+    async_fetch<T, C>(stage_lds, A, layout, tile + tr.step, TIDT);                            \
   if constexpr (!(inverse && kind <= K_DD)) fast_passes<T, C, true, 0, true>(S.tile, tw_fft, LT, QT); \
   else fast_passes<T, C, false, 0, true>(S.tile, tw_fft, LT, QT);                             \
   const TileOrigin o = tile_origin(g, tile);                                                   \
   long long base;                                                                              \
   int lines = 0;                                                                               \
-  if (g.layout == 0) {                                                                         \
+  if (layout == 0) {                                                                         \
     base = LT < (1 << g.lognl) ? line_base(g, o, LT) : -1;                                     \
   } else {                                                                                     \
     base = (long long)o.L0 * L::N;                                                             \
     lines = g.nlines - o.L0;                                                                   \
   }                                                                                            \
   if (sizeof(T) == 4 && A.out64) { /* widened last pass of an FP32 solve */                   \
-    async_store_wide<T, C, ivk>(S.tile, tw_b, kind, inverse, A, base, lines, LT, QT, TIDT);      \
+    async_store_wide<T, C, ivk>(S.tile, tw_b, kind, inverse, A, layout, base, lines, LT, QT,   \
+                                TIDT);                                                         \
     stores_pending = false;                                                                    \
   } else if constexpr (ivk) {                                                                  \
-    post_store_body<T, C>(S.tile, tw_b, kind, as_global(A.data), base, g.sp, g.layout, lines, \
+    post_store_body<T, C>(S.tile, tw_b, kind, as_global(A.data), base, g.sp, layout, lines, \
                            A.scale, LT, QT, TIDT);                                             \
-    stores_pending = g.layout == 0 || lines >= NL;                                             \
+    stores_pending = layout == 0 || lines >= NL;                                             \
   } else if constexpr (!inverse) {                                                             \
-    split_store_body<T, C>(S.tile, tw_a, tw_b, kind, as_global(A.data), base, g.sp, g.layout,  \
+    split_store_body<T, C>(S.tile, tw_a, tw_b, kind, as_global(A.data), base, g.sp, layout,  \
                             lines, A.scale, LT, QT, TIDT);                                     \
-    stores_pending = g.layout == 0 || lines >= NL;                                             \
+    stores_pending = layout == 0 || lines >= NL;                                             \
   } else {                                                                                     \
-    fast_store<T, C, true>(S.tile, as_global(A.data), base, g.sp, g.layout, lines, kind,       \
+    fast_store<T, C, true>(S.tile, as_global(A.data), base, g.sp, layout, lines, kind,       \
                            inverse, A.scale, LT, QT, TIDT);                                    \
     /* strided tiles: each wave holds line 0, which always exists, so it */                   \
     /* issues all its stores; contiguous tiles only when no line is missing */                \
-    stores_pending = g.layout == 0 || lines >= NL;                                             \
+    stores_pending = layout == 0 || lines >= NL;                                             \
   }                                                                                            \
   lds_barrier();
 
-template <typename T, typename C, int KIND, int INV>
+template <typename T, typename C, int KIND, int INV, int LAYOUT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void r2r_async_kernel(R2RFastArgs<T> A) {
   POISSON_ASYNC_SETUP
@@ -975,7 +980,7 @@ void r2r_async_kernel(R2RFastArgs<T> A) {
   }
 }
 
-template <typename T, typename C, int KIND, int INV>
+template <typename T, typename C, int KIND, int INV, int LAYOUT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 void r2r_async_tight_kernel(R2RFastArgs<T> A) {
   POISSON_ASYNC_SETUP
