@@ -316,20 +316,24 @@ __device__ __forceinline__ void fast_store_body(lptr<const T> lds, gptr<O> data,
 #pragma unroll
       for (int i = 0; i < L::EPT; ++i) data[base + (q + i * L::QT) * sp] = (O)buf[i];
     }
-  } else {
+  } else {   // two adjacent points of a line per lane (one 16-byte store for FP64)
 #pragma unroll
     for (int i = 0; i < L::EPT; ++i) {
-      const int e = tid + i * L::NT;
+      const int e = 2 * (tid + (i >> 1) * L::NT) + (i & 1);
       const int ll = e / N, p = e % N;
       bool neg;
       const int r = store_row(kind, inverse, p, N, neg);
       const T v = lds[r * L::NLP + ll] * scale;
       buf[i] = neg ? -v : v;
     }
+    const gptr<O> row = data + base;
 #pragma unroll
-    for (int i = 0; i < L::EPT; ++i) {
-      const int e = tid + i * L::NT;
-      if ((e / N) < lines) data[base + e] = (O)buf[i];
+    for (int i = 0; i < L::EPT; i += 2) {
+      const int e = 2 * (tid + (i >> 1) * L::NT);   // even: e and e + 1 share a line
+      if ((e / N) < lines) {
+        row[e] = (O)buf[i];
+        row[e + 1] = (O)buf[i + 1];
+      }
     }
   }
 }
@@ -910,15 +914,17 @@ struct AsyncBudget {
   const lptr<unsigned char> stage_lds = as_lds(stage_raw);                                     \
   if (tr.first < tr.end) async_fetch<T, C>(stage_lds, A, layout, tr.first, tid);              \
   /* Stores of the previous tile issued after the staged reads, a lower */                     \
-  /* bound per wave for a whole tile: the plain and DCT-IV stores write */                    \
-  /* every element (EPT) through a run-time stride, one instruction */                        \
-  /* each; the forward split writes 4 points for every pair k of */                          \
-  /* 1 <= k < M/2, and each wave has such lanes in each of the first */                       \
-  /* M/(2 QT) steps.  On the strided axis those are 4 instructions; on */                     \
-  /* the contiguous one two adjacent points may become one store, which */                    \
-  /* leaves at least 2 (KEEP_C).  Ragged tiles keep nothing in flight. */                     \
+  /* bound per wave for a whole tile (KEEP strided, KEEP_C contiguous): */                     \
+  /* the plain and DCT-IV stores write every element (EPT) through a */                       \
+  /* run-time stride, one instruction each, except the plain store on */                      \
+  /* the contiguous axis, which writes two adjacent elements per lane */                      \
+  /* (EPT/2 instructions at least); the forward split writes 4 points */                      \
+  /* for every pair k of 1 <= k < M/2, and each wave has such lanes in */                     \
+  /* each of the first M/(2 QT) steps: 4 instructions on the strided */                       \
+  /* axis, at least 2 on the contiguous one (two adjacent points may */                       \
+  /* become one store).  Ragged tiles keep nothing in flight. */                              \
   constexpr int KEEP = (ivk || inverse) ? L::EPT : 4 * (M / (2 * L::QT));                      \
-  constexpr int KEEP_C = (ivk || inverse) ? L::EPT : 2 * (M / (2 * L::QT));                    \
+  constexpr int KEEP_C = ivk ? L::EPT : inverse ? L::EPT / 2 : 2 * (M / (2 * L::QT));          \
   static_assert(KEEP_C >= 1 && KEEP < 64, "vector-memory counter range");                     \
   bool stores_pending = false;
 
