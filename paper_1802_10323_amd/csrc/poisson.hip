@@ -274,8 +274,10 @@ static int lds_setup_once() {
       for (int V = 0; V < 2; ++V)
         with_tri_cfg(n, V, [&](auto cfg) {
           using C = decltype(cfg);
-          ALLOW((tri_fast_kernel<double, C::RPC, C::P>));
-          ALLOW((tri_fast_kernel<float, C::RPC, C::P>));
+          ALLOW((tri_fast_kernel<double, C::RPC, C::P, 0>));
+          ALLOW((tri_fast_kernel<double, C::RPC, C::P, 1>));
+          ALLOW((tri_fast_kernel<float, C::RPC, C::P, 0>));
+          ALLOW((tri_fast_kernel<float, C::RPC, C::P, 1>));
           return 0LL;
         });
     ALLOW((batch_r2r_kernel<double>));
@@ -529,9 +531,11 @@ static int launch_tri_fast(const poisson_plan* p, T* data, hipStream_t st, const
   using L = TriFastLayout<T, RPC, P>;
   const TriFastArgs<T> a = tri_fast_args<T, RPC, P>(p, data, skip);
   const size_t lds = tri_fast_lds_bytes<T, RPC, P>();
-  const void* fn = reinterpret_cast<const void*>(&tri_fast_kernel<T, RPC, P>);
-  hipLaunchKernelGGL((tri_fast_kernel<T, RPC, P>), dim3(resident_grid(fn, L::NT, lds, a.g.ntiles)),
-                     dim3(L::NT), lds, st, a);
+  // one kernel per layout (strided, contiguous)
+  void (*k)(TriFastArgs<T>) =
+      a.g.layout == 0 ? tri_fast_kernel<T, RPC, P, 0> : tri_fast_kernel<T, RPC, P, 1>;
+  const void* fn = reinterpret_cast<const void*>(k);
+  hipLaunchKernelGGL(k, dim3(resident_grid(fn, L::NT, lds, a.g.ntiles)), dim3(L::NT), lds, st, a);
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
 }

@@ -91,12 +91,13 @@ __device__ __forceinline__ int tri_fast_slot(int p, int ll) {
 // Tile load: global -> LDS; all global loads of a thread are issued before
 // its first LDS write.  Strided layout: line tid mod NL, points
 // tid / NL + i P; contiguous layout: element tid + i NT of the tile's run.
-template <typename T, int RPC, int P>
+// LAY >= 0: the layout as a constant (0 strided, 1 contiguous); -1: `layout`.
+template <typename T, int RPC, int P, int LAY = -1>
 __device__ __noinline__ void tri_fast_load(lptr<T> lds, gptr<const T> data, long long base,
                                            long long sp, int layout, int lines, int tid) {
   using L = TriFastLayout<T, RPC, P>;
   T buf[RPC];
-  if (layout == 0) {
+  if ((LAY >= 0 ? LAY : layout) == 0) {
     const int l = tid % L::NL, q = tid / L::NL;
 #pragma unroll
     for (int i = 0; i < RPC; ++i) buf[i] = base >= 0 ? data[base + (q + i * P) * sp] : (T)0;
@@ -145,10 +146,10 @@ __device__ __forceinline__ void tri_fast_store_body(lptr<const T> lds, gptr<T> d
   }
 }
 
-template <typename T, int RPC, int P>
+template <typename T, int RPC, int P, int LAY = -1>
 __device__ __noinline__ void tri_fast_store(lptr<const T> lds, gptr<T> data, long long base,
                                             long long sp, int layout, int lines, int tid) {
-  tri_fast_store_body<T, RPC, P>(lds, data, base, sp, layout, lines, tid);
+  tri_fast_store_body<T, RPC, P>(lds, data, base, sp, LAY >= 0 ? LAY : layout, lines, tid);
 }
 
 // Sum over the P lanes of a line.
@@ -375,12 +376,13 @@ __device__ __forceinline__ void tri_fast_coefs(lptr<double> coef, const TriFastA
 
 // One tile of lines of the launch described by A, with the coefficients in
 // LDS; ends with a barrier.
-template <typename T, int RPC, int P>
+template <typename T, int RPC, int P, int LAY = -1>
 __device__ __forceinline__ void tri_fast_tile(lptr<T> lds, lptr<const double> coef,
                                               const TriFastArgs<T>& A, int tile, int tid) {
   using L = TriFastLayout<T, RPC, P>;
   constexpr int N = L::N, NL = L::NL;
-  const LineGeom& g = A.g;
+  LineGeom g = A.g;
+  if (LAY >= 0) g.layout = LAY;   // a constant for the inlined geometry helpers
   const int c = tid % P;        // chunk of this thread
   const int l = tid / P;        // line of this thread within the tile
   const int nlt = 1 << g.lognl; // lines in a full tile of this launch (<= NL)
@@ -396,7 +398,7 @@ __device__ __forceinline__ void tri_fast_tile(lptr<T> lds, lptr<const double> co
     base = (long long)o.L0 * N;
     lines = min(g.nlines - o.L0, nlt);
   }
-  tri_fast_load<T, RPC, P>(lds, as_global((const T*)A.data), base, g.sp, g.layout, lines, tid);
+  tri_fast_load<T, RPC, P, LAY>(lds, as_global((const T*)A.data), base, g.sp, g.layout, lines, tid);
   __syncthreads();
 
   const bool valid = l < nlt && line_base(g, o, l) >= 0;
@@ -408,11 +410,11 @@ __device__ __forceinline__ void tri_fast_tile(lptr<T> lds, lptr<const double> co
   tri_fast_line<T, RPC, P>(col, coef, c, mu, sing ? 1 : 0, wave_sing, A.periodic);
   __syncthreads();
 
-  tri_fast_store<T, RPC, P>(lds, as_global(A.data), base, g.sp, g.layout, lines, tid);
+  tri_fast_store<T, RPC, P, LAY>(lds, as_global(A.data), base, g.sp, g.layout, lines, tid);
   __syncthreads();
 }
 
-template <typename T, int RPC, int P>
+template <typename T, int RPC, int P, int LAYOUT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 void tri_fast_kernel(TriFastArgs<T> A) {
   using L = TriFastLayout<T, RPC, P>;
@@ -430,7 +432,7 @@ void tri_fast_kernel(TriFastArgs<T> A) {
     // spilled) across the loop; shorter chunks are faster with them held
     int t = tid;
     if constexpr (RPC >= 16) asm volatile("" : "+v"(t));
-    tri_fast_tile<T, RPC, P>(lds, coef, A, tile, t);
+    tri_fast_tile<T, RPC, P, LAYOUT>(lds, coef, A, tile, t);
   }
 }
 
