@@ -206,7 +206,8 @@ int batch_autotune(poisson_batch* batch, int reps, hipStream_t stream, double* r
  * lengths 256 and 512 (variant 5 for FP64 length 256 and for FP32 length 512
  * on the contiguous axis, 6 for FP32 length 512 on the strided axes, else 4)
  * and variant 0 otherwise; eliminations variant 1 on strided lines of 384
- * points and FP32 lines of 256, else 0.  Plans and batches read the
+ * points and FP32 lines of 256, variant 2 on contiguous FP32 lines of 512,
+ * else 0.  Plans and batches read the
  * table when they launch (batches when they are bound; batches use the
  * synchronous variants only: transforms 0-3, elimination 0-1). */
 

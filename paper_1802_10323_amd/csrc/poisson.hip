@@ -224,8 +224,10 @@ static std::map<std::tuple<int, int, int, int, int>, int> g_tune;
 // 0, whose wider tile rows use each DRAM page better.
 static int default_choice(int family, int bytes, int n, int layout) {
   if (family == 1) {
-    // elimination: the second chunking (shorter interface reduction) wins on
-    // strided lines of 384 points, and of 256 points in FP32
+    // elimination: the staging form wins on contiguous FP32 lines of 512
+    // points; the second chunking (shorter interface reduction) on strided
+    // lines of 384 points, and of 256 points in FP32
+    if (layout == 1 && bytes == 4 && n == 512) return kTriAsyncVariant;
     return layout == 0 && (n == 384 || (bytes == 4 && n == 256)) ? 1 : 0;
   }
   if (n != 128 && n != 256) return 0;

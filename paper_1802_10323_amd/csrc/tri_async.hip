@@ -11,7 +11,8 @@ namespace {
 
 template <typename T, int RPC, int P>
 hipError_t launch(const TriFastArgs<T>& a, hipStream_t st) {
-  void (*k)(TriFastArgs<T>) = tri_async_kernel<T, RPC, P>;
+  void (*k)(TriFastArgs<T>) =
+      a.g.layout == 0 ? tri_async_kernel<T, RPC, P, 0> : tri_async_kernel<T, RPC, P, 1>;
   hipLaunchKernelGGL(k, dim3(async_resident_blocks(reinterpret_cast<const void*>(k), a.g.ntiles)),
                      dim3(512), 0, st, a);
   return hipGetLastError();

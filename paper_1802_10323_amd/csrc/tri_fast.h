@@ -452,7 +452,7 @@ struct TriAsyncLayout {
   static constexpr int STAGE_BYTES = L::NL * L::N * (int)sizeof(T);
 };
 
-template <typename T, int RPC, int P>
+template <typename T, int RPC, int P, int LAYOUT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void tri_async_kernel(TriFastArgs<T> A) {
   using L = TriFastLayout<T, RPC, P>;
@@ -469,7 +469,8 @@ void tri_async_kernel(TriFastArgs<T> A) {
   const lptr<const T> stage = as_lds(reinterpret_cast<const T*>(stage_raw));
   const lptr<unsigned char> stage_lds = as_lds(stage_raw);
   const int tid0 = threadIdx.x;
-  const LineGeom& g = A.g;
+  LineGeom g = A.g;
+  g.layout = LAYOUT;   // one kernel per layout: its branches are constants
   const int nlt = 1 << g.lognl;
 
   for (int i = tid0; i < A.nu; i += NT) lam[i] = as_global(A.lamu)[i];
