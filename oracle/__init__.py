@@ -22,4 +22,5 @@ elimination, dense solves, closed-form eigenfunctions).  Parity is not
 unpinned for any function here.
 """
 from . import transforms, tridiagonal, poisson  # noqa: F401
-from .poisson import solve, apply_operator, residual, is_singular, weighted_mean  # noqa: F401
+from .poisson import (solve, solve_corrected, apply_operator, residual, is_singular,  # noqa: F401
+                      weighted_mean)

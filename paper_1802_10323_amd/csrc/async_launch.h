@@ -36,6 +36,13 @@ hipError_t async_elimination_launch(const TriFastArgs<float>& a, int n, hipStrea
 hipError_t async_wide_launch(const R2RFastArgs<double>& a, int kind, int inverse,
                              hipStream_t stream);
 
+// Upper bound on the blocks of the persistent launch being made on this
+// thread (0: none): the grid cap of the plan whose stage is launched.  A
+// testing switch (environment variable POISSON_GRID_CAP, read by
+// plan_create) that makes small fields loop over many tiles per block, as
+// the largest fields do.
+int grid_cap_blocks();
+
 // Blocks of a persistent launch of `fn` (512 threads, static LDS only): as
 // many as are resident at once, at most one per tile.
 inline int async_resident_blocks(const void* fn, long long ntiles) {
@@ -57,6 +64,8 @@ inline int async_resident_blocks(const void* fn, long long ntiles) {
     std::lock_guard<std::mutex> lk(mu);
     cache.push_back({{fn, dev}, blocks});
   }
+  const int cap = grid_cap_blocks();
+  if (cap > 0) blocks = std::min(blocks, cap);
   return (int)std::min<long long>(ntiles, blocks);
 }
 

@@ -136,6 +136,7 @@ struct poisson_plan {
   bool z_uniform;
   bool generic_r2r = false;    // POISSON_GENERIC_R2R=1: size-generic transform kernel only
   bool generic_tri = false;    // POISSON_GENERIC_TRI=1: size-generic elimination kernel only
+  int grid_cap = 0;            // POISSON_GRID_CAP=B: at most B blocks per stage launch (0: none)
   int t1, t2, s;
   bool singular, s_periodic;
   int device;
@@ -337,6 +338,9 @@ static unsigned div_magic(int d) {
   return d > 1 ? (unsigned)((((unsigned long long)1 << 32) + d - 1) / d) : 0u;
 }
 
+static thread_local int t_grid_cap = 0;
+int poisson_dev::grid_cap_blocks() { return t_grid_cap; }
+
 // Persistent grid: as many blocks as can be resident at once (CUs x blocks
 // per CU for this kernel, block size and LDS), each looping over tiles, so
 // that no block pays launch and set-up more than once per launch.
@@ -361,7 +365,10 @@ static int resident_grid(const void* fn, int block, size_t lds, long long ntiles
     std::lock_guard<std::mutex> lk(mu);
     cache.push_back({{fn, lds + (size_t)dev * 0x100000000ull}, {per_cu, cus}});
   }
-  return (int)std::min<long long>(ntiles, (long long)cus * per_cu);
+  long long blocks = (long long)cus * per_cu;
+  const int cap = grid_cap_blocks();
+  if (cap > 0) blocks = std::min<long long>(blocks, cap);
+  return (int)std::min<long long>(ntiles, blocks);
 }
 
 // ------------------------------------------------------------------ launches
@@ -461,6 +468,7 @@ static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hip
                       const double* skip = nullptr, double* out64 = nullptr) {
   const AxisTables& A = p->ax[role];
   if constexpr (sizeof(T) == 8) out64 = nullptr;
+  t_grid_cap = p->grid_cap;
   if (!p->generic_r2r) {
     const int rc = launch_fast_variant<T>(p, A, tuned_choice(0, sizeof(T), A.m, A.axis == 0),
                                           inverse, data, st, skip, out64);
@@ -591,6 +599,7 @@ static int r2r_fast_length(const AxisTables& A) {
 template <typename T>
 static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
                           const double* skip = nullptr) {
+  t_grid_cap = p->grid_cap;
   if (!p->generic_tri) {
     const int n = p->dims[p->s];
     const int rc = launch_tri_variant<T>(p, tuned_choice(1, sizeof(T), n, p->s == 0), data, st, skip);
@@ -728,6 +737,8 @@ extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double d
     p->generic_r2r = env && env[0] == '1';
     env = std::getenv("POISSON_GENERIC_TRI");
     p->generic_tri = env && env[0] == '1';
+    env = std::getenv("POISSON_GRID_CAP");
+    p->grid_cap = env ? std::max(0, std::atoi(env)) : 0;
   }
   for (int k = 1; k < nz; ++k) if (dz[k] != dz[0]) p->z_uniform = false;
 
@@ -1329,6 +1340,7 @@ extern "C" int batch_bind(poisson_batch* b, double* const* rhs) {
 template <typename T>
 static int batch_enqueue_typed(poisson_batch* b, int k, hipStream_t st) {
   if (b->items[k] == 0) return POISSON_OK;
+  t_grid_cap = 0;   // batched launches are never capped
   const size_t lds = b->lds[k];
   if (kStepRole[k % 5] >= 0) {
     const auto* jobs = reinterpret_cast<const BatchR2RJob<T>*>(b->djobs + b->off[k]);

@@ -10,7 +10,7 @@ import sys
 import numpy as np
 import pytest
 
-from gpu_util import AXIS, gpu_solve, oracle_solve, rel_l2, to_dev, to_host
+from gpu_util import AXIS, check_elimination, gpu_solve, oracle_solve, rel_l2, to_dev, to_host
 from paper_1802_10323_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -19,19 +19,6 @@ KINDS = ("P", "NN", "DD", "ND", "DN")
 TOL64 = 1e-12
 FAST_M = [16, 32, 48, 64, 96, 128, 192, 256]
 ELIM_LENGTHS = [64, 96, 128, 192, 256, 384, 512]
-
-
-@pytest.fixture
-def default_variants():
-    """Put every entry of the variant table back to what it was before the
-    test."""
-    from paper_1802_10323_amd import set_tuned_variant, tuned_variant
-    keys = [(0, 2 * M, layout, fp64) for M in FAST_M for layout in (0, 1) for fp64 in (True, False)]
-    keys += [(1, n, layout, fp64) for n in ELIM_LENGTHS for layout in (0, 1) for fp64 in (True, False)]
-    saved = [(k, tuned_variant(*k)) for k in keys]
-    yield
-    for (family, n, layout, fp64), v in saved:
-        set_tuned_variant(family, n, layout, v, fp64)
 
 
 def say(*a):
@@ -137,89 +124,13 @@ def test_transform_lengths(kind, n, path, monkeypatch):
         plan.close()
 
 
-UNIT = 2.0 ** -53
-
-
-def _line_systems(x, f, a, b, c, periodic, shift):
-    """Largest normwise backward error over the lines (columns) of
-    (b + shift) x + a x_{k-1} + c x_{k+1} = f."""
-    ax = (b[:, None] + shift[None, :]) * x
-    ax[1:] += a[1:, None] * x[:-1]
-    ax[:-1] += c[:-1, None] * x[1:]
-    if periodic:
-        ax[0] += a[0] * x[-1]
-        ax[-1] += c[-1] * x[0]
-    norm_a = (np.abs(a)[:, None] + np.abs(b[:, None] + shift[None, :]) + np.abs(c)[:, None]).max(axis=0)
-    scale = norm_a * np.linalg.norm(x, axis=0) + np.linalg.norm(f, axis=0)
-    return float((np.linalg.norm(ax - f, axis=0) / scale).max())
-
-
 @pytest.mark.parametrize("path", ["specialised", "generic"])
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("n", ELIM_LENGTHS)
 def test_elimination_lengths(n, kind, path, monkeypatch):
     if path == "generic":
         monkeypatch.setenv("POISSON_GENERIC_TRI", "1")
-    _check_elimination(n, kind)
-
-
-def _check_elimination(n, kind):
-    """The elimination stage alone for lengths that have size-specialised
-    kernels (and the size-generic kernel on the same input), on the strided
-    (s = z) and contiguous (s = x) layouts, singular and regular, uniform and
-    stretched, with ragged last tiles.
-
-    Checks: (1) every regular line's normwise backward error is at rounding
-    level (<= 1e-14, condition-independent); (2) the result matches the
-    oracle within max(1e-12, kappa u), kappa the 2-norm condition number of
-    the zero-shift (or, when singular, pinned) line operator, which bounds
-    the forward error of any backward-stable solver of the worst line."""
-    from oracle import transforms as tr
-    from oracle import tridiagonal as td
-    from oracle.poisson import tridiagonal_stage
-    from paper_1802_10323_amd import Plan
-    import oracle
-    if kind == "P":   # a periodic elimination axis only occurs when all axes are
-        cases = [((20, 10, n), ("P", "P", "P"), "z")]
-    else:
-        cases = [((20, 10, n), ("P", "P", kind), "z"), ((20, 10, n), ("P", "DD", kind), "z"),
-                 ((n, 10, 6), (kind, "P", "P"), "x"), ((n, 10, 6), (kind, "DD", "P"), "x")]
-    for shape, bcs, s_expect in cases:
-        for stretched in ((False, True) if bcs[2] != "P" else (False,)):
-            prob = inputs.make_uniform(*shape, bcs, seed=n + len(kind),
-                                       stretch_z=1.8 if stretched else None)
-            plan = Plan.from_problem(prob)
-            t1, t2, s = plan.roles
-            assert s == s_expect
-            h = {"x": prob.hx, "y": prob.hy, "z": prob.hz}
-            bc = dict(zip("xyz", bcs))
-            dims = dict(zip("xyz", shape))
-            singular = oracle.is_singular(*bcs)
-            # lines along s as columns: (n_s, n_t1 * n_t2)
-            order = (AXIS[s], AXIS[t1], AXIS[t2])
-            fin = np.transpose(prob.rhs, order).copy()
-            if singular:   # the zero-wavenumber line of a transformed compatible field
-                w = h[s]
-                fin[:, 0, 0] -= (w * fin[:, 0, 0]).sum() / w.sum()
-            f = np.ascontiguousarray(np.transpose(fin, np.argsort(order)))
-            lam1 = tr.eigenvalues(bc[t1], dims[t1]) / h[t1][0] ** 2
-            lam2 = tr.eigenvalues(bc[t2], dims[t2]) / h[t2][0] ** 2
-            ref = tridiagonal_stage(f, s, h[s], bc[s], lam1, lam2, t1, t2, singular)
-            d = to_dev(f)
-            plan.tridiag_stage(d)
-            got = to_host(d)
-            plan.close()
-            a, b, c, periodic = td.coefficients(h[s], bc[s])
-            shift = (lam1[:, None] + lam2[None, :]).reshape(-1)
-            xg = np.transpose(got, order).reshape(dims[s], -1)
-            fl = fin.reshape(dims[s], -1)
-            first = 1 if singular else 0
-            back = _line_systems(xg[:, first:], fl[:, first:], a, b, c, periodic, shift[first:])
-            assert back <= 1e-14, (shape, bcs, stretched, "backward error", back)
-            ops = np.diag(b) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
-            kappa = np.linalg.cond(ops[:-1, :-1] if singular else ops)
-            err = rel_l2(got, ref)
-            assert err <= max(1e-12, kappa * UNIT), (shape, bcs, stretched, err, kappa)
+    check_elimination(n, kind)
 
 
 # --------------------------------------------------------------- whole solve
@@ -303,24 +214,6 @@ def test_channel_full_size():
     err = rel_l2(got, ref)
     say("channel rel-L2", err)
     assert err <= TOL64
-
-
-def test_cube_full_size_residual():
-    """The 512^3 (DD, ND, P) workload at full size: the FP64 seven-point
-    residual of the GPU solution (computed on the CPU by the oracle's
-    operator) is at round-off, and a 256^3 version of the same problem
-    matches the oracle solve."""
-    import oracle
-    prob = inputs.cube(0)
-    got, _ = gpu_solve(prob)
-    r = oracle.residual(prob.rhs, got, prob.hx, prob.hy, prob.hz, *prob.bcs)
-    rr = np.linalg.norm(r) / np.linalg.norm(prob.rhs)
-    say("cube 512^3 relative residual", rr)
-    assert rr <= 1e-13
-    del got, r
-    half = inputs.cube(0, n=256)
-    got, _ = gpu_solve(half)
-    assert rel_l2(got, oracle_solve(half)) <= TOL64
 
 
 # --------------------------------------------------------------- precision
@@ -584,7 +477,7 @@ def test_elimination_variants(n, kind, V, default_variants):
     from paper_1802_10323_amd import set_tuned_variant
     for layout in (0, 1):
         set_tuned_variant(1, n, layout, V)
-    _check_elimination(n, kind)
+    check_elimination(n, kind)
 
 
 @pytest.mark.parametrize("vt,ve", [(1, 0), (2, 1), (3, 1)])
