@@ -281,6 +281,37 @@ int server_stats(poisson_server* server, long long* plan_hits, long long* plan_m
 /* Finish every queued request, stop the worker, free the cached plans. */
 void server_destroy(poisson_server* server);
 
+/* ---- refined solve that allocates nothing ----
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * FP32 + FP64 refinement as solve() on a POISSON_FP32_REFINED plan (same
+ * kernels, same launch sequence: the same bits), whatever the plan's own
+ * precision mode, but its workspace (FP64 copy of f, FP32 residual /
+ * correction field, status block) is a static array of the library, 256 MiB
+ * per device, held from the library's load on that device until the
+ * process ends.  The call allocates nothing and calls no allocating
+ * routine.  Every call on a device uses that device's one array and leaves
+ * its contents behind (each call re-initialises what it reads): calls that
+ * overlap on one device, on any streams, race and give wrong results; the
+ * caller orders them (one stream, or events). */
+
+/* Largest nx*ny*nz that solve_refined_noalloc accepts (the workspace takes
+ * 12 B per point plus a status block). */
+size_t refined_noalloc_max_points(void);
+
+/* Refined solve of rhs in place (DEVICE, nx*ny*nz doubles, x fastest) with
+ * tolerance tol (> 0) and at most max_iters FP32 solves (1..64), as
+ * plan_set_precision describes, on the workspace above, enqueued on
+ * `stream`.  status_out (DEVICE, 3 doubles, may be NULL) receives at the end
+ * of the stream: FP32 solves performed, 1.0 if the tolerance was reached
+ * (else 0.0), and the last relative update.  solve_status() does not report
+ * this call.  POISSON_EUNSUPPORTED if the grid has more than
+ * refined_noalloc_max_points() points; POISSON_EINVAL for bad arguments or
+ * when the current device is not the plan's. */
+int solve_refined_noalloc(poisson_plan* plan, double* rhs, double tol, int max_iters,
+                          double* status_out, hipStream_t stream);
+
 /* ---- stage entry points (the steps of Sec. 2.1, for stage-level checks) ---- */
 
 /* Axis roles chosen by the plan: roles[0] = t1, roles[1] = t2 (the transformed

@@ -165,6 +165,7 @@ struct poisson_plan {
 };
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+static constexpr size_t align_up_c(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // ------------------------------------------------------------------ variants
 
@@ -966,7 +967,23 @@ extern "C" int solve_status(poisson_plan* p, int* iters, double* rel) {
   return p->last_converged ? POISSON_OK : POISSON_ENOTCONVERGED;
 }
 
-static RefineGeom refine_geom(const poisson_plan* p) {
+// Workspace of a refined solve: the FP64 copy of f, the FP32 residual /
+// correction field and the status block (REFINE_STAT_SLOTS doubles).  A
+// plan's own (plan_set_precision), lent by a server slot, or the library's
+// static scratch array (solve_refined_noalloc).
+struct RefineWork {
+  double* f64;
+  float* e32;
+  double* stats;
+  double tol;
+  int max_iters;
+};
+
+static RefineWork plan_work(const poisson_plan* p) {
+  return RefineWork{p->f64, p->e32, p->stats, p->tol, p->max_iters};
+}
+
+static RefineGeom refine_geom(const poisson_plan* p, double* stats) {
   RefineGeom G{};
   for (int q = 0; q < 3; ++q) {
     const int n = p->dims[q];
@@ -974,7 +991,7 @@ static RefineGeom refine_geom(const poisson_plan* p) {
     G.ax[q] = OpAxis{base, base + n, base + 2 * n, base + 3 * n, n};
   }
   G.npts = (long long)field_points(p);
-  G.stats = p->stats;
+  G.stats = stats;
   return G;
 }
 
@@ -992,75 +1009,166 @@ struct RefineLaunch {
   ResidualGrid rg;
 };
 
-static RefineLaunch refine_launch(const poisson_plan* p) {
+static RefineLaunch refine_launch(const poisson_plan* p, double* stats) {
   RefineLaunch r;
   r.N = (long long)field_points(p);
-  r.G = refine_geom(p);
+  r.G = refine_geom(p, stats);
   r.nb = (int)std::min<long long>(REFINE_BLOCKS, (r.N + REFINE_NT - 1) / REFINE_NT);
   r.rg = residual_grid(p->dims[0], p->dims[1], p->dims[2]);
   return r;
 }
 
 // Status reset, projection of f if singular, the FP64 copy of f and its FP32 cast.
-static int refine_begin(poisson_plan* p, double* rhs, hipStream_t st) {
-  const RefineLaunch r = refine_launch(p);
-  hipLaunchKernelGGL(refine_init_kernel, dim3(1), dim3(256), 0, st, p->stats);
+static int refine_begin(const poisson_plan* p, const RefineWork& W, double* rhs, hipStream_t st) {
+  const RefineLaunch r = refine_launch(p, W.stats);
+  hipLaunchKernelGGL(refine_init_kernel, dim3(1), dim3(256), 0, st, W.stats);
   if (p->singular) {
     hipLaunchKernelGGL(refine_wsum_kernel, dim3(r.nb), dim3(REFINE_NT), 0, st, (const double*)rhs, r.G);
-    hipLaunchKernelGGL(refine_mean_kernel, dim3(1), dim3(REFINE_NT), 0, st, p->stats, r.nb);
+    hipLaunchKernelGGL(refine_mean_kernel, dim3(1), dim3(REFINE_NT), 0, st, W.stats, r.nb);
   }
   hipLaunchKernelGGL(refine_prep_kernel, dim3(r.nb), dim3(REFINE_NT), 0, st, (const double*)rhs,
-                     p->f64, p->e32, (const double*)p->stats, (int)p->singular, r.N);
+                     W.f64, W.e32, (const double*)W.stats, (int)p->singular, r.N);
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
 }
 
 // Sweep `sweep` before its FP32 solve: the FP64 residual into e32.
-static int refine_sweep_begin(poisson_plan* p, double* rhs, hipStream_t st) {
-  const RefineLaunch r = refine_launch(p);
+static int refine_sweep_begin(const poisson_plan* p, const RefineWork& W, double* rhs,
+                              hipStream_t st) {
+  const RefineLaunch r = refine_launch(p, W.stats);
   hipLaunchKernelGGL(refine_residual_kernel, dim3(r.rg.blocks), dim3(REFINE_NT), 0, st,
-                     (const double*)rhs, (const double*)p->f64, p->e32, r.G, r.rg);
+                     (const double*)rhs, (const double*)W.f64, W.e32, r.G, r.rg);
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
 }
 
 // Sweep `sweep` after its FP32 solve: Phi += e and the convergence test.
-static int refine_sweep_end(poisson_plan* p, double* rhs, int sweep, hipStream_t st) {
-  const RefineLaunch r = refine_launch(p);
+static int refine_sweep_end(const poisson_plan* p, const RefineWork& W, double* rhs, int sweep,
+                            hipStream_t st) {
+  const RefineLaunch r = refine_launch(p, W.stats);
   hipLaunchKernelGGL(refine_update_kernel, dim3(r.nb), dim3(REFINE_NT), 0, st, rhs,
-                     (const float*)p->e32, r.G);
-  hipLaunchKernelGGL(refine_status_kernel, dim3(1), dim3(REFINE_NT), 0, st, p->stats, r.nb, sweep,
-                     p->tol);
+                     (const float*)W.e32, r.G);
+  hipLaunchKernelGGL(refine_status_kernel, dim3(1), dim3(REFINE_NT), 0, st, W.stats, r.nb, sweep,
+                     W.tol);
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
 }
 
-// Gauge of a singular problem and the status copy for solve_status.
-static int refine_end(poisson_plan* p, double* rhs, hipStream_t st) {
-  const RefineLaunch r = refine_launch(p);
+// Gauge of a singular problem.
+static int refine_end(const poisson_plan* p, const RefineWork& W, double* rhs, hipStream_t st) {
+  const RefineLaunch r = refine_launch(p, W.stats);
   if (p->singular) {
     hipLaunchKernelGGL(refine_wsum_kernel, dim3(r.nb), dim3(REFINE_NT), 0, st, (const double*)rhs, r.G);
-    hipLaunchKernelGGL(refine_mean_kernel, dim3(1), dim3(REFINE_NT), 0, st, p->stats, r.nb);
+    hipLaunchKernelGGL(refine_mean_kernel, dim3(1), dim3(REFINE_NT), 0, st, W.stats, r.nb);
     hipLaunchKernelGGL(refine_shift_kernel, dim3(r.nb), dim3(REFINE_NT), 0, st, rhs,
-                       (const double*)p->stats, r.N);
+                       (const double*)W.stats, r.N);
   }
   HIP_TRY(hipGetLastError());
+  return POISSON_OK;
+}
+
+// The whole refined solve on workspace W.
+static int run_refined(const poisson_plan* p, const RefineWork& W, double* rhs, hipStream_t st) {
+  int rc;
+  if ((rc = refine_begin(p, W, rhs, st))) return rc;
+  // the first FP32 solve's last pass writes Phi (widened) into rhs
+  if ((rc = solve_typed<float>(p, W.e32, st, nullptr, rhs))) return rc;
+  for (int sweep = 1; sweep < W.max_iters; ++sweep) {
+    if ((rc = refine_sweep_begin(p, W, rhs, st))) return rc;
+    if ((rc = solve_typed<float>(p, W.e32, st, W.stats))) return rc;
+    if ((rc = refine_sweep_end(p, W, rhs, sweep, st))) return rc;
+  }
+  return refine_end(p, W, rhs, st);
+}
+
+// The plan's refined solve, and the status copy for solve_status.
+static int solve_refined(poisson_plan* p, double* rhs, hipStream_t st) {
+  const RefineWork W = plan_work(p);
+  const int rc = run_refined(p, W, rhs, st);
+  if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(p->stats_host, p->stats, REFINE_PARTIALS * sizeof(double),
                          hipMemcpyDeviceToHost, st));
   return POISSON_OK;
 }
 
-static int solve_refined(poisson_plan* p, double* rhs, hipStream_t st) {
-  int rc;
-  if ((rc = refine_begin(p, rhs, st))) return rc;
-  // the first FP32 solve's last pass writes Phi (widened) into rhs
-  if ((rc = solve_typed<float>(p, p->e32, st, nullptr, rhs))) return rc;
-  for (int sweep = 1; sweep < p->max_iters; ++sweep) {
-    if ((rc = refine_sweep_begin(p, rhs, st))) return rc;
-    if ((rc = solve_typed<float>(p, p->e32, st, p->stats))) return rc;
-    if ((rc = refine_sweep_end(p, rhs, sweep, st))) return rc;
+// ------------------------------------------------------------------ no-allocation refined solve
+
+// Workspace of solve_refined_noalloc: one array per device, allocated when
+// the library's code object is loaded and held until the process ends.
+// In host code `scratch` names a host-side stand-in; its device address is
+// taken once per device (hipGetSymbolAddress) and only that address is used.
+static constexpr size_t kScratchBytes = size_t(256) << 20;
+static constexpr size_t kScratchStatsBytes = align_up_c(REFINE_STAT_SLOTS * sizeof(double), 256);
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (taken on the first
+// call on that device).
+static int scratch_address(char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(POISSON_EUNSUPPORTED, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    char* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(POISSON_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
   }
-  return refine_end(p, rhs, st);
+  *out = g_scratch_dev[dev];
+  return POISSON_OK;
+}
+
+extern "C" size_t refined_noalloc_max_points(void) {
+  return (kScratchBytes - kScratchStatsBytes) / (sizeof(double) + sizeof(float));
+}
+
+// status_out[0] = FP32 solves run, [1] = 1 if converged else 0, [2] = last
+// relative update (device memory of the caller).
+__global__ void refine_report_kernel(const double* __restrict__ stats, int max_iters,
+                                     double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  int it = 1;
+  for (int sweep = 1; sweep < max_iters; ++sweep)
+    if (stats[4 + 2 * sweep] >= 0.0) ++it;
+  out[0] = (double)it;
+  out[1] = stats[2] != 0.0 ? 1.0 : 0.0;
+  out[2] = stats[3];
+}
+
+extern "C" int solve_refined_noalloc(poisson_plan* p, double* rhs, double tol, int max_iters,
+                                     double* status_out, hipStream_t st) {
+  if (!p || !rhs) return fail(POISSON_EINVAL, "null argument");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(POISSON_EINVAL, "tol must be finite and > 0");
+  if (max_iters < 1 || max_iters > REFINE_MAX_SWEEPS)
+    return fail(POISSON_EINVAL, "max_iters must be in [1, %d]", REFINE_MAX_SWEEPS);
+  const size_t N = field_points(p);
+  if (N > refined_noalloc_max_points())
+    return fail(POISSON_EUNSUPPORTED,
+                "grid of %zu points exceeds the no-allocation workspace (%zu points, %zu B)", N,
+                refined_noalloc_max_points(), kScratchBytes);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != p->device) return fail(POISSON_EINVAL, "plan lives on device %d, current is %d", p->device, dev);
+  char* base = nullptr;
+  if (int rc = scratch_address(&base)) return rc;
+  RefineWork W;
+  W.stats = reinterpret_cast<double*>(base);
+  W.f64 = reinterpret_cast<double*>(base + kScratchStatsBytes);
+  W.e32 = reinterpret_cast<float*>(base + kScratchStatsBytes + N * sizeof(double));
+  W.tol = tol;
+  W.max_iters = max_iters;
+  if (int rc = run_refined(p, W, rhs, st)) return rc;
+  if (status_out) {
+    hipLaunchKernelGGL(refine_report_kernel, dim3(1), dim3(64), 0, st, (const double*)W.stats,
+                       max_iters, status_out);
+    HIP_TRY(hipGetLastError());
+  }
+  return POISSON_OK;
 }
 
 // ------------------------------------------------------------------ batch
@@ -1293,7 +1401,7 @@ static int batch_upload(poisson_batch* b) {
     int fe = 0, fr = 0;
     for (size_t i = 0; i < b->plans.size(); ++i) {
       const poisson_plan* p = b->plans[i];
-      const RefineLaunch r = refine_launch(p);
+      const RefineLaunch r = refine_launch(p, p->stats);
       RefineJob& J = jobs[i];
       J.G = r.G;
       J.phi = b->rhs[i];

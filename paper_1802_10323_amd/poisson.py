@@ -58,6 +58,8 @@ SIGNATURES = {
                                     ctypes.POINTER(ctypes.c_longlong),
                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t)]),
     "server_destroy": (None, [_VP]),
+    "refined_noalloc_max_points": (ctypes.c_size_t, []),
+    "solve_refined_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP, _VP]),
 }
 
 _lib = None
@@ -152,6 +154,23 @@ class Plan:
         if tuple(field.shape) != self.shape and field.numel() != int(np.prod(self.shape)):
             raise ValueError(f"field shape {tuple(field.shape)} != {self.shape}")
         _check(lib().solve(self.handle, _field_ptr(field), _stream_handle(stream)))
+        return field
+
+    def solve_refined_noalloc(self, field, tol=1e-10, max_iters=4, status=None, stream=None):
+        """FP32 + FP64 refinement solve of ``field`` in place on the
+        library's static workspace (allocates nothing; see
+        ``solve_refined_noalloc`` in include/poisson.h).  ``status``: optional
+        device float64 tensor of 3 values, filled at the end of the stream
+        with (FP32 solves, converged 1/0, last relative update)."""
+        if field.numel() != int(np.prod(self.shape)):
+            raise ValueError(f"field shape {tuple(field.shape)} != {self.shape}")
+        sp = None
+        if status is not None:
+            if status.numel() < 3:
+                raise ValueError("status needs 3 values")
+            sp = _field_ptr(status)
+        _check(lib().solve_refined_noalloc(self.handle, _field_ptr(field), float(tol),
+                                           int(max_iters), sp, _stream_handle(stream)))
         return field
 
     def set_precision(self, mode, tol=1e-10, max_iters=4):
@@ -350,6 +369,11 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def refined_noalloc_max_points():
+    """Largest grid (points) that ``Plan.solve_refined_noalloc`` accepts."""
+    return int(lib().refined_noalloc_max_points())
 
 
 def tuned_variant(family, n, layout, fp64=True):
