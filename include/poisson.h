@@ -104,8 +104,10 @@ const char* last_error_message(void);
 /* Select the arithmetic of solve().  mode = POISSON_FP64 (default) or
  * POISSON_FP32_REFINED: transforms and elimination in FP32, then up to
  * max_iters refinement sweeps r = f - A Phi (FP64 seven-point residual),
- * e = FP32 solve of r, Phi += e (FP64), stopping once
- * ||e||_2 <= tol * ||Phi||_2 (both measured on the device).  tol > 0,
+ * e = FP32 solve of r, Phi += e (FP64), stopping once the error left after
+ * the update, estimated from the sweep's contraction rho (the ratio of
+ * successive relative updates ||e||_2 / ||Phi||_2, measured on the device)
+ * as (||e||/||Phi||) rho / (1 - rho), is below tol / 10.  tol > 0,
  * 1 <= max_iters <= 64.  Allocates the refinement workspace (FP64 copy of f,
  * FP32 correction field) on first use.  Not to be called while a solve with
  * this plan is in flight. */
@@ -231,13 +233,20 @@ int set_tuned_variant(int family, int n, int layout, int fp64, int variant);
  *
  * A server owns `slots` HIP streams and a worker thread.  Requests are queued
  * in arrival order; the request at the head is admitted as soon as a slot is
- * free and the HBM it holds while running (8 B per point for the field, plus
- * 12 B per point of refinement workspace for POISSON_FP32_REFINED) fits the
- * budget next to the requests already running, and its solve is enqueued on
- * that slot's stream at once, so it overlaps on the device with the solves in
- * flight.  Plans are cached by problem and reused (FP64 plans are shared by
- * concurrent requests; a refined plan serves one request at a time).  Each
- * result equals solve() of the same request on its own. */
+ * free and its HBM fits the budget next to what is already held, and its
+ * solve is enqueued on that slot's stream at once, so it overlaps on the
+ * device with the solves in flight.  HBM counted against the budget: the
+ * fields of the admitted requests (8 B per point) and everything the server
+ * holds on the device (refinement workspaces of the slots, 12 B per point of
+ * the largest refined request a slot has run plus a status block; cached
+ * plans' tables; memory waiting to be freed).  This stays within the budget
+ * whenever more than one request runs; a request that fits alone is admitted
+ * once the device is idle.  The server frees device memory (grown-out
+ * workspaces, evicted plans) only when no request is in flight, since a free
+ * waits for the whole device.  Plans are cached by problem geometry and
+ * shared by concurrent requests, FP64 and refined alike (a refined solve
+ * runs on its slot's workspace).  Each result equals solve() of the same
+ * request on its own. */
 typedef struct poisson_server poisson_server;
 
 typedef struct poisson_request_info {
@@ -252,31 +261,35 @@ typedef struct poisson_request_info {
 } poisson_request_info;
 
 /* slots: streams (1..64); hbm_budget: bytes (0 = 80 % of the device's free
- * memory now); max_plans: plans kept when idle (least recently used evicted).
- * A cached plan holds only its tables (a few values per grid line): refined
- * solves run on refinement workspace owned by their slot, grown to the
- * largest refined request the slot has run and freed by server_destroy, so
- * serving itself frees no device memory.  Uses the current device.  NULL on
- * error. */
+ * memory now); max_plans: plans kept in the cache (least recently used idle
+ * plans evicted beyond it).  Uses the current device.  NULL on error. */
 poisson_server* server_create(int slots, size_t hbm_budget, int max_plans);
 
 /* Queue one solve (arguments as plan_create, plus precision mode, tolerance and
  * sweep limit as plan_set_precision; field: DEVICE pointer, nx*ny*nz doubles,
  * solved in place, owned by the caller and kept alive until server_wait
- * returns for this request).  dz is copied.  Returns a request id >= 0, or a
- * negative error code (POISSON_EUNSUPPORTED if the request alone exceeds the
- * budget). */
+ * returns for this request).  producer: the stream on which the caller
+ * wrote the field (NULL = the legacy default stream); the solve runs after
+ * the work enqueued on it before this call.  dz is copied.  Returns a request
+ * id >= 0, or a negative error code (POISSON_EUNSUPPORTED if the request
+ * alone, field and refinement workspace, exceeds the budget). */
 long long server_submit(poisson_server* server, int nx, int ny, int nz, double dx, double dy,
                         const double* dz, int bc_x, int bc_y, int bc_z, int precision,
-                        double tol, int max_iters, double* field);
+                        double tol, int max_iters, double* field, hipStream_t producer);
 
 /* Block until request `id` has completed; fills *info (may be NULL) and
  * forgets the request.  Returns its status. */
 int server_wait(poisson_server* server, long long id, poisson_request_info* info);
 
-/* Plan-cache counters and the admission budget in bytes (any pointer may be NULL). */
+/* Plan-cache counters, plans resident (cached, and evicted ones not yet
+ * freed) and the admission budget in bytes (any pointer may be NULL). */
 int server_stats(poisson_server* server, long long* plan_hits, long long* plan_misses,
                  int* plans_resident, size_t* budget);
+
+/* Device bytes the server holds now (workspaces, plan tables, memory
+ * waiting to be freed) and the largest total of held bytes plus admitted
+ * fields seen at an admission (any pointer may be NULL). */
+int server_usage(poisson_server* server, size_t* held_bytes, size_t* peak_bytes);
 
 /* Finish every queued request, stop the worker, free the cached plans. */
 void server_destroy(poisson_server* server);

@@ -136,7 +136,7 @@ def solve(f, hx, hy, hz, bcx, bcy, bcz, roles=("x", "y", "z")):
     return g
 
 
-def solve_corrected(f, hx, hy, hz, bcx, bcy, bcz, roles=("x", "y", "z")):
+def solve_corrected(f, hx, hy, hz, bcx, bcy, bcz, roles=("x", "y", "z"), phi=None):
     """``solve`` followed by one correction with its own FP64 residual:
     Phi1 = solve(f), Phi = Phi1 + solve(f - A Phi1).
 
@@ -150,7 +150,9 @@ def solve_corrected(f, hx, hy, hz, bcx, bcy, bcz, roles=("x", "y", "z")):
     u (the correction itself carries the solve's relative error on a
     quantity 1e-13 times smaller).  The result is the plain definition of
     the solve (A Phi = f, gauge as in ``solve``) computed more exactly, for
-    comparisons at the largest sizes."""
-    phi = solve(f, hx, hy, hz, bcx, bcy, bcz, roles=roles)
+    comparisons at the largest sizes.  ``phi``: the plain solve of the same
+    problem (with the same roles), if already computed."""
+    if phi is None:
+        phi = solve(f, hx, hy, hz, bcx, bcy, bcz, roles=roles)
     r = residual(f, phi, hx, hy, hz, bcx, bcy, bcz)
     return phi + solve(r, hx, hy, hz, bcx, bcy, bcz, roles=roles)

@@ -1,17 +1,39 @@
 """Measurements of the solver's further forms for the benchmark report
-(each separate from the headline FP64 number):
+(each separate from the headline FP64 number), each with its relative L2
+error against the FP64 oracle on the same seeded input (the oracle runs on
+the host; it is the test reference, timed nowhere here):
 
-* mixed  - 512^3 (DD, ND, P) cube: FP32 transforms/elimination + FP64
-           refinement to 1e-10 against plain FP64 on the same shape.
-* batch  - 64 uneven instances (sizes per axis from {64, 96, 128, 192, 256},
-           random boundary pairs, half the walled z axes stretched) in one
-           batched launch sequence against one solve at a time.
-* serve  - continuous-batching server fed by Poisson arrivals at 80 % of its
-           measured capacity: p50 / p99 latency and points/s.
+* mixed   - 512^3 (DD, ND, P) cube: FP32 transforms (elimination
+            recurrences in FP64 on FP32 data) + FP64 residual/update,
+            refined to 1e-10, against plain FP64 on the same shape.
+* channel - 512 x 256 x 192 channel (P, P, NN; tanh z), FP64.
+* small   - 32^3 (P, P, NN), FP64: a latency-bound solve; host round-trip
+            latency p50/p99 over 2000 solves and device time per solve.
+* batch   - 64 uneven instances (sizes per axis from {64, 96, 128, 192,
+            256}, random boundary pairs, half the walled z axes stretched) in
+            one batched launch sequence against one solve at a time.
+* serve   - continuous-batching server fed by Poisson arrivals at 80 % of
+            its measured capacity: p50 / p99 latency and points/s, for 2, 4
+            and 8 slots.
 """
+import threading
 import time
 
 import numpy as np
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _oracle_pair(prob, refs=None, key=None):
+    """(plain, corrected) oracle solutions of prob, from refs[key] if there."""
+    import oracle
+    if refs is not None and key in refs:
+        return refs[key]
+    args = (prob.rhs, prob.hx, prob.hy, prob.hz, *prob.bcs)
+    plain = oracle.solve(*args)
+    return plain, oracle.solve_corrected(*args, phi=plain)
 
 
 def _timed(fn, reps, torch):
@@ -26,7 +48,7 @@ def _timed(fn, reps, torch):
     return [a.elapsed_time(b) for a, b in evs]
 
 
-def mixed(log, steps=6, warmup=2):
+def mixed(log, refs=None, with_oracle=True, steps=6, warmup=2):
     import torch
     from . import FP32_REFINED, Plan, inputs
     prob = inputs.cube(0)
@@ -52,19 +74,119 @@ def mixed(log, steps=6, warmup=2):
     torch.cuda.synchronize()
     iters, upd, conv = p32.status()
     rel = float(torch.linalg.norm(work - ref) / torch.linalg.norm(ref))
+    out = {"workload": "cube 512^3 (DD,ND,P)", "points": N,
+           "arithmetic": "FP32 transforms, FP64 elimination recurrences on FP32 data, "
+                         "FP64 residual/update/gauge",
+           "fp64_ms": round(t64, 4), "fp64_points_per_s": N / (t64 * 1e-3),
+           "mixed_ms": round(t32, 4), "mixed_points_per_s": N / (t32 * 1e-3),
+           "speedup_vs_fp64": round(t64 / t32, 4), "fp32_solves": iters,
+           "converged": bool(conv), "last_update_rel": upd,
+           "rel_l2_vs_gpu_fp64": rel, "tolerance": 1e-10}
+    if with_oracle:
+        plain, corrected = _oracle_pair(prob, refs, "cube")
+        got = work.cpu().numpy()
+        out["rel_l2_vs_oracle"] = _rel(got, plain)
+        out["rel_l2_vs_oracle_corrected"] = _rel(got, corrected)
+        out["fp64_rel_l2_vs_oracle_corrected"] = _rel(ref.cpu().numpy(), corrected)
     log(f"[forms] mixed 512^3: fp64 {t64:.3f} ms, fp32+refine {t32:.3f} ms ({iters} FP32 solves), "
-        f"rel-L2 vs FP64 {rel:.2e}")
+        f"rel-L2 vs FP64 {rel:.2e}, vs oracle {out.get('rel_l2_vs_oracle_corrected', float('nan')):.2e}")
     p64.close()
     p32.close()
-    return {"workload": "cube 512^3 (DD,ND,P)", "points": N,
-            "fp64_ms": round(t64, 4), "fp64_points_per_s": N / (t64 * 1e-3),
-            "mixed_ms": round(t32, 4), "mixed_points_per_s": N / (t32 * 1e-3),
-            "speedup_vs_fp64": round(t64 / t32, 4), "fp32_solves": iters,
-            "converged": bool(conv), "last_update_rel": upd,
-            "rel_l2_vs_gpu_fp64": rel, "tolerance": 1e-10}
+    return out
 
 
-def batch(log, count=64, steps=5, warmup=2, seed=0):
+def channel(log, refs=None, with_oracle=True, steps=20, warmup=3):
+    """The 512 x 256 x 192 channel (P, P, NN; z tanh-stretched), FP64."""
+    import torch
+    from . import Plan, inputs
+    prob = inputs.channel(0)
+    N = prob.points
+    src = torch.from_numpy(prob.rhs).cuda()
+    work = torch.empty_like(src)
+    plan = Plan.from_problem(prob)
+
+    def run():
+        work.copy_(src)
+        plan.solve(work)
+
+    for _ in range(warmup):
+        run()
+    copy_ms = float(np.median(_timed(lambda: work.copy_(src), steps, torch)))
+    t = float(np.median(_timed(run, steps, torch))) - copy_ms
+    run()
+    torch.cuda.synchronize()
+    out = {"workload": "channel 512x256x192 (P,P,NN; tanh z beta 1.8; Lx=4pi Ly=2pi Lz=2)",
+           "points": N, "ms": round(t, 4), "points_per_s": N / (t * 1e-3),
+           "hbm_effective_frac": round(80.0 * N / (t * 1e-3) / 8e12, 4),
+           "note": "the FP64 field (201 MB) fits in the 256 MB Infinity Cache: part of each "
+                   "sweep's traffic may be served there, not by HBM"}
+    if with_oracle:
+        plain, corrected = _oracle_pair(prob, refs, "channel")
+        got = work.cpu().numpy()
+        out["rel_l2_vs_oracle"] = _rel(got, plain)
+        out["rel_l2_vs_oracle_corrected"] = _rel(got, corrected)
+    plan.close()
+    log(f"[forms] channel: {t:.4f} ms, {N / (t * 1e-3):.3e} points/s, rel-L2 vs oracle "
+        f"{out.get('rel_l2_vs_oracle', float('nan')):.2e}")
+    return out
+
+
+def small(log, refs=None, with_oracle=True, count=2000, warmup=200):
+    """32^3 (P, P, NN), FP64, latency-bound: per solve, the host round trip
+    (enqueue the solve, wait for the stream) and the device time between
+    events around it; the field is refilled (untimed) before each solve."""
+    import torch
+    from . import Plan, inputs
+    prob = inputs.small(0)
+    N = prob.points
+    src = torch.from_numpy(prob.rhs).cuda()
+    work = torch.empty_like(src)
+    plan = Plan.from_problem(prob)
+    stream = torch.cuda.current_stream()
+    host_us, dev_us = [], []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for i in range(warmup + count):
+        work.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        plan.solve(work)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if i >= warmup:
+            host_us.append((t1 - t0) * 1e6)
+            dev_us.append(e0.elapsed_time(e1) * 1e3)
+    # throughput: solves enqueued back to back (each on its own refilled copy)
+    bufs = [src.clone() for _ in range(64)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in bufs:
+        plan.solve(b)
+    torch.cuda.synchronize()
+    back_to_back_us = (time.perf_counter() - t0) / len(bufs) * 1e6
+    host_us, dev_us = np.array(host_us), np.array(dev_us)
+    out = {"workload": "small 32^3 (P,P,NN; uniform, unit box)", "points": N, "solves": count,
+           "latency_p50_us": float(np.percentile(host_us, 50)),
+           "latency_p99_us": float(np.percentile(host_us, 99)),
+           "device_p50_us": float(np.percentile(dev_us, 50)),
+           "device_p99_us": float(np.percentile(dev_us, 99)),
+           "back_to_back_us_per_solve": back_to_back_us,
+           "points_per_s_latency": N / (np.percentile(host_us, 50) * 1e-6),
+           "points_per_s_back_to_back": N / (back_to_back_us * 1e-6)}
+    if with_oracle:
+        plain, corrected = _oracle_pair(prob)
+        got = bufs[0].cpu().numpy()
+        out["rel_l2_vs_oracle"] = _rel(got, plain)
+        out["rel_l2_vs_oracle_corrected"] = _rel(got, corrected)
+    plan.close()
+    log(f"[forms] small 32^3: latency p50 {out['latency_p50_us']:.1f} us, p99 "
+        f"{out['latency_p99_us']:.1f} us (device {out['device_p50_us']:.1f} us), back to back "
+        f"{back_to_back_us:.1f} us/solve")
+    return out
+
+
+def batch(log, refs=None, with_oracle=True, count=64, steps=5, warmup=2, seed=0, checked=4):
     """64 uneven instances: one solve() per instance in turn, against the
     batched form (one persistent launch per stage) enqueued directly and as
     a replayed HIP graph.  Every form solves the same fields."""
@@ -147,6 +269,13 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
         f"variants {ms['graph_table']:.3f} ms, graph tuned as a batch {ms['graph_tuned']:.3f} ms; "
         f"max relative difference to single solves {diff:.1e}")
     fp64_ref = results["single_tuned"]
+    # oracle check of the `checked` smallest of the instances kept above
+    check_ids = sorted(range(len(results["graph_tuned"])), key=lambda i: probs[i].points)[:checked]
+    oracle_rel = {}
+    if with_oracle:
+        for i in check_ids:
+            plain, corrected = _oracle_pair(probs[i])
+            oracle_rel[i] = (plain, corrected)
     B.close()
     # the same instances in FP32 + refinement to 1e-10: one refined solve at
     # a time against the refined batch (each FP32 solve batched) as a graph
@@ -161,6 +290,8 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
     err32 = max(float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
                 for a, b in zip(results["graph_fp32"], fp64_ref))
     solves = [pl.status()[0] for pl in plans]
+    rel64 = {i: _rel(results["graph_tuned"][i].cpu().numpy(), oracle_rel[i][1]) for i in oracle_rel}
+    rel32 = {i: _rel(results["graph_fp32"][i].cpu().numpy(), oracle_rel[i][1]) for i in oracle_rel}
     log(f"[forms] batch FP32 + refinement: one by one {ms['single_fp32']:.3f} ms, graph "
         f"{ms['graph_fp32']:.3f} ms ({min(solves)}-{max(solves)} FP32 solves per instance); "
         f"max relative difference to refined single solves {diff32:.1e}, to FP64 {err32:.1e}")
@@ -181,111 +312,186 @@ def batch(log, count=64, steps=5, warmup=2, seed=0):
             "tuned_variants": chosen,
             "batch_step_choice": batch_choice,
             "max_rel_diff_vs_single": diff,
+            "rel_l2_vs_oracle_corrected": {f"instance {i} {probs[i].nx}x{probs[i].ny}x{probs[i].nz} "
+                                           f"{','.join(probs[i].bcs)}": v for i, v in rel64.items()},
             "fp32_refined": {"single_ms": round(ms["single_fp32"], 4),
                              "graph_ms": round(ms["graph_fp32"], 4),
                              "graph_points_per_s": points / (ms["graph_fp32"] * 1e-3),
                              "speedup_vs_single": round(ms["single_fp32"] / ms["graph_fp32"], 4),
                              "fp32_solves": [min(solves), max(solves)],
                              "max_rel_diff_vs_single": diff32,
-                             "max_rel_l2_vs_fp64": err32, "tolerance": 1e-10}}
+                             "max_rel_l2_vs_fp64": err32, "tolerance": 1e-10,
+                             "rel_l2_vs_oracle_corrected": {f"instance {i}": v for i, v in rel32.items()}}}
 
 
-def serve(log, count=400, warmup=50, seed=0, slots=8, load=0.8, sample=12):
-    """Served stream: per request, per-axis n log-uniform in [32, 512]
-    (snapped to even 2^a 3^b 5^c), random boundary pairs, z stretched with
-    probability 1/2 when walled, FP64 or FP32 + refinement (tol 1e-10) with
-    probability 1/2.  Fields are filled on the device from a seeded
-    generator.  Capacity = requests/s of a closed-loop run (all requests
-    queued at once); then Poisson arrivals at `load` x capacity, latency =
-    completion - submission per request."""
+def _serve_once(log, specs, order, slots, load, seed, window):
+    """One server with `slots` streams: warm-up (every spec of the catalogue
+    once, so every plan is cached), a closed loop over the timed requests
+    (at most `window` outstanding) for the capacity, then the same requests
+    as Poisson arrivals at `load` x capacity.  Each request's field is
+    written (seeded uniform values) on the caller's stream just before it is
+    submitted, and released when it completes."""
     import torch
-    from . import FP32_REFINED, FP64, Plan, Server, inputs
-    specs = [inputs.served_request(seed, i, with_rhs=False) for i in range(warmup + count)]
+    from . import FP32_REFINED, FP64, Server
     gen = torch.Generator(device="cuda")
-    fields = [torch.empty(sp.points, dtype=torch.float64, device="cuda") for sp in specs]
-
-    def refill():
-        gen.manual_seed(seed)
-        for f in fields:
-            f.uniform_(-1.0, 1.0, generator=gen)
-        torch.cuda.synchronize()
-
+    gen.manual_seed(seed)
     srv = Server(slots=slots)
 
-    def submit(i):
-        sp = specs[i]
-        return srv.submit(sp, fields[i], FP32_REFINED if sp.mixed else FP64, 1e-10, 6)
+    def submit(k, fields):
+        sp = specs[k]
+        f = torch.empty(sp.points, dtype=torch.float64, device="cuda")
+        f.uniform_(-1.0, 1.0, generator=gen)
+        rid = srv.submit(sp, f, FP32_REFINED if sp.mixed else FP64, 1e-10, 6)
+        fields[rid] = f
+        return rid
 
-    refill()
-    for rid in [submit(i) for i in range(warmup)]:
+    fields = {}
+    warm = [submit(k, fields) for k in range(len(specs))]
+    for rid in warm:
         srv.wait(rid)
-    timed = list(range(warmup, warmup + count))
-    points = sum(specs[i].points for i in timed)
+        fields.pop(rid)
+    st0 = srv.stats()
+    points = sum(specs[k].points for k in order)
+    count = len(order)
 
-    # closed loop: everything queued at once
-    refill()
+    # closed loop: `window` requests outstanding
     t0 = time.perf_counter()
-    infos = [srv.wait(r) for r in [submit(i) for i in timed]]
+    pending = []
+    infos = []
+    for k in order:
+        if len(pending) >= window:
+            rid = pending.pop(0)
+            infos.append(srv.wait(rid))
+            fields.pop(rid)
+        pending.append(submit(k, fields))
+    for rid in pending:
+        infos.append(srv.wait(rid))
+        fields.pop(rid)
     closed_s = time.perf_counter() - t0
     capacity = count / closed_s
     bad = sum(1 for x in infos if x["status"] != 0)
 
-    # open loop: Poisson arrivals at load x capacity
-    refill()
+    # open loop: Poisson arrivals; a second thread waits for completions
     rng = np.random.default_rng(seed + 1)
     arrivals = np.cumsum(rng.exponential(1.0 / (load * capacity), count))
-    keep = set(timed[:: max(1, count // sample)])
-    saved = {i: fields[i].clone() for i in keep}
-    torch.cuda.synchronize()
     ids = []
-    t0 = time.perf_counter()
-    for k, i in enumerate(timed):
-        while time.perf_counter() - t0 < arrivals[k]:
-            pass
-        ids.append(submit(i))
-    infos = [srv.wait(r) for r in ids]
-    lat = np.array([x["done_s"] - x["submit_s"] for x in infos]) * 1e3
-    queue = np.array([x["start_s"] - x["submit_s"] for x in infos]) * 1e3
-    span = max(x["done_s"] for x in infos) - min(x["submit_s"] for x in infos)
-    bad += sum(1 for x in infos if x["status"] != 0)
-    stats = srv.stats()
-    srv.close()
+    done = []
+    lock = threading.Lock()
+    ready = threading.Semaphore(0)
 
-    # the same requests alone (fresh plan, default stream)
-    same = True
-    for i in sorted(keep):
-        sp = specs[i]
-        plan = Plan.from_problem(sp)
-        if sp.mixed:
-            plan.set_precision(FP32_REFINED, 1e-10, 6)
-        plan.solve(saved[i])
-        torch.cuda.synchronize()
-        same = same and bool(torch.equal(saved[i], fields[i]))
-        plan.close()
-    out = {"workload": "served stream, per-axis n log-uniform [32, 512], random BC pairs, "
-                       "FP64 or FP32+IR (1e-10) with p = 1/2",
-           "requests": count, "warmup": warmup, "slots": slots, "points": points,
-           "closed_loop_req_per_s": capacity,
-           "closed_loop_points_per_s": points / closed_s,
+    def waiter():
+        for _ in range(count):
+            ready.acquire()
+            with lock:
+                rid = ids[len(done)]
+            info = srv.wait(rid)
+            with lock:
+                done.append(info)
+                fields.pop(rid, None)
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for a, k in zip(arrivals, order):
+        while time.perf_counter() - t0 < a:
+            pass
+        rid = submit(k, fields)
+        with lock:
+            ids.append(rid)
+        ready.release()
+    th.join()
+    lat = np.array([x["done_s"] - x["submit_s"] for x in done]) * 1e3
+    queue = np.array([x["start_s"] - x["submit_s"] for x in done]) * 1e3
+    span = max(x["done_s"] for x in done) - min(x["submit_s"] for x in done)
+    bad += sum(1 for x in done if x["status"] != 0)
+    st1 = srv.stats()
+    use = srv.usage()
+    srv.close()
+    out = {"slots": slots, "requests": count, "warmup": len(specs), "points": points,
+           "closed_loop_window": window,
+           "closed_loop_req_per_s": capacity, "closed_loop_points_per_s": points / closed_s,
            "arrival_rate_req_per_s": load * capacity,
+           "achieved_req_per_s": count / span, "achieved_load": count / span / capacity,
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-           "mean_queue_ms": float(queue.mean()),
-           "open_loop_points_per_s": points / span,
-           "failed": bad, "plan_cache": stats,
-           "sampled_equal_to_solo": same, "sampled": len(keep)}
-    log(f"[forms] serve: capacity {capacity:.1f} req/s ({points / closed_s:.3e} points/s closed "
-        f"loop); at {load:.0%}: p50 {out['p50_ms']:.3f} ms, p99 {out['p99_ms']:.3f} ms, "
-        f"{out['open_loop_points_per_s']:.3e} points/s; {len(keep)} sampled results equal "
-        f"to solo solves: {same}")
+           "mean_queue_ms": float(queue.mean()), "open_loop_points_per_s": points / span,
+           "failed": bad,
+           "plan_misses_warmup": st0["plan_misses"],
+           "plan_misses_timed": st1["plan_misses"] - st0["plan_misses"],
+           "plans_resident": st1["plans_resident"], "hbm_budget": st1["hbm_budget"],
+           "server_peak_bytes": use["peak_bytes"]}
+    log(f"[forms] serve, {slots} slots: capacity {capacity:.1f} req/s ({points / closed_s:.3e} "
+        f"points/s); at {out['achieved_load']:.0%} of it: p50 {out['p50_ms']:.3f} ms, p99 "
+        f"{out['p99_ms']:.3f} ms; plan misses {out['plan_misses_warmup']} warm-up, "
+        f"{out['plan_misses_timed']} timed")
     return out
 
 
-def run(wanted, log):
+def serve(log, refs=None, with_oracle=True, count=2000, catalogue=200, seed=0,
+          slot_counts=(2, 4, 8), load=0.8, sample=8):
+    """Served stream: a catalogue of `catalogue` request kinds (per-axis n
+    log-uniform in [32, 512] snapped to even 2^a 3^b 5^c, random boundary
+    pairs, z stretched with probability 1/2 when walled, FP64 or FP32 +
+    refinement to 1e-10 with probability 1/2); `count` timed requests drawn
+    from it at random after a warm-up of one request per kind.  Measured for
+    each slot count.  Then `sample` small requests with host-generated
+    fields are served in the middle of a burst of others and compared with
+    the oracle and with solo solves."""
+    import torch
+    from . import FP32_REFINED, FP64, Plan, Server, inputs
+    specs = [inputs.served_request(seed, i, with_rhs=False) for i in range(catalogue)]
+    order = np.random.default_rng(seed + 7).integers(0, catalogue, count).tolist()
+    runs = [_serve_once(log, specs, order, s, load, seed, window=2 * s) for s in slot_counts]
+
+    # correctness: sampled requests (host fields) inside a burst of others
+    small_specs = [i for i in range(catalogue) if specs[i].points <= 400_000][:sample]
+    probs = [inputs.served_request(seed, i) for i in small_specs]
+    srv = Server(slots=max(slot_counts))
+    burst = []
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed + 3)
+    for k in range(16):
+        sp = specs[order[k]]
+        f = torch.empty(sp.points, dtype=torch.float64, device="cuda").uniform_(-1, 1, generator=gen)
+        burst.append((srv.submit(sp, f, FP32_REFINED if sp.mixed else FP64, 1e-10, 6), f))
+    fields = [torch.from_numpy(p.rhs).cuda() for p in probs]
+    ids = [srv.submit(p, f, FP32_REFINED if p.mixed else FP64, 1e-10, 6)
+           for p, f in zip(probs, fields)]
+    for rid, _ in burst:
+        srv.wait(rid)
+    infos = [srv.wait(r) for r in ids]
+    srv.close()
+    same, rel_max = True, {"fp64": 0.0, "fp32_refined": 0.0}
+    for p, f, info in zip(probs, fields, infos):
+        got = f.cpu().numpy()
+        plan = Plan.from_problem(p)
+        if p.mixed:
+            plan.set_precision(FP32_REFINED, 1e-10, 6)
+        solo = torch.from_numpy(p.rhs).cuda()
+        plan.solve(solo)
+        torch.cuda.synchronize()
+        same = same and np.array_equal(solo.cpu().numpy(), got) and info["status"] == 0
+        plan.close()
+        if with_oracle:
+            _, corrected = _oracle_pair(p)
+            key = "fp32_refined" if p.mixed else "fp64"
+            rel_max[key] = max(rel_max[key], _rel(got, corrected))
+    out = {"workload": f"served stream, {catalogue} request kinds (per-axis n log-uniform "
+                       "[32, 512], random BC pairs, FP64 or FP32+IR (1e-10) with p = 1/2), "
+                       f"{count} timed requests drawn from them after one warm-up request "
+                       "per kind; each field written on the caller's stream just before "
+                       "submission",
+           "runs": runs, "sampled": len(probs), "sampled_equal_to_solo": bool(same)}
+    if with_oracle:
+        out["sampled_max_rel_l2_vs_oracle_corrected"] = rel_max
+    log(f"[forms] serve: {len(probs)} sampled requests equal to solo solves: {same}; "
+        f"max rel-L2 vs oracle {rel_max}")
+    return out
+
+
+def run(wanted, log, refs=None, with_oracle=True):
     out = {}
-    if "mixed" in wanted:
-        out["mixed"] = mixed(log)
-    if "batch" in wanted:
-        out["batch"] = batch(log)
-    if "serve" in wanted:
-        out["serve"] = serve(log)
+    for name, fn in (("mixed", mixed), ("channel", channel), ("small", small),
+                     ("batch", batch), ("serve", serve)):
+        if name in wanted:
+            out[name] = fn(log, refs, with_oracle)
     return out

@@ -949,19 +949,22 @@ extern "C" int solve(poisson_plan* p, double* rhs, hipStream_t st) {
   return solve_typed<double>(p, rhs, st);
 }
 
+// Status of a refined solve from its status block, copied to host memory at
+// the end of its stream: the FP32 solves run (sweeps that ran have
+// ||e||^2 >= 0), the last relative update, and whether it converged.
+static bool refine_status_decode(const double* h, int max_iters, int* iters, double* rel) {
+  int it = 1;
+  for (int sweep = 1; sweep < max_iters; ++sweep)
+    if (h[4 + 2 * sweep] >= 0.0) ++it;
+  *iters = it;
+  *rel = h[3];
+  return h[2] != 0.0;
+}
+
 extern "C" int solve_status(poisson_plan* p, int* iters, double* rel) {
   if (!p) return fail(POISSON_EINVAL, "null plan");
-  if (p->mode == POISSON_FP32_REFINED && p->stats_host) {
-    // the refined solve copies its status block to pinned host memory at the
-    // end of its stream: sweeps that ran have ||e||^2 >= 0
-    const double* h = p->stats_host;
-    int it = 1;
-    for (int sweep = 1; sweep < p->max_iters; ++sweep)
-      if (h[4 + 2 * sweep] >= 0.0) ++it;
-    p->last_iters = it;
-    p->last_rel = h[3];
-    p->last_converged = h[2] != 0.0;
-  }
+  if (p->mode == POISSON_FP32_REFINED && p->stats_host)
+    p->last_converged = refine_status_decode(p->stats_host, p->max_iters, &p->last_iters, &p->last_rel);
   if (iters) *iters = p->last_iters;
   if (rel) *rel = p->last_rel;
   return p->last_converged ? POISSON_OK : POISSON_ENOTCONVERGED;

@@ -52,11 +52,13 @@ SIGNATURES = {
                                           ctypes.c_double, ctypes.c_double,
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                           ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                          ctypes.c_double, ctypes.c_int, _VP]),
+                                          ctypes.c_double, ctypes.c_int, _VP, _VP]),
     "server_wait": (ctypes.c_int, [_VP, ctypes.c_longlong, _VP]),
     "server_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_longlong),
                                     ctypes.POINTER(ctypes.c_longlong),
                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t)]),
+    "server_usage": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t),
+                                    ctypes.POINTER(ctypes.c_size_t)]),
     "server_destroy": (None, [_VP]),
     "refined_noalloc_max_points": (ctypes.c_size_t, []),
     "solve_refined_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP, _VP]),
@@ -322,10 +324,12 @@ class Server:
         self._h = ctypes.c_void_p(h)
         self._fields = {}
 
-    def submit(self, problem, field, precision=FP64, tol=1e-10, max_iters=4):
+    def submit(self, problem, field, precision=FP64, tol=1e-10, max_iters=4, stream=None):
         """Queue the solve of ``problem`` (an inputs.Problem or anything with
-        nx, ny, nz, dx, dy, hz, bcs) on ``field`` (device float64, contiguous);
-        returns the request id."""
+        nx, ny, nz, dx, dy, hz, bcs) on ``field`` (device float64, contiguous),
+        after the work already enqueued on ``stream`` (default: torch's
+        current stream, where the field was written); returns the request
+        id."""
         dz = np.ascontiguousarray(np.asarray(problem.hz, dtype=np.float64))
         if field.numel() != problem.nx * problem.ny * problem.nz:
             raise ValueError("field size does not match the problem")
@@ -334,7 +338,7 @@ class Server:
                                   float(problem.dx), float(problem.dy),
                                   dz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), *codes,
                                   int(precision), float(tol), int(max_iters),
-                                  _field_ptr(field))
+                                  _field_ptr(field), _stream_handle(stream))
         if rid < 0:
             _check(int(rid))
         self._fields[rid] = field
@@ -357,6 +361,13 @@ class Server:
                                   ctypes.byref(resident), ctypes.byref(budget)))
         return {"plan_hits": hits.value, "plan_misses": misses.value,
                 "plans_resident": resident.value, "hbm_budget": budget.value}
+
+    def usage(self):
+        """Device bytes the server holds now and the peak of held bytes plus
+        admitted fields."""
+        held, peak = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        _check(lib().server_usage(self._h, ctypes.byref(held), ctypes.byref(peak)))
+        return {"held_bytes": held.value, "peak_bytes": peak.value}
 
     def close(self):
         if getattr(self, "_h", None) is not None:

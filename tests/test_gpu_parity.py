@@ -366,6 +366,18 @@ def _solo(prob, field):
     return out, st
 
 
+def _solo_prec(prob, field, precision):
+    from paper_1802_10323_amd import FP32_REFINED, Plan
+    plan = Plan.from_problem(prob)
+    if precision == FP32_REFINED:
+        plan.set_precision(FP32_REFINED, 1e-10, 6)
+    plan.solve(field)
+    out = to_host(field)
+    st = plan.status()
+    plan.close()
+    return out, st
+
+
 def test_server_results_equal_solo_solves():
     """Requests of mixed sizes, boundary pairs and precisions submitted at
     once run concurrently on the server's streams; each result equals the
@@ -400,24 +412,43 @@ def test_server_results_equal_solo_solves():
 
 
 def test_server_admission_by_hbm_budget():
-    """With a budget that holds only the largest request, the HBM held by
-    the requests in flight never exceeds the budget (admission waits), the
+    """With a budget that holds only the largest request (field plus
+    refinement workspace), the fields admitted plus everything the server
+    holds on the device never exceed the budget (admission waits), the
+    device memory the server takes (hipMemGetInfo) stays within it, the
     results equal the solo ones, and a request larger than the budget is
     refused."""
+    import torch
     from paper_1802_10323_amd import FP32_REFINED, FP64, PoissonError, Server
-    probs = [inputs.served_request(6, i, lo=32, hi=96) for i in range(6)]
-    foot = [8 * p.points + (12 * p.points if p.mixed else 0) for p in probs]
-    need = max(foot)
-    srv = Server(slots=4, hbm_budget=need)
+    probs = [inputs.served_request(6, i, lo=32, hi=96) for i in range(8)]
+    for k in (1, 4):
+        probs[k].mixed = True     # several refined requests: slot workspaces count
+    work = [8 * p.points + ((12 * p.points + 8 * 2200) if p.mixed else 0) for p in probs]
+    need = max(work) + 16 * 1024 * 1024      # + cached plans' tables
     src = [to_dev(p.rhs) for p in probs]
     fields = [f.clone() for f in src]
+    srv = Server(slots=4, hbm_budget=need)
+    # the runtime's own set-up of the server's streams is not the server's
+    # memory: one tiny FP64 request on every slot first
+    tiny = inputs.make_uniform(8, 8, 8, ("P", "P", "DD"), seed=2)
+    warm = [to_dev(tiny.rhs) for _ in range(4)]
+    for rid in [srv.submit(tiny, w) for w in warm]:
+        srv.wait(rid)
+    torch.cuda.synchronize()
+    held0 = srv.usage()["held_bytes"]
+    free0, _ = torch.cuda.mem_get_info()
     ids = [srv.submit(p, f, FP32_REFINED if p.mixed else FP64, 1e-10, 6)
            for p, f in zip(probs, fields)]
     infos = [srv.wait(i) for i in ids]
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    use = srv.usage()
+    say("budget", need, "usage", use, "device memory taken", free0 - free1)
+    assert use["peak_bytes"] <= need
+    assert 0 < use["held_bytes"] <= need
+    assert free0 - free1 <= need - held0
     for x in infos:
-        t = x["start_s"]     # HBM held at each admission: requests started and not yet done
-        held = sum(fp for y, fp in zip(infos, foot) if y["start_s"] <= t < y["done_s"])
-        assert held <= need, (held, need)
+        assert x["status"] == 0, x
     for p, f, s in zip(probs, fields, src):
         solo, _ = _solo(p, s.clone())
         assert np.array_equal(to_host(f), solo)
@@ -425,6 +456,37 @@ def test_server_admission_by_hbm_budget():
     if 8 * big.points > need:
         with pytest.raises(PoissonError):
             srv.submit(big, to_dev(big.rhs))
+    srv.close()
+
+
+def test_server_orders_solve_after_producer_stream():
+    """A cache-hit request submitted right after an asynchronous fill of its
+    field on the caller's stream (behind a long fill of another large
+    buffer): the solve waits for the fill (the server's streams wait for an
+    event recorded on the producer stream at submission), so the result is
+    the solo one, bit for bit; also for a refined request."""
+    import torch
+    from paper_1802_10323_amd import FP32_REFINED, FP64, Server
+    srv = Server(slots=4)
+    big = torch.empty(1 << 28, dtype=torch.float64, device="cuda")     # 2 GiB
+    cases = (((192, 160, 128), ("P", "P", "NN"), FP64),
+             ((128, 96, 160), ("DD", "ND", "P"), FP32_REFINED))
+    for k, (shape, bcs, prec) in enumerate(cases):
+        prob = inputs.make_uniform(*shape, bcs, seed=40 + k)
+        src = to_dev(prob.rhs)
+        warm = src.clone()
+        srv.wait(srv.submit(prob, warm, prec, 1e-10, 6))        # caches the plan
+        solo, _ = _solo_prec(prob, src.clone(), prec)
+        for _ in range(3):
+            field = torch.zeros_like(src)
+            torch.cuda.synchronize()
+            big.uniform_(-1.0, 1.0)          # keeps the current stream busy
+            field.copy_(src)                 # the request's input, written after it
+            rid = srv.submit(prob, field, prec, 1e-10, 6)
+            info = srv.wait(rid)
+            assert info["plan_cached"] == 1 and info["status"] == 0, info
+            assert np.array_equal(to_host(field), solo), (shape, bcs)
+    del big
     srv.close()
 
 
