@@ -31,6 +31,12 @@ hipError_t async_transform_launch(const R2RFastArgs<float>& a, int M, int shape,
 hipError_t async_elimination_launch(const TriFastArgs<double>& a, int n, hipStream_t stream);
 hipError_t async_elimination_launch(const TriFastArgs<float>& a, int n, hipStream_t stream);
 
+// The register-staged transform (FP64, length 512, strided axes, 32 lines
+// per tile; r2r_async_wide.hip), arguments as for r2r_fast_kernel with
+// RegStageCfg.  hipErrorInvalidValue for a contiguous axis.
+hipError_t regstage_launch(const R2RFastArgs<double>& a, int kind, int inverse,
+                           hipStream_t stream);
+
 // The kernels of AsyncBudget<double, FastVar<256, 0>, kind>::WIDE
 // (r2r_async_wide.hip).
 hipError_t async_wide_launch(const R2RFastArgs<double>& a, int kind, int inverse,

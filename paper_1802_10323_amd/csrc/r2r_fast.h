@@ -478,7 +478,7 @@ __device__ __noinline__ void post_store_call(lptr<const T> lds, lptr<const cplx<
 // whose inverse FFT interleaves the even and odd output points; written
 // into the tile (column ln, pairs k = qq + s QT) from the input points of
 // the line, point(p) (tile row r holds point r, D-D: point n-1-r).
-template <typename T, typename C, typename Point>
+template <typename T, typename C, bool SYNC = false, typename Point>
 __device__ __forceinline__ void combine_to_tile(Point point, lptr<T> lds,
                                                 lptr<const cplx<T>> split,
                                                 lptr<const cplx<T>> quarter, int kind, int ln,
@@ -508,6 +508,7 @@ __device__ __forceinline__ void combine_to_tile(Point point, lptr<T> lds,
       }
     }
   }
+  if constexpr (SYNC) lds_barrier();   // the points are read from the tile itself
 #pragma unroll
   for (int s = 0; s < SP; ++s) {
     const int k = qq + s * QT;
@@ -540,7 +541,7 @@ __device__ __forceinline__ void combine_to_tile(Point point, lptr<T> lds,
 // sequence (tile rows 2j and 2j+1: input points 2j and n-1-2j for N-D, the
 // mirrored points n-1-2j and 2j for D-N) times the pre-twiddle, into the
 // tile (column ln, j = qq + s QT).
-template <typename T, typename C, typename Point>
+template <typename T, typename C, bool SYNC = false, typename Point>
 __device__ __forceinline__ void pre_to_tile(Point point, lptr<T> lds, lptr<const cplx<T>> pre,
                                             int kind, int ln, int qq) {
   using L = FastLayout<T, C>;
@@ -552,6 +553,7 @@ __device__ __forceinline__ void pre_to_tile(Point point, lptr<T> lds, lptr<const
     v[s][0] = point(kind == K_ND ? 2 * j : N - 1 - 2 * j);
     v[s][1] = point(kind == K_ND ? N - 1 - 2 * j : 2 * j);
   }
+  if constexpr (SYNC) lds_barrier();   // the points are read from the tile itself
 #pragma unroll
   for (int s = 0; s < L::E; ++s) {
     const int j = qq + s * QT;
@@ -996,6 +998,96 @@ void r2r_async_tight_kernel(R2RFastArgs<T> A) {
     POISSON_ASYNC_TILE(lt, qt, tidt)
   }
 }
+
+// ---------------------------------------------------------------- register-staged form
+// FP64 length 512 on the strided axes with 32 lines per tile, so that each
+// row of a tile is 256 contiguous bytes of the field (16 lines give
+// 128-byte rows, which cost a strided sweep of a 512^3 field about a tenth
+// of its bandwidth: measured 0.43 against 0.48 ms for an in-place read and
+// write of every tile).  The tile (135 KiB) and the twiddles fill the LDS,
+// so the next tile is read into registers (32 values per thread) while the
+// current one is transformed and stored.  Types whose input step pairs
+// points (inverse combine, DCT-IV pre-twiddle) place the registers in the
+// tile unpermuted and run that step in place (a barrier between its reads
+// and its writes).
+template <typename T, typename C, int KIND, int INV>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void r2r_regstage_kernel(R2RFastArgs<T> A) {
+  using L = FastLayout<T, C>;
+  constexpr int M = L::M, NL = L::NL, QT = L::QT, N = L::N, EPT = L::EPT, NLP = L::NLP;
+  constexpr int kind = KIND, inverse = INV;
+  constexpr bool ivk = kind >= K_ND;
+  if (A.skip && A.skip[0] != 0.0) return;
+  __shared__ __align__(16) unsigned char tile_raw[fast_lds_bytes<T, C>()];
+  const FastLds<T, C> S = fast_lds<T, C>(tile_raw);
+  const int tid = threadIdx.x;
+  LineGeom g = A.g;
+  g.layout = 0;
+  const lptr<const cplx<T>> tw_fft = S.twf;
+  const lptr<const cplx<T>> tw_a = S.twa;
+  const lptr<const cplx<T>> tw_b = S.twa + (ivk ? M : L::SPLIT);
+  fast_twiddles<T, C>(S, A, tid);
+  const TileRange tr = xcd_tiles(g.ntiles);
+  T buf[EPT];
+  // a tile is 32 consecutive x positions of one band (nx >= 32, checked at
+  // launch): a uniform base per row plus a 32-bit lane offset (the launch
+  // checks that every offset fits), so no load needs a 64-bit lane address
+  const size_t row_step = (size_t)QT * (size_t)g.sp;
+  auto fetch = [&](int tile, int lt, int qt) {
+    const TileOrigin o = tile_origin(g, tile);
+    const gptr<const T> tb = as_global(static_cast<const T*>(A.data)) + (o.x0 + (long long)o.b0 * g.sb);
+    const unsigned lane_off = (unsigned)lt + (unsigned)qt * (unsigned)g.sp;
+    if (o.x0 + lt < g.nx) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) buf[i] = (tb + i * row_step)[lane_off];
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) buf[i] = (T)0;
+    }
+  };
+  if (tr.first < tr.end) fetch(tr.first, tid % NL, tid / NL);
+  for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+    // thread indices opaque per tile: addresses are recomputed in each step
+    // instead of being held across the loop
+    int l = tid % NL, q = tid / NL, tt = tid;
+    asm volatile("" : "+v"(l), "+v"(q), "+v"(tt));
+    if constexpr (!ivk && !inverse) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        bool neg;
+        const int r = load_row(kind, inverse, q + i * QT, N, neg);
+        S.tile[r * NLP + l] = neg ? -buf[i] : buf[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) S.tile[(q + i * QT) * NLP + l] = buf[i];
+      lds_barrier();
+      const lptr<const T> raw = S.tile;
+      auto point = [&](int p) -> T { return raw[p * NLP + l]; };
+      if constexpr (ivk) pre_to_tile<T, C, true>(point, S.tile, tw_a, kind, l, q);
+      else combine_to_tile<T, C, true>(point, S.tile, tw_a, tw_b, kind, l, q);
+    }
+    lds_barrier();
+    if (tile + tr.step < tr.end) fetch(tile + tr.step, l, q);
+    if constexpr (!(inverse && kind <= K_DD)) fast_passes<T, C, true, 0, true>(S.tile, tw_fft, l, q);
+    else fast_passes<T, C, false, 0, true>(S.tile, tw_fft, l, q);
+    const TileOrigin o = tile_origin(g, tile);
+    const long long base = line_base(g, o, l);
+    if constexpr (ivk)
+      post_store_body<T, C>(S.tile, tw_b, kind, as_global(A.data), base, g.sp, 0, 0, A.scale, l, q,
+                            tt);
+    else if constexpr (!inverse)
+      split_store_body<T, C>(S.tile, tw_a, tw_b, kind, as_global(A.data), base, g.sp, 0, 0, A.scale,
+                             l, q, tt);
+    else
+      fast_store<T, C, true>(S.tile, as_global(A.data), base, g.sp, 0, 0, kind, inverse, A.scale, l,
+                             q, tt);
+    lds_barrier();
+  }
+}
+
+// Tile shape of the register-staged form.
+using RegStageCfg = FastCfg<256, 16, 32, 0>;
 
 #undef POISSON_ASYNC_TILE
 #undef POISSON_ASYNC_SETUP

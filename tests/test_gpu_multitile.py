@@ -79,8 +79,10 @@ def _stage(shape, bcs, role, f, inverse, cap, monkeypatch):
 @pytest.mark.parametrize("axis,kind,n", TRANSFORM_CASES)
 def test_transform_multitile(axis, kind, n, monkeypatch, default_variants):
     """FP64 transform stage, default variant and each staging tile shape
-    (variant 6 has no FP64 form and falls back to variant 0), grid capped
-    and uncapped, against the Table 2 sums; backward stage returns f."""
+    (variant 6 has no FP64 form and falls back to variant 0; variant 7, the
+    register-staged 32-line form, runs on strided axes of length 512 with
+    at least 32 x positions), grid capped and uncapped, against the Table 2
+    sums; backward stage returns f."""
     from oracle import transforms as tr
     from paper_1802_10323_amd import set_tuned_variant, tuned_variant
     shape, bcs, role = transform_case(axis, kind, n)
@@ -88,7 +90,7 @@ def test_transform_multitile(axis, kind, n, monkeypatch, default_variants):
     f = rng.uniform(-1.0, 1.0, (shape[2], shape[1], shape[0]))
     ref = tr.forward(f, AXIS[axis], kind)
     layout = 1 if axis == "x" else 0
-    for V in (None, 4, 5, 6):
+    for V in (None, 4, 5, 6, 7):
         if V is not None:
             set_tuned_variant(0, n, layout, V)
         say("transform", axis, kind, n, "variant", tuned_variant(0, n, layout))

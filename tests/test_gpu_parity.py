@@ -493,7 +493,7 @@ def test_server_orders_solve_after_producer_stream():
 # --------------------------------------------------------------- kernel variants
 
 
-@pytest.mark.parametrize("V", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("V", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("M", FAST_M)
 def test_transform_variants(M, V, default_variants):
     """Every compiled transform variant (tile shape x radix order, and the
@@ -587,7 +587,7 @@ def test_autotune_records_fastest(default_variants):
     for prec, fp64 in (("fp64", True), ("fp32", False)):
         r = rep[prec]
         assert all(v > 0 for v in r["t1"][:4] + r["t2"][:4] + r["elimination"])
-        assert r["t2"][4] == r["t2"][5] == r["t2"][6] == -1.0   # no staging transform for length 96
+        assert r["t2"][4] == r["t2"][5] == r["t2"][6] == r["t2"][7] == -1.0   # no staging form for 96
         t1 = [v if v > 0 else np.inf for v in r["t1"]]
         assert tuned_variant(0, 128, 1, fp64) == int(np.argmin(t1))
         assert tuned_variant(0, 96, 0, fp64) == int(np.argmin(r["t2"][:4]))
