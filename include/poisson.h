@@ -202,18 +202,18 @@ int batch_autotune(poisson_batch* batch, int reps, hipStream_t stream, double* r
  * it runs variant 0); variant 7 (FP64 length 512 on a strided axis with
  * nx >= 32; elsewhere it runs variant 4) uses 32-line tiles too, with the
  * next tile read into registers instead; for the elimination, variants 0-1
- * are two chunkings (rows per chunk x chunks per line) and variant 2 reads
- * the next tile into LDS while the current one is eliminated.  All give the same result up to
+ * are two chunkings (rows per chunk x chunks per line), variant 2 reads
+ * the next tile into LDS while the current one is eliminated, and variant 3
+ * (contiguous lines only, elsewhere variant 0) keeps each chunk in
+ * registers from its read to its write, with no tile in LDS.  All give the same result up to
  * rounding.  The variant used for a length is chosen per device, precision
  * and layout (strided: the axis is y or z; contiguous: x) from a
  * process-wide table; where nothing was tuned, a staging transform for
  * lengths 256 and 512 (variant 5 for FP64 length 256 and for FP32 length 512
  * on the contiguous axis, 6 for FP32 length 512 on the strided axes, 7 for
- * FP64 length 512 along z, else 4; tuned_variant() reports the choice for
- * lines that are not along z)
- * and variant 0 otherwise; eliminations variant 1 on strided lines of 384
- * points and FP32 lines of 256, variant 2 on contiguous FP32 lines of 512,
- * else 0.  Plans and batches read the
+ * FP64 length 512 on the strided axes, else 4)
+ * and variant 0 otherwise; eliminations variant 3 on contiguous lines,
+ * variant 1 on strided lines of 384 points and FP32 lines of 256, else 0.  Plans and batches read the
  * table when they launch (batches when they are bound; batches use the
  * synchronous variants only: transforms 0-3, elimination 0-1). */
 
@@ -221,9 +221,9 @@ int batch_autotune(poisson_batch* batch, int reps, hipStream_t stream, double* r
  * elimination, FP64 and FP32) on `scratch` (DEVICE, at least nx*ny*nz
  * doubles; overwritten), `reps` launches each after one warm-up, and record
  * the fastest in the table.  Synchronous (waits for `stream`).  report (HOST,
- * may be NULL): 2 x (8 + 8 + 3) doubles, per precision (FP64 first) the
+ * may be NULL): 2 x (8 + 8 + 4) doubles, per precision (FP64 first) the
  * average ms of variants 0-7 of t1, 0-7 of t2 (forward + backward pair) and
- * 0-2 of the elimination, -1 where a variant does not apply. */
+ * 0-3 of the elimination, -1 where a variant does not apply. */
 int plan_autotune(poisson_plan* plan, double* scratch, int reps, hipStream_t stream, double* report);
 
 /* Variant in the table for kernel family 0 (transform) or 1 (elimination),

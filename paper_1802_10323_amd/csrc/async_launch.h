@@ -37,6 +37,12 @@ hipError_t async_elimination_launch(const TriFastArgs<float>& a, int n, hipStrea
 hipError_t regstage_launch(const R2RFastArgs<double>& a, int kind, int inverse,
                            hipStream_t stream);
 
+// The direct elimination of contiguous lines (tri_async.hip), with the
+// chunking of variant 0 (tri_fast.h).  hipErrorInvalidValue if n has none
+// or its chunks are not whole 16-byte pieces.
+hipError_t direct_elimination_launch(const TriFastArgs<double>& a, int n, hipStream_t stream);
+hipError_t direct_elimination_launch(const TriFastArgs<float>& a, int n, hipStream_t stream);
+
 // The kernels of AsyncBudget<double, FastVar<256, 0>, kind>::WIDE
 // (r2r_async_wide.hip).
 hipError_t async_wide_launch(const R2RFastArgs<double>& a, int kind, int inverse,
@@ -73,6 +79,32 @@ inline int async_resident_blocks(const void* fn, long long ntiles) {
   const int cap = grid_cap_blocks();
   if (cap > 0) blocks = std::min(blocks, cap);
   return (int)std::min<long long>(ntiles, blocks);
+}
+
+// Blocks of a persistent launch of `fn` with 256 threads and static LDS
+// only: as many as are resident at once (occupancy API), at most `work`.
+inline int direct_blocks(const void* fn, long long work) {
+  static std::mutex mu;
+  static std::vector<std::pair<std::pair<const void*, int>, int>> cache;   // (fn, device) -> blocks
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int blocks = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& e : cache)
+      if (e.first.first == fn && e.first.second == dev) blocks = e.second;
+  }
+  if (!blocks) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess) per_cu = 1;
+    blocks = cus * std::max(per_cu, 1);
+    std::lock_guard<std::mutex> lk(mu);
+    cache.push_back({{fn, dev}, blocks});
+  }
+  const int cap = grid_cap_blocks();
+  if (cap > 0) blocks = std::min(blocks, cap);
+  return (int)std::max<long long>(1, std::min<long long>(work, blocks));
 }
 
 }  // namespace poisson_dev

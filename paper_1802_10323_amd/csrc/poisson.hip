@@ -178,8 +178,9 @@ struct TriCfg {
 static constexpr int kFastVariants = 8;   // transform: tile shape x radix order, + staging forms
 static constexpr int kAsyncVariant = 4;   // 4, 5, 6: asynchronous staging in tile shape 0, 1, 2
 static constexpr int kRegStageVariant = 7;  // register-staged 32-line tiles (FP64, 512, strided)
-static constexpr int kTriVariants = 3;    // elimination: two chunkings, + asynchronous staging
+static constexpr int kTriVariants = 4;    // elimination: two chunkings, staging, direct
 static constexpr int kTriAsyncVariant = 2;
+static constexpr int kTriDirectVariant = 3;   // contiguous lines, registers only
 
 // Call f(FastVar<M, V>{}) for a specialised transform length; -1 otherwise.
 template <typename F>
@@ -225,33 +226,34 @@ static std::map<std::tuple<int, int, int, int, int>, int> g_tune;
 // where the extra overlap pays most; shape 2 (32 lines) for FP32 length 512
 // on the strided axes, whose tile rows are then 128 bytes long; else shape
 // 0, whose wider tile rows use each DRAM page better.
-static int default_choice(int family, int bytes, int n, int layout, int axis) {
+static int default_choice(int family, int bytes, int n, int layout) {
   if (family == 1) {
-    // elimination: the staging form wins on contiguous FP32 lines of 512
-    // points; the second chunking (shorter interface reduction) on strided
-    // lines of 384 points, and of 256 points in FP32
-    if (layout == 1 && bytes == 4 && n == 512) return kTriAsyncVariant;
+    // elimination: the direct form on contiguous lines (the 512^3 cube's
+    // lines of 512 points: 0.438 against 0.509 ms in FP64, 0.337 against
+    // 0.420 ms for the staging form in FP32); the second chunking (shorter
+    // interface reduction) on strided lines of 384 points, and of 256
+    // points in FP32
+    if (layout == 1) return kTriDirectVariant;
     return layout == 0 && (n == 384 || (bytes == 4 && n == 256)) ? 1 : 0;
   }
   if (n != 128 && n != 256) return 0;
-  // FP64 length 512 along z (lines 2 MiB apart in a 512^2 plane): the
-  // register-staged 32-line tile, whose 256-byte rows use each DRAM page
-  // better (measured on the 512^3 cube: 0.517 against 0.542 ms per z
-  // transform; along y, 4 KiB apart, the LDS-staged 16-line tile is faster)
-  if (bytes == 8 && n == 256 && layout == 0 && axis == 2) return kRegStageVariant;
+  // FP64 length 512 on a strided axis: the register-staged 32-line tile,
+  // whose 256-byte rows use each DRAM page better (measured on the 512^3
+  // cube, forward + backward: z 1.037 against 1.086 ms, y 0.876 against
+  // 0.895 ms for the LDS-staged 16-line tile)
+  if (bytes == 8 && n == 256 && layout == 0) return kRegStageVariant;
   int shape = 0;
   if (bytes == 8 && n == 128) shape = 1;
   if (bytes == 4 && n == 256) shape = layout == 1 ? 1 : 2;
   return kAsyncVariant + shape;
 }
 
-// axis: the axis of the lines (0 x, 1 y, 2 z; -1 unknown), for the default.
-static int tuned_choice(int family, int bytes, int n, int layout, int axis = -1) {
+static int tuned_choice(int family, int bytes, int n, int layout) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   const auto it = g_tune.find(std::make_tuple(dev, family, bytes, n, layout));
-  return it == g_tune.end() ? default_choice(family, bytes, n, layout, axis) : it->second;
+  return it == g_tune.end() ? default_choice(family, bytes, n, layout) : it->second;
 }
 
 static void set_tuned_choice(int family, int bytes, int n, int layout, int v) {
@@ -458,12 +460,13 @@ static bool async_applies(const poisson_plan* p, const AxisTables& A, int shape)
 // True if the register-staged form applies to axis A in type T (FP64,
 // length 512, strided axis).
 // length 512, strided axis, at least 32 x positions (a tile is 32
-// consecutive x of one band) and lane offsets that fit 32 bits.
+// consecutive x of one band) and element offsets within a tile's lines
+// that fit 32 bits.
 template <typename T>
 static bool regstage_applies(const poisson_plan* p, const AxisTables& A) {
   if (sizeof(T) != 8 || A.m != 256 || A.axis == 0 || p->dims[0] < 32) return false;
   const long long sp = A.axis == 1 ? (long long)p->dims[0] : (long long)p->dims[0] * p->dims[1];
-  return 32 + 16 * sp < (1LL << 32);
+  return 32 + (long long)A.n * sp < (1LL << 32);
 }
 
 // Specialised transform of axis A in variant V (-1: the length has none).
@@ -501,7 +504,7 @@ static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hip
   if constexpr (sizeof(T) == 8) out64 = nullptr;
   t_grid_cap = p->grid_cap;
   if (!p->generic_r2r) {
-    const int rc = launch_fast_variant<T>(p, A, tuned_choice(0, sizeof(T), A.m, A.axis == 0, A.axis),
+    const int rc = launch_fast_variant<T>(p, A, tuned_choice(0, sizeof(T), A.m, A.axis == 0),
                                           inverse, data, st, skip, out64);
     if (rc != -1) return rc;
   }
@@ -588,10 +591,36 @@ static bool tri_async_applies(const poisson_plan* p) {
   return p->s == 0 || p->dims[0] % (int)(16 / sizeof(T)) == 0;
 }
 
+// True if the direct elimination applies: contiguous lines whose chunks (of
+// the variant-0 chunking) are whole 16-byte pieces, a 16-byte aligned field.
+template <typename T>
+static bool tri_direct_applies(const poisson_plan* p, const T* data) {
+  if (p->s != 0 || (reinterpret_cast<uintptr_t>(data) & 15) != 0) return false;
+  const long long rpc = with_tri_cfg(p->dims[0], 0, [](auto cfg) {
+    return (long long)decltype(cfg)::RPC;
+  });
+  return rpc > 0 && (rpc * (long long)sizeof(T)) % 16 == 0;
+}
+
 // Specialised elimination in variant V (-1: the length has none).
 template <typename T>
 static int launch_tri_variant(const poisson_plan* p, int V, T* data, hipStream_t st,
                               const double* skip) {
+  if (V == kTriDirectVariant) {
+    if (tri_direct_applies<T>(p, data)) {
+      const int n = p->dims[p->s];
+      const long long rc = with_tri_cfg(n, 0, [&](auto cfg) {
+        using C = decltype(cfg);
+        const TriFastArgs<T> a = tri_fast_args<T, C::RPC, C::P>(p, data, skip);
+        const hipError_t e = direct_elimination_launch(a, n, st);
+        return (long long)(e == hipSuccess ? POISSON_OK
+                                           : fail(POISSON_EHIP, "direct elimination launch: %s",
+                                                  hipGetErrorString(e)));
+      });
+      if (rc != -1) return (int)rc;
+    }
+    V = 0;
+  }
   if (V == kTriAsyncVariant) {
     if (tri_async_applies<T>(p)) {
       const int n = p->dims[p->s];
@@ -1656,6 +1685,7 @@ static int autotune_typed(poisson_plan* p, double* scratch, int reps, hipStream_
     double best_ms = 1e300;
     for (int V = 0; V < kTriVariants; ++V) {
       if (V == kTriAsyncVariant && !tri_async_applies<T>(p)) continue;
+      if (V == kTriDirectVariant && !tri_direct_applies<T>(p, data)) continue;
       if ((rc = reset())) return rc;
       const double ms = time_launches(st, reps, [&]() -> int {
         return launch_tri_variant<T>(p, V, data, st, nullptr);

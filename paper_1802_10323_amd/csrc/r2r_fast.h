@@ -478,49 +478,63 @@ __device__ __noinline__ void post_store_call(lptr<const T> lds, lptr<const cplx<
 // whose inverse FFT interleaves the even and odd output points; written
 // into the tile (column ln, pairs k = qq + s QT) from the input points of
 // the line, point(p) (tile row r holds point r, D-D: point n-1-r).
-template <typename T, typename C, bool SYNC = false, typename Point>
-__device__ __forceinline__ void combine_to_tile(Point point, lptr<T> lds,
-                                                lptr<const cplx<T>> split,
-                                                lptr<const cplx<T>> quarter, int kind, int ln,
-                                                int qq) {
-  using L = FastLayout<T, C>;
-  constexpr int M = L::M, N = L::N, NLP = L::NLP, QT = L::QT;
-  constexpr int NP = M / 2 + 1;
-  constexpr int SP = (NP + QT - 1) / QT;
-  auto row = [&](int r) -> T { return point(kind == K_DD ? N - 1 - r : r); };
-  // all reads first (global reads stay in flight together), then the math
+//
+// combine_read: the points thread qq needs, v[s] = the four rows of
+// wavenumbers k = qq + s QT and M - k; combine_write: the math and the tile
+// writes.
+template <typename T, typename C>
+struct CombineRegs {
+  static constexpr int SP = (FastLayout<T, C>::M / 2 + 1 + FastLayout<T, C>::QT - 1) /
+                            FastLayout<T, C>::QT;
   T v[SP][4];
+};
+
+template <typename T, typename C, typename Point>
+__device__ __forceinline__ void combine_read(Point point, CombineRegs<T, C>& R, int kind, int qq) {
+  using L = FastLayout<T, C>;
+  constexpr int M = L::M, N = L::N, QT = L::QT;
+  constexpr int NP = M / 2 + 1;
+  auto row = [&](int r) -> T { return point(kind == K_DD ? N - 1 - r : r); };
 #pragma unroll
-  for (int s = 0; s < SP; ++s) {
+  for (int s = 0; s < CombineRegs<T, C>::SP; ++s) {
     const int k = qq + s * QT;
     const int j = M - k;
     if (k < NP) {
       if (kind == K_P) {
-        v[s][0] = row(k == 0 ? 0 : 2 * k - 1);
-        v[s][1] = k == 0 ? (T)0 : row(2 * k);
-        v[s][2] = row(j == M ? N - 1 : 2 * j - 1);
-        v[s][3] = j == M ? (T)0 : row(2 * j);
+        R.v[s][0] = row(k == 0 ? 0 : 2 * k - 1);
+        R.v[s][1] = k == 0 ? (T)0 : row(2 * k);
+        R.v[s][2] = row(j == M ? N - 1 : 2 * j - 1);
+        R.v[s][3] = j == M ? (T)0 : row(2 * j);
       } else {
-        v[s][0] = row(k);
-        v[s][1] = k == 0 ? (T)0 : row(N - k);
-        v[s][2] = row(j);
-        v[s][3] = row(N - j);
+        R.v[s][0] = row(k);
+        R.v[s][1] = k == 0 ? (T)0 : row(N - k);
+        R.v[s][2] = row(j);
+        R.v[s][3] = row(N - j);
       }
     }
   }
-  if constexpr (SYNC) lds_barrier();   // the points are read from the tile itself
+}
+
+template <typename T, typename C>
+__device__ __forceinline__ void combine_write(const CombineRegs<T, C>& R, lptr<T> lds,
+                                              lptr<const cplx<T>> split,
+                                              lptr<const cplx<T>> quarter, int kind, int ln,
+                                              int qq) {
+  using L = FastLayout<T, C>;
+  constexpr int M = L::M, NLP = L::NLP, QT = L::QT;
+  constexpr int NP = M / 2 + 1;
 #pragma unroll
-  for (int s = 0; s < SP; ++s) {
+  for (int s = 0; s < CombineRegs<T, C>::SP; ++s) {
     const int k = qq + s * QT;
     if (k < NP) {
       const int j = M - k;
       cplx<T> xk, xj;
       if (kind == K_P) {
-        xk = {v[s][0], k == 0 ? (T)0 : -v[s][1]};
-        xj = {v[s][2], j == M ? (T)0 : -v[s][3]};
+        xk = {R.v[s][0], k == 0 ? (T)0 : -R.v[s][1]};
+        xj = {R.v[s][2], j == M ? (T)0 : -R.v[s][3]};
       } else {
-        xk = cmul(cconj(ldc(quarter, k)), cplx<T>{(T)0.5 * v[s][0], (T)-0.5 * v[s][1]});
-        xj = cmul(cconj(ldc(quarter, j)), cplx<T>{(T)0.5 * v[s][2], (T)-0.5 * v[s][3]});
+        xk = cmul(cconj(ldc(quarter, k)), cplx<T>{(T)0.5 * R.v[s][0], (T)-0.5 * R.v[s][1]});
+        xj = cmul(cconj(ldc(quarter, j)), cplx<T>{(T)0.5 * R.v[s][2], (T)-0.5 * R.v[s][3]});
       }
       const cplx<T> sk = ldc(split, k);
       const cplx<T> s1 = cadd(xk, cconj(xj));
@@ -537,30 +551,63 @@ __device__ __forceinline__ void combine_to_tile(Point point, lptr<T> lds,
   }
 }
 
-// DCT-IV / DST-IV, fused with the placement: complex value j of the packed
-// sequence (tile rows 2j and 2j+1: input points 2j and n-1-2j for N-D, the
-// mirrored points n-1-2j and 2j for D-N) times the pre-twiddle, into the
-// tile (column ln, j = qq + s QT).
+// Both: all reads first (global reads stay in flight together), then the
+// math.  SYNC: the points are read from the tile itself (a barrier between
+// the reads and the writes).
 template <typename T, typename C, bool SYNC = false, typename Point>
-__device__ __forceinline__ void pre_to_tile(Point point, lptr<T> lds, lptr<const cplx<T>> pre,
-                                            int kind, int ln, int qq) {
+__device__ __forceinline__ void combine_to_tile(Point point, lptr<T> lds,
+                                                lptr<const cplx<T>> split,
+                                                lptr<const cplx<T>> quarter, int kind, int ln,
+                                                int qq) {
+  CombineRegs<T, C> R;
+  combine_read<T, C>(point, R, kind, qq);
+  if constexpr (SYNC) lds_barrier();
+  combine_write<T, C>(R, lds, split, quarter, kind, ln, qq);
+}
+
+// Points read by pre_to_tile for thread qq: v[s] = the two points of
+// complex index j = qq + s QT.
+template <typename T, typename C>
+struct PreRegs {
+  T v[FastLayout<T, C>::E][2];
+};
+
+template <typename T, typename C, typename Point>
+__device__ __forceinline__ void pre_read(Point point, PreRegs<T, C>& R, int kind, int qq) {
   using L = FastLayout<T, C>;
-  constexpr int N = L::N, NLP = L::NLP, QT = L::QT;
-  T v[L::E][2];   // all reads first, then the math
+  constexpr int N = L::N, QT = L::QT;
 #pragma unroll
   for (int s = 0; s < L::E; ++s) {
     const int j = qq + s * QT;
-    v[s][0] = point(kind == K_ND ? 2 * j : N - 1 - 2 * j);
-    v[s][1] = point(kind == K_ND ? N - 1 - 2 * j : 2 * j);
+    R.v[s][0] = point(kind == K_ND ? 2 * j : N - 1 - 2 * j);
+    R.v[s][1] = point(kind == K_ND ? N - 1 - 2 * j : 2 * j);
   }
-  if constexpr (SYNC) lds_barrier();   // the points are read from the tile itself
+}
+
+template <typename T, typename C>
+__device__ __forceinline__ void pre_write(const PreRegs<T, C>& R, lptr<T> lds,
+                                          lptr<const cplx<T>> pre, int ln, int qq) {
+  using L = FastLayout<T, C>;
+  constexpr int NLP = L::NLP, QT = L::QT;
 #pragma unroll
   for (int s = 0; s < L::E; ++s) {
     const int j = qq + s * QT;
-    const cplx<T> z = cmul(cplx<T>{v[s][0], v[s][1]}, ldc(pre, j));
+    const cplx<T> z = cmul(cplx<T>{R.v[s][0], R.v[s][1]}, ldc(pre, j));
     lds[(2 * j) * NLP + ln] = z.re;
     lds[(2 * j + 1) * NLP + ln] = z.im;
   }
+}
+
+// The input step of the DCT-IV / DST-IV types: the pre-twiddled complex
+// sequence of the half-length FFT, written into the tile (reads first;
+// SYNC as for combine_to_tile).
+template <typename T, typename C, bool SYNC = false, typename Point>
+__device__ __forceinline__ void pre_to_tile(Point point, lptr<T> lds, lptr<const cplx<T>> pre,
+                                            int kind, int ln, int qq) {
+  PreRegs<T, C> R;
+  pre_read<T, C>(point, R, kind, qq);
+  if constexpr (SYNC) lds_barrier();
+  pre_write<T, C>(R, lds, pre, ln, qq);
 }
 
 // The two above from global memory, for the synchronous kernels: the lanes
@@ -1005,11 +1052,14 @@ void r2r_async_tight_kernel(R2RFastArgs<T> A) {
 // 128-byte rows, which cost a strided sweep of a 512^3 field about a tenth
 // of its bandwidth: measured 0.43 against 0.48 ms for an in-place read and
 // write of every tile).  The tile (135 KiB) and the twiddles fill the LDS,
-// so the next tile is read into registers (32 values per thread) while the
-// current one is transformed and stored.  Types whose input step pairs
-// points (inverse combine, DCT-IV pre-twiddle) place the registers in the
-// tile unpermuted and run that step in place (a barrier between its reads
-// and its writes).
+// so the next tile is read into registers while the current one is
+// transformed and stored: the points of the thread's rows, or for the
+// DCT-IV / DST-IV types straight away the two points each complex index of
+// the pre-twiddle pairs, so that this step runs from registers into the
+// tile.  The inverse real DFT / DCT-II / DST-II place the rows unpermuted
+// and run their combine step in the tile (a barrier between its reads and
+// its writes): reading its four rows per wavenumber pair from HBM instead
+// was slower on the 512^3 cube's z axis (0.57 against 0.54 ms).
 template <typename T, typename C, int KIND, int INV>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void r2r_regstage_kernel(R2RFastArgs<T> A) {
@@ -1017,6 +1067,7 @@ void r2r_regstage_kernel(R2RFastArgs<T> A) {
   constexpr int M = L::M, NL = L::NL, QT = L::QT, N = L::N, EPT = L::EPT, NLP = L::NLP;
   constexpr int kind = KIND, inverse = INV;
   constexpr bool ivk = kind >= K_ND;
+  constexpr bool plain = !ivk;      // rows of the thread; IV types: pre-twiddle pairs
   if (A.skip && A.skip[0] != 0.0) return;
   __shared__ __align__(16) unsigned char tile_raw[fast_lds_bytes<T, C>()];
   const FastLds<T, C> S = fast_lds<T, C>(tile_raw);
@@ -1028,21 +1079,31 @@ void r2r_regstage_kernel(R2RFastArgs<T> A) {
   const lptr<const cplx<T>> tw_b = S.twa + (ivk ? M : L::SPLIT);
   fast_twiddles<T, C>(S, A, tid);
   const TileRange tr = xcd_tiles(g.ntiles);
-  T buf[EPT];
+  // the prefetched points (one of the two, by type)
+  T buf[plain ? EPT : 1];
+  PreRegs<T, C> pr;
   // a tile is 32 consecutive x positions of one band (nx >= 32, checked at
-  // launch): a uniform base per row plus a 32-bit lane offset (the launch
-  // checks that every offset fits), so no load needs a 64-bit lane address
+  // launch): a uniform base plus a 32-bit lane offset (the launch checks
+  // that every offset fits), so no load needs a 64-bit lane address
   const size_t row_step = (size_t)QT * (size_t)g.sp;
+  const unsigned sp32 = (unsigned)g.sp;
   auto fetch = [&](int tile, int lt, int qt) {
     const TileOrigin o = tile_origin(g, tile);
     const gptr<const T> tb = as_global(static_cast<const T*>(A.data)) + (o.x0 + (long long)o.b0 * g.sb);
-    const unsigned lane_off = (unsigned)lt + (unsigned)qt * (unsigned)g.sp;
-    if (o.x0 + lt < g.nx) {
+    const bool ok = o.x0 + lt < g.nx;
+    if constexpr (plain) {
+      const unsigned lane_off = (unsigned)lt + (unsigned)qt * sp32;
+      if (ok) {
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) buf[i] = (tb + i * row_step)[lane_off];
+        for (int i = 0; i < EPT; ++i) buf[i] = (tb + i * row_step)[lane_off];
+      } else {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) buf[i] = (T)0;
+      }
+    } else if (ok) {
+      pre_read<T, C>([&](int p) -> T { return tb[(unsigned)lt + (unsigned)p * sp32]; }, pr, kind, qt);
     } else {
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) buf[i] = (T)0;
+      pre_read<T, C>([](int) -> T { return (T)0; }, pr, kind, qt);
     }
   };
   if (tr.first < tr.end) fetch(tr.first, tid % NL, tid / NL);
@@ -1051,7 +1112,9 @@ void r2r_regstage_kernel(R2RFastArgs<T> A) {
     // instead of being held across the loop
     int l = tid % NL, q = tid / NL, tt = tid;
     asm volatile("" : "+v"(l), "+v"(q), "+v"(tt));
-    if constexpr (!ivk && !inverse) {
+    if constexpr (ivk) {
+      pre_write<T, C>(pr, S.tile, tw_a, l, q);
+    } else if constexpr (!inverse) {
 #pragma unroll
       for (int i = 0; i < EPT; ++i) {
         bool neg;
@@ -1063,9 +1126,8 @@ void r2r_regstage_kernel(R2RFastArgs<T> A) {
       for (int i = 0; i < EPT; ++i) S.tile[(q + i * QT) * NLP + l] = buf[i];
       lds_barrier();
       const lptr<const T> raw = S.tile;
-      auto point = [&](int p) -> T { return raw[p * NLP + l]; };
-      if constexpr (ivk) pre_to_tile<T, C, true>(point, S.tile, tw_a, kind, l, q);
-      else combine_to_tile<T, C, true>(point, S.tile, tw_a, tw_b, kind, l, q);
+      combine_to_tile<T, C, true>([&](int p) -> T { return raw[p * NLP + l]; }, S.tile, tw_a, tw_b,
+                                  kind, l, q);
     }
     lds_barrier();
     if (tile + tr.step < tr.end) fetch(tile + tr.step, l, q);

@@ -32,7 +32,43 @@ hipError_t launch_n(const TriFastArgs<T>& a, int n, hipStream_t st) {
   }
 }
 
+template <typename T, int RPC, int P>
+hipError_t launch_direct(const TriFastArgs<T>& a, hipStream_t st) {
+  if constexpr ((RPC * sizeof(T)) % 16 != 0) {
+    return hipErrorInvalidValue;
+  } else {
+    if (a.g.layout != 1) return hipErrorInvalidValue;
+    void (*k)(TriFastArgs<T>) = tri_direct_kernel<T, RPC, P>;
+    const long long groups = ((long long)a.g.nlines + 64 / P - 1) / (64 / P);
+    hipLaunchKernelGGL(k, dim3(direct_blocks(reinterpret_cast<const void*>(k), (groups + 3) / 4)),
+                       dim3(256), 0, st, a);
+    return hipGetLastError();
+  }
+}
+
+template <typename T>
+hipError_t launch_direct_n(const TriFastArgs<T>& a, int n, hipStream_t st) {
+  switch (n) {
+    case 64: return launch_direct<T, 4, 16>(a, st);
+    case 96: return launch_direct<T, 6, 16>(a, st);
+    case 128: return launch_direct<T, 8, 16>(a, st);
+    case 192: return launch_direct<T, 12, 16>(a, st);
+    case 256: return launch_direct<T, 8, 32>(a, st);
+    case 384: return launch_direct<T, 6, 64>(a, st);
+    case 512: return launch_direct<T, 8, 64>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
+
+hipError_t direct_elimination_launch(const TriFastArgs<double>& a, int n, hipStream_t stream) {
+  return launch_direct_n<double>(a, n, stream);
+}
+
+hipError_t direct_elimination_launch(const TriFastArgs<float>& a, int n, hipStream_t stream) {
+  return launch_direct_n<float>(a, n, stream);
+}
 
 hipError_t async_elimination_launch(const TriFastArgs<double>& a, int n, hipStream_t stream) {
   return launch_n<double>(a, n, stream);

@@ -19,6 +19,7 @@
 //    16-lane row of the wavefront, so its exchanges are DPP row rotations
 //    (VALU) instead of LDS permutes.
 #pragma once
+#include <type_traits>
 #include "tridiag_kernel.h"
 #include "stage_dma.h"
 
@@ -226,39 +227,23 @@ __device__ __forceinline__ void pcr(T& l, T& u, T& r, int c, int gbase, int peri
 // leave errors near 1e-2 and make iterative refinement slow; in FP64 the
 // FP32 solve is limited by its transforms instead.  The kernel is bound by
 // HBM traffic, which only the field type sets.
-template <typename T, int RPC, int P>
-__device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const double> coef, int c,
-                                              double mu, int sing, int wave_sing, int periodic) {
-  using L = TriFastLayout<T, RPC, P>;
+// The elimination of one line of N = RPC P rows, chunk c of it on this
+// lane (the P lanes of a line are consecutive lanes of a wave): the rows of
+// the chunk are read and written through xget(i) / xset(i, v) (registers or
+// the tile), coefficient tables ca/cb/cc/cw in LDS laid out [row in
+// chunk][chunk], shift mu, and the singular-line flags.  FENCE: keep each
+// row's coefficient loads in its own step (long chunks held in the tile).
+template <int RPC, int P, bool FENCE, typename Get, typename Set>
+__device__ __forceinline__ void tri_line_solve(Get xget, Set xset, lptr<const double> coef, int c,
+                                               double mu, int sing, int wave_sing, int periodic) {
   using R = double;
-  constexpr int N = L::N;
-  // Long chunks of an FP64 field keep the eliminated right-hand side in the
-  // tile (LDS) instead of registers: the pivots and spikes of RPC rows plus
-  // RPC values would not fit 128 VGPRs.  FP32 fields keep it in registers
-  // (the tile cannot hold FP64 intermediates).
-  constexpr bool XL = sizeof(T) == 8 && RPC >= 12 && RPC * P >= 256;
-  const lptr<const R> ca = coef, cb = coef + N, cc = coef + 2 * N, cw = coef + 3 * N;
+  constexpr int N = RPC * P;
   const int lane = threadIdx.x & 63;
   const int gbase = lane - c;
-
-  R xr[XL ? 1 : RPC];
-  auto xget = [&](int i) -> R {
-    if constexpr (XL) return (R)col[i * L::NLP];
-    else return xr[i];
-  };
-  auto xset = [&](int i, R v) {
-    if constexpr (XL) col[i * L::NLP] = (T)v;
-    else xr[i] = v;
-  };
-  // long chunks: keep each row's loads in its own step (the scheduler would
-  // otherwise issue every row's coefficient loads at once, RPC x 3 values live)
   auto row_fence = [] {
-    if constexpr (XL) __builtin_amdgcn_sched_barrier(0);
+    if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
   };
-  if constexpr (!XL) {
-#pragma unroll
-    for (int i = 0; i < RPC; ++i) xr[i] = (R)col[i * L::NLP];
-  }
+  const lptr<const R> ca = coef, cb = coef + N, cc = coef + 2 * N, cw = coef + 3 * N;
 
   if (wave_sing) {   // project the right-hand side of the null-space line
     R sw = 0, swf = 0;
@@ -350,7 +335,39 @@ __device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const double> co
       for (int i = 0; i < RPC; ++i) xset(i, xget(i) - mean);
     }
   }
-  if constexpr (!XL) {
+}
+
+// Eliminate the line held by this lane's group: chunk c of the line, LDS
+// column col (row i at col[i * NLP]), coefficient tables ca/cb/cc/cw laid out
+// [row in chunk][chunk], shift mu, and the singular-line flags.
+//
+// The arithmetic is FP64 whatever the field type T: an FP32 field is widened
+// on reading and rounded once on writing.  Gauss elimination amplifies
+// rounding by up to the condition number of the line (about 1e5 for a
+// 512-point Dirichlet line with a small shift), so FP32 recurrences would
+// leave errors near 1e-2 and make iterative refinement slow; in FP64 the
+// FP32 solve is limited by its transforms instead.  The kernel is bound by
+// HBM traffic, which only the field type sets.
+template <typename T, int RPC, int P>
+__device__ __forceinline__ void tri_fast_line(lptr<T> col, lptr<const double> coef, int c,
+                                              double mu, int sing, int wave_sing, int periodic) {
+  using L = TriFastLayout<T, RPC, P>;
+  using R = double;
+  // Long chunks of an FP64 field keep the eliminated right-hand side in the
+  // tile (LDS) instead of registers: the pivots and spikes of RPC rows plus
+  // RPC values would not fit 128 VGPRs.  FP32 fields keep it in registers
+  // (the tile cannot hold FP64 intermediates).
+  constexpr bool XL = sizeof(T) == 8 && RPC >= 12 && RPC * P >= 256;
+  if constexpr (XL) {
+    tri_line_solve<RPC, P, true>([&](int i) -> R { return (R)col[i * L::NLP]; },
+                                 [&](int i, R v) { col[i * L::NLP] = (T)v; }, coef, c, mu, sing,
+                                 wave_sing, periodic);
+  } else {
+    R xr[RPC];
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) xr[i] = (R)col[i * L::NLP];
+    tri_line_solve<RPC, P, false>([&](int i) -> R { return xr[i]; }, [&](int i, R v) { xr[i] = v; },
+                                  coef, c, mu, sing, wave_sing, periodic);
 #pragma unroll
     for (int i = 0; i < RPC; ++i) col[i * L::NLP] = (T)xr[i];
   }
@@ -433,6 +450,126 @@ void tri_fast_kernel(TriFastArgs<T> A) {
     int t = tid;
     if constexpr (RPC >= 16) asm volatile("" : "+v"(t));
     tri_fast_tile<T, RPC, P, LAYOUT>(lds, coef, A, tile, t);
+  }
+}
+
+// ---------------------------------------------------------------- direct form
+// Contiguous lines only, no tile and no block barrier in the loop: each
+// wave loops over its own groups of 64 / P lines (P lanes per line).  The
+// group is one contiguous run of the field, read and written with
+// coalesced 16-byte pieces (piece i + 64 k on lane i); the move between
+// that order and the chunk order of the elimination (RPC consecutive
+// points per lane) goes through a buffer of the wave's own in LDS, padded
+// by one value per chunk so that the chunk reads and writes meet no bank
+// conflicts.  The next group's loads are in flight while the current one
+// is eliminated.  Only the coefficient tables are shared by the block.
+
+template <typename T, int RPC>
+struct DirectVec {
+  static constexpr int BYTES = RPC * (int)sizeof(T);
+  static_assert(BYTES % 16 == 0, "chunks of whole 16-byte pieces");
+  static constexpr int PIECES = BYTES / 16;       // per lane and group
+  static constexpr int PER = 16 / (int)sizeof(T); // values per piece
+};
+
+// Within-wave hand-off through LDS: the wave's LDS operations complete in
+// issue order, so only the compiler must keep them in order.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+template <typename T, int RPC, int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void tri_direct_kernel(TriFastArgs<T> A) {
+  using V = DirectVec<T, RPC>;
+  constexpr int N = RPC * P;
+  constexpr int LPW = 64 / P;                  // lines per wave
+  constexpr int WPB = 256 / 64;                // waves per block
+  constexpr int GV = LPW * N;                  // values of a group
+  constexpr int BUF = GV + GV / RPC;           // padded: one slot after every chunk
+  if (A.skip && A.skip[0] != 0.0) return;
+  __shared__ double coef_raw[4 * N];
+  __shared__ T buf_raw[WPB * BUF];
+  const lptr<double> coef = as_lds(coef_raw);
+  for (int k = threadIdx.x; k < N; k += 256) {
+    const int ch = k / RPC, i = k - ch * RPC;
+    const int s = i * P + ch;
+    coef[s] = as_global(A.a)[k];
+    coef[N + s] = as_global(A.b)[k];
+    coef[2 * N + s] = as_global(A.c)[k];
+    coef[3 * N + s] = as_global(A.w)[k];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const lptr<T> wbuf = as_lds(buf_raw) + wave * BUF;
+  const int c = lane % P;                      // chunk of this lane
+  const int lw = lane / P;                     // line within the group
+  const int nlines = A.g.nlines;
+  const int groups = (nlines + LPW - 1) / LPW;
+  const int gstep = gridDim.x * WPB;
+  using Piece = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+  Piece nxt[V::PIECES];
+  // padded LDS slot of value e of the group
+  auto slot = [](int e) { return e + e / RPC; };
+  auto fetch = [&](int grp) {
+    const long long first = (long long)grp * GV;
+    const long long avail = ((long long)nlines * N - first) / V::PER;   // whole pieces left
+    const Piece* src = reinterpret_cast<const Piece*>(A.data + first);
+#pragma unroll
+    for (int k = 0; k < V::PIECES; ++k)
+      if (lane + 64 * k < avail) nxt[k] = src[lane + 64 * k];
+  };
+  int grp = blockIdx.x * WPB + wave;
+  if (grp < groups) fetch(grp);
+  for (; grp < groups; grp += gstep) {
+    // coalesced pieces -> chunk order, through the wave's buffer
+#pragma unroll
+    for (int k = 0; k < V::PIECES; ++k) {
+      const T* v = reinterpret_cast<const T*>(&nxt[k]);
+      const int e0 = (lane + 64 * k) * V::PER;
+#pragma unroll
+      for (int e = 0; e < V::PER; ++e) wbuf[slot(e0 + e)] = v[e];
+    }
+    wave_lds_fence();
+    double xr[RPC];
+    const int cb = slot(lw * N + c * RPC);
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) xr[i] = (double)wbuf[cb + i];
+    if (grp + gstep < groups) fetch(grp + gstep);
+    const int line = grp * LPW + lw;
+    const bool valid = line < nlines;
+    int u = 0, v = 0;
+    if (valid) {
+      v = line / A.nu;
+      u = line - v * A.nu;
+    }
+    const double mu = valid ? A.lamu[u] + A.lamv[v] : -1.0;
+    const bool sing = A.singular && valid && u == 0 && v == 0;
+    const int wave_sing = __any(sing) ? 1 : 0;
+    tri_line_solve<RPC, P, false>([&](int i) -> double { return xr[i]; },
+                                  [&](int i, double x) { xr[i] = x; }, coef, c, mu,
+                                  sing ? 1 : 0, wave_sing, A.periodic);
+    // chunk order -> coalesced pieces
+    wave_lds_fence();
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) wbuf[cb + i] = (T)xr[i];
+    wave_lds_fence();
+    const long long first = (long long)grp * GV;
+    const long long avail = ((long long)nlines * N - first) / V::PER;
+    Piece* dst = reinterpret_cast<Piece*>(A.data + first);
+#pragma unroll
+    for (int k = 0; k < V::PIECES; ++k) {
+      Piece out;
+      T* o = reinterpret_cast<T*>(&out);
+      const int e0 = (lane + 64 * k) * V::PER;
+#pragma unroll
+      for (int e = 0; e < V::PER; ++e) o[e] = wbuf[slot(e0 + e)];
+      if (lane + 64 * k < avail) dst[lane + 64 * k] = out;
+    }
+    wave_lds_fence();
   }
 }
 

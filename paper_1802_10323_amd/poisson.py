@@ -211,17 +211,17 @@ class Plan:
         """Time every kernel variant of this plan on ``scratch`` (a device
         float64 tensor of the field's size, overwritten) and record the
         fastest per length; returns the timing report (ms) as
-        {"fp64"|"fp32": {"t1": [8], "t2": [8], "elimination": [3]}}
+        {"fp64"|"fp32": {"t1": [8], "t2": [8], "elimination": [4]}}
         (-1 where a variant does not apply)."""
         if scratch.numel() < int(np.prod(self.shape)):
             raise ValueError("scratch is smaller than the field")
-        rep = (ctypes.c_double * 38)()
+        rep = (ctypes.c_double * 40)()
         _check(lib().plan_autotune(self.handle, _field_ptr(scratch), int(reps),
                                    _stream_handle(stream), rep))
         out = {}
         for k, name in enumerate(("fp64", "fp32")):
-            r = list(rep)[19 * k:19 * (k + 1)]
-            out[name] = {"t1": r[0:8], "t2": r[8:16], "elimination": r[16:19]}
+            r = list(rep)[20 * k:20 * (k + 1)]
+            out[name] = {"t1": r[0:8], "t2": r[8:16], "elimination": r[16:20]}
         return out
 
     def close(self):

@@ -127,10 +127,11 @@ def test_transform_more_tiles_than_blocks(monkeypatch):
 ELIM_CASES = [(n, k) for n in (64, 128, 192, 256, 384, 512) for k in ("NN", "DD", "ND", "DN")]
 
 
-@pytest.mark.parametrize("V", [0, 1, 2])
+@pytest.mark.parametrize("V", [0, 1, 2, 3])
 @pytest.mark.parametrize("n,kind", ELIM_CASES)
 def test_elimination_multitile(n, kind, V, monkeypatch, default_variants):
-    """FP64 elimination, every variant (two chunkings and the staging form),
+    """FP64 elimination, every variant (two chunkings, the staging form and
+    the direct form of contiguous lines),
     grid capped, contiguous (s = x; 1080 lines, ragged) and strided (s = z;
     x extent 40, ragged), regular, singular and stretched."""
     from paper_1802_10323_amd import set_tuned_variant
@@ -182,7 +183,7 @@ def test_fp32_transform_multitile_refined(axis, kind, n, monkeypatch, default_va
             assert np.array_equal(full, got), (axis, kind, n)
 
 
-@pytest.mark.parametrize("V", [0, 1, 2])
+@pytest.mark.parametrize("V", [0, 1, 2, 3])
 @pytest.mark.parametrize("n", [256, 384, 512])
 @pytest.mark.parametrize("layout", ["x", "z"])
 def test_fp32_elimination_multitile_refined(layout, n, V, monkeypatch, default_variants):
@@ -204,17 +205,17 @@ def test_fp32_elimination_multitile_refined(layout, n, V, monkeypatch, default_v
     assert err <= 1e-10, (layout, n, V, err)
 
 
-def test_fp32_contiguous_staging_elimination_default(monkeypatch, default_variants):
+def test_fp32_contiguous_elimination_default(monkeypatch, default_variants):
     """The default FP32 elimination of contiguous lines of 512 points is the
-    staging form (the 512^3 cube's refined solve runs it): uncapped, on a
-    field with more tiles than resident blocks ((512, 128, 64): 8192 lines,
-    1024 tiles of 8), within 1e-10 of the oracle solve."""
+    direct form (the 512^3 cube's refined solve runs it): uncapped, on a
+    field with more line groups than resident waves ((512, 128, 64): 8192
+    lines), within 1e-10 of the oracle solve."""
     from paper_1802_10323_amd import tuned_variant
-    assert tuned_variant(1, 512, 1, fp64=False) == 2
+    assert tuned_variant(1, 512, 1, fp64=False) == 3
     prob = inputs.make_uniform(512, 128, 64, ("DD", "ND", "P"), seed=21)
     ref = oracle_solve(prob)
     got, (iters, rel, conv) = _refined(prob, 0, monkeypatch)
     err = rel_l2(got, ref)
-    say("fp32 staging elimination (512, 128, 64)", iters, err)
+    say("fp32 direct elimination (512, 128, 64)", iters, err)
     assert conv and iters <= 4
     assert err <= 1e-10
