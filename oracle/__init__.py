@@ -15,12 +15,14 @@ Modules:
   transforms   Table 2 sums (forward / backward) and Table 1 eigenvalues
   tridiagonal  the 1D operator rows, Gauss elimination, cyclic and pinned solves
   poisson      the seven-point operator (Eq. (poi)) and the three-step solve
+  projection   the pressure-correction steps around the solve (Sec. 2):
+               divergence, gradient, right-hand side and projection
 
 Every function is pinned by tests under ``tests/`` against things other than
 itself (library transforms, LAPACK's tridiagonal routine, exact rational
 elimination, dense solves, closed-form eigenfunctions).  Parity is not
 unpinned for any function here.
 """
-from . import transforms, tridiagonal, poisson  # noqa: F401
+from . import transforms, tridiagonal, poisson, projection  # noqa: F401
 from .poisson import (solve, solve_corrected, apply_operator, residual, is_singular,  # noqa: F401
                       weighted_mean)
