@@ -298,6 +298,47 @@ int server_usage(poisson_server* server, size_t* held_bytes, size_t* peak_bytes)
 /* Finish every queued request, stop the worker, free the cached plans. */
 void server_destroy(poisson_server* server);
 
+/* ---- the pressure-correction steps around the solve (Sec. 2) ----
+ *
+ * The substep of the paper's projection method: the right-hand side
+ * div(u*) / (gamma_k dt) of Eq. (poi_ns), the solve, and the updates
+ * u = u* - gamma_k dt grad(Phi), p = p + Phi, on the staggered grid of the
+ * plan (its widths and boundary pairs; the boundary pair of Phi along an
+ * axis sets that of the normal velocity: P periodic, N an impermeable
+ * wall whose velocity the projection leaves as it is, D an open face with
+ * Phi = 0 on it).
+ *
+ * Layout (DEVICE arrays of doubles, x fastest): Phi, p and rhs at the
+ * cells, nx*ny*nz.  The velocity component along an axis on the faces
+ * normal to it: along a periodic axis of n cells n faces, face f between
+ * cells f-1 (cyclically) and f; along a walled axis n + 1 faces, face 0
+ * the low wall and face n the high wall.  So u is (nx + wx) x ny x nz, v
+ * nx x (ny + wy) x nz, w nx x ny x (nz + wz), with w_ = 1 on a walled axis.
+ * Face gradients use centre distances (the mean of the two widths) and,
+ * at a wall, the ghost rule of the solve (Neumann: zero gradient;
+ * Dirichlet: 2 Phi_edge / h_edge inward), so that the divergence of the
+ * gradient is the solve's operator and the projected velocity is
+ * divergence-free up to rounding.  When the operator is singular (no
+ * Dirichlet face) only a prediction whose net flux through the walls is
+ * zero can be made divergence-free; the solve removes the mean of the
+ * right-hand side as usual. */
+
+/* rhs = div(u, v, w) / gamma_dt at every cell (gamma_dt finite, non-zero).
+ * Enqueued on `stream`. */
+int projection_rhs(poisson_plan* plan, const double* u, const double* v, const double* w,
+                   double gamma_dt, double* rhs, hipStream_t stream);
+
+/* In place: u, v, w -= gamma_dt * grad(phi) on every face, p += phi at every
+ * cell.  Enqueued on `stream`. */
+int projection_update(poisson_plan* plan, const double* phi, double gamma_dt, double* u,
+                      double* v, double* w, double* p, hipStream_t stream);
+
+/* The whole step on `stream`: projection_rhs into phi (caller-owned, DEVICE,
+ * nx*ny*nz doubles), solve(plan, phi) in the plan's precision mode, then
+ * projection_update.  On return phi holds the correction pressure. */
+int pressure_correction(poisson_plan* plan, double* u, double* v, double* w, double* p,
+                        double gamma_dt, double* phi, hipStream_t stream);
+
 /* ---- refined solve that allocates nothing ----
  *
  * For callers that cannot allocate device memory: code under HIP graph

@@ -12,6 +12,9 @@ the host; it is the test reference, timed nowhere here):
 * batch   - 64 uneven instances (sizes per axis from {64, 96, 128, 192,
             256}, random boundary pairs, half the walled z axes stretched) in
             one batched launch sequence against one solve at a time.
+* projection - one pressure-correction step (right-hand side of
+            Eq. (poi_ns), FP64 solve, velocity and pressure update) on the
+            channel grid.
 * serve   - continuous-batching server fed by Poisson arrivals at 80 % of
             its measured capacity: p50 / p99 latency and points/s, for 2, 4
             and 8 slots.
@@ -324,6 +327,69 @@ def batch(log, refs=None, with_oracle=True, count=64, steps=5, warmup=2, seed=0,
                              "rel_l2_vs_oracle_corrected": {f"instance {i}": v for i, v in rel32.items()}}}
 
 
+def projection(log, refs=None, with_oracle=True, steps=10, warmup=2):
+    """One pressure-correction step on the channel grid (512 x 256 x 192,
+    periodic x/y, walls in z): projection_rhs (32 B per cell: three face
+    arrays read, the right-hand side written), the FP64 solve (80 B per
+    cell) and projection_update (72 B per cell: Phi, the face arrays and p
+    read, the face arrays and p written), timed with events on one stream."""
+    import torch
+    from . import Plan, inputs
+    prob = inputs.channel(0)
+    N = prob.points
+    u, v, w = inputs.prediction_velocity(prob, 5)
+    src = [torch.from_numpy(a).cuda() for a in (u, v, w)]
+    p0 = torch.from_numpy(np.random.default_rng(6).uniform(-1, 1, prob.shape)).cuda()
+    work = [a.clone() for a in src]
+    pres = p0.clone()
+    phi = torch.empty(N, dtype=torch.float64, device="cuda")
+    plan = Plan.from_problem(prob)
+    gdt = 0.01
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.pressure_correction(*work, pres, gdt, phi)
+    times = {"rhs": [], "solve": [], "update": []}
+    for _ in range(steps):
+        for a, b in zip(work, src):
+            a.copy_(b)
+        pres.copy_(p0)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        plan.projection_rhs(*work, gdt, phi)
+        ev[1].record(stream)
+        plan.solve(phi)
+        ev[2].record(stream)
+        plan.projection_update(phi, gdt, *work, pres)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        for k, name in enumerate(("rhs", "solve", "update")):
+            times[name].append(ev[k].elapsed_time(ev[k + 1]))
+    ms = {k: float(np.median(t)) for k, t in times.items()}
+    total = sum(ms.values())
+    out = {"workload": "pressure-correction step on the channel grid 512x256x192 (P,P,NN; tanh z)",
+           "points": N, "rhs_ms": round(ms["rhs"], 4), "solve_ms": round(ms["solve"], 4),
+           "update_ms": round(ms["update"], 4), "step_ms": round(total, 4),
+           "points_per_s": N / (total * 1e-3),
+           "rhs_GBs": round(32.0 * N / (ms["rhs"] * 1e-3) / 1e9, 1),
+           "update_GBs": round(72.0 * N / (ms["update"] * 1e-3) / 1e9, 1),
+           "fused": False}
+    if with_oracle:
+        from oracle import projection as pj
+        ref = pj.pressure_correction(u, v, w, p0.cpu().numpy(), gdt, prob.hx, prob.hy, prob.hz,
+                                     prob.bcs)
+        got = [a.cpu().numpy() for a in work] + [pres.cpu().numpy()]
+        out["rel_l2_vs_oracle"] = max(_rel(g.reshape(r.shape), r) for g, r in zip(got, ref[:4]))
+        div = torch.empty_like(phi)
+        plan.projection_rhs(*work, 1.0, div)
+        out["divergence_after_over_before"] = float(
+            np.linalg.norm(div.cpu().numpy())
+            / np.linalg.norm(pj.divergence(u, v, w, prob.hx, prob.hy, prob.hz, prob.bcs)))
+    plan.close()
+    log(f"[forms] projection step (channel): rhs {ms['rhs']:.4f} ms, solve {ms['solve']:.4f} ms, "
+        f"update {ms['update']:.4f} ms; rel-L2 vs oracle {out.get('rel_l2_vs_oracle', float('nan')):.2e}")
+    return out
+
+
 def _serve_once(log, specs, order, slots, load, seed, window):
     """One server with `slots` streams: warm-up (every spec of the catalogue
     once, so every plan is cached), a closed loop over the timed requests
@@ -491,7 +557,7 @@ def serve(log, refs=None, with_oracle=True, count=2000, catalogue=200, seed=0,
 def run(wanted, log, refs=None, with_oracle=True):
     out = {}
     for name, fn in (("mixed", mixed), ("channel", channel), ("small", small),
-                     ("batch", batch), ("serve", serve)):
+                     ("projection", projection), ("batch", batch), ("serve", serve)):
         if name in wanted:
             out[name] = fn(log, refs, with_oracle)
     return out

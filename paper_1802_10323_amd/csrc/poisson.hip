@@ -25,6 +25,7 @@
 #include "batch_kernels.h"
 #include "async_launch.h"
 #include "refine_kernels.h"
+#include "projection.h"
 
 using namespace poisson_dev;
 
@@ -145,6 +146,7 @@ struct poisson_plan {
   size_t off_tri_d = 0, off_tri_f = 0;     // a, b, c, w   (4 n_s)
   size_t off_lam_d = 0, off_lam_f = 0;     // lamu, lamv
   size_t off_ops[3] = {0, 0, 0};           // per axis: a, b, c, h (FP64, residual)
+  size_t off_proj[3] = {0, 0, 0};          // per axis: 1/h (n), 1/centre distance (n + 1)
   int nu = 0, nv = 0;
   int P = 1, lcmax = 1;
   char* dtab = nullptr;        // device tables
@@ -869,6 +871,21 @@ extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double d
       axis_rows(axis_widths(p, q), bcs[q], ops.data());
       p->off_ops[q] = push(ops.data(), ops.size() * sizeof(double));
     }
+    for (int q = 0; q < 3; ++q) {   // projection: 1/h per cell, 1/centre distance per face
+      const std::vector<double> hs = axis_widths(p, q);
+      const int n = (int)hs.size();
+      std::vector<double> t(2 * (size_t)n + 1);
+      for (int k = 0; k < n; ++k) t[k] = 1.0 / hs[k];
+      double* idc = t.data() + n;
+      for (int f = 1; f < n; ++f) idc[f] = 1.0 / (0.5 * (hs[f - 1] + hs[f]));
+      if (bcs[q] == BC_PERIODIC) {
+        idc[0] = idc[n] = 1.0 / (0.5 * (hs[n - 1] + hs[0]));
+      } else {
+        idc[0] = 1.0 / hs[0];
+        idc[n] = 1.0 / hs[n - 1];
+      }
+      p->off_proj[q] = push(t.data(), t.size() * sizeof(double));
+    }
     std::vector<double> lam;
     for (int r = 0; r < 2; ++r) {
       const AxisTables& A = p->ax[r];
@@ -1231,6 +1248,53 @@ extern "C" int solve_refined_noalloc(poisson_plan* p, double* rhs, double tol, i
     HIP_TRY(hipGetLastError());
   }
   return POISSON_OK;
+}
+
+// ------------------------------------------------------------------ projection
+
+static ProjGeom proj_geom(const poisson_plan* p) {
+  ProjGeom G{};
+  for (int q = 0; q < 3; ++q) {
+    const int n = p->dims[q];
+    const double* t = reinterpret_cast<const double*>(p->dtab + p->off_proj[q]);
+    const int kind = p->bc[q];
+    G.ax[q] = ProjAxis{t, t + n, n, kind != BC_PERIODIC ? 1 : 0,
+                       kind == BC_DD || kind == BC_DN ? 1 : 0, kind == BC_DD || kind == BC_ND ? 1 : 0};
+  }
+  G.npts = (long long)field_points(p);
+  return G;
+}
+
+static int proj_blocks(const poisson_plan* p) {
+  return (int)std::max<long long>(1, std::min<long long>(PROJ_BLOCKS, ((long long)field_points(p) + PROJ_NT - 1) / PROJ_NT));
+}
+
+extern "C" int projection_rhs(poisson_plan* p, const double* u, const double* v, const double* w,
+                              double gamma_dt, double* rhs, hipStream_t st) {
+  if (!p || !u || !v || !w || !rhs) return fail(POISSON_EINVAL, "null argument");
+  if (!(gamma_dt != 0.0) || !std::isfinite(gamma_dt)) return fail(POISSON_EINVAL, "gamma_dt must be finite and non-zero");
+  hipLaunchKernelGGL(proj_rhs_kernel, dim3(proj_blocks(p)), dim3(PROJ_NT), 0, st, u, v, w,
+                     1.0 / gamma_dt, rhs, proj_geom(p));
+  HIP_TRY(hipGetLastError());
+  return POISSON_OK;
+}
+
+extern "C" int projection_update(poisson_plan* p, const double* phi, double gamma_dt, double* u,
+                                 double* v, double* w, double* pres, hipStream_t st) {
+  if (!p || !phi || !u || !v || !w || !pres) return fail(POISSON_EINVAL, "null argument");
+  if (!std::isfinite(gamma_dt)) return fail(POISSON_EINVAL, "gamma_dt must be finite");
+  hipLaunchKernelGGL(proj_update_kernel, dim3(proj_blocks(p)), dim3(PROJ_NT), 0, st, phi, gamma_dt,
+                     u, v, w, pres, proj_geom(p));
+  HIP_TRY(hipGetLastError());
+  return POISSON_OK;
+}
+
+extern "C" int pressure_correction(poisson_plan* p, double* u, double* v, double* w, double* pres,
+                                   double gamma_dt, double* phi, hipStream_t st) {
+  int rc;
+  if ((rc = projection_rhs(p, u, v, w, gamma_dt, phi, st))) return rc;
+  if ((rc = solve(p, phi, st))) return rc;
+  return projection_update(p, phi, gamma_dt, u, v, w, pres, st);
 }
 
 // ------------------------------------------------------------------ batch

@@ -228,3 +228,33 @@ def served_request(seed, i, lo=32, hi=512, beta=1.8, max_points=None, with_rhs=T
                      stretch_z=stretch, name=f"req{i}", with_rhs=with_rhs)
     p.mixed = mixed
     return p
+
+
+def face_shape(comp, nx, ny, nz, bcs):
+    """(nz, ny, nx)-order shape of the face array of velocity component comp
+    ('x', 'y' or 'z'): n faces along a periodic axis of n cells, n + 1 along
+    a walled one."""
+    dims = {"x": nx, "y": ny, "z": nz}
+    kind = dict(zip("xyz", bcs))[comp]
+    dims[comp] += 0 if kind == "P" else 1
+    return (dims["z"], dims["y"], dims["x"])
+
+
+def prediction_velocity(prob, seed, amplitude=1.0):
+    """Seeded face velocities (u, v, w) ~ amplitude * U[-1, 1] on the faces
+    of `prob`'s grid, zero on the faces of impermeable walls (the Neumann
+    letter of a boundary pair), so that the net flux through the walls is
+    zero."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for comp, ax in (("x", 2), ("y", 1), ("z", 0)):
+        shape = face_shape(comp, prob.nx, prob.ny, prob.nz, prob.bcs)
+        vel = amplitude * rng.uniform(-1.0, 1.0, size=shape)
+        kind = dict(zip("xyz", prob.bcs))[comp]
+        if kind != "P":
+            if kind[0] == "N":
+                np.moveaxis(vel, ax, 0)[0] = 0.0
+            if kind[1] == "N":
+                np.moveaxis(vel, ax, 0)[-1] = 0.0
+        out.append(vel)
+    return out

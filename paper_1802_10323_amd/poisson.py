@@ -60,6 +60,9 @@ SIGNATURES = {
     "server_usage": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t),
                                     ctypes.POINTER(ctypes.c_size_t)]),
     "server_destroy": (None, [_VP]),
+    "projection_rhs": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
+    "projection_update": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP, _VP]),
+    "pressure_correction": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
     "refined_noalloc_max_points": (ctypes.c_size_t, []),
     "solve_refined_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP, _VP]),
 }
@@ -174,6 +177,49 @@ class Plan:
         _check(lib().solve_refined_noalloc(self.handle, _field_ptr(field), float(tol),
                                            int(max_iters), sp, _stream_handle(stream)))
         return field
+
+    def velocity_shapes(self):
+        """Shapes (z, y, x order) of the face arrays u, v, w: one more face
+        along a walled axis than cells."""
+        nz, ny, nx = self.shape
+        walled = [0 if (b == "P" or b == 0) else 1 for b in self.bcs]
+        return ((nz, ny, nx + walled[0]), (nz, ny + walled[1], nx), (nz + walled[2], ny, nx))
+
+    def _check_velocity(self, u, v, w):
+        for t, shp, name in zip((u, v, w), self.velocity_shapes(), "uvw"):
+            if t.numel() != int(np.prod(shp)):
+                raise ValueError(f"{name} has {t.numel()} values, expected shape {shp}")
+
+    def projection_rhs(self, u, v, w, gamma_dt, rhs, stream=None):
+        """rhs = div(u, v, w) / gamma_dt (Eq. (poi_ns)) at the cells."""
+        self._check_velocity(u, v, w)
+        if rhs.numel() != int(np.prod(self.shape)):
+            raise ValueError("rhs size does not match the grid")
+        _check(lib().projection_rhs(self.handle, _field_ptr(u), _field_ptr(v), _field_ptr(w),
+                                    float(gamma_dt), _field_ptr(rhs), _stream_handle(stream)))
+        return rhs
+
+    def projection_update(self, phi, gamma_dt, u, v, w, p, stream=None):
+        """In place: u, v, w -= gamma_dt grad(phi); p += phi."""
+        self._check_velocity(u, v, w)
+        for t in (phi, p):
+            if t.numel() != int(np.prod(self.shape)):
+                raise ValueError("cell field size does not match the grid")
+        _check(lib().projection_update(self.handle, _field_ptr(phi), float(gamma_dt),
+                                       _field_ptr(u), _field_ptr(v), _field_ptr(w),
+                                       _field_ptr(p), _stream_handle(stream)))
+
+    def pressure_correction(self, u, v, w, p, gamma_dt, phi, stream=None):
+        """The whole pressure-correction step; phi (cell field) receives the
+        correction pressure."""
+        self._check_velocity(u, v, w)
+        for t in (phi, p):
+            if t.numel() != int(np.prod(self.shape)):
+                raise ValueError("cell field size does not match the grid")
+        _check(lib().pressure_correction(self.handle, _field_ptr(u), _field_ptr(v), _field_ptr(w),
+                                         _field_ptr(p), float(gamma_dt), _field_ptr(phi),
+                                         _stream_handle(stream)))
+        return phi
 
     def set_precision(self, mode, tol=1e-10, max_iters=4):
         _check(lib().plan_set_precision(self.handle, int(mode), float(tol), int(max_iters)))
