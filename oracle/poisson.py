@@ -22,10 +22,11 @@ from . import tridiagonal as td
 AXIS = {"x": 2, "y": 1, "z": 0}
 
 
-def is_singular(bcx, bcy, bcz):
+def is_singular(bcx, bcy, bcz, shift=0.0):
     """The operator has a null space (the constants) iff no face is Dirichlet,
-    i.e. every axis is periodic or Neumann-Neumann."""
-    return all(k in ("P", "NN") for k in (bcx, bcy, bcz))
+    i.e. every axis is periodic or Neumann-Neumann (staggered or on nodes),
+    and there is no Helmholtz shift."""
+    return shift == 0.0 and all(k in ("P", "NN", "NNn") for k in (bcx, bcy, bcz))
 
 
 def volume_weights(hx, hy, hz):
@@ -41,12 +42,14 @@ def weighted_mean(f, hx, hy, hz):
     return float((w * f).sum() / w.sum())
 
 
-def apply_operator(phi, hx, hy, hz, bcx, bcy, bcz):
+def apply_operator(phi, hx, hy, hz, bcx, bcy, bcz, shift=0.0):
     """(A phi)[k, j, i]: the seven-point operator of Eq. (poi), with the
     one-dimensional rows of ``tridiagonal.coefficients`` along each axis
-    (uniform widths give exactly the central differences of Eq. (poi))."""
+    (uniform widths give exactly the central differences of Eq. (poi)),
+    plus ``shift`` * phi (the Helmholtz operator of an implicit diffusion
+    step, Sec. 2)."""
     phi = np.asarray(phi, dtype=np.float64)
-    out = np.zeros_like(phi)
+    out = shift * phi
     for name, h, kind in (("x", hx, bcx), ("y", hy, bcy), ("z", hz, bcz)):
         ax = AXIS[name]
         a, b, c, periodic = td.coefficients(h, kind)
@@ -62,12 +65,12 @@ def apply_operator(phi, hx, hy, hz, bcx, bcy, bcz):
     return out
 
 
-def residual(f, phi, hx, hy, hz, bcx, bcy, bcz):
+def residual(f, phi, hx, hy, hz, bcx, bcy, bcz, shift=0.0):
     """r = f - A phi (f projected first when the operator is singular)."""
     f = np.asarray(f, dtype=np.float64)
-    if is_singular(bcx, bcy, bcz):
+    if is_singular(bcx, bcy, bcz, shift):
         f = f - weighted_mean(f, hx, hy, hz)
-    return f - apply_operator(phi, hx, hy, hz, bcx, bcy, bcz)
+    return f - apply_operator(phi, hx, hy, hz, bcx, bcy, bcz, shift)
 
 
 def _uniform_spacing(h):
@@ -106,19 +109,27 @@ def tridiagonal_stage(fhat, s, hs, bcs, lam1, lam2, t1, t2, singular):
     return np.ascontiguousarray(np.transpose(x, inv))
 
 
-def solve(f, hx, hy, hz, bcx, bcy, bcz, roles=("x", "y", "z")):
+def solve(f, hx, hy, hz, bcx, bcy, bcz, roles=("x", "y", "z"), shift=0.0):
     """Phi with A Phi = f (f projected onto the range of A when A is
     singular; then Phi has zero volume-weighted mean).
 
     ``hx``, ``hy``, ``hz`` are the cell widths along each axis (arrays);
     ``roles`` = (t1, t2, s) names the two transformed axes, in the order they
     are transformed, and the Gauss-elimination axis.  Any role assignment
-    gives the same Phi up to rounding, as long as t1 and t2 are uniform."""
+    gives the same Phi up to rounding, as long as t1 and t2 are uniform.
+
+    ``shift`` (<= 0) solves the Helmholtz equation (A + shift) Phi = f of an
+    implicit diffusion step instead (Sec. 2); it joins the eigenvalue shift
+    of every reduced system.  Node pairs (DDn, NNn) are the non-staggered
+    transforms such steps need (Sec. 2.1); a singular problem with a node
+    pair has no volume-weighted gauge here and is refused."""
     f = np.asarray(f, dtype=np.float64)
     t1, t2, s = roles
     h = {"x": np.asarray(hx, float), "y": np.asarray(hy, float), "z": np.asarray(hz, float)}
     bc = {"x": bcx, "y": bcy, "z": bcz}
-    singular = is_singular(bcx, bcy, bcz)
+    singular = is_singular(bcx, bcy, bcz, shift)
+    if singular and any(k in td.NODE_KINDS for k in (bcx, bcy, bcz)):
+        raise ValueError("a singular problem with a node boundary pair is not supported")
     if singular:                                        # compatibility (projection)
         f = f - weighted_mean(f, hx, hy, hz)
     d1 = _uniform_spacing(h[t1])
@@ -127,7 +138,7 @@ def solve(f, hx, hy, hz, bcx, bcy, bcz, roles=("x", "y", "z")):
     g = tr.forward(f, AXIS[t1], bc[t1])
     g = tr.forward(g, AXIS[t2], bc[t2])
     # step 2: tridiagonal systems along s
-    lam1 = tr.eigenvalues(bc[t1], f.shape[AXIS[t1]]) / d1 ** 2
+    lam1 = tr.eigenvalues(bc[t1], f.shape[AXIS[t1]]) / d1 ** 2 + shift
     lam2 = tr.eigenvalues(bc[t2], f.shape[AXIS[t2]]) / d2 ** 2
     g = tridiagonal_stage(g, s, h[s], bc[s], lam1, lam2, t1, t2, singular)
     # step 3: backward transforms, t2 then t1
@@ -136,7 +147,7 @@ def solve(f, hx, hy, hz, bcx, bcy, bcz, roles=("x", "y", "z")):
     return g
 
 
-def solve_corrected(f, hx, hy, hz, bcx, bcy, bcz, roles=("x", "y", "z"), phi=None):
+def solve_corrected(f, hx, hy, hz, bcx, bcy, bcz, roles=("x", "y", "z"), phi=None, shift=0.0):
     """``solve`` followed by one correction with its own FP64 residual:
     Phi1 = solve(f), Phi = Phi1 + solve(f - A Phi1).
 
@@ -153,6 +164,6 @@ def solve_corrected(f, hx, hy, hz, bcx, bcy, bcz, roles=("x", "y", "z"), phi=Non
     comparisons at the largest sizes.  ``phi``: the plain solve of the same
     problem (with the same roles), if already computed."""
     if phi is None:
-        phi = solve(f, hx, hy, hz, bcx, bcy, bcz, roles=roles)
-    r = residual(f, phi, hx, hy, hz, bcx, bcy, bcz)
-    return phi + solve(r, hx, hy, hz, bcx, bcy, bcz, roles=roles)
+        phi = solve(f, hx, hy, hz, bcx, bcy, bcz, roles=roles, shift=shift)
+    r = residual(f, phi, hx, hy, hz, bcx, bcy, bcz, shift)
+    return phi + solve(r, hx, hy, hz, bcx, bcy, bcz, roles=roles, shift=shift)

@@ -18,10 +18,19 @@ Readings of the paper used here (each listed in the design notes):
   and wavenumber l, so that (1/n) IDFT inverts the DFT (Table 1).
 * D-N (Dirichlet at the low face, Neumann at the high face) is not listed in
   Table 1; it is the DST-IV, with the same angles as N-D.
+* Non-staggered pairs (Sec. 2.1 says they are needed when diffusion is
+  integrated implicitly; the paper gives no table).  The unknowns sit on
+  grid nodes: "DDn" has m interior nodes between two boundary nodes where
+  the value is zero (DST-I), "NNn" has m nodes whose end nodes carry a zero
+  gradient through a mirrored neighbour, x_{-1} = x_1 (DCT-I).  The sums
+  are the textbook DST-I and DCT-I; the eigenvalues of the second
+  difference with those end rules are -4 sin^2 of pi (q+1) / (2(m+1)) and of
+  pi q / (2(m-1)).
 """
 import numpy as np
 
 KINDS = ("P", "NN", "DD", "ND", "DN")
+NODE_KINDS = ("DDn", "NNn")
 
 
 def _cos_sin(n, M):
@@ -63,6 +72,17 @@ def forward_matrix(kind, n):
     if kind == "DN":   # 2 sum a_p sin(pi (p+1/2) (q+1/2) / n)
         _, s = _cos_sin(n, (2 * p + 1) * (2 * q + 1))
         return 2.0 * s
+    if kind == "DDn":  # DST-I: 2 sum a_p sin(pi (p+1)(q+1) / (n+1)); angle = pi*M/(4(n+1))
+        _, s = _cos_sin(n + 1, 4 * (p + 1) * (q + 1))
+        return 2.0 * s
+    if kind == "NNn":  # DCT-I: a_0 + (-1)^q a_{n-1} + 2 sum_{p=1}^{n-2} a_p cos(pi p q / (n-1))
+        if n < 2:
+            raise ValueError("a DCT-I needs at least 2 nodes")
+        c, _ = _cos_sin(n - 1, 4 * p * q)
+        T = 2.0 * c
+        T[:, 0] = 1.0
+        T[:, n - 1] = (-1.0) ** np.arange(n)
+        return T
     raise ValueError(f"unknown boundary pair {kind!r}")
 
 
@@ -96,6 +116,10 @@ def backward_matrix(kind, n):
         return B / (2.0 * n)
     if kind in ("ND", "DN"):   # DCT-IV and DST-IV are their own inverses up to 2n
         return forward_matrix(kind, n) / (2.0 * n)
+    if kind == "DDn":          # DST-I is its own inverse up to 2(n+1)
+        return forward_matrix(kind, n) / (2.0 * (n + 1))
+    if kind == "NNn":          # DCT-I is its own inverse up to 2(n-1)
+        return forward_matrix(kind, n) / (2.0 * (n - 1))
     raise ValueError(f"unknown boundary pair {kind!r}")
 
 
@@ -104,9 +128,16 @@ def eigenvalues(kind, n):
 
     P: theta_0 = 0, theta_{2l-1} = theta_{2l} = l*pi/n, theta_{n-1} = pi/2.
     NN: q*pi/(2n).  DD: (q+1)*pi/(2n).  ND and DN: (2q+1)*pi/(4n).
-    Each theta is pi*M/(4n) with the integer M below.
+    Each theta is pi*M/(4n) with the integer M below.  Node pairs: DDn
+    (q+1)*pi/(2(n+1)), NNn q*pi/(2(n-1)).
     """
     q = np.arange(n)
+    if kind == "DDn":
+        _, s = _cos_sin(n + 1, 2 * (q + 1))
+        return -4.0 * s * s
+    if kind == "NNn":
+        _, s = _cos_sin(n - 1, 2 * q)
+        return -4.0 * s * s
     if kind == "P":
         if n % 2:
             raise ValueError("periodic transforms need an even n")

@@ -29,11 +29,16 @@ Readings of the paper used here (each listed in the design notes):
   silent): the last equation of the zero-wavenumber column is dropped and its
   unknown set to zero, the remaining system is solved, and the volume-weighted
   mean is then subtracted.
+* Non-staggered (node) pairs, uniform spacing h only: DDn, the neighbours
+  beyond the two ends are boundary nodes with value zero (no ghost term);
+  NNn, the neighbour beyond an end node mirrors the node next to it
+  (x_{-1} = x_1), so the end rows read 2 (x_1 - x_0) / h^2.
 """
 import numpy as np
 
 LOW = {"P": "P", "NN": "N", "DD": "D", "ND": "N", "DN": "D"}
 HIGH = {"P": "P", "NN": "N", "DD": "D", "ND": "D", "DN": "N"}
+NODE_KINDS = ("DDn", "NNn")
 
 
 def coefficients(h, kind):
@@ -43,6 +48,19 @@ def coefficients(h, kind):
     to x_0; otherwise a[0] = c[n-1] = 0 and the ghost rule is folded into b."""
     h = np.asarray(h, dtype=np.float64)
     n = h.size
+    if kind in NODE_KINDS:
+        if not np.all(h == h[0]):
+            raise ValueError("node boundary pairs need a uniform spacing")
+        inv = 1.0 / (h[0] * h[0])
+        a = np.full(n, inv)
+        c = np.full(n, inv)
+        b = np.full(n, -2.0 * inv)
+        a[0] = 0.0
+        c[n - 1] = 0.0
+        if kind == "NNn" and n > 1:   # mirrored neighbours beyond the end nodes
+            c[0] = 2.0 * inv
+            a[n - 1] = 2.0 * inv
+        return a, b, c, False
     periodic = kind == "P"
     dc = np.empty(n + 1)
     dc[1:n] = 0.5 * (h[:-1] + h[1:])
