@@ -161,7 +161,7 @@ def main():
     ap.add_argument("--workload", default="cube", choices=["cube", "channel", "small"])
     ap.add_argument("--forms", default="all",
                     help="extra forms to measure: none, or a comma list of "
-                         "mixed,channel,small,projection,batch,serve (all)")
+                         "mixed,channel,small,projection,helmholtz,batch,serve (all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -233,7 +233,8 @@ def main():
 
     forms = {}
     wanted = set() if args.forms == "none" else (
-        {"mixed", "channel", "small", "projection", "batch", "serve"} if args.forms == "all"
+        {"mixed", "channel", "small", "projection", "helmholtz", "batch", "serve"}
+        if args.forms == "all"
         else set(args.forms.split(",")))
     if wanted:
         from paper_1802_10323_amd import benchforms

@@ -49,7 +49,17 @@ enum poisson_bc {
   BC_NN = 1,
   BC_DD = 2,
   BC_ND = 3,
-  BC_DN = 4
+  BC_DN = 4,
+  /* Non-staggered (node) pairs, for the Helmholtz equations of an implicit
+   * diffusion step (Sec. 2; Sec. 2.1 notes they need non-staggered
+   * transforms): the n unknowns of the axis sit on grid nodes, spaced
+   * uniformly by the axis spacing.  BC_DD_NODE: zero on the two boundary
+   * nodes just beyond the ends (DST-I); BC_NN_NODE: the end nodes have a
+   * mirrored neighbour, x_{-1} = x_1 (DCT-I).  Along z they need a uniform
+   * dz.  A problem that would be singular (no Dirichlet face, no shift)
+   * with a node pair is refused. */
+  BC_DD_NODE = 5,
+  BC_NN_NODE = 6
 };
 
 enum poisson_status {
@@ -83,6 +93,18 @@ typedef struct poisson_plan poisson_plan;
  * Returns NULL on error (see last_error()). */
 poisson_plan* plan_create(int nx, int ny, int nz, double dx, double dy, const double* dz,
                           int bc_x, int bc_y, int bc_z);
+
+/* Plan for the Helmholtz equation (A + shift) Phi = f, A the operator of
+ * plan_create: the equations of an implicit (Crank-Nicolson) diffusion step
+ * of Sec. 2, shift = -2 / (nu dt) for one velocity component.  shift <= 0
+ * (finite); shift = 0 is plan_create.  Transformed axes of a node pair run
+ * the DST-I / DCT-I through a real FFT of length 2(n+1) / 2(n-1), whose
+ * half must have no prime factor above 5 (and be at most 512).  Everything
+ * else as plan_create, including solve(), the FP32 + refinement mode and
+ * the stage entry points; batches and the projection steps take staggered
+ * pairs only. */
+poisson_plan* plan_create_helmholtz(int nx, int ny, int nz, double dx, double dy, const double* dz,
+                                    int bc_x, int bc_y, int bc_z, double shift);
 
 /* Solve in place.  rhs: DEVICE pointer to nx*ny*nz doubles (x fastest), on the
  * plan's device, overwritten with Phi.  When no face is Dirichlet the operator

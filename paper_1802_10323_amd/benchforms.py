@@ -15,6 +15,10 @@ the host; it is the test reference, timed nowhere here):
 * projection - one pressure-correction step (right-hand side of
             Eq. (poi_ns), FP64 solve, velocity and pressure update) on the
             channel grid.
+* helmholtz - Helmholtz solves (A + shift) Phi = f of an implicit
+            diffusion step: the wall-normal velocity of a channel (node
+            Dirichlet pair along z, 512 x 256 x 191 interior nodes) and a
+            field whose x axis carries a node pair (DST-I of 255 nodes).
 * serve   - continuous-batching server fed by Poisson arrivals at 80 % of
             its measured capacity: p50 / p99 latency and points/s, for 2, 4
             and 8 slots.
@@ -390,6 +394,49 @@ def projection(log, refs=None, with_oracle=True, steps=10, warmup=2):
     return out
 
 
+def helmholtz(log, refs=None, with_oracle=True, steps=10, warmup=2):
+    """FP64 Helmholtz solves, shift -2/(nu dt) = -2e4 (a Crank-Nicolson
+    step): (a) 512 x 256 x 191, periodic x/y, node Dirichlet pair along z
+    (uniform, Lz = 2): the transforms are the channel's, the elimination
+    runs on node rows; (b) 255 x 256 x 192, node Dirichlet pair along x
+    (DST-I through the size-generic transform), periodic y, walls in z."""
+    import torch
+    from . import Plan, inputs
+    out = {}
+    for name, shape, bcs, lengths in (
+            ("channel_w", (512, 256, 191), ("P", "P", "DDn"), (4 * np.pi, 2 * np.pi, 2.0 * 191 / 192)),
+            ("node_x", (255, 256, 192), ("DDn", "P", "DD"), (1.0, 1.0, 1.0))):
+        prob = inputs.make_uniform(*shape, bcs, seed=7, lengths=lengths)
+        prob.shift = -2.0e4
+        N = prob.points
+        src = torch.from_numpy(prob.rhs).cuda()
+        work = torch.empty_like(src)
+        plan = Plan.from_problem(prob)
+
+        def run():
+            work.copy_(src)
+            plan.solve(work)
+
+        for _ in range(warmup):
+            run()
+        copy_ms = float(np.median(_timed(lambda: work.copy_(src), steps, torch)))
+        t = float(np.median(_timed(run, steps, torch))) - copy_ms
+        run()
+        torch.cuda.synchronize()
+        res = {"shape": list(shape), "bcs": list(bcs), "shift": prob.shift, "roles": "".join(plan.roles),
+               "ms": round(t, 4), "points_per_s": N / (t * 1e-3),
+               "hbm_effective_frac": round(80.0 * N / (t * 1e-3) / 8e12, 4)}
+        if with_oracle:
+            import oracle
+            ref = oracle.solve(prob.rhs, prob.hx, prob.hy, prob.hz, *prob.bcs, shift=prob.shift)
+            res["rel_l2_vs_oracle"] = _rel(work.cpu().numpy(), ref)
+        plan.close()
+        out[name] = res
+        log(f"[forms] helmholtz {name} {shape} {bcs}: {t:.4f} ms, rel-L2 vs oracle "
+            f"{res.get('rel_l2_vs_oracle', float('nan')):.2e}")
+    return out
+
+
 def _serve_once(log, specs, order, slots, load, seed, window):
     """One server with `slots` streams: warm-up (every spec of the catalogue
     once, so every plan is cached), a closed loop over the timed requests
@@ -557,7 +604,8 @@ def serve(log, refs=None, with_oracle=True, count=2000, catalogue=200, seed=0,
 def run(wanted, log, refs=None, with_oracle=True):
     out = {}
     for name, fn in (("mixed", mixed), ("channel", channel), ("small", small),
-                     ("projection", projection), ("batch", batch), ("serve", serve)):
+                     ("projection", projection), ("helmholtz", helmholtz), ("batch", batch),
+                     ("serve", serve)):
         if name in wanted:
             out[name] = fn(log, refs, with_oracle)
     return out

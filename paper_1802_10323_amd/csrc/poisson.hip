@@ -95,6 +95,12 @@ static cplx<double> expm(long long M, long long n) {
 // Table 1: lambda_q = -4 sin^2(theta_q), theta_q = pi M_q / (4n).
 static double eigenvalue(int kind, int n, int q) {
   long long M;
+  if (kind == BC_DD_NODE || kind == BC_NN_NODE) {   // theta = pi(q+1)/(2(n+1)), pi q/(2(n-1))
+    double c, s;
+    if (kind == BC_DD_NODE) cos_sin_quarter(2LL * (q + 1), n + 1, c, s);
+    else cos_sin_quarter(2LL * q, n - 1, c, s);
+    return -4.0 * s * s;
+  }
   switch (kind) {
     case BC_PERIODIC: M = 4LL * ((q + 1) / 2); break;   // wavenumber of storage slot q
     case BC_NN: M = 2LL * q; break;
@@ -135,6 +141,7 @@ struct poisson_plan {
   double h[3];                 // uniform spacing (x, y) ; z uses dz
   std::vector<double> dz;
   bool z_uniform;
+  double shift = 0.0;          // Helmholtz shift: (A + shift) Phi = f
   bool generic_r2r = false;    // POISSON_GENERIC_R2R=1: size-generic transform kernel only
   bool generic_tri = false;    // POISSON_GENERIC_TRI=1: size-generic elimination kernel only
   int grid_cap = 0;            // POISSON_GRID_CAP=B: at most B blocks per stage launch (0: none)
@@ -167,6 +174,8 @@ struct poisson_plan {
 };
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+// Non-staggered (node) boundary pairs: DST-I / DCT-I transforms.
+static bool node_pair(int kind) { return kind == BC_DD_NODE || kind == BC_NN_NODE; }
 static constexpr size_t align_up_c(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // ------------------------------------------------------------------ variants
@@ -397,7 +406,7 @@ static R2RFastArgs<T> fast_args(const poisson_plan* p, const AxisTables& A, int 
   a.kind = A.kind;
   a.inverse = inverse;
   if (!inverse) a.scale = (T)1;
-  else a.scale = (T)(A.kind <= BC_DD ? 1.0 / A.n : 1.0 / (2.0 * A.n));
+  else a.scale = (T)(node_pair(A.kind) ? 1.0 / (2.0 * A.m) : A.kind <= BC_DD ? 1.0 / A.n : 1.0 / (2.0 * A.n));
   const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(p->dtab + (sizeof(T) == 8 ? A.off_d : A.off_f));
   a.tw_fft = tw;
   a.tw_split = tw + M;
@@ -505,14 +514,15 @@ static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hip
   const AxisTables& A = p->ax[role];
   if constexpr (sizeof(T) == 8) out64 = nullptr;
   t_grid_cap = p->grid_cap;
-  if (!p->generic_r2r) {
+  if (!p->generic_r2r && !node_pair(A.kind)) {
     const int rc = launch_fast_variant<T>(p, A, tuned_choice(0, sizeof(T), A.m, A.axis == 0),
                                           inverse, data, st, skip, out64);
     if (rc != -1) return rc;
   }
   constexpr int EMAX = sizeof(T) == 8 ? R2R_EMAX_D : R2R_EMAX_F;
   const int cap_reals = 2 * EMAX * R2R_NT;
-  const int lognl_max = ilog2(std::max(1, std::min(cap_reals / A.n, R2R_NT)));
+  const int rows = 2 * A.m;   // tile rows per line (node pairs: their extension)
+  const int lognl_max = ilog2(std::max(1, std::min(cap_reals / rows, R2R_NT)));
   R2RArgs<T> a{};
   a.data = data;
   a.g = make_geom(A.axis, p->dims, lognl_max);
@@ -529,7 +539,7 @@ static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hip
   a.nlp = (1 << a.g.lognl) | 1;
   a.n_magic = div_magic(A.n);
   if (!inverse) a.scale = (T)1;
-  else a.scale = (T)(A.kind <= BC_DD ? 1.0 / A.n : 1.0 / (2.0 * A.n));
+  else a.scale = (T)(node_pair(A.kind) ? 1.0 / (2.0 * A.m) : A.kind <= BC_DD ? 1.0 / A.n : 1.0 / (2.0 * A.n));
   const char* base = p->dtab + (sizeof(T) == 8 ? A.off_d : A.off_f);
   const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(base);
   a.tw_fft = tw;
@@ -539,7 +549,7 @@ static int launch_r2r(const poisson_plan* p, int role, int inverse, T* data, hip
   a.tw_post = tw + 4 * A.m + 2;
   a.skip = skip;
   a.out64 = out64;
-  const size_t lds = (size_t)A.n * a.nlp * sizeof(T);
+  const size_t lds = (size_t)rows * a.nlp * sizeof(T);
   if (lds > LDS_LIMIT) return fail(POISSON_EUNSUPPORTED, "transform tile needs %zu B of LDS", lds);
   const void* fn = reinterpret_cast<const void*>(&r2r_kernel<T, EMAX, R2R_NT>);
   hipLaunchKernelGGL((r2r_kernel<T, EMAX, R2R_NT>),
@@ -652,6 +662,7 @@ static bool tri_fast_length(int n) {
 // Complex length M of the size-specialised transform kernel for axis A, or
 // 0 if its length has none.
 static int r2r_fast_length(const AxisTables& A) {
+  if (node_pair(A.kind)) return 0;
   switch (A.m) {
     case 16: case 32: case 48: case 64: case 96: case 128: case 192: case 256: return A.m;
     default: return 0;
@@ -736,6 +747,24 @@ static std::vector<double> axis_widths(const poisson_plan* p, int q) {
 // c_{n-1} as the wrap couplings).  out = [a | b | c | h], each n long.
 static void axis_rows(const std::vector<double>& hs, int kind, double* out) {
   const int n = (int)hs.size();
+  if (node_pair(kind)) {   // uniform node spacing: zero beyond DD ends, mirrored beyond NN ends
+    double* a = out;
+    double* b = a + n;
+    double* c = b + n;
+    double* w = c + n;
+    const double inv = 1.0 / (hs[0] * hs[0]);
+    for (int k = 0; k < n; ++k) {
+      a[k] = k > 0 ? inv : 0.0;
+      c[k] = k < n - 1 ? inv : 0.0;
+      b[k] = -2.0 * inv;
+      w[k] = hs[k];
+    }
+    if (kind == BC_NN_NODE && n > 1) {
+      c[0] = 2.0 * inv;
+      a[n - 1] = 2.0 * inv;
+    }
+    return;
+  }
   const bool periodic = kind == BC_PERIODIC;
   std::vector<double> dc(n + 1);
   for (int k = 1; k < n; ++k) dc[k] = 0.5 * (hs[k - 1] + hs[k]);
@@ -776,6 +805,12 @@ static int choose_chunks(int n, int& P, int& lcmax) {
 
 extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double dy, const double* dz,
                                      int bc_x, int bc_y, int bc_z) {
+  return plan_create_helmholtz(nx, ny, nz, dx, dy, dz, bc_x, bc_y, bc_z, 0.0);
+}
+
+extern "C" poisson_plan* plan_create_helmholtz(int nx, int ny, int nz, double dx, double dy,
+                                               const double* dz, int bc_x, int bc_y, int bc_z,
+                                               double shift) {
   g_err = 0;
   g_msg[0] = 0;
   if (nx < 1 || ny < 1 || nz < 1) { fail(POISSON_EINVAL, "sizes must be >= 1 (got %d %d %d)", nx, ny, nz); return nullptr; }
@@ -783,7 +818,8 @@ extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double d
   if (!finite_pos(dx) || !finite_pos(dy)) { fail(POISSON_EINVAL, "dx, dy must be finite and > 0"); return nullptr; }
   const int bcs[3] = {bc_x, bc_y, bc_z};
   for (int i = 0; i < 3; ++i)
-    if (bcs[i] < BC_PERIODIC || bcs[i] > BC_DN) { fail(POISSON_EINVAL, "boundary pair %d out of range on axis %d", bcs[i], i); return nullptr; }
+    if (bcs[i] < BC_PERIODIC || bcs[i] > BC_NN_NODE) { fail(POISSON_EINVAL, "boundary pair %d out of range on axis %d", bcs[i], i); return nullptr; }
+  if (!std::isfinite(shift) || shift > 0.0) { fail(POISSON_EINVAL, "the Helmholtz shift must be finite and <= 0"); return nullptr; }
   for (int k = 0; k < nz; ++k)
     if (!finite_pos(dz[k])) { fail(POISSON_EINVAL, "dz[%d] must be finite and > 0", k); return nullptr; }
   if ((long long)nx * ny * nz > (1LL << 34)) { fail(POISSON_EUNSUPPORTED, "grid too large"); return nullptr; }
@@ -803,6 +839,12 @@ extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double d
     p->grid_cap = env ? std::max(0, std::atoi(env)) : 0;
   }
   for (int k = 1; k < nz; ++k) if (dz[k] != dz[0]) p->z_uniform = false;
+  p->shift = shift;
+  if (node_pair(bc_z) && !p->z_uniform) {
+    fail(POISSON_EUNSUPPORTED, "a node boundary pair needs a uniform spacing (z)");
+    delete p;
+    return nullptr;
+  }
 
   // axis roles (elimination axis s; the others transformed, in x, y, z order)
   if (!p->z_uniform || bc_z != BC_PERIODIC) p->s = 2;
@@ -813,9 +855,15 @@ extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double d
   for (int i = 0; i < 3; ++i) if (i != p->s) t[nt++] = i;
   p->t1 = t[0];
   p->t2 = t[1];
-  p->singular = true;
-  for (int i = 0; i < 3; ++i) if (bcs[i] != BC_PERIODIC && bcs[i] != BC_NN) p->singular = false;
+  p->singular = shift == 0.0;
+  for (int i = 0; i < 3; ++i)
+    if (bcs[i] != BC_PERIODIC && bcs[i] != BC_NN && bcs[i] != BC_NN_NODE) p->singular = false;
   p->s_periodic = bcs[p->s] == BC_PERIODIC;
+  if (p->singular && (node_pair(bc_x) || node_pair(bc_y) || node_pair(bc_z))) {
+    fail(POISSON_EUNSUPPORTED, "a singular problem with a node boundary pair (no Dirichlet face, no shift)");
+    delete p;
+    return nullptr;
+  }
 
   auto reject = [&](int code, const char* msg, int a) { fail(code, msg, a); delete p; return (poisson_plan*)nullptr; };
   for (int r = 0; r < 2; ++r) {
@@ -823,6 +871,14 @@ extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double d
     A.axis = t[r];
     A.n = p->dims[A.axis];
     A.kind = bcs[A.axis];
+    if (node_pair(A.kind)) {   // DST-I / DCT-I through a real DFT of length 2m
+      A.m = A.kind == BC_DD_NODE ? A.n + 1 : A.n - 1;
+      if (A.m < 1 || 2 * A.m > MAX_TRANSFORM_N)
+        return reject(POISSON_EUNSUPPORTED, "node axis length %d out of range", A.n);
+      if (!factor_radices(A.m, A.radices))
+        return reject(POISSON_EUNSUPPORTED, "node axis length %d: its FFT length has a prime factor > 5", A.n);
+      continue;
+    }
     if (A.n % 2 || A.n < 2 || A.n > MAX_TRANSFORM_N)
       return reject(POISSON_EUNSUPPORTED, "transformed axis length %d must be even and in [2, 1024]", A.n);
     A.m = A.n / 2;
@@ -847,7 +903,7 @@ extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double d
   };
   for (int r = 0; r < 2; ++r) {
     AxisTables& A = p->ax[r];
-    const int n = A.n, m = A.m;
+    const int m = A.m, n = 2 * m;   // n: the real length of the FFT (node pairs: their extension)
     std::vector<cplx<double>> tw;
     for (int t = 0; t < m; ++t) tw.push_back(expm(16LL * t, n));        // e^{-2 pi i t/m}
     for (int k = 0; k <= m; ++k) tw.push_back(expm(8LL * k, n));        // e^{-2 pi i k/n}
@@ -863,12 +919,15 @@ extern "C" poisson_plan* plan_create(int nx, int ny, int nz, double dx, double d
     const int ns_ = ns;
     std::vector<double> tri(4 * ns_);
     axis_rows(axis_widths(p, p->s), bcs[p->s], tri.data());
+    for (int k = 0; k < ns_; ++k) tri[ns_ + k] += shift;   // the Helmholtz shift joins every diagonal
     std::vector<float> trif(tri.begin(), tri.end());
     p->off_tri_d = push(tri.data(), tri.size() * sizeof(double));
     p->off_tri_f = push(trif.data(), trif.size() * sizeof(float));
     for (int q = 0; q < 3; ++q) {
       std::vector<double> ops(4 * (size_t)p->dims[q]);
       axis_rows(axis_widths(p, q), bcs[q], ops.data());
+      if (q == 0)   // the residual's operator: the shift once, on the x rows
+        for (int k = 0; k < p->dims[0]; ++k) ops[p->dims[0] + k] += shift;
       p->off_ops[q] = push(ops.data(), ops.size() * sizeof(double));
     }
     for (int q = 0; q < 3; ++q) {   // projection: 1/h per cell, 1/centre distance per face
@@ -1269,9 +1328,14 @@ static int proj_blocks(const poisson_plan* p) {
   return (int)std::max<long long>(1, std::min<long long>(PROJ_BLOCKS, ((long long)field_points(p) + PROJ_NT - 1) / PROJ_NT));
 }
 
+static bool staggered_plan(const poisson_plan* p) {
+  return !node_pair(p->bc[0]) && !node_pair(p->bc[1]) && !node_pair(p->bc[2]);
+}
+
 extern "C" int projection_rhs(poisson_plan* p, const double* u, const double* v, const double* w,
                               double gamma_dt, double* rhs, hipStream_t st) {
   if (!p || !u || !v || !w || !rhs) return fail(POISSON_EINVAL, "null argument");
+  if (!staggered_plan(p)) return fail(POISSON_EUNSUPPORTED, "projection needs staggered boundary pairs");
   if (!(gamma_dt != 0.0) || !std::isfinite(gamma_dt)) return fail(POISSON_EINVAL, "gamma_dt must be finite and non-zero");
   hipLaunchKernelGGL(proj_rhs_kernel, dim3(proj_blocks(p)), dim3(PROJ_NT), 0, st, u, v, w,
                      1.0 / gamma_dt, rhs, proj_geom(p));
@@ -1282,6 +1346,7 @@ extern "C" int projection_rhs(poisson_plan* p, const double* u, const double* v,
 extern "C" int projection_update(poisson_plan* p, const double* phi, double gamma_dt, double* u,
                                  double* v, double* w, double* pres, hipStream_t st) {
   if (!p || !phi || !u || !v || !w || !pres) return fail(POISSON_EINVAL, "null argument");
+  if (!staggered_plan(p)) return fail(POISSON_EUNSUPPORTED, "projection needs staggered boundary pairs");
   if (!std::isfinite(gamma_dt)) return fail(POISSON_EINVAL, "gamma_dt must be finite");
   hipLaunchKernelGGL(proj_update_kernel, dim3(proj_blocks(p)), dim3(PROJ_NT), 0, st, phi, gamma_dt,
                      u, v, w, pres, proj_geom(p));

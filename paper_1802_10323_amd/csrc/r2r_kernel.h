@@ -13,6 +13,14 @@
 //      e^{-i pi (4j+1)/(4n)}, FFT, then V_k = Z_k e^{-i pi k/n} gives
 //      y_2k = 2 Re V_k and y_{n-1-2k} = -2 Im V_k.
 //  DN (DST-IV): DST-IV(a)_k = (-1)^k DCT-IV(reversed a)_k.
+//  DDN (DST-I of n node values, the non-staggered Dirichlet pair): the real
+//      DFT of length n' = 2(n+1) of the odd extension (0, a, 0, -a reversed)
+//      holds 2 sum a_p sin(pi (p+1) q / (n+1)) in its sine slot 2q.
+//  NNN (DCT-I of n node values, the non-staggered Neumann pair): the real
+//      DFT of length n' = 2(n-1) of the even extension (a, a_{n-2} .. a_1)
+//      is the DCT-I: cosine slots 2q-1, slot 0 and slot n'-1.
+//      Both are their own inverses up to n', so the backward transform runs
+//      the same steps with the scale 1/n'.
 //
 // A kernel launch processes tiles of lines (see device_common.h).  Per tile:
 //   1. load: global -> LDS with the input permutation and sign of the type;
@@ -28,7 +36,7 @@
 
 namespace poisson_dev {
 
-enum Kind { K_P = 0, K_NN = 1, K_DD = 2, K_ND = 3, K_DN = 4 };
+enum Kind { K_P = 0, K_NN = 1, K_DD = 2, K_ND = 3, K_DN = 4, K_DDN = 5, K_NNN = 6 };
 
 template <typename T>
 struct R2RArgs {
@@ -36,7 +44,7 @@ struct R2RArgs {
   LineGeom g;
   int kind;
   int inverse;
-  int m;                     // n / 2
+  int m;                     // complex FFT length: n / 2 (node pairs: (n + 1) or (n - 1))
   int npass;
   int radix[16];
   unsigned ns_magic[16];     // ceil(2^32 / Ns) of each pass (Ns = product of earlier radices)
@@ -458,6 +466,29 @@ __device__ __noinline__ void r2r_load_tile(T* lds, const T* __restrict__ data, G
     const long long off = tile_elem<NT>(g, o, sbase, n_magic, tid, i, l, p);
     buf[i] = off >= 0 ? as_global(data)[off] : (T)0;
   }
+  if (kind >= K_DDN) {   // odd / even extension of the node values (n' = 2m rows)
+    const int m = kind == K_DDN ? g.n + 1 : g.n - 1;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      int l, p;
+      tile_elem<NT>(g, o, sbase, n_magic, tid, i, l, p);
+      if (p < g.n && l < (1 << g.lognl)) {
+        if (kind == K_DDN) {
+          lds[(p + 1) * nlp + l] = buf[i];
+          lds[(2 * m - 1 - p) * nlp + l] = -buf[i];
+        } else {
+          lds[p * nlp + l] = buf[i];
+          if (p > 0 && p < m) lds[(2 * m - p) * nlp + l] = buf[i];
+        }
+      }
+    }
+    if (kind == K_DDN)
+      for (int l = tid; l < (1 << g.lognl); l += NT) {
+        lds[l] = (T)0;
+        lds[m * nlp + l] = (T)0;
+      }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     int l, p;
@@ -486,8 +517,11 @@ __device__ __noinline__ void r2r_store_tile(const T* lds, O* __restrict__ data, 
     tile_elem<NT>(g, o, sbase, n_magic, tid, i, l, q);
     buf[i] = (T)0;
     if (q < g.n && l < (1 << g.lognl)) {
-      bool neg;
-      const int r = store_row(kind, inverse, q, g.n, neg);
+      bool neg = false;
+      int r;
+      if (kind == K_DDN) r = 2 * (q + 1);                       // sine slot of wavenumber q+1
+      else if (kind == K_NNN) r = q == 0 ? 0 : (q == g.n - 1 ? 2 * (g.n - 1) - 1 : 2 * q - 1);
+      else r = store_row(kind, inverse, q, g.n, neg);
       const T v = lds[r * nlp + l] * scale;
       buf[i] = neg ? -v : v;
     }
@@ -511,8 +545,10 @@ void r2r_kernel(R2RArgs<T> A) {
   T* lds = reinterpret_cast<T*>(smem_raw);
   const int tid = threadIdx.x;
   const LineGeom& g = A.g;
-  const int n = g.n, lognl = g.lognl, nlp = A.nlp;
+  const int lognl = g.lognl, nlp = A.nlp;
   const int kind = A.kind, inverse = A.inverse;
+  const bool node = kind >= K_DDN;     // node pairs: the forward real DFT in both directions
+  const int n = node ? 2 * A.m : g.n;  // rows of the tile
   T* __restrict__ data = A.data;
   const bool fwd_fft = !(inverse && kind <= K_DD);
 
@@ -521,16 +557,17 @@ void r2r_kernel(R2RArgs<T> A) {
     r2r_load_tile<T, 2 * EMAX, NT>(lds, data, GEOM_ARGS(g), tile, kind, inverse, nlp, A.n_magic, tid);
     __syncthreads();
 
-    if (kind >= K_ND) iv_pre<T, NT>(lds, A.m, lognl, nlp, A.tw_pre, tid);
-    else if (inverse)
+    if (kind == K_ND || kind == K_DN) iv_pre<T, NT>(lds, A.m, lognl, nlp, A.tw_pre, tid);
+    else if (inverse && !node)
       combine_inverse<T, EMAX, NT>(lds, kind, n, A.m, lognl, nlp, A.tw_split, A.tw_quarter, tid);
 
     if (fwd_fft) fft_all<T, true, EMAX, NT>(lds, A, lognl, nlp, tid);
     else fft_all<T, false, EMAX, NT>(lds, A, lognl, nlp, tid);
 
-    if (kind >= K_ND) iv_post<T, EMAX, NT>(lds, n, A.m, lognl, nlp, A.tw_post, tid);
-    else if (!inverse)
-      split_forward<T, EMAX, NT>(lds, kind, n, A.m, lognl, nlp, A.tw_split, A.tw_quarter, tid);
+    if (kind == K_ND || kind == K_DN) iv_post<T, EMAX, NT>(lds, n, A.m, lognl, nlp, A.tw_post, tid);
+    else if (!inverse || node)
+      split_forward<T, EMAX, NT>(lds, node ? (int)K_P : kind, n, A.m, lognl, nlp, A.tw_split,
+                                 A.tw_quarter, tid);
 
     bool widened = false;
     if constexpr (sizeof(T) == 4) {

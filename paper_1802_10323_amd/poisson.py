@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # POISSON_HIP_LIB selects another build of the same library (A/B timing)
 LIB_PATH = os.environ.get("POISSON_HIP_LIB") or os.path.join(HERE, "libpoisson_hip.so")
 
-BC = {"P": 0, "NN": 1, "DD": 2, "ND": 3, "DN": 4}
+BC = {"P": 0, "NN": 1, "DD": 2, "ND": 3, "DN": 4, "DDn": 5, "NNn": 6}
 AXES = "xyz"
 FP64 = 0
 FP32_REFINED = 1
@@ -26,6 +26,9 @@ SIGNATURES = {
     "plan_create": (_VP, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                           ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                           ctypes.c_int, ctypes.c_int]),
+    "plan_create_helmholtz": (_VP, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_double]),
     "solve": (ctypes.c_int, [_VP, _VP, _VP]),
     "plan_destroy": (None, [_VP]),
     "last_error": (ctypes.c_int, []),
@@ -131,21 +134,27 @@ class Plan:
     uniform with spacings dx, dy.  ``bcs`` = (bc_x, bc_y, bc_z), each one of
     "P", "NN", "DD", "ND", "DN" (first letter = low face)."""
 
-    def __init__(self, nx, ny, nz, dx, dy, dz, bcs):
+    def __init__(self, nx, ny, nz, dx, dy, dz, bcs, shift=0.0):
         L = lib()
         dz = np.ascontiguousarray(np.broadcast_to(np.asarray(dz, dtype=np.float64), (nz,)))
         self.shape = (nz, ny, nx)
         self.bcs = tuple(bcs)
+        self.shift = float(shift)
         codes = [BC[b] if isinstance(b, str) else int(b) for b in bcs]
-        h = L.plan_create(int(nx), int(ny), int(nz), float(dx), float(dy),
-                          dz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), *codes)
+        if self.shift == 0.0:
+            h = L.plan_create(int(nx), int(ny), int(nz), float(dx), float(dy),
+                              dz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), *codes)
+        else:   # the Helmholtz operator (A + shift)
+            h = L.plan_create_helmholtz(int(nx), int(ny), int(nz), float(dx), float(dy),
+                                        dz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), *codes,
+                                        self.shift)
         if not h:
             _check(L.last_error() or EINVAL)
         self._h = ctypes.c_void_p(h)
 
     @classmethod
     def from_problem(cls, p):
-        return cls(p.nx, p.ny, p.nz, p.dx, p.dy, p.hz, p.bcs)
+        return cls(p.nx, p.ny, p.nz, p.dx, p.dy, p.hz, p.bcs, getattr(p, "shift", 0.0))
 
     @property
     def handle(self):

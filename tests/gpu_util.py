@@ -37,7 +37,8 @@ def gpu_solve(prob, mixed=False, tol=1e-10, max_iters=4):
 
 def oracle_solve(prob, roles=("x", "y", "z")):
     import oracle
-    return oracle.solve(prob.rhs, prob.hx, prob.hy, prob.hz, *prob.bcs, roles=roles)
+    return oracle.solve(prob.rhs, prob.hx, prob.hy, prob.hz, *prob.bcs, roles=roles,
+                        shift=getattr(prob, "shift", 0.0))
 
 
 UNIT = 2.0 ** -53
