@@ -17,12 +17,15 @@ Modules:
   poisson      the seven-point operator (Eq. (poi)) and the three-step solve
   projection   the pressure-correction steps around the solve (Sec. 2):
                divergence, gradient, right-hand side and projection
+  navier_stokes  one low-storage RK3 step with a pressure correction per
+               substep (Sec. 2, Eq. (up)) on a tri-periodic grid: the
+               divergence-form advection-diffusion term and the substeps
 
 Every function is pinned by tests under ``tests/`` against things other than
 itself (library transforms, LAPACK's tridiagonal routine, exact rational
 elimination, dense solves, closed-form eigenfunctions).  Parity is not
 unpinned for any function here.
 """
-from . import transforms, tridiagonal, poisson, projection  # noqa: F401
+from . import transforms, tridiagonal, poisson, projection, navier_stokes  # noqa: F401
 from .poisson import (solve, solve_corrected, apply_operator, residual, is_singular,  # noqa: F401
                       weighted_mean)

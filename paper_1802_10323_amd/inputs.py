@@ -258,3 +258,31 @@ def prediction_velocity(prob, seed, amplitude=1.0):
                 np.moveaxis(vel, ax, 0)[-1] = 0.0
         out.append(vel)
     return out
+
+
+def taylor_green(n=512, U=1.0, L=1.0, with_pressure=True):
+    """The Taylor-Green vortex initial condition (Sec. 4.1, Table 3) on the
+    tri-periodic box [0, 2 pi L]^3 with n cells per axis:
+    u = U sin(x/L) cos(y/L) cos(z/L), v = -U cos(x/L) sin(y/L) cos(z/L),
+    w = 0, sampled where each component is stored (u[k, j, i] at
+    (i dx, (j + 1/2) dx, (k + 1/2) dx), v and w likewise on their own faces).
+
+    The pressure is not part of the stated condition; with_pressure gives
+    the one of the inviscid Taylor-Green flow at t = 0,
+    p = (U^2 / 16) (cos(2x/L) + cos(2y/L)) (cos(2z/L) + 2), at cell centres,
+    else zero.  Returns (u, v, w, p, dx), arrays indexed [k, j, i]."""
+    d = 2.0 * math.pi * L / n
+    face = np.arange(n, dtype=np.float64) * d / L
+    centre = (np.arange(n, dtype=np.float64) + 0.5) * d / L
+    X = (None, None, slice(None))                # broadcast along the last axis (x)
+    Y = (None, slice(None), None)
+    Z = (slice(None), None, None)
+    u = U * np.sin(face)[X] * np.cos(centre)[Y] * np.cos(centre)[Z]
+    v = -U * np.cos(centre)[X] * np.sin(face)[Y] * np.cos(centre)[Z]
+    w = np.zeros((n, n, n))
+    if with_pressure:
+        p = ((U * U / 16.0) * (np.cos(2 * centre)[X] + np.cos(2 * centre)[Y])
+             * (np.cos(2 * centre)[Z] + 2.0))
+    else:
+        p = np.zeros((n, n, n))
+    return u, v, w, p, d
