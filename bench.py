@@ -233,7 +233,7 @@ def main():
 
     forms = {}
     wanted = set() if args.forms == "none" else (
-        {"mixed", "channel", "small", "projection", "helmholtz", "batch", "serve"}
+        {"mixed", "channel", "small", "projection", "helmholtz", "taylor_green", "batch", "serve"}
         if args.forms == "all"
         else set(args.forms.split(",")))
     if wanted:

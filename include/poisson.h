@@ -361,6 +361,37 @@ int projection_update(poisson_plan* plan, const double* phi, double gamma_dt, do
 int pressure_correction(poisson_plan* plan, double* u, double* v, double* w, double* p,
                         double gamma_dt, double* phi, hipStream_t stream);
 
+/* ---- one Navier-Stokes time step (Sec. 2, Eq. (up) and the pressure
+ * correction of every substep) ----
+ *
+ * The low-storage three-substep Runge-Kutta scheme with alpha = {8/15,
+ * 5/12, 3/4}, beta = {0, -17/60, -5/12}, gamma = alpha + beta, on a plan
+ * periodic along every axis with uniform widths (the Taylor-Green case of
+ * Sec. 4.1); other plans give POISSON_EUNSUPPORTED.
+ *
+ * Fields (all DEVICE, caller-owned, x fastest, N = nx*ny*nz doubles each):
+ *   vel   3 N: u, v, w one after another; component c at (i, j, k) lives on
+ *         the low face of cell (i, j, k) normal to axis c.  In / out.
+ *   work  3 N: the prediction u* (scratch; overwritten).
+ *   ad    3 N: AD = -(u . grad) u + nu lap(u) of the substep (advection in
+ *         divergence form, second-order central differences).  Read by
+ *         substeps 2 and 3 (AD of the one before), written by substeps 1
+ *         and 2; substep 3 leaves it as it is.
+ *   p     N: the pressure p^{k-1/2} at cell centres; gains phi.  In / out.
+ *   phi   N: the correction pressure of the substep (zero mean).  Out.
+ * Arrays must not overlap.  Enqueued on `stream`; the solve uses the plan's
+ * precision mode.  dt > 0, nu >= 0 (POISSON_EINVAL otherwise). */
+
+/* Substep k (1, 2, 3): u* = u + dt (alpha_k AD + beta_k AD_prev -
+ * gamma_k grad p), phi = solve(div(u*) / (gamma_k dt)),
+ * u = u* - gamma_k dt grad phi, p += phi. */
+int rk3_substep(poisson_plan* plan, int k, double dt, double nu, double* vel, double* work,
+                double* ad, double* p, double* phi, hipStream_t stream);
+
+/* One time step: substeps 1, 2, 3 (gamma_1 + gamma_2 + gamma_3 = 1). */
+int rk3_step(poisson_plan* plan, double dt, double nu, double* vel, double* work, double* ad,
+             double* p, double* phi, hipStream_t stream);
+
 /* ---- refined solve that allocates nothing ----
  *
  * For callers that cannot allocate device memory: code under HIP graph

@@ -103,6 +103,20 @@ def widths(n, d):
     return np.full(n, float(d))
 
 
+def prediction(k, u, v, w, p, ad_prev, dt, nu, dx, dy, dz):
+    """Eq. (up) for substep k: u* = u + dt (alpha_k AD(u) + beta_k AD_prev
+    - gamma_k grad p).  Returns ((u*, v*, w*), ad), ad = AD(u)."""
+    a, b, g = ALPHA[k - 1], BETA[k - 1], GAMMA[k - 1]
+    nz, ny, nx = np.shape(u)
+    ad = advection_diffusion(u, v, w, dx, dy, dz, nu)
+    gp = pj.gradient(p, widths(nx, dx), widths(ny, dy), widths(nz, dz), PERIODIC)
+    star = []
+    for c in range(3):
+        prev = b * ad_prev[c] if k > 1 else 0.0
+        star.append(np.asarray((u, v, w)[c], float) + dt * (a * ad[c] + prev - g * gp[c]))
+    return tuple(star), ad
+
+
 def rk3_substep(k, u, v, w, p, ad_prev, dt, nu, dx, dy, dz):
     """Substep k (1, 2 or 3) of Eq. (up) and the pressure correction:
 
@@ -112,16 +126,10 @@ def rk3_substep(k, u, v, w, p, ad_prev, dt, nu, dx, dy, dz):
 
     ``ad_prev``: the AD of the previous substep (ignored for k = 1).
     Returns (u, v, w, p, ad, phi) with ad = AD(u) of this substep's input."""
-    a, b, g = ALPHA[k - 1], BETA[k - 1], GAMMA[k - 1]
+    g = GAMMA[k - 1]
     nz, ny, nx = np.shape(u)
     hx, hy, hz = widths(nx, dx), widths(ny, dy), widths(nz, dz)
-    ad = advection_diffusion(u, v, w, dx, dy, dz, nu)
-    gp = pj.gradient(p, hx, hy, hz, PERIODIC)
-    star = []
-    for c in range(3):
-        prev = b * ad_prev[c] if k > 1 else 0.0
-        star.append(np.asarray((u, v, w)[c], float) + dt * (a * ad[c] + prev - g * gp[c]))
-    us, vs, ws = star
+    (us, vs, ws), ad = prediction(k, u, v, w, p, ad_prev, dt, nu, dx, dy, dz)
     rhs = pj.projection_rhs(us, vs, ws, g * dt, hx, hy, hz, PERIODIC)
     phi = ps.solve(rhs, hx, hy, hz, *PERIODIC)
     u1, v1, w1, p1 = pj.project(us, vs, ws, p, phi, g * dt, hx, hy, hz, PERIODIC)

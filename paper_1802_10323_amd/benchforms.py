@@ -19,10 +19,14 @@ the host; it is the test reference, timed nowhere here):
             diffusion step: the wall-normal velocity of a channel (node
             Dirichlet pair along z, 512 x 256 x 191 interior nodes) and a
             field whose x axis carries a node pair (DST-I of 255 nodes).
+* taylor_green - one low-storage RK3 time step of the 512^3 Taylor-Green
+            vortex (tri-periodic, Re 1600): per substep the prediction, the
+            right-hand side, the FP64 solve and the update.
 * serve   - continuous-batching server fed by Poisson arrivals at 80 % of
             its measured capacity: p50 / p99 latency and points/s, for 2, 4
             and 8 slots.
 """
+import math
 import threading
 import time
 
@@ -437,6 +441,87 @@ def helmholtz(log, refs=None, with_oracle=True, steps=10, warmup=2):
     return out
 
 
+def taylor_green(log, refs=None, with_oracle=True, steps=5, warmup=1):
+    """One Runge-Kutta time step of the 512^3 Taylor-Green vortex (Re 1600,
+    tri-periodic 2 pi box, dt at 0.9 of the stability bound), FP64: per
+    substep the prediction (AD and u*, 80-104 B per cell), the right-hand
+    side (32 B), the solve and the update (72 B); timed with events per
+    substep on one stream.  The solve is timed alone on the same plan for
+    the split.  Checks: the energy budget of the start (dE/dt = -6 nu E)
+    and the divergence after the step, at full size on the GPU's result,
+    and one 64^3 step against the oracle."""
+    import torch
+    from . import Plan, inputs
+    n = 512
+    u, v, w, p, d = inputs.taylor_green(n)
+    N = n ** 3
+    nu = 1.0 / 1600
+    vmax = float(np.max(np.abs(u) + np.abs(v)))          # w = 0 at the start
+    dt = 0.9 * min(1.65 * d * d / nu, math.sqrt(3.0) * d / vmax)
+    plan = Plan(n, n, n, d, d, d, ("P", "P", "P"))
+    vel0 = torch.from_numpy(np.concatenate([u.reshape(-1), v.reshape(-1), w.reshape(-1)])).cuda()
+    p0 = torch.from_numpy(p.reshape(-1)).cuda()
+    e0 = 0.5 * float(torch.sum(vel0 * vel0))
+    del u, v, w, p
+    vel, pres = vel0.clone(), p0.clone()
+    work = torch.empty_like(vel0)
+    ad = torch.zeros_like(vel0)
+    phi = torch.empty_like(p0)
+    stream = torch.cuda.current_stream()
+    # the first step from the start, for the checks
+    plan.rk3_step(dt, nu, vel, work, ad, pres, phi)
+    torch.cuda.synchronize()
+    e1 = 0.5 * float(torch.sum(vel * vel))
+    plan.projection_rhs(vel[:N], vel[N:2 * N], vel[2 * N:], 1.0, phi)
+    div_rel = float(torch.max(torch.abs(phi))) / (float(torch.max(torch.abs(vel))) / d)
+    for _ in range(warmup):
+        plan.rk3_step(dt, nu, vel, work, ad, pres, phi)
+    sub = {1: [], 2: [], 3: []}
+    for _ in range(steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        for k in (1, 2, 3):
+            plan.rk3_substep(k, dt, nu, vel, work, ad, pres, phi)
+            ev[k].record(stream)
+        torch.cuda.synchronize()
+        for k in (1, 2, 3):
+            sub[k].append(ev[k - 1].elapsed_time(ev[k]))
+    solve_ms = float(np.median(_timed(lambda: plan.solve(phi), 10, torch)))
+    ms = {k: float(np.median(t)) for k, t in sub.items()}
+    step = sum(ms.values())
+    out = {"workload": "RK3 step, Taylor-Green vortex 512^3 (P,P,P), Re 1600, FP64",
+           "points": N, "dt": dt, "step_ms": round(step, 4),
+           "substep_ms": [round(ms[k], 4) for k in (1, 2, 3)],
+           "solve_ms": round(solve_ms, 4),
+           "around_solve_ms": round(step - 3 * solve_ms, 4),
+           "cell_steps_per_s": N / (step * 1e-3),
+           "energy_rate_over_minus_6nu": (e1 - e0) / (dt * e0) / (-6 * nu),
+           "divergence_after_step": div_rel}
+    del vel, work, ad, pres, phi, vel0, p0
+    plan.close()
+    torch.cuda.empty_cache()
+    if with_oracle:
+        from oracle import navier_stokes as ns
+        m = 64
+        u, v, w, p, dm = inputs.taylor_green(m)
+        dtm = 0.9 * ns.stable_dt(u, v, w, dm, dm, dm, nu)
+        pm = Plan(m, m, m, dm, dm, dm, ("P", "P", "P"))
+        dv = torch.from_numpy(np.concatenate([u.reshape(-1), v.reshape(-1), w.reshape(-1)])).cuda()
+        dp = torch.from_numpy(p.reshape(-1).copy()).cuda()
+        pm.rk3_step(dtm, nu, dv, torch.empty_like(dv), torch.zeros_like(dv), dp,
+                    torch.empty_like(dp))
+        ref = ns.rk3_step(u, v, w, p, dtm, nu, dm, dm, dm)
+        got = dv.cpu().numpy().reshape(3, m, m, m)
+        out["rel_l2_vs_oracle_64"] = max([_rel(got[c], ref[c]) for c in range(3)]
+                                         + [_rel(dp.cpu().numpy().reshape(p.shape), ref[3])])
+        pm.close()
+    log(f"[forms] Taylor-Green 512^3 RK3 step: {step:.3f} ms (substeps "
+        f"{ms[1]:.3f}/{ms[2]:.3f}/{ms[3]:.3f}, solve {solve_ms:.3f} ms each); energy rate "
+        f"{out['energy_rate_over_minus_6nu']:.6f} x (-6 nu); divergence {div_rel:.1e}; "
+        f"64^3 rel-L2 vs oracle {out.get('rel_l2_vs_oracle_64', float('nan')):.2e}")
+    return out
+
+
 def _serve_once(log, specs, order, slots, load, seed, window):
     """One server with `slots` streams: warm-up (every spec of the catalogue
     once, so every plan is cached), a closed loop over the timed requests
@@ -604,8 +689,8 @@ def serve(log, refs=None, with_oracle=True, count=2000, catalogue=200, seed=0,
 def run(wanted, log, refs=None, with_oracle=True):
     out = {}
     for name, fn in (("mixed", mixed), ("channel", channel), ("small", small),
-                     ("projection", projection), ("helmholtz", helmholtz), ("batch", batch),
-                     ("serve", serve)):
+                     ("projection", projection), ("helmholtz", helmholtz),
+                     ("taylor_green", taylor_green), ("batch", batch), ("serve", serve)):
         if name in wanted:
             out[name] = fn(log, refs, with_oracle)
     return out

@@ -26,6 +26,7 @@
 #include "async_launch.h"
 #include "refine_kernels.h"
 #include "projection.h"
+#include "navier_stokes.h"
 
 using namespace poisson_dev;
 
@@ -1349,7 +1350,8 @@ extern "C" int projection_update(poisson_plan* p, const double* phi, double gamm
   if (!staggered_plan(p)) return fail(POISSON_EUNSUPPORTED, "projection needs staggered boundary pairs");
   if (!std::isfinite(gamma_dt)) return fail(POISSON_EINVAL, "gamma_dt must be finite");
   hipLaunchKernelGGL(proj_update_kernel, dim3(proj_blocks(p)), dim3(PROJ_NT), 0, st, phi, gamma_dt,
-                     u, v, w, pres, proj_geom(p));
+                     (const double*)u, (const double*)v, (const double*)w, u, v, w, pres,
+                     proj_geom(p));
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
 }
@@ -1360,6 +1362,79 @@ extern "C" int pressure_correction(poisson_plan* p, double* u, double* v, double
   if ((rc = projection_rhs(p, u, v, w, gamma_dt, phi, st))) return rc;
   if ((rc = solve(p, phi, st))) return rc;
   return projection_update(p, phi, gamma_dt, u, v, w, pres, st);
+}
+
+// ------------------------------------------------------------------ Navier-Stokes step
+
+static constexpr double kRK3Alpha[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+static constexpr double kRK3Beta[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+
+// A plan the time step runs on: periodic along every axis, uniform widths.
+static int rk3_plan_check(const poisson_plan* p) {
+  if (p->bc[0] != BC_PERIODIC || p->bc[1] != BC_PERIODIC || p->bc[2] != BC_PERIODIC)
+    return fail(POISSON_EUNSUPPORTED, "the time step needs a plan periodic along every axis");
+  if (!p->z_uniform) return fail(POISSON_EUNSUPPORTED, "the time step needs uniform widths along z");
+  if (p->shift != 0.0) return fail(POISSON_EUNSUPPORTED, "the time step needs a Poisson (unshifted) plan");
+  return POISSON_OK;
+}
+
+extern "C" int rk3_substep(poisson_plan* p, int k, double dt, double nu, double* vel, double* work,
+                           double* ad, double* pres, double* phi, hipStream_t st) {
+  if (!p || !vel || !work || !ad || !pres || !phi) return fail(POISSON_EINVAL, "null argument");
+  if (k < 1 || k > 3) return fail(POISSON_EINVAL, "substep %d is not 1, 2 or 3", k);
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(POISSON_EINVAL, "dt must be finite and positive");
+  if (!(nu >= 0.0) || !std::isfinite(nu)) return fail(POISSON_EINVAL, "nu must be finite and >= 0");
+  if (int rc = rk3_plan_check(p)) return rc;
+  const long long N = (long long)field_points(p);
+  const double dx = p->h[0], dy = p->h[1], dz = p->dz[0];
+  RK3Args A;
+  A.vel = vel;
+  A.p = pres;
+  A.ad_prev = ad;
+  A.ad = ad;
+  A.star = work;
+  A.idx = 1.0 / dx;
+  A.idy = 1.0 / dy;
+  A.idz = 1.0 / dz;
+  A.kx = nu / (dx * dx);
+  A.ky = nu / (dy * dy);
+  A.kz = nu / (dz * dz);
+  const double alpha = kRK3Alpha[k - 1], beta = kRK3Beta[k - 1], gamma = alpha + beta;
+  A.a_dt = dt * alpha;
+  A.b_dt = dt * beta;
+  A.g_dt = dt * gamma;
+  A.nx = p->dims[0];
+  A.ny = p->dims[1];
+  A.nz = p->dims[2];
+  A.npts = N;
+  const int blocks = (int)std::max<long long>(1, std::min<long long>(RK3_BLOCKS, (N + RK3_NT - 1) / RK3_NT));
+  // AD_prev is read when beta_k != 0 (k = 2, 3); AD is kept for the next
+  // substep (k = 1, 2): the first substep of the next step does not read it
+  if (k == 1)
+    hipLaunchKernelGGL((rk3_predict_kernel<false, true>), dim3(blocks), dim3(RK3_NT), 0, st, A);
+  else if (k == 2)
+    hipLaunchKernelGGL((rk3_predict_kernel<true, true>), dim3(blocks), dim3(RK3_NT), 0, st, A);
+  else
+    hipLaunchKernelGGL((rk3_predict_kernel<true, false>), dim3(blocks), dim3(RK3_NT), 0, st, A);
+  HIP_TRY(hipGetLastError());
+  // pressure correction: phi = solve(div(u*) / (gamma dt)), u = u* - gamma dt grad phi, p += phi
+  const double gdt = gamma * dt;
+  hipLaunchKernelGGL(proj_rhs_kernel, dim3(proj_blocks(p)), dim3(PROJ_NT), 0, st, (const double*)work,
+                     (const double*)(work + N), (const double*)(work + 2 * N), 1.0 / gdt, phi, proj_geom(p));
+  HIP_TRY(hipGetLastError());
+  if (int rc = solve(p, phi, st)) return rc;
+  hipLaunchKernelGGL(proj_update_kernel, dim3(proj_blocks(p)), dim3(PROJ_NT), 0, st, (const double*)phi,
+                     gdt, (const double*)work, (const double*)(work + N), (const double*)(work + 2 * N),
+                     vel, vel + N, vel + 2 * N, pres, proj_geom(p));
+  HIP_TRY(hipGetLastError());
+  return POISSON_OK;
+}
+
+extern "C" int rk3_step(poisson_plan* p, double dt, double nu, double* vel, double* work, double* ad,
+                        double* pres, double* phi, hipStream_t st) {
+  for (int k = 1; k <= 3; ++k)
+    if (int rc = rk3_substep(p, k, dt, nu, vel, work, ad, pres, phi, st)) return rc;
+  return POISSON_OK;
 }
 
 // ------------------------------------------------------------------ batch

@@ -20,7 +20,8 @@
 // threads; the neighbours along y and z come from the caches): the
 // right-hand side reads three face arrays and writes one cell array
 // (32 B per cell), the update reads Phi, the three face arrays and p and
-// writes the face arrays and p (72 B per cell).
+// writes the face arrays (in place or into a second set) and p (72 B per
+// cell).
 #pragma once
 #include "refine_kernels.h"
 
@@ -93,11 +94,14 @@ __device__ __forceinline__ double proj_low_grad(const double* __restrict__ phi, 
   return 2.0 * p0 * A.inv_dc[0];                                       // Dirichlet wall
 }
 
-// u -= gdt grad(phi) on every face, p += phi at every cell.
+// u = u_in - gdt grad(phi) on every face, p += phi at every cell.  In
+// place when u_in == u (and so on): each face is read before it is written,
+// by the same thread, and by no other.
 __global__ __launch_bounds__(PROJ_NT) void proj_update_kernel(const double* __restrict__ phi,
-                                                              double gdt, double* __restrict__ u,
-                                                              double* __restrict__ v,
-                                                              double* __restrict__ w,
+                                                              double gdt, const double* u_in,
+                                                              const double* v_in,
+                                                              const double* w_in, double* u,
+                                                              double* v, double* w,
                                                               double* __restrict__ p, ProjGeom G) {
   const int nx = G.ax[0].n, ny = G.ax[1].n, nz = G.ax[2].n;
   const int ux = nx + G.ax[0].walled;
@@ -108,26 +112,30 @@ __global__ __launch_bounds__(PROJ_NT) void proj_update_kernel(const double* __re
   GridWalk at(first, step, nx, ny);
   for (long long c = first; c < G.npts; c += step, at.advance()) {
     const int i = at.i, j = at.j, k = at.k;
-    bool apply;
-    // x faces of row (j, k)
-    const long long ur = (long long)ux * (j + (long long)ny * k);
-    double g = proj_low_grad(phi, c, 1, i, G.ax[0], apply);
-    if (apply) u[ur + i] -= gdt * g;
-    if (G.ax[0].walled && i == nx - 1 && G.ax[0].hi_dirichlet)
-      u[ur + nx] -= gdt * (-2.0 * phi[c] * G.ax[0].inv_dc[nx]);
-    // y faces of column (i, k)
-    const long long vb = i + (long long)nx * vy * k;
-    g = proj_low_grad(phi, c, nx, j, G.ax[1], apply);
-    if (apply) v[vb + (long long)nx * j] -= gdt * g;
-    if (G.ax[1].walled && j == ny - 1 && G.ax[1].hi_dirichlet)
-      v[vb + (long long)nx * ny] -= gdt * (-2.0 * phi[c] * G.ax[1].inv_dc[ny]);
-    // z faces of column (i, j)
-    const long long wb = i + (long long)nx * j;
-    g = proj_low_grad(phi, c, plane, k, G.ax[2], apply);
-    if (apply) w[wb + plane * k] -= gdt * g;
-    if (G.ax[2].walled && k == nz - 1 && G.ax[2].hi_dirichlet)
-      w[wb + plane * nz] -= gdt * (-2.0 * phi[c] * G.ax[2].inv_dc[nz]);
-    p[c] += phi[c];
+    bool ax_, ay_, az_;
+    const double gx = proj_low_grad(phi, c, 1, i, G.ax[0], ax_);
+    const double gy = proj_low_grad(phi, c, nx, j, G.ax[1], ay_);
+    const double gz = proj_low_grad(phi, c, plane, k, G.ax[2], az_);
+    const double ph = phi[c];
+    const long long fu = (long long)ux * (j + (long long)ny * k) + i;    // x face i of row (j, k)
+    const long long fv = i + (long long)nx * (j + (long long)vy * k);    // y face j of column (i, k)
+    const long long fw = i + (long long)nx * j + plane * k;              // z face k of column (i, j)
+    const double u0 = u_in[fu], v0 = v_in[fv], w0 = w_in[fw], p0 = p[c];
+    // the high wall faces belong to the last cell along their axis
+    const bool xh = G.ax[0].walled && i == nx - 1;
+    const bool yh = G.ax[1].walled && j == ny - 1;
+    const bool zh = G.ax[2].walled && k == nz - 1;
+    const double uh = xh ? u_in[fu + 1] : 0.0;
+    const double vh = yh ? v_in[fv + nx] : 0.0;
+    const double wh = zh ? w_in[fw + plane] : 0.0;
+    u[fu] = ax_ ? u0 - gdt * gx : u0;
+    v[fv] = ay_ ? v0 - gdt * gy : v0;
+    w[fw] = az_ ? w0 - gdt * gz : w0;
+    // Dirichlet high wall: gradient -2 phi_edge / h_edge; Neumann: unchanged
+    if (xh) u[fu + 1] = G.ax[0].hi_dirichlet ? uh - gdt * (-2.0 * ph * G.ax[0].inv_dc[nx]) : uh;
+    if (yh) v[fv + nx] = G.ax[1].hi_dirichlet ? vh - gdt * (-2.0 * ph * G.ax[1].inv_dc[ny]) : vh;
+    if (zh) w[fw + plane] = G.ax[2].hi_dirichlet ? wh - gdt * (-2.0 * ph * G.ax[2].inv_dc[nz]) : wh;
+    p[c] = p0 + ph;
   }
 }
 

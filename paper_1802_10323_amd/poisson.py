@@ -66,6 +66,9 @@ SIGNATURES = {
     "projection_rhs": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
     "projection_update": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP, _VP]),
     "pressure_correction": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
+    "rk3_substep": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                   _VP, _VP, _VP, _VP, _VP, _VP]),
+    "rk3_step": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _VP]),
     "refined_noalloc_max_points": (ctypes.c_size_t, []),
     "solve_refined_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP, _VP]),
 }
@@ -229,6 +232,27 @@ class Plan:
                                          _field_ptr(p), float(gamma_dt), _field_ptr(phi),
                                          _stream_handle(stream)))
         return phi
+
+    def _check_step_fields(self, vel, work, ad, p, phi):
+        n = int(np.prod(self.shape))
+        for t, m, name in ((vel, 3 * n, "vel"), (work, 3 * n, "work"), (ad, 3 * n, "ad"),
+                           (p, n, "p"), (phi, n, "phi")):
+            if t.numel() != m:
+                raise ValueError(f"{name} has {t.numel()} values, expected {m}")
+
+    def rk3_substep(self, k, dt, nu, vel, work, ad, p, phi, stream=None):
+        """Substep k (1, 2, 3) of the Runge-Kutta step with its pressure
+        correction (Sec. 2); vel = (u, v, w) stacked, 3 N doubles."""
+        self._check_step_fields(vel, work, ad, p, phi)
+        _check(lib().rk3_substep(self.handle, int(k), float(dt), float(nu), _field_ptr(vel),
+                                 _field_ptr(work), _field_ptr(ad), _field_ptr(p), _field_ptr(phi),
+                                 _stream_handle(stream)))
+
+    def rk3_step(self, dt, nu, vel, work, ad, p, phi, stream=None):
+        """One time step: the three substeps."""
+        self._check_step_fields(vel, work, ad, p, phi)
+        _check(lib().rk3_step(self.handle, float(dt), float(nu), _field_ptr(vel), _field_ptr(work),
+                              _field_ptr(ad), _field_ptr(p), _field_ptr(phi), _stream_handle(stream)))
 
     def set_precision(self, mode, tol=1e-10, max_iters=4):
         _check(lib().plan_set_precision(self.handle, int(mode), float(tol), int(max_iters)))
