@@ -84,8 +84,9 @@ typedef struct poisson_plan poisson_plan;
  *            be non-uniform; a non-uniform z always becomes the elimination axis.
  *   bc_x, bc_y, bc_z : enum poisson_bc.
  * Axis roles: the elimination axis s is z if z is non-uniform or not periodic;
- * otherwise the first non-periodic axis among x, y; z (cyclic) if all three are
- * periodic.  The other two axes are transformed.
+ * otherwise the first non-periodic axis among x, y; if all three are periodic,
+ * x (cyclic, contiguous lines) when y and z both have supported transform
+ * lengths, else z (cyclic).  The other two axes are transformed.
  * Supported sizes: every transformed axis needs an even n >= 2 whose half has
  * no prime factor above 5 and n <= 1024; the elimination axis needs
  * 1 <= n <= 512 (n >= 3 if it is periodic).  Otherwise POISSON_EUNSUPPORTED.

@@ -118,4 +118,148 @@ __global__ __launch_bounds__(RK3_NT) void rk3_predict_kernel(RK3Args A) {
   }
 }
 
+// The same prediction, z-marching over LDS plane tiles: a block owns a
+// 64 x 4 (x, y) tile of columns and RK3_KC consecutive planes.  Each plane
+// of u, v, w and p is loaded once per block, with a one-cell periodic halo
+// in x and y, into a ring of four LDS planes; computing plane k reads
+// planes k-1, k, k+1 from the ring while plane k+2 arrives.  One barrier
+// per plane.  Every LDS slot (lx, ly) of a tile holds the value at
+// ((i0 + lx) mod nx, (j0 + ly) mod ny), so ragged and wrapped tiles need
+// no special case: threads outside the grid load, but do not store.
+// HBM traffic is the per-cell figure above plus 2 / RK3_KC of the planes
+// (the two halo planes of a block's z range).
+static constexpr int RK3_TX = 64, RK3_TY = 4, RK3_KC = 64;
+static constexpr int RK3_HX = RK3_TX + 2, RK3_HY = RK3_TY + 2;
+static constexpr int RK3_PL = RK3_HX * RK3_HY;                  // slots per plane and field
+static constexpr int RK3_HALO = 2 * RK3_HX + 2 * RK3_TY;        // halo slots per plane
+static_assert(RK3_TX * RK3_TY == RK3_NT && RK3_HALO <= RK3_NT, "tile shape");
+
+template <bool READ_PREV, bool WRITE_AD>
+__global__ __launch_bounds__(RK3_NT) void rk3_predict_tiled_kernel(RK3Args A) {
+  __shared__ double ring[4][4][RK3_PL];    // [plane slot][u, v, w, p][slot]
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const long long N = A.npts;
+  const long long plane = (long long)nx * ny;
+  const int tx = threadIdx.x & (RK3_TX - 1), ty = threadIdx.x / RK3_TX;
+  const int i0 = blockIdx.x * RK3_TX, j0 = blockIdx.y * RK3_TY, k0 = blockIdx.z * RK3_KC;
+  const int kend = min(k0 + RK3_KC, nz);
+  auto wrap = [](int a, int n) { a %= n; return a < 0 ? a + n : a; };
+  // this thread's interior slot and (for the first RK3_HALO threads) halo slot
+  const int own_slot = (ty + 1) * RK3_HX + tx + 1;
+  const long long own_off = wrap(i0 + tx, nx) + (long long)nx * wrap(j0 + ty, ny);
+  int halo_slot = -1;
+  long long halo_off = 0;
+  {
+    const int t = threadIdx.x;
+    int lx = 0, ly = 0;
+    if (t < RK3_HX) { lx = t - 1; ly = -1; }
+    else if (t < 2 * RK3_HX) { lx = t - RK3_HX - 1; ly = RK3_TY; }
+    else if (t < 2 * RK3_HX + RK3_TY) { lx = -1; ly = t - 2 * RK3_HX; }
+    else if (t < RK3_HALO) { lx = RK3_TX; ly = t - 2 * RK3_HX - RK3_TY; }
+    if (t < RK3_HALO) {
+      halo_slot = (ly + 1) * RK3_HX + lx + 1;
+      halo_off = wrap(i0 + lx, nx) + (long long)nx * wrap(j0 + ly, ny);
+    }
+  }
+  const bool active = i0 + tx < nx && j0 + ty < ny;
+  const double* __restrict__ src[4] = {A.vel, A.vel + N, A.vel + 2 * N, A.p};
+
+  // plane q (k0 - 1 <= q <= kend) sits in ring slot (q - k0 + 1) & 3
+  auto fetch = [&](int q, double (&own)[4], double (&halo)[4]) {
+    const long long base = plane * wrap(q, nz);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      own[f] = src[f][base + own_off];
+      halo[f] = halo_slot >= 0 ? src[f][base + halo_off] : 0.0;
+    }
+  };
+  auto put = [&](int q, const double (&own)[4], const double (&halo)[4]) {
+    double(*r)[RK3_PL] = ring[(q - k0 + 1) & 3];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      r[f][own_slot] = own[f];
+      if (halo_slot >= 0) r[f][halo_slot] = halo[f];
+    }
+  };
+  {
+    double own[4], halo[4];
+    for (int q = k0 - 1; q <= min(k0 + 1, kend); ++q) {
+      fetch(q, own, halo);
+      put(q, own, halo);
+    }
+  }
+  __syncthreads();
+
+  const int c = own_slot;
+  for (int k = k0; k < kend; ++k) {
+    double own[4], halo[4];
+    const bool more = k + 2 <= kend;
+    if (more) fetch(k + 2, own, halo);
+    const long long g = own_off + plane * k;
+    double prev[3] = {0.0, 0.0, 0.0};
+    if (READ_PREV && active) {
+      prev[0] = A.ad_prev[g];
+      prev[1] = A.ad_prev[g + N];
+      prev[2] = A.ad_prev[g + 2 * N];
+    }
+    const double(*Rm)[RK3_PL] = ring[(k - k0) & 3];       // plane k - 1
+    const double(*R0)[RK3_PL] = ring[(k - k0 + 1) & 3];   // plane k
+    const double(*Rp)[RK3_PL] = ring[(k - k0 + 2) & 3];   // plane k + 1
+    const int X = 1, Y = RK3_HX;
+    const double u0 = R0[0][c], uxm = R0[0][c - X], uxp = R0[0][c + X], uym = R0[0][c - Y],
+                 uyp = R0[0][c + Y], uzm = Rm[0][c], uzp = Rp[0][c], uxpym = R0[0][c + X - Y],
+                 uxpzm = Rm[0][c + X];
+    const double v0 = R0[1][c], vxm = R0[1][c - X], vxp = R0[1][c + X], vym = R0[1][c - Y],
+                 vyp = R0[1][c + Y], vzm = Rm[1][c], vzp = Rp[1][c], vxmyp = R0[1][c - X + Y],
+                 vypzm = Rm[1][c + Y];
+    const double w0 = R0[2][c], wxm = R0[2][c - X], wxp = R0[2][c + X], wym = R0[2][c - Y],
+                 wyp = R0[2][c + Y], wzm = Rm[2][c], wzp = Rp[2][c], wxmzp = Rp[2][c - X],
+                 wymzp = Rp[2][c - Y];
+    const double p0 = R0[3][c], pxm = R0[3][c - X], pym = R0[3][c - Y], pzm = Rm[3][c];
+
+    const double uu0 = 0.25 * (u0 + uxp) * (u0 + uxp), uum = 0.25 * (uxm + u0) * (uxm + u0);
+    const double vv0 = 0.25 * (v0 + vyp) * (v0 + vyp), vvm = 0.25 * (vym + v0) * (vym + v0);
+    const double ww0 = 0.25 * (w0 + wzp) * (w0 + wzp), wwm = 0.25 * (wzm + w0) * (wzm + w0);
+    const double uv00 = 0.25 * (uym + u0) * (vxm + v0);
+    const double uv01 = 0.25 * (u0 + uyp) * (vxmyp + vyp);
+    const double uv10 = 0.25 * (uxpym + uxp) * (v0 + vxp);
+    const double uw00 = 0.25 * (uzm + u0) * (wxm + w0);
+    const double uw01 = 0.25 * (u0 + uzp) * (wxmzp + wzp);
+    const double uw10 = 0.25 * (uxpzm + uxp) * (w0 + wxp);
+    const double vw00 = 0.25 * (vzm + v0) * (wym + w0);
+    const double vw01 = 0.25 * (v0 + vzp) * (wymzp + wzp);
+    const double vw10 = 0.25 * (vypzm + vyp) * (w0 + wyp);
+
+    const double adu = -((uu0 - uum) * A.idx + (uv01 - uv00) * A.idy + (uw01 - uw00) * A.idz) +
+                       (A.kx * (uxp - 2.0 * u0 + uxm) + A.ky * (uyp - 2.0 * u0 + uym) +
+                        A.kz * (uzp - 2.0 * u0 + uzm));
+    const double adv = -((uv10 - uv00) * A.idx + (vv0 - vvm) * A.idy + (vw01 - vw00) * A.idz) +
+                       (A.kx * (vxp - 2.0 * v0 + vxm) + A.ky * (vyp - 2.0 * v0 + vym) +
+                        A.kz * (vzp - 2.0 * v0 + vzm));
+    const double adw = -((uw10 - uw00) * A.idx + (vw10 - vw00) * A.idy + (ww0 - wwm) * A.idz) +
+                       (A.kx * (wxp - 2.0 * w0 + wxm) + A.ky * (wyp - 2.0 * w0 + wym) +
+                        A.kz * (wzp - 2.0 * w0 + wzm));
+    if (active) {
+      double su = A.a_dt * adu - A.g_dt * (p0 - pxm) * A.idx;
+      double sv = A.a_dt * adv - A.g_dt * (p0 - pym) * A.idy;
+      double sw = A.a_dt * adw - A.g_dt * (p0 - pzm) * A.idz;
+      if (READ_PREV) {
+        su += A.b_dt * prev[0];
+        sv += A.b_dt * prev[1];
+        sw += A.b_dt * prev[2];
+      }
+      if (WRITE_AD) {
+        A.ad[g] = adu;
+        A.ad[g + N] = adv;
+        A.ad[g + 2 * N] = adw;
+      }
+      A.star[g] = u0 + su;
+      A.star[g + N] = v0 + sv;
+      A.star[g + 2 * N] = w0 + sw;
+    }
+    if (more) put(k + 2, own, halo);
+    __syncthreads();
+  }
+}
+
 }  // namespace poisson_dev

@@ -146,6 +146,7 @@ struct poisson_plan {
   bool generic_r2r = false;    // POISSON_GENERIC_R2R=1: size-generic transform kernel only
   bool generic_tri = false;    // POISSON_GENERIC_TRI=1: size-generic elimination kernel only
   int grid_cap = 0;            // POISSON_GRID_CAP=B: at most B blocks per stage launch (0: none)
+  bool rk3_simple = false;     // POISSON_RK3_SIMPLE=1: one-cell-per-thread prediction kernel
   int t1, t2, s;
   bool singular, s_periodic;
   int device;
@@ -838,6 +839,8 @@ extern "C" poisson_plan* plan_create_helmholtz(int nx, int ny, int nz, double dx
     p->generic_tri = env && env[0] == '1';
     env = std::getenv("POISSON_GRID_CAP");
     p->grid_cap = env ? std::max(0, std::atoi(env)) : 0;
+    env = std::getenv("POISSON_RK3_SIMPLE");
+    p->rk3_simple = env && env[0] == '1';
   }
   for (int k = 1; k < nz; ++k) if (dz[k] != dz[0]) p->z_uniform = false;
   p->shift = shift;
@@ -847,10 +850,17 @@ extern "C" poisson_plan* plan_create_helmholtz(int nx, int ny, int nz, double dx
     return nullptr;
   }
 
-  // axis roles (elimination axis s; the others transformed, in x, y, z order)
+  // axis roles (elimination axis s; the others transformed, in x, y, z order).
+  // All periodic: eliminate along the contiguous x (lines in registers, no
+  // strided pass) when y and z take the DFT, else along z.
+  auto dft_length = [](int n) {
+    std::vector<int> r;
+    return n >= 2 && n % 2 == 0 && n <= MAX_TRANSFORM_N && factor_radices(n / 2, r);
+  };
   if (!p->z_uniform || bc_z != BC_PERIODIC) p->s = 2;
   else if (bc_x != BC_PERIODIC) p->s = 0;
   else if (bc_y != BC_PERIODIC) p->s = 1;
+  else if (dft_length(ny) && dft_length(nz)) p->s = 0;
   else p->s = 2;
   int t[2], nt = 0;
   for (int i = 0; i < 3; ++i) if (i != p->s) t[nt++] = i;
@@ -1407,15 +1417,26 @@ extern "C" int rk3_substep(poisson_plan* p, int k, double dt, double nu, double*
   A.ny = p->dims[1];
   A.nz = p->dims[2];
   A.npts = N;
-  const int blocks = (int)std::max<long long>(1, std::min<long long>(RK3_BLOCKS, (N + RK3_NT - 1) / RK3_NT));
   // AD_prev is read when beta_k != 0 (k = 2, 3); AD is kept for the next
   // substep (k = 1, 2): the first substep of the next step does not read it
-  if (k == 1)
-    hipLaunchKernelGGL((rk3_predict_kernel<false, true>), dim3(blocks), dim3(RK3_NT), 0, st, A);
-  else if (k == 2)
-    hipLaunchKernelGGL((rk3_predict_kernel<true, true>), dim3(blocks), dim3(RK3_NT), 0, st, A);
-  else
-    hipLaunchKernelGGL((rk3_predict_kernel<true, false>), dim3(blocks), dim3(RK3_NT), 0, st, A);
+  if (p->rk3_simple) {
+    const int blocks = (int)std::max<long long>(1, std::min<long long>(RK3_BLOCKS, (N + RK3_NT - 1) / RK3_NT));
+    if (k == 1)
+      hipLaunchKernelGGL((rk3_predict_kernel<false, true>), dim3(blocks), dim3(RK3_NT), 0, st, A);
+    else if (k == 2)
+      hipLaunchKernelGGL((rk3_predict_kernel<true, true>), dim3(blocks), dim3(RK3_NT), 0, st, A);
+    else
+      hipLaunchKernelGGL((rk3_predict_kernel<true, false>), dim3(blocks), dim3(RK3_NT), 0, st, A);
+  } else {
+    const dim3 grid((A.nx + RK3_TX - 1) / RK3_TX, (A.ny + RK3_TY - 1) / RK3_TY,
+                    (A.nz + RK3_KC - 1) / RK3_KC);
+    if (k == 1)
+      hipLaunchKernelGGL((rk3_predict_tiled_kernel<false, true>), grid, dim3(RK3_NT), 0, st, A);
+    else if (k == 2)
+      hipLaunchKernelGGL((rk3_predict_tiled_kernel<true, true>), grid, dim3(RK3_NT), 0, st, A);
+    else
+      hipLaunchKernelGGL((rk3_predict_tiled_kernel<true, false>), grid, dim3(RK3_NT), 0, st, A);
+  }
   HIP_TRY(hipGetLastError());
   // pressure correction: phi = solve(div(u*) / (gamma dt)), u = u* - gamma dt grad phi, p += phi
   const double gdt = gamma * dt;

@@ -75,13 +75,18 @@ def check_elimination(n, kind, cases=None):
     from oracle.poisson import tridiagonal_stage
     from paper_1802_10323_amd import Plan, inputs
     import oracle
-    if cases is None and kind == "P":   # a periodic elimination axis: all axes periodic
-        cases = [((20, 10, n), ("P", "P", "P"), "z")]
+    if cases is None and kind == "P":
+        # a periodic elimination axis: all axes periodic; contiguous (s = x
+        # when y and z take the DFT) and strided (a stretched z is always s)
+        cases = [((n, 10, 6), ("P", "P", "P"), "x"), ((20, 10, n), ("P", "P", "P"), "z", (True,))]
     elif cases is None:
         cases = [((20, 10, n), ("P", "P", kind), "z"), ((20, 10, n), ("P", "DD", kind), "z"),
                  ((n, 10, 6), (kind, "P", "P"), "x"), ((n, 10, 6), (kind, "DD", "P"), "x")]
-    for shape, bcs, s_expect in cases:
-        for stretched in ((False, True) if bcs[2] != "P" else (False,)):
+    for case in cases:
+        shape, bcs, s_expect = case[:3]
+        stretch_options = case[3] if len(case) > 3 else (
+            (False, True) if bcs[2] != "P" else (False,))
+        for stretched in stretch_options:
             prob = inputs.make_uniform(*shape, bcs, seed=n + len(kind),
                                        stretch_z=1.8 if stretched else None)
             plan = Plan.from_problem(prob)

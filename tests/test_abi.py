@@ -55,7 +55,7 @@ def test_library_exports_every_declared_symbol():
     ((14, 4, 4, 1.0, 1.0, "P", "P", "NN"), P.EUNSUPPORTED),       # n/2 = 7
     ((2048, 4, 4, 1.0, 1.0, "P", "P", "NN"), P.EUNSUPPORTED),     # too long
     ((4, 4, 600, 1.0, 1.0, "P", "P", "NN"), P.EUNSUPPORTED),      # elimination axis > 512
-    ((4, 4, 2, 1.0, 1.0, "P", "P", "P"), P.EUNSUPPORTED),         # periodic s with n < 3
+    ((2, 4, 4, 1.0, 1.0, "P", "P", "P"), P.EUNSUPPORTED),         # periodic s = x with n < 3
 ])
 def test_plan_create_rejects(args, code):
     nx, ny, nz, dx, dy, bx, by, bz = args

@@ -77,19 +77,25 @@ def split(t, shape):
 
 SUBSTEP_CASES = [
     # nx, ny, nz, lengths, dt, nu
-    (32, 24, 20, (1.0, 0.8, 1.3), 0.003, 0.01),
+    (32, 24, 20, (1.0, 0.8, 1.3), 0.003, 0.01),       # x narrower than a tile
+    (200, 12, 150, (1.0, 0.3, 0.9), 0.001, 0.005),    # ragged x tiles, several z ranges
     (90, 30, 9, (2.0, 1.0, 0.5), 0.001, 0.002),      # ragged rows, odd short z
     (160, 128, 130, (1.0, 1.0, 1.0), 0.0005, 0.001),  # more cells than one grid-stride pass
 ]
 
 
+@pytest.mark.parametrize("kernel", ["tiled", "simple"])
 @pytest.mark.parametrize("case", SUBSTEP_CASES, ids=lambda c: "x".join(map(str, c[:3])))
 @pytest.mark.parametrize("k", [1, 2, 3])
-def test_substep_vs_oracle(case, k):
+def test_substep_vs_oracle(case, k, kernel, monkeypatch):
+    """Both prediction kernels: the z-marching LDS tile kernel (default) and
+    the one-cell-per-thread kernel (POISSON_RK3_SIMPLE=1)."""
     from oracle import navier_stokes as ns
+    if kernel == "simple":
+        monkeypatch.setenv("POISSON_RK3_SIMPLE", "1")
     nx, ny, nz, lengths, dt, nu = case
     shape = (nz, ny, nx)
-    say("rk3 substep", k, case)
+    say("rk3 substep", k, case, kernel)
     plan, (dx, dy, dz) = periodic_plan(nx, ny, nz, lengths)
     vel, ad_prev, p = random_state(100 * k + nx, shape)
     dvel, work, dad, dp, phi = device_state(vel, ad_prev, p)

@@ -43,7 +43,9 @@ STAGE_CASES = [
     ((40, 50, 24), ("DN", "ND", "P"), False),     # z periodic uniform: s = x
     ((33, 24, 20), ("DD", "P", "P"), False),      # s = x with odd length
     ((20, 31, 16), ("P", "ND", "P"), False),      # s = y
-    ((16, 12, 10), ("P", "P", "P"), False),       # cyclic s = z
+    ((16, 12, 10), ("P", "P", "P"), False),       # all periodic: cyclic s = x
+    ((16, 12, 10), ("P", "P", "P"), True),        # cyclic s = z, stretched
+    ((16, 12, 14), ("P", "P", "P"), False),       # z has no DFT (n/2 = 7): cyclic s = z
 ]
 
 
