@@ -374,17 +374,24 @@ int pressure_correction(poisson_plan* plan, double* u, double* v, double* w, dou
  *   vel   3 N: u, v, w one after another; component c at (i, j, k) lives on
  *         the low face of cell (i, j, k) normal to axis c.  In / out.
  *   work  3 N: the prediction u* (scratch; overwritten).
- *   ad    3 N: AD = -(u . grad) u + nu lap(u) of the substep (advection in
- *         divergence form, second-order central differences).  Read by
- *         substeps 2 and 3 (AD of the one before), written by substeps 1
- *         and 2; substep 3 leaves it as it is.
+ *   ad    6 N: two buffers of AD = -(u . grad) u + nu lap(u) (advection in
+ *         divergence form, second-order central differences), each 3 N:
+ *         substep 1 writes its AD into the first, substep 2 reads the first
+ *         and writes its own into the second, substep 3 reads the second and
+ *         writes nothing (the next step's first substep needs no AD).
  *   p     N: the pressure p^{k-1/2} at cell centres; gains phi.  In / out.
  *   phi   N: the correction pressure of the substep (zero mean).  Out.
  * Arrays must not overlap.  Enqueued on `stream`; the solve uses the plan's
  * precision mode.  dt > 0, nu >= 0 (POISSON_EINVAL otherwise). */
 
-/* Substep k (1, 2, 3): u* = u + dt (alpha_k AD + beta_k AD_prev -
- * gamma_k grad p), phi = solve(div(u*) / (gamma_k dt)),
+/* The prediction of substep k (1, 2, 3) and the right-hand side of its
+ * pressure equation (Eq. (up), Eq. (poi_ns)): work = u* = u + dt (alpha_k AD
+ * + beta_k AD_prev - gamma_k grad p), ad as described above, and
+ * rhs (N doubles) = div(u*) / (gamma_k dt).  vel and p are only read. */
+int rk3_predict(poisson_plan* plan, int k, double dt, double nu, const double* vel, double* work,
+                double* ad, const double* p, double* rhs, hipStream_t stream);
+
+/* Substep k (1, 2, 3): rk3_predict into work and phi, phi = solve(phi),
  * u = u* - gamma_k dt grad phi, p += phi. */
 int rk3_substep(poisson_plan* plan, int k, double dt, double nu, double* vel, double* work,
                 double* ad, double* p, double* phi, hipStream_t stream);

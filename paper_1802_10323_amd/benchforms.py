@@ -465,7 +465,7 @@ def taylor_green(log, refs=None, with_oracle=True, steps=5, warmup=1):
     del u, v, w, p
     vel, pres = vel0.clone(), p0.clone()
     work = torch.empty_like(vel0)
-    ad = torch.zeros_like(vel0)
+    ad = torch.zeros(2 * vel0.numel(), dtype=torch.float64, device="cuda")   # two AD buffers
     phi = torch.empty_like(p0)
     stream = torch.cuda.current_stream()
     # the first step from the start, for the checks
@@ -508,7 +508,8 @@ def taylor_green(log, refs=None, with_oracle=True, steps=5, warmup=1):
         pm = Plan(m, m, m, dm, dm, dm, ("P", "P", "P"))
         dv = torch.from_numpy(np.concatenate([u.reshape(-1), v.reshape(-1), w.reshape(-1)])).cuda()
         dp = torch.from_numpy(p.reshape(-1).copy()).cuda()
-        pm.rk3_step(dtm, nu, dv, torch.empty_like(dv), torch.zeros_like(dv), dp,
+        pm.rk3_step(dtm, nu, dv, torch.empty_like(dv), torch.zeros(2 * dv.numel(), dtype=dv.dtype,
+                                                                    device="cuda"), dp,
                     torch.empty_like(dp))
         ref = ns.rk3_step(u, v, w, p, dtm, nu, dm, dm, dm)
         got = dv.cpu().numpy().reshape(3, m, m, m)

@@ -134,6 +134,60 @@ static constexpr int RK3_PL = RK3_HX * RK3_HY;                  // slots per pla
 static constexpr int RK3_HALO = 2 * RK3_HX + 2 * RK3_TY;        // halo slots per plane
 static_assert(RK3_TX * RK3_TY == RK3_NT && RK3_HALO <= RK3_NT, "tile shape");
 
+// AD and u* of the three faces a cell owns, from three LDS planes (field
+// order u, v, w, p; row pitch Y) at slot c.  Shared by the tile kernels,
+// so that a face computed twice (a tile's own cell and a neighbour tile's
+// edge) is computed by the same code.
+struct RK3Cell {
+  double ad[3];
+  double star[3];
+};
+
+template <int PL, int Y>
+__device__ __forceinline__ RK3Cell rk3_cell(const double (*Rm)[PL], const double (*R0)[PL],
+                                            const double (*Rp)[PL], int c, const RK3Args& A,
+                                            const double (&prev)[3]) {
+  constexpr int X = 1;
+  const double u0 = R0[0][c], uxm = R0[0][c - X], uxp = R0[0][c + X], uym = R0[0][c - Y],
+               uyp = R0[0][c + Y], uzm = Rm[0][c], uzp = Rp[0][c], uxpym = R0[0][c + X - Y],
+               uxpzm = Rm[0][c + X];
+  const double v0 = R0[1][c], vxm = R0[1][c - X], vxp = R0[1][c + X], vym = R0[1][c - Y],
+               vyp = R0[1][c + Y], vzm = Rm[1][c], vzp = Rp[1][c], vxmyp = R0[1][c - X + Y],
+               vypzm = Rm[1][c + Y];
+  const double w0 = R0[2][c], wxm = R0[2][c - X], wxp = R0[2][c + X], wym = R0[2][c - Y],
+               wyp = R0[2][c + Y], wzm = Rm[2][c], wzp = Rp[2][c], wxmzp = Rp[2][c - X],
+               wymzp = Rp[2][c - Y];
+  const double p0 = R0[3][c], pxm = R0[3][c - X], pym = R0[3][c - Y], pzm = Rm[3][c];
+
+  const double uu0 = 0.25 * (u0 + uxp) * (u0 + uxp), uum = 0.25 * (uxm + u0) * (uxm + u0);
+  const double vv0 = 0.25 * (v0 + vyp) * (v0 + vyp), vvm = 0.25 * (vym + v0) * (vym + v0);
+  const double ww0 = 0.25 * (w0 + wzp) * (w0 + wzp), wwm = 0.25 * (wzm + w0) * (wzm + w0);
+  const double uv00 = 0.25 * (uym + u0) * (vxm + v0);
+  const double uv01 = 0.25 * (u0 + uyp) * (vxmyp + vyp);
+  const double uv10 = 0.25 * (uxpym + uxp) * (v0 + vxp);
+  const double uw00 = 0.25 * (uzm + u0) * (wxm + w0);
+  const double uw01 = 0.25 * (u0 + uzp) * (wxmzp + wzp);
+  const double uw10 = 0.25 * (uxpzm + uxp) * (w0 + wxp);
+  const double vw00 = 0.25 * (vzm + v0) * (wym + w0);
+  const double vw01 = 0.25 * (v0 + vzp) * (wymzp + wzp);
+  const double vw10 = 0.25 * (vypzm + vyp) * (w0 + wyp);
+
+  RK3Cell r;
+  r.ad[0] = -((uu0 - uum) * A.idx + (uv01 - uv00) * A.idy + (uw01 - uw00) * A.idz) +
+            (A.kx * (uxp - 2.0 * u0 + uxm) + A.ky * (uyp - 2.0 * u0 + uym) +
+             A.kz * (uzp - 2.0 * u0 + uzm));
+  r.ad[1] = -((uv10 - uv00) * A.idx + (vv0 - vvm) * A.idy + (vw01 - vw00) * A.idz) +
+            (A.kx * (vxp - 2.0 * v0 + vxm) + A.ky * (vyp - 2.0 * v0 + vym) +
+             A.kz * (vzp - 2.0 * v0 + vzm));
+  r.ad[2] = -((uw10 - uw00) * A.idx + (vw10 - vw00) * A.idy + (ww0 - wwm) * A.idz) +
+            (A.kx * (wxp - 2.0 * w0 + wxm) + A.ky * (wyp - 2.0 * w0 + wym) +
+             A.kz * (wzp - 2.0 * w0 + wzm));
+  r.star[0] = u0 + (A.a_dt * r.ad[0] - A.g_dt * (p0 - pxm) * A.idx + A.b_dt * prev[0]);
+  r.star[1] = v0 + (A.a_dt * r.ad[1] - A.g_dt * (p0 - pym) * A.idy + A.b_dt * prev[1]);
+  r.star[2] = w0 + (A.a_dt * r.ad[2] - A.g_dt * (p0 - pzm) * A.idz + A.b_dt * prev[2]);
+  return r;
+}
+
 template <bool READ_PREV, bool WRITE_AD>
 __global__ __launch_bounds__(RK3_NT) void rk3_predict_tiled_kernel(RK3Args A) {
   __shared__ double ring[4][4][RK3_PL];    // [plane slot][u, v, w, p][slot]
@@ -190,7 +244,6 @@ __global__ __launch_bounds__(RK3_NT) void rk3_predict_tiled_kernel(RK3Args A) {
   }
   __syncthreads();
 
-  const int c = own_slot;
   for (int k = k0; k < kend; ++k) {
     double own[4], halo[4];
     const bool more = k + 2 <= kend;
@@ -202,62 +255,182 @@ __global__ __launch_bounds__(RK3_NT) void rk3_predict_tiled_kernel(RK3Args A) {
       prev[1] = A.ad_prev[g + N];
       prev[2] = A.ad_prev[g + 2 * N];
     }
-    const double(*Rm)[RK3_PL] = ring[(k - k0) & 3];       // plane k - 1
-    const double(*R0)[RK3_PL] = ring[(k - k0 + 1) & 3];   // plane k
-    const double(*Rp)[RK3_PL] = ring[(k - k0 + 2) & 3];   // plane k + 1
-    const int X = 1, Y = RK3_HX;
-    const double u0 = R0[0][c], uxm = R0[0][c - X], uxp = R0[0][c + X], uym = R0[0][c - Y],
-                 uyp = R0[0][c + Y], uzm = Rm[0][c], uzp = Rp[0][c], uxpym = R0[0][c + X - Y],
-                 uxpzm = Rm[0][c + X];
-    const double v0 = R0[1][c], vxm = R0[1][c - X], vxp = R0[1][c + X], vym = R0[1][c - Y],
-                 vyp = R0[1][c + Y], vzm = Rm[1][c], vzp = Rp[1][c], vxmyp = R0[1][c - X + Y],
-                 vypzm = Rm[1][c + Y];
-    const double w0 = R0[2][c], wxm = R0[2][c - X], wxp = R0[2][c + X], wym = R0[2][c - Y],
-                 wyp = R0[2][c + Y], wzm = Rm[2][c], wzp = Rp[2][c], wxmzp = Rp[2][c - X],
-                 wymzp = Rp[2][c - Y];
-    const double p0 = R0[3][c], pxm = R0[3][c - X], pym = R0[3][c - Y], pzm = Rm[3][c];
-
-    const double uu0 = 0.25 * (u0 + uxp) * (u0 + uxp), uum = 0.25 * (uxm + u0) * (uxm + u0);
-    const double vv0 = 0.25 * (v0 + vyp) * (v0 + vyp), vvm = 0.25 * (vym + v0) * (vym + v0);
-    const double ww0 = 0.25 * (w0 + wzp) * (w0 + wzp), wwm = 0.25 * (wzm + w0) * (wzm + w0);
-    const double uv00 = 0.25 * (uym + u0) * (vxm + v0);
-    const double uv01 = 0.25 * (u0 + uyp) * (vxmyp + vyp);
-    const double uv10 = 0.25 * (uxpym + uxp) * (v0 + vxp);
-    const double uw00 = 0.25 * (uzm + u0) * (wxm + w0);
-    const double uw01 = 0.25 * (u0 + uzp) * (wxmzp + wzp);
-    const double uw10 = 0.25 * (uxpzm + uxp) * (w0 + wxp);
-    const double vw00 = 0.25 * (vzm + v0) * (wym + w0);
-    const double vw01 = 0.25 * (v0 + vzp) * (wymzp + wzp);
-    const double vw10 = 0.25 * (vypzm + vyp) * (w0 + wyp);
-
-    const double adu = -((uu0 - uum) * A.idx + (uv01 - uv00) * A.idy + (uw01 - uw00) * A.idz) +
-                       (A.kx * (uxp - 2.0 * u0 + uxm) + A.ky * (uyp - 2.0 * u0 + uym) +
-                        A.kz * (uzp - 2.0 * u0 + uzm));
-    const double adv = -((uv10 - uv00) * A.idx + (vv0 - vvm) * A.idy + (vw01 - vw00) * A.idz) +
-                       (A.kx * (vxp - 2.0 * v0 + vxm) + A.ky * (vyp - 2.0 * v0 + vym) +
-                        A.kz * (vzp - 2.0 * v0 + vzm));
-    const double adw = -((uw10 - uw00) * A.idx + (vw10 - vw00) * A.idy + (ww0 - wwm) * A.idz) +
-                       (A.kx * (wxp - 2.0 * w0 + wxm) + A.ky * (wyp - 2.0 * w0 + wym) +
-                        A.kz * (wzp - 2.0 * w0 + wzm));
+    const RK3Cell r = rk3_cell<RK3_PL, RK3_HX>(ring[(k - k0) & 3], ring[(k - k0 + 1) & 3],
+                                               ring[(k - k0 + 2) & 3], own_slot, A, prev);
     if (active) {
-      double su = A.a_dt * adu - A.g_dt * (p0 - pxm) * A.idx;
-      double sv = A.a_dt * adv - A.g_dt * (p0 - pym) * A.idy;
-      double sw = A.a_dt * adw - A.g_dt * (p0 - pzm) * A.idz;
-      if (READ_PREV) {
-        su += A.b_dt * prev[0];
-        sv += A.b_dt * prev[1];
-        sw += A.b_dt * prev[2];
-      }
       if (WRITE_AD) {
-        A.ad[g] = adu;
-        A.ad[g + N] = adv;
-        A.ad[g + 2 * N] = adw;
+        A.ad[g] = r.ad[0];
+        A.ad[g + N] = r.ad[1];
+        A.ad[g + 2 * N] = r.ad[2];
       }
-      A.star[g] = u0 + su;
-      A.star[g + N] = v0 + sv;
-      A.star[g + 2 * N] = w0 + sw;
+      A.star[g] = r.star[0];
+      A.star[g + N] = r.star[1];
+      A.star[g + 2 * N] = r.star[2];
     }
     if (more) put(k + 2, own, halo);
+    __syncthreads();
+  }
+}
+
+// The tiled prediction with the right-hand side of the pressure equation,
+// div(u*) / (gamma_k dt), fused (Eq. (poi_ns)): the divergence of a cell
+// needs u* on its high x face and v* on its high y face, which for the
+// tile's last column and row belong to the neighbouring tiles, so the
+// tile holds a two-cell halo on its high sides (rows and columns of
+// 64 + 3 and 4 + 3 slots) and recomputes those faces: wave 0 the cells of
+// the row beyond the tile, four lanes of wave 1 the column beyond it,
+// with the same cell function as the tile's own faces.  u* and v* of a
+// plane pass to the neighbouring threads through a double-buffered LDS
+// exchange; w* of the plane above is the next iteration's own value, so
+// plane k's divergence is formed in iteration k + 1, and each block
+// computes one plane beyond its z range (w* only is used there).  The
+// right-hand side costs 8 B per cell instead of the 32 B of a separate
+// sweep over u*.
+static constexpr int RK3D_HX = RK3_TX + 3, RK3D_HY = RK3_TY + 3;  // lx in [-1, TX+1], ly in [-1, TY+1]
+static constexpr int RK3D_PL = RK3D_HX * RK3D_HY;
+static constexpr int RK3D_HALO = RK3D_PL - RK3_TX * RK3_TY;
+static_assert(RK3D_HALO <= RK3_NT && RK3_TX + RK3_TY <= RK3_NT, "fused tile shape");
+
+template <bool READ_PREV, bool WRITE_AD>
+__global__ __launch_bounds__(RK3_NT) void rk3_predict_div_kernel(RK3Args A, double* __restrict__ rhs,
+                                                                 double inv_gdt) {
+  __shared__ double ring[4][4][RK3D_PL];             // [plane slot][u, v, w, p][slot]
+  __shared__ double xu[2][RK3_TY][RK3_TX + 1];        // u* of a plane: the tile and column TX
+  __shared__ double xv[2][RK3_TY + 1][RK3_TX];        // v* of a plane: the tile and row TY
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const long long N = A.npts;
+  const long long plane = (long long)nx * ny;
+  const int t = threadIdx.x;
+  const int tx = t & (RK3_TX - 1), ty = t / RK3_TX;
+  const int i0 = blockIdx.x * RK3_TX, j0 = blockIdx.y * RK3_TY, k0 = blockIdx.z * RK3_KC;
+  const int kend = min(k0 + RK3_KC, nz);
+  auto wrap = [](int a, int n) { a %= n; return a < 0 ? a + n : a; };
+  auto slot_of = [](int lx, int ly) { return (ly + 1) * RK3D_HX + lx + 1; };
+  auto off_of = [&](int lx, int ly) {
+    return wrap(i0 + lx, nx) + (long long)nx * wrap(j0 + ly, ny);
+  };
+  const int own_slot = slot_of(tx, ty);
+  const long long own_off = off_of(tx, ty);
+  // halo slots, row by row: row -1 (67), rows 0..TY-1 (columns -1, TX, TX+1), rows TY, TY+1 (67 each)
+  int halo_slot = -1;
+  long long halo_off = 0;
+  if (t < RK3D_HALO) {
+    int lx, ly;
+    if (t < RK3D_HX) { ly = -1; lx = t - 1; }
+    else if (t < RK3D_HX + 3 * RK3_TY) {
+      const int r = t - RK3D_HX;
+      ly = r / 3;
+      lx = r % 3 == 0 ? -1 : RK3_TX - 1 + r % 3;
+    } else {
+      const int r = t - RK3D_HX - 3 * RK3_TY;
+      ly = RK3_TY + r / RK3D_HX;
+      lx = r % RK3D_HX - 1;
+    }
+    halo_slot = slot_of(lx, ly);
+    halo_off = off_of(lx, ly);
+  }
+  // edge faces: wave 0 the row TY (v* there), lanes 0..TY-1 of wave 1 the column TX (u* there)
+  int edge_slot = -1;
+  long long edge_off = 0;
+  if (t < RK3_TX) {
+    edge_slot = slot_of(t, RK3_TY);
+    edge_off = off_of(t, RK3_TY);
+  } else if (t < RK3_TX + RK3_TY) {
+    edge_slot = slot_of(RK3_TX, t - RK3_TX);
+    edge_off = off_of(RK3_TX, t - RK3_TX);
+  }
+  const bool active = i0 + tx < nx && j0 + ty < ny;
+  const double* __restrict__ src[4] = {A.vel, A.vel + N, A.vel + 2 * N, A.p};
+
+  // plane q (k0 - 1 <= q <= kend + 1) sits in ring slot (q - k0 + 1) & 3
+  auto fetch = [&](int q, double (&own)[4], double (&halo)[4]) {
+    const long long base = plane * wrap(q, nz);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      own[f] = src[f][base + own_off];
+      halo[f] = halo_slot >= 0 ? src[f][base + halo_off] : 0.0;
+    }
+  };
+  auto put = [&](int q, const double (&own)[4], const double (&halo)[4]) {
+    double(*r)[RK3D_PL] = ring[(q - k0 + 1) & 3];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      r[f][own_slot] = own[f];
+      if (halo_slot >= 0) r[f][halo_slot] = halo[f];
+    }
+  };
+  auto load_prev = [&](long long g, double (&prev)[3]) {
+    prev[0] = prev[1] = prev[2] = 0.0;
+    if (READ_PREV) {
+      prev[0] = A.ad_prev[g];
+      prev[1] = A.ad_prev[g + N];
+      prev[2] = A.ad_prev[g + 2 * N];
+    }
+  };
+  {
+    double own[4], halo[4];
+    for (int q = k0 - 1; q <= k0 + 1; ++q) {
+      fetch(q, own, halo);
+      put(q, own, halo);
+    }
+  }
+  // plane reads run two planes ahead of the arithmetic: plane k + 2 is in
+  // flight while plane k is computed
+  double own_n[4], halo_n[4];
+  if (k0 + 2 <= kend + 1) fetch(k0 + 2, own_n, halo_n);
+  __syncthreads();
+
+  double star_below[3] = {0.0, 0.0, 0.0};   // this thread's u*, v*, w* of plane k - 1
+  for (int k = k0; k <= kend; ++k) {        // k == kend: w* above the range only
+    double own_f[4], halo_f[4];
+    const bool more = k + 3 <= kend + 1;
+    if (more) fetch(k + 3, own_f, halo_f);
+    const long long base = plane * wrap(k, nz);
+    const long long g = own_off + base;
+    double prev[3];
+    load_prev(g, prev);
+    const double(*Rm)[RK3D_PL] = ring[(k - k0) & 3];
+    const double(*R0)[RK3D_PL] = ring[(k - k0 + 1) & 3];
+    const double(*Rp)[RK3D_PL] = ring[(k - k0 + 2) & 3];
+    const RK3Cell r = rk3_cell<RK3D_PL, RK3D_HX>(Rm, R0, Rp, own_slot, A, prev);
+    if (k < kend && active) {
+      if (WRITE_AD) {
+        A.ad[g] = r.ad[0];
+        A.ad[g + N] = r.ad[1];
+        A.ad[g + 2 * N] = r.ad[2];
+      }
+      A.star[g] = r.star[0];
+      A.star[g + N] = r.star[1];
+      A.star[g + 2 * N] = r.star[2];
+    }
+    if (k > k0 && active) {                 // divergence of plane k - 1
+      const int b = (k - 1 - k0) & 1;
+      const double du = xu[b][ty][tx + 1] - xu[b][ty][tx];
+      const double dv = xv[b][ty + 1][tx] - xv[b][ty][tx];
+      const double dw = r.star[2] - star_below[2];
+      rhs[g - base + plane * (k - 1)] = (du * A.idx + dv * A.idy + dw * A.idz) * inv_gdt;
+    }
+    if (k < kend) {
+      const int b = (k - k0) & 1;
+      xu[b][ty][tx] = r.star[0];
+      xv[b][ty][tx] = r.star[1];
+      if (edge_slot >= 0) {
+        double eprev[3];
+        load_prev(edge_off + base, eprev);
+        const RK3Cell e = rk3_cell<RK3D_PL, RK3D_HX>(Rm, R0, Rp, edge_slot, A, eprev);
+        if (t < RK3_TX) xv[b][RK3_TY][t] = e.star[1];
+        else xu[b][t - RK3_TX][RK3_TX] = e.star[0];
+      }
+    }
+    star_below[0] = r.star[0];
+    star_below[1] = r.star[1];
+    star_below[2] = r.star[2];
+    if (k + 2 <= kend + 1) put(k + 2, own_n, halo_n);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      own_n[f] = own_f[f];
+      halo_n[f] = halo_f[f];
+    }
     __syncthreads();
   }
 }

@@ -146,7 +146,7 @@ struct poisson_plan {
   bool generic_r2r = false;    // POISSON_GENERIC_R2R=1: size-generic transform kernel only
   bool generic_tri = false;    // POISSON_GENERIC_TRI=1: size-generic elimination kernel only
   int grid_cap = 0;            // POISSON_GRID_CAP=B: at most B blocks per stage launch (0: none)
-  bool rk3_simple = false;     // POISSON_RK3_SIMPLE=1: one-cell-per-thread prediction kernel
+  int rk3_kernel = 0;          // POISSON_RK3_KERNEL: 0 fused (default), 1 "tiled", 2 "simple"
   int t1, t2, s;
   bool singular, s_periodic;
   int device;
@@ -839,8 +839,8 @@ extern "C" poisson_plan* plan_create_helmholtz(int nx, int ny, int nz, double dx
     p->generic_tri = env && env[0] == '1';
     env = std::getenv("POISSON_GRID_CAP");
     p->grid_cap = env ? std::max(0, std::atoi(env)) : 0;
-    env = std::getenv("POISSON_RK3_SIMPLE");
-    p->rk3_simple = env && env[0] == '1';
+    env = std::getenv("POISSON_RK3_KERNEL");
+    p->rk3_kernel = !env ? 0 : std::strcmp(env, "tiled") == 0 ? 1 : std::strcmp(env, "simple") == 0 ? 2 : 0;
   }
   for (int k = 1; k < nz; ++k) if (dz[k] != dz[0]) p->z_uniform = false;
   p->shift = shift;
@@ -1339,6 +1339,18 @@ static int proj_blocks(const poisson_plan* p) {
   return (int)std::max<long long>(1, std::min<long long>(PROJ_BLOCKS, ((long long)field_points(p) + PROJ_NT - 1) / PROJ_NT));
 }
 
+// u = u_in - gamma_dt grad(phi), p += phi (z-marching tiles; in place when u_in == u)
+static int launch_proj_update(const poisson_plan* p, const double* phi, double gamma_dt,
+                              const double* ui, const double* vi, const double* wi, double* u,
+                              double* v, double* w, double* pres, hipStream_t st) {
+  const dim3 grid((p->dims[0] + PROJ_TX - 1) / PROJ_TX, (p->dims[1] + PROJ_TY - 1) / PROJ_TY,
+                  (p->dims[2] + PROJ_KC - 1) / PROJ_KC);
+  hipLaunchKernelGGL(proj_update_zmarch_kernel, grid, dim3(PROJ_NT), 0, st, phi, gamma_dt, ui, vi, wi,
+                     u, v, w, pres, proj_geom(p));
+  HIP_TRY(hipGetLastError());
+  return POISSON_OK;
+}
+
 static bool staggered_plan(const poisson_plan* p) {
   return !node_pair(p->bc[0]) && !node_pair(p->bc[1]) && !node_pair(p->bc[2]);
 }
@@ -1359,11 +1371,7 @@ extern "C" int projection_update(poisson_plan* p, const double* phi, double gamm
   if (!p || !phi || !u || !v || !w || !pres) return fail(POISSON_EINVAL, "null argument");
   if (!staggered_plan(p)) return fail(POISSON_EUNSUPPORTED, "projection needs staggered boundary pairs");
   if (!std::isfinite(gamma_dt)) return fail(POISSON_EINVAL, "gamma_dt must be finite");
-  hipLaunchKernelGGL(proj_update_kernel, dim3(proj_blocks(p)), dim3(PROJ_NT), 0, st, phi, gamma_dt,
-                     (const double*)u, (const double*)v, (const double*)w, u, v, w, pres,
-                     proj_geom(p));
-  HIP_TRY(hipGetLastError());
-  return POISSON_OK;
+  return launch_proj_update(p, phi, gamma_dt, u, v, w, u, v, w, pres, st);
 }
 
 extern "C" int pressure_correction(poisson_plan* p, double* u, double* v, double* w, double* pres,
@@ -1388,9 +1396,9 @@ static int rk3_plan_check(const poisson_plan* p) {
   return POISSON_OK;
 }
 
-extern "C" int rk3_substep(poisson_plan* p, int k, double dt, double nu, double* vel, double* work,
-                           double* ad, double* pres, double* phi, hipStream_t st) {
-  if (!p || !vel || !work || !ad || !pres || !phi) return fail(POISSON_EINVAL, "null argument");
+extern "C" int rk3_predict(poisson_plan* p, int k, double dt, double nu, const double* vel, double* work,
+                           double* ad, const double* pres, double* rhs, hipStream_t st) {
+  if (!p || !vel || !work || !ad || !pres || !rhs) return fail(POISSON_EINVAL, "null argument");
   if (k < 1 || k > 3) return fail(POISSON_EINVAL, "substep %d is not 1, 2 or 3", k);
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(POISSON_EINVAL, "dt must be finite and positive");
   if (!(nu >= 0.0) || !std::isfinite(nu)) return fail(POISSON_EINVAL, "nu must be finite and >= 0");
@@ -1400,8 +1408,11 @@ extern "C" int rk3_substep(poisson_plan* p, int k, double dt, double nu, double*
   RK3Args A;
   A.vel = vel;
   A.p = pres;
-  A.ad_prev = ad;
-  A.ad = ad;
+  // two AD buffers: substep 1 writes the first, substep 2 reads it and
+  // writes the second (a tile also reads the previous AD of faces that its
+  // neighbours own and overwrite), substep 3 reads the second
+  A.ad_prev = k == 3 ? ad + 3 * N : ad;
+  A.ad = k == 1 ? ad : ad + 3 * N;
   A.star = work;
   A.idx = 1.0 / dx;
   A.idy = 1.0 / dy;
@@ -1419,36 +1430,50 @@ extern "C" int rk3_substep(poisson_plan* p, int k, double dt, double nu, double*
   A.npts = N;
   // AD_prev is read when beta_k != 0 (k = 2, 3); AD is kept for the next
   // substep (k = 1, 2): the first substep of the next step does not read it
-  if (p->rk3_simple) {
-    const int blocks = (int)std::max<long long>(1, std::min<long long>(RK3_BLOCKS, (N + RK3_NT - 1) / RK3_NT));
-    if (k == 1)
-      hipLaunchKernelGGL((rk3_predict_kernel<false, true>), dim3(blocks), dim3(RK3_NT), 0, st, A);
-    else if (k == 2)
-      hipLaunchKernelGGL((rk3_predict_kernel<true, true>), dim3(blocks), dim3(RK3_NT), 0, st, A);
-    else
-      hipLaunchKernelGGL((rk3_predict_kernel<true, false>), dim3(blocks), dim3(RK3_NT), 0, st, A);
-  } else {
-    const dim3 grid((A.nx + RK3_TX - 1) / RK3_TX, (A.ny + RK3_TY - 1) / RK3_TY,
-                    (A.nz + RK3_KC - 1) / RK3_KC);
-    if (k == 1)
-      hipLaunchKernelGGL((rk3_predict_tiled_kernel<false, true>), grid, dim3(RK3_NT), 0, st, A);
-    else if (k == 2)
-      hipLaunchKernelGGL((rk3_predict_tiled_kernel<true, true>), grid, dim3(RK3_NT), 0, st, A);
-    else
-      hipLaunchKernelGGL((rk3_predict_tiled_kernel<true, false>), grid, dim3(RK3_NT), 0, st, A);
-  }
-  HIP_TRY(hipGetLastError());
-  // pressure correction: phi = solve(div(u*) / (gamma dt)), u = u* - gamma dt grad phi, p += phi
   const double gdt = gamma * dt;
-  hipLaunchKernelGGL(proj_rhs_kernel, dim3(proj_blocks(p)), dim3(PROJ_NT), 0, st, (const double*)work,
-                     (const double*)(work + N), (const double*)(work + 2 * N), 1.0 / gdt, phi, proj_geom(p));
-  HIP_TRY(hipGetLastError());
-  if (int rc = solve(p, phi, st)) return rc;
-  hipLaunchKernelGGL(proj_update_kernel, dim3(proj_blocks(p)), dim3(PROJ_NT), 0, st, (const double*)phi,
-                     gdt, (const double*)work, (const double*)(work + N), (const double*)(work + 2 * N),
-                     vel, vel + N, vel + 2 * N, pres, proj_geom(p));
-  HIP_TRY(hipGetLastError());
+  const dim3 tiles((A.nx + RK3_TX - 1) / RK3_TX, (A.ny + RK3_TY - 1) / RK3_TY,
+                   (A.nz + RK3_KC - 1) / RK3_KC);
+  if (p->rk3_kernel == 0) {        // prediction and right-hand side in one sweep
+    if (k == 1)
+      hipLaunchKernelGGL((rk3_predict_div_kernel<false, true>), tiles, dim3(RK3_NT), 0, st, A, rhs, 1.0 / gdt);
+    else if (k == 2)
+      hipLaunchKernelGGL((rk3_predict_div_kernel<true, true>), tiles, dim3(RK3_NT), 0, st, A, rhs, 1.0 / gdt);
+    else
+      hipLaunchKernelGGL((rk3_predict_div_kernel<true, false>), tiles, dim3(RK3_NT), 0, st, A, rhs, 1.0 / gdt);
+    HIP_TRY(hipGetLastError());
+  } else {
+    if (p->rk3_kernel == 2) {
+      const int blocks = (int)std::max<long long>(1, std::min<long long>(RK3_BLOCKS, (N + RK3_NT - 1) / RK3_NT));
+      if (k == 1)
+        hipLaunchKernelGGL((rk3_predict_kernel<false, true>), dim3(blocks), dim3(RK3_NT), 0, st, A);
+      else if (k == 2)
+        hipLaunchKernelGGL((rk3_predict_kernel<true, true>), dim3(blocks), dim3(RK3_NT), 0, st, A);
+      else
+        hipLaunchKernelGGL((rk3_predict_kernel<true, false>), dim3(blocks), dim3(RK3_NT), 0, st, A);
+    } else {
+      if (k == 1)
+        hipLaunchKernelGGL((rk3_predict_tiled_kernel<false, true>), tiles, dim3(RK3_NT), 0, st, A);
+      else if (k == 2)
+        hipLaunchKernelGGL((rk3_predict_tiled_kernel<true, true>), tiles, dim3(RK3_NT), 0, st, A);
+      else
+        hipLaunchKernelGGL((rk3_predict_tiled_kernel<true, false>), tiles, dim3(RK3_NT), 0, st, A);
+    }
+    HIP_TRY(hipGetLastError());
+    // right-hand side of the pressure equation, div(u*) / (gamma dt), in a sweep of its own
+    hipLaunchKernelGGL(proj_rhs_kernel, dim3(proj_blocks(p)), dim3(PROJ_NT), 0, st, (const double*)work,
+                       (const double*)(work + N), (const double*)(work + 2 * N), 1.0 / gdt, rhs, proj_geom(p));
+    HIP_TRY(hipGetLastError());
+  }
   return POISSON_OK;
+}
+
+extern "C" int rk3_substep(poisson_plan* p, int k, double dt, double nu, double* vel, double* work,
+                           double* ad, double* pres, double* phi, hipStream_t st) {
+  if (int rc = rk3_predict(p, k, dt, nu, vel, work, ad, pres, phi, st)) return rc;
+  const long long N = (long long)field_points(p);
+  const double gdt = (kRK3Alpha[k - 1] + kRK3Beta[k - 1]) * dt;
+  if (int rc = solve(p, phi, st)) return rc;
+  return launch_proj_update(p, phi, gdt, work, work + N, work + 2 * N, vel, vel + N, vel + 2 * N, pres, st);
 }
 
 extern "C" int rk3_step(poisson_plan* p, double dt, double nu, double* vel, double* work, double* ad,

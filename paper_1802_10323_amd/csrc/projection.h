@@ -17,11 +17,10 @@
 // velocity is divergence-free up to rounding.
 //
 // Both kernels are one HBM sweep over the cells (x fastest across the
-// threads; the neighbours along y and z come from the caches): the
-// right-hand side reads three face arrays and writes one cell array
-// (32 B per cell), the update reads Phi, the three face arrays and p and
-// writes the face arrays (in place or into a second set) and p (72 B per
-// cell).
+// threads): the right-hand side reads three face arrays and writes one
+// cell array (32 B per cell), the update reads Phi, the three face arrays
+// and p and writes the face arrays (in place or into a second set) and p
+// (72 B per cell).
 #pragma once
 #include "refine_kernels.h"
 
@@ -45,7 +44,7 @@ struct ProjGeom {
 };
 
 static constexpr int PROJ_NT = 256;
-static constexpr int PROJ_BLOCKS = 8192;   // grid-stride blocks (2048: update 33 % slower)
+static constexpr int PROJ_BLOCKS = 8192;   // grid-stride blocks of the right-hand side
 
 // rhs = div(u, v, w) * inv_gdt at every cell.
 __global__ __launch_bounds__(PROJ_NT) void proj_rhs_kernel(const double* __restrict__ u,
@@ -94,48 +93,62 @@ __device__ __forceinline__ double proj_low_grad(const double* __restrict__ phi, 
   return 2.0 * p0 * A.inv_dc[0];                                       // Dirichlet wall
 }
 
-// u = u_in - gdt grad(phi) on every face, p += phi at every cell.  In
-// place when u_in == u (and so on): each face is read before it is written,
-// by the same thread, and by no other.
-__global__ __launch_bounds__(PROJ_NT) void proj_update_kernel(const double* __restrict__ phi,
-                                                              double gdt, const double* u_in,
-                                                              const double* v_in,
-                                                              const double* w_in, double* u,
-                                                              double* v, double* w,
-                                                              double* __restrict__ p, ProjGeom G) {
+// u = u_in - gdt grad(phi) on every face, p += phi at every cell; in place
+// when u_in == u (each face is read before it is written, by the same
+// thread, and by no other).  z-marching: a block owns a 64 x 4 tile of
+// (i, j) columns and PROJ_KC consecutive planes; each thread walks its
+// column upward with Phi of the cell below in a register, so the z
+// gradient reads no other plane (the x and y neighbours come from the
+// lines the adjacent lanes and rows load).
+static constexpr int PROJ_TX = 64, PROJ_TY = 4, PROJ_KC = 32;
+
+__global__ __launch_bounds__(PROJ_NT) void proj_update_zmarch_kernel(
+    const double* __restrict__ phi, double gdt, const double* u_in, const double* v_in,
+    const double* w_in, double* u, double* v, double* w, double* __restrict__ p, ProjGeom G) {
   const int nx = G.ax[0].n, ny = G.ax[1].n, nz = G.ax[2].n;
   const int ux = nx + G.ax[0].walled;
   const int vy = ny + G.ax[1].walled;
   const long long plane = (long long)nx * ny;
-  const long long step = (long long)gridDim.x * PROJ_NT;
-  const long long first = blockIdx.x * (long long)PROJ_NT + threadIdx.x;
-  GridWalk at(first, step, nx, ny);
-  for (long long c = first; c < G.npts; c += step, at.advance()) {
-    const int i = at.i, j = at.j, k = at.k;
-    bool ax_, ay_, az_;
+  const int i = blockIdx.x * PROJ_TX + (threadIdx.x & (PROJ_TX - 1));
+  const int j = blockIdx.y * PROJ_TY + threadIdx.x / PROJ_TX;
+  const int k0 = blockIdx.z * PROJ_KC;
+  const int kend = min(k0 + PROJ_KC, nz);
+  if (i >= nx || j >= ny) return;
+  const ProjAxis& Z = G.ax[2];
+  const long long col = i + (long long)nx * j;
+  // Phi below the first plane: the plane under it, the periodic wrap, or none (a wall)
+  double below = 0.0;
+  if (k0 > 0) below = phi[col + plane * (k0 - 1)];
+  else if (!Z.walled) below = phi[col + plane * (nz - 1)];
+  for (int k = k0; k < kend; ++k) {
+    const long long c = col + plane * k;
+    bool ax_, ay_;
     const double gx = proj_low_grad(phi, c, 1, i, G.ax[0], ax_);
     const double gy = proj_low_grad(phi, c, nx, j, G.ax[1], ay_);
-    const double gz = proj_low_grad(phi, c, plane, k, G.ax[2], az_);
     const double ph = phi[c];
-    const long long fu = (long long)ux * (j + (long long)ny * k) + i;    // x face i of row (j, k)
-    const long long fv = i + (long long)nx * (j + (long long)vy * k);    // y face j of column (i, k)
-    const long long fw = i + (long long)nx * j + plane * k;              // z face k of column (i, j)
+    bool az_ = true;
+    double gz;
+    if (k > 0 || !Z.walled) gz = (ph - below) * Z.inv_dc[k];
+    else if (!Z.lo_dirichlet) { az_ = false; gz = 0.0; }
+    else gz = 2.0 * ph * Z.inv_dc[0];
+    const long long fu = (long long)ux * (j + (long long)ny * k) + i;
+    const long long fv = i + (long long)nx * (j + (long long)vy * k);
+    const long long fw = col + plane * k;
     const double u0 = u_in[fu], v0 = v_in[fv], w0 = w_in[fw], p0 = p[c];
-    // the high wall faces belong to the last cell along their axis
     const bool xh = G.ax[0].walled && i == nx - 1;
     const bool yh = G.ax[1].walled && j == ny - 1;
-    const bool zh = G.ax[2].walled && k == nz - 1;
+    const bool zh = Z.walled && k == nz - 1;
     const double uh = xh ? u_in[fu + 1] : 0.0;
     const double vh = yh ? v_in[fv + nx] : 0.0;
     const double wh = zh ? w_in[fw + plane] : 0.0;
     u[fu] = ax_ ? u0 - gdt * gx : u0;
     v[fv] = ay_ ? v0 - gdt * gy : v0;
     w[fw] = az_ ? w0 - gdt * gz : w0;
-    // Dirichlet high wall: gradient -2 phi_edge / h_edge; Neumann: unchanged
     if (xh) u[fu + 1] = G.ax[0].hi_dirichlet ? uh - gdt * (-2.0 * ph * G.ax[0].inv_dc[nx]) : uh;
     if (yh) v[fv + nx] = G.ax[1].hi_dirichlet ? vh - gdt * (-2.0 * ph * G.ax[1].inv_dc[ny]) : vh;
-    if (zh) w[fw + plane] = G.ax[2].hi_dirichlet ? wh - gdt * (-2.0 * ph * G.ax[2].inv_dc[nz]) : wh;
+    if (zh) w[fw + plane] = Z.hi_dirichlet ? wh - gdt * (-2.0 * ph * Z.inv_dc[nz]) : wh;
     p[c] = p0 + ph;
+    below = ph;
   }
 }
 

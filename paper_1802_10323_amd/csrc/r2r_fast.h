@@ -30,6 +30,7 @@
 #pragma once
 #include <type_traits>
 #include "r2r_kernel.h"
+#include "stage_dma.h"
 
 namespace poisson_dev {
 
@@ -796,21 +797,6 @@ constexpr size_t async_lds_bytes() {
   return (size_t)AsyncLayout<T, C>::STAGE * sizeof(T) + fast_lds_bytes<T, C>();
 }
 
-// One 16-byte piece per lane from global memory straight into LDS: lane i
-// of the wave writes bytes [16 i, 16 i + 16) after `lds_addr` (uniform).
-// Written as inline assembly so that the compiler does not treat it as an
-// LDS write that every later LDS access must wait for (it cannot tell the
-// stage from the tile); the kernel waits for it explicitly (s_waitcnt)
-// before reading the stage.
-__device__ __forceinline__ void lds_dma16(const void* gaddr, unsigned lds_addr) {
-  asm volatile(
-      "s_mov_b32 m0, %1\n\t"
-      "global_load_lds_dwordx4 %0, off"
-      :
-      : "v"(gaddr), "s"(__builtin_amdgcn_readfirstlane(lds_addr))
-      : "memory", "m0");
-}
-
 // Issue the reads of tile `tile` into the stage (asynchronous: completion
 // is awaited by the vector-memory counter before the stage is read).
 template <typename T, typename C>
@@ -836,7 +822,7 @@ __device__ __forceinline__ void async_fetch(lptr<unsigned char> stage, const R2R
       const int e = (c * 64 + lane) * AL::EPL;
       if (e / L::N < g.nlines - o.L0 && e / L::N < nlt) src = data + (long long)o.L0 * L::N + e;
     }
-    lds_dma16(src, (unsigned)(size_t)(stage + c * 1024));
+    stage_dma16(src, (unsigned)(size_t)(stage + c * 1024));
   }
 }
 

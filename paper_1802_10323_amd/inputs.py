@@ -135,13 +135,19 @@ def small(seed=0):
     return make_uniform(32, 32, 32, ("P", "P", "NN"), seed, name="small")
 
 
-def channel(seed=0, nx=512, ny=256, nz=192, modes=64, noise=1e-3):
+def channel(seed=0, nx=512, ny=256, nz=192, modes=64, noise=1e-3, z_profiles=None, drawn=None):
     """Channel-like grid: Lx = 4 pi, Ly = 2 pi, Lz = 2, periodic x/y, Neumann z
     clustered toward both walls (tanh, beta = 1.8).  The right-hand side is a
     seeded sum of ``modes`` separable modes with U[-1, 1] amplitudes: Fourier
-    modes exp(2 pi i k x / L) (real or imaginary part) in x and y, and
-    cos(pi k (z / Lz)) evaluated at the stretched cell centres in z; plus
-    ``noise`` * U[-1, 1]; the volume-weighted mean is removed."""
+    modes exp(2 pi i k x / L) (real or imaginary part) in x and y, and in z
+    profile number kz (0 <= kz < nz), by default cos(pi kz (z / Lz)) at the
+    stretched cell centres; plus ``noise`` * U[-1, 1]; the volume-weighted
+    mean is removed.
+
+    ``z_profiles``: optional callable kz -> nz values replacing the cosines
+    (the tests pass the discrete eigenvectors of the stretched z operator,
+    which they build from the oracle, to make a manufactured solution);
+    ``drawn``: optional list that receives (kx, ky, kz, px, py, amp) per mode."""
     rng = np.random.default_rng(seed)
     Lx, Ly, Lz = 4.0 * math.pi, 2.0 * math.pi, 2.0
     hx = uniform_widths(nx, Lx)
@@ -157,9 +163,12 @@ def channel(seed=0, nx=512, ny=256, nz=192, modes=64, noise=1e-3):
         px = rng.integers(0, 2) * 0.5 * math.pi    # cos or sin
         py = rng.integers(0, 2) * 0.5 * math.pi
         amp = rng.uniform(-1.0, 1.0)
+        if drawn is not None:
+            drawn.append((kx, ky, kz, px, py, amp))
         fx = np.cos(2.0 * math.pi * kx * xc / Lx - px)
         fy = np.cos(2.0 * math.pi * ky * yc / Ly - py)
-        FZ[m] = amp * np.cos(math.pi * kz * zc / Lz)
+        prof = np.cos(math.pi * kz * zc / Lz) if z_profiles is None else np.asarray(z_profiles(kz))
+        FZ[m] = amp * prof
         FYX[m] = np.outer(fy, fx).reshape(-1)
     f = (FZ.T @ FYX).reshape(nz, ny, nx)              # sum of the separable modes
     f += noise * rng.uniform(-1.0, 1.0, size=f.shape)

@@ -66,6 +66,8 @@ SIGNATURES = {
     "projection_rhs": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
     "projection_update": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP, _VP]),
     "pressure_correction": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
+    "rk3_predict": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                   _VP, _VP, _VP, _VP, _VP, _VP]),
     "rk3_substep": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    _VP, _VP, _VP, _VP, _VP, _VP]),
     "rk3_step": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -235,10 +237,19 @@ class Plan:
 
     def _check_step_fields(self, vel, work, ad, p, phi):
         n = int(np.prod(self.shape))
-        for t, m, name in ((vel, 3 * n, "vel"), (work, 3 * n, "work"), (ad, 3 * n, "ad"),
+        for t, m, name in ((vel, 3 * n, "vel"), (work, 3 * n, "work"), (ad, 6 * n, "ad"),
                            (p, n, "p"), (phi, n, "phi")):
             if t.numel() != m:
                 raise ValueError(f"{name} has {t.numel()} values, expected {m}")
+
+    def rk3_predict(self, k, dt, nu, vel, work, ad, p, rhs, stream=None):
+        """The prediction u* of substep k into work (and AD into ad) and the
+        right-hand side div(u*) / (gamma_k dt) into rhs (Eq. (up),
+        Eq. (poi_ns))."""
+        self._check_step_fields(vel, work, ad, p, rhs)
+        _check(lib().rk3_predict(self.handle, int(k), float(dt), float(nu), _field_ptr(vel),
+                                 _field_ptr(work), _field_ptr(ad), _field_ptr(p), _field_ptr(rhs),
+                                 _stream_handle(stream)))
 
     def rk3_substep(self, k, dt, nu, vel, work, ad, p, phi, stream=None):
         """Substep k (1, 2, 3) of the Runge-Kutta step with its pressure

@@ -60,10 +60,12 @@ def random_state(seed, shape):
 
 
 def device_state(vel, ad, p):
+    """Device buffers; ad fills both AD buffers (substep 2 reads the first,
+    substep 3 the second)."""
     import torch
     n = p.size
     dvel = to_dev(np.concatenate([a.reshape(-1) for a in vel]))
-    dad = to_dev(np.concatenate([a.reshape(-1) for a in ad]))
+    dad = to_dev(np.concatenate([a.reshape(-1) for a in ad] * 2))
     work = torch.empty(3 * n, dtype=torch.float64, device="cuda")
     phi = torch.empty(n, dtype=torch.float64, device="cuda")
     return dvel, work, dad, to_dev(p), phi
@@ -84,15 +86,17 @@ SUBSTEP_CASES = [
 ]
 
 
-@pytest.mark.parametrize("kernel", ["tiled", "simple"])
+@pytest.mark.parametrize("kernel", ["fused", "tiled", "simple"])
 @pytest.mark.parametrize("case", SUBSTEP_CASES, ids=lambda c: "x".join(map(str, c[:3])))
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_substep_vs_oracle(case, k, kernel, monkeypatch):
-    """Both prediction kernels: the z-marching LDS tile kernel (default) and
-    the one-cell-per-thread kernel (POISSON_RK3_SIMPLE=1)."""
+    """Every prediction kernel: the z-marching LDS tile kernel with the
+    right-hand side fused (default), the same without it (the right-hand
+    side in a sweep of its own; POISSON_RK3_KERNEL=tiled) and one cell per
+    thread (POISSON_RK3_KERNEL=simple)."""
     from oracle import navier_stokes as ns
-    if kernel == "simple":
-        monkeypatch.setenv("POISSON_RK3_SIMPLE", "1")
+    if kernel != "fused":
+        monkeypatch.setenv("POISSON_RK3_KERNEL", kernel)
     nx, ny, nz, lengths, dt, nu = case
     shape = (nz, ny, nx)
     say("rk3 substep", k, case, kernel)
@@ -109,12 +113,58 @@ def test_substep_vs_oracle(case, k, kernel, monkeypatch):
     errs["p"] = rel_l2(to_host(dp).reshape(shape), ref[3])
     errs["phi"] = rel_l2(to_host(phi).reshape(shape), ref[5])
     for c, name in enumerate(("adu", "adv", "adw")):
-        # substeps 1 and 2 leave this substep's AD; substep 3 leaves AD_prev
-        expect = ref[4][c] if k < 3 else ad_prev[c]
-        errs[name] = rel_l2(got_ad[c], expect)
+        # substep 1 writes its AD into the first buffer, substep 2 into the
+        # second; the other buffer (and both after substep 3) keep AD_prev
+        first = ref[4][c] if k == 1 else ad_prev[c]
+        second = ref[4][c] if k == 2 else ad_prev[c]
+        errs[name] = max(rel_l2(got_ad[c], first), rel_l2(got_ad[3 + c], second))
     say("  rel-L2", {a: f"{b:.2e}" for a, b in errs.items()})
     assert max(errs.values()) <= TOL, errs
     plan.close()
+
+
+@pytest.mark.parametrize("case", SUBSTEP_CASES, ids=lambda c: "x".join(map(str, c[:3])))
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_fused_right_hand_side(case, k, monkeypatch):
+    """rk3_predict: the fused kernel's u* and AD agree with the tiled
+    kernel's to rounding (one cell function, compiled in two kernels that
+    may contract differently), and its right-hand side with the separate
+    divergence sweep over the tiled u*, on the scale of the divergence's
+    terms, |u*| / (dx gamma dt); both against the oracle's prediction and
+    right-hand side."""
+    import torch
+    from oracle import navier_stokes as ns
+    from oracle import projection as pj
+    nx, ny, nz, lengths, dt, nu = case
+    shape = (nz, ny, nx)
+    vel, ad_prev, p = random_state(7 * k + nx, shape)
+    out = {}
+    for kernel in ("fused", "tiled"):
+        if kernel == "tiled":
+            monkeypatch.setenv("POISSON_RK3_KERNEL", "tiled")
+        plan, (dx, dy, dz) = periodic_plan(nx, ny, nz, lengths)
+        dvel, work, dad, dp, rhs = device_state(vel, ad_prev, p)
+        plan.rk3_predict(k, dt, nu, dvel, work, dad, dp, rhs)
+        torch.cuda.synchronize()
+        out[kernel] = (work.clone(), dad.clone(), rhs.clone())
+        plan.close()
+    star, ad = ns.prediction(k, *vel, p, ad_prev, dt, nu, dx, dy, dz)
+    scale = max(np.abs(a).max() for a in star) / (min(dx, dy, dz) * ns.GAMMA[k - 1] * dt)
+    for a, b, name, sc in zip(out["fused"], out["tiled"], ("u*", "AD", "rhs"),
+                              (float(torch.abs(out["tiled"][0]).max()),
+                               float(torch.abs(out["tiled"][1]).max()), scale)):
+        d = float(torch.abs(a - b).max()) / sc
+        say("  fused vs tiled", name, d)
+        assert d <= 4 * 2.0 ** -52, name
+    h = [ns.widths(n, d) for n, d in zip((nx, ny, nz), (dx, dy, dz))]
+    rhs_ref = pj.projection_rhs(*star, ns.GAMMA[k - 1] * dt, *h, ("P", "P", "P"))
+    got_star = split(out["fused"][0], shape)
+    assert max(rel_l2(g, r) for g, r in zip(got_star, star)) <= TOL
+    # the right-hand side is the small divergence of a nearly cancelling sum:
+    # bound it on the scale of its terms
+    err = np.abs(to_host(out["fused"][2]).reshape(shape) - rhs_ref).max() / scale
+    say("rk3_predict", case, k, "rhs max error / (|u*| / (dx gamma dt))", err)
+    assert err <= 1e-14
 
 
 @pytest.mark.parametrize("n,lengths", [(64, None), ((48, 40, 36), (1.0, 1.5, 0.75))])
@@ -189,14 +239,14 @@ def test_taylor_green_512_vs_oracle():
     dt = 0.9 * ns.stable_dt(u, v, w, d, d, d, nu)
     plan, _ = periodic_plan(n, n, n, (2 * math.pi,) * 3)
     dvel = to_dev(np.concatenate([u.reshape(-1), v.reshape(-1), w.reshape(-1)]))
-    dad = torch.zeros_like(dvel)
+    dad = torch.zeros(2 * dvel.numel(), dtype=torch.float64, device="cuda")
     work = torch.empty_like(dvel)
     dp = to_dev(p)
     phi = torch.empty_like(dp)
     say("rk3 substep 1 of the 512^3 Taylor-Green start on the GPU, dt", dt)
     plan.rk3_substep(1, dt, nu, dvel, work, dad, dp, phi)
     got = split(dvel, shape) + [to_host(dp).reshape(shape), to_host(phi).reshape(shape)]
-    got_ad = split(dad, shape)
+    got_ad = split(dad, shape)[:3]
     say("oracle substep 1")
     ref = ns.rk3_substep(1, u, v, w, p, None, dt, nu, d, d, d)
     errs = {name: rel_l2(g, r) for name, g, r in zip(("u", "v", "w", "p", "phi"), got, ref[:4] + ref[5:])}
