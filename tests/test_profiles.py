@@ -17,6 +17,7 @@ POINTS = {"channel": 512 * 256 * 192, "cube": 512 ** 3}
 
 
 @pytest.mark.parametrize("name", ["kernel_trace_channel.txt", "kernel_trace_cube.txt",
+                                  "kernel_trace_taylor_green.txt",
                                   "traffic_channel.txt", "traffic_cube.txt"])
 def test_summary_names_its_command_and_sources(name):
     text = open(os.path.join(PROFILES, name)).read()
