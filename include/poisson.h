@@ -16,6 +16,13 @@
  * are solved by Gauss elimination along the third axis (cyclic when that axis
  * is periodic, Sec. 3), and the backward transforms return Phi.
  *
+ * Around the solve (Sec. 2): Helmholtz plans (A + shift) Phi = f with the
+ * non-staggered DST-I / DCT-I pairs of an implicit diffusion step; the
+ * pressure-correction steps on the staggered grid (right-hand side of
+ * Eq. (poi_ns), the velocity and pressure updates); and one low-storage
+ * three-substep Runge-Kutta time step of the Navier-Stokes equations on a
+ * tri-periodic grid (Eq. (up)).
+ *
  * Data layout: a field is nx*ny*nz values, index i + nx*(j + ny*k), x fastest.
  * All field pointers are DEVICE pointers; all other pointers are HOST pointers.
  * Streams are hipStream_t values (NULL = the legacy default stream).
