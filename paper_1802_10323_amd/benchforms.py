@@ -32,6 +32,10 @@ import time
 
 import numpy as np
 
+# low-storage RK3 coefficients of the time step (Sec. 2), for timing its parts
+ALPHA = (8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0)
+BETA = (0.0, -17.0 / 60.0, -5.0 / 12.0)
+
 
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
@@ -486,15 +490,45 @@ def taylor_green(log, refs=None, with_oracle=True, steps=5, warmup=1):
         torch.cuda.synchronize()
         for k in (1, 2, 3):
             sub[k].append(ev[k - 1].elapsed_time(ev[k]))
-    solve_ms = float(np.median(_timed(lambda: plan.solve(phi), 10, torch)))
+    # the same substeps through the component entry points, one event per
+    # kernel sweep: prediction (+ right-hand side), solve, update (in place
+    # on u*, which then serves as the velocity: the same arithmetic)
+    parts = {(k, name): [] for k in (1, 2, 3) for name in ("predict", "solve", "update")}
+    for _ in range(steps):
+        for k in (1, 2, 3):
+            gdt = dt * (ALPHA[k - 1] + BETA[k - 1])
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[0].record(stream)
+            plan.rk3_predict(k, dt, nu, vel, work, ad, pres, phi)
+            ev[1].record(stream)
+            plan.solve(phi)
+            ev[2].record(stream)
+            plan.projection_update(phi, gdt, work[:N], work[N:2 * N], work[2 * N:], pres)
+            ev[3].record(stream)
+            vel, work = work, vel
+            torch.cuda.synchronize()
+            for i, name in enumerate(("predict", "solve", "update")):
+                parts[(k, name)].append(ev[i].elapsed_time(ev[i + 1]))
+    pm_ = {key: float(np.median(t)) for key, t in parts.items()}
+    solve_ms = float(np.median([pm_[(k, "solve")] for k in (1, 2, 3)]))
     ms = {k: float(np.median(t)) for k, t in sub.items()}
     step = sum(ms.values())
+    predict_bytes = {1: 88.0, 2: 112.0, 3: 88.0}
     out = {"workload": "RK3 step, Taylor-Green vortex 512^3 (P,P,P), Re 1600, FP64",
            "points": N, "dt": dt, "step_ms": round(step, 4),
            "substep_ms": [round(ms[k], 4) for k in (1, 2, 3)],
            "solve_ms": round(solve_ms, 4),
            "around_solve_ms": round(step - 3 * solve_ms, 4),
            "cell_steps_per_s": N / (step * 1e-3),
+           "kernels": [{"substep": k, "predict_ms": round(pm_[(k, "predict")], 4),
+                        "predict_GBs": round(predict_bytes[k] * N / (pm_[(k, "predict")] * 1e-3) / 1e9, 1),
+                        "solve_ms": round(pm_[(k, "solve")], 4),
+                        "solve_GBs": round(80.0 * N / (pm_[(k, "solve")] * 1e-3) / 1e9, 1),
+                        "update_ms": round(pm_[(k, "update")], 4),
+                        "update_GBs": round(72.0 * N / (pm_[(k, "update")] * 1e-3) / 1e9, 1)}
+                       for k in (1, 2, 3)],
+           "bytes_per_cell": "prediction + right-hand side 88 / 112 / 88 (substeps 1 / 2 / 3), "
+                             "solve 80, update 72",
            "energy_rate_over_minus_6nu": (e1 - e0) / (dt * e0) / (-6 * nu),
            "divergence_after_step": div_rel}
     del vel, work, ad, pres, phi, vel0, p0
@@ -516,6 +550,10 @@ def taylor_green(log, refs=None, with_oracle=True, steps=5, warmup=1):
         out["rel_l2_vs_oracle_64"] = max([_rel(got[c], ref[c]) for c in range(3)]
                                          + [_rel(dp.cpu().numpy().reshape(p.shape), ref[3])])
         pm.close()
+    for kk in out["kernels"]:
+        log(f"[forms]   substep {kk['substep']}: predict {kk['predict_ms']:.3f} ms "
+            f"({kk['predict_GBs']} GB/s), solve {kk['solve_ms']:.3f} ms ({kk['solve_GBs']} GB/s), "
+            f"update {kk['update_ms']:.3f} ms ({kk['update_GBs']} GB/s)")
     log(f"[forms] Taylor-Green 512^3 RK3 step: {step:.3f} ms (substeps "
         f"{ms[1]:.3f}/{ms[2]:.3f}/{ms[3]:.3f}, solve {solve_ms:.3f} ms each); energy rate "
         f"{out['energy_rate_over_minus_6nu']:.6f} x (-6 nu); divergence {div_rel:.1e}; "

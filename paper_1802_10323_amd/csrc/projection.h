@@ -76,23 +76,6 @@ __global__ __launch_bounds__(PROJ_NT) void proj_rhs_kernel(const double* __restr
   }
 }
 
-// Gradient of phi on the low face of the cell at offset `c`, whose index
-// along the axis (stride s) is f; `apply` is false on a Neumann wall face,
-// whose velocity the projection leaves as it is.
-__device__ __forceinline__ double proj_low_grad(const double* __restrict__ phi, long long c,
-                                                long long s, int f, const ProjAxis& A,
-                                                bool& apply) {
-  const double p0 = phi[c];
-  apply = true;
-  if (f > 0) return (p0 - phi[c - s]) * A.inv_dc[f];
-  if (!A.walled) return (p0 - phi[c + s * (A.n - 1)]) * A.inv_dc[0];   // wrap face
-  if (!A.lo_dirichlet) {                                               // Neumann wall
-    apply = false;
-    return 0.0;
-  }
-  return 2.0 * p0 * A.inv_dc[0];                                       // Dirichlet wall
-}
-
 // u = u_in - gdt grad(phi) on every face, p += phi at every cell; in place
 // when u_in == u (each face is read before it is written, by the same
 // thread, and by no other).  z-marching: a block owns a 64 x 4 tile of
@@ -114,41 +97,69 @@ __global__ __launch_bounds__(PROJ_NT) void proj_update_zmarch_kernel(
   const int k0 = blockIdx.z * PROJ_KC;
   const int kend = min(k0 + PROJ_KC, nz);
   if (i >= nx || j >= ny) return;
+  const ProjAxis& X = G.ax[0];
+  const ProjAxis& Y = G.ax[1];
   const ProjAxis& Z = G.ax[2];
   const long long col = i + (long long)nx * j;
+  const bool xh = X.walled && i == nx - 1;   // this column also owns the high wall faces
+  const bool yh = Y.walled && j == ny - 1;
+  // the inputs of one plane; the next plane's are read before this one's
+  // results are stored, so a thread keeps two planes' reads in flight
+  struct In {
+    double ph, phx, phy, u0, v0, w0, p0, uh, vh, wh;
+  };
+  auto face_u = [&](int k) { return (long long)ux * (j + (long long)ny * k) + i; };
+  auto face_v = [&](int k) { return i + (long long)nx * (j + (long long)vy * k); };
+  auto load = [&](int k) {
+    In r;
+    const long long c = col + plane * k;
+    r.ph = phi[c];
+    r.phx = i > 0 ? phi[c - 1] : (!X.walled ? phi[c + nx - 1] : 0.0);
+    r.phy = j > 0 ? phi[c - nx] : (!Y.walled ? phi[c + (long long)nx * (ny - 1)] : 0.0);
+    const long long fu = face_u(k), fv = face_v(k);
+    r.u0 = u_in[fu];
+    r.v0 = v_in[fv];
+    r.w0 = w_in[c];
+    r.p0 = p[c];
+    r.uh = xh ? u_in[fu + 1] : 0.0;
+    r.vh = yh ? v_in[fv + nx] : 0.0;
+    r.wh = Z.walled && k == nz - 1 ? w_in[c + plane] : 0.0;
+    return r;
+  };
   // Phi below the first plane: the plane under it, the periodic wrap, or none (a wall)
   double below = 0.0;
   if (k0 > 0) below = phi[col + plane * (k0 - 1)];
   else if (!Z.walled) below = phi[col + plane * (nz - 1)];
+  In cur = load(k0);
   for (int k = k0; k < kend; ++k) {
+    In nxt = cur;
+    if (k + 1 < kend) nxt = load(k + 1);
     const long long c = col + plane * k;
-    bool ax_, ay_;
-    const double gx = proj_low_grad(phi, c, 1, i, G.ax[0], ax_);
-    const double gy = proj_low_grad(phi, c, nx, j, G.ax[1], ay_);
-    const double ph = phi[c];
-    bool az_ = true;
-    double gz;
+    const double ph = cur.ph;
+    // low-face gradients; a Neumann wall face keeps its velocity
+    bool ax_ = true, ay_ = true, az_ = true;
+    double gx, gy, gz;
+    if (i > 0 || !X.walled) gx = (ph - cur.phx) * X.inv_dc[i];
+    else if (!X.lo_dirichlet) { ax_ = false; gx = 0.0; }
+    else gx = 2.0 * ph * X.inv_dc[0];
+    if (j > 0 || !Y.walled) gy = (ph - cur.phy) * Y.inv_dc[j];
+    else if (!Y.lo_dirichlet) { ay_ = false; gy = 0.0; }
+    else gy = 2.0 * ph * Y.inv_dc[0];
     if (k > 0 || !Z.walled) gz = (ph - below) * Z.inv_dc[k];
     else if (!Z.lo_dirichlet) { az_ = false; gz = 0.0; }
     else gz = 2.0 * ph * Z.inv_dc[0];
-    const long long fu = (long long)ux * (j + (long long)ny * k) + i;
-    const long long fv = i + (long long)nx * (j + (long long)vy * k);
-    const long long fw = col + plane * k;
-    const double u0 = u_in[fu], v0 = v_in[fv], w0 = w_in[fw], p0 = p[c];
-    const bool xh = G.ax[0].walled && i == nx - 1;
-    const bool yh = G.ax[1].walled && j == ny - 1;
-    const bool zh = Z.walled && k == nz - 1;
-    const double uh = xh ? u_in[fu + 1] : 0.0;
-    const double vh = yh ? v_in[fv + nx] : 0.0;
-    const double wh = zh ? w_in[fw + plane] : 0.0;
-    u[fu] = ax_ ? u0 - gdt * gx : u0;
-    v[fv] = ay_ ? v0 - gdt * gy : v0;
-    w[fw] = az_ ? w0 - gdt * gz : w0;
-    if (xh) u[fu + 1] = G.ax[0].hi_dirichlet ? uh - gdt * (-2.0 * ph * G.ax[0].inv_dc[nx]) : uh;
-    if (yh) v[fv + nx] = G.ax[1].hi_dirichlet ? vh - gdt * (-2.0 * ph * G.ax[1].inv_dc[ny]) : vh;
-    if (zh) w[fw + plane] = Z.hi_dirichlet ? wh - gdt * (-2.0 * ph * Z.inv_dc[nz]) : wh;
-    p[c] = p0 + ph;
+    const long long fu = face_u(k), fv = face_v(k);
+    u[fu] = ax_ ? cur.u0 - gdt * gx : cur.u0;
+    v[fv] = ay_ ? cur.v0 - gdt * gy : cur.v0;
+    w[c] = az_ ? cur.w0 - gdt * gz : cur.w0;
+    // high wall faces: Dirichlet gradient -2 phi_edge / h_edge; Neumann unchanged
+    if (xh) u[fu + 1] = X.hi_dirichlet ? cur.uh - gdt * (-2.0 * ph * X.inv_dc[nx]) : cur.uh;
+    if (yh) v[fv + nx] = Y.hi_dirichlet ? cur.vh - gdt * (-2.0 * ph * Y.inv_dc[ny]) : cur.vh;
+    if (Z.walled && k == nz - 1)
+      w[c + plane] = Z.hi_dirichlet ? cur.wh - gdt * (-2.0 * ph * Z.inv_dc[nz]) : cur.wh;
+    p[c] = cur.p0 + ph;
     below = ph;
+    cur = nxt;
   }
 }
 
