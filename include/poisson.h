@@ -403,9 +403,15 @@ int rk3_predict(poisson_plan* plan, int k, double dt, double nu, const double* v
 int rk3_substep(poisson_plan* plan, int k, double dt, double nu, double* vel, double* work,
                 double* ad, double* p, double* phi, hipStream_t stream);
 
-/* One time step: substeps 1, 2, 3 (gamma_1 + gamma_2 + gamma_3 = 1). */
+/* One time step: substeps 1, 2, 3 (gamma_1 + gamma_2 + gamma_3 = 1), with
+ * the same results as rk3_substep three times up to rounding.  The
+ * projection of substeps 1 and 2 is applied by the next substep's
+ * prediction as it reads its input instead of in a sweep of its own;
+ * scratch (DEVICE, 2 N doubles, overwritten) holds the intermediate
+ * pressure and correction pressure.  On return vel and p hold the new
+ * velocity and pressure, phi the third substep's correction pressure. */
 int rk3_step(poisson_plan* plan, double dt, double nu, double* vel, double* work, double* ad,
-             double* p, double* phi, hipStream_t stream);
+             double* p, double* phi, double* scratch, hipStream_t stream);
 
 /* ---- refined solve that allocates nothing ----
  *

@@ -27,11 +27,14 @@
 namespace poisson_dev {
 
 struct RK3Args {
-  const double* vel;       // u, v, w (3 npts)
+  const double* vel;       // u, v, w (3 npts); with CORRECT: u* of the previous substep
   const double* p;         // npts
   const double* ad_prev;   // 3 npts, read when READ_PREV
   double* ad;              // 3 npts, written when WRITE_AD
   double* star;            // 3 npts: the prediction u*
+  const double* phi_prev;  // CORRECT: Phi of the previous substep (npts)
+  double* p_out;           // CORRECT: p + Phi of the previous substep (npts)
+  double c_gdt;            // CORRECT: gamma dt of the previous substep
   double idx, idy, idz;    // 1 / spacing
   double kx, ky, kz;       // nu / spacing^2
   double a_dt, b_dt, g_dt; // dt alpha_k, dt beta_k, dt gamma_k
@@ -291,7 +294,15 @@ static constexpr int RK3D_PL = RK3D_HX * RK3D_HY;
 static constexpr int RK3D_HALO = RK3D_PL - RK3_TX * RK3_TY;
 static_assert(RK3D_HALO <= RK3_NT && RK3_TX + RK3_TY <= RK3_NT, "fused tile shape");
 
-template <bool READ_PREV, bool WRITE_AD>
+// CORRECT: the previous substep's projection is applied as the planes
+// arrive instead of in a sweep of its own: the kernel reads u* and Phi of
+// the previous substep (and p before it) and forms, at every slot of the
+// tile, u = u* - gamma dt grad Phi and p + Phi, the velocity and pressure
+// that sweep would have written (same arithmetic); it writes p + Phi of
+// its own cells to p_out (a second buffer: the neighbouring tiles still
+// read p).  The z gradient takes Phi of the plane below from the previous
+// fetch of the same slot.
+template <bool READ_PREV, bool WRITE_AD, bool CORRECT>
 __global__ __launch_bounds__(RK3_NT) void rk3_predict_div_kernel(RK3Args A, double* __restrict__ rhs,
                                                                  double inv_gdt) {
   __shared__ double ring[4][4][RK3D_PL];             // [plane slot][u, v, w, p][slot]
@@ -340,18 +351,46 @@ __global__ __launch_bounds__(RK3_NT) void rk3_predict_div_kernel(RK3Args A, doub
     edge_off = off_of(RK3_TX, t - RK3_TX);
   }
   const bool active = i0 + tx < nx && j0 + ty < ny;
-  const double* __restrict__ src[4] = {A.vel, A.vel + N, A.vel + 2 * N, A.p};
+  // fields read per slot: u, v, w, p; with CORRECT also Phi and its x and y
+  // neighbours below the slot
+  constexpr int NF = CORRECT ? 7 : 4;
+  const double* __restrict__ src[7] = {A.vel, A.vel + N, A.vel + 2 * N, A.p,
+                                       A.phi_prev, A.phi_prev, A.phi_prev};
+  long long own_o[3] = {own_off, 0, 0}, halo_o[3] = {halo_off, 0, 0};
+  if (CORRECT) {
+    own_o[1] = off_of(tx - 1, ty);
+    own_o[2] = off_of(tx, ty - 1);
+    if (halo_slot >= 0) {
+      const int hl = halo_slot % RK3D_HX - 1, hr = halo_slot / RK3D_HX - 1;
+      halo_o[1] = off_of(hl - 1, hr);
+      halo_o[2] = off_of(hl, hr - 1);
+    }
+  }
+  double phib_own = 0.0, phib_halo = 0.0;   // CORRECT: Phi of the plane below, at the two slots
 
   // plane q (k0 - 1 <= q <= kend + 1) sits in ring slot (q - k0 + 1) & 3
-  auto fetch = [&](int q, double (&own)[4], double (&halo)[4]) {
+  auto fetch = [&](int q, double (&own)[7], double (&halo)[7]) {
     const long long base = plane * wrap(q, nz);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      own[f] = src[f][base + own_off];
-      halo[f] = halo_slot >= 0 ? src[f][base + halo_off] : 0.0;
+    for (int f = 0; f < NF; ++f) {
+      const int o = f < 5 ? 0 : f - 4;
+      own[f] = src[f][base + own_o[o]];
+      halo[f] = halo_slot >= 0 ? src[f][base + halo_o[o]] : 0.0;
     }
   };
-  auto put = [&](int q, const double (&own)[4], const double (&halo)[4]) {
+  auto correct = [&](double (&val)[7], double& phib) {
+    if (CORRECT) {
+      const double ph = val[4];
+      val[0] = val[0] - A.c_gdt * ((ph - val[5]) * A.idx);
+      val[1] = val[1] - A.c_gdt * ((ph - val[6]) * A.idy);
+      val[2] = val[2] - A.c_gdt * ((ph - phib) * A.idz);
+      val[3] = val[3] + ph;
+      phib = ph;
+    }
+  };
+  auto put = [&](int q, double (&own)[7], double (&halo)[7]) {
+    correct(own, phib_own);
+    if (halo_slot >= 0) correct(halo, phib_halo);
     double(*r)[RK3D_PL] = ring[(q - k0 + 1) & 3];
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -359,6 +398,11 @@ __global__ __launch_bounds__(RK3_NT) void rk3_predict_div_kernel(RK3Args A, doub
       if (halo_slot >= 0) r[f][halo_slot] = halo[f];
     }
   };
+  if (CORRECT) {
+    const long long base = plane * wrap(k0 - 2, nz);
+    phib_own = A.phi_prev[base + own_off];
+    if (halo_slot >= 0) phib_halo = A.phi_prev[base + halo_off];
+  }
   auto load_prev = [&](long long g, double (&prev)[3]) {
     prev[0] = prev[1] = prev[2] = 0.0;
     if (READ_PREV) {
@@ -368,7 +412,7 @@ __global__ __launch_bounds__(RK3_NT) void rk3_predict_div_kernel(RK3Args A, doub
     }
   };
   {
-    double own[4], halo[4];
+    double own[7], halo[7];
     for (int q = k0 - 1; q <= k0 + 1; ++q) {
       fetch(q, own, halo);
       put(q, own, halo);
@@ -376,13 +420,13 @@ __global__ __launch_bounds__(RK3_NT) void rk3_predict_div_kernel(RK3Args A, doub
   }
   // plane reads run two planes ahead of the arithmetic: plane k + 2 is in
   // flight while plane k is computed
-  double own_n[4], halo_n[4];
+  double own_n[7], halo_n[7];
   if (k0 + 2 <= kend + 1) fetch(k0 + 2, own_n, halo_n);
   __syncthreads();
 
   double star_below[3] = {0.0, 0.0, 0.0};   // this thread's u*, v*, w* of plane k - 1
   for (int k = k0; k <= kend; ++k) {        // k == kend: w* above the range only
-    double own_f[4], halo_f[4];
+    double own_f[7], halo_f[7];
     const bool more = k + 3 <= kend + 1;
     if (more) fetch(k + 3, own_f, halo_f);
     const long long base = plane * wrap(k, nz);
@@ -402,6 +446,7 @@ __global__ __launch_bounds__(RK3_NT) void rk3_predict_div_kernel(RK3Args A, doub
       A.star[g] = r.star[0];
       A.star[g + N] = r.star[1];
       A.star[g + 2 * N] = r.star[2];
+      if (CORRECT) A.p_out[g] = R0[3][own_slot];
     }
     if (k > k0 && active) {                 // divergence of plane k - 1
       const int b = (k - 1 - k0) & 1;
@@ -427,7 +472,7 @@ __global__ __launch_bounds__(RK3_NT) void rk3_predict_div_kernel(RK3Args A, doub
     star_below[2] = r.star[2];
     if (k + 2 <= kend + 1) put(k + 2, own_n, halo_n);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < NF; ++f) {
       own_n[f] = own_f[f];
       halo_n[f] = halo_f[f];
     }

@@ -1396,13 +1396,10 @@ static int rk3_plan_check(const poisson_plan* p) {
   return POISSON_OK;
 }
 
-extern "C" int rk3_predict(poisson_plan* p, int k, double dt, double nu, const double* vel, double* work,
-                           double* ad, const double* pres, double* rhs, hipStream_t st) {
-  if (!p || !vel || !work || !ad || !pres || !rhs) return fail(POISSON_EINVAL, "null argument");
-  if (k < 1 || k > 3) return fail(POISSON_EINVAL, "substep %d is not 1, 2 or 3", k);
-  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(POISSON_EINVAL, "dt must be finite and positive");
-  if (!(nu >= 0.0) || !std::isfinite(nu)) return fail(POISSON_EINVAL, "nu must be finite and >= 0");
-  if (int rc = rk3_plan_check(p)) return rc;
+// Arguments of substep k's prediction: AD buffers as described at
+// rk3_predict, no correction.
+static RK3Args rk3_args(const poisson_plan* p, int k, double dt, double nu, const double* vel,
+                        double* work, double* ad, const double* pres) {
   const long long N = (long long)field_points(p);
   const double dx = p->h[0], dy = p->h[1], dz = p->dz[0];
   RK3Args A;
@@ -1414,33 +1411,68 @@ extern "C" int rk3_predict(poisson_plan* p, int k, double dt, double nu, const d
   A.ad_prev = k == 3 ? ad + 3 * N : ad;
   A.ad = k == 1 ? ad : ad + 3 * N;
   A.star = work;
+  A.phi_prev = nullptr;
+  A.p_out = nullptr;
+  A.c_gdt = 0.0;
   A.idx = 1.0 / dx;
   A.idy = 1.0 / dy;
   A.idz = 1.0 / dz;
   A.kx = nu / (dx * dx);
   A.ky = nu / (dy * dy);
   A.kz = nu / (dz * dz);
-  const double alpha = kRK3Alpha[k - 1], beta = kRK3Beta[k - 1], gamma = alpha + beta;
+  const double alpha = kRK3Alpha[k - 1], beta = kRK3Beta[k - 1];
   A.a_dt = dt * alpha;
   A.b_dt = dt * beta;
-  A.g_dt = dt * gamma;
+  A.g_dt = dt * (alpha + beta);
   A.nx = p->dims[0];
   A.ny = p->dims[1];
   A.nz = p->dims[2];
   A.npts = N;
+  return A;
+}
+
+static dim3 rk3_tiles(const RK3Args& A) {
+  return dim3((A.nx + RK3_TX - 1) / RK3_TX, (A.ny + RK3_TY - 1) / RK3_TY, (A.nz + RK3_KC - 1) / RK3_KC);
+}
+
+// The fused prediction of substep k (with the previous substep's
+// correction when `correct`); rhs = div(u*) / (gamma_k dt).
+static int launch_predict_div(const RK3Args& A, int k, bool correct, double* rhs, hipStream_t st) {
+  const dim3 tiles = rk3_tiles(A);
+  const double inv_gdt = 1.0 / A.g_dt;
+  if (k == 1)
+    hipLaunchKernelGGL((rk3_predict_div_kernel<false, true, false>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
+  else if (k == 2 && !correct)
+    hipLaunchKernelGGL((rk3_predict_div_kernel<true, true, false>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
+  else if (k == 2)
+    hipLaunchKernelGGL((rk3_predict_div_kernel<true, true, true>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
+  else if (!correct)
+    hipLaunchKernelGGL((rk3_predict_div_kernel<true, false, false>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
+  else
+    hipLaunchKernelGGL((rk3_predict_div_kernel<true, false, true>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
+  HIP_TRY(hipGetLastError());
+  return POISSON_OK;
+}
+
+static int rk3_check(const poisson_plan* p, int k, double dt, double nu) {
+  if (k < 1 || k > 3) return fail(POISSON_EINVAL, "substep %d is not 1, 2 or 3", k);
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(POISSON_EINVAL, "dt must be finite and positive");
+  if (!(nu >= 0.0) || !std::isfinite(nu)) return fail(POISSON_EINVAL, "nu must be finite and >= 0");
+  return rk3_plan_check(p);
+}
+
+extern "C" int rk3_predict(poisson_plan* p, int k, double dt, double nu, const double* vel, double* work,
+                           double* ad, const double* pres, double* rhs, hipStream_t st) {
+  if (!p || !vel || !work || !ad || !pres || !rhs) return fail(POISSON_EINVAL, "null argument");
+  if (int rc = rk3_check(p, k, dt, nu)) return rc;
+  const long long N = (long long)field_points(p);
+  const RK3Args A = rk3_args(p, k, dt, nu, vel, work, ad, pres);
   // AD_prev is read when beta_k != 0 (k = 2, 3); AD is kept for the next
   // substep (k = 1, 2): the first substep of the next step does not read it
-  const double gdt = gamma * dt;
-  const dim3 tiles((A.nx + RK3_TX - 1) / RK3_TX, (A.ny + RK3_TY - 1) / RK3_TY,
-                   (A.nz + RK3_KC - 1) / RK3_KC);
+  const double gdt = A.g_dt;
+  const dim3 tiles = rk3_tiles(A);
   if (p->rk3_kernel == 0) {        // prediction and right-hand side in one sweep
-    if (k == 1)
-      hipLaunchKernelGGL((rk3_predict_div_kernel<false, true>), tiles, dim3(RK3_NT), 0, st, A, rhs, 1.0 / gdt);
-    else if (k == 2)
-      hipLaunchKernelGGL((rk3_predict_div_kernel<true, true>), tiles, dim3(RK3_NT), 0, st, A, rhs, 1.0 / gdt);
-    else
-      hipLaunchKernelGGL((rk3_predict_div_kernel<true, false>), tiles, dim3(RK3_NT), 0, st, A, rhs, 1.0 / gdt);
-    HIP_TRY(hipGetLastError());
+    if (int rc = launch_predict_div(A, k, false, rhs, st)) return rc;
   } else {
     if (p->rk3_kernel == 2) {
       const int blocks = (int)std::max<long long>(1, std::min<long long>(RK3_BLOCKS, (N + RK3_NT - 1) / RK3_NT));
@@ -1477,10 +1509,39 @@ extern "C" int rk3_substep(poisson_plan* p, int k, double dt, double nu, double*
 }
 
 extern "C" int rk3_step(poisson_plan* p, double dt, double nu, double* vel, double* work, double* ad,
-                        double* pres, double* phi, hipStream_t st) {
-  for (int k = 1; k <= 3; ++k)
-    if (int rc = rk3_substep(p, k, dt, nu, vel, work, ad, pres, phi, st)) return rc;
-  return POISSON_OK;
+                        double* pres, double* phi, double* scratch, hipStream_t st) {
+  if (!p || !vel || !work || !ad || !pres || !phi || !scratch) return fail(POISSON_EINVAL, "null argument");
+  if (int rc = rk3_check(p, 1, dt, nu)) return rc;
+  if (p->rk3_kernel != 0) {        // the other prediction kernels: substep by substep
+    for (int k = 1; k <= 3; ++k)
+      if (int rc = rk3_substep(p, k, dt, nu, vel, work, ad, pres, phi, st)) return rc;
+    return POISSON_OK;
+  }
+  // Each substep's projection is applied by the next substep's prediction
+  // as it reads the planes (u* alternates between work and vel, p between
+  // pres and the first half of scratch, Phi between phi and its second
+  // half); the third substep's projection is the update sweep.
+  const long long N = (long long)field_points(p);
+  double* p2 = scratch;
+  double* phi2 = scratch + N;
+  auto gdt = [&](int k) { return (kRK3Alpha[k - 1] + kRK3Beta[k - 1]) * dt; };
+  RK3Args A = rk3_args(p, 1, dt, nu, vel, work, ad, pres);          // vel -> work (u*1)
+  if (int rc = launch_predict_div(A, 1, false, phi, st)) return rc;
+  if (int rc = solve(p, phi, st)) return rc;                        // Phi1
+  A = rk3_args(p, 2, dt, nu, work, vel, ad, pres);                  // u*1, Phi1, p -> vel (u*2), p2
+  A.phi_prev = phi;
+  A.p_out = p2;
+  A.c_gdt = gdt(1);
+  if (int rc = launch_predict_div(A, 2, true, phi2, st)) return rc;
+  if (int rc = solve(p, phi2, st)) return rc;                       // Phi2
+  A = rk3_args(p, 3, dt, nu, vel, work, ad, p2);                    // u*2, Phi2, p2 -> work (u*3), pres
+  A.phi_prev = phi2;
+  A.p_out = pres;
+  A.c_gdt = gdt(2);
+  if (int rc = launch_predict_div(A, 3, true, phi, st)) return rc;
+  if (int rc = solve(p, phi, st)) return rc;                        // Phi3
+  return launch_proj_update(p, phi, gdt(3), work, work + N, work + 2 * N, vel, vel + N, vel + 2 * N,
+                            pres, st);
 }
 
 // ------------------------------------------------------------------ batch

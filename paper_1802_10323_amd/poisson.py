@@ -70,7 +70,8 @@ SIGNATURES = {
                                    _VP, _VP, _VP, _VP, _VP, _VP]),
     "rk3_substep": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    _VP, _VP, _VP, _VP, _VP, _VP]),
-    "rk3_step": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "rk3_step": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _VP,
+                                _VP]),
     "refined_noalloc_max_points": (ctypes.c_size_t, []),
     "solve_refined_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP, _VP]),
 }
@@ -259,11 +260,14 @@ class Plan:
                                  _field_ptr(work), _field_ptr(ad), _field_ptr(p), _field_ptr(phi),
                                  _stream_handle(stream)))
 
-    def rk3_step(self, dt, nu, vel, work, ad, p, phi, stream=None):
-        """One time step: the three substeps."""
+    def rk3_step(self, dt, nu, vel, work, ad, p, phi, scratch, stream=None):
+        """One time step: the three substeps (scratch: 2 N doubles)."""
         self._check_step_fields(vel, work, ad, p, phi)
+        if scratch.numel() != 2 * int(np.prod(self.shape)):
+            raise ValueError(f"scratch has {scratch.numel()} values, expected {2 * int(np.prod(self.shape))}")
         _check(lib().rk3_step(self.handle, float(dt), float(nu), _field_ptr(vel), _field_ptr(work),
-                              _field_ptr(ad), _field_ptr(p), _field_ptr(phi), _stream_handle(stream)))
+                              _field_ptr(ad), _field_ptr(p), _field_ptr(phi), _field_ptr(scratch),
+                              _stream_handle(stream)))
 
     def set_precision(self, mode, tol=1e-10, max_iters=4):
         _check(lib().plan_set_precision(self.handle, int(mode), float(tol), int(max_iters)))

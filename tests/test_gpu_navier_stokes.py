@@ -16,8 +16,9 @@ with respect to the rounding of u* (measured in the test) sets its bound.
 Shapes: several blocks per plane with ragged rows, three different spacings,
 a grid larger than one pass of the grid-stride launch, and the 512^3
 Taylor-Green vortex, the workload the benchmark times, in the same launch
-configuration: its first substep against the oracle's, the whole step by
-divergence and the energy budget.  Rejections of plans the step does not
+configuration: its first substep against the oracle's, the whole step (each
+projection applied by the next prediction) by divergence and the energy
+budget.  Rejections of plans the step does not
 support come last."""
 import math
 
@@ -69,6 +70,11 @@ def device_state(vel, ad, p):
     work = torch.empty(3 * n, dtype=torch.float64, device="cuda")
     phi = torch.empty(n, dtype=torch.float64, device="cuda")
     return dvel, work, dad, to_dev(p), phi
+
+
+def scratch_for(shape):
+    import torch
+    return torch.empty(2 * int(np.prod(shape)), dtype=torch.float64, device="cuda")
 
 
 def split(t, shape):
@@ -167,11 +173,20 @@ def test_fused_right_hand_side(case, k, monkeypatch):
     assert err <= 1e-14
 
 
-@pytest.mark.parametrize("n,lengths", [(64, None), ((48, 40, 36), (1.0, 1.5, 0.75))])
-def test_step_vs_oracle(n, lengths):
-    """One whole step: the Taylor-Green start at 64^3 (2 pi box, Re 1600)
-    and a random field on a box with three spacings."""
+STEP_CASES = [(64, None, 0.0, 0.0)] + [((nx, ny, nz), L, dt, nu) for nx, ny, nz, L, dt, nu in SUBSTEP_CASES]
+
+
+@pytest.mark.parametrize("kernel", ["fused", "tiled"])
+@pytest.mark.parametrize("case", STEP_CASES, ids=lambda c: "tg64" if c[1] is None else "x".join(map(str, c[0])))
+def test_step_vs_oracle(case, kernel, monkeypatch):
+    """One whole step: the Taylor-Green start at 64^3 (2 pi box, Re 1600) and
+    random fields on the substep shapes (ragged tiles, several z ranges).
+    Default: each substep's projection applied by the next prediction;
+    tiled: substep by substep."""
     from oracle import navier_stokes as ns
+    if kernel != "fused":
+        monkeypatch.setenv("POISSON_RK3_KERNEL", kernel)
+    n, lengths, dt, nu = case
     if lengths is None:
         u, v, w, p, d = inputs.taylor_green(n)
         vel = [u, v, w]
@@ -184,12 +199,11 @@ def test_step_vs_oracle(n, lengths):
         shape = (nz, ny, nx)
         vel, _, p = random_state(7, shape)
         plan, (dx, dy, dz) = periodic_plan(nx, ny, nz, lengths)
-        nu = 0.01
         dt = 0.5 * ns.stable_dt(*vel, dx, dy, dz, nu)
-    say("rk3 step", shape, "dt", dt)
+    say("rk3 step", shape, kernel, "dt", dt)
     zeros = [np.zeros(shape)] * 3
     dvel, work, dad, dp, phi = device_state(vel, zeros, p)
-    plan.rk3_step(dt, nu, dvel, work, dad, dp, phi)
+    plan.rk3_step(dt, nu, dvel, work, dad, dp, phi, scratch_for(shape))
     ref = ns.rk3_step(*vel, p, dt, nu, dx, dy, dz)
     got = split(dvel, shape) + [to_host(dp).reshape(shape)]
     errs = [rel_l2(g, r) for g, r in zip(got, ref) if np.linalg.norm(r) > 0]
@@ -198,23 +212,34 @@ def test_step_vs_oracle(n, lengths):
     plan.close()
 
 
-def test_substeps_compose_to_the_step():
-    """rk3_step is substeps 1, 2, 3 in order on the same buffers: bitwise."""
+@pytest.mark.parametrize("kernel", ["fused", "tiled"])
+def test_substeps_compose_to_the_step(kernel, monkeypatch):
+    """rk3_step against substeps 1, 2, 3 on the same inputs: bitwise when the
+    step runs substep by substep (tiled), to rounding when it applies each
+    projection inside the next prediction (the same arithmetic compiled in
+    another kernel: each value within 4 ulp of the field's largest)."""
     import torch
+    if kernel != "fused":
+        monkeypatch.setenv("POISSON_RK3_KERNEL", kernel)
     nx, ny, nz = 40, 36, 20
     shape = (nz, ny, nx)
     plan, _ = periodic_plan(nx, ny, nz, (1.0, 1.0, 1.0))
     vel, ad, p = random_state(3, shape)
     a = device_state(vel, ad, p)
     b = device_state(vel, ad, p)
-    plan.rk3_step(0.002, 0.01, *a)
+    plan.rk3_step(0.002, 0.01, *a, scratch_for(shape))
     for k in (1, 2, 3):
         plan.rk3_substep(k, 0.002, 0.01, *b)
     torch.cuda.synchronize()
-    for x, y in zip(a, b):
-        if x is a[1]:
-            continue                                    # work: scratch
-        assert torch.equal(x, y)
+    for x, y, name in zip(a, b, ("vel", "work", "ad", "p", "phi")):
+        if name in ("work", "ad"):
+            continue                                    # scratch, and AD of the last substeps
+        if kernel == "fused":
+            d = float(torch.abs(x - y).max()) / float(torch.abs(y).max())
+            say("  fused step vs substeps", name, d)
+            assert d <= 4 * 2.0 ** -52, name
+        else:
+            assert torch.equal(x, y), name
     plan.close()
 
 
@@ -269,11 +294,15 @@ def test_taylor_green_512_vs_oracle():
     assert errs.pop("phi") <= phi_tol, (errs, sens)
     assert max(errs.values()) <= TOL, errs
     del ref, got, got_ad
-    # the rest of the step on the GPU, then the properties
-    plan.rk3_substep(2, dt, nu, dvel, work, dad, dp, phi)
-    plan.rk3_substep(3, dt, nu, dvel, work, dad, dp, phi)
+    # the whole step on the GPU from the start (each projection applied by
+    # the next prediction), then the properties
+    dvel.copy_(to_dev(np.concatenate([u.reshape(-1), v.reshape(-1), w.reshape(-1)])))
+    dp.copy_(to_dev(p))
+    scratch = scratch_for(shape)
+    say("rk3 step 512^3")
+    plan.rk3_step(dt, nu, dvel, work, dad, dp, phi, scratch)
     u1, v1, w1 = split(dvel, shape)
-    del work, dad, phi, dvel, dp
+    del work, dad, phi, dvel, dp, scratch
     torch.cuda.empty_cache()
     div = pj.divergence(u1, v1, w1, h, h, h, ("P", "P", "P"))
     div_scale = np.abs(u1).max() / d
@@ -297,13 +326,15 @@ def test_unsupported_plans_are_refused():
     for bcs, hz in ((("P", "P", "NN"), h), (("P", "P", "P"), inputs.tanh_widths(16, 1.0, 1.5))):
         plan = Plan(16, 16, 16, h[0], h[0], hz, bcs)
         with pytest.raises(PoissonError):
-            plan.rk3_step(0.01, 0.01, *state)
+            plan.rk3_step(0.01, 0.01, *state, scratch_for(shape))
         plan.close()
     plan = Plan(16, 16, 16, h[0], h[0], h, ("P", "P", "P"))
     for k, dt, nu in ((0, 0.01, 0.1), (4, 0.01, 0.1), (1, 0.0, 0.1), (1, 0.01, -1.0)):
         with pytest.raises(PoissonError):
             plan.rk3_substep(k, dt, nu, *state)
     with pytest.raises(ValueError):
-        plan.rk3_step(0.01, 0.01, state[0][:10], *state[1:])
+        plan.rk3_step(0.01, 0.01, state[0][:10], *state[1:], scratch_for(shape))
+    with pytest.raises(ValueError):
+        plan.rk3_step(0.01, 0.01, *state, state[4])      # scratch too small
     torch.cuda.synchronize()
     plan.close()
