@@ -1335,17 +1335,17 @@ static ProjGeom proj_geom(const poisson_plan* p) {
   return G;
 }
 
-static int proj_blocks(const poisson_plan* p) {
-  return (int)std::max<long long>(1, std::min<long long>(PROJ_BLOCKS, ((long long)field_points(p) + PROJ_NT - 1) / PROJ_NT));
+// z-marching tiles of the projection kernels: 64 x 4 columns, PROJ_KC planes
+static dim3 proj_tiles(const poisson_plan* p) {
+  return dim3((p->dims[0] + PROJ_TX - 1) / PROJ_TX, (p->dims[1] + PROJ_TY - 1) / PROJ_TY,
+              (p->dims[2] + PROJ_KC - 1) / PROJ_KC);
 }
 
 // u = u_in - gamma_dt grad(phi), p += phi (z-marching tiles; in place when u_in == u)
 static int launch_proj_update(const poisson_plan* p, const double* phi, double gamma_dt,
                               const double* ui, const double* vi, const double* wi, double* u,
                               double* v, double* w, double* pres, hipStream_t st) {
-  const dim3 grid((p->dims[0] + PROJ_TX - 1) / PROJ_TX, (p->dims[1] + PROJ_TY - 1) / PROJ_TY,
-                  (p->dims[2] + PROJ_KC - 1) / PROJ_KC);
-  hipLaunchKernelGGL(proj_update_zmarch_kernel, grid, dim3(PROJ_NT), 0, st, phi, gamma_dt, ui, vi, wi,
+  hipLaunchKernelGGL(proj_update_zmarch_kernel, proj_tiles(p), dim3(PROJ_NT), 0, st, phi, gamma_dt, ui, vi, wi,
                      u, v, w, pres, proj_geom(p));
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
@@ -1360,7 +1360,7 @@ extern "C" int projection_rhs(poisson_plan* p, const double* u, const double* v,
   if (!p || !u || !v || !w || !rhs) return fail(POISSON_EINVAL, "null argument");
   if (!staggered_plan(p)) return fail(POISSON_EUNSUPPORTED, "projection needs staggered boundary pairs");
   if (!(gamma_dt != 0.0) || !std::isfinite(gamma_dt)) return fail(POISSON_EINVAL, "gamma_dt must be finite and non-zero");
-  hipLaunchKernelGGL(proj_rhs_kernel, dim3(proj_blocks(p)), dim3(PROJ_NT), 0, st, u, v, w,
+  hipLaunchKernelGGL(proj_rhs_kernel, proj_tiles(p), dim3(PROJ_NT), 0, st, u, v, w,
                      1.0 / gamma_dt, rhs, proj_geom(p));
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
@@ -1492,7 +1492,7 @@ extern "C" int rk3_predict(poisson_plan* p, int k, double dt, double nu, const d
     }
     HIP_TRY(hipGetLastError());
     // right-hand side of the pressure equation, div(u*) / (gamma dt), in a sweep of its own
-    hipLaunchKernelGGL(proj_rhs_kernel, dim3(proj_blocks(p)), dim3(PROJ_NT), 0, st, (const double*)work,
+    hipLaunchKernelGGL(proj_rhs_kernel, proj_tiles(p), dim3(PROJ_NT), 0, st, (const double*)work,
                        (const double*)(work + N), (const double*)(work + 2 * N), 1.0 / gdt, rhs, proj_geom(p));
     HIP_TRY(hipGetLastError());
   }

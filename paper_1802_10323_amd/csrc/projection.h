@@ -44,9 +44,14 @@ struct ProjGeom {
 };
 
 static constexpr int PROJ_NT = 256;
-static constexpr int PROJ_BLOCKS = 8192;   // grid-stride blocks of the right-hand side
 
-// rhs = div(u, v, w) * inv_gdt at every cell.
+// rhs = div(u, v, w) * inv_gdt at every cell.  z-marching like the update
+// below (tiles of 64 x 4 columns, PROJ_KC planes): w on the high face of a
+// cell is w on the low face of the cell above, so each plane reads one new
+// w face per cell and keeps it for the next; the next plane's faces are
+// read before this plane's result is stored.
+static constexpr int PROJ_TX = 64, PROJ_TY = 4, PROJ_KC = 32;
+
 __global__ __launch_bounds__(PROJ_NT) void proj_rhs_kernel(const double* __restrict__ u,
                                                            const double* __restrict__ v,
                                                            const double* __restrict__ w,
@@ -55,24 +60,41 @@ __global__ __launch_bounds__(PROJ_NT) void proj_rhs_kernel(const double* __restr
   const int nx = G.ax[0].n, ny = G.ax[1].n, nz = G.ax[2].n;
   const int ux = nx + G.ax[0].walled;          // faces along x
   const int vy = ny + G.ax[1].walled;          // faces along y
-  const long long step = (long long)gridDim.x * PROJ_NT;
-  const long long first = blockIdx.x * (long long)PROJ_NT + threadIdx.x;
-  GridWalk at(first, step, nx, ny);
-  for (long long c = first; c < G.npts; c += step, at.advance()) {
-    const int i = at.i, j = at.j, k = at.k;
-    // x: faces i and i + 1 of row (j, k)
+  const long long plane = (long long)nx * ny;
+  const int i = blockIdx.x * PROJ_TX + (threadIdx.x & (PROJ_TX - 1));
+  const int j = blockIdx.y * PROJ_TY + threadIdx.x / PROJ_TX;
+  const int k0 = blockIdx.z * PROJ_KC;
+  const int kend = min(k0 + PROJ_KC, nz);
+  if (i >= nx || j >= ny) return;
+  const int ip = G.ax[0].walled || i + 1 < nx ? i + 1 : 0;     // high x face
+  const int jp = G.ax[1].walled || j + 1 < ny ? j + 1 : 0;     // high y face
+  const long long col = i + (long long)nx * j;
+  const double ihx = G.ax[0].inv_h[i], ihy = G.ax[1].inv_h[j];
+  struct In {
+    double u0, u1, v0, v1, w1;
+  };
+  // the faces of plane k other than its low z face (the high z face of the plane below)
+  auto load = [&](int k) {
+    In r;
     const long long ur = (long long)ux * (j + (long long)ny * k);
-    const double du = u[ur + (G.ax[0].walled || i + 1 < nx ? i + 1 : 0)] - u[ur + i];
-    // y: faces j and j + 1 of column (i, k)
+    r.u0 = u[ur + i];
+    r.u1 = u[ur + ip];
     const long long vb = i + (long long)nx * vy * k;
-    const double dv = v[vb + (long long)nx * (G.ax[1].walled || j + 1 < ny ? j + 1 : 0)] -
-                      v[vb + (long long)nx * j];
-    // z: faces k and k + 1 of column (i, j)
-    const long long wb = i + (long long)nx * j;
-    const long long plane = (long long)nx * ny;
-    const double dw = w[wb + plane * (G.ax[2].walled || k + 1 < nz ? k + 1 : 0)] -
-                      w[wb + plane * k];
-    rhs[c] = (du * G.ax[0].inv_h[i] + dv * G.ax[1].inv_h[j] + dw * G.ax[2].inv_h[k]) * inv_gdt;
+    r.v0 = v[vb + (long long)nx * j];
+    r.v1 = v[vb + (long long)nx * jp];
+    const int kp = G.ax[2].walled || k + 1 < nz ? k + 1 : 0;
+    r.w1 = w[col + plane * kp];
+    return r;
+  };
+  double w0 = w[col + plane * k0];
+  In cur = load(k0);
+  for (int k = k0; k < kend; ++k) {
+    In nxt = cur;
+    if (k + 1 < kend) nxt = load(k + 1);
+    const double du = cur.u1 - cur.u0, dv = cur.v1 - cur.v0, dw = cur.w1 - w0;
+    rhs[col + plane * k] = (du * ihx + dv * ihy + dw * G.ax[2].inv_h[k]) * inv_gdt;
+    w0 = cur.w1;
+    cur = nxt;
   }
 }
 
@@ -83,8 +105,6 @@ __global__ __launch_bounds__(PROJ_NT) void proj_rhs_kernel(const double* __restr
 // column upward with Phi of the cell below in a register, so the z
 // gradient reads no other plane (the x and y neighbours come from the
 // lines the adjacent lanes and rows load).
-static constexpr int PROJ_TX = 64, PROJ_TY = 4, PROJ_KC = 32;
-
 __global__ __launch_bounds__(PROJ_NT) void proj_update_zmarch_kernel(
     const double* __restrict__ phi, double gdt, const double* u_in, const double* v_in,
     const double* w_in, double* u, double* v, double* w, double* __restrict__ p, ProjGeom G) {
