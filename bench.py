@@ -130,6 +130,36 @@ def host_cpu():
     return model, usable, threads
 
 
+def hbm_reference(src, torch, reps=10):
+    """Bandwidth that plain sweeps of the field reach with the runtime's own
+    kernels (medians over `reps`, events): a copy into a second buffer and an
+    in-place scale, each reading and writing the field once (16 B per point,
+    like a solver stage).  Context for the stage kernels, not a peak."""
+    a = src.clone()
+    b = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        out = []
+        for _ in range(reps + 2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return float(sorted(out[2:])[reps // 2])
+
+    nbytes = 2 * src.numel() * src.element_size()
+    copy_ms = timed(lambda: b.copy_(a))
+    scale_ms = timed(lambda: a.mul_(1.0))
+    del a, b
+    return {"bytes": nbytes, "copy_ms": round(copy_ms, 4),
+            "copy_GBs": round(nbytes / (copy_ms * 1e-3) / 1e9, 1),
+            "inplace_ms": round(scale_ms, 4),
+            "inplace_GBs": round(nbytes / (scale_ms * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(prob, budget_s=12.0, max_reps=6):
     """The FP64 oracle on the host: plain solves of the full workload, as
     many as fit in about `budget_s` (at least one); returns the baseline
@@ -207,6 +237,12 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": names[STAGES[dom]], "algorithmic_bytes_per_launch": alg_bytes}
 
+    # what plain sweeps of the same field reach on this GPU (runtime kernels,
+    # no solver arithmetic): context for the stage kernels' bandwidth
+    ref_bw = hbm_reference(src, torch)
+    log(f"[bench] plain sweeps of the field: copy {ref_bw['copy_GBs']} GB/s, "
+        f"in-place scale {ref_bw['inplace_GBs']} GB/s")
+
     # correctness of the product entry point on this workload
     check = src.clone()
     plan.solve(check)
@@ -260,6 +296,7 @@ def main():
                           "GBs": round(5 * alg_bytes / (ms_per_step * 1e-3) / 1e9, 1),
                           "frac": round(5 * alg_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels": kernels,
+        "hbm_reference": ref_bw,
         "rel_l2_vs_oracle": rel,
         "cpu_baseline": cpu,
         "forms": forms,
