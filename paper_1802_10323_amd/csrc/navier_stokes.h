@@ -16,11 +16,14 @@
 // the products on its two sides over the spacing.  Diffusion is the
 // three-point second difference per axis.
 //
-// One thread per cell computes the three faces that cell owns; neighbours
-// along x come from the adjacent lanes' lines, along y and z from the
-// caches.  Traffic per cell: velocity 24 B, p 8 B, AD_prev 24 B (read
-// when beta_k != 0), AD 24 B (written when the next substep needs it),
-// u* 24 B.
+// Three kernels compute it, each thread the three faces its cell owns:
+// rk3_predict_kernel (one cell per thread, neighbours through the
+// caches), rk3_predict_tiled_kernel (z-marching LDS plane tiles) and
+// rk3_predict_div_kernel (the tiled form with the right-hand side of the
+// pressure equation, and optionally the previous substep's projection,
+// fused in; the default).  Traffic per cell: velocity 24 B, p 8 B,
+// AD_prev 24 B (read when beta_k != 0), AD 24 B (written when the next
+// substep needs it), u* 24 B.
 #pragma once
 #include "refine_kernels.h"
 
