@@ -135,6 +135,31 @@ def cmd_stats(a):
     print(text, end="")
 
 
+def cmd_counters(a):
+    """Per solver stage, the median per launch of every counter in one
+    counter file (any counters, e.g. address-translation ones)."""
+    names = set()
+    with open(a.csv) as fh:
+        for r in csv.DictReader(fh):
+            names.add(r["Counter_Name"])
+    names = sorted(names)
+    per = {c: stage_values(read_counters(a.csv, c)) for c in names}
+    lines = [f"# hardware counters per launch of each solver stage, workload {a.workload}",
+             "# command:"]
+    lines += [f"#   {c}" for c in a.command]
+    lines.append(f"kernel_source_hash {kernel_source_hash()}")
+    for s in STAGES:
+        kname = next((per[c][s][0] for c in names if per[c][s][0]), None)
+        if kname is None:
+            continue
+        vals = " ".join(f"{c} {statistics.median(per[c][s][1]):.0f}" for c in names if per[c][s][1])
+        lines.append(f"stage {s} kernel {short_name(kname).replace(' ', '')} {vals}")
+    text = "\n".join(lines) + "\n"
+    with open(a.out, "w") as fh:
+        fh.write(text)
+    print(text, end="")
+
+
 def read_traffic(path):
     """{stage: bytes per launch} from a traffic summary, with its source hash."""
     out, src = {}, None
@@ -164,8 +189,13 @@ def main():
     s.add_argument("--csv", required=True)
     s.add_argument("--out", required=True)
     s.add_argument("--command", action="append", default=[])
+    c = sub.add_parser("counters")
+    c.add_argument("--csv", required=True)
+    c.add_argument("--workload", required=True)
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", action="append", default=[])
     a = ap.parse_args()
-    (cmd_traffic if a.what == "traffic" else cmd_stats)(a)
+    {"traffic": cmd_traffic, "stats": cmd_stats, "counters": cmd_counters}[a.what](a)
 
 
 if __name__ == "__main__":
