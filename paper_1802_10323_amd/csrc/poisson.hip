@@ -27,6 +27,7 @@
 #include "refine_kernels.h"
 #include "projection.h"
 #include "navier_stokes.h"
+#include "plane_kernels.h"
 
 using namespace poisson_dev;
 
@@ -147,6 +148,9 @@ struct poisson_plan {
   bool generic_tri = false;    // POISSON_GENERIC_TRI=1: size-generic elimination kernel only
   int grid_cap = 0;            // POISSON_GRID_CAP=B: at most B blocks per stage launch (0: none)
   int rk3_kernel = 0;          // POISSON_RK3_KERNEL: 0 fused (default), 1 "tiled", 2 "simple"
+  bool plane_off = false;      // POISSON_PLANE=0: no small-plane transforms
+  char* plane_mats = nullptr;  // small grids: dense transform matrices (FP64, then FP32)
+  size_t plane_off_f = 0;      // byte offset of the FP32 copy in plane_mats
   int t1, t2, s;
   bool singular, s_periodic;
   int device;
@@ -306,6 +310,14 @@ static int lds_setup_once() {
           ALLOW((tri_fast_kernel<float, C::RPC, C::P, 1>));
           return 0LL;
         });
+    ALLOW((tri_fast_kernel<double, 2, 16, 0>));
+    ALLOW((tri_fast_kernel<float, 2, 16, 0>));
+    ALLOW((tri_fast_kernel<double, 3, 16, 0>));
+    ALLOW((tri_fast_kernel<float, 3, 16, 0>));
+    ALLOW((plane_transform_kernel<double, false>));
+    ALLOW((plane_transform_kernel<double, true>));
+    ALLOW((plane_transform_kernel<float, false>));
+    ALLOW((plane_transform_kernel<float, true>));
     ALLOW((batch_r2r_kernel<double>));
     ALLOW((batch_tri_kernel<double>));
     ALLOW((batch_r2r_kernel<float>));
@@ -677,6 +689,10 @@ static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
   t_grid_cap = p->grid_cap;
   if (!p->generic_tri) {
     const int n = p->dims[p->s];
+    // small grids (transforms as dense matrices): lines of 32 or 48 points in
+    // the 16-lane chunking, instead of the size-generic kernel
+    if (p->plane_mats && n == 32) return launch_tri_fast<T, 2, 16>(p, data, st, skip);
+    if (p->plane_mats && n == 48) return launch_tri_fast<T, 3, 16>(p, data, st, skip);
     const int rc = launch_tri_variant<T>(p, tuned_choice(1, sizeof(T), n, p->s == 0), data, st, skip);
     if (rc != -1) return rc;
   }
@@ -722,15 +738,97 @@ static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
 // The three steps of Sec. 2.1: forward transforms t1 then t2, elimination
 // along s, backward transforms t2 then t1.  out64 (FP32 only): the last
 // launch writes the widened solution there instead of in place.
+// Both transforms of one direction on a small grid (plane_kernels.h).
+template <typename T>
+static int launch_plane(const poisson_plan* p, bool inverse, T* data, hipStream_t st,
+                        const double* skip, double* out64) {
+  const int nx = p->dims[0], ny = p->dims[1];
+  const size_t n2x = (size_t)nx * nx, n2y = (size_t)ny * ny;
+  const T* m = reinterpret_cast<const T*>(p->plane_mats + (sizeof(T) == 8 ? 0 : p->plane_off_f));
+  // order: forward x, forward y, backward x, backward y
+  const T* mx = m + (inverse ? n2x + n2y : 0);
+  const T* my = mx + n2x;
+  const size_t lds = (2 * (size_t)nx * ny + n2x + n2y) * sizeof(T);
+  if (inverse)
+    hipLaunchKernelGGL((plane_transform_kernel<T, true>), dim3(p->dims[2]), dim3(PLANE_NT), lds, st,
+                       data, out64, mx, my, nx, ny, skip);
+  else
+    hipLaunchKernelGGL((plane_transform_kernel<T, false>), dim3(p->dims[2]), dim3(PLANE_NT), lds, st,
+                       data, out64, mx, my, nx, ny, skip);
+  HIP_TRY(hipGetLastError());
+  return POISSON_OK;
+}
+
 template <typename T>
 static int solve_typed(const poisson_plan* p, T* data, hipStream_t st,
                        const double* skip = nullptr, double* out64 = nullptr) {
   int rc;
+  if (p->plane_mats) {             // small grid: both transforms of a direction in one launch
+    if ((rc = launch_plane<T>(p, false, data, st, skip, nullptr))) return rc;
+    if ((rc = launch_tridiag<T>(p, data, st, skip))) return rc;
+    return launch_plane<T>(p, true, data, st, skip, sizeof(T) == 8 ? nullptr : out64);
+  }
   if ((rc = launch_r2r<T>(p, 0, 0, data, st, skip))) return rc;
   if ((rc = launch_r2r<T>(p, 1, 0, data, st, skip))) return rc;
   if ((rc = launch_tridiag<T>(p, data, st, skip))) return rc;
   if ((rc = launch_r2r<T>(p, 1, 1, data, st, skip))) return rc;
   if ((rc = launch_r2r<T>(p, 0, 1, data, st, skip, out64))) return rc;
+  return POISSON_OK;
+}
+
+// Dense transform matrices of a small grid's two transformed axes (x and
+// y), FP64 then FP32, in plane_mats: forward x, forward y, backward x,
+// backward y, each n x n with row j the transform of unit vector j.  They
+// are made by running the plan's own transform kernels (same tables, same
+// variants) on the unit vectors, laid out as contiguous lines.
+static int build_plane_matrices(poisson_plan* p) {
+  const int n[2] = {p->dims[0], p->dims[1]};
+  const int nmax = std::max(n[0], n[1]);
+  double* tmp = nullptr;
+  if (hipMalloc(&tmp, (size_t)nmax * nmax * sizeof(double)) != hipSuccess)
+    return fail(POISSON_ENOMEM, "transform matrix scratch allocation failed");
+  std::vector<double> h, eye;
+  int rc = POISSON_OK;
+  for (int inv = 0; inv < 2 && rc == POISSON_OK; ++inv)
+    for (int r = 0; r < 2 && rc == POISSON_OK; ++r) {
+      const int m = n[r];
+      const size_t mm = (size_t)m * m;
+      eye.assign(mm, 0.0);
+      for (int j = 0; j < m; ++j) eye[(size_t)j * m + j] = 1.0;
+      if (hipMemcpy(tmp, eye.data(), mm * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        rc = fail(POISSON_EHIP, "transform matrix upload failed");
+        break;
+      }
+      poisson_plan q = *p;            // the same tables; m lines of m contiguous points
+      q.dims[0] = m;
+      q.dims[1] = m;
+      q.dims[2] = 1;
+      q.ax[r].axis = 0;
+      q.grid_cap = 0;
+      q.plane_mats = nullptr;
+      if ((rc = launch_r2r<double>(&q, r, inv, tmp, nullptr))) break;
+      const size_t off = h.size();
+      h.resize(off + mm);
+      if (hipMemcpy(h.data() + off, tmp, mm * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = fail(POISSON_EHIP, "transform matrix download failed");
+    }
+  (void)hipFree(tmp);
+  if (rc != POISSON_OK) return rc;
+  const std::vector<float> hf(h.begin(), h.end());
+  const size_t bytes_d = h.size() * sizeof(double);
+  const size_t off_f = align_up(bytes_d, 256);
+  const size_t total = off_f + hf.size() * sizeof(float);
+  if (hipMalloc(&p->plane_mats, total) != hipSuccess)
+    return fail(POISSON_ENOMEM, "transform matrix allocation (%zu B) failed", total);
+  if (hipMemcpy(p->plane_mats, h.data(), bytes_d, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->plane_mats + off_f, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    (void)hipFree(p->plane_mats);
+    p->plane_mats = nullptr;
+    return fail(POISSON_EHIP, "transform matrix upload failed");
+  }
+  p->plane_off_f = off_f;
+  p->tab_bytes += total;
   return POISSON_OK;
 }
 
@@ -839,6 +937,8 @@ extern "C" poisson_plan* plan_create_helmholtz(int nx, int ny, int nz, double dx
     p->generic_tri = env && env[0] == '1';
     env = std::getenv("POISSON_GRID_CAP");
     p->grid_cap = env ? std::max(0, std::atoi(env)) : 0;
+    env = std::getenv("POISSON_PLANE");
+    p->plane_off = env && env[0] == '0';
     env = std::getenv("POISSON_RK3_KERNEL");
     p->rk3_kernel = !env ? 0 : std::strcmp(env, "tiled") == 0 ? 1 : std::strcmp(env, "simple") == 0 ? 2 : 0;
   }
@@ -976,6 +1076,15 @@ extern "C" poisson_plan* plan_create_helmholtz(int nx, int ny, int nz, double dx
     delete p;
     return nullptr;
   }
+  // small grid transformed along x and y: the transforms as dense matrices
+  if (p->s == 2 && !p->plane_off && !p->generic_r2r && p->dims[0] <= PLANE_NMAX &&
+      p->dims[1] <= PLANE_NMAX) {
+    if (build_plane_matrices(p)) {
+      (void)hipFree(p->dtab);
+      delete p;
+      return nullptr;
+    }
+  }
   return p;
 }
 
@@ -996,6 +1105,7 @@ extern "C" void plan_destroy(poisson_plan* p) {
   if (!p) return;
   free_workspace(p);
   if (p->dtab) (void)hipFree(p->dtab);
+  if (p->plane_mats) (void)hipFree(p->plane_mats);
   delete p;
 }
 
