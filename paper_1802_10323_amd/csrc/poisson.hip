@@ -482,14 +482,15 @@ static bool async_applies(const poisson_plan* p, const AxisTables& A, int shape)
          (A.axis == 0 || p->dims[0] % (int)(16 / sizeof(T)) == 0);
 }
 
-// True if the register-staged form applies to axis A in type T (FP64,
-// length 512, strided axis).
-// length 512, strided axis, at least 32 x positions (a tile is 32
-// consecutive x of one band) and element offsets within a tile's lines
-// that fit 32 bits.
+// True if the register-staged form applies to axis A in type T: FP64,
+// length 512, strided axis, nx a multiple of 32 (a tile is 32 consecutive x
+// of one band, and every line of every tile exists, so its stores need no
+// branch) and element offsets within a tile's lines that fit 32 bits.  The
+// launch also needs a 16-byte aligned field (pairs of lines are read with
+// 16-byte loads).
 template <typename T>
 static bool regstage_applies(const poisson_plan* p, const AxisTables& A) {
-  if (sizeof(T) != 8 || A.m != 256 || A.axis == 0 || p->dims[0] < 32) return false;
+  if (sizeof(T) != 8 || A.m != 256 || A.axis == 0 || p->dims[0] % 32) return false;
   const long long sp = A.axis == 1 ? (long long)p->dims[0] : (long long)p->dims[0] * p->dims[1];
   return 32 + (long long)A.n * sp < (1LL << 32);
 }
@@ -501,7 +502,7 @@ static int launch_fast_variant(const poisson_plan* p, const AxisTables& A, int V
                                double* out64 = nullptr) {
   if (V == kRegStageVariant) {
     if constexpr (sizeof(T) == 8) {
-      if (regstage_applies<T>(p, A)) {
+      if (regstage_applies<T>(p, A) && (reinterpret_cast<uintptr_t>(data) & 15) == 0) {
         const R2RFastArgs<T> a = fast_args<T, RegStageCfg>(p, A, inverse, data, skip);
         const hipError_t e = regstage_launch(a, A.kind, inverse, st);
         if (e != hipSuccess)

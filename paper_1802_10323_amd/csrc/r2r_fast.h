@@ -1032,6 +1032,101 @@ void r2r_async_tight_kernel(R2RFastArgs<T> A) {
   }
 }
 
+// ---------------------------------------------------------------- full-tile stores
+// The forward real-DFT / DCT-II / DST-II split and the DCT-IV / DST-IV
+// post-twiddle of split_store_body and post_store_body, for strided tiles
+// whose lines all exist: every lane issues the same number of stores with
+// no branch around them (a lane's outputs differ only by selects), so that
+// the compiler's waits for loads issued before them can leave the stores in
+// flight.  `out` is point 0 of the lane's line, `sp` the point stride.
+//
+// Split: lane qq takes wavenumbers k = qq + s*QT, s < M/(2 QT), each with
+// its partner j = M - k, four outputs per k; the lane with k = 0 has two
+// outputs there and takes the middle wavenumber M/2 (two outputs) in the
+// same step.
+template <typename T, typename C, int KIND>
+__device__ __forceinline__ void split_store_full(lptr<const T> lds, lptr<const cplx<T>> split,
+                                                 lptr<const cplx<T>> quarter, gptr<T> out,
+                                                 long long sp, T scale, int ln, int qq) {
+  using L = FastLayout<T, C>;
+  constexpr int M = L::M, N = L::N, NLP = L::NLP, QT = L::QT, H = M / 2;
+  static_assert(H % QT == 0, "wavenumbers split evenly over the lanes of a line");
+  auto xy = [&](int k, cplx<T>& X, cplx<T>& Y) {
+    const int kc = (M - k) % M;
+    const cplx<T> z = {lds[(2 * k) * NLP + ln], lds[(2 * k + 1) * NLP + ln]};
+    const cplx<T> zc = {lds[(2 * kc) * NLP + ln], -lds[(2 * kc + 1) * NLP + ln]};
+    const cplx<T> E = {(T)0.5 * (z.re + zc.re), (T)0.5 * (z.im + zc.im)};
+    const cplx<T> D = csub(z, zc);
+    const cplx<T> O = {(T)0.5 * D.im, (T)-0.5 * D.re};
+    const cplx<T> wO = cmul(ldc(split, k), O);
+    X = cadd(E, wO);
+    Y = cconj(csub(E, wO));
+  };
+  const bool zero = qq == 0;
+#pragma unroll
+  for (int s = 0; s < H / QT; ++s) {
+    const int k = qq + s * QT, j = M - k;
+    cplx<T> X, Y;
+    xy(k, X, Y);
+    int r[4];
+    T v[4];
+    if constexpr (KIND == K_P) {
+      r[0] = 2 * k - 1; r[1] = 2 * k; r[2] = 2 * j - 1; r[3] = 2 * j;
+      v[0] = X.re; v[1] = -X.im; v[2] = Y.re; v[3] = -Y.im;
+      if (s == 0) {
+        cplx<T> Xm, Ym;
+        xy(H, Xm, Ym);
+        r[0] = zero ? 0 : r[0];
+        r[1] = zero ? N - 1 : r[1];
+        r[2] = zero ? 2 * H - 1 : r[2];
+        r[3] = zero ? 2 * H : r[3];
+        v[1] = zero ? Y.re : v[1];
+        v[2] = zero ? Xm.re : v[2];
+        v[3] = zero ? -Xm.im : v[3];
+      }
+    } else {
+      constexpr bool rev = KIND == K_DD;
+      const cplx<T> u = cmul(ldc(quarter, k), X);
+      const cplx<T> u2 = cmul(ldc(quarter, j), Y);
+      r[0] = rev ? N - 1 - k : k; r[1] = rev ? k - 1 : N - k;
+      r[2] = rev ? N - 1 - j : j; r[3] = rev ? j - 1 : N - j;
+      v[0] = (T)2 * u.re; v[1] = (T)-2 * u.im; v[2] = (T)2 * u2.re; v[3] = (T)-2 * u2.im;
+      if (s == 0) {
+        cplx<T> Xm, Ym;
+        xy(H, Xm, Ym);
+        const cplx<T> um = cmul(ldc(quarter, H), Xm);
+        r[1] = zero ? (rev ? N - 1 - M : M) : r[1];
+        r[2] = zero ? (rev ? N - 1 - H : H) : r[2];
+        r[3] = zero ? (rev ? H - 1 : N - H) : r[3];
+        v[1] = zero ? v[2] : v[1];
+        v[2] = zero ? (T)2 * um.re : v[2];
+        v[3] = zero ? (T)-2 * um.im : v[3];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) out[(long long)r[t] * sp] = v[t] * scale;
+  }
+}
+
+// DCT-IV / DST-IV post-twiddle (post_store_body) for full strided tiles.
+template <typename T, typename C, int KIND>
+__device__ __forceinline__ void post_store_full(lptr<const T> lds, lptr<const cplx<T>> post,
+                                                gptr<T> out, long long sp, T scale, int ln,
+                                                int qq) {
+  using L = FastLayout<T, C>;
+  constexpr int N = L::N, NLP = L::NLP, QT = L::QT;
+#pragma unroll
+  for (int s = 0; s < L::E; ++s) {
+    const int k = qq + s * QT;
+    const cplx<T> V = cmul(cplx<T>{lds[(2 * k) * NLP + ln], lds[(2 * k + 1) * NLP + ln]},
+                           ldc(post, k));
+    const T ye = ((T)2 * V.re) * scale;
+    const T yo = ((T)-2 * V.im) * scale;
+    out[(long long)(2 * k) * sp] = ye;
+    out[(long long)(N - 1 - 2 * k) * sp] = KIND == K_ND ? yo : -yo;
+  }
+}
+
 // ---------------------------------------------------------------- register-staged form
 // FP64 length 512 on the strided axes with 32 lines per tile, so that each
 // row of a tile is 256 contiguous bytes of the field (16 lines give
@@ -1065,72 +1160,133 @@ void r2r_regstage_kernel(R2RFastArgs<T> A) {
   const lptr<const cplx<T>> tw_b = S.twa + (ivk ? M : L::SPLIT);
   fast_twiddles<T, C>(S, A, tid);
   const TileRange tr = xcd_tiles(g.ntiles);
-  // the prefetched points (one of the two, by type)
-  T buf[plain ? EPT : 1];
-  PreRegs<T, C> pr;
-  // a tile is 32 consecutive x positions of one band (nx >= 32, checked at
-  // launch): a uniform base plus a 32-bit lane offset (the launch checks
-  // that every offset fits), so no load needs a 64-bit lane address
-  const size_t row_step = (size_t)QT * (size_t)g.sp;
+  // The plain types read two adjacent lines per thread (16-byte loads): a
+  // thread's EPT points then take EPT/2 load instructions, so that they and
+  // the EPT stores of the tile before stay within the 63 operations the
+  // vector-memory counter tracks (beyond it the compiler's waits drain the
+  // stores along with the loads).  Thread t reads lines 2*(t mod NL/2) + {0,1}
+  // at rows t / (NL/2) + i*QP.
+  constexpr int NL2 = NL / 2, QP = L::NT / NL2, EPP = N / QP;
+  static_assert(EPP * QP == N && 2 * EPP == EPT, "line-pair rows");
+  using T2 = T __attribute__((ext_vector_type(2)));
+  T2 buf[plain ? EPP : 1];
+  // DCT-IV / DST-IV: the two points of each of the thread's EPP/2 complex
+  // indices j = t / (NL/2) + s*QP, for both lines
+  T2 pv[ivk ? EPP / 2 : 1][2];
+  // a tile is 32 consecutive x positions of one band (nx >= 32 and even,
+  // a 16-byte aligned field, checked at launch): a uniform base plus a
+  // 32-bit lane offset (the launch checks that every offset fits), so no
+  // load needs a 64-bit lane address
+  const size_t pair_step = (size_t)QP * (size_t)g.sp;
   const unsigned sp32 = (unsigned)g.sp;
-  auto fetch = [&](int tile, int lt, int qt) {
+  auto fetch = [&](int tile, int lt, int qt, int tt) {
     const TileOrigin o = tile_origin(g, tile);
     const gptr<const T> tb = as_global(static_cast<const T*>(A.data)) + (o.x0 + (long long)o.b0 * g.sb);
-    const bool ok = o.x0 + lt < g.nx;
     if constexpr (plain) {
-      const unsigned lane_off = (unsigned)lt + (unsigned)qt * sp32;
-      if (ok) {
+      const int lp = tt % NL2, qp = tt / NL2;
+      const unsigned lane_off = 2u * (unsigned)lp + (unsigned)qp * sp32;
+      if (o.x0 + 2 * lp < g.nx) {
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) buf[i] = (tb + i * row_step)[lane_off];
+        for (int i = 0; i < EPP; ++i)
+          buf[i] = *reinterpret_cast<const gptr<const T2>>(&(tb + i * pair_step)[lane_off]);
       } else {
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) buf[i] = (T)0;
+        for (int i = 0; i < EPP; ++i) buf[i] = T2{(T)0, (T)0};
       }
-    } else if (ok) {
-      pre_read<T, C>([&](int p) -> T { return tb[(unsigned)lt + (unsigned)p * sp32]; }, pr, kind, qt);
     } else {
-      pre_read<T, C>([](int) -> T { return (T)0; }, pr, kind, qt);
+      const int lp = tt % NL2, qp = tt / NL2;
+      const bool ok = o.x0 + 2 * lp < g.nx;
+#pragma unroll
+      for (int i = 0; i < EPP / 2; ++i) {
+        const int j = qp + i * QP;
+        const int r0 = kind == K_ND ? 2 * j : N - 1 - 2 * j;
+        const int r1 = kind == K_ND ? N - 1 - 2 * j : 2 * j;
+        if (ok) {
+          pv[i][0] = *reinterpret_cast<const gptr<const T2>>(&tb[2u * (unsigned)lp + (unsigned)r0 * sp32]);
+          pv[i][1] = *reinterpret_cast<const gptr<const T2>>(&tb[2u * (unsigned)lp + (unsigned)r1 * sp32]);
+        } else {
+          pv[i][0] = T2{(T)0, (T)0};
+          pv[i][1] = T2{(T)0, (T)0};
+        }
+      }
+    }
+    (void)lt;
+    (void)qt;
+  };
+  // registers -> tile: the DCT-IV / DST-IV pre-twiddle, or the rows (the
+  // forward types at their permuted rows, the inverse ones unpermuted)
+  auto place = [&](int l, int q, int tt) {
+    if constexpr (ivk) {
+      const int lp = tt % NL2, qp = tt / NL2;
+#pragma unroll
+      for (int i = 0; i < EPP / 2; ++i) {
+        const int j = qp + i * QP;
+        const cplx<T> w = ldc(tw_a, j);
+        const cplx<T> z0 = cmul(cplx<T>{pv[i][0].x, pv[i][1].x}, w);
+        const cplx<T> z1 = cmul(cplx<T>{pv[i][0].y, pv[i][1].y}, w);
+        S.tile[(2 * j) * NLP + 2 * lp] = z0.re;
+        S.tile[(2 * j + 1) * NLP + 2 * lp] = z0.im;
+        S.tile[(2 * j) * NLP + 2 * lp + 1] = z1.re;
+        S.tile[(2 * j + 1) * NLP + 2 * lp + 1] = z1.im;
+      }
+      (void)l;
+      (void)q;
+    } else {
+      const int lp = tt % NL2, qp = tt / NL2;
+#pragma unroll
+      for (int i = 0; i < EPP; ++i) {
+        bool neg = false;
+        const int r = inverse ? qp + i * QP : load_row(kind, inverse, qp + i * QP, N, neg);
+        S.tile[r * NLP + 2 * lp] = neg ? -buf[i].x : buf[i].x;
+        S.tile[r * NLP + 2 * lp + 1] = neg ? -buf[i].y : buf[i].y;
+      }
     }
   };
-  if (tr.first < tr.end) fetch(tr.first, tid % NL, tid / NL);
+  if (tr.first < tr.end) {
+    fetch(tr.first, tid % NL, tid / NL, tid);
+    place(tid % NL, tid / NL, tid);
+  }
+  // The next tile is placed at the bottom of the loop, after the current
+  // tile's stores: its loads were issued before those stores in the same
+  // iteration, so the waits for them leave the stores in flight (placed at
+  // the top, the waits would be counted from the first tile's state, which
+  // has no stores, and would drain every store of the previous tile).
   for (int tile = tr.first; tile < tr.end; tile += tr.step) {
     // thread indices opaque per tile: addresses are recomputed in each step
     // instead of being held across the loop
     int l = tid % NL, q = tid / NL, tt = tid;
     asm volatile("" : "+v"(l), "+v"(q), "+v"(tt));
-    if constexpr (ivk) {
-      pre_write<T, C>(pr, S.tile, tw_a, l, q);
-    } else if constexpr (!inverse) {
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        bool neg;
-        const int r = load_row(kind, inverse, q + i * QT, N, neg);
-        S.tile[r * NLP + l] = neg ? -buf[i] : buf[i];
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) S.tile[(q + i * QT) * NLP + l] = buf[i];
-      lds_barrier();
+    lds_barrier();
+    if constexpr (plain && inverse) {
       const lptr<const T> raw = S.tile;
       combine_to_tile<T, C, true>([&](int p) -> T { return raw[p * NLP + l]; }, S.tile, tw_a, tw_b,
                                   kind, l, q);
+      lds_barrier();
     }
-    lds_barrier();
-    if (tile + tr.step < tr.end) fetch(tile + tr.step, l, q);
+    const bool more = tile + tr.step < tr.end;
+    if (more) fetch(tile + tr.step, l, q, tt);
     if constexpr (!(inverse && kind <= K_DD)) fast_passes<T, C, true, 0, true>(S.tile, tw_fft, l, q);
     else fast_passes<T, C, false, 0, true>(S.tile, tw_fft, l, q);
     const TileOrigin o = tile_origin(g, tile);
     const long long base = line_base(g, o, l);
     if constexpr (ivk)
-      post_store_body<T, C>(S.tile, tw_b, kind, as_global(A.data), base, g.sp, 0, 0, A.scale, l, q,
-                            tt);
+      post_store_full<T, C, KIND>(S.tile, tw_b, as_global(A.data) + base, g.sp, A.scale, l, q);
     else if constexpr (!inverse)
-      split_store_body<T, C>(S.tile, tw_a, tw_b, kind, as_global(A.data), base, g.sp, 0, 0, A.scale,
-                             l, q, tt);
-    else
-      fast_store<T, C, true>(S.tile, as_global(A.data), base, g.sp, 0, 0, kind, inverse, A.scale, l,
-                             q, tt);
+      split_store_full<T, C, KIND>(S.tile, tw_a, tw_b, as_global(A.data) + base, g.sp, A.scale, l, q);
+    else {
+      // every line of the tile exists (nx a multiple of 32): no branch
+      // around the stores, so the waits for the next tile's loads count them
+      const gptr<T> out = as_global(A.data) + base;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        bool neg;
+        const int r = store_row(kind, inverse, q + i * QT, N, neg);
+        const T v = S.tile[r * NLP + l] * A.scale;
+        out[(long long)(q + i * QT) * g.sp] = neg ? -v : v;
+      }
+    }
     lds_barrier();
+    if (more) place(l, q, tt);
   }
 }
 
