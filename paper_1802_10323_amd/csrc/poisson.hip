@@ -619,14 +619,20 @@ static bool tri_async_applies(const poisson_plan* p) {
 }
 
 // True if the direct elimination applies: contiguous lines whose chunks (of
-// the variant-0 chunking) are whole 16-byte pieces, a 16-byte aligned field.
+// the variant-0 chunking) are whole 16-byte pieces, a 16-byte aligned field,
+// and a line count that splits into whole groups of 64 / P lines.
 template <typename T>
 static bool tri_direct_applies(const poisson_plan* p, const T* data) {
   if (p->s != 0 || (reinterpret_cast<uintptr_t>(data) & 15) != 0) return false;
   const long long rpc = with_tri_cfg(p->dims[0], 0, [](auto cfg) {
     return (long long)decltype(cfg)::RPC;
   });
-  return rpc > 0 && (rpc * (long long)sizeof(T)) % 16 == 0;
+  const long long lanes = with_tri_cfg(p->dims[0], 0, [](auto cfg) {
+    return (long long)decltype(cfg)::P;
+  });
+  // whole groups of 64 / P lines (a wave's lines per step)
+  return rpc > 0 && (rpc * (long long)sizeof(T)) % 16 == 0 &&
+         ((long long)p->dims[1] * p->dims[2]) % (64 / lanes) == 0;
 }
 
 // Specialised elimination in variant V (-1: the length has none).

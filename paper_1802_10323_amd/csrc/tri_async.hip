@@ -37,9 +37,10 @@ hipError_t launch_direct(const TriFastArgs<T>& a, hipStream_t st) {
   if constexpr ((RPC * sizeof(T)) % 16 != 0) {
     return hipErrorInvalidValue;
   } else {
-    if (a.g.layout != 1) return hipErrorInvalidValue;
+    // whole groups of 64 / P lines only
+    if (a.g.layout != 1 || a.g.nlines % (64 / P) != 0) return hipErrorInvalidValue;
     void (*k)(TriFastArgs<T>) = tri_direct_kernel<T, RPC, P>;
-    const long long groups = ((long long)a.g.nlines + 64 / P - 1) / (64 / P);
+    const long long groups = (long long)a.g.nlines / (64 / P);
     hipLaunchKernelGGL(k, dim3(direct_blocks(reinterpret_cast<const void*>(k), (groups + 3) / 4)),
                        dim3(256), 0, st, a);
     return hipGetLastError();

@@ -507,25 +507,36 @@ void tri_direct_kernel(TriFastArgs<T> A) {
   const lptr<T> wbuf = as_lds(buf_raw) + wave * BUF;
   const int c = lane % P;                      // chunk of this lane
   const int lw = lane / P;                     // line within the group
-  const int nlines = A.g.nlines;
-  const int groups = (nlines + LPW - 1) / LPW;
+  const int groups = A.g.nlines / LPW;          // whole groups (checked at launch)
   const int gstep = gridDim.x * WPB;
   using Piece = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+  // The next group's pieces and eigenvalue shifts are read before the
+  // current group's stores are issued, and placed after them, at the bottom
+  // of the loop: the waits for those reads then leave the stores in flight.
+  // With whole groups no lane skips a load or a store, so the compiler can
+  // count them (a branch around them would make it wait for everything).
   Piece nxt[V::PIECES];
+  double lu_n = 0.0, lv_n = 0.0;
+  bool sing_n = false;
   // padded LDS slot of value e of the group
   auto slot = [](int e) { return e + e / RPC; };
   auto fetch = [&](int grp) {
-    const long long first = (long long)grp * GV;
-    const long long avail = ((long long)nlines * N - first) / V::PER;   // whole pieces left
-    const Piece* src = reinterpret_cast<const Piece*>(A.data + first);
+    const Piece* src = reinterpret_cast<const Piece*>(A.data + (long long)grp * GV);
 #pragma unroll
-    for (int k = 0; k < V::PIECES; ++k)
-      if (lane + 64 * k < avail) nxt[k] = src[lane + 64 * k];
+    for (int k = 0; k < V::PIECES; ++k) nxt[k] = src[lane + 64 * k];
+    const int line = grp * LPW + lw;
+    const int v = line / A.nu;
+    const int u = line - v * A.nu;
+    lu_n = A.lamu[u];
+    lv_n = A.lamv[v];
+    sing_n = A.singular && u == 0 && v == 0;
   };
-  int grp = blockIdx.x * WPB + wave;
-  if (grp < groups) fetch(grp);
-  for (; grp < groups; grp += gstep) {
-    // coalesced pieces -> chunk order, through the wave's buffer
+  double xr[RPC];
+  double mu = 0.0;
+  bool sing = false;
+  const int cb = slot(lw * N + c * RPC);
+  // coalesced pieces -> chunk order, through the wave's buffer
+  auto place = [&]() {
 #pragma unroll
     for (int k = 0; k < V::PIECES; ++k) {
       const T* v = reinterpret_cast<const T*>(&nxt[k]);
@@ -534,20 +545,19 @@ void tri_direct_kernel(TriFastArgs<T> A) {
       for (int e = 0; e < V::PER; ++e) wbuf[slot(e0 + e)] = v[e];
     }
     wave_lds_fence();
-    double xr[RPC];
-    const int cb = slot(lw * N + c * RPC);
 #pragma unroll
     for (int i = 0; i < RPC; ++i) xr[i] = (double)wbuf[cb + i];
-    if (grp + gstep < groups) fetch(grp + gstep);
-    const int line = grp * LPW + lw;
-    const bool valid = line < nlines;
-    int u = 0, v = 0;
-    if (valid) {
-      v = line / A.nu;
-      u = line - v * A.nu;
-    }
-    const double mu = valid ? A.lamu[u] + A.lamv[v] : -1.0;
-    const bool sing = A.singular && valid && u == 0 && v == 0;
+    mu = lu_n + lv_n;
+    sing = sing_n;
+  };
+  int grp = blockIdx.x * WPB + wave;
+  if (grp < groups) {
+    fetch(grp);
+    place();
+  }
+  for (; grp < groups; grp += gstep) {
+    const bool more = grp + gstep < groups;
+    if (more) fetch(grp + gstep);
     const int wave_sing = __any(sing) ? 1 : 0;
     tri_line_solve<RPC, P, false>([&](int i) -> double { return xr[i]; },
                                   [&](int i, double x) { xr[i] = x; }, coef, c, mu,
@@ -557,9 +567,7 @@ void tri_direct_kernel(TriFastArgs<T> A) {
 #pragma unroll
     for (int i = 0; i < RPC; ++i) wbuf[cb + i] = (T)xr[i];
     wave_lds_fence();
-    const long long first = (long long)grp * GV;
-    const long long avail = ((long long)nlines * N - first) / V::PER;
-    Piece* dst = reinterpret_cast<Piece*>(A.data + first);
+    Piece* dst = reinterpret_cast<Piece*>(A.data + (long long)grp * GV);
 #pragma unroll
     for (int k = 0; k < V::PIECES; ++k) {
       Piece out;
@@ -567,9 +575,10 @@ void tri_direct_kernel(TriFastArgs<T> A) {
       const int e0 = (lane + 64 * k) * V::PER;
 #pragma unroll
       for (int e = 0; e < V::PER; ++e) o[e] = wbuf[slot(e0 + e)];
-      if (lane + 64 * k < avail) dst[lane + 64 * k] = out;
+      dst[lane + 64 * k] = out;
     }
     wave_lds_fence();
+    if (more) place();
   }
 }
 
