@@ -1134,13 +1134,13 @@ __device__ __forceinline__ void post_store_full(lptr<const T> lds, lptr<const cp
 // of its bandwidth: measured 0.43 against 0.48 ms for an in-place read and
 // write of every tile).  The tile (135 KiB) and the twiddles fill the LDS,
 // so the next tile is read into registers while the current one is
-// transformed and stored: the points of the thread's rows, or for the
-// DCT-IV / DST-IV types straight away the two points each complex index of
-// the pre-twiddle pairs, so that this step runs from registers into the
-// tile.  The inverse real DFT / DCT-II / DST-II place the rows unpermuted
-// and run their combine step in the tile (a barrier between its reads and
-// its writes): reading its four rows per wavenumber pair from HBM instead
-// was slower on the 512^3 cube's z axis (0.57 against 0.54 ms).
+// transformed and stored, and each input step runs from registers into the
+// tile as the tile is placed: the forward real DFT / DCT-II / DST-II place
+// the thread's rows at their permuted positions, the DCT-IV / DST-IV types
+// read the two points of each complex index and apply the pre-twiddle, and
+// the inverse real DFT / DCT-II / DST-II read the four rows of each of the
+// thread's wavenumber pairs (k, M - k) and combine them.  Each thread reads
+// two adjacent lines with 16-byte loads.
 template <typename T, typename C, int KIND, int INV>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void r2r_regstage_kernel(R2RFastArgs<T> A) {
@@ -1178,11 +1178,46 @@ void r2r_regstage_kernel(R2RFastArgs<T> A) {
   // 32-bit lane offset (the launch checks that every offset fits), so no
   // load needs a 64-bit lane address
   const size_t pair_step = (size_t)QP * (size_t)g.sp;
+  // Inverse real DFT / DCT-II / DST-II: the wavenumber pairs (k, M - k) of
+  // a thread are k = qp + s*QP, s < M / (2 QP); their four input rows are
+  // read into registers and combined there.  The lane with k = 0 has two
+  // of its four rows unused and reads the two rows of the middle
+  // wavenumber M/2 into them.
+  static_assert(2 * QP * (EPP / 4) == M, "wavenumber pairs split evenly over the lanes");
+  auto combine_rows = [](int k, bool zero, int (&r)[4]) {
+    constexpr int H = M / 2;
+    auto row = [](int x) { return kind == K_DD ? N - 1 - x : x; };
+    const int j = M - k;
+    if constexpr (kind == K_P) {
+      r[0] = zero ? 0 : 2 * k - 1;
+      r[1] = zero ? 2 * H - 1 : 2 * k;
+      r[2] = zero ? N - 1 : 2 * j - 1;
+      r[3] = zero ? 2 * H : 2 * j;
+    } else {
+      r[0] = row(k);
+      r[1] = zero ? row(H) : row(N - k);
+      r[2] = row(j);
+      r[3] = zero ? row(N - H) : row(N - j);
+    }
+  };
   const unsigned sp32 = (unsigned)g.sp;
   auto fetch = [&](int tile, int lt, int qt, int tt) {
     const TileOrigin o = tile_origin(g, tile);
     const gptr<const T> tb = as_global(static_cast<const T*>(A.data)) + (o.x0 + (long long)o.b0 * g.sb);
-    if constexpr (plain) {
+    if constexpr (plain && inverse) {
+      const int lp = tt % NL2, qp = tt / NL2;
+      const bool ok = o.x0 + 2 * lp < g.nx;
+#pragma unroll
+      for (int s = 0; s < EPP / 4; ++s) {
+        int r[4];
+        combine_rows(qp + s * QP, s == 0 && qp == 0, r);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          buf[4 * s + a] = ok ? *reinterpret_cast<const gptr<const T2>>(
+                                    &tb[2u * (unsigned)lp + (unsigned)r[a] * sp32])
+                              : T2{(T)0, (T)0};
+      }
+    } else if constexpr (plain) {
       const int lp = tt % NL2, qp = tt / NL2;
       const unsigned lane_off = 2u * (unsigned)lp + (unsigned)qp * sp32;
       if (o.x0 + 2 * lp < g.nx) {
@@ -1231,12 +1266,68 @@ void r2r_regstage_kernel(R2RFastArgs<T> A) {
       }
       (void)l;
       (void)q;
+    } else if constexpr (inverse) {
+      constexpr int H = M / 2;
+      const int lp = tt % NL2, qp = tt / NL2;
+      const bool zero = qp == 0;
+      // x_k from the rows of wavenumber k (kinds as in combine_write)
+      auto xform = [&](int k, T a, T b) -> cplx<T> {
+        if constexpr (kind == K_P) return cplx<T>{a, -b};
+        else return cmul(cconj(ldc(tw_b, k)), cplx<T>{(T)0.5 * a, (T)-0.5 * b});
+      };
+      // outputs 2k, 2k+1 of the pair (xk, xj) and 2j, 2j+1
+      auto pair_out = [&](int k, cplx<T> xk, cplx<T> xj, T (&o)[4]) {
+        const cplx<T> sk = ldc(tw_a, k);
+        const cplx<T> s1 = cadd(xk, cconj(xj));
+        const cplx<T> d1 = cmul(csub(xk, cconj(xj)), cconj(sk));
+        const cplx<T> s2 = cadd(xj, cconj(xk));
+        const cplx<T> d2 = cmul(csub(cconj(xk), xj), sk);
+        o[0] = s1.re - d1.im;
+        o[1] = s1.im + d1.re;
+        o[2] = s2.re - d2.im;
+        o[3] = s2.im + d2.re;
+      };
+#pragma unroll
+      for (int s = 0; s < EPP / 4; ++s) {
+        const int k = qp + s * QP, j = M - k;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const T v0 = h ? buf[4 * s].y : buf[4 * s].x, v1 = h ? buf[4 * s + 1].y : buf[4 * s + 1].x;
+          const T v2 = h ? buf[4 * s + 2].y : buf[4 * s + 2].x, v3 = h ? buf[4 * s + 3].y : buf[4 * s + 3].x;
+          T o[4];
+          pair_out(k, xform(k, v0, v1), xform(j, v2, v3), o);
+          int r[4] = {2 * k, 2 * k + 1, 2 * j, 2 * j + 1};
+          if (s == 0) {
+            // k = 0 (rows 0, 1) and the middle wavenumber (rows M, M + 1)
+            cplx<T> x0, xM;
+            if constexpr (kind == K_P) {
+              x0 = {v0, (T)0};
+              xM = {v2, (T)0};
+            } else {
+              x0 = xform(0, v0, (T)0);
+              xM = xform(M, v2, v2);
+            }
+            T oz[4], om[4];
+            pair_out(0, x0, xM, oz);
+            const cplx<T> xh = xform(H, v1, v3);
+            pair_out(H, xh, xh, om);
+            o[0] = zero ? oz[0] : o[0];
+            o[1] = zero ? oz[1] : o[1];
+            o[2] = zero ? om[0] : o[2];
+            o[3] = zero ? om[1] : o[3];
+            r[2] = zero ? 2 * H : r[2];
+            r[3] = zero ? 2 * H + 1 : r[3];
+          }
+#pragma unroll
+          for (int a = 0; a < 4; ++a) S.tile[r[a] * NLP + 2 * lp + h] = o[a];
+        }
+      }
     } else {
       const int lp = tt % NL2, qp = tt / NL2;
 #pragma unroll
       for (int i = 0; i < EPP; ++i) {
         bool neg = false;
-        const int r = inverse ? qp + i * QP : load_row(kind, inverse, qp + i * QP, N, neg);
+        const int r = load_row(kind, inverse, qp + i * QP, N, neg);
         S.tile[r * NLP + 2 * lp] = neg ? -buf[i].x : buf[i].x;
         S.tile[r * NLP + 2 * lp + 1] = neg ? -buf[i].y : buf[i].y;
       }
@@ -1257,12 +1348,6 @@ void r2r_regstage_kernel(R2RFastArgs<T> A) {
     int l = tid % NL, q = tid / NL, tt = tid;
     asm volatile("" : "+v"(l), "+v"(q), "+v"(tt));
     lds_barrier();
-    if constexpr (plain && inverse) {
-      const lptr<const T> raw = S.tile;
-      combine_to_tile<T, C, true>([&](int p) -> T { return raw[p * NLP + l]; }, S.tile, tw_a, tw_b,
-                                  kind, l, q);
-      lds_barrier();
-    }
     const bool more = tile + tr.step < tr.end;
     if (more) fetch(tile + tr.step, l, q, tt);
     if constexpr (!(inverse && kind <= K_DD)) fast_passes<T, C, true, 0, true>(S.tile, tw_fft, l, q);
