@@ -25,6 +25,7 @@
 // AD_prev 24 B (read when beta_k != 0), AD 24 B (written when the next
 // substep needs it), u* 24 B.
 #pragma once
+#include <type_traits>
 #include "refine_kernels.h"
 
 namespace poisson_dev {
@@ -305,7 +306,17 @@ static_assert(RK3D_HALO <= RK3_NT && RK3_TX + RK3_TY <= RK3_NT, "fused tile shap
 // its own cells to p_out (a second buffer: the neighbouring tiles still
 // read p).  The z gradient takes Phi of the plane below from the previous
 // fetch of the same slot.
-template <bool READ_PREV, bool WRITE_AD, bool CORRECT>
+//
+// FULL (nx a multiple of RK3_TX, ny of RK3_TY, nz of RK3_KC): every cell of
+// every tile exists, so no lane skips a load or a store in the z loop, and
+// the compiler's waits for a plane's reads leave the later reads and the
+// stores in flight.  The previous AD of a plane (the own cell's, and for
+// the edge lanes the edge cell's) is read before the plane three ahead,
+// the halo reads of lanes without a halo slot read their own cell instead,
+// and the first plane and the last two are peeled off the loop (no
+// divergence yet; no plane left to read; w* only).  The other shapes keep
+// the general loop, in which these reads and stores sit behind branches.
+template <bool READ_PREV, bool WRITE_AD, bool CORRECT, bool FULL>
 __global__ __launch_bounds__(RK3_NT) void rk3_predict_div_kernel(RK3Args A, double* __restrict__ rhs,
                                                                  double inv_gdt) {
   __shared__ double ring[4][4][RK3D_PL];             // [plane slot][u, v, w, p][slot]
@@ -414,20 +425,122 @@ __global__ __launch_bounds__(RK3_NT) void rk3_predict_div_kernel(RK3Args A, doub
       prev[2] = A.ad_prev[g + 2 * N];
     }
   };
+  // FULL: the halo reads of lanes without a halo slot read their own cell
+  long long hsel_o[3] = {halo_o[0], halo_o[1], halo_o[2]};
+  if (halo_slot < 0) {
+    hsel_o[0] = own_o[0];
+    hsel_o[1] = own_o[1];
+    hsel_o[2] = own_o[2];
+  }
+  auto fetch_full = [&](int q, double (&own)[7], double (&halo)[7]) {
+    const long long base = plane * wrap(q, nz);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int o = f < 5 ? 0 : f - 4;
+      own[f] = src[f][base + own_o[o]];
+      halo[f] = src[f][base + hsel_o[o]];
+    }
+  };
   {
     double own[7], halo[7];
     for (int q = k0 - 1; q <= k0 + 1; ++q) {
-      fetch(q, own, halo);
+      if (FULL) fetch_full(q, own, halo);
+      else fetch(q, own, halo);
       put(q, own, halo);
     }
   }
   // plane reads run two planes ahead of the arithmetic: plane k + 2 is in
   // flight while plane k is computed
   double own_n[7], halo_n[7];
-  if (k0 + 2 <= kend + 1) fetch(k0 + 2, own_n, halo_n);
+  // FULL: the previous AD of plane k (the own cell's and the edge cell's),
+  // read one plane ahead
+  double prev_n[3], eprev_n[3];
+  const long long edge_o = edge_slot >= 0 ? edge_off : own_off;
+  if (FULL) {
+    load_prev(own_off + plane * wrap(k0, nz), prev_n);
+    load_prev(edge_o + plane * wrap(k0, nz), eprev_n);
+    fetch_full(k0 + 2, own_n, halo_n);
+  } else if (k0 + 2 <= kend + 1) {
+    fetch(k0 + 2, own_n, halo_n);
+  }
   __syncthreads();
 
   double star_below[3] = {0.0, 0.0, 0.0};   // this thread's u*, v*, w* of plane k - 1
+  if constexpr (FULL) {
+    // FIRST: no divergence yet; MORE: plane k + 3 is read (and the next
+    // plane has edge cells); LAST: k == kend.  The reads of a step go out
+    // in the order previous AD of plane k + 1, plane k + 3, before the
+    // step's stores: waiting for this step's previous AD then waits for
+    // nothing issued after the last step's reads.
+    auto step = [&](int k, auto first_c, auto more_c, auto last_c) {
+      constexpr bool FIRST = decltype(first_c)::value;
+      constexpr bool MORE = decltype(more_c)::value;
+      constexpr bool LAST = decltype(last_c)::value;
+      const long long base = plane * wrap(k, nz);
+      const long long g = own_off + base;
+      double prev[3], eprev[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        prev[c] = prev_n[c];
+        eprev[c] = eprev_n[c];
+      }
+      if constexpr (!LAST) load_prev(own_off + plane * wrap(k + 1, nz), prev_n);
+      if constexpr (MORE) load_prev(edge_o + plane * wrap(k + 1, nz), eprev_n);
+      double own_f[7], halo_f[7];
+      if constexpr (MORE) fetch_full(k + 3, own_f, halo_f);
+      const double(*Rm)[RK3D_PL] = ring[(k - k0) & 3];
+      const double(*R0)[RK3D_PL] = ring[(k - k0 + 1) & 3];
+      const double(*Rp)[RK3D_PL] = ring[(k - k0 + 2) & 3];
+      const RK3Cell r = rk3_cell<RK3D_PL, RK3D_HX>(Rm, R0, Rp, own_slot, A, prev);
+      if constexpr (!LAST) {
+        if (WRITE_AD) {
+          A.ad[g] = r.ad[0];
+          A.ad[g + N] = r.ad[1];
+          A.ad[g + 2 * N] = r.ad[2];
+        }
+        A.star[g] = r.star[0];
+        A.star[g + N] = r.star[1];
+        A.star[g + 2 * N] = r.star[2];
+        if (CORRECT) A.p_out[g] = R0[3][own_slot];
+      }
+      if constexpr (!FIRST) {                 // divergence of plane k - 1
+        const int b = (k - 1 - k0) & 1;
+        const double du = xu[b][ty][tx + 1] - xu[b][ty][tx];
+        const double dv = xv[b][ty + 1][tx] - xv[b][ty][tx];
+        const double dw = r.star[2] - star_below[2];
+        rhs[g - base + plane * (k - 1)] = (du * A.idx + dv * A.idy + dw * A.idz) * inv_gdt;
+      }
+      if constexpr (!LAST) {
+        const int b = (k - k0) & 1;
+        xu[b][ty][tx] = r.star[0];
+        xv[b][ty][tx] = r.star[1];
+        if (edge_slot >= 0) {
+          const RK3Cell e = rk3_cell<RK3D_PL, RK3D_HX>(Rm, R0, Rp, edge_slot, A, eprev);
+          if (t < RK3_TX) xv[b][RK3_TY][t] = e.star[1];
+          else xu[b][t - RK3_TX][RK3_TX] = e.star[0];
+        }
+      }
+      star_below[0] = r.star[0];
+      star_below[1] = r.star[1];
+      star_below[2] = r.star[2];
+      if constexpr (!LAST) put(k + 2, own_n, halo_n);
+      if constexpr (MORE) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          own_n[f] = own_f[f];
+          halo_n[f] = halo_f[f];
+        }
+      }
+      __syncthreads();
+    };
+    using yes = std::true_type;
+    using no = std::false_type;
+    step(k0, yes{}, yes{}, no{});
+    for (int k = k0 + 1; k < kend - 1; ++k) step(k, no{}, yes{}, no{});
+    step(kend - 1, no{}, no{}, no{});
+    step(kend, no{}, no{}, yes{});
+    return;
+  }
   for (int k = k0; k <= kend; ++k) {        // k == kend: w* above the range only
     double own_f[7], halo_f[7];
     const bool more = k + 3 <= kend + 1;

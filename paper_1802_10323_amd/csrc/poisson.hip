@@ -148,6 +148,7 @@ struct poisson_plan {
   bool generic_tri = false;    // POISSON_GENERIC_TRI=1: size-generic elimination kernel only
   int grid_cap = 0;            // POISSON_GRID_CAP=B: at most B blocks per stage launch (0: none)
   int rk3_kernel = 0;          // POISSON_RK3_KERNEL: 0 fused (default), 1 "tiled", 2 "simple"
+  bool rk3_general = false;    // POISSON_RK3_GENERAL=1: the fused kernel's general z loop on whole tiles too
   bool plane_off = false;      // POISSON_PLANE=0: no small-plane transforms
   char* plane_mats = nullptr;  // small grids: dense transform matrices (FP64, then FP32)
   size_t plane_off_f = 0;      // byte offset of the FP32 copy in plane_mats
@@ -948,6 +949,8 @@ extern "C" poisson_plan* plan_create_helmholtz(int nx, int ny, int nz, double dx
     p->plane_off = env && env[0] == '0';
     env = std::getenv("POISSON_RK3_KERNEL");
     p->rk3_kernel = !env ? 0 : std::strcmp(env, "tiled") == 0 ? 1 : std::strcmp(env, "simple") == 0 ? 2 : 0;
+    env = std::getenv("POISSON_RK3_GENERAL");
+    p->rk3_general = env && std::strcmp(env, "1") == 0;
   }
   for (int k = 1; k < nz; ++k) if (dz[k] != dz[0]) p->z_uniform = false;
   p->shift = shift;
@@ -1554,19 +1557,27 @@ static dim3 rk3_tiles(const RK3Args& A) {
 
 // The fused prediction of substep k (with the previous substep's
 // correction when `correct`); rhs = div(u*) / (gamma_k dt).
-static int launch_predict_div(const RK3Args& A, int k, bool correct, double* rhs, hipStream_t st) {
+static int launch_predict_div(const RK3Args& A, int k, bool correct, double* rhs, hipStream_t st,
+                              bool general) {
   const dim3 tiles = rk3_tiles(A);
   const double inv_gdt = 1.0 / A.g_dt;
-  if (k == 1)
-    hipLaunchKernelGGL((rk3_predict_div_kernel<false, true, false>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
-  else if (k == 2 && !correct)
-    hipLaunchKernelGGL((rk3_predict_div_kernel<true, true, false>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
-  else if (k == 2)
-    hipLaunchKernelGGL((rk3_predict_div_kernel<true, true, true>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
-  else if (!correct)
-    hipLaunchKernelGGL((rk3_predict_div_kernel<true, false, false>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
-  else
-    hipLaunchKernelGGL((rk3_predict_div_kernel<true, false, true>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
+  // whole tiles and z ranges: the branch-free form of the z loop
+  const bool full = A.nx % RK3_TX == 0 && A.ny % RK3_TY == 0 && A.nz % RK3_KC == 0 && !general;
+  auto go = [&](auto full_c) {
+    constexpr bool F = decltype(full_c)::value;
+    if (k == 1)
+      hipLaunchKernelGGL((rk3_predict_div_kernel<false, true, false, F>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
+    else if (k == 2 && !correct)
+      hipLaunchKernelGGL((rk3_predict_div_kernel<true, true, false, F>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
+    else if (k == 2)
+      hipLaunchKernelGGL((rk3_predict_div_kernel<true, true, true, F>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
+    else if (!correct)
+      hipLaunchKernelGGL((rk3_predict_div_kernel<true, false, false, F>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
+    else
+      hipLaunchKernelGGL((rk3_predict_div_kernel<true, false, true, F>), tiles, dim3(RK3_NT), 0, st, A, rhs, inv_gdt);
+  };
+  if (full) go(std::true_type{});
+  else go(std::false_type{});
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
 }
@@ -1589,7 +1600,7 @@ extern "C" int rk3_predict(poisson_plan* p, int k, double dt, double nu, const d
   const double gdt = A.g_dt;
   const dim3 tiles = rk3_tiles(A);
   if (p->rk3_kernel == 0) {        // prediction and right-hand side in one sweep
-    if (int rc = launch_predict_div(A, k, false, rhs, st)) return rc;
+    if (int rc = launch_predict_div(A, k, false, rhs, st, p->rk3_general)) return rc;
   } else {
     if (p->rk3_kernel == 2) {
       const int blocks = (int)std::max<long long>(1, std::min<long long>(RK3_BLOCKS, (N + RK3_NT - 1) / RK3_NT));
@@ -1643,19 +1654,19 @@ extern "C" int rk3_step(poisson_plan* p, double dt, double nu, double* vel, doub
   double* phi2 = scratch + N;
   auto gdt = [&](int k) { return (kRK3Alpha[k - 1] + kRK3Beta[k - 1]) * dt; };
   RK3Args A = rk3_args(p, 1, dt, nu, vel, work, ad, pres);          // vel -> work (u*1)
-  if (int rc = launch_predict_div(A, 1, false, phi, st)) return rc;
+  if (int rc = launch_predict_div(A, 1, false, phi, st, p->rk3_general)) return rc;
   if (int rc = solve(p, phi, st)) return rc;                        // Phi1
   A = rk3_args(p, 2, dt, nu, work, vel, ad, pres);                  // u*1, Phi1, p -> vel (u*2), p2
   A.phi_prev = phi;
   A.p_out = p2;
   A.c_gdt = gdt(1);
-  if (int rc = launch_predict_div(A, 2, true, phi2, st)) return rc;
+  if (int rc = launch_predict_div(A, 2, true, phi2, st, p->rk3_general)) return rc;
   if (int rc = solve(p, phi2, st)) return rc;                       // Phi2
   A = rk3_args(p, 3, dt, nu, vel, work, ad, p2);                    // u*2, Phi2, p2 -> work (u*3), pres
   A.phi_prev = phi2;
   A.p_out = pres;
   A.c_gdt = gdt(2);
-  if (int rc = launch_predict_div(A, 3, true, phi, st)) return rc;
+  if (int rc = launch_predict_div(A, 3, true, phi, st, p->rk3_general)) return rc;
   if (int rc = solve(p, phi, st)) return rc;                        // Phi3
   return launch_proj_update(p, phi, gdt(3), work, work + N, work + 2 * N, vel, vel + N, vel + 2 * N,
                             pres, st);

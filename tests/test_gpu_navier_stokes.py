@@ -89,6 +89,7 @@ SUBSTEP_CASES = [
     (200, 12, 150, (1.0, 0.3, 0.9), 0.001, 0.005),    # ragged x tiles, several z ranges
     (90, 30, 9, (2.0, 1.0, 0.5), 0.001, 0.002),      # ragged rows, odd short z
     (160, 128, 130, (1.0, 1.0, 1.0), 0.0005, 0.001),  # more cells than one grid-stride pass
+    (128, 16, 192, (1.0, 0.6, 1.4), 0.001, 0.004),    # whole tiles, three z ranges: the branch-free loop
 ]
 
 
@@ -127,6 +128,32 @@ def test_substep_vs_oracle(case, k, kernel, monkeypatch):
     say("  rel-L2", {a: f"{b:.2e}" for a, b in errs.items()})
     assert max(errs.values()) <= TOL, errs
     plan.close()
+
+
+@pytest.mark.parametrize("shape", [(128, 16, 192), (64, 8, 128)], ids=lambda s: "x".join(map(str, s)))
+def test_whole_tile_loop_equals_general_loop(shape, monkeypatch):
+    """On whole tiles (nx, ny, nz multiples of 64, 4, 64) the fused
+    prediction runs its branch-free z loop; POISSON_RK3_GENERAL=1 forces
+    the general loop.  Both run the same cell arithmetic in the same order:
+    a whole step (three predictions, the correcting ones included) is
+    equal bit for bit."""
+    import torch
+    nx, ny, nz = shape
+    vel, _, p = random_state(11 + nx, (nz, ny, nx))
+    out = {}
+    for general in (False, True):
+        if general:
+            monkeypatch.setenv("POISSON_RK3_GENERAL", "1")
+        else:
+            monkeypatch.delenv("POISSON_RK3_GENERAL", raising=False)
+        plan, _ = periodic_plan(nx, ny, nz, (1.0, 0.7, 1.2))
+        dvel, work, dad, dp, phi = device_state(vel, np.zeros_like(vel), p)
+        plan.rk3_step(0.001, 0.003, dvel, work, dad, dp, phi, scratch_for((nz, ny, nx)))
+        torch.cuda.synchronize()
+        out[general] = (dvel.clone(), dp.clone())
+        plan.close()
+    say("whole-tile loop", shape)
+    assert torch.equal(out[False][0], out[True][0]) and torch.equal(out[False][1], out[True][1])
 
 
 @pytest.mark.parametrize("case", SUBSTEP_CASES, ids=lambda c: "x".join(map(str, c[:3])))
