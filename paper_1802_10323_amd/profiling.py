@@ -144,10 +144,29 @@ def cmd_counters(a):
             names.add(r["Counter_Name"])
     names = sorted(names)
     per = {c: stage_values(read_counters(a.csv, c)) for c in names}
-    lines = [f"# hardware counters per launch of each solver stage, workload {a.workload}",
+    what = "kernel (medians over its launches)" if a.kernels else "solver stage"
+    lines = [f"# hardware counters per launch of each {what}, workload {a.workload}",
              "# command:"]
     lines += [f"#   {c}" for c in a.command]
     lines.append(f"kernel_source_hash {kernel_source_hash()}")
+    if a.kernels:
+        # per kernel instead of per solver stage: medians over its launches
+        # of the launches that did work (more than one wave)
+        per_k = {}
+        with open(a.csv) as fh:
+            for r in csv.DictReader(fh):
+                k = short_name(r["Kernel_Name"]).replace(" ", "")
+                per_k.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        for k, cs in sorted(per_k.items()):
+            if not any(x in k for x in a.kernels.split(",")):
+                continue
+            vals = " ".join(f"{c} {statistics.median(v):.0f}" for c, v in sorted(cs.items()))
+            lines.append(f"kernel {k} {vals}")
+        text = "\n".join(lines) + "\n"
+        with open(a.out, "w") as fh:
+            fh.write(text)
+        print(text, end="")
+        return
     for s in STAGES:
         kname = next((per[c][s][0] for c in names if per[c][s][0]), None)
         if kname is None:
@@ -194,6 +213,8 @@ def main():
     c.add_argument("--workload", required=True)
     c.add_argument("--out", required=True)
     c.add_argument("--command", action="append", default=[])
+    c.add_argument("--kernels", default="",
+                   help="comma list of name fragments: summarise these kernels, not the solver stages")
     a = ap.parse_args()
     {"traffic": cmd_traffic, "stats": cmd_stats, "counters": cmd_counters}[a.what](a)
 
