@@ -148,6 +148,52 @@ struct SmallDFT<5, T, FWD> {
   }
 };
 
+// Length 16 as 4 x 4: inputs n = 4 n1 + n2, outputs k = k1 + 4 k2; length-4
+// DFTs over n1, the twiddles W16^(n2 k1), length-4 DFTs over n2.
+template <typename T, bool FWD>
+struct SmallDFT<16, T, FWD> {
+  // v * W16^m (W16 = exp(-+ 2 pi i / 16)) for the products m = n2 k1 that occur
+  template <int M_>
+  static __device__ __forceinline__ cplx<T> tw16(cplx<T> v) {
+    const T c1 = (T)0.92387953251128675613;   // cos(pi/8)
+    const T s1 = (T)0.38268343236508977173;   // sin(pi/8)
+    const T h = (T)0.70710678118654752440;    // cos(pi/4)
+    T wr = 1, wi = 0;                         // cos, sin of 2 pi m / 16
+    if constexpr (M_ == 0) return v;
+    if constexpr (M_ == 4) return mul_mi<T, FWD>(v);
+    if constexpr (M_ == 1) { wr = c1; wi = s1; }
+    if constexpr (M_ == 2) { wr = h; wi = h; }
+    if constexpr (M_ == 3) { wr = s1; wi = c1; }
+    if constexpr (M_ == 6) { wr = -h; wi = h; }
+    if constexpr (M_ == 9) { wr = -c1; wi = -s1; }
+    if (FWD) wi = -wi;
+    return cplx<T>{v.re * wr - v.im * wi, v.re * wi + v.im * wr};
+  }
+  template <int N2>
+  static __device__ __forceinline__ void column(cplx<T>* v, cplx<T> (&y)[4][4]) {
+    cplx<T> c[4] = {v[N2], v[4 + N2], v[8 + N2], v[12 + N2]};
+    SmallDFT<4, T, FWD>::run(c);
+    y[N2][0] = c[0];
+    y[N2][1] = tw16<N2 * 1>(c[1]);
+    y[N2][2] = tw16<N2 * 2>(c[2]);
+    y[N2][3] = tw16<N2 * 3>(c[3]);
+  }
+  static __device__ __forceinline__ void run(cplx<T>* v) {
+    cplx<T> y[4][4];
+    column<0>(v, y);
+    column<1>(v, y);
+    column<2>(v, y);
+    column<3>(v, y);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cplx<T> c[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+      SmallDFT<4, T, FWD>::run(c);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = c[k2];
+    }
+  }
+};
+
 // ---------------------------------------------------------------- LDS access
 
 template <typename T>
