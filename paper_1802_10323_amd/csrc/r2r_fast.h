@@ -118,7 +118,7 @@ using FastVar = FastCfg<M, FastShapes<M>::QT[V & 1], FastShapes<M>::NL[V & 1], (
 // shape 2: FP32 length 512 with 32 lines per tile, so that the rows of a
 // strided tile are 128 bytes long, as in FP64 with 16 lines).
 template <int M, int SHAPE>
-using AsyncVar = std::conditional_t<SHAPE == 2, FastCfg<M, 16, 32, 0>, FastVar<M, SHAPE>>;
+using AsyncVar = std::conditional_t<SHAPE == 2, FastCfg<M, 16, 32, 2>, FastVar<M, SHAPE>>;
 
 template <typename T>
 struct R2RFastArgs {
