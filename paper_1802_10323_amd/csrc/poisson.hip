@@ -1176,34 +1176,6 @@ extern "C" int plan_set_precision(poisson_plan* p, int mode, double tol, int max
   return POISSON_OK;
 }
 
-
-// FP32 + refinement on workspace lent by the caller (f64: N doubles, e32: N
-// floats, valid while the plan's solves run); only the small reduction
-// slots are the plan's own.
-static int plan_refine_on(poisson_plan* p, double tol, int max_iters, double* f64, float* e32) {
-  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(POISSON_EINVAL, "tol must be finite and > 0");
-  if (max_iters < 1 || max_iters > 64) return fail(POISSON_EINVAL, "max_iters must be in [1, 64]");
-  if (p->f64 && !p->ws_external) {
-    (void)hipFree(p->f64);
-    (void)hipFree(p->e32);
-  }
-  if (!p->stats) {
-    if (hipMalloc(&p->stats, REFINE_STAT_SLOTS * sizeof(double)) != hipSuccess ||
-        hipHostMalloc(&p->stats_host, REFINE_STAT_SLOTS * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-      free_workspace(p);
-      return fail(POISSON_ENOMEM, "refinement status allocation failed");
-    }
-  }
-  p->f64 = f64;
-  p->e32 = e32;
-  p->ws_external = true;
-  p->ws_bytes = REFINE_STAT_SLOTS * sizeof(double);
-  p->tol = tol;
-  p->max_iters = max_iters;
-  p->mode = POISSON_FP32_REFINED;
-  return POISSON_OK;
-}
-
 static int solve_refined(poisson_plan* p, double* rhs, hipStream_t st);
 
 extern "C" int solve(poisson_plan* p, double* rhs, hipStream_t st) {

@@ -434,7 +434,6 @@ __device__ __forceinline__ void tri_fast_tile(lptr<T> lds, lptr<const double> co
 template <typename T, int RPC, int P, int LAYOUT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 void tri_fast_kernel(TriFastArgs<T> A) {
-  using L = TriFastLayout<T, RPC, P>;
   if (A.skip && A.skip[0] != 0.0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const lptr<T> lds = as_lds(reinterpret_cast<T*>(smem_raw));
