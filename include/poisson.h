@@ -27,6 +27,15 @@
  * All field pointers are DEVICE pointers; all other pointers are HOST pointers.
  * Streams are hipStream_t values (NULL = the legacy default stream).
  *
+ * Alignment: a field the solve kernels work on must be 16-byte aligned (they
+ * move neighbouring points with 16-byte accesses).  hipMalloc and torch
+ * allocations are; a view at an odd element offset is not.  This covers
+ * the field of solve, solve_refined_noalloc, transform_stage, tridiag_stage,
+ * batch_solve, batch_bind and server_submit, phi of pressure_correction and
+ * rk3_substep, phi and scratch of rk3_step, and the scratch of
+ * plan_autotune.  A misaligned one is refused with POISSON_EINVAL before any
+ * work is enqueued.
+ *
  * Error handling: functions return POISSON_OK (0) or a negative code;
  * plan_create returns NULL on error.  The code and a message of the last
  * failing call on the calling thread are available from last_error() and

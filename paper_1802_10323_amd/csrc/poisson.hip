@@ -53,6 +53,15 @@ static int fail(int code, const char* fmt, ...) {
       return fail(POISSON_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
   } while (0)
 
+// The solve kernels move two neighbouring points of a line with one 16-byte
+// access, so a field they work on must be 16-byte aligned (hipMalloc and
+// torch allocations are; a view at an odd element offset is not).  Returns
+// POISSON_EINVAL, naming the argument, when it is not.
+static int misaligned(const void* ptr, const char* what) {
+  if ((reinterpret_cast<uintptr_t>(ptr) & 15) == 0) return POISSON_OK;
+  return fail(POISSON_EINVAL, "%s must be 16-byte aligned", what);
+}
+
 extern "C" int last_error(void) { return g_err; }
 extern "C" const char* last_error_message(void) { return g_msg; }
 
@@ -1141,12 +1150,14 @@ extern "C" int plan_roles(const poisson_plan* p, int roles[3]) {
 
 extern "C" int transform_stage(poisson_plan* p, int role, int inverse, double* field, hipStream_t st) {
   if (!p || !field) return fail(POISSON_EINVAL, "null argument");
+  if (int rc = misaligned(field, "field")) return rc;
   if (role < 0 || role > 1) return fail(POISSON_EINVAL, "role must be 0 or 1");
   return launch_r2r<double>(p, role, inverse ? 1 : 0, field, st);
 }
 
 extern "C" int tridiag_stage(poisson_plan* p, double* field, hipStream_t st) {
   if (!p || !field) return fail(POISSON_EINVAL, "null argument");
+  if (int rc = misaligned(field, "field")) return rc;
   return launch_tridiag<double>(p, field, st);
 }
 
@@ -1180,6 +1191,7 @@ static int solve_refined(poisson_plan* p, double* rhs, hipStream_t st);
 
 extern "C" int solve(poisson_plan* p, double* rhs, hipStream_t st) {
   if (!p || !rhs) return fail(POISSON_EINVAL, "null argument");
+  if (int rc = misaligned(rhs, "rhs")) return rc;
   if (p->mode == POISSON_FP32_REFINED) return solve_refined(p, rhs, st);
   p->last_iters = 1;
   p->last_rel = 0.0;
@@ -1384,6 +1396,7 @@ __global__ void refine_report_kernel(const double* __restrict__ stats, int max_i
 extern "C" int solve_refined_noalloc(poisson_plan* p, double* rhs, double tol, int max_iters,
                                      double* status_out, hipStream_t st) {
   if (!p || !rhs) return fail(POISSON_EINVAL, "null argument");
+  if (int rc = misaligned(rhs, "rhs")) return rc;
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(POISSON_EINVAL, "tol must be finite and > 0");
   if (max_iters < 1 || max_iters > REFINE_MAX_SWEEPS)
     return fail(POISSON_EINVAL, "max_iters must be in [1, %d]", REFINE_MAX_SWEEPS);
@@ -1469,6 +1482,7 @@ extern "C" int projection_update(poisson_plan* p, const double* phi, double gamm
 extern "C" int pressure_correction(poisson_plan* p, double* u, double* v, double* w, double* pres,
                                    double gamma_dt, double* phi, hipStream_t st) {
   int rc;
+  if (phi && (rc = misaligned(phi, "phi"))) return rc;
   if ((rc = projection_rhs(p, u, v, w, gamma_dt, phi, st))) return rc;
   if ((rc = solve(p, phi, st))) return rc;
   return projection_update(p, phi, gamma_dt, u, v, w, pres, st);
@@ -1601,6 +1615,8 @@ extern "C" int rk3_predict(poisson_plan* p, int k, double dt, double nu, const d
 
 extern "C" int rk3_substep(poisson_plan* p, int k, double dt, double nu, double* vel, double* work,
                            double* ad, double* pres, double* phi, hipStream_t st) {
+  if (phi)
+    if (int rc = misaligned(phi, "phi")) return rc;
   if (int rc = rk3_predict(p, k, dt, nu, vel, work, ad, pres, phi, st)) return rc;
   const long long N = (long long)field_points(p);
   const double gdt = (kRK3Alpha[k - 1] + kRK3Beta[k - 1]) * dt;
@@ -1611,6 +1627,8 @@ extern "C" int rk3_substep(poisson_plan* p, int k, double dt, double nu, double*
 extern "C" int rk3_step(poisson_plan* p, double dt, double nu, double* vel, double* work, double* ad,
                         double* pres, double* phi, double* scratch, hipStream_t st) {
   if (!p || !vel || !work || !ad || !pres || !phi || !scratch) return fail(POISSON_EINVAL, "null argument");
+  if (int rc = misaligned(phi, "phi")) return rc;
+  if (int rc = misaligned(scratch, "scratch")) return rc;
   if (int rc = rk3_check(p, 1, dt, nu)) return rc;
   if (p->rk3_kernel != 0) {        // the other prediction kernels: substep by substep
     for (int k = 1; k <= 3; ++k)
@@ -1650,6 +1668,7 @@ extern "C" int batch_solve(poisson_plan* const* plans, double* const* rhs, int c
   if (count < 0 || (count > 0 && (!plans || !rhs))) return fail(POISSON_EINVAL, "bad batch arguments");
   for (int i = 0; i < count; ++i) {
     if (!plans[i] || !rhs[i]) return fail(POISSON_EINVAL, "null plan or field at batch index %d", i);
+    if (int rc = misaligned(rhs[i], "every batch field")) return rc;
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i] && plans[i]->mode == POISSON_FP32_REFINED)
         return fail(POISSON_EINVAL, "refined plan at batch index %d appears twice", i);
@@ -1903,6 +1922,7 @@ extern "C" int batch_bind(poisson_batch* b, double* const* rhs) {
   if (!b || !rhs) return fail(POISSON_EINVAL, "null argument");
   for (size_t i = 0; i < b->plans.size(); ++i)
     if (!rhs[i]) return fail(POISSON_EINVAL, "null field at batch index %zu", i);
+    else if (int rc = misaligned(rhs[i], "every batch field")) return rc;
   b->rhs.assign(rhs, rhs + b->plans.size());
   if (b->exec) {
     // the refinement kernels around the batched steps take the fields as
@@ -2113,6 +2133,7 @@ static int autotune_typed(poisson_plan* p, double* scratch, int reps, hipStream_
 extern "C" int plan_autotune(poisson_plan* p, double* scratch, int reps, hipStream_t st,
                              double* report) {
   if (!p || !scratch) return fail(POISSON_EINVAL, "null argument");
+  if (int rc = misaligned(scratch, "scratch")) return rc;
   if (reps < 1 || reps > 1000) return fail(POISSON_EINVAL, "reps must be in [1, 1000]");
   if (lds_setup_once()) return g_err;
   if (report)

@@ -403,6 +403,7 @@ extern "C" long long server_submit(poisson_server* S, int nx, int ny, int nz, do
                                    const double* dz, int bc_x, int bc_y, int bc_z, int precision,
                                    double tol, int max_iters, double* field, hipStream_t producer) {
   if (!S || !dz || !field) return fail(POISSON_EINVAL, "null argument");
+  if (int rc = misaligned(field, "field")) return rc;
   if (nx < 1 || ny < 1 || nz < 1) return fail(POISSON_EINVAL, "sizes must be >= 1");
   if (precision != POISSON_FP64 && precision != POISSON_FP32_REFINED)
     return fail(POISSON_EINVAL, "unknown precision mode %d", precision);
