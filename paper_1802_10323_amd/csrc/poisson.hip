@@ -167,6 +167,11 @@ struct poisson_plan {
   AxisTables ax[2];
   // elimination axis tables
   size_t off_tri_d = 0, off_tri_f = 0;     // a, b, c, w   (4 n_s)
+  // Strided lines whose length has no size-specialised kernel are run in the
+  // kernel of the next specialised length pad_n (0: not padded), with the
+  // tables extended by decoupled rows (see plan_create).
+  int pad_n = 0;
+  size_t off_tri_pad = 0;                  // a, b, c, w   (4 pad_n), FP64
   size_t off_lam_d = 0, off_lam_f = 0;     // lamu, lamv
   size_t off_ops[3] = {0, 0, 0};           // per axis: a, b, c, h (FP64, residual)
   size_t off_proj[3] = {0, 0, 0};          // per axis: 1/h (n), 1/centre distance (n + 1)
@@ -594,8 +599,11 @@ static TriFastArgs<T> tri_fast_args(const poisson_plan* p, T* data, const double
   a.singular = p->singular;
   a.nu = p->nu;
   a.nv = p->nv;
-  // FP64 tables for both field precisions (the recurrences run in FP64)
-  const double* tri = reinterpret_cast<const double*>(p->dtab + p->off_tri_d);
+  // FP64 tables for both field precisions (the recurrences run in FP64);
+  // a padded plan's tables have L::N = pad_n rows
+  const double* tri = reinterpret_cast<const double*>(
+      p->dtab + (p->pad_n && p->pad_n == L::N ? p->off_tri_pad : p->off_tri_d));
+  a.nreal = p->dims[p->s];
   a.a = tri;
   a.b = tri + L::N;
   a.c = tri + 2 * L::N;
@@ -704,6 +712,12 @@ template <typename T>
 static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
                           const double* skip = nullptr) {
   t_grid_cap = p->grid_cap;
+  if (p->pad_n) {   // padded strided lines: the plain chunked kernel of length pad_n
+    return (int)with_tri_cfg(p->pad_n, 0, [&](auto cfg) {
+      using C = decltype(cfg);
+      return (long long)launch_tri_fast<T, C::RPC, C::P>(p, data, st, skip);
+    });
+  }
   if (!p->generic_tri) {
     const int n = p->dims[p->s];
     // small grids (transforms as dense matrices): lines of 32 or 48 points in
@@ -1053,6 +1067,34 @@ extern "C" poisson_plan* plan_create_helmholtz(int nx, int ny, int nz, double dx
     std::vector<float> trif(tri.begin(), tri.end());
     p->off_tri_d = push(tri.data(), tri.size() * sizeof(double));
     p->off_tri_f = push(trif.data(), trif.size() * sizeof(float));
+    // Padding: a line of ns < N points, N the next specialised length (at most
+    // 3/2 ns), solved as a line of N whose last N - ns rows are decoupled
+    // (a = c = 0, diagonal -1: with the shifts mu <= 0 of the transformed
+    // axes no pivot of theirs comes near 0) and whose right-hand side there
+    // is 0, so they come out 0 and leave the first ns unknowns those of the
+    // real line.  Only for strided, non-periodic lines (the real last row
+    // then has no coupling past it) of non-singular plans (the gauge pins
+    // the line's last row).
+    if (p->s != 0 && !p->s_periodic && !p->singular && !p->generic_tri && !tri_fast_length(ns_)) {
+      for (const int cand : {64, 96, 128, 192, 256, 384, 512}) {
+        if (cand >= ns_ && 2 * cand <= 3 * ns_) {
+          p->pad_n = cand;
+          break;
+        }
+      }
+    }
+    if (p->pad_n) {
+      const int N = p->pad_n;
+      std::vector<double> pad(4 * (size_t)N, 0.0);
+      for (int k = 0; k < N; ++k) {
+        const bool real = k < ns_;
+        pad[k] = real ? tri[k] : 0.0;                          // a
+        pad[N + k] = real ? tri[ns_ + k] : -1.0;               // b (shift included)
+        pad[2 * N + k] = real ? tri[2 * ns_ + k] : 0.0;        // c
+        pad[3 * N + k] = real ? tri[3 * ns_ + k] : 0.0;        // w
+      }
+      p->off_tri_pad = push(pad.data(), pad.size() * sizeof(double));
+    }
     for (int q = 0; q < 3; ++q) {
       std::vector<double> ops(4 * (size_t)p->dims[q]);
       axis_rows(axis_widths(p, q), bcs[q], ops.data());

@@ -42,6 +42,7 @@ struct TriFastArgs {
   const double* lamu;
   const double* lamv;
   const double* skip;
+  int nreal;          // rows of a line that exist (< N for a padded strided line)
 };
 
 template <typename T, int RPC, int P>
@@ -95,13 +96,15 @@ __device__ __forceinline__ int tri_fast_slot(int p, int ll) {
 // LAY >= 0: the layout as a constant (0 strided, 1 contiguous); -1: `layout`.
 template <typename T, int RPC, int P, int LAY = -1>
 __device__ __noinline__ void tri_fast_load(lptr<T> lds, gptr<const T> data, long long base,
-                                           long long sp, int layout, int lines, int tid) {
+                                           long long sp, int layout, int lines, int tid,
+                                           int nreal) {
   using L = TriFastLayout<T, RPC, P>;
   T buf[RPC];
   if ((LAY >= 0 ? LAY : layout) == 0) {
     const int l = tid % L::NL, q = tid / L::NL;
 #pragma unroll
-    for (int i = 0; i < RPC; ++i) buf[i] = base >= 0 ? data[base + (q + i * P) * sp] : (T)0;
+    for (int i = 0; i < RPC; ++i)
+      buf[i] = base >= 0 && q + i * P < nreal ? data[base + (q + i * P) * sp] : (T)0;
 #pragma unroll
     for (int i = 0; i < RPC; ++i) lds[tri_fast_slot<T, RPC, P>(q + i * P, l)] = buf[i];
   } else {
@@ -121,7 +124,8 @@ __device__ __noinline__ void tri_fast_load(lptr<T> lds, gptr<const T> data, long
 
 template <typename T, int RPC, int P>
 __device__ __forceinline__ void tri_fast_store_body(lptr<const T> lds, gptr<T> data, long long base,
-                                                    long long sp, int layout, int lines, int tid) {
+                                                    long long sp, int layout, int lines, int tid,
+                                                    int nreal) {
   using L = TriFastLayout<T, RPC, P>;
   T buf[RPC];
   if (layout == 0) {
@@ -130,7 +134,8 @@ __device__ __forceinline__ void tri_fast_store_body(lptr<const T> lds, gptr<T> d
     for (int i = 0; i < RPC; ++i) buf[i] = lds[tri_fast_slot<T, RPC, P>(q + i * P, l)];
     if (base >= 0) {
 #pragma unroll
-      for (int i = 0; i < RPC; ++i) data[base + (q + i * P) * sp] = buf[i];
+      for (int i = 0; i < RPC; ++i)
+        if (q + i * P < nreal) data[base + (q + i * P) * sp] = buf[i];
     }
   } else {
 #pragma unroll
@@ -149,8 +154,9 @@ __device__ __forceinline__ void tri_fast_store_body(lptr<const T> lds, gptr<T> d
 
 template <typename T, int RPC, int P, int LAY = -1>
 __device__ __noinline__ void tri_fast_store(lptr<const T> lds, gptr<T> data, long long base,
-                                            long long sp, int layout, int lines, int tid) {
-  tri_fast_store_body<T, RPC, P>(lds, data, base, sp, LAY >= 0 ? LAY : layout, lines, tid);
+                                            long long sp, int layout, int lines, int tid,
+                                            int nreal) {
+  tri_fast_store_body<T, RPC, P>(lds, data, base, sp, LAY >= 0 ? LAY : layout, lines, tid, nreal);
 }
 
 // Sum over the P lanes of a line.
@@ -415,7 +421,8 @@ __device__ __forceinline__ void tri_fast_tile(lptr<T> lds, lptr<const double> co
     base = (long long)o.L0 * N;
     lines = min(g.nlines - o.L0, nlt);
   }
-  tri_fast_load<T, RPC, P, LAY>(lds, as_global((const T*)A.data), base, g.sp, g.layout, lines, tid);
+  tri_fast_load<T, RPC, P, LAY>(lds, as_global((const T*)A.data), base, g.sp, g.layout, lines, tid,
+                                A.nreal);
   __syncthreads();
 
   const bool valid = l < nlt && line_base(g, o, l) >= 0;
@@ -427,7 +434,7 @@ __device__ __forceinline__ void tri_fast_tile(lptr<T> lds, lptr<const double> co
   tri_fast_line<T, RPC, P>(col, coef, c, mu, sing ? 1 : 0, wave_sing, A.periodic);
   __syncthreads();
 
-  tri_fast_store<T, RPC, P, LAY>(lds, as_global(A.data), base, g.sp, g.layout, lines, tid);
+  tri_fast_store<T, RPC, P, LAY>(lds, as_global(A.data), base, g.sp, g.layout, lines, tid, A.nreal);
   __syncthreads();
 }
 
@@ -674,7 +681,8 @@ void tri_async_kernel(TriFastArgs<T> A) {
       base = (long long)o.L0 * N;
       lines = min(g.nlines - o.L0, nlt);
     }
-    tri_fast_store_body<T, RPC, P>(lds, as_global(A.data), base, g.sp, g.layout, lines, tid);
+    tri_fast_store_body<T, RPC, P>(lds, as_global(A.data), base, g.sp, g.layout, lines, tid,
+                                   A.nreal);
     // strided tiles: every wave holds line 0, which always exists, so it
     // issues all RPC stores; contiguous tiles only when no line is missing
     stores_pending = g.layout == 0 || lines >= NL;

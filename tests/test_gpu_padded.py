@@ -1,0 +1,93 @@
+"""Strided elimination lines whose length has no size-specialised kernel
+are solved in the kernel of the next specialised length (at most 3/2 of
+theirs), with the extra rows decoupled (a = c = 0, diagonal -1, right-hand
+side 0).  Against the oracle (<= 1e-12; FP32 + refinement <= 1e-10) and
+against the size-generic kernel (POISSON_GENERIC_TRI=1) on the same plan,
+for both strided axes, stretched z, node pairs with a Helmholtz shift, and
+with every launch capped at 16 blocks so that blocks loop over tiles.
+Periodic and singular lines keep the generic kernel."""
+import pytest
+
+from gpu_util import oracle_solve, rel_l2, to_dev, to_host
+from paper_1802_10323_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_10323_amd import lib
+    lib()
+
+
+def _solve(prob, monkeypatch, generic=False, mixed=False, cap=None):
+    from paper_1802_10323_amd import FP32_REFINED, Plan
+    if generic:
+        monkeypatch.setenv("POISSON_GENERIC_TRI", "1")
+    else:
+        monkeypatch.delenv("POISSON_GENERIC_TRI", raising=False)
+    if cap:
+        monkeypatch.setenv("POISSON_GRID_CAP", str(cap))
+    else:
+        monkeypatch.delenv("POISSON_GRID_CAP", raising=False)
+    plan = Plan.from_problem(prob)
+    if mixed:
+        plan.set_precision(FP32_REFINED, 1e-10, 4)
+    t = to_dev(prob.rhs)
+    plan.solve(t)
+    out = to_host(t)
+    status = plan.status()
+    roles = plan.roles
+    plan.close()
+    return out, status, roles
+
+
+CASES = [
+    # shape, bcs, stretch z, shift
+    ((24, 20, 191), ("P", "NN", "DD"), None, 0.0),
+    ((24, 20, 191), ("P", "NN", "DD"), 1.8, 0.0),
+    ((16, 12, 100), ("DD", "P", "ND"), None, 0.0),
+    ((12, 10, 250), ("NN", "DD", "DN"), 1.8, 0.0),
+    ((8, 6, 480), ("DD", "DD", "DD"), None, 0.0),
+    ((20, 16, 45), ("P", "DD", "ND"), None, 0.0),
+    ((16, 191, 12), ("P", "DD", "P"), None, 0.0),          # s = y
+    ((32, 16, 191), ("P", "P", "DDn"), None, -2.0e3),      # node pair with a shift
+    ((30, 16, 161), ("P", "NN", "NNn"), None, -50.0),      # NN nodes, shifted: not singular
+    ((10, 8, 320), ("P", "NN", "NN"), None, 0.0),          # singular: generic kernel
+    ((12, 8, 150), ("P", "P", "P"), 1.8, 0.0),             # periodic s: generic kernel
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[0])) + "-" + "".join(c[1]))
+def test_padded_lines(case, monkeypatch):
+    shape, bcs, stretch, shift = case
+    prob = inputs.make_uniform(*shape, bcs, seed=sum(shape), stretch_z=stretch)
+    if shift:
+        prob.rhs = inputs.make_uniform(*shape, ("DD", "DD", "DD"), seed=sum(shape)).rhs
+        prob.shift = shift
+    ref = oracle_solve(prob)
+    got, _, roles = _solve(prob, monkeypatch)
+    gen, _, _ = _solve(prob, monkeypatch, generic=True)
+    capped, _, _ = _solve(prob, monkeypatch, cap=16)
+    e_ref, e_gen, e_cap = rel_l2(got, ref), rel_l2(got, gen), rel_l2(capped, got)
+    print(shape, bcs, roles, "vs oracle", e_ref, "vs generic", e_gen, "capped", e_cap, flush=True)
+    # both kernels meet the oracle's bar; they round differently along a line,
+    # so against each other the bound is the sum of theirs
+    assert e_ref <= 1e-12 and rel_l2(gen, ref) <= 1e-12 and e_gen <= 2e-12 and e_cap == 0.0
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[3], CASES[7]], ids=lambda c: "x".join(map(str, c[0])))
+def test_padded_lines_refined(case, monkeypatch):
+    shape, bcs, stretch, shift = case
+    prob = inputs.make_uniform(*shape, bcs, seed=7, stretch_z=stretch)
+    if shift:
+        prob.rhs = inputs.make_uniform(*shape, ("DD", "DD", "DD"), seed=7).rhs
+        prob.shift = shift
+    ref = oracle_solve(prob)
+    got, (iters, rel, conv), _ = _solve(prob, monkeypatch, mixed=True)
+    err = rel_l2(got, ref)
+    print(shape, "FP32 + refinement", iters, err, flush=True)
+    assert conv and err <= 1e-10
