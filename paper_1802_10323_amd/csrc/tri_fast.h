@@ -102,9 +102,14 @@ __device__ __noinline__ void tri_fast_load(lptr<T> lds, gptr<const T> data, long
   T buf[RPC];
   if ((LAY >= 0 ? LAY : layout) == 0) {
     const int l = tid % L::NL, q = tid / L::NL;
+    if (nreal >= L::N) {   // whole lines (uniform): no row mask
 #pragma unroll
-    for (int i = 0; i < RPC; ++i)
-      buf[i] = base >= 0 && q + i * P < nreal ? data[base + (q + i * P) * sp] : (T)0;
+      for (int i = 0; i < RPC; ++i) buf[i] = base >= 0 ? data[base + (q + i * P) * sp] : (T)0;
+    } else {               // a padded line: rows past nreal read as 0
+#pragma unroll
+      for (int i = 0; i < RPC; ++i)
+        buf[i] = base >= 0 && q + i * P < nreal ? data[base + (q + i * P) * sp] : (T)0;
+    }
 #pragma unroll
     for (int i = 0; i < RPC; ++i) lds[tri_fast_slot<T, RPC, P>(q + i * P, l)] = buf[i];
   } else {
@@ -132,7 +137,10 @@ __device__ __forceinline__ void tri_fast_store_body(lptr<const T> lds, gptr<T> d
     const int l = tid % L::NL, q = tid / L::NL;
 #pragma unroll
     for (int i = 0; i < RPC; ++i) buf[i] = lds[tri_fast_slot<T, RPC, P>(q + i * P, l)];
-    if (base >= 0) {
+    if (base >= 0 && nreal >= L::N) {
+#pragma unroll
+      for (int i = 0; i < RPC; ++i) data[base + (q + i * P) * sp] = buf[i];
+    } else if (base >= 0) {   // a padded line: rows past nreal are not stored
 #pragma unroll
       for (int i = 0; i < RPC; ++i)
         if (q + i * P < nreal) data[base + (q + i * P) * sp] = buf[i];
