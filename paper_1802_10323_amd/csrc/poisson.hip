@@ -167,9 +167,9 @@ struct poisson_plan {
   AxisTables ax[2];
   // elimination axis tables
   size_t off_tri_d = 0, off_tri_f = 0;     // a, b, c, w   (4 n_s)
-  // Strided lines whose length has no size-specialised kernel are run in the
-  // kernel of the next specialised length pad_n (0: not padded), with the
-  // tables extended by decoupled rows (see plan_create).
+  // Lines whose length has no size-specialised kernel are run in the kernel
+  // of the next specialised length pad_n (0: not padded), with the tables
+  // extended by decoupled rows (see plan_create).
   int pad_n = 0;
   size_t off_tri_pad = 0;                  // a, b, c, w   (4 pad_n), FP64
   size_t off_lam_d = 0, off_lam_f = 0;     // lamu, lamv
@@ -712,7 +712,7 @@ template <typename T>
 static int launch_tridiag(const poisson_plan* p, T* data, hipStream_t st,
                           const double* skip = nullptr) {
   t_grid_cap = p->grid_cap;
-  if (p->pad_n) {   // padded strided lines: the plain chunked kernel of length pad_n
+  if (p->pad_n) {   // padded lines: the plain chunked kernel of length pad_n
     return (int)with_tri_cfg(p->pad_n, 0, [&](auto cfg) {
       using C = decltype(cfg);
       return (long long)launch_tri_fast<T, C::RPC, C::P>(p, data, st, skip);
@@ -1072,10 +1072,10 @@ extern "C" poisson_plan* plan_create_helmholtz(int nx, int ny, int nz, double dx
     // (a = c = 0, diagonal -1: with the shifts mu <= 0 of the transformed
     // axes no pivot of theirs comes near 0) and whose right-hand side there
     // is 0, so they come out 0 and leave the first ns unknowns those of the
-    // real line.  Only for strided, non-periodic lines (the real last row
-    // then has no coupling past it) of non-singular plans (the gauge pins
-    // the line's last row).
-    if (p->s != 0 && !p->s_periodic && !p->singular && !p->generic_tri && !tri_fast_length(ns_)) {
+    // real line.  Only for non-periodic lines (the real last row then has no
+    // coupling past it) of non-singular plans (the gauge pins the line's
+    // last row).
+    if (!p->s_periodic && !p->singular && !p->generic_tri && !tri_fast_length(ns_)) {
       for (const int cand : {64, 96, 128, 192, 256, 384, 512}) {
         if (cand >= ns_ && 2 * cand <= 3 * ns_) {
           p->pad_n = cand;

@@ -113,10 +113,19 @@ __device__ __noinline__ void tri_fast_load(lptr<T> lds, gptr<const T> data, long
 #pragma unroll
     for (int i = 0; i < RPC; ++i) lds[tri_fast_slot<T, RPC, P>(q + i * P, l)] = buf[i];
   } else {
+    if (nreal >= L::N) {   // whole lines (uniform): one contiguous run
 #pragma unroll
-    for (int i = 0; i < RPC; ++i) {
-      const int e = tid + i * L::NT;
-      buf[i] = e / L::N < lines ? data[base + e] : (T)0;
+      for (int i = 0; i < RPC; ++i) {
+        const int e = tid + i * L::NT;
+        buf[i] = e / L::N < lines ? data[base + e] : (T)0;
+      }
+    } else {               // padded lines: stride nreal, rows past it read as 0
+#pragma unroll
+      for (int i = 0; i < RPC; ++i) {
+        const int e = tid + i * L::NT;
+        const int ll = e / L::N, r = e - ll * L::N;
+        buf[i] = ll < lines && r < nreal ? data[base + (long long)ll * nreal + r] : (T)0;
+      }
     }
 #pragma unroll
     for (int i = 0; i < RPC; ++i) {
@@ -152,10 +161,19 @@ __device__ __forceinline__ void tri_fast_store_body(lptr<const T> lds, gptr<T> d
       const int ll = e / L::N;
       buf[i] = lds[tri_fast_slot<T, RPC, P>(e - ll * L::N, ll)];
     }
+    if (nreal >= L::N) {
 #pragma unroll
-    for (int i = 0; i < RPC; ++i) {
-      const int e = tid + i * L::NT;
-      if (e / L::N < lines) data[base + e] = buf[i];
+      for (int i = 0; i < RPC; ++i) {
+        const int e = tid + i * L::NT;
+        if (e / L::N < lines) data[base + e] = buf[i];
+      }
+    } else {   // padded lines: stride nreal, rows past it not stored
+#pragma unroll
+      for (int i = 0; i < RPC; ++i) {
+        const int e = tid + i * L::NT;
+        const int ll = e / L::N, r = e - ll * L::N;
+        if (ll < lines && r < nreal) data[base + (long long)ll * nreal + r] = buf[i];
+      }
     }
   }
 }
@@ -426,7 +444,7 @@ __device__ __forceinline__ void tri_fast_tile(lptr<T> lds, lptr<const double> co
     const int ll = tid % NL;
     base = ll < nlt ? line_base(g, o, ll) : -1;
   } else {
-    base = (long long)o.L0 * N;
+    base = (long long)o.L0 * g.n;   // g.n = N, or the real length of a padded line
     lines = min(g.nlines - o.L0, nlt);
   }
   tri_fast_load<T, RPC, P, LAY>(lds, as_global((const T*)A.data), base, g.sp, g.layout, lines, tid,

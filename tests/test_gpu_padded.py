@@ -3,8 +3,9 @@ are solved in the kernel of the next specialised length (at most 3/2 of
 theirs), with the extra rows decoupled (a = c = 0, diagonal -1, right-hand
 side 0).  Against the oracle (<= 1e-12; FP32 + refinement <= 1e-10) and
 against the size-generic kernel (POISSON_GENERIC_TRI=1) on the same plan,
-for both strided axes, stretched z, node pairs with a Helmholtz shift, and
-with every launch capped at 16 blocks so that blocks loop over tiles.
+for all three axes (strided and contiguous lines), stretched z, node pairs
+with a Helmholtz shift, and with every launch capped at 16 blocks so that
+blocks loop over tiles.
 Periodic and singular lines keep the generic kernel."""
 import pytest
 
@@ -54,6 +55,9 @@ CASES = [
     ((8, 6, 480), ("DD", "DD", "DD"), None, 0.0),
     ((20, 16, 45), ("P", "DD", "ND"), None, 0.0),
     ((16, 191, 12), ("P", "DD", "P"), None, 0.0),          # s = y
+    ((191, 16, 12), ("DD", "P", "P"), None, 0.0),          # s = x (contiguous lines)
+    ((100, 8, 10), ("ND", "P", "P"), None, 0.0),           # s = x
+    ((161, 16, 8), ("NNn", "P", "P"), None, -50.0),        # s = x, node pair with a shift
     ((32, 16, 191), ("P", "P", "DDn"), None, -2.0e3),      # node pair with a shift
     ((30, 16, 161), ("P", "NN", "NNn"), None, -50.0),      # NN nodes, shifted: not singular
     ((10, 8, 320), ("P", "NN", "NN"), None, 0.0),          # singular: generic kernel
@@ -79,7 +83,7 @@ def test_padded_lines(case, monkeypatch):
     assert e_ref <= 1e-12 and rel_l2(gen, ref) <= 1e-12 and e_gen <= 2e-12 and e_cap == 0.0
 
 
-@pytest.mark.parametrize("case", [CASES[0], CASES[3], CASES[7]], ids=lambda c: "x".join(map(str, c[0])))
+@pytest.mark.parametrize("case", [CASES[0], CASES[3], CASES[7], CASES[10]], ids=lambda c: "x".join(map(str, c[0])))
 def test_padded_lines_refined(case, monkeypatch):
     shape, bcs, stretch, shift = case
     prob = inputs.make_uniform(*shape, bcs, seed=7, stretch_z=stretch)
