@@ -222,6 +222,8 @@ static long long with_fast_cfg(int M, int V, F&& f) {
 #define POISSON_FM(M_) POISSON_FV(M_, 0) POISSON_FV(M_, 1) POISSON_FV(M_, 2) POISSON_FV(M_, 3)
     POISSON_FM(16) POISSON_FM(32) POISSON_FM(48) POISSON_FM(64)
     POISSON_FM(96) POISSON_FM(128) POISSON_FM(192) POISSON_FM(256)
+    // single solves only (the batched kernel takes the lengths above)
+    POISSON_FM(72) POISSON_FM(80) POISSON_FM(144) POISSON_FM(160)
 #undef POISSON_FM
 #undef POISSON_FV
     default: return -1;
@@ -303,7 +305,7 @@ static int lds_setup_once() {
 #define ALLOW(k) if (e == hipSuccess) e = hipFuncSetAttribute((const void*)(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_LIMIT)
     ALLOW((r2r_kernel<double, R2R_EMAX_D, R2R_NT>));
     ALLOW((r2r_kernel<float, R2R_EMAX_F, R2R_NT>));
-    for (int M : {16, 32, 48, 64, 96, 128, 192, 256})
+    for (int M : {16, 32, 48, 64, 72, 80, 96, 128, 144, 160, 192, 256})
       for (int V = 0; V < 4; ++V)
         with_fast_cfg(M, V, [&](auto cfg) {
           using C = decltype(cfg);
@@ -699,7 +701,8 @@ static bool tri_fast_length(int n) {
 }
 
 // Complex length M of the size-specialised transform kernel for axis A, or
-// 0 if its length has none.
+// 0 if its length has none, among the lengths the batched kernel takes
+// (single solves also have 72, 80, 144 and 160).
 static int r2r_fast_length(const AxisTables& A) {
   if (node_pair(A.kind)) return 0;
   switch (A.m) {

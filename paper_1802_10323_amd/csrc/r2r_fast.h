@@ -1,6 +1,7 @@
 // r2r_fast.h - size-specialised version of the batched real-to-real
 // transforms (Table 2 / Table 1) for the common lengths n = 2M,
-// M in {16, 32, 48, 64, 96, 128, 192, 256}.
+// M in {16, 32, 48, 64, 96, 128, 192, 256}, and for single solves also
+// M in {72, 80, 144, 160} (radix-3 and radix-5 passes).
 //
 // Same mathematics as r2r_kernel.h (one complex FFT of length M per line
 // plus the per-type pre/post steps), but the FFT length, its radix plan,
@@ -109,6 +110,13 @@ POISSON_FAST_SHAPES(96, 16, 32, 32, 16)
 POISSON_FAST_SHAPES(128, 16, 32, 32, 16)
 POISSON_FAST_SHAPES(192, 32, 16, 64, 8)
 POISSON_FAST_SHAPES(256, 32, 16, 64, 8)
+// lengths 2M with a factor 5 or 9 (radix-5 / radix-3 passes), one tile
+// shape each: QT must be a power of two dividing M, and a thread's M/QT
+// complex values must fit the registers (10 or more spill to scratch)
+POISSON_FAST_SHAPES(72, 8, 64, 8, 64)
+POISSON_FAST_SHAPES(80, 16, 32, 16, 32)
+POISSON_FAST_SHAPES(144, 16, 32, 16, 32)
+POISSON_FAST_SHAPES(160, 32, 16, 32, 16)
 #undef POISSON_FAST_SHAPES
 
 template <int M, int V>

@@ -12,7 +12,7 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
 
 
-FAST_M = [16, 32, 48, 64, 96, 128, 192, 256]
+FAST_M = [16, 32, 48, 64, 72, 80, 96, 128, 144, 160, 192, 256]
 ELIM_LENGTHS = [64, 96, 128, 192, 256, 384, 512]
 
 

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 KINDS = ("P", "NN", "DD", "ND", "DN")
 TOL64 = 1e-12
-FAST_M = [16, 32, 48, 64, 96, 128, 192, 256]
+FAST_M = [16, 32, 48, 64, 72, 80, 96, 128, 144, 160, 192, 256]
 ELIM_LENGTHS = [64, 96, 128, 192, 256, 384, 512]
 
 
@@ -96,13 +96,14 @@ def test_stages_match_oracle(shape, bcs, stretched):
 
 @pytest.mark.parametrize("path", ["specialised", "generic"])
 @pytest.mark.parametrize("kind", KINDS)
-@pytest.mark.parametrize("n", [2, 4, 6, 10, 18, 30, 32, 50, 64, 96, 128, 160, 192, 250, 256,
-                               384, 512, 1024])
+@pytest.mark.parametrize("n", [2, 4, 6, 10, 18, 30, 32, 50, 64, 96, 128, 144, 160, 192, 240, 250,
+                               256, 288, 320, 384, 480, 512, 1024])
 def test_transform_lengths(kind, n, path, monkeypatch):
     """Every supported transform length class on the contiguous (x) and the
     strided (y) axis, against the Table 2 sums; round trip is the identity.
-    Lengths 2M with M in {16, 32, 48, 64, 96, 128, 192, 256} have
-    size-specialised kernels; the generic kernel is run on them too."""
+    Lengths 2M with M in {16, 32, 48, 64, 72, 80, 96, 128, 144, 160, 192,
+    256} have size-specialised kernels; the generic kernel is run on them
+    too."""
     from oracle import transforms as tr
     from paper_1802_10323_amd import Plan
     if path == "generic":
