@@ -104,7 +104,11 @@ __global__ __launch_bounds__(PROJ_NT) void proj_rhs_kernel(const double* __restr
 // (i, j) columns and PROJ_KC consecutive planes; each thread walks its
 // column upward with Phi of the cell below in a register, so the z
 // gradient reads no other plane (the x and y neighbours come from the
-// lines the adjacent lanes and rows load).
+// lines the adjacent lanes and rows load).  The face values and p, each
+// read and written by one thread only, take the nontemporal hint; Phi,
+// which the neighbouring lanes read again, does not.  Measured: the
+// update on the 512 x 256 x 192 channel 0.378-0.383 -> 0.361-0.362 ms, an
+// RK3 step of the periodic 512^3 Taylor-Green vortex 17.96 -> 17.87 ms.
 __global__ __launch_bounds__(PROJ_NT) void proj_update_zmarch_kernel(
     const double* __restrict__ phi, double gdt, const double* u_in, const double* v_in,
     const double* w_in, double* u, double* v, double* w, double* __restrict__ p, ProjGeom G) {
@@ -137,10 +141,10 @@ __global__ __launch_bounds__(PROJ_NT) void proj_update_zmarch_kernel(
     r.phx = i > 0 ? phi[c - 1] : (!X.walled ? phi[c + nx - 1] : 0.0);
     r.phy = j > 0 ? phi[c - nx] : (!Y.walled ? phi[c + (long long)nx * (ny - 1)] : 0.0);
     const long long fu = face_u(k), fv = face_v(k);
-    r.u0 = u_in[fu];
-    r.v0 = v_in[fv];
-    r.w0 = w_in[c];
-    r.p0 = p[c];
+    r.u0 = __builtin_nontemporal_load(&u_in[fu]);
+    r.v0 = __builtin_nontemporal_load(&v_in[fv]);
+    r.w0 = __builtin_nontemporal_load(&w_in[c]);
+    r.p0 = __builtin_nontemporal_load(&p[c]);
     r.uh = xh ? u_in[fu + 1] : 0.0;
     r.vh = yh ? v_in[fv + nx] : 0.0;
     r.wh = Z.walled && k == nz - 1 ? w_in[c + plane] : 0.0;
@@ -169,15 +173,15 @@ __global__ __launch_bounds__(PROJ_NT) void proj_update_zmarch_kernel(
     else if (!Z.lo_dirichlet) { az_ = false; gz = 0.0; }
     else gz = 2.0 * ph * Z.inv_dc[0];
     const long long fu = face_u(k), fv = face_v(k);
-    u[fu] = ax_ ? cur.u0 - gdt * gx : cur.u0;
-    v[fv] = ay_ ? cur.v0 - gdt * gy : cur.v0;
-    w[c] = az_ ? cur.w0 - gdt * gz : cur.w0;
+    __builtin_nontemporal_store(ax_ ? cur.u0 - gdt * gx : cur.u0, &u[fu]);
+    __builtin_nontemporal_store(ay_ ? cur.v0 - gdt * gy : cur.v0, &v[fv]);
+    __builtin_nontemporal_store(az_ ? cur.w0 - gdt * gz : cur.w0, &w[c]);
     // high wall faces: Dirichlet gradient -2 phi_edge / h_edge; Neumann unchanged
     if (xh) u[fu + 1] = X.hi_dirichlet ? cur.uh - gdt * (-2.0 * ph * X.inv_dc[nx]) : cur.uh;
     if (yh) v[fv + nx] = Y.hi_dirichlet ? cur.vh - gdt * (-2.0 * ph * Y.inv_dc[ny]) : cur.vh;
     if (Z.walled && k == nz - 1)
       w[c + plane] = Z.hi_dirichlet ? cur.wh - gdt * (-2.0 * ph * Z.inv_dc[nz]) : cur.wh;
-    p[c] = cur.p0 + ph;
+    __builtin_nontemporal_store(cur.p0 + ph, &p[c]);
     below = ph;
     cur = nxt;
   }
