@@ -33,8 +33,9 @@ hipError_t async_elimination_launch(const TriFastArgs<float>& a, int n, hipStrea
 
 // The register-staged transform (FP64, length 512, strided axes, 32 lines
 // per tile; r2r_async_wide.hip), arguments as for r2r_fast_kernel with
-// RegStageCfg.  hipErrorInvalidValue for a contiguous axis.
-hipError_t regstage_launch(const R2RFastArgs<double>& a, int kind, int inverse,
+// RegStageCfg; `hinted` selects the form with nontemporal accesses.
+// hipErrorInvalidValue for a contiguous axis.
+hipError_t regstage_launch(const R2RFastArgs<double>& a, int kind, int inverse, bool hinted,
                            hipStream_t stream);
 
 // The direct elimination of contiguous lines (tri_async.hip), with the

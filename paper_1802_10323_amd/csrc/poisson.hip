@@ -521,7 +521,11 @@ static int launch_fast_variant(const poisson_plan* p, const AxisTables& A, int V
     if constexpr (sizeof(T) == 8) {
       if (regstage_applies<T>(p, A) && (reinterpret_cast<uintptr_t>(data) & 15) == 0) {
         const R2RFastArgs<T> a = fast_args<T, RegStageCfg>(p, A, inverse, data, skip);
-        const hipError_t e = regstage_launch(a, A.kind, inverse, st);
+        // nontemporal accesses on fields at least twice the 256 MB
+        // Infinity Cache (smaller ones can stay there between stages)
+        const bool hinted = (double)p->dims[0] * p->dims[1] * p->dims[2] * sizeof(T) >=
+                            (double)(512u << 20);
+        const hipError_t e = regstage_launch(a, A.kind, inverse, hinted, st);
         if (e != hipSuccess)
           return fail(POISSON_EHIP, "register-staged transform launch: %s", hipGetErrorString(e));
         return POISSON_OK;

@@ -28,13 +28,16 @@ hipError_t async_wide_launch(const R2RFastArgs<double>& a, int kind, int inverse
   return hipGetLastError();
 }
 
-hipError_t regstage_launch(const R2RFastArgs<double>& a, int kind, int inverse,
+hipError_t regstage_launch(const R2RFastArgs<double>& a, int kind, int inverse, bool hinted,
                            hipStream_t stream) {
   if (a.g.layout != 0) return hipErrorInvalidValue;
   void (*k)(R2RFastArgs<double>) = nullptr;
   switch (kind * 2 + inverse) {
-#define POISSON_RS(K_, I_) \
-  case K_ * 2 + I_: k = r2r_regstage_kernel<double, RegStageCfg, K_, I_>; break;
+#define POISSON_RS(K_, I_)                                                                    \
+  case K_ * 2 + I_:                                                                          \
+    k = hinted ? r2r_regstage_kernel<double, RegStageCfg, K_, I_, true>                     \
+               : r2r_regstage_kernel<double, RegStageCfg, K_, I_, false>;                   \
+    break;
     POISSON_RS(0, 0) POISSON_RS(0, 1) POISSON_RS(1, 0) POISSON_RS(1, 1) POISSON_RS(2, 0)
     POISSON_RS(2, 1) POISSON_RS(3, 0) POISSON_RS(3, 1) POISSON_RS(4, 0) POISSON_RS(4, 1)
 #undef POISSON_RS

@@ -1172,15 +1172,19 @@ __device__ __forceinline__ void post_store_full(lptr<const T> lds, lptr<const cp
 // thread's wavenumber pairs (k, M - k) and combine them.  Each thread reads
 // two adjacent lines with 16-byte loads.
 //
-// The forward DCT-IV / DST-IV and every inverse type read and write the
-// field with the nontemporal hint.  Measured on the 512^3 cube: the forward
+// HINTED: the forward DCT-IV / DST-IV and every inverse type read and
+// write the field with the nontemporal hint (the launch asks for it on
+// fields of 512 MiB and more).  Measured on the 512^3 cube: the forward
 // DCT-IV along y, the inverse real DFT along z and the inverse DCT-IV along
 // y ran 3-7 % faster, and the forward real DFT along z, which runs after
 // the hinted forward y, 4 % faster (the solve 2.19 -> 2.11 ms; an RK3 step
 // of the periodic 512^3 Taylor-Green vortex 18.65 -> 18.48 ms).  The forward
 // real DFT / DCT-II / DST-II (its split stores scatter the rows) keeps plain
-// accesses: with the hint it ran 15-25 % slower.
-template <typename T, typename C, int KIND, int INV>
+// accesses: with the hint it ran 15-25 % slower.  On fields that fit the
+// 256 MB Infinity Cache the hint cost 2-5 % (64 x 512 x 512: 0.277 ->
+// 0.284 ms, 128 x 512 x 512: 0.490 -> 0.517 ms); at 256 x 512 x 512 it
+// was neutral.
+template <typename T, typename C, int KIND, int INV, bool HINTED>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void r2r_regstage_kernel(R2RFastArgs<T> A) {
   using L = FastLayout<T, C>;
@@ -1188,7 +1192,7 @@ void r2r_regstage_kernel(R2RFastArgs<T> A) {
   constexpr int kind = KIND, inverse = INV;
   constexpr bool ivk = kind >= K_ND;
   constexpr bool plain = !ivk;      // rows of the thread; IV types: pre-twiddle pairs
-  constexpr bool nt = inverse || ivk;   // nontemporal loads and stores
+  constexpr bool nt = HINTED && (inverse || ivk);   // nontemporal loads and stores
   if (A.skip && A.skip[0] != 0.0) return;
   __shared__ __align__(16) unsigned char tile_raw[fast_lds_bytes<T, C>()];
   const FastLds<T, C> S = fast_lds<T, C>(tile_raw);
