@@ -1320,6 +1320,12 @@ static RefineLaunch refine_launch(const poisson_plan* p, double* stats) {
   return r;
 }
 
+// Nontemporal accesses in the refinement sweeps on fields of at least
+// 512 MiB (twice the 256 MB Infinity Cache).
+static bool refine_hinted(const poisson_plan* p) {
+  return (double)p->dims[0] * p->dims[1] * p->dims[2] * sizeof(double) >= (double)(512u << 20);
+}
+
 // Status reset, projection of f if singular, the FP64 copy of f and its FP32 cast.
 static int refine_begin(const poisson_plan* p, const RefineWork& W, double* rhs, hipStream_t st) {
   const RefineLaunch r = refine_launch(p, W.stats);
@@ -1328,7 +1334,8 @@ static int refine_begin(const poisson_plan* p, const RefineWork& W, double* rhs,
     hipLaunchKernelGGL(refine_wsum_kernel, dim3(r.nb), dim3(REFINE_NT), 0, st, (const double*)rhs, r.G);
     hipLaunchKernelGGL(refine_mean_kernel, dim3(1), dim3(REFINE_NT), 0, st, W.stats, r.nb);
   }
-  hipLaunchKernelGGL(refine_prep_kernel, dim3(r.nb), dim3(REFINE_NT), 0, st, (const double*)rhs,
+  hipLaunchKernelGGL(refine_hinted(p) ? refine_prep_kernel<true> : refine_prep_kernel<false>,
+                     dim3(r.nb), dim3(REFINE_NT), 0, st, (const double*)rhs,
                      W.f64, W.e32, (const double*)W.stats, (int)p->singular, r.N);
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
@@ -1338,7 +1345,8 @@ static int refine_begin(const poisson_plan* p, const RefineWork& W, double* rhs,
 static int refine_sweep_begin(const poisson_plan* p, const RefineWork& W, double* rhs,
                               hipStream_t st) {
   const RefineLaunch r = refine_launch(p, W.stats);
-  hipLaunchKernelGGL(refine_residual_kernel, dim3(r.rg.blocks), dim3(REFINE_NT), 0, st,
+  hipLaunchKernelGGL(refine_hinted(p) ? refine_residual_kernel<true> : refine_residual_kernel<false>,
+                     dim3(r.rg.blocks), dim3(REFINE_NT), 0, st,
                      (const double*)rhs, (const double*)W.f64, W.e32, r.G, r.rg);
   HIP_TRY(hipGetLastError());
   return POISSON_OK;
@@ -1348,7 +1356,8 @@ static int refine_sweep_begin(const poisson_plan* p, const RefineWork& W, double
 static int refine_sweep_end(const poisson_plan* p, const RefineWork& W, double* rhs, int sweep,
                             hipStream_t st) {
   const RefineLaunch r = refine_launch(p, W.stats);
-  hipLaunchKernelGGL(refine_update_kernel, dim3(r.nb), dim3(REFINE_NT), 0, st, rhs,
+  hipLaunchKernelGGL(refine_hinted(p) ? refine_update_kernel<true> : refine_update_kernel<false>,
+                     dim3(r.nb), dim3(REFINE_NT), 0, st, rhs,
                      (const float*)W.e32, r.G);
   hipLaunchKernelGGL(refine_status_kernel, dim3(1), dim3(REFINE_NT), 0, st, W.stats, r.nb, sweep,
                      W.tol);
