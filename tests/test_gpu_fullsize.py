@@ -66,3 +66,29 @@ def test_cube_fp32_refined_vs_oracle(cube):
         "vs plain oracle", rel_l2(got, plain))
     assert conv and iters <= 4
     assert err <= 1e-10
+
+
+# 256 x 512 x 512 fields are 512 MiB, the smallest on which the strided
+# transforms of length 512 and the refinement sweeps take their
+# nontemporal form: other boundary pairs than the cube's (DCT-II / DST-II
+# and real-DFT transforms along y and z, a singular problem with its gauge)
+# through that form, against the oracle's corrected solve (Sec. 2.1,
+# Eq. (poi); Tables 1-2).
+@pytest.mark.parametrize("bcs,mixed", [(("NN", "DD", "P"), False), (("DN", "P", "P"), False),
+                                       (("NN", "P", "P"), False), (("NN", "P", "P"), True)])
+def test_half_cube_vs_oracle(bcs, mixed):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    prob = inputs.make_uniform(256, 512, 512, bcs, 3, name="half cube")
+    say("256 x 512 x 512", bcs, "mixed" if mixed else "FP64")
+    ref = oracle.solve_corrected(prob.rhs, prob.hx, prob.hy, prob.hz, *prob.bcs)
+    got, (iters, rel, conv) = gpu_solve(prob, mixed=mixed, tol=1e-10, max_iters=6)
+    err = rel_l2(got, ref)
+    say("  rel-L2 vs corrected oracle", err, *(("FP32 solves", iters, "converged", conv) if mixed else ()))
+    if mixed:
+        assert conv and iters <= 4
+        assert err <= 1e-10
+    else:
+        assert err <= 1e-12
