@@ -123,9 +123,14 @@ def cmd_stats(a):
     lines = ["# rocprofv3 --kernel-trace --stats summary", "# command:"]
     lines += [f"#   {c}" for c in a.command]
     lines.append(f"# kernel sources {kernel_source_hash()}")
-    lines.append(f"{'kernel':60s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'total_ms':>10s} {'pct':>6s}")
-    for r in rows:
-        lines.append(f"{short_name(r['Name'])[:60]:60s} {int(r['Calls']):6d} "
+    # whole template argument lists (kind, direction, form of each
+    # instantiation), without the spaces
+    names = [short_name(r["Name"]).replace(", ", ",").removeprefix("void ") for r in rows]
+    w = min(100, max([60] + [len(n) for n in names]))
+    names = [n[:w] for n in names]
+    lines.append(f"{'kernel':{w}s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'total_ms':>10s} {'pct':>6s}")
+    for r, name in zip(rows, names):
+        lines.append(f"{name:{w}s} {int(r['Calls']):6d} "
                      f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:10.2f} "
                      f"{float(r['MaxNs']) / 1e3:10.2f} {float(r['TotalDurationNs']) / 1e6:10.3f} "
                      f"{float(r['Percentage']):6.2f}")
